@@ -1,0 +1,192 @@
+"""Benchmark of the cyclic-to-cyclic multidimensional FFT on one MI355X.
+
+Default workload: the 512 x 512 x 512 complex128 forward DFT on a 4 x 4 x 4
+virtual processor grid (cyclic in, cyclic out), iid uniform[-1, 1) input from
+seed 2. One step is one full transform (Superstep 0 local FFTs, twiddle, the
+one permutation, Superstep 2 length-p FFTs) with the input already in HBM.
+
+Prints one JSON line: GFLOP/s under the 5 N log2 N convention, the roofline of
+the dominant kernel (HIP events on the execution stream, algorithmic bytes =
+one read and one write of the N-element array per launch), the oracle timed on
+the host cores, and the error of the timed output against the oracle.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload 512cube|64cube|64pow5]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "GFLOP/s (5N log2N) + %HBM roofline, 512^3 c2c FP64; served p50/p99 latency"
+
+WORKLOADS = {
+    "512cube": dict(n=(512, 512, 512), p=(4, 4, 4), dtype="complex128", dist="uniform", seed=2,
+                    name="512x512x512 complex128 forward DFT, 4x4x4 cyclic grid"),
+    "64cube": dict(n=(64, 64, 64), p=(2, 2, 2), dtype="complex128", dist="uniform", seed=1,
+                   name="64x64x64 complex128 forward DFT, 2x2x2 cyclic grid"),
+    "64pow5": dict(n=(64,) * 5, p=(2,) * 5, dtype="complex64", dist="normal", seed=3,
+                   name="64^5 complex64 forward DFT, 2x2x2x2x2 cyclic grid (FP32 butterflies, FP64-generated twiddles)"),
+}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_symbols(info):
+    names = ["k_pass"] * info["s0_kernels"]
+    if info["exchange_fused"]:
+        names.append("k_exchange")
+    else:
+        names += ["k_twiddle", "k_permute"] + ["k_pass"] * (info["s2_kernels"] - 2)
+    return names
+
+
+def source_digest():
+    h = hashlib.sha256()
+    for f in ["fftu_kernels.hip", "fftu_api.cpp", "fftu_internal.hpp"]:
+        with open(os.path.join(ROOT, "paper_2203_11795_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload, kernel):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was
+    taken from the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", f"pmc_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("source_sha256") != source_digest():
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    if not k:
+        return None
+    return float(k["hbm_bytes_per_launch"])
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="512cube", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-check", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): this build has no multi-GPU path; "
+              "the exchange is an on-device permutation.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2203_11795_amd as fftu
+    import synth
+
+    wl = WORKLOADS[args.workload]
+    n, p, dtype = wl["n"], wl["p"], wl["dtype"]
+    N = math.prod(n)
+    esize = 16 if dtype == "complex128" else 8
+    npdt = np.complex128 if dtype == "complex128" else np.complex64
+
+    log(f"[bench] workload {args.workload}: generating input")
+    gen = synth.uniform_complex if wl["dist"] == "uniform" else synth.normal_complex
+    D = gen(N, wl["seed"], npdt)
+    dev = torch.device("cuda:0")
+    x = torch.from_numpy(D).to(dev)
+    out = torch.empty_like(x)
+    plan = fftu.Plan(n, p, dtype, fftu.FORWARD)
+    info = plan.info()
+    stream = torch.cuda.current_stream(dev)
+
+    log(f"[bench] plan: {info}; warmup {args.warmup}")
+    for _ in range(args.warmup):
+        plan(x, out)
+    torch.cuda.synchronize()
+
+    plan.timing_begin(args.steps)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        plan(x, out, stream=stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    total_ms = ev0.elapsed_time(ev1)
+    per_launch, ncalls = plan.timing_end()
+    ms = total_ms / args.steps
+    flops = 5.0 * N * math.log2(N)
+    gflops = flops / (ms * 1e-3) / 1e9
+    log(f"[bench] {args.steps} steps: {ms:.3f} ms/step, {gflops:.1f} GFLOP/s; per launch ms {per_launch}")
+
+    # Roofline of the dominant kernel: every launch reads and writes the N-element array once.
+    alg_bytes = 2.0 * N * esize
+    syms = kernel_symbols(info)
+    per_sym = {}
+    for s, t in zip(syms, per_launch):
+        tot, cnt = per_sym.get(s, (0.0, 0))
+        per_sym[s] = (tot + t, cnt + 1)
+    dom = max(per_sym, key=lambda s: per_sym[s][0])
+    dom_avg_ms = per_sym[dom][0] / per_sym[dom][1]
+    achieved = alg_bytes / (dom_avg_ms * 1e-3) / 1e9
+    kname = f"{dom}<{'double' if esize == 16 else 'float'}>"
+    traffic = measured_traffic(args.workload, kname)
+    roofline = {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic, "algorithmic_bytes_per_launch": alg_bytes,
+                "avg_launch_ms": round(dom_avg_ms, 4), "launches_per_step": per_sym[dom][1]}
+    kernels = [{"launch": i, "kernel": s, "avg_ms": round(t, 4),
+                "GBps_alg": round(alg_bytes / (t * 1e-3) / 1e9, 1) if t > 0 else None}
+               for i, (s, t) in enumerate(zip(syms, per_launch))]
+    transform_bytes = info["launches"] * alg_bytes
+    frac_transform = transform_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS
+
+    result = {
+        "metric": METRIC, "value": round(gflops, 2), "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64" if esize == 16 else "f32", "data": "synthetic",
+        "config": {"workload": wl["name"], "n": list(n), "p": list(p), "direction": "forward",
+                   "input": f"iid {wl['dist']} real/imag, seed {wl['seed']}"},
+        "roofline": roofline,
+        "hbm_roofline_frac_transform": round(frac_transform, 4),
+        "transform_algorithmic_bytes": transform_bytes,
+        "kernels": kernels,
+    }
+
+    need_oracle = not (args.no_cpu_baseline and args.no_check)
+    if need_oracle:
+        import oracle
+        log("[bench] oracle: layout + FP64 transform on the host")
+        X = oracle.from_cyclic(D.astype(np.complex128), n, p)
+        t0 = time.perf_counter()
+        Y = oracle.fft_axes(X, range(len(n)), oracle.FORWARD)
+        t_oracle = time.perf_counter() - t0
+        if not args.no_cpu_baseline:
+            result["cpu_baseline"] = {
+                "value": round(flops / t_oracle / 1e9, 3), "unit": "GFLOP/s", "cores": oracle.max_threads(),
+                "kind": "oracle",
+                "sample": f"one full {'x'.join(map(str, n))} forward DFT (FP64 separable radix-2, natural order) "
+                          f"of the same seeded input: {t_oracle:.2f} s"}
+        if not args.no_check:
+            got = out.cpu().numpy()
+            result["rel_l2_vs_oracle"] = oracle.rel_l2(got, oracle.to_cyclic(Y, p))
+    plan.close()
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

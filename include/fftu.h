@@ -1,0 +1,186 @@
+/*
+ * fftu.h -- C ABI of the MI355X (gfx950) implementation of the cyclic-to-cyclic
+ * multidimensional FFT with a single all-to-all of Koopman & Bisseling,
+ * "Minimizing communication in the multidimensional FFT" (arXiv 2203.11795).
+ *
+ * What is computed (Section 2.2, Algorithm 2.3 and Theorem 2.1): the
+ * d-dimensional DFT of eq. (1.2),
+ *     Y[k] = sum_j X[j] prod_l omega_{n_l}^{j_l k_l},  omega_n = exp(-2 pi i / n),
+ * of an n_1 x ... x n_d complex array X that is held in the d-dimensional cyclic
+ * distribution over a virtual p_1 x ... x p_d processor grid (Section 1.1,
+ * phi(s, k) = s + k p elementwise), and the result Y is returned in the same
+ * distribution. The P = p_1...p_d virtual processors live in one GPU's HBM; the
+ * one all-to-all of Superstep 1 is a permutation inside that memory.
+ *
+ * Buffer layout (both input and output): N = n_1...n_d complex elements,
+ * interleaved (re, im), stored processor by processor:
+ *     buf[rank(s) * M + lin(k)] = X[s_1 + k_1 p_1, ..., s_d + k_d p_d]
+ * with M = N / P, rank(s) row-major over s (s_d fastest) and lin(k) row-major
+ * over the local index k in [n_1/p_1] x ... x [n_d/p_d] (the paper's local
+ * arrays are row-major, Section 3). With p = (1, ..., 1) this is the ordinary
+ * row-major array.
+ *
+ * Requirements on a plan (Algorithm 2.3, Input): p_l^2 divides n_l for every l.
+ * This implementation also requires every n_l and p_l to be a power of two,
+ * 1 <= d <= FFTU_MAX_DIMS, N < 2^40, n_l/p_l <= 2048 (complex128) or 4096
+ * (complex64), and p_l <= 2048 / 4096 likewise.
+ *
+ * Directions: FFTU_FORWARD uses omega_n = exp(-2 pi i / n) and is unnormalised;
+ * FFTU_INVERSE conjugates every weight and multiplies by 1/N (Section 1.3,
+ * last paragraph), so that inverse(forward(x)) = x.
+ *
+ * Ownership: the caller owns the input and output buffers (device memory). A
+ * plan owns its twiddle table and a workspace of N elements in device memory,
+ * allocated on the device that is current when the plan is created, and freed
+ * by fftu_destroy. Execution calls never allocate and never synchronise.
+ *
+ * Errors: each call returns (or records, for calls returning a handle) a status;
+ * fftu_last_error() returns the status of the last failing or succeeding call
+ * on the calling thread. Argument errors are reported by fftu_plan/fftu_check;
+ * execution calls report only FFTU_ERROR_INVALID_VALUE (NULL plan or buffer,
+ * or a forbidden aliasing) and FFTU_ERROR_DEVICE (a HIP launch error).
+ *
+ * Concurrency: a plan may be executed by one stream at a time (the workspace is
+ * shared by its calls). Different plans are independent.
+ */
+#ifndef FFTU_H
+#define FFTU_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FFTU_MAX_DIMS 8
+
+typedef struct fftu_plan_s *fftu_plan_t;
+
+/* Element types: interleaved complex. */
+typedef enum {
+    FFTU_C64 = 1,  /* float re, float im  (8 bytes)  */
+    FFTU_C128 = 2  /* double re, double im (16 bytes) */
+} fftu_dtype;
+
+typedef enum {
+    FFTU_FORWARD = -1, /* omega_n = exp(-2 pi i / n), unnormalised */
+    FFTU_INVERSE = 1   /* conjugated weights, times 1/N */
+} fftu_direction;
+
+typedef enum {
+    FFTU_SUCCESS = 0,
+    FFTU_ERROR_INVALID_VALUE = 1, /* bad argument: d, n_l, p_l < 1, NULL pointer, bad enum, aliasing */
+    FFTU_ERROR_NOT_DIVISIBLE = 2, /* p_l^2 does not divide n_l (Algorithm 2.3 precondition) */
+    FFTU_ERROR_UNSUPPORTED = 3,   /* valid for the paper's method but outside this build: non-power-of-two
+                                     sizes, d > FFTU_MAX_DIMS, local length above the limit */
+    FFTU_ERROR_OUT_OF_MEMORY = 4, /* device allocation failed */
+    FFTU_ERROR_DEVICE = 5         /* HIP runtime or launch error */
+} fftu_status;
+
+/* Static description of how a plan executes (host-side; see fftu_describe). */
+typedef struct {
+    int32_t d;
+    int64_t N;                /* total elements */
+    int64_t P;                /* virtual processors p_1...p_d */
+    int64_t M;                /* local elements per processor, N / P */
+    int32_t s0_kernels;       /* kernel launches of Superstep 0 (local FFTs) */
+    int32_t exchange_fused;   /* 1: twiddle, permutation, length-p FFTs and scaling run as one kernel */
+    int32_t s2_kernels;       /* extra launches for Supersteps 1-2 when not fused (twiddle, permute, F_p passes) */
+    int32_t launches;         /* kernel launches of one fftu_execute */
+    uint64_t workspace_bytes; /* device workspace owned by the plan */
+    uint64_t table_bytes;     /* device twiddle table owned by the plan */
+} fftu_plan_info;
+
+/* Library version string ("fftu <major>.<minor>"). */
+const char *fftu_version(void);
+
+/* Human-readable name of a status code. Never NULL. */
+const char *fftu_status_string(fftu_status s);
+
+/* Status of the most recent fftu_* call on the calling thread. */
+fftu_status fftu_last_error(void);
+
+/*
+ * Validate a plan request on the host without touching any device.
+ * Returns FFTU_SUCCESS iff fftu_plan with the same arguments would succeed
+ * (device memory permitting). Arguments as for fftu_plan.
+ */
+fftu_status fftu_check(int d, const int64_t n[], const int64_t p[], fftu_dtype dtype, fftu_direction direction);
+
+/*
+ * Host-only dry run of the planner: fills *info for a valid request without
+ * touching any device. Returns the same status as fftu_check.
+ */
+fftu_status fftu_describe(int d, const int64_t n[], const int64_t p[], fftu_dtype dtype,
+                          fftu_direction direction, fftu_plan_info *info);
+
+/*
+ * Create a plan for the d-dimensional transform of an n[0] x ... x n[d-1]
+ * array over the p[0] x ... x p[d-1] virtual grid (Algorithm 2.3).
+ * n and p are host arrays of d entries, read during the call only.
+ * Allocates the twiddle table (omega_L^j, j in [L], L = max n_l, generated in
+ * FP64 on the host; the complex64 table is the FP64 table rounded once) and
+ * an N-element workspace on the current device.
+ * Returns NULL on failure; fftu_last_error() gives the reason.
+ */
+fftu_plan_t fftu_plan(int d, const int64_t n[], const int64_t p[], fftu_dtype dtype, fftu_direction direction);
+
+/* Fill *info for an existing plan. */
+fftu_status fftu_get_plan_info(fftu_plan_t plan, fftu_plan_info *info);
+
+/* Device bytes owned by the plan (table + workspace), for memory admission. */
+size_t fftu_plan_device_bytes(fftu_plan_t plan);
+
+/*
+ * The whole transform (Algorithm 2.3: Superstep 0 local FFTs and twiddle,
+ * Superstep 1 permutation, Superstep 2 length-p FFTs): out = F(in), both in the
+ * cyclic buffer layout above. in and out are device pointers to N elements of
+ * the plan's dtype, on the plan's device; in == out is allowed (in-place);
+ * otherwise the buffers must not overlap and in is left unchanged. Enqueued on
+ * `stream` (0 = the null stream); returns without waiting.
+ */
+fftu_status fftu_execute(fftu_plan_t plan, const void *in, void *out, hipStream_t stream);
+
+/*
+ * The supersteps one at a time, for checking each against its definition.
+ * All use the plan's direction for every weight and none applies 1/N.
+ * Same buffer rules as fftu_execute, except fftu_stage_exchange, which needs
+ * in != out.
+ *
+ *  local_fft:     Y^(s) = (F_{n_1/p_1} x ... x F_{n_d/p_d}) X^(s) for every s   (Superstep 0, first line)
+ *  twiddle:       Z^(s)[k] = prod_l omega_{n_l}^{k_l s_l} Y^(s)[k]                (Superstep 0, loop)
+ *  exchange:      W^(r)[s q + t] = Z^(s)[r + t p], q = n/p^2                     (Superstep 1, the Put)
+ *  remaining_fft: V^(r)(t : q : n/p) = (F_{p_1} x ... x F_{p_d}) W^(r)(t : q : n/p)  (Superstep 2)
+ */
+fftu_status fftu_stage_local_fft(fftu_plan_t plan, const void *in, void *out, hipStream_t stream);
+fftu_status fftu_stage_twiddle(fftu_plan_t plan, const void *in, void *out, hipStream_t stream);
+fftu_status fftu_stage_exchange(fftu_plan_t plan, const void *in, void *out, hipStream_t stream);
+fftu_status fftu_stage_remaining_fft(fftu_plan_t plan, const void *in, void *out, hipStream_t stream);
+
+/*
+ * Per-kernel timing on the execution stream. After fftu_timing_begin(plan, K),
+ * each of the next K calls of fftu_execute on this plan records a HIP event
+ * before its first kernel and after each kernel it launches (on the call's
+ * stream). fftu_timing_end waits for those events, writes the mean duration in
+ * milliseconds of each launch position (launch i of every recorded call) to
+ * avg_ms[0 .. min(capacity, launches) - 1], sets *nkernels to the launches per
+ * call and *ncalls to the calls recorded, and releases the events. The event
+ * pool is created by fftu_timing_begin (host allocation and hipEventCreate);
+ * calls beyond K are not recorded. Returns FFTU_ERROR_INVALID_VALUE without a
+ * preceding fftu_timing_begin.
+ */
+fftu_status fftu_timing_begin(fftu_plan_t plan, int max_calls);
+fftu_status fftu_timing_end(fftu_plan_t plan, float *avg_ms, int capacity, int *nkernels, int *ncalls);
+
+/* Release a plan and its device memory. NULL is ignored. The caller must make
+ * sure no enqueued work still uses the plan. */
+void fftu_destroy(fftu_plan_t plan);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FFTU_H */

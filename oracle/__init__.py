@@ -198,6 +198,83 @@ def _root(nl: int, e: np.ndarray, sign: int) -> np.ndarray:
     return w
 
 
+def _grid(n, p):
+    n, p, m = _local_shape(n, p)
+    for nl, pl in zip(n, p):
+        if nl % (pl * pl):
+            raise ValueError(f"Algorithm 2.3 needs p_l^2 | n_l, got n={n} p={p}")
+    q = tuple(ml // pl for ml, pl in zip(m, p))
+    procs = list(itertools.product(*[range(pl) for pl in p]))   # row-major rank order
+    return n, p, m, q, procs
+
+
+def emulate_local_fft(D: np.ndarray, n, p, direction: int = FORWARD) -> np.ndarray:
+    """Superstep 0, first line: Y^(s) = (F_{m_1} x ... x F_{m_d}) X^(s) on every processor s."""
+    _check_direction(direction)
+    n, p, m, q, procs = _grid(n, p)
+    X = np.asarray(D, dtype=np.complex128).reshape((len(procs),) + m)
+    Y = np.empty_like(X)
+    for rank in range(len(procs)):
+        Y[rank] = fft_axes(X[rank], range(len(n)), direction)
+    return Y.reshape(-1)
+
+
+def emulate_twiddle(Y: np.ndarray, n, p, direction: int = FORWARD) -> np.ndarray:
+    """Superstep 0, loop: Z^(s)[k] = (prod_l omega_{n_l}^{k_l s_l}) Y^(s)[k]; the factor is
+    built dimension by dimension as in Algorithm 3.1 (factor_1, factor_1*factor_2, ...)."""
+    _check_direction(direction)
+    n, p, m, q, procs = _grid(n, p)
+    d = len(n)
+    M = int(np.prod(m))
+    Y = np.asarray(Y, dtype=np.complex128).reshape(len(procs), M)
+    Z = np.empty_like(Y)
+    kgrid = np.indices(m).reshape(d, -1)
+    for rank, s in enumerate(procs):
+        factor = np.ones(M, dtype=np.complex128)
+        for l in range(d):
+            factor = factor * _root(n[l], kgrid[l] * s[l], direction)
+        Z[rank] = factor * Y[rank]
+    return Z.reshape(-1)
+
+
+def emulate_permute(Z: np.ndarray, n, p) -> np.ndarray:
+    """Superstep 1: P(s) puts Z^(s)(r : p : m) into P(r) as W^(r)[s*q : (s+1)*q - 1].
+
+    Pure data movement; the dtype of Z is kept so the result can be compared bit for bit.
+    """
+    n, p, m, q, procs = _grid(n, p)
+    d = len(n)
+    Z = np.asarray(Z)
+    Zv = Z.reshape((len(procs),) + m)
+    W = np.empty_like(Zv)
+    for rank_s, s in enumerate(procs):
+        for rank_r, r in enumerate(procs):
+            dst = tuple(slice(s[l] * q[l], (s[l] + 1) * q[l]) for l in range(d))
+            src = tuple(slice(r[l], None, p[l]) for l in range(d))
+            W[(rank_r,) + dst] = Zv[(rank_s,) + src]
+    return W.reshape(-1)
+
+
+def emulate_remaining_fft(W: np.ndarray, n, p, direction: int = FORWARD) -> np.ndarray:
+    """Superstep 2: V^(r)(t : q : m) = (F_{p_1} x ... x F_{p_d}) W^(r)(t : q : m) for every t.
+
+    Inside a processor the local index is i_l = s'_l q_l + t_l, so the subarray
+    W^(r)(t : q : m) is the (s'_1, ..., s'_d) slice of W^(r) viewed as
+    (p_1, q_1, ..., p_d, q_d); all t are transformed together."""
+    _check_direction(direction)
+    n, p, m, q, procs = _grid(n, p)
+    d = len(n)
+    M = int(np.prod(m))
+    W = np.asarray(W, dtype=np.complex128).reshape(len(procs), M)
+    V = np.empty_like(W)
+    split = []
+    for l in range(d):
+        split += [p[l], q[l]]
+    for rank_r in range(len(procs)):
+        V[rank_r] = fft_axes(W[rank_r].reshape(split), [2 * l for l in range(d)], direction).reshape(-1)
+    return V.reshape(-1)
+
+
 def emulate(D: np.ndarray, n, p, direction: int = FORWARD) -> dict:
     """Run Algorithm 2.3 on the cyclic buffer D and return every intermediate buffer.
 
@@ -209,54 +286,14 @@ def emulate(D: np.ndarray, n, p, direction: int = FORWARD) -> dict:
       "out"     S2, times 1/N for the inverse
     with m = n/p and q = n/p^2 elementwise. INVERSE conjugates every weight.
     """
-    _check_direction(direction)
-    n, p, m = _local_shape(n, p)
-    d = len(n)
-    for nl, pl in zip(n, p):
-        if nl % (pl * pl):
-            raise ValueError(f"Algorithm 2.3 needs p_l^2 | n_l, got n={n} p={p}")
-    q = tuple(ml // pl for ml, pl in zip(m, p))
-    P = int(np.prod(p))
-    M = int(np.prod(m))
-    D = np.asarray(D, dtype=np.complex128).reshape(P, M)
-    procs = list(itertools.product(*[range(pl) for pl in p]))   # row-major rank order
-
-    # Superstep 0: local d-dimensional DFT, then twiddle.
-    Y = np.empty((P, M), dtype=np.complex128)
-    Z = np.empty((P, M), dtype=np.complex128)
-    kgrid = np.indices(m).reshape(d, -1) if d else np.zeros((0, 1), np.int64)
-    for rank, s in enumerate(procs):
-        Ys = fft_axes(D[rank].reshape(m), range(d), direction)
-        Y[rank] = Ys.reshape(-1)
-        factor = np.ones(M, dtype=np.complex128)
-        for l in range(d):
-            factor = factor * _root(n[l], kgrid[l] * s[l], direction)
-        Z[rank] = factor * Y[rank]
-
-    # Superstep 1: P(s) puts Z^(s)(r : p : m) into P(r) as W^(r)[s*q : (s+1)*q - 1].
-    W = np.empty((P, M), dtype=np.complex128)
-    Wv = W.reshape((P,) + m)
-    Zv = Z.reshape((P,) + m)
-    for rank_s, s in enumerate(procs):
-        for rank_r, r in enumerate(procs):
-            dst = tuple(slice(s[l] * q[l], (s[l] + 1) * q[l]) for l in range(d))
-            src = tuple(slice(r[l], None, p[l]) for l in range(d))
-            Wv[(rank_r,) + dst] = Zv[(rank_s,) + src]
-
-    # Superstep 2: d-dimensional DFT of size p over every W^(r)(t : q : m).
-    V = np.empty((P, M), dtype=np.complex128)
-    for rank_r in range(P):
-        split = []
-        for l in range(d):
-            split += [p[l], q[l]]        # local index i_l = s'_l * q_l + t_l
-        Wr = W[rank_r].reshape(split)
-        V[rank_r] = fft_axes(Wr, [2 * l for l in range(d)], direction).reshape(-1)
-
-    out = V.reshape(-1).copy()
+    Y = emulate_local_fft(D, n, p, direction)
+    Z = emulate_twiddle(Y, n, p, direction)
+    W = emulate_permute(Z, n, p)
+    V = emulate_remaining_fft(W, n, p, direction)
+    out = V.copy()
     if direction == INVERSE:
-        out *= 1.0 / (P * M)
-    return {"S0": Y.reshape(-1), "twiddle": Z.reshape(-1), "S1": W.reshape(-1), "S2": V.reshape(-1),
-            "out": out}
+        out *= 1.0 / V.size
+    return {"S0": Y, "twiddle": Z, "S1": W, "S2": V, "out": out}
 
 
 def rel_l2(y: np.ndarray, yref: np.ndarray) -> float:

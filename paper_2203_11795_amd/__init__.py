@@ -1,0 +1,9 @@
+"""MI355X (gfx950) implementation of the cyclic-to-cyclic multidimensional FFT
+with a single all-to-all (Koopman & Bisseling, arXiv 2203.11795, Algorithm 2.3).
+
+The transform runs in the HIP kernels of ``libfftu.so`` (C ABI in
+``include/fftu.h``); :mod:`.fftu` is its Python binding.
+"""
+from .fftu import (C64, C128, FORWARD, INVERSE, FftuError, Plan, check, describe, load_library)
+
+__all__ = ["Plan", "FftuError", "check", "describe", "load_library", "FORWARD", "INVERSE", "C64", "C128"]

@@ -1,0 +1,651 @@
+// Host side of libfftu: argument checks, the planner, twiddle-table generation
+// and the C ABI declared in include/fftu.h.
+//
+// The planner maps Algorithm 2.3 (arXiv 2203.11795) onto kernel launches:
+//   Superstep 0, local FFTs   -> one k_pass launch per group of consecutive local
+//                                dimensions whose tile fits in LDS (innermost first)
+//   Superstep 0, twiddle      \
+//   Superstep 1, the Put       > one k_exchange launch when P <= 64; otherwise
+//   Superstep 2, F_p          /  k_twiddle, k_permute and one k_pass per grid dimension
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "fftu_internal.hpp"
+
+using fftu::ExchangeDesc;
+using fftu::GridDesc;
+using fftu::PassDesc;
+using fftu::Precision;
+
+struct fftu_plan_s {
+    int d = 0;
+    int64_t n[fftu::kMaxDims] = {};
+    int64_t p[fftu::kMaxDims] = {};
+    fftu_dtype dtype = FFTU_C128;
+    fftu_direction dir = FFTU_FORWARD;
+    Precision prec = Precision::F64;
+    size_t esize = 16;
+    int device = 0;
+    void *table = nullptr;
+    void *ws = nullptr;
+    uint64_t table_bytes = 0;
+    uint64_t ws_bytes = 0;
+    GridDesc grid{};                 // geometry, no conjugation or scaling
+    std::vector<PassDesc> s0;        // Superstep 0 local FFT passes
+    std::vector<PassDesc> s2;        // Superstep 2 passes (unfused form)
+    bool fused = false;
+    ExchangeDesc ex{};
+    // per-kernel timing (fftu_timing_begin / fftu_timing_end)
+    std::vector<hipEvent_t> events;  // timing_max x (launches + 1)
+    int timing_max = 0;
+    int timing_used = 0;
+    int launches = 0;
+};
+
+namespace {
+
+thread_local fftu_status g_last = FFTU_SUCCESS;
+
+fftu_status record(fftu_status s)
+{
+    g_last = s;
+    return s;
+}
+
+bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+
+int ilog2(int64_t v)
+{
+    int r = 0;
+    while ((int64_t(1) << r) < v) ++r;
+    return r;
+}
+
+// Largest local length (n_l / p_l) and grid side p_l that one LDS tile can hold.
+int log_tile(fftu_dtype dt) { return dt == FFTU_C128 ? fftu::kLogTileF64 : fftu::kLogTileF32; }
+int64_t max_len(fftu_dtype dt) { return int64_t(1) << log_tile(dt); }
+int log_wmax(fftu_dtype dt) { return dt == FFTU_C128 ? 4 : 5; }       // 256-byte column runs
+
+fftu_status validate(int d, const int64_t n[], const int64_t p[], fftu_dtype dtype, fftu_direction direction)
+{
+    if (d < 1 || !n || !p) return FFTU_ERROR_INVALID_VALUE;
+    if (dtype != FFTU_C64 && dtype != FFTU_C128) return FFTU_ERROR_INVALID_VALUE;
+    if (direction != FFTU_FORWARD && direction != FFTU_INVERSE) return FFTU_ERROR_INVALID_VALUE;
+    if (d > FFTU_MAX_DIMS) return FFTU_ERROR_UNSUPPORTED;
+    for (int l = 0; l < d; ++l)
+        if (n[l] < 1 || p[l] < 1) return FFTU_ERROR_INVALID_VALUE;
+    // Algorithm 2.3, Input: p_l^2 | n_l.
+    for (int l = 0; l < d; ++l)
+        if (n[l] % p[l] != 0 || (n[l] / p[l]) % p[l] != 0) return FFTU_ERROR_NOT_DIVISIBLE;
+    int logN = 0;
+    for (int l = 0; l < d; ++l) {
+        if (!is_pow2(n[l]) || !is_pow2(p[l])) return FFTU_ERROR_UNSUPPORTED;
+        logN += ilog2(n[l]);
+        if (n[l] / p[l] > max_len(dtype) || p[l] > max_len(dtype)) return FFTU_ERROR_UNSUPPORTED;
+    }
+    if (logN >= 40) return FFTU_ERROR_UNSUPPORTED;
+    return FFTU_SUCCESS;
+}
+
+// Radix split of a length 2^logL into stages of at most 16, as even as possible.
+void split_radix(int logL, int32_t *out, int32_t *count)
+{
+    const int nst = (logL + 3) / 4;
+    for (int s = 0; s < nst; ++s) out[s] = logL / nst + (s < logL % nst ? 1 : 0);
+    *count = nst;
+}
+
+// A pass over an array viewed as (A, group..., B).
+PassDesc make_pass(int logA, const std::vector<int> &loglens, int logB, fftu_dtype dt, int lognmax)
+{
+    PassDesc pd{};
+    int logG = 0;
+    for (int v : loglens) logG += v;
+    const int esize = dt == FFTU_C128 ? 16 : 8;
+    int logW = std::min(log_tile(dt) - logG, logB + logA);
+    if (logB >= log_wmax(dt)) logW = std::min(logW, log_wmax(dt));
+    if (logW < 0) logW = 0;
+    pd.logB = logB;
+    pd.logG = logG;
+    pd.logW = logW;
+    pd.logBt = std::min(logB, logW);
+    pd.logTPA = logB >= logW ? logB - logW : 0;
+    pd.GB = int64_t(1) << (logG + logB);
+    pd.tiles = int64_t(1) << (logA + logB - logW);
+    pd.lw = (1 << logW) + (logW >= 2 ? 1 : 0);
+    pd.naxes = int32_t(loglens.size());
+    int stride = 0;
+    for (int i = pd.naxes - 1; i >= 0; --i) {
+        pd.loglen[i] = loglens[i];
+        pd.logstride[i] = stride;
+        stride += loglens[i];
+        split_radix(loglens[i], pd.lograd[i], &pd.nstages[i]);
+    }
+    pd.lognmax = lognmax;
+    pd.conj_in = 0;
+    pd.conj_out = 0;
+    pd.scale = 1.0;
+    pd.lds_bytes = uint32_t(uint32_t(pd.lw) * (1u << logG) * uint32_t(esize));
+    return pd;
+}
+
+struct Geometry {
+    int d;
+    int logn[fftu::kMaxDims], logp[fftu::kMaxDims], logm[fftu::kMaxDims], logq[fftu::kMaxDims];
+    int logP, logM, logN, lognmax;
+};
+
+Geometry geometry(int d, const int64_t n[], const int64_t p[])
+{
+    Geometry G{};
+    G.d = d;
+    for (int l = 0; l < d; ++l) {
+        G.logn[l] = ilog2(n[l]);
+        G.logp[l] = ilog2(p[l]);
+        G.logm[l] = G.logn[l] - G.logp[l];
+        G.logq[l] = G.logm[l] - G.logp[l];
+        G.logP += G.logp[l];
+        G.logM += G.logm[l];
+        G.lognmax = std::max(G.lognmax, G.logn[l]);
+    }
+    G.logN = G.logP + G.logM;
+    return G;
+}
+
+// Superstep 0: group consecutive local dimensions, innermost first, while a tile fits.
+std::vector<PassDesc> plan_s0(const Geometry &G, fftu_dtype dt)
+{
+    std::vector<PassDesc> passes;
+    int l = G.d - 1;
+    while (l >= 0) {
+        if (G.logm[l] == 0) {
+            --l;
+            continue;
+        }
+        int logB = 0;
+        for (int j = l + 1; j < G.d; ++j) logB += G.logm[j];
+        std::vector<int> lens{G.logm[l]};
+        int logG = G.logm[l];
+        const int wneed = std::min(log_wmax(dt), logB);
+        while (l - 1 >= 0 && int(lens.size()) < fftu::kMaxGroup &&
+               logG + G.logm[l - 1] + wneed <= log_tile(dt)) {
+            --l;
+            if (G.logm[l] > 0) lens.insert(lens.begin(), G.logm[l]);
+            logG += G.logm[l];
+        }
+        int logA = G.logP;
+        for (int j = 0; j < l; ++j) logA += G.logm[j];
+        passes.push_back(make_pass(logA, lens, logB, dt, G.lognmax));
+        --l;
+    }
+    return passes;
+}
+
+// Superstep 2 in unfused form: one pass per grid dimension with p_l > 1; inside a
+// destination block the local index splits as (s'_1, t_1, ..., s'_d, t_d).
+std::vector<PassDesc> plan_s2(const Geometry &G, fftu_dtype dt)
+{
+    std::vector<PassDesc> passes;
+    for (int l = G.d - 1; l >= 0; --l) {
+        if (G.logp[l] == 0) continue;
+        int logA = G.logP, logB = G.logq[l];
+        for (int j = 0; j < l; ++j) logA += G.logm[j];
+        for (int j = l + 1; j < G.d; ++j) logB += G.logm[j];
+        passes.push_back(make_pass(logA, {G.logp[l]}, logB, dt, G.lognmax));
+    }
+    return passes;
+}
+
+GridDesc make_grid(const Geometry &G)
+{
+    GridDesc g{};
+    g.d = G.d;
+    g.M = int64_t(1) << G.logM;
+    g.N = int64_t(1) << G.logN;
+    g.lognmax = G.lognmax;
+    int ms = 0, ps = 0;
+    for (int l = G.d - 1; l >= 0; --l) {
+        g.logn[l] = G.logn[l];
+        g.logm[l] = G.logm[l];
+        g.logp[l] = G.logp[l];
+        g.logmstride[l] = ms;
+        g.logpstride[l] = ps;
+        ms += G.logm[l];
+        ps += G.logp[l];
+    }
+    g.conj_in = g.conj_out = 0;
+    g.scale = 1.0;
+    return g;
+}
+
+int bitrev(int x, int bits)
+{
+    int r = 0;
+    for (int i = 0; i < bits; ++i) r |= ((x >> i) & 1) << (bits - 1 - i);
+    return r;
+}
+
+ExchangeDesc make_exchange(const Geometry &G, const GridDesc &g)
+{
+    ExchangeDesc ex{};
+    ex.g = g;
+    ex.logP = G.logP;
+    int lo[fftu::kMaxDims];
+    int acc = 0;
+    for (int l = G.d - 1; l >= 0; --l) {
+        lo[l] = acc;
+        acc += G.logp[l];
+    }
+    for (int b = 0; b < G.logP; ++b)
+        for (int l = 0; l < G.d; ++l)
+            if (b >= lo[l] && b < lo[l] + G.logp[l]) {
+                ex.bit_dim[b] = l;
+                ex.bit_h[b] = b - lo[l];
+            }
+    for (int i = 0; i < (1 << G.logP); ++i) {
+        int64_t off = 0;
+        for (int l = 0; l < G.d; ++l) {
+            const int x = (i >> lo[l]) & ((1 << G.logp[l]) - 1);
+            off += int64_t(bitrev(x, G.logp[l])) << (G.logq[l] + g.logmstride[l]);
+        }
+        ex.okp[i] = off;
+    }
+    return ex;
+}
+
+// omega_L^j = exp(-2 pi i j / L) for j in [L], L = 2^logL, in FP64. Each value is
+// reduced to the first octant by exact symmetries before cosl/sinl, so the table is
+// exactly symmetric and exact at the multiples of L/8's quarter turns.
+void cos_sin(int64_t L, int64_t j, long double &c, long double &s)
+{
+    if (L >= 2 && j >= L / 2) {
+        cos_sin(L, j - L / 2, c, s);
+        c = -c;
+        s = -s;
+        return;
+    }
+    if (L >= 4 && j >= L / 4) {
+        long double c2, s2;
+        cos_sin(L, j - L / 4, c2, s2);
+        c = -s2;
+        s = c2;
+        return;
+    }
+    if (L >= 8 && j > L / 8) {
+        const long double th = 2.0L * 3.14159265358979323846264338327950288L * (long double)(L / 4 - j) / (long double)L;
+        c = sinl(th);
+        s = cosl(th);
+        return;
+    }
+    if (j == 0) {
+        c = 1.0L;
+        s = 0.0L;
+        return;
+    }
+    const long double th = 2.0L * 3.14159265358979323846264338327950288L * (long double)j / (long double)L;
+    c = cosl(th);
+    s = sinl(th);
+}
+
+std::vector<double> make_table_f64(int logL)
+{
+    const int64_t L = int64_t(1) << logL;
+    std::vector<double> t(size_t(2 * L));
+    for (int64_t j = 0; j < L; ++j) {
+        long double c, s;
+        cos_sin(L, j, c, s);
+        t[size_t(2 * j)] = double(c);
+        t[size_t(2 * j + 1)] = -double(s);
+    }
+    return t;
+}
+
+void fill_info(const Geometry &G, const std::vector<PassDesc> &s0, bool fused, size_t nS2, fftu_dtype dt,
+               fftu_plan_info *info)
+{
+    const uint64_t esize = dt == FFTU_C128 ? 16 : 8;
+    info->d = G.d;
+    info->N = int64_t(1) << G.logN;
+    info->P = int64_t(1) << G.logP;
+    info->M = int64_t(1) << G.logM;
+    info->s0_kernels = int32_t(s0.size());
+    info->exchange_fused = fused ? 1 : 0;
+    info->s2_kernels = fused ? 0 : int32_t(2 + nS2);
+    info->launches = info->s0_kernels + (fused ? 1 : info->s2_kernels);
+    info->workspace_bytes = uint64_t(info->N) * esize;
+    info->table_bytes = (uint64_t(1) << G.lognmax) * esize;
+}
+
+fftu_status from_hip(hipError_t e)
+{
+    if (e == hipSuccess) return FFTU_SUCCESS;
+    if (e == hipErrorOutOfMemory) return FFTU_ERROR_OUT_OF_MEMORY;
+    return FFTU_ERROR_DEVICE;
+}
+
+// Records the next timing event of the current call, if timing is on.
+struct Marker {
+    fftu_plan_s *pl;
+    hipStream_t stream;
+    int slot = -1;
+    int next = 0;
+    Marker(fftu_plan_s *p, hipStream_t s) : pl(p), stream(s)
+    {
+        if (pl->timing_max > 0 && pl->timing_used < pl->timing_max) slot = pl->timing_used++;
+    }
+    void mark()
+    {
+        if (slot >= 0 && next <= pl->launches)
+            (void)hipEventRecord(pl->events[size_t(slot) * size_t(pl->launches + 1) + size_t(next++)], stream);
+    }
+};
+
+// Run the passes of one superstep from `in` into `out`: the first pass reads `in`,
+// the rest work in place on `out`. conj_first / conj_last conjugate the chain's
+// first load and last store; scale_last multiplies the last store.
+fftu_status run_passes(const fftu_plan_s *pl, const std::vector<PassDesc> &passes, const void *in, void *out,
+                       int conj_first, int conj_last, double scale_last, hipStream_t stream,
+                       Marker *mk = nullptr)
+{
+    if (passes.empty()) {
+        if (in != out)
+            return from_hip(hipMemcpyAsync(out, in, pl->grid.N * pl->esize, hipMemcpyDeviceToDevice, stream));
+        return FFTU_SUCCESS;
+    }
+    const void *src = in;
+    for (size_t i = 0; i < passes.size(); ++i) {
+        PassDesc pd = passes[i];
+        pd.conj_in = (i == 0) ? conj_first : 0;
+        pd.conj_out = (i + 1 == passes.size()) ? conj_last : 0;
+        pd.scale = (i + 1 == passes.size()) ? scale_last : 1.0;
+        hipError_t e = fftu::launch_pass(pl->prec, src, out, pd, pl->table, stream);
+        if (e != hipSuccess) return from_hip(e);
+        if (mk) mk->mark();
+        src = out;
+    }
+    return FFTU_SUCCESS;
+}
+
+fftu_status check_exec_args(const fftu_plan_s *plan, const void *in, const void *out)
+{
+    if (!plan || !in || !out) return FFTU_ERROR_INVALID_VALUE;
+    if (in != out) {
+        const char *a = static_cast<const char *>(in);
+        const char *b = static_cast<const char *>(out);
+        const size_t bytes = size_t(plan->grid.N) * plan->esize;
+        if (a < b + bytes && b < a + bytes) return FFTU_ERROR_INVALID_VALUE;   // partial overlap
+    }
+    return FFTU_SUCCESS;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *fftu_version(void) { return "fftu 0.1"; }
+
+const char *fftu_status_string(fftu_status s)
+{
+    switch (s) {
+    case FFTU_SUCCESS: return "FFTU_SUCCESS";
+    case FFTU_ERROR_INVALID_VALUE: return "FFTU_ERROR_INVALID_VALUE";
+    case FFTU_ERROR_NOT_DIVISIBLE: return "FFTU_ERROR_NOT_DIVISIBLE";
+    case FFTU_ERROR_UNSUPPORTED: return "FFTU_ERROR_UNSUPPORTED";
+    case FFTU_ERROR_OUT_OF_MEMORY: return "FFTU_ERROR_OUT_OF_MEMORY";
+    case FFTU_ERROR_DEVICE: return "FFTU_ERROR_DEVICE";
+    }
+    return "FFTU_UNKNOWN_STATUS";
+}
+
+fftu_status fftu_last_error(void) { return g_last; }
+
+fftu_status fftu_check(int d, const int64_t n[], const int64_t p[], fftu_dtype dtype, fftu_direction direction)
+{
+    return record(validate(d, n, p, dtype, direction));
+}
+
+fftu_status fftu_describe(int d, const int64_t n[], const int64_t p[], fftu_dtype dtype, fftu_direction direction,
+                          fftu_plan_info *info)
+{
+    fftu_status s = validate(d, n, p, dtype, direction);
+    if (s != FFTU_SUCCESS) return record(s);
+    if (!info) return record(FFTU_ERROR_INVALID_VALUE);
+    const Geometry G = geometry(d, n, p);
+    const auto s0 = plan_s0(G, dtype);
+    const bool fused = G.logP <= fftu::kMaxLogP;
+    const auto s2 = plan_s2(G, dtype);
+    fill_info(G, s0, fused, s2.size(), dtype, info);
+    return record(FFTU_SUCCESS);
+}
+
+fftu_plan_t fftu_plan(int d, const int64_t n[], const int64_t p[], fftu_dtype dtype, fftu_direction direction)
+{
+    fftu_status s = validate(d, n, p, dtype, direction);
+    if (s != FFTU_SUCCESS) {
+        record(s);
+        return nullptr;
+    }
+    fftu_plan_s *pl = new (std::nothrow) fftu_plan_s();
+    if (!pl) {
+        record(FFTU_ERROR_OUT_OF_MEMORY);
+        return nullptr;
+    }
+    pl->d = d;
+    for (int l = 0; l < d; ++l) {
+        pl->n[l] = n[l];
+        pl->p[l] = p[l];
+    }
+    pl->dtype = dtype;
+    pl->dir = direction;
+    pl->prec = dtype == FFTU_C128 ? Precision::F64 : Precision::F32;
+    pl->esize = dtype == FFTU_C128 ? 16 : 8;
+    const Geometry G = geometry(d, n, p);
+    pl->grid = make_grid(G);
+    pl->s0 = plan_s0(G, dtype);
+    pl->s2 = plan_s2(G, dtype);
+    pl->fused = G.logP <= fftu::kMaxLogP;
+    pl->ex = make_exchange(G, pl->grid);
+    {
+        fftu_plan_info info{};
+        fill_info(G, pl->s0, pl->fused, pl->s2.size(), dtype, &info);
+        pl->launches = info.launches;
+    }
+
+    if (hipGetDevice(&pl->device) != hipSuccess) {
+        delete pl;
+        record(FFTU_ERROR_DEVICE);
+        return nullptr;
+    }
+    const std::vector<double> t64 = make_table_f64(G.lognmax);
+    const int64_t L = int64_t(1) << G.lognmax;
+    pl->table_bytes = uint64_t(L) * pl->esize;
+    pl->ws_bytes = uint64_t(pl->grid.N) * pl->esize;
+    hipError_t e = hipMalloc(&pl->table, pl->table_bytes);
+    if (e == hipSuccess) e = hipMalloc(&pl->ws, pl->ws_bytes);
+    if (e == hipSuccess) {
+        if (dtype == FFTU_C128) {
+            e = hipMemcpy(pl->table, t64.data(), pl->table_bytes, hipMemcpyHostToDevice);
+        } else {
+            std::vector<float> t32(t64.size());
+            for (size_t i = 0; i < t64.size(); ++i) t32[i] = float(t64[i]);   // rounded once
+            e = hipMemcpy(pl->table, t32.data(), pl->table_bytes, hipMemcpyHostToDevice);
+        }
+    }
+    if (e != hipSuccess) {
+        fftu_status st = from_hip(e);
+        if (pl->table) (void)hipFree(pl->table);
+        if (pl->ws) (void)hipFree(pl->ws);
+        delete pl;
+        record(st);
+        return nullptr;
+    }
+    record(FFTU_SUCCESS);
+    return pl;
+}
+
+fftu_status fftu_get_plan_info(fftu_plan_t plan, fftu_plan_info *info)
+{
+    if (!plan || !info) return record(FFTU_ERROR_INVALID_VALUE);
+    const Geometry G = geometry(plan->d, plan->n, plan->p);
+    fill_info(G, plan->s0, plan->fused, plan->s2.size(), plan->dtype, info);
+    return record(FFTU_SUCCESS);
+}
+
+size_t fftu_plan_device_bytes(fftu_plan_t plan)
+{
+    if (!plan) {
+        record(FFTU_ERROR_INVALID_VALUE);
+        return 0;
+    }
+    record(FFTU_SUCCESS);
+    return size_t(plan->table_bytes + plan->ws_bytes);
+}
+
+fftu_status fftu_execute(fftu_plan_t plan, const void *in, void *out, hipStream_t stream)
+{
+    fftu_status s = check_exec_args(plan, in, out);
+    if (s != FFTU_SUCCESS) return record(s);
+    Marker mk(plan, stream);
+    mk.mark();
+    const int inv = plan->dir == FFTU_INVERSE ? 1 : 0;
+    const double scale = inv ? 1.0 / double(plan->grid.N) : 1.0;
+    const void *src = in;
+    if (!plan->s0.empty()) {
+        s = run_passes(plan, plan->s0, in, plan->ws, inv, 0, 1.0, stream, &mk);
+        if (s != FFTU_SUCCESS) return record(s);
+        src = plan->ws;
+    } else if (in == out) {
+        // N = 1: the exchange below must not read and write the same buffer.
+        hipError_t e = hipMemcpyAsync(plan->ws, in, plan->grid.N * plan->esize, hipMemcpyDeviceToDevice, stream);
+        if (e != hipSuccess) return record(from_hip(e));
+        src = plan->ws;
+    }
+    const int conj_first = plan->s0.empty() ? inv : 0;
+    if (plan->fused) {
+        ExchangeDesc ex = plan->ex;
+        ex.g.conj_in = conj_first;
+        ex.g.conj_out = inv;
+        ex.g.scale = scale;
+        hipError_t e = fftu::launch_exchange(plan->prec, src, out, ex, plan->table, stream);
+        if (e == hipSuccess) mk.mark();
+        return record(from_hip(e));
+    }
+    GridDesc g = plan->grid;
+    g.conj_in = conj_first;
+    hipError_t e = fftu::launch_twiddle(plan->prec, src, plan->ws, g, plan->table, stream);
+    if (e == hipSuccess) {
+        mk.mark();
+        e = fftu::launch_permute(plan->prec, plan->ws, out, plan->grid, stream);
+    }
+    if (e != hipSuccess) return record(from_hip(e));
+    mk.mark();
+    return record(run_passes(plan, plan->s2, out, out, 0, inv, scale, stream, &mk));
+}
+
+fftu_status fftu_timing_begin(fftu_plan_t plan, int max_calls)
+{
+    if (!plan || max_calls < 1) return record(FFTU_ERROR_INVALID_VALUE);
+    for (hipEvent_t ev : plan->events) (void)hipEventDestroy(ev);
+    plan->events.clear();
+    const size_t count = size_t(max_calls) * size_t(plan->launches + 1);
+    plan->events.reserve(count);
+    for (size_t i = 0; i < count; ++i) {
+        hipEvent_t ev;
+        hipError_t e = hipEventCreate(&ev);
+        if (e != hipSuccess) {
+            for (hipEvent_t x : plan->events) (void)hipEventDestroy(x);
+            plan->events.clear();
+            plan->timing_max = 0;
+            return record(from_hip(e));
+        }
+        plan->events.push_back(ev);
+    }
+    plan->timing_max = max_calls;
+    plan->timing_used = 0;
+    return record(FFTU_SUCCESS);
+}
+
+fftu_status fftu_timing_end(fftu_plan_t plan, float *avg_ms, int capacity, int *nkernels, int *ncalls)
+{
+    if (!plan || plan->timing_max == 0) return record(FFTU_ERROR_INVALID_VALUE);
+    const int L = plan->launches;
+    std::vector<double> sum(size_t(L), 0.0);
+    fftu_status st = FFTU_SUCCESS;
+    for (int c = 0; c < plan->timing_used && st == FFTU_SUCCESS; ++c) {
+        for (int i = 0; i < L; ++i) {
+            hipEvent_t a = plan->events[size_t(c) * size_t(L + 1) + size_t(i)];
+            hipEvent_t b = plan->events[size_t(c) * size_t(L + 1) + size_t(i + 1)];
+            float ms = 0.f;
+            hipError_t e = hipEventSynchronize(b);
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+            if (e != hipSuccess) {
+                st = from_hip(e);
+                break;
+            }
+            sum[size_t(i)] += ms;
+        }
+    }
+    const int used = plan->timing_used;
+    for (int i = 0; avg_ms && i < L && i < capacity; ++i) avg_ms[i] = used ? float(sum[size_t(i)] / used) : 0.f;
+    if (nkernels) *nkernels = L;
+    if (ncalls) *ncalls = used;
+    for (hipEvent_t ev : plan->events) (void)hipEventDestroy(ev);
+    plan->events.clear();
+    plan->timing_max = 0;
+    plan->timing_used = 0;
+    return record(st);
+}
+
+fftu_status fftu_stage_local_fft(fftu_plan_t plan, const void *in, void *out, hipStream_t stream)
+{
+    fftu_status s = check_exec_args(plan, in, out);
+    if (s != FFTU_SUCCESS) return record(s);
+    const int inv = plan->dir == FFTU_INVERSE ? 1 : 0;
+    return record(run_passes(plan, plan->s0, in, out, inv, inv, 1.0, stream));
+}
+
+fftu_status fftu_stage_twiddle(fftu_plan_t plan, const void *in, void *out, hipStream_t stream)
+{
+    fftu_status s = check_exec_args(plan, in, out);
+    if (s != FFTU_SUCCESS) return record(s);
+    GridDesc g = plan->grid;
+    g.conj_in = g.conj_out = plan->dir == FFTU_INVERSE ? 1 : 0;
+    return record(from_hip(fftu::launch_twiddle(plan->prec, in, out, g, plan->table, stream)));
+}
+
+fftu_status fftu_stage_exchange(fftu_plan_t plan, const void *in, void *out, hipStream_t stream)
+{
+    fftu_status s = check_exec_args(plan, in, out);
+    if (s != FFTU_SUCCESS) return record(s);
+    if (in == out) return record(FFTU_ERROR_INVALID_VALUE);
+    return record(from_hip(fftu::launch_permute(plan->prec, in, out, plan->grid, stream)));
+}
+
+fftu_status fftu_stage_remaining_fft(fftu_plan_t plan, const void *in, void *out, hipStream_t stream)
+{
+    fftu_status s = check_exec_args(plan, in, out);
+    if (s != FFTU_SUCCESS) return record(s);
+    const int inv = plan->dir == FFTU_INVERSE ? 1 : 0;
+    return record(run_passes(plan, plan->s2, in, out, inv, inv, 1.0, stream));
+}
+
+void fftu_destroy(fftu_plan_t plan)
+{
+    if (!plan) return;
+    int cur = 0;
+    const bool have_cur = hipGetDevice(&cur) == hipSuccess;
+    if (have_cur && cur != plan->device) (void)hipSetDevice(plan->device);
+    for (hipEvent_t ev : plan->events) (void)hipEventDestroy(ev);
+    if (plan->table) (void)hipFree(plan->table);
+    if (plan->ws) (void)hipFree(plan->ws);
+    if (have_cur && cur != plan->device) (void)hipSetDevice(cur);
+    delete plan;
+    record(FFTU_SUCCESS);
+}
+
+}  // extern "C"

@@ -1,0 +1,484 @@
+// HIP kernels for gfx950 (MI355X) of the cyclic-to-cyclic multidimensional FFT
+// (Koopman & Bisseling, arXiv 2203.11795, Algorithm 2.3).
+//
+//   k_pass      Superstep 0 (and the unfused Superstep 2): batched Stockham FFTs
+//               along a group of consecutive dimensions, one LDS tile per
+//               workgroup, coalesced HBM reads and writes.
+//   k_twiddle   Superstep 0's twiddle loop, Z[k] = prod_l omega_{n_l}^{k_l s_l} Y[k].
+//   k_permute   Superstep 1 on its own: W^(r)[s q + t] = Z^(s)[r + t p].
+//   k_exchange  Superstep 0's twiddle + Superstep 1 + Superstep 2 in one pass:
+//               one thread per local index k gathers the P values Z^(s')[k],
+//               twiddles them, applies F_{p_1} x ... x F_{p_d} in registers and
+//               scatters them to their destinations.
+//
+// Inverse transforms are run as conj(F(conj(x))): conjugation is exact, so this
+// equals the transform with conjugated weights. Only the first load and the last
+// store of a chain conjugate.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <utility>
+
+#include "fftu_internal.hpp"
+
+namespace fftu {
+
+template <typename T>
+struct alignas(2 * sizeof(T)) cx {
+    T x, y;
+};
+
+template <typename T>
+__device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename T>
+__device__ __forceinline__ cx<T> operator-(cx<T> a, cx<T> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename T>
+__device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b)
+{
+    return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename T>
+__device__ __forceinline__ cx<T> conj_if(cx<T> a, int c) { return c ? cx<T>{a.x, -a.y} : a; }
+
+// cos(2 pi j / 32) for j = 0..8; every 32nd root of unity follows by symmetry.
+__host__ __device__ constexpr double cos32_octant(int j)
+{
+    return j == 0 ? 1.0
+         : j == 1 ? 0.98078528040323044912618223613424
+         : j == 2 ? 0.92387953251128675612818318939679
+         : j == 3 ? 0.83146961230254523707878837761791
+         : j == 4 ? 0.70710678118654752440084436210485
+         : j == 5 ? 0.55557023301960222474283081394853
+         : j == 6 ? 0.38268343236508977172845998403040
+         : j == 7 ? 0.19509032201612826784828486847702
+                  : 0.0;
+}
+__host__ __device__ constexpr double cos32(int j)
+{
+    j = ((j % 32) + 32) % 32;
+    return j <= 8 ? cos32_octant(j) : j <= 16 ? -cos32_octant(16 - j) : j <= 24 ? -cos32_octant(j - 16)
+                                                                          : cos32_octant(32 - j);
+}
+__host__ __device__ constexpr double sin32(int j) { return cos32(j - 8); }
+
+// a * omega_R^K with omega_R = exp(-2 pi i / R), R | 32; the quarter turns are exact.
+template <typename T, int R, int K>
+__device__ __forceinline__ cx<T> mul_root(cx<T> a)
+{
+    constexpr int k = ((K % R) + R) % R;
+    if constexpr (k == 0) {
+        return a;
+    } else if constexpr (4 * k == R) {
+        return {a.y, -a.x};
+    } else if constexpr (2 * k == R) {
+        return {-a.x, -a.y};
+    } else if constexpr (4 * k == 3 * R) {
+        return {-a.y, a.x};
+    } else {
+        constexpr int j = k * (32 / R);
+        constexpr T c = static_cast<T>(cos32(j));
+        constexpr T s = static_cast<T>(-sin32(j));
+        return cmul(a, cx<T>{c, s});
+    }
+}
+
+// In-register DFT of length R (power of two <= 32), natural order in and out:
+// radix-2 decimation in time, recursively.
+template <typename T, int R>
+struct Dft {
+    template <int... K>
+    static __device__ __forceinline__ void combine(cx<T> *v, const cx<T> *e, const cx<T> *o,
+                                                   std::integer_sequence<int, K...>)
+    {
+        ((v[K] = e[K] + mul_root<T, R, K>(o[K]), v[K + R / 2] = e[K] - mul_root<T, R, K>(o[K])), ...);
+    }
+    static __device__ __forceinline__ void run(cx<T> *v)
+    {
+        cx<T> e[R / 2], o[R / 2];
+#pragma unroll
+        for (int k = 0; k < R / 2; ++k) {
+            e[k] = v[2 * k];
+            o[k] = v[2 * k + 1];
+        }
+        Dft<T, R / 2>::run(e);
+        Dft<T, R / 2>::run(o);
+        combine(v, e, o, std::make_integer_sequence<int, R / 2>{});
+    }
+};
+template <typename T>
+struct Dft<T, 2> {
+    static __device__ __forceinline__ void run(cx<T> *v)
+    {
+        cx<T> a = v[0], b = v[1];
+        v[0] = a + b;
+        v[1] = a - b;
+    }
+};
+template <typename T>
+struct Dft<T, 1> {
+    static __device__ __forceinline__ void run(cx<T> *) {}
+};
+
+// ---------------------------------------------------------------------------
+// k_pass: one Stockham stage over every line of one group axis, in place in LDS.
+// Stage with radix R after Ns = 2^logNs: butterfly jj reads positions
+// jj + r L/R, multiplies by omega_{Ns R}^{r (jj mod Ns)}, and writes positions
+// (jj div Ns) Ns R + (jj mod Ns) + r Ns. Every thread holds its butterflies'
+// operands in registers across the barrier between the reads and the writes.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct TileMax {
+    static constexpr int value = 1 << (sizeof(T) == 8 ? kLogTileF64 : kLogTileF32);
+};
+
+template <typename T, int R>
+__device__ __forceinline__ void pass_stage(cx<T> *buf, const PassDesc &pd, int logL, int logS, int logNs,
+                                           const cx<T> *__restrict__ table)
+{
+    constexpr int logR = R == 2 ? 1 : R == 4 ? 2 : R == 8 ? 3 : R == 16 ? 4 : 5;
+    constexpr int NU = TileMax<T>::value / R / kPassThreads > 0 ? TileMax<T>::value / R / kPassThreads : 1;
+    const int logW = pd.logW;
+    const int logLR = logL - logR;
+    const int units = 1 << (pd.logG + logW - logR);
+    const int lw = pd.lw;
+    cx<T> v[NU][R];
+    int base[NU], ob[NU];
+#pragma unroll
+    for (int it = 0; it < NU; ++it) {
+        const int u = threadIdx.x + it * kPassThreads;
+        if (u < units) {
+            const int w = u & ((1 << logW) - 1);
+            const int rest = u >> logW;
+            const int jj = rest & ((1 << logLR) - 1);
+            const int other = rest >> logLR;
+            const int lo = other & ((1 << logS) - 1);
+            const int hi = other >> logS;
+            base[it] = (((hi << (logL + logS)) + lo) * lw) + w;
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[it][r] = buf[base[it] + (((jj + (r << logLR)) << logS) * lw)];
+            if (logNs > 0) {
+                const int jm = jj & ((1 << logNs) - 1);
+                const int sh = pd.lognmax - logNs - logR;
+#pragma unroll
+                for (int r = 1; r < R; ++r) v[it][r] = cmul(v[it][r], table[(r * jm) << sh]);
+            }
+            Dft<T, R>::run(v[it]);
+            ob[it] = ((jj >> logNs) << (logNs + logR)) + (jj & ((1 << logNs) - 1));
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < NU; ++it) {
+        const int u = threadIdx.x + it * kPassThreads;
+        if (u < units) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) buf[base[it] + (((ob[it] + (r << logNs)) << logS) * lw)] = v[it][r];
+        }
+    }
+    __syncthreads();
+}
+
+template <typename T>
+__device__ __forceinline__ void pass_tile(const cx<T> *in, cx<T> *out, const PassDesc &pd,
+                                          const cx<T> *__restrict__ table, cx<T> *buf, int64_t t)
+{
+    int64_t a_base, b_base;
+    if (pd.logB >= pd.logW) {
+        a_base = t >> pd.logTPA;
+        b_base = (t & ((int64_t(1) << pd.logTPA) - 1)) << pd.logW;
+    } else {
+        a_base = t << (pd.logW - pd.logBt);
+        b_base = 0;
+    }
+    const int64_t gbase = a_base * pd.GB + b_base;
+    const int tile = 1 << (pd.logG + pd.logW);
+    const int bmask = (1 << pd.logBt) - 1;
+    const int gmask = (1 << pd.logG) - 1;
+
+    // Coalesced load of the tile: element e walks memory order (outer block, group position, inner).
+    for (int e = threadIdx.x; e < tile; e += kPassThreads) {
+        const int b = e & bmask;
+        const int pos = (e >> pd.logBt) & gmask;
+        const int ap = e >> (pd.logBt + pd.logG);
+        const int64_t goff = gbase + int64_t(ap) * pd.GB + (int64_t(pos) << pd.logB) + b;
+        buf[pos * pd.lw + ((ap << pd.logBt) | b)] = conj_if(in[goff], pd.conj_in);
+    }
+    __syncthreads();
+
+    for (int ax = 0; ax < pd.naxes; ++ax) {
+        const int logL = pd.loglen[ax], logS = pd.logstride[ax];
+        int logNs = 0;
+        for (int st = 0; st < pd.nstages[ax]; ++st) {
+            const int logR = pd.lograd[ax][st];
+            switch (logR) {
+            case 1: pass_stage<T, 2>(buf, pd, logL, logS, logNs, table); break;
+            case 2: pass_stage<T, 4>(buf, pd, logL, logS, logNs, table); break;
+            case 3: pass_stage<T, 8>(buf, pd, logL, logS, logNs, table); break;
+            default: pass_stage<T, 16>(buf, pd, logL, logS, logNs, table); break;
+            }
+            logNs += logR;
+        }
+    }
+
+    const T scale = static_cast<T>(pd.scale);
+    for (int e = threadIdx.x; e < tile; e += kPassThreads) {
+        const int b = e & bmask;
+        const int pos = (e >> pd.logBt) & gmask;
+        const int ap = e >> (pd.logBt + pd.logG);
+        const int64_t goff = gbase + int64_t(ap) * pd.GB + (int64_t(pos) << pd.logB) + b;
+        cx<T> v = conj_if(buf[pos * pd.lw + ((ap << pd.logBt) | b)], pd.conj_out);
+        if (pd.scale != 1.0) v = {v.x * scale, v.y * scale};
+        out[goff] = v;
+    }
+}
+
+
+template <typename T>
+__global__ __launch_bounds__(kPassThreads) void k_pass(const cx<T> *in, cx<T> *out, const PassDesc pd,
+                                                       const cx<T> *__restrict__ table)
+{
+    extern __shared__ unsigned char smem_raw[];
+    cx<T> *buf = reinterpret_cast<cx<T> *>(smem_raw);
+    for (int64_t t = blockIdx.x; t < pd.tiles; t += gridDim.x) {
+        pass_tile(in, out, pd, table, buf, t);
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Pointwise kernels over the cyclic buffer (grid-stride over N elements).
+// ---------------------------------------------------------------------------
+
+// Twiddle exponent of local index k on processor s, as a power of
+// omega_{2^lognmax}: sum_l k_l s_l 2^(lognmax - logn_l), reduced mod 2^lognmax.
+__device__ __forceinline__ uint32_t twiddle_exponent(const GridDesc &g, int64_t rank_s, int64_t k)
+{
+    uint32_t e = 0;
+    for (int l = 0; l < g.d; ++l) {
+        const uint32_t kl = uint32_t((k >> g.logmstride[l]) & ((int64_t(1) << g.logm[l]) - 1));
+        const uint32_t sl = uint32_t((rank_s >> g.logpstride[l]) & ((int64_t(1) << g.logp[l]) - 1));
+        e += (kl * sl) << (g.lognmax - g.logn[l]);
+    }
+    return e & ((uint32_t(1) << g.lognmax) - 1);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kPointwiseThreads) void k_twiddle(const cx<T> *in, cx<T> *out, const GridDesc g,
+                                                               const cx<T> *__restrict__ table)
+{
+    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    const int logM = g.logmstride[0] + g.logm[0];
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < g.N; i += stride) {
+        const int64_t s = i >> logM, k = i & ((int64_t(1) << logM) - 1);
+        cx<T> v = cmul(conj_if(in[i], g.conj_in), table[twiddle_exponent(g, s, k)]);
+        out[i] = conj_if(v, g.conj_out);
+    }
+}
+
+// One thread per destination element (r, i): i_l = s_l q_l + t_l, so the source
+// is processor s at local index r + t p.
+template <typename T>
+__global__ __launch_bounds__(kPointwiseThreads) void k_permute(const cx<T> *__restrict__ in, cx<T> *__restrict__ out,
+                                                               const GridDesc g)
+{
+    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    const int logM = g.logmstride[0] + g.logm[0];
+    for (int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; j < g.N; j += stride) {
+        const int64_t r = j >> logM, i = j & ((int64_t(1) << logM) - 1);
+        int64_t s = 0, src = 0;
+        for (int l = 0; l < g.d; ++l) {
+            const int logq = g.logm[l] - g.logp[l];
+            const int64_t il = (i >> g.logmstride[l]) & ((int64_t(1) << g.logm[l]) - 1);
+            const int64_t sl = il >> logq, tl = il & ((int64_t(1) << logq) - 1);
+            const int64_t rl = (r >> g.logpstride[l]) & ((int64_t(1) << g.logp[l]) - 1);
+            s += sl << g.logpstride[l];
+            src += (rl + (tl << g.logp[l])) << g.logmstride[l];
+        }
+        out[j] = in[(s << logM) + src];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_exchange: fused twiddle + permutation + length-p FFTs.
+// ---------------------------------------------------------------------------
+template <typename T, int LOGP>
+__device__ __forceinline__ void exchange_one(const cx<T> *__restrict__ Z, cx<T> *__restrict__ V,
+                                             const ExchangeDesc &ex, const cx<T> *__restrict__ table, int64_t k)
+{
+    constexpr int P = 1 << LOGP;
+    const GridDesc &g = ex.g;
+
+    // Split k into (r, t) per dimension (k_l = r_l + t_l p_l) and form the per-dimension
+    // twiddle steps c_l = k_l 2^(lognmax - logn_l).
+    uint32_t c[kMaxDims];
+    int64_t rank_r = 0, dst_t = 0;
+#pragma unroll
+    for (int l = 0; l < kMaxDims; ++l) {
+        c[l] = 0;
+        if (l < g.d) {
+            const int64_t kl = (k >> g.logmstride[l]) & ((int64_t(1) << g.logm[l]) - 1);
+            const int64_t rl = kl & ((int64_t(1) << g.logp[l]) - 1);
+            const int64_t tl = kl >> g.logp[l];
+            rank_r += rl << g.logpstride[l];
+            dst_t += tl << g.logmstride[l];
+            c[l] = uint32_t(kl) << (g.lognmax - g.logn[l]);
+        }
+    }
+    // Exponent step of bit b of s': bit h of s'_l contributes c_l 2^h.
+    uint32_t gb[LOGP > 0 ? LOGP : 1];
+#pragma unroll
+    for (int b = 0; b < LOGP; ++b) {
+        uint32_t acc = 0;
+#pragma unroll
+        for (int l = 0; l < kMaxDims; ++l)
+            if (ex.bit_dim[b] == l) acc = c[l] << ex.bit_h[b];
+        gb[b] = acc;
+    }
+    const uint32_t emask = (uint32_t(1) << g.lognmax) - 1;
+
+    // Gather Z^(s')[k] for every source s' and twiddle it.
+    cx<T> v[P];
+    uint32_t e[P];
+#pragma unroll
+    for (int i = 0; i < P; ++i) v[i] = Z[int64_t(i) * g.M + k];
+    e[0] = 0;
+#pragma unroll
+    for (int i = 1; i < P; ++i) e[i] = e[i & (i - 1)] + gb[__builtin_ctz(i)];
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+        v[i] = conj_if(v[i], g.conj_in);
+        if (i) v[i] = cmul(v[i], table[e[i] & emask]);
+    }
+
+    // F_{p_1} x ... x F_{p_d}: radix-2 decimation in frequency on every bit of s',
+    // highest bit first, so that each dimension's bits run from high to low.
+#pragma unroll
+    for (int b = LOGP - 1; b >= 0; --b) {
+        const int h = ex.bit_h[b];
+        const int sh = g.lognmax - h - 1;
+#pragma unroll
+        for (int i = 0; i < P; ++i) {
+            if (i & (1 << b)) continue;
+            const cx<T> a = v[i], bb = v[i | (1 << b)];
+            v[i] = a + bb;
+            const int jm = (i >> (b - h)) & ((1 << h) - 1);
+            v[i | (1 << b)] = cmul(a - bb, table[uint32_t(jm) << sh]);
+        }
+    }
+
+    // Scatter: register i holds output k' (bit-reversed per dimension) of destination r.
+    const int64_t obase = (rank_r << (g.logmstride[0] + g.logm[0])) + dst_t;
+    const T scale = static_cast<T>(g.scale);
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+        cx<T> w = conj_if(v[i], g.conj_out);
+        if (g.scale != 1.0) w = {w.x * scale, w.y * scale};
+        V[obase + ex.okp[i]] = w;
+    }
+}
+
+template <typename T, int LOGP>
+__global__ __launch_bounds__(kExchangeThreads) void k_exchange(const cx<T> *__restrict__ Z, cx<T> *__restrict__ V,
+                                                               const ExchangeDesc ex,
+                                                               const cx<T> *__restrict__ table)
+{
+    constexpr int P = 1 << LOGP;
+    const GridDesc &g = ex.g;
+    for (int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; k < g.M; k += int64_t(gridDim.x) * blockDim.x)
+        exchange_one<T, LOGP>(Z, V, ex, table, k);
+}
+
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+namespace {
+constexpr int64_t kMaxBlocks = int64_t(1) << 22;   // keeps blocks x threads below 2^32
+
+template <typename T>
+hipError_t launch_pass_t(const void *in, void *out, const PassDesc &pd, const void *table, hipStream_t stream)
+{
+    const uint32_t blocks = uint32_t(pd.tiles < kMaxBlocks ? pd.tiles : kMaxBlocks);
+    hipLaunchKernelGGL(k_pass<T>, dim3(blocks), dim3(kPassThreads), pd.lds_bytes, stream,
+                       static_cast<const cx<T> *>(in), static_cast<cx<T> *>(out), pd,
+                       static_cast<const cx<T> *>(table));
+    return hipGetLastError();
+}
+
+uint32_t pointwise_blocks(int64_t n)
+{
+    const int64_t want = (n + kPointwiseThreads - 1) / kPointwiseThreads;
+    return uint32_t(want < 262144 ? (want > 0 ? want : 1) : 262144);
+}
+
+template <typename T, int LOGP>
+hipError_t launch_exchange_t(const void *in, void *out, const ExchangeDesc &ex, const void *table,
+                             hipStream_t stream)
+{
+    const int64_t want = (ex.g.M + kExchangeThreads - 1) / kExchangeThreads;
+    const uint32_t blocks = uint32_t(want < kMaxBlocks ? want : kMaxBlocks);
+    hipLaunchKernelGGL((k_exchange<T, LOGP>), dim3(blocks), dim3(kExchangeThreads), 0, stream,
+                       static_cast<const cx<T> *>(in), static_cast<cx<T> *>(out), ex,
+                       static_cast<const cx<T> *>(table));
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_exchange_logp(const void *in, void *out, const ExchangeDesc &ex, const void *table,
+                                hipStream_t stream)
+{
+    switch (ex.logP) {
+    case 0: return launch_exchange_t<T, 0>(in, out, ex, table, stream);
+    case 1: return launch_exchange_t<T, 1>(in, out, ex, table, stream);
+    case 2: return launch_exchange_t<T, 2>(in, out, ex, table, stream);
+    case 3: return launch_exchange_t<T, 3>(in, out, ex, table, stream);
+    case 4: return launch_exchange_t<T, 4>(in, out, ex, table, stream);
+    case 5: return launch_exchange_t<T, 5>(in, out, ex, table, stream);
+    case 6: return launch_exchange_t<T, 6>(in, out, ex, table, stream);
+    default: return hipErrorInvalidValue;
+    }
+}
+}  // namespace
+
+hipError_t launch_pass(Precision prec, const void *in, void *out, const PassDesc &pd, const void *table,
+                       hipStream_t stream)
+{
+    return prec == Precision::F64 ? launch_pass_t<double>(in, out, pd, table, stream)
+                                  : launch_pass_t<float>(in, out, pd, table, stream);
+}
+
+hipError_t launch_twiddle(Precision prec, const void *in, void *out, const GridDesc &g, const void *table,
+                          hipStream_t stream)
+{
+    const uint32_t blocks = pointwise_blocks(g.N);
+    if (prec == Precision::F64)
+        hipLaunchKernelGGL(k_twiddle<double>, dim3(blocks), dim3(kPointwiseThreads), 0, stream,
+                           static_cast<const cx<double> *>(in), static_cast<cx<double> *>(out), g,
+                           static_cast<const cx<double> *>(table));
+    else
+        hipLaunchKernelGGL(k_twiddle<float>, dim3(blocks), dim3(kPointwiseThreads), 0, stream,
+                           static_cast<const cx<float> *>(in), static_cast<cx<float> *>(out), g,
+                           static_cast<const cx<float> *>(table));
+    return hipGetLastError();
+}
+
+hipError_t launch_permute(Precision prec, const void *in, void *out, const GridDesc &g, hipStream_t stream)
+{
+    const uint32_t blocks = pointwise_blocks(g.N);
+    if (prec == Precision::F64)
+        hipLaunchKernelGGL(k_permute<double>, dim3(blocks), dim3(kPointwiseThreads), 0, stream,
+                           static_cast<const cx<double> *>(in), static_cast<cx<double> *>(out), g);
+    else
+        hipLaunchKernelGGL(k_permute<float>, dim3(blocks), dim3(kPointwiseThreads), 0, stream,
+                           static_cast<const cx<float> *>(in), static_cast<cx<float> *>(out), g);
+    return hipGetLastError();
+}
+
+hipError_t launch_exchange(Precision prec, const void *in, void *out, const ExchangeDesc &ex, const void *table,
+                           hipStream_t stream)
+{
+    return prec == Precision::F64 ? launch_exchange_logp<double>(in, out, ex, table, stream)
+                                  : launch_exchange_logp<float>(in, out, ex, table, stream);
+}
+
+}  // namespace fftu

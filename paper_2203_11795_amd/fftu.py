@@ -1,0 +1,242 @@
+"""ctypes binding of libfftu (include/fftu.h): argument marshalling only.
+
+Every step of the transform runs in the HIP kernels of libfftu.so; this module
+only passes device pointers, sizes and streams. PyTorch supplies device memory
+and streams. If the library is missing, loading fails loudly -- there is no
+fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfftu.so")
+
+FORWARD = -1
+INVERSE = 1
+C64 = 1
+C128 = 2
+MAX_DIMS = 8
+
+STATUS = {0: "FFTU_SUCCESS", 1: "FFTU_ERROR_INVALID_VALUE", 2: "FFTU_ERROR_NOT_DIVISIBLE",
+          3: "FFTU_ERROR_UNSUPPORTED", 4: "FFTU_ERROR_OUT_OF_MEMORY", 5: "FFTU_ERROR_DEVICE"}
+
+# Every entry point declared in include/fftu.h.
+EXPORTS = ["fftu_version", "fftu_status_string", "fftu_last_error", "fftu_check", "fftu_describe", "fftu_plan",
+           "fftu_get_plan_info", "fftu_plan_device_bytes", "fftu_execute", "fftu_stage_local_fft",
+           "fftu_stage_twiddle", "fftu_stage_exchange", "fftu_stage_remaining_fft", "fftu_timing_begin",
+           "fftu_timing_end", "fftu_destroy"]
+
+
+class FftuError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = int(status)
+        super().__init__(f"{where}: {STATUS.get(self.status, self.status)}")
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("d", ctypes.c_int32), ("N", ctypes.c_int64), ("P", ctypes.c_int64), ("M", ctypes.c_int64),
+                ("s0_kernels", ctypes.c_int32), ("exchange_fused", ctypes.c_int32),
+                ("s2_kernels", ctypes.c_int32), ("launches", ctypes.c_int32),
+                ("workspace_bytes", ctypes.c_uint64), ("table_bytes", ctypes.c_uint64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libfftu.so and declare the signatures. Raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"libfftu.so is not built ({path}); run `python -m paper_2203_11795_amd.build`")
+    lib = ctypes.CDLL(path)
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    vp = ctypes.c_void_p
+    lib.fftu_version.restype = ctypes.c_char_p
+    lib.fftu_version.argtypes = []
+    lib.fftu_status_string.restype = ctypes.c_char_p
+    lib.fftu_status_string.argtypes = [ctypes.c_int]
+    lib.fftu_last_error.restype = ctypes.c_int
+    lib.fftu_last_error.argtypes = []
+    lib.fftu_check.restype = ctypes.c_int
+    lib.fftu_check.argtypes = [ctypes.c_int, i64p, i64p, ctypes.c_int, ctypes.c_int]
+    lib.fftu_describe.restype = ctypes.c_int
+    lib.fftu_describe.argtypes = [ctypes.c_int, i64p, i64p, ctypes.c_int, ctypes.c_int, ctypes.POINTER(PlanInfo)]
+    lib.fftu_plan.restype = vp
+    lib.fftu_plan.argtypes = [ctypes.c_int, i64p, i64p, ctypes.c_int, ctypes.c_int]
+    lib.fftu_get_plan_info.restype = ctypes.c_int
+    lib.fftu_get_plan_info.argtypes = [vp, ctypes.POINTER(PlanInfo)]
+    lib.fftu_plan_device_bytes.restype = ctypes.c_size_t
+    lib.fftu_plan_device_bytes.argtypes = [vp]
+    for name in ["fftu_execute", "fftu_stage_local_fft", "fftu_stage_twiddle", "fftu_stage_exchange",
+                 "fftu_stage_remaining_fft"]:
+        fn = getattr(lib, name)
+        fn.restype = ctypes.c_int
+        fn.argtypes = [vp, vp, vp, vp]
+    lib.fftu_timing_begin.restype = ctypes.c_int
+    lib.fftu_timing_begin.argtypes = [vp, ctypes.c_int]
+    lib.fftu_timing_end.restype = ctypes.c_int
+    lib.fftu_timing_end.argtypes = [vp, ctypes.POINTER(ctypes.c_float), ctypes.c_int,
+                                    ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
+    lib.fftu_destroy.restype = None
+    lib.fftu_destroy.argtypes = [vp]
+    _lib = lib
+    return lib
+
+
+def _arr(vals):
+    vals = [int(v) for v in vals]
+    return (ctypes.c_int64 * len(vals))(*vals)
+
+
+def _dtype_code(dtype) -> int:
+    name = str(dtype)
+    if name.endswith("complex128"):
+        return C128
+    if name.endswith("complex64"):
+        return C64
+    if dtype in (C64, C128):
+        return int(dtype)
+    raise ValueError(f"dtype must be complex64 or complex128, got {dtype!r}")
+
+
+def check(n, p, dtype="complex128", direction=FORWARD) -> int:
+    """Host-only validation (fftu_check); returns the status code."""
+    lib = load_library()
+    return int(lib.fftu_check(len(n), _arr(n), _arr(p), _dtype_code(dtype), int(direction)))
+
+
+def describe(n, p, dtype="complex128", direction=FORWARD) -> dict:
+    """Host-only planner dry run (fftu_describe)."""
+    lib = load_library()
+    info = PlanInfo()
+    st = lib.fftu_describe(len(n), _arr(n), _arr(p), _dtype_code(dtype), int(direction), ctypes.byref(info))
+    if st != 0:
+        raise FftuError(st, "fftu_describe")
+    return info.as_dict()
+
+
+@dataclass
+class _Shape:
+    n: tuple
+    p: tuple
+
+
+class Plan:
+    """A plan for the cyclic-to-cyclic d-D FFT (Algorithm 2.3) of an n-array on a p-grid.
+
+    Buffers are torch tensors on the plan's device holding N complex elements
+    in the cyclic buffer layout (processor-major; see include/fftu.h).
+    """
+
+    def __init__(self, n, p, dtype="complex128", direction=FORWARD):
+        self.n = tuple(int(v) for v in n)
+        self.p = tuple(int(v) for v in p)
+        if len(self.n) != len(self.p):
+            raise ValueError("n and p must have the same length")
+        self.dtype_code = _dtype_code(dtype)
+        self.direction = int(direction)
+        self._lib = load_library()
+        h = self._lib.fftu_plan(len(self.n), _arr(self.n), _arr(self.p), self.dtype_code, self.direction)
+        if not h:
+            raise FftuError(self._lib.fftu_last_error(), "fftu_plan")
+        self._h = ctypes.c_void_p(h)
+        self.N = 1
+        for v in self.n:
+            self.N *= v
+
+    # -- introspection
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self) -> dict:
+        info = PlanInfo()
+        st = self._lib.fftu_get_plan_info(self._h, ctypes.byref(info))
+        if st != 0:
+            raise FftuError(st, "fftu_get_plan_info")
+        return info.as_dict()
+
+    def device_bytes(self) -> int:
+        return int(self._lib.fftu_plan_device_bytes(self._h))
+
+    @property
+    def torch_dtype(self):
+        import torch
+        return torch.complex128 if self.dtype_code == C128 else torch.complex64
+
+    # -- execution on raw pointers (device addresses, hipStream_t)
+    def execute_ptr(self, in_ptr: int, out_ptr: int, stream: int = 0, entry: str = "fftu_execute") -> None:
+        fn = getattr(self._lib, entry)
+        st = fn(self._h, ctypes.c_void_p(in_ptr), ctypes.c_void_p(out_ptr), ctypes.c_void_p(stream))
+        if st != 0:
+            raise FftuError(st, entry)
+
+    # -- execution on torch tensors
+    def _check_tensor(self, t, name):
+        import torch
+        if not isinstance(t, torch.Tensor) or not t.is_cuda:
+            raise TypeError(f"{name} must be a device tensor")
+        if t.dtype != self.torch_dtype or t.numel() != self.N or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous {self.torch_dtype} tensor of {self.N} elements")
+
+    def _run(self, entry, x, out, stream):
+        import torch
+        self._check_tensor(x, "input")
+        if out is None:
+            out = torch.empty_like(x)
+        self._check_tensor(out, "output")
+        if stream is None:
+            stream = torch.cuda.current_stream(x.device)
+        self.execute_ptr(x.data_ptr(), out.data_ptr(), int(stream.cuda_stream), entry)
+        return out
+
+    def __call__(self, x, out=None, stream=None):
+        """out = F(x) (forward) or F^{-1}(x) (inverse), asynchronously on `stream`."""
+        return self._run("fftu_execute", x, out, stream)
+
+    def stage(self, name: str, x, out=None, stream=None):
+        """Run one superstep: 'local_fft', 'twiddle', 'exchange' or 'remaining_fft'."""
+        if name not in ("local_fft", "twiddle", "exchange", "remaining_fft"):
+            raise ValueError(f"unknown stage {name!r}")
+        return self._run(f"fftu_stage_{name}", x, out, stream)
+
+    # -- per-kernel timing with HIP events on the execution stream
+    def timing_begin(self, max_calls: int) -> None:
+        st = self._lib.fftu_timing_begin(self._h, int(max_calls))
+        if st != 0:
+            raise FftuError(st, "fftu_timing_begin")
+
+    def timing_end(self):
+        """Mean milliseconds of each launch position over the recorded calls, and the call count."""
+        cap = 64
+        buf = (ctypes.c_float * cap)()
+        nk, nc = ctypes.c_int(0), ctypes.c_int(0)
+        st = self._lib.fftu_timing_end(self._h, buf, cap, ctypes.byref(nk), ctypes.byref(nc))
+        if st != 0:
+            raise FftuError(st, "fftu_timing_end")
+        return [float(buf[i]) for i in range(min(nk.value, cap))], nc.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.fftu_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

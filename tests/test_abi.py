@@ -1,0 +1,123 @@
+"""Host-side checks of the C-ABI library: it loads, exports every entry point that
+include/fftu.h declares, and validates plans (Algorithm 2.3's precondition
+p_l^2 | n_l and this build's limits) without touching a device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2203_11795_amd as fftu
+from paper_2203_11795_amd import fftu as binding
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fftu.h")
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(fftu_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function():
+    lib = fftu.load_library()
+    names = declared_functions()
+    assert len(names) >= 14
+    for name in names:
+        assert hasattr(lib, name), name
+    assert sorted(binding.EXPORTS) == names
+
+
+def test_version_and_status_strings():
+    lib = fftu.load_library()
+    assert lib.fftu_version().startswith(b"fftu ")
+    for code, name in binding.STATUS.items():
+        assert lib.fftu_status_string(code).decode() == name
+    assert lib.fftu_status_string(99) == b"FFTU_UNKNOWN_STATUS"
+
+
+@pytest.mark.parametrize("n,p,expect", [
+    ((512, 512, 512), (4, 4, 4), 0),
+    ((64, 64, 64), (2, 2, 2), 0),
+    ((64,) * 5, (2,) * 5, 0),
+    ((8,), (2,), 0),
+    ((1,), (1,), 0),
+    ((16,), (4,), 0),            # p^2 = n: q = 1
+    ((8,), (4,), 2),             # 16 does not divide 8
+    ((32, 32), (2, 8), 2),
+    ((12,), (2,), 3),            # p^2 | n holds, but 12 is not a power of two
+    ((12,), (3,), 2),
+    ((64,) * 9, (2,) * 9, 3),    # d > 8
+    ((0,), (1,), 1),
+    ((8,), (0,), 1),
+    ((1 << 24, 64), (1, 1), 3),  # local length above one LDS tile
+])
+def test_check_status(n, p, expect):
+    assert fftu.check(n, p) == expect
+    assert fftu.load_library().fftu_last_error() == expect
+
+
+def test_check_rejects_bad_enums_and_null():
+    lib = fftu.load_library()
+    n = binding._arr([8])
+    p = binding._arr([2])
+    assert lib.fftu_check(1, n, p, 3, -1) == 1
+    assert lib.fftu_check(1, n, p, 2, 0) == 1
+    assert lib.fftu_check(0, n, p, 2, -1) == 1
+    assert lib.fftu_check(1, None, p, 2, -1) == 1
+    assert lib.fftu_execute(None, None, None, None) == 1
+    assert lib.fftu_get_plan_info(None, None) == 1
+    lib.fftu_destroy(None)
+
+
+def test_p_max_examples():
+    """eq. (2.13) and the examples after it: the largest grid with one all-to-all is
+    accepted, and doubling any side of it is rejected as not divisible."""
+    for line in open(os.path.join(GOLDEN, "pmax_examples.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        shape_s, pmax_s = line.split()
+        n = tuple(int(v) for v in shape_s.split("x"))
+        grid = []
+        for nl in n:
+            e = nl.bit_length() - 1
+            grid.append(1 << (e // 2))
+        prod = 1
+        for g in grid:
+            prod *= g
+        assert prod == int(pmax_s)
+        st = fftu.check(n, grid)
+        assert st in (0, 3)     # 3 only where a local length exceeds one tile (2^24 x 64)
+        for l in range(len(n)):
+            bigger = list(grid)
+            bigger[l] *= 2
+            assert fftu.check(n, bigger) == 2
+
+
+@pytest.mark.parametrize("n,p,dtype,s0,fused,launches", [
+    ((512, 512, 512), (4, 4, 4), "complex128", 3, 1, 4),
+    ((64, 64, 64), (2, 2, 2), "complex128", 2, 1, 3),
+    ((64,) * 5, (2,) * 5, "complex64", 4, 1, 5),
+    ((1024,) * 3, (16, 16, 16), "complex128", 3, 0, 8),
+    ((1,), (1,), "complex128", 0, 1, 1),
+])
+def test_describe(n, p, dtype, s0, fused, launches):
+    info = fftu.describe(n, p, dtype)
+    N = 1
+    for v in n:
+        N *= v
+    P = 1
+    for v in p:
+        P *= v
+    assert info["N"] == N and info["P"] == P and info["M"] == N // P
+    assert info["s0_kernels"] == s0 and info["exchange_fused"] == fused and info["launches"] == launches
+    assert info["workspace_bytes"] == N * (16 if dtype == "complex128" else 8)
+    with pytest.raises(fftu.FftuError):
+        fftu.describe((8,), (4,))
+
+
+def test_info_struct_layout_matches_header():
+    # int32 d, int64 N, P, M, 4 x int32, 2 x uint64
+    assert ctypes.sizeof(binding.PlanInfo) == 4 + 4 + 8 * 3 + 4 * 4 + 8 * 2

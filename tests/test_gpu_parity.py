@@ -1,0 +1,206 @@
+"""Parity of the HIP path with the FP64 oracle, element by element, through the C ABI.
+
+Tolerances (relative L2 over all outputs): 1e-12 for complex128, 5e-6 for
+complex64. The permutation of Superstep 1 moves data only and must match the
+emulator of Algorithm 2.3 bit for bit.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import FORWARD, INVERSE
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"complex128": 1e-12, "complex64": 5e-6}
+NP_DTYPE = {"complex128": np.complex128, "complex64": np.complex64}
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2203_11795_amd as fftu
+    fftu.load_library()
+    return torch
+
+
+def say(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def run_plan(torch, n, p, dtype, direction, D, entry=None, out_init=None, inplace=False):
+    import paper_2203_11795_amd as fftu
+    plan = fftu.Plan(n, p, dtype, direction)
+    x = torch.from_numpy(np.ascontiguousarray(D.astype(NP_DTYPE[dtype]))).to("cuda")
+    if inplace:
+        out = x
+    elif out_init is not None:
+        out = torch.from_numpy(out_init.astype(NP_DTYPE[dtype])).to("cuda")
+    else:
+        out = torch.empty_like(x)
+    if entry is None:
+        plan(x, out)
+    else:
+        plan.stage(entry, x, out)
+    torch.cuda.synchronize()
+    res = out.cpu().numpy()
+    plan.close()
+    return res
+
+
+CASES = [
+    ((64, 64, 64), (2, 2, 2)),        # the 64^3 configuration
+    ((8,), (2,)),                     # Algorithm 2.2, n = 8, p = 2
+    ((16,), (4,)),                    # q = 1
+    ((4,), (2,)),
+    ((1,), (1,)),                     # N = 1
+    ((2,), (1,)),
+    ((256,), (1,)),                   # plain 1-D FFT
+    ((1024,), (32,)),
+    ((16, 8), (2, 2)),
+    ((64, 64), (8, 8)),               # P = 64, q = 1
+    ((16, 16, 4), (4, 2, 2)),
+    ((4, 16, 8), (2, 2, 2)),          # uneven sides
+    ((8, 1, 4), (2, 1, 1)),           # a side of 1
+    ((32, 8, 4, 16), (2, 2, 1, 4)),
+    ((4, 4, 4, 4, 4), (2, 2, 2, 2, 2)),
+    ((16, 16, 16), (4, 4, 4)),        # P = 64 in registers
+    ((64, 64, 64), (8, 8, 2)),        # P = 128: unfused twiddle / permute / F_p passes
+    ((4,) * 8, (2,) * 8),             # d = 8, P = 256, unfused
+    ((128, 128, 32), (1, 1, 1)),      # ordinary row-major fftn
+    ((2048,), (1,)),                  # longest complex128 line in one tile
+    ((32, 2048), (2, 4)),
+]
+
+
+@pytest.mark.parametrize("dtype", ["complex128", "complex64"])
+@pytest.mark.parametrize("direction", [FORWARD, INVERSE])
+@pytest.mark.parametrize("n,p", CASES, ids=[f"{'x'.join(map(str, n))}-p{'x'.join(map(str, p))}" for n, p in CASES])
+def test_end_to_end_matches_oracle(torch_dev, n, p, dtype, direction):
+    N = int(np.prod(n))
+    seed = 1 + N % 1000 + 7 * len(n)
+    say(f"e2e n={n} p={p} {dtype} dir={direction} seed={seed}")
+    D = synth.uniform_complex(N, seed, NP_DTYPE[dtype])
+    got = run_plan(torch_dev, n, p, dtype, direction, D)
+    want = oracle.cyclic_dft(D.astype(np.complex128), n, p, direction)
+    err = oracle.rel_l2(got, want)
+    assert err <= TOL[dtype], f"rel-L2 {err:.3e}"
+
+
+def test_complex64_longest_line(torch_dev):
+    n, p = (4096,), (1,)
+    D = synth.uniform_complex(4096, 11, np.complex64)
+    got = run_plan(torch_dev, n, p, "complex64", FORWARD, D)
+    assert oracle.rel_l2(got, oracle.cyclic_dft(D.astype(np.complex128), n, p)) <= TOL["complex64"]
+
+
+def test_forward_inverse_64cubed(torch_dev):
+    """The 64^3 / 2x2x2 configuration: forward checked against the oracle, then the
+    inverse of the GPU result checked against the original input."""
+    n, p = (64, 64, 64), (2, 2, 2)
+    D = synth.uniform_complex(64 ** 3, 1)
+    Y = run_plan(torch_dev, n, p, "complex128", FORWARD, D)
+    assert oracle.rel_l2(Y, oracle.cyclic_dft(D, n, p)) <= 1e-12
+    X = run_plan(torch_dev, n, p, "complex128", INVERSE, Y)
+    assert oracle.rel_l2(X, D) <= 1e-12
+
+
+STAGE_CASES = [((64, 64, 64), (2, 2, 2)), ((16, 16, 4), (4, 2, 2)), ((32, 8, 4, 16), (2, 2, 1, 4)),
+               ((64, 64, 64), (8, 8, 2)), ((16,), (4,))]
+
+
+@pytest.mark.parametrize("dtype", ["complex128", "complex64"])
+@pytest.mark.parametrize("direction", [FORWARD, INVERSE])
+@pytest.mark.parametrize("n,p", STAGE_CASES)
+def test_each_superstep_matches_emulator(torch_dev, n, p, dtype, direction):
+    N = int(np.prod(n))
+    say(f"stages n={n} p={p} {dtype} dir={direction}")
+    D = synth.uniform_complex(N, 3, NP_DTYPE[dtype]).astype(np.complex128)
+    st = oracle.emulate(D, n, p, direction)
+    tol = TOL[dtype]
+    got = run_plan(torch_dev, n, p, dtype, direction, D, "local_fft")
+    assert oracle.rel_l2(got, st["S0"]) <= tol
+    Yin = st["S0"].astype(NP_DTYPE[dtype]).astype(np.complex128)
+    got = run_plan(torch_dev, n, p, dtype, direction, Yin, "twiddle")
+    assert oracle.rel_l2(got, oracle.emulate_twiddle(Yin, n, p, direction)) <= (1e-15 if dtype == "complex128"
+                                                                                 else 1e-6)
+    Z = st["twiddle"].astype(NP_DTYPE[dtype])
+    got = run_plan(torch_dev, n, p, dtype, direction, Z, "exchange")
+    assert np.array_equal(got, oracle.emulate_permute(Z, n, p)), "Superstep 1 must be an exact permutation"
+    got = run_plan(torch_dev, n, p, dtype, direction, st["S1"], "remaining_fft")
+    assert oracle.rel_l2(got, st["S2"]) <= tol
+
+
+@pytest.mark.parametrize("dtype", ["complex128", "complex64"])
+@pytest.mark.parametrize("n,p", [((64, 64, 64), (2, 2, 2)), ((16, 16, 16), (4, 4, 4)), ((64, 64, 64), (8, 8, 2)),
+                                 ((4, 4, 4, 4, 4), (2, 2, 2, 2, 2))])
+def test_impulse_at_origin_gives_exact_ones(torch_dev, n, p, dtype):
+    N = int(np.prod(n))
+    D = np.zeros(N, np.complex128)
+    D[0] = 1.0               # global element 0 is local element 0 of processor 0
+    got = run_plan(torch_dev, n, p, dtype, FORWARD, D)
+    assert np.array_equal(got, np.ones(N, NP_DTYPE[dtype]))
+
+
+@pytest.mark.parametrize("n,p", [((64, 64, 64), (2, 2, 2)), ((64, 64, 64), (8, 8, 2)), ((1,), (1,))])
+def test_in_place_equals_out_of_place_and_is_deterministic(torch_dev, n, p):
+    N = int(np.prod(n))
+    D = synth.uniform_complex(N, 21)
+    a = run_plan(torch_dev, n, p, "complex128", FORWARD, D)
+    b = run_plan(torch_dev, n, p, "complex128", FORWARD, D, inplace=True)
+    c = run_plan(torch_dev, n, p, "complex128", FORWARD, D)
+    assert np.array_equal(a, b)
+    assert np.array_equal(a, c)
+
+
+@pytest.mark.parametrize("n,p", [((64, 64, 64), (2, 2, 2)), ((32, 8, 4, 16), (2, 2, 1, 4)), ((16,), (4,))])
+def test_exchange_writes_every_output_once(torch_dev, n, p):
+    """NaN sentinels in the output must all be overwritten, and W is a permutation of Z."""
+    N = int(np.prod(n))
+    Z = synth.uniform_complex(N, 5)
+    sentinel = np.full(N, np.nan + 1j * np.nan)
+    got = run_plan(torch_dev, n, p, "complex128", FORWARD, Z, "exchange", out_init=sentinel)
+    assert not np.isnan(got).any()
+    assert np.array_equal(np.sort_complex(got), np.sort_complex(Z))
+
+
+def test_input_left_unchanged(torch_dev):
+    import paper_2203_11795_amd as fftu
+    torch = torch_dev
+    n, p = (64, 64, 64), (2, 2, 2)
+    D = synth.uniform_complex(64 ** 3, 8)
+    x = torch.from_numpy(D).to("cuda")
+    with fftu.Plan(n, p, "complex128", FORWARD) as plan:
+        plan(x)
+        torch.cuda.synchronize()
+    assert np.array_equal(x.cpu().numpy(), D)
+
+
+def test_execute_rejects_partial_overlap(torch_dev):
+    import paper_2203_11795_amd as fftu
+    torch = torch_dev
+    x = torch.zeros(2 * 4096, dtype=torch.complex128, device="cuda")
+    with fftu.Plan((4096,), (8,), "complex128", FORWARD) as plan:
+        with pytest.raises(fftu.FftuError):
+            plan.execute_ptr(x.data_ptr(), x.data_ptr() + 16 * 7, 0)
+        with pytest.raises(fftu.FftuError):
+            plan.stage("exchange", x[:4096], x[:4096])
+
+
+def test_512_cubed_full_size(torch_dev):
+    """The 512^3 complex128 configuration on the 4x4x4 grid, in the launch
+    configuration the benchmark times, checked over all 2^27 outputs."""
+    n, p = (512, 512, 512), (4, 4, 4)
+    N = 512 ** 3
+    say("512^3 full size: generating input")
+    D = synth.uniform_complex(N, 2)
+    got = run_plan(torch_dev, n, p, "complex128", FORWARD, D)
+    say("512^3 full size: oracle")
+    want = oracle.cyclic_dft(D, n, p)
+    err = oracle.rel_l2(got, want)
+    say(f"512^3 rel-L2 {err:.3e}")
+    assert err <= 1e-12
