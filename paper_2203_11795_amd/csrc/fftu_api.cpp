@@ -230,9 +230,11 @@ int bitrev(int x, int bits)
     return r;
 }
 
+// Only for grids with P <= 2^kMaxLogP (the register-resident form).
 ExchangeDesc make_exchange(const Geometry &G, const GridDesc &g)
 {
     ExchangeDesc ex{};
+    if (G.logP > fftu::kMaxLogP) return ex;
     ex.g = g;
     ex.logP = G.logP;
     int lo[fftu::kMaxDims];
@@ -449,7 +451,7 @@ fftu_plan_t fftu_plan(int d, const int64_t n[], const int64_t p[], fftu_dtype dt
     pl->s0 = plan_s0(G, dtype);
     pl->s2 = plan_s2(G, dtype);
     pl->fused = G.logP <= fftu::kMaxLogP;
-    pl->ex = make_exchange(G, pl->grid);
+    if (pl->fused) pl->ex = make_exchange(G, pl->grid);
     {
         fftu_plan_info info{};
         fill_info(G, pl->s0, pl->fused, pl->s2.size(), dtype, &info);
