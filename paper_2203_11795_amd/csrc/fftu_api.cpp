@@ -5,7 +5,7 @@
 //   Superstep 0, local FFTs   -> one k_pass launch per group of consecutive local
 //                                dimensions whose tile fits in LDS (innermost first)
 //   Superstep 0, twiddle      \
-//   Superstep 1, the Put       > one k_exchange launch when P <= 64; otherwise
+//   Superstep 1, the Put       > one k_exchange launch when the grid splits (see exchange_split);
 //   Superstep 2, F_p          /  k_twiddle, k_permute and one k_pass per grid dimension
 #include <hip/hip_runtime.h>
 
@@ -100,10 +100,65 @@ void split_radix(int logL, int32_t *out, int32_t *count)
     *count = nst;
 }
 
+// k_line for a single dimension of length 2^logL when a good layout exists;
+// returns false to fall back to the generic tile pass.
+bool make_line_pass(int logA, int logL, int logB, fftu_dtype dt, int lognmax, PassDesc &pd)
+{
+    if (logL < 1 || logL > 12) return false;
+    const int esize = dt == FFTU_C128 ? 16 : 8;
+    const int logTPL = logL - fftu::line_loge(logL);
+    const int64_t L = int64_t(1) << logL;
+    const int64_t lds_cap = 64 * 1024;
+    pd = PassDesc{};
+    pd.loglen[0] = logL;
+    pd.naxes = 1;
+    pd.logB = logB;
+    pd.logG = logL;
+    pd.GB = int64_t(1) << (logL + logB);
+    pd.lognmax = lognmax;
+    pd.scale = 1.0;
+    if (logB >= 2) {
+        // columns: W consecutive b per workgroup, W*esize bytes per row run
+        int logW = std::min(log_wmax(dt), logB);
+        while (logW > 0 && ((int64_t(1) << logW) * L + L) * esize > lds_cap) --logW;
+        while (logW > 0 && (logW + logTPL) > 8) --logW;
+        if (logW < 2) return false;
+        pd.kind = fftu::kLineStrided;
+        pd.logW = logW;
+        pd.logBt = logW;
+        pd.logTPA = logB - logW;
+        pd.lw = (1 << logW) + 1;
+        pd.tiles = int64_t(1) << (logA + logB - logW);
+        pd.threads = 1 << (logW + logTPL);
+        pd.lds_bytes = uint32_t((L + L * pd.lw) * esize);
+        return true;
+    }
+    if (logB == 0) {
+        // contiguous lines: about one LDS tile of lines per workgroup
+        int logW = std::max(0, log_tile(dt) - logL);
+        logW = std::min(logW, logA);
+        while (logW > 0 && (logW + logTPL) > 8) --logW;
+        if (logW + logTPL > 8) return false;
+        pd.kind = ((int64_t(1) << logTPL) * esize >= 128) ? fftu::kLineContig : fftu::kLineStaged;
+        pd.logW = logW;
+        pd.logBt = 0;
+        pd.logTPA = 0;
+        pd.lw = int32_t(L + (L >> 4) + 1);
+        pd.tiles = int64_t(1) << (logA - logW);
+        pd.threads = 1 << (logW + logTPL);
+        pd.lds_bytes = uint32_t((L + (int64_t(1) << logW) * pd.lw) * esize);
+        return pd.lds_bytes <= lds_cap && pd.threads >= 1;
+    }
+    return false;
+}
+
 // A pass over an array viewed as (A, group..., B).
 PassDesc make_pass(int logA, const std::vector<int> &loglens, int logB, fftu_dtype dt, int lognmax)
 {
     PassDesc pd{};
+    if (loglens.size() == 1 && make_line_pass(logA, loglens[0], logB, dt, lognmax, pd)) return pd;
+    pd.kind = fftu::kTilePass;
+    pd.threads = fftu::kPassThreads;
     int logG = 0;
     for (int v : loglens) logG += v;
     const int esize = dt == FFTU_C128 ? 16 : 8;
@@ -230,33 +285,75 @@ int bitrev(int x, int bits)
     return r;
 }
 
-// Only for grids with P <= 2^kMaxLogP (the register-resident form).
-ExchangeDesc make_exchange(const Geometry &G, const GridDesc &g)
+// Split of the grid for k_exchange: the dimensions with p_l > 1, in order, become
+// nh leading wave dimensions (all of one size 2^lph, at most 2 bits in total) and
+// nr trailing register dimensions (all of one size 2^lpr, at most 16 complex128 or
+// 32 complex64 values). Returns false when no split has a compiled kernel; the
+// unfused path (twiddle, permutation, one pass per grid dimension) is used then.
+struct ExchangeSplit {
+    int nr = 0, lpr = 0, nh = 0, lph = 0;
+    std::vector<int> rdims, hdims;
+};
+
+bool reg_part_ok(int nr, int lpr, int rmax)
+{
+    if (nr == 0) return true;
+    if (nr * lpr > rmax) return false;
+    return lpr == 1 || (lpr == 2 && nr <= 2) || nr == 1;
+}
+
+bool wave_part_ok(int nh, int lph)
+{
+    return nh == 0 || (nh == 1 && (lph == 1 || lph == 2)) || (nh == 2 && lph == 1);
+}
+
+bool exchange_split(const Geometry &G, fftu_dtype dt, ExchangeSplit *out)
+{
+    const int rmax = dt == FFTU_C128 ? fftu::kExchangeRegBitsF64 : fftu::kExchangeRegBitsF32;
+    std::vector<int> dims;
+    for (int l = 0; l < G.d; ++l)
+        if (G.logp[l] > 0) dims.push_back(l);
+    for (size_t c = 0; c <= dims.size(); ++c) {
+        ExchangeSplit sp;
+        bool uniform = true;
+        for (size_t i = 0; i < dims.size(); ++i) {
+            const int lp = G.logp[dims[i]];
+            if (i < c) {
+                if (sp.nh > 0 && lp != sp.lph) uniform = false;
+                sp.lph = lp;
+                ++sp.nh;
+                sp.hdims.push_back(dims[i]);
+            } else {
+                if (sp.nr > 0 && lp != sp.lpr) uniform = false;
+                sp.lpr = lp;
+                ++sp.nr;
+                sp.rdims.push_back(dims[i]);
+            }
+        }
+        const int logH = sp.nh * sp.lph, logR = sp.nr * sp.lpr;
+        if (!uniform || logH > fftu::kExchangeMaxWaveBits) continue;
+        if (!wave_part_ok(sp.nh, sp.lph) || !reg_part_ok(sp.nr, sp.lpr, rmax)) continue;
+        if (logH > 0 && logH > logR) continue;
+        *out = sp;
+        return true;
+    }
+    return false;
+}
+
+ExchangeDesc make_exchange(const Geometry &G, const GridDesc &g, const ExchangeSplit &sp, fftu_dtype dt)
 {
     ExchangeDesc ex{};
-    if (G.logP > fftu::kMaxLogP) return ex;
     ex.g = g;
-    ex.logP = G.logP;
-    int lo[fftu::kMaxDims];
-    int acc = 0;
-    for (int l = G.d - 1; l >= 0; --l) {
-        lo[l] = acc;
-        acc += G.logp[l];
-    }
-    for (int b = 0; b < G.logP; ++b)
-        for (int l = 0; l < G.d; ++l)
-            if (b >= lo[l] && b < lo[l] + G.logp[l]) {
-                ex.bit_dim[b] = l;
-                ex.bit_h[b] = b - lo[l];
-            }
-    for (int i = 0; i < (1 << G.logP); ++i) {
-        int64_t off = 0;
-        for (int l = 0; l < G.d; ++l) {
-            const int x = (i >> lo[l]) & ((1 << G.logp[l]) - 1);
-            off += int64_t(bitrev(x, G.logp[l])) << (G.logq[l] + g.logmstride[l]);
-        }
-        ex.okp[i] = off;
-    }
+    ex.nr = sp.nr;
+    ex.lpr = sp.lpr;
+    ex.nh = sp.nh;
+    ex.lph = sp.lph;
+    for (size_t i = 0; i < sp.rdims.size(); ++i) ex.rdim[i] = sp.rdims[i];
+    for (size_t i = 0; i < sp.hdims.size(); ++i) ex.hdim[i] = sp.hdims[i];
+    for (int l = 0; l < G.d; ++l) ex.oshift[l] = G.logq[l] + g.logmstride[l];
+    const uint32_t esize = dt == FFTU_C128 ? 16 : 8;
+    const int logR = sp.nr * sp.lpr;
+    ex.lds_bytes = sp.nh > 0 ? uint32_t(fftu::kExchangeThreads / 64) * 64u * (1u << logR) * esize : 0u;
     return ex;
 }
 
@@ -419,7 +516,8 @@ fftu_status fftu_describe(int d, const int64_t n[], const int64_t p[], fftu_dtyp
     if (!info) return record(FFTU_ERROR_INVALID_VALUE);
     const Geometry G = geometry(d, n, p);
     const auto s0 = plan_s0(G, dtype);
-    const bool fused = G.logP <= fftu::kMaxLogP;
+    ExchangeSplit sp;
+    const bool fused = exchange_split(G, dtype, &sp);
     const auto s2 = plan_s2(G, dtype);
     fill_info(G, s0, fused, s2.size(), dtype, info);
     return record(FFTU_SUCCESS);
@@ -450,8 +548,9 @@ fftu_plan_t fftu_plan(int d, const int64_t n[], const int64_t p[], fftu_dtype dt
     pl->grid = make_grid(G);
     pl->s0 = plan_s0(G, dtype);
     pl->s2 = plan_s2(G, dtype);
-    pl->fused = G.logP <= fftu::kMaxLogP;
-    if (pl->fused) pl->ex = make_exchange(G, pl->grid);
+    ExchangeSplit sp;
+    pl->fused = exchange_split(G, dtype, &sp);
+    if (pl->fused) pl->ex = make_exchange(G, pl->grid, sp, dtype);
     {
         fftu_plan_info info{};
         fill_info(G, pl->s0, pl->fused, pl->s2.size(), dtype, &info);

@@ -1,0 +1,108 @@
+// Device helpers shared by the kernels: interleaved complex type, complex
+// arithmetic, exact constant roots of unity up to order 32, and in-register DFTs.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <utility>
+
+namespace fftu {
+
+template <typename T>
+struct alignas(2 * sizeof(T)) cx {
+    T x, y;
+};
+
+template <typename T>
+__device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename T>
+__device__ __forceinline__ cx<T> operator-(cx<T> a, cx<T> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename T>
+__device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b)
+{
+    return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename T>
+__device__ __forceinline__ cx<T> conj_if(cx<T> a, int c) { return c ? cx<T>{a.x, -a.y} : a; }
+
+// cos(2 pi j / 32) for j = 0..8; every 32nd root of unity follows by symmetry.
+__host__ __device__ constexpr double cos32_octant(int j)
+{
+    return j == 0 ? 1.0
+         : j == 1 ? 0.98078528040323044912618223613424
+         : j == 2 ? 0.92387953251128675612818318939679
+         : j == 3 ? 0.83146961230254523707878837761791
+         : j == 4 ? 0.70710678118654752440084436210485
+         : j == 5 ? 0.55557023301960222474283081394853
+         : j == 6 ? 0.38268343236508977172845998403040
+         : j == 7 ? 0.19509032201612826784828486847702
+                  : 0.0;
+}
+__host__ __device__ constexpr double cos32(int j)
+{
+    j = ((j % 32) + 32) % 32;
+    return j <= 8 ? cos32_octant(j) : j <= 16 ? -cos32_octant(16 - j) : j <= 24 ? -cos32_octant(j - 16)
+                                                                          : cos32_octant(32 - j);
+}
+__host__ __device__ constexpr double sin32(int j) { return cos32(j - 8); }
+
+// a * omega_R^K with omega_R = exp(-2 pi i / R), R | 32; the quarter turns are exact.
+template <typename T, int R, int K>
+__device__ __forceinline__ cx<T> mul_root(cx<T> a)
+{
+    constexpr int k = ((K % R) + R) % R;
+    if constexpr (k == 0) {
+        return a;
+    } else if constexpr (4 * k == R) {
+        return {a.y, -a.x};
+    } else if constexpr (2 * k == R) {
+        return {-a.x, -a.y};
+    } else if constexpr (4 * k == 3 * R) {
+        return {-a.y, a.x};
+    } else {
+        constexpr int j = k * (32 / R);
+        constexpr T c = static_cast<T>(cos32(j));
+        constexpr T s = static_cast<T>(-sin32(j));
+        return cmul(a, cx<T>{c, s});
+    }
+}
+
+// In-register DFT of length R (power of two <= 32), natural order in and out:
+// radix-2 decimation in time, recursively.
+template <typename T, int R>
+struct Dft {
+    template <int... K>
+    static __device__ __forceinline__ void combine(cx<T> *v, const cx<T> *e, const cx<T> *o,
+                                                   std::integer_sequence<int, K...>)
+    {
+        ((v[K] = e[K] + mul_root<T, R, K>(o[K]), v[K + R / 2] = e[K] - mul_root<T, R, K>(o[K])), ...);
+    }
+    static __device__ __forceinline__ void run(cx<T> *v)
+    {
+        cx<T> e[R / 2], o[R / 2];
+#pragma unroll
+        for (int k = 0; k < R / 2; ++k) {
+            e[k] = v[2 * k];
+            o[k] = v[2 * k + 1];
+        }
+        Dft<T, R / 2>::run(e);
+        Dft<T, R / 2>::run(o);
+        combine(v, e, o, std::make_integer_sequence<int, R / 2>{});
+    }
+};
+template <typename T>
+struct Dft<T, 2> {
+    static __device__ __forceinline__ void run(cx<T> *v)
+    {
+        cx<T> a = v[0], b = v[1];
+        v[0] = a + b;
+        v[1] = a - b;
+    }
+};
+template <typename T>
+struct Dft<T, 1> {
+    static __device__ __forceinline__ void run(cx<T> *) {}
+};
+
+}  // namespace fftu

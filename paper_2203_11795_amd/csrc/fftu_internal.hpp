@@ -13,7 +13,10 @@ namespace fftu {
 constexpr int kMaxDims = FFTU_MAX_DIMS;
 constexpr int kMaxGroup = 4;     // dimensions transformed by one pass kernel
 constexpr int kMaxStages = 12;   // radix stages per dimension inside a pass
-constexpr int kMaxLogP = 6;      // largest grid (P = 64) whose length-p FFTs run in registers
+constexpr int kMaxLogP = 7;      // largest grid (P = 128) of the fused exchange kernel
+constexpr int kExchangeRegBitsF64 = 4;   // complex128 values per thread in the exchange: 16
+constexpr int kExchangeRegBitsF32 = 5;   // complex64: 32
+constexpr int kExchangeMaxWaveBits = 2;  // at most 4 waves share one group of 64 local indices
 constexpr int kPassThreads = 256;
 constexpr int kExchangeThreads = 256;
 constexpr int kPointwiseThreads = 256;
@@ -22,19 +25,34 @@ constexpr int kPointwiseThreads = 256;
 constexpr int kLogTileF64 = 11;
 constexpr int kLogTileF32 = 12;
 
+// Pass kernels. kTilePass: generic LDS tile over a group of dimensions (k_pass).
+// The others are k_line layouts for a single dimension (see fftu_line.hip).
+constexpr int kTilePass = 0;
+constexpr int kLineStrided = 1;
+constexpr int kLineContig = 2;
+constexpr int kLineStaged = 3;
+constexpr int kLineMaxThreads = 256;   // k_line workgroup bound (register budget per thread)
+
+// Radix split of k_line for a line of 2^logl: 1, 2 or 3 stages of 2^line_loge
+// elements per thread (the last stage may be smaller). Shared by host and device.
+constexpr int line_stages_of(int logl) { return logl <= 4 ? 1 : (logl <= 8 ? 2 : 3); }
+constexpr int line_loge(int logl) { return (logl + line_stages_of(logl) - 1) / line_stages_of(logl); }
+
 // One pass kernel: 1-D FFTs along a group of consecutive dimensions of an array
 // viewed as (A, G, B) row-major, where G is the product of the group's lengths
 // and B the product of the lengths after it. A tile holds W = 2^logW columns:
 // W consecutive inner indices (B >= W) or W/B consecutive outer blocks (B < W).
 struct PassDesc {
-    int64_t tiles;         // workgroups launched
+    int32_t kind;          // kTilePass or a k_line layout
+    int32_t threads;       // workgroup size
+    int64_t tiles;         // tiles (workgroups, or grid-stride iterations)
     int64_t GB;            // elements per outer block, G * B
     int32_t logB;
     int32_t logG;
     int32_t logW;
     int32_t logBt;         // log2 min(B, W)
     int32_t logTPA;        // log2(B / W) when B >= W (tiles per outer block), else 0
-    int32_t lw;            // LDS row pitch in elements (W plus padding)
+    int32_t lw;            // LDS pitch in elements (tile: row of W plus padding; k_line: see fftu_line.hip)
     int32_t naxes;         // dimensions in the group, outermost first
     int32_t loglen[kMaxGroup];
     int32_t logstride[kMaxGroup];  // stride of each group dimension inside the group (in group positions)
@@ -63,23 +81,26 @@ struct GridDesc {
     double scale;
 };
 
-// The fused Superstep-1/2 kernel: twiddle, permutation, F_{p_1} x ... x F_{p_d}
-// in registers, conjugation and scaling. Bit b of the flat processor index s'
-// (row-major over the grid) belongs to dimension bit_dim[b] at bit bit_h[b]
-// of s'_l. Register i ends up holding output k' whose offset inside the
-// destination block is okp[i] = sum_l bitrev(k'_l) q_l prod_{j>l} m_j.
+// The fused kernel for Superstep 0's twiddle, Superstep 1 and Superstep 2. The grid
+// dimensions with p_l > 1 split into nh leading "wave" dimensions of 2^lph each
+// (joined through LDS across waves) and nr trailing "register" dimensions of
+// 2^lpr each (held by one thread): hdim[] and rdim[] list their indices.
+// oshift[l] = log2(q_l prod_{j>l} m_j), the move of output digit k'_l.
 struct ExchangeDesc {
     GridDesc g;
-    int32_t logP;
-    int32_t bit_dim[kMaxLogP];
-    int32_t bit_h[kMaxLogP];
-    int64_t okp[1 << kMaxLogP];
+    int32_t nr, lpr, nh, lph;
+    int32_t rdim[kMaxDims];
+    int32_t hdim[kMaxDims];
+    int32_t oshift[kMaxDims];
+    uint32_t lds_bytes;
 };
 
 enum class Precision { F32, F64 };
 
 // Launchers (fftu_kernels.hip). All return hipSuccess or the launch error.
 hipError_t launch_pass(Precision prec, const void *in, void *out, const PassDesc &pd, const void *table,
+                       hipStream_t stream);
+hipError_t launch_line(Precision prec, const void *in, void *out, const PassDesc &pd, const void *table,
                        hipStream_t stream);
 hipError_t launch_twiddle(Precision prec, const void *in, void *out, const GridDesc &g, const void *table,
                           hipStream_t stream);

@@ -6,10 +6,8 @@
 //               workgroup, coalesced HBM reads and writes.
 //   k_twiddle   Superstep 0's twiddle loop, Z[k] = prod_l omega_{n_l}^{k_l s_l} Y[k].
 //   k_permute   Superstep 1 on its own: W^(r)[s q + t] = Z^(s)[r + t p].
-//   k_exchange  Superstep 0's twiddle + Superstep 1 + Superstep 2 in one pass:
-//               one thread per local index k gathers the P values Z^(s')[k],
-//               twiddles them, applies F_{p_1} x ... x F_{p_d} in registers and
-//               scatters them to their destinations.
+//   (k_exchange, the fused twiddle + permutation + length-p FFTs, is in fftu_exchange.hip;
+//    k_line, the register-direct single-dimension pass, is in fftu_line.hip.)
 //
 // Inverse transforms are run as conj(F(conj(x))): conjugation is exact, so this
 // equals the transform with conjugated weights. Only the first load and the last
@@ -19,105 +17,10 @@
 #include <cstdint>
 #include <utility>
 
+#include "fftu_device.hpp"
 #include "fftu_internal.hpp"
 
 namespace fftu {
-
-template <typename T>
-struct alignas(2 * sizeof(T)) cx {
-    T x, y;
-};
-
-template <typename T>
-__device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) { return {a.x + b.x, a.y + b.y}; }
-template <typename T>
-__device__ __forceinline__ cx<T> operator-(cx<T> a, cx<T> b) { return {a.x - b.x, a.y - b.y}; }
-template <typename T>
-__device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b)
-{
-    return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
-}
-template <typename T>
-__device__ __forceinline__ cx<T> conj_if(cx<T> a, int c) { return c ? cx<T>{a.x, -a.y} : a; }
-
-// cos(2 pi j / 32) for j = 0..8; every 32nd root of unity follows by symmetry.
-__host__ __device__ constexpr double cos32_octant(int j)
-{
-    return j == 0 ? 1.0
-         : j == 1 ? 0.98078528040323044912618223613424
-         : j == 2 ? 0.92387953251128675612818318939679
-         : j == 3 ? 0.83146961230254523707878837761791
-         : j == 4 ? 0.70710678118654752440084436210485
-         : j == 5 ? 0.55557023301960222474283081394853
-         : j == 6 ? 0.38268343236508977172845998403040
-         : j == 7 ? 0.19509032201612826784828486847702
-                  : 0.0;
-}
-__host__ __device__ constexpr double cos32(int j)
-{
-    j = ((j % 32) + 32) % 32;
-    return j <= 8 ? cos32_octant(j) : j <= 16 ? -cos32_octant(16 - j) : j <= 24 ? -cos32_octant(j - 16)
-                                                                          : cos32_octant(32 - j);
-}
-__host__ __device__ constexpr double sin32(int j) { return cos32(j - 8); }
-
-// a * omega_R^K with omega_R = exp(-2 pi i / R), R | 32; the quarter turns are exact.
-template <typename T, int R, int K>
-__device__ __forceinline__ cx<T> mul_root(cx<T> a)
-{
-    constexpr int k = ((K % R) + R) % R;
-    if constexpr (k == 0) {
-        return a;
-    } else if constexpr (4 * k == R) {
-        return {a.y, -a.x};
-    } else if constexpr (2 * k == R) {
-        return {-a.x, -a.y};
-    } else if constexpr (4 * k == 3 * R) {
-        return {-a.y, a.x};
-    } else {
-        constexpr int j = k * (32 / R);
-        constexpr T c = static_cast<T>(cos32(j));
-        constexpr T s = static_cast<T>(-sin32(j));
-        return cmul(a, cx<T>{c, s});
-    }
-}
-
-// In-register DFT of length R (power of two <= 32), natural order in and out:
-// radix-2 decimation in time, recursively.
-template <typename T, int R>
-struct Dft {
-    template <int... K>
-    static __device__ __forceinline__ void combine(cx<T> *v, const cx<T> *e, const cx<T> *o,
-                                                   std::integer_sequence<int, K...>)
-    {
-        ((v[K] = e[K] + mul_root<T, R, K>(o[K]), v[K + R / 2] = e[K] - mul_root<T, R, K>(o[K])), ...);
-    }
-    static __device__ __forceinline__ void run(cx<T> *v)
-    {
-        cx<T> e[R / 2], o[R / 2];
-#pragma unroll
-        for (int k = 0; k < R / 2; ++k) {
-            e[k] = v[2 * k];
-            o[k] = v[2 * k + 1];
-        }
-        Dft<T, R / 2>::run(e);
-        Dft<T, R / 2>::run(o);
-        combine(v, e, o, std::make_integer_sequence<int, R / 2>{});
-    }
-};
-template <typename T>
-struct Dft<T, 2> {
-    static __device__ __forceinline__ void run(cx<T> *v)
-    {
-        cx<T> a = v[0], b = v[1];
-        v[0] = a + b;
-        v[1] = a - b;
-    }
-};
-template <typename T>
-struct Dft<T, 1> {
-    static __device__ __forceinline__ void run(cx<T> *) {}
-};
 
 // ---------------------------------------------------------------------------
 // k_pass: one Stockham stage over every line of one group axis, in place in LDS.
@@ -299,97 +202,6 @@ __global__ __launch_bounds__(kPointwiseThreads) void k_permute(const cx<T> *__re
 }
 
 // ---------------------------------------------------------------------------
-// k_exchange: fused twiddle + permutation + length-p FFTs.
-// ---------------------------------------------------------------------------
-template <typename T, int LOGP>
-__device__ __forceinline__ void exchange_one(const cx<T> *__restrict__ Z, cx<T> *__restrict__ V,
-                                             const ExchangeDesc &ex, const cx<T> *__restrict__ table, int64_t k)
-{
-    constexpr int P = 1 << LOGP;
-    const GridDesc &g = ex.g;
-
-    // Split k into (r, t) per dimension (k_l = r_l + t_l p_l) and form the per-dimension
-    // twiddle steps c_l = k_l 2^(lognmax - logn_l).
-    uint32_t c[kMaxDims];
-    int64_t rank_r = 0, dst_t = 0;
-#pragma unroll
-    for (int l = 0; l < kMaxDims; ++l) {
-        c[l] = 0;
-        if (l < g.d) {
-            const int64_t kl = (k >> g.logmstride[l]) & ((int64_t(1) << g.logm[l]) - 1);
-            const int64_t rl = kl & ((int64_t(1) << g.logp[l]) - 1);
-            const int64_t tl = kl >> g.logp[l];
-            rank_r += rl << g.logpstride[l];
-            dst_t += tl << g.logmstride[l];
-            c[l] = uint32_t(kl) << (g.lognmax - g.logn[l]);
-        }
-    }
-    // Exponent step of bit b of s': bit h of s'_l contributes c_l 2^h.
-    uint32_t gb[LOGP > 0 ? LOGP : 1];
-#pragma unroll
-    for (int b = 0; b < LOGP; ++b) {
-        uint32_t acc = 0;
-#pragma unroll
-        for (int l = 0; l < kMaxDims; ++l)
-            if (ex.bit_dim[b] == l) acc = c[l] << ex.bit_h[b];
-        gb[b] = acc;
-    }
-    const uint32_t emask = (uint32_t(1) << g.lognmax) - 1;
-
-    // Gather Z^(s')[k] for every source s' and twiddle it.
-    cx<T> v[P];
-    uint32_t e[P];
-#pragma unroll
-    for (int i = 0; i < P; ++i) v[i] = Z[int64_t(i) * g.M + k];
-    e[0] = 0;
-#pragma unroll
-    for (int i = 1; i < P; ++i) e[i] = e[i & (i - 1)] + gb[__builtin_ctz(i)];
-#pragma unroll
-    for (int i = 0; i < P; ++i) {
-        v[i] = conj_if(v[i], g.conj_in);
-        if (i) v[i] = cmul(v[i], table[e[i] & emask]);
-    }
-
-    // F_{p_1} x ... x F_{p_d}: radix-2 decimation in frequency on every bit of s',
-    // highest bit first, so that each dimension's bits run from high to low.
-#pragma unroll
-    for (int b = LOGP - 1; b >= 0; --b) {
-        const int h = ex.bit_h[b];
-        const int sh = g.lognmax - h - 1;
-#pragma unroll
-        for (int i = 0; i < P; ++i) {
-            if (i & (1 << b)) continue;
-            const cx<T> a = v[i], bb = v[i | (1 << b)];
-            v[i] = a + bb;
-            const int jm = (i >> (b - h)) & ((1 << h) - 1);
-            v[i | (1 << b)] = cmul(a - bb, table[uint32_t(jm) << sh]);
-        }
-    }
-
-    // Scatter: register i holds output k' (bit-reversed per dimension) of destination r.
-    const int64_t obase = (rank_r << (g.logmstride[0] + g.logm[0])) + dst_t;
-    const T scale = static_cast<T>(g.scale);
-#pragma unroll
-    for (int i = 0; i < P; ++i) {
-        cx<T> w = conj_if(v[i], g.conj_out);
-        if (g.scale != 1.0) w = {w.x * scale, w.y * scale};
-        V[obase + ex.okp[i]] = w;
-    }
-}
-
-template <typename T, int LOGP>
-__global__ __launch_bounds__(kExchangeThreads) void k_exchange(const cx<T> *__restrict__ Z, cx<T> *__restrict__ V,
-                                                               const ExchangeDesc ex,
-                                                               const cx<T> *__restrict__ table)
-{
-    constexpr int P = 1 << LOGP;
-    const GridDesc &g = ex.g;
-    for (int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; k < g.M; k += int64_t(gridDim.x) * blockDim.x)
-        exchange_one<T, LOGP>(Z, V, ex, table, k);
-}
-
-
-// ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
 namespace {
@@ -411,38 +223,12 @@ uint32_t pointwise_blocks(int64_t n)
     return uint32_t(want < 262144 ? (want > 0 ? want : 1) : 262144);
 }
 
-template <typename T, int LOGP>
-hipError_t launch_exchange_t(const void *in, void *out, const ExchangeDesc &ex, const void *table,
-                             hipStream_t stream)
-{
-    const int64_t want = (ex.g.M + kExchangeThreads - 1) / kExchangeThreads;
-    const uint32_t blocks = uint32_t(want < kMaxBlocks ? want : kMaxBlocks);
-    hipLaunchKernelGGL((k_exchange<T, LOGP>), dim3(blocks), dim3(kExchangeThreads), 0, stream,
-                       static_cast<const cx<T> *>(in), static_cast<cx<T> *>(out), ex,
-                       static_cast<const cx<T> *>(table));
-    return hipGetLastError();
-}
-
-template <typename T>
-hipError_t launch_exchange_logp(const void *in, void *out, const ExchangeDesc &ex, const void *table,
-                                hipStream_t stream)
-{
-    switch (ex.logP) {
-    case 0: return launch_exchange_t<T, 0>(in, out, ex, table, stream);
-    case 1: return launch_exchange_t<T, 1>(in, out, ex, table, stream);
-    case 2: return launch_exchange_t<T, 2>(in, out, ex, table, stream);
-    case 3: return launch_exchange_t<T, 3>(in, out, ex, table, stream);
-    case 4: return launch_exchange_t<T, 4>(in, out, ex, table, stream);
-    case 5: return launch_exchange_t<T, 5>(in, out, ex, table, stream);
-    case 6: return launch_exchange_t<T, 6>(in, out, ex, table, stream);
-    default: return hipErrorInvalidValue;
-    }
-}
 }  // namespace
 
 hipError_t launch_pass(Precision prec, const void *in, void *out, const PassDesc &pd, const void *table,
                        hipStream_t stream)
 {
+    if (pd.kind != kTilePass) return launch_line(prec, in, out, pd, table, stream);
     return prec == Precision::F64 ? launch_pass_t<double>(in, out, pd, table, stream)
                                   : launch_pass_t<float>(in, out, pd, table, stream);
 }
@@ -472,13 +258,6 @@ hipError_t launch_permute(Precision prec, const void *in, void *out, const GridD
         hipLaunchKernelGGL(k_permute<float>, dim3(blocks), dim3(kPointwiseThreads), 0, stream,
                            static_cast<const cx<float> *>(in), static_cast<cx<float> *>(out), g);
     return hipGetLastError();
-}
-
-hipError_t launch_exchange(Precision prec, const void *in, void *out, const ExchangeDesc &ex, const void *table,
-                           hipStream_t stream)
-{
-    return prec == Precision::F64 ? launch_exchange_logp<double>(in, out, ex, table, stream)
-                                  : launch_exchange_logp<float>(in, out, ex, table, stream);
 }
 
 }  // namespace fftu

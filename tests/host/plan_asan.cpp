@@ -22,7 +22,7 @@ hipError_t launch_twiddle(Precision, const void *, void *, const GridDesc &, con
 hipError_t launch_permute(Precision, const void *, void *, const GridDesc &, hipStream_t) { return hipSuccess; }
 hipError_t launch_exchange(Precision, const void *, void *, const ExchangeDesc &ex, const void *, hipStream_t)
 {
-    if (ex.logP > kMaxLogP) std::abort();
+    if (ex.nh * ex.lph > kExchangeMaxWaveBits || ex.nr * ex.lpr > kExchangeRegBitsF32) std::abort();
     return hipSuccess;
 }
 }  // namespace fftu
