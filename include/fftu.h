@@ -80,6 +80,25 @@ typedef enum {
     FFTU_ERROR_DEVICE = 5         /* HIP runtime or launch error */
 } fftu_status;
 
+/*
+ * Planner tuning knobs (process-wide, read when a plan is created; plans that
+ * exist keep their choices). A value of -1 restores the planner's default.
+ * Used by the autotuner; every setting gives the same results up to rounding.
+ */
+typedef enum {
+    FFTU_TUNE_LINE_STRIDED_LOGW = 0, /* log2 columns per workgroup, strided single-dimension passes (2..6) */
+    FFTU_TUNE_LINE_CONTIG_LOGW = 1,  /* log2 lines per workgroup, contiguous single-dimension passes (0..8) */
+    FFTU_TUNE_LINE_PAD = 2,          /* LDS padding (elements) per row of a strided pass tile (0..4) */
+    FFTU_TUNE_MAX_LDS_KB = 3,        /* LDS budget per workgroup of a pass, KiB (16..160; default 64) */
+    FFTU_TUNE_COUNT = 4
+} fftu_tune_param;
+
+/* Set a tuning knob; FFTU_ERROR_INVALID_VALUE for an unknown knob or a value out of range. */
+fftu_status fftu_set_tuning(fftu_tune_param param, int value);
+
+/* Current value of a knob (-1: planner default). */
+int fftu_get_tuning(fftu_tune_param param);
+
 /* Static description of how a plan executes (host-side; see fftu_describe). */
 typedef struct {
     int32_t d;

@@ -51,6 +51,13 @@ namespace {
 
 thread_local fftu_status g_last = FFTU_SUCCESS;
 
+// Planner tuning knobs (fftu_set_tuning); -1 = default.
+int g_tune[FFTU_TUNE_COUNT] = {-1, -1, -1, -1};
+const int g_tune_min[FFTU_TUNE_COUNT] = {2, 0, 0, 16};
+const int g_tune_max[FFTU_TUNE_COUNT] = {6, 8, 4, 160};
+
+int64_t lds_cap() { return int64_t(g_tune[FFTU_TUNE_MAX_LDS_KB] >= 0 ? g_tune[FFTU_TUNE_MAX_LDS_KB] : 64) * 1024; }
+
 fftu_status record(fftu_status s)
 {
     g_last = s;
@@ -69,7 +76,7 @@ int ilog2(int64_t v)
 // Largest local length (n_l / p_l) and grid side p_l that one LDS tile can hold.
 int log_tile(fftu_dtype dt) { return dt == FFTU_C128 ? fftu::kLogTileF64 : fftu::kLogTileF32; }
 int64_t max_len(fftu_dtype dt) { return int64_t(1) << log_tile(dt); }
-int log_wmax(fftu_dtype dt) { return dt == FFTU_C128 ? 4 : 5; }       // 256-byte column runs
+int log_wmax(fftu_dtype dt) { return dt == FFTU_C128 ? 5 : 6; }       // 512-byte column runs
 
 fftu_status validate(int d, const int64_t n[], const int64_t p[], fftu_dtype dtype, fftu_direction direction)
 {
@@ -106,9 +113,10 @@ bool make_line_pass(int logA, int logL, int logB, fftu_dtype dt, int lognmax, Pa
 {
     if (logL < 1 || logL > 12) return false;
     const int esize = dt == FFTU_C128 ? 16 : 8;
+    const int xbytes = 8;   // LDS bytes per element in a stage exchange: one double (re/im rounds) or one complex64
     const int logTPL = logL - fftu::line_loge(logL);
     const int64_t L = int64_t(1) << logL;
-    const int64_t lds_cap = 64 * 1024;
+    const int64_t cap = lds_cap();
     pd = PassDesc{};
     pd.loglen[0] = logL;
     pd.naxes = 1;
@@ -119,23 +127,28 @@ bool make_line_pass(int logA, int logL, int logB, fftu_dtype dt, int lognmax, Pa
     pd.scale = 1.0;
     if (logB >= 2) {
         // columns: W consecutive b per workgroup, W*esize bytes per row run
-        int logW = std::min(log_wmax(dt), logB);
-        while (logW > 0 && ((int64_t(1) << logW) * L + L) * esize > lds_cap) --logW;
+        int logW = std::min(g_tune[FFTU_TUNE_LINE_STRIDED_LOGW] >= 0 ? g_tune[FFTU_TUNE_LINE_STRIDED_LOGW]
+                                                                      : log_wmax(dt),
+                            logB);
+        const int pad = g_tune[FFTU_TUNE_LINE_PAD] >= 0 ? g_tune[FFTU_TUNE_LINE_PAD] : 1;
+        while (logW > 0 && (((int64_t(1) << logW) + pad) * L * xbytes + L * esize) > cap) --logW;
         while (logW > 0 && (logW + logTPL) > 8) --logW;
         if (logW < 2) return false;
         pd.kind = fftu::kLineStrided;
         pd.logW = logW;
         pd.logBt = logW;
         pd.logTPA = logB - logW;
-        pd.lw = (1 << logW) + 1;
+        pd.lw = (1 << logW) + pad;
         pd.tiles = int64_t(1) << (logA + logB - logW);
         pd.threads = 1 << (logW + logTPL);
-        pd.lds_bytes = uint32_t((L + L * pd.lw) * esize);
+        pd.lds_bytes = uint32_t(L * esize + L * pd.lw * xbytes);
         return true;
     }
     if (logB == 0) {
-        // contiguous lines: about one LDS tile of lines per workgroup
-        int logW = std::max(0, log_tile(dt) - logL);
+        // contiguous lines: about 2^9 (complex128) or 2^10 (complex64) elements per workgroup
+        const int log_target = dt == FFTU_C128 ? 9 : 10;
+        int logW = g_tune[FFTU_TUNE_LINE_CONTIG_LOGW] >= 0 ? g_tune[FFTU_TUNE_LINE_CONTIG_LOGW]
+                                                           : std::max(0, log_target - logL);
         logW = std::min(logW, logA);
         while (logW > 0 && (logW + logTPL) > 8) --logW;
         if (logW + logTPL > 8) return false;
@@ -146,8 +159,9 @@ bool make_line_pass(int logA, int logL, int logB, fftu_dtype dt, int lognmax, Pa
         pd.lw = int32_t(L + (L >> 4) + 1);
         pd.tiles = int64_t(1) << (logA - logW);
         pd.threads = 1 << (logW + logTPL);
-        pd.lds_bytes = uint32_t((L + (int64_t(1) << logW) * pd.lw) * esize);
-        return pd.lds_bytes <= lds_cap && pd.threads >= 1;
+        const int per = pd.kind == fftu::kLineStaged ? esize : xbytes;
+        pd.lds_bytes = uint32_t(L * esize + (int64_t(1) << logW) * pd.lw * per);
+        return pd.lds_bytes <= cap && pd.threads >= 1;
     }
     return false;
 }
@@ -212,31 +226,72 @@ Geometry geometry(int d, const int64_t n[], const int64_t p[])
     return G;
 }
 
-// Superstep 0: group consecutive local dimensions, innermost first, while a tile fits.
+// k_group2 for the two innermost dimensions 2^logL1 (outer) x 2^logL2 (inner) of
+// contiguous planes (B = 1), when both sides are 4..64 and a plane fits in 16 KiB.
+bool make_group2_pass(int logA, int logL1, int logL2, fftu_dtype dt, int lognmax, PassDesc &pd)
+{
+    if (logL1 < 2 || logL1 > 6 || logL2 < 2 || logL2 > 6) return false;
+    const int esize = dt == FFTU_C128 ? 16 : 8;
+    const int logG = logL1 + logL2;
+    if ((int64_t(1) << logG) * esize > 16 * 1024) return false;
+    // threads per plane along each dimension: (lines) x (threads per line)
+    const int t1 = logL2 + (logL1 - fftu::line_loge(logL1));
+    const int t2 = logL1 + (logL2 - fftu::line_loge(logL2));
+    const int tmax = std::max(t1, t2);
+    if (tmax > 8) return false;
+    int logW = std::min(8 - tmax, logA);
+    const int64_t L1 = int64_t(1) << logL1, L2 = int64_t(1) << logL2;
+    const int64_t PG = L1 * (L2 + 1);
+    while (logW > 0 && (L1 + L2 + (int64_t(1) << logW) * PG) * esize > lds_cap()) --logW;
+    pd = PassDesc{};
+    pd.kind = fftu::kGroup2;
+    pd.naxes = 2;
+    pd.loglen[0] = logL1;
+    pd.loglen[1] = logL2;
+    pd.logG = logG;
+    pd.logB = 0;
+    pd.GB = int64_t(1) << logG;
+    pd.logW = logW;
+    pd.tiles = int64_t(1) << (logA - logW);
+    pd.threads = 1 << (logW + tmax);
+    pd.lognmax = lognmax;
+    pd.scale = 1.0;
+    pd.lds_bytes = uint32_t((L1 + L2 + (int64_t(1) << logW) * PG) * esize);
+    return pd.lds_bytes <= lds_cap();
+}
+
+// Superstep 0: the local d-D FFT as a sequence of passes, innermost dimension
+// first (the order is free: the DFT factorises over dimensions, eq. (1.3)).
+// The two innermost dimensions share one k_group2 pass when their planes are
+// small; every other dimension gets its own pass.
 std::vector<PassDesc> plan_s0(const Geometry &G, fftu_dtype dt)
 {
     std::vector<PassDesc> passes;
-    int l = G.d - 1;
-    while (l >= 0) {
-        if (G.logm[l] == 0) {
-            --l;
-            continue;
-        }
-        int logB = 0;
-        for (int j = l + 1; j < G.d; ++j) logB += G.logm[j];
-        std::vector<int> lens{G.logm[l]};
-        int logG = G.logm[l];
-        const int wneed = std::min(log_wmax(dt), logB);
-        while (l - 1 >= 0 && int(lens.size()) < fftu::kMaxGroup &&
-               logG + G.logm[l - 1] + wneed <= log_tile(dt)) {
-            --l;
-            if (G.logm[l] > 0) lens.insert(lens.begin(), G.logm[l]);
-            logG += G.logm[l];
-        }
+    std::vector<int> dims;   // dimensions with m_l > 1, innermost first
+    for (int l = G.d - 1; l >= 0; --l)
+        if (G.logm[l] > 0) dims.push_back(l);
+    auto outer_of = [&](int l) {
         int logA = G.logP;
         for (int j = 0; j < l; ++j) logA += G.logm[j];
-        passes.push_back(make_pass(logA, lens, logB, dt, G.lognmax));
-        --l;
+        return logA;
+    };
+    auto inner_of = [&](int l) {
+        int logB = 0;
+        for (int j = l + 1; j < G.d; ++j) logB += G.logm[j];
+        return logB;
+    };
+    size_t first = 0;
+    if (dims.size() >= 2) {
+        PassDesc pd;
+        const int li = dims[0], lo = dims[1];
+        if (make_group2_pass(outer_of(lo), G.logm[lo], G.logm[li], dt, G.lognmax, pd)) {
+            passes.push_back(pd);
+            first = 2;
+        }
+    }
+    for (size_t i = first; i < dims.size(); ++i) {
+        const int l = dims[i];
+        passes.push_back(make_pass(outer_of(l), {G.logm[l]}, inner_of(l), dt, G.lognmax));
     }
     return passes;
 }
@@ -351,9 +406,9 @@ ExchangeDesc make_exchange(const Geometry &G, const GridDesc &g, const ExchangeS
     for (size_t i = 0; i < sp.rdims.size(); ++i) ex.rdim[i] = sp.rdims[i];
     for (size_t i = 0; i < sp.hdims.size(); ++i) ex.hdim[i] = sp.hdims[i];
     for (int l = 0; l < G.d; ++l) ex.oshift[l] = G.logq[l] + g.logmstride[l];
-    const uint32_t esize = dt == FFTU_C128 ? 16 : 8;
-    const int logR = sp.nr * sp.lpr;
-    ex.lds_bytes = sp.nh > 0 ? uint32_t(fftu::kExchangeThreads / 64) * 64u * (1u << logR) * esize : 0u;
+    (void)dt;
+    const int logR = sp.nr * sp.lpr;   // the LDS swap moves one double (complex128: re, then im) or one complex64
+    ex.lds_bytes = sp.nh > 0 ? uint32_t(fftu::kExchangeThreads / 64) * 64u * (1u << logR) * 8u : 0u;
     return ex;
 }
 
@@ -502,6 +557,26 @@ const char *fftu_status_string(fftu_status s)
 }
 
 fftu_status fftu_last_error(void) { return g_last; }
+
+fftu_status fftu_set_tuning(fftu_tune_param param, int value)
+{
+    const int i = int(param);
+    if (i < 0 || i >= FFTU_TUNE_COUNT) return record(FFTU_ERROR_INVALID_VALUE);
+    if (value != -1 && (value < g_tune_min[i] || value > g_tune_max[i])) return record(FFTU_ERROR_INVALID_VALUE);
+    g_tune[i] = value;
+    return record(FFTU_SUCCESS);
+}
+
+int fftu_get_tuning(fftu_tune_param param)
+{
+    const int i = int(param);
+    if (i < 0 || i >= FFTU_TUNE_COUNT) {
+        record(FFTU_ERROR_INVALID_VALUE);
+        return -1;
+    }
+    record(FFTU_SUCCESS);
+    return g_tune[i];
+}
 
 fftu_status fftu_check(int d, const int64_t n[], const int64_t p[], fftu_dtype dtype, fftu_direction direction)
 {

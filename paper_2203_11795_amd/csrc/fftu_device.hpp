@@ -7,6 +7,8 @@
 #include <cstdint>
 #include <utility>
 
+#include "fftu_internal.hpp"
+
 namespace fftu {
 
 template <typename T>
@@ -104,5 +106,43 @@ template <typename T>
 struct Dft<T, 1> {
     static __device__ __forceinline__ void run(cx<T> *) {}
 };
+
+// Compile-time radix plan of a line of 2^LOGL split over TPL = L / E threads with
+// E elements each (see line_stages_of / line_loge in fftu_internal.hpp). Register
+// m of thread j holds line position j + TPL m before the first and after the last
+// stage. Stage s has radix 2^lr(s) and follows Ns = 2^lns(s) points.
+template <int LOGL>
+struct LinePlan {
+    static constexpr int NS = line_stages_of(LOGL);
+    static constexpr int LOGE = line_loge(LOGL);
+    static constexpr int E = 1 << LOGE;
+    static constexpr int LOGTPL = LOGL - LOGE;
+    static constexpr int TPL = 1 << LOGTPL;
+    static constexpr int L = 1 << LOGL;
+    static constexpr int lr(int s) { return s < NS - 1 ? LOGE : LOGL - (NS - 1) * LOGE; }
+    static constexpr int lns(int s) { return s * LOGE; }
+};
+
+// Radix stage S on the thread's registers (register m <-> position j + TPL m).
+template <typename T, int LOGL, int S>
+__device__ __forceinline__ void line_compute(cx<T> (&v)[LinePlan<LOGL>::E], int j, const cx<T> *tw)
+{
+    using PL = LinePlan<LOGL>;
+    constexpr int LR = PL::lr(S), R = 1 << LR, LNS = PL::lns(S), NB = PL::E / R;
+#pragma unroll
+    for (int c = 0; c < NB; ++c) {
+        cx<T> x[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) x[r] = v[c + r * NB];
+        if constexpr (S > 0) {
+            const int jm = (j + c * PL::TPL) & ((1 << LNS) - 1);
+#pragma unroll
+            for (int r = 1; r < R; ++r) x[r] = cmul(x[r], tw[(r * jm) << (LOGL - LNS - LR)]);
+        }
+        Dft<T, R>::run(x);
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[c + r * NB] = x[r];
+    }
+}
 
 }  // namespace fftu

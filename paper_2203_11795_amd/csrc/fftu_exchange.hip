@@ -151,16 +151,37 @@ __global__ __launch_bounds__(kExchangeThreads) void k_exchange(const cx<T> *__re
                 if (valid) V[obase + digit_offset<NR, LPR>(ex.rdim, ex, j)] = w;
             }
         } else {
-            // Swap through LDS: register j of wave hw goes to the wave that owns slot j.
-            __syncthreads();
-#pragma unroll
-            for (int j = 0; j < R; ++j) lds[((hw * R + j) * KG + grp) * 64 + lane] = v[j];
-            __syncthreads();
+            // Swap through LDS: register j of wave hw goes to the wave that owns slot j
+            // (complex128 in two rounds of doubles, so the swap needs 8 bytes per value).
             cx<T> w[H * U];
+            if constexpr (sizeof(T) == 8) {
+                T *ld = reinterpret_cast<T *>(smem_raw);
+                __syncthreads();
 #pragma unroll
-            for (int x = 0; x < H; ++x)
+                for (int j = 0; j < R; ++j) ld[((hw * R + j) * KG + grp) * 64 + lane] = v[j].x;
+                __syncthreads();
 #pragma unroll
-                for (int u = 0; u < U; ++u) w[x * U + u] = lds[((x * R + hw * U + u) * KG + grp) * 64 + lane];
+                for (int x = 0; x < H; ++x)
+#pragma unroll
+                    for (int u = 0; u < U; ++u) w[x * U + u].x = ld[((x * R + hw * U + u) * KG + grp) * 64 + lane];
+                __syncthreads();
+#pragma unroll
+                for (int j = 0; j < R; ++j) ld[((hw * R + j) * KG + grp) * 64 + lane] = v[j].y;
+                __syncthreads();
+#pragma unroll
+                for (int x = 0; x < H; ++x)
+#pragma unroll
+                    for (int u = 0; u < U; ++u) w[x * U + u].y = ld[((x * R + hw * U + u) * KG + grp) * 64 + lane];
+            } else {
+                __syncthreads();
+#pragma unroll
+                for (int j = 0; j < R; ++j) lds[((hw * R + j) * KG + grp) * 64 + lane] = v[j];
+                __syncthreads();
+#pragma unroll
+                for (int x = 0; x < H; ++x)
+#pragma unroll
+                    for (int u = 0; u < U; ++u) w[x * U + u] = lds[((x * R + hw * U + u) * KG + grp) * 64 + lane];
+            }
 
             // DFTs over the wave dimensions, for each of this thread's U register outputs.
             dft_digits<T, NH, LPH, U, U>(w);

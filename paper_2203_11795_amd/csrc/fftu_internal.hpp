@@ -31,6 +31,7 @@ constexpr int kTilePass = 0;
 constexpr int kLineStrided = 1;
 constexpr int kLineContig = 2;
 constexpr int kLineStaged = 3;
+constexpr int kGroup2 = 4;             // k_group2: two innermost dimensions of small contiguous planes
 constexpr int kLineMaxThreads = 256;   // k_line workgroup bound (register budget per thread)
 
 // Radix split of k_line for a line of 2^logl: 1, 2 or 3 stages of 2^line_loge
@@ -102,6 +103,8 @@ hipError_t launch_pass(Precision prec, const void *in, void *out, const PassDesc
                        hipStream_t stream);
 hipError_t launch_line(Precision prec, const void *in, void *out, const PassDesc &pd, const void *table,
                        hipStream_t stream);
+hipError_t launch_group2(Precision prec, const void *in, void *out, const PassDesc &pd, const void *table,
+                         hipStream_t stream);
 hipError_t launch_twiddle(Precision prec, const void *in, void *out, const GridDesc &g, const void *table,
                           hipStream_t stream);
 hipError_t launch_permute(Precision prec, const void *in, void *out, const GridDesc &g, hipStream_t stream);

@@ -228,6 +228,7 @@ uint32_t pointwise_blocks(int64_t n)
 hipError_t launch_pass(Precision prec, const void *in, void *out, const PassDesc &pd, const void *table,
                        hipStream_t stream)
 {
+    if (pd.kind == kGroup2) return launch_group2(prec, in, out, pd, table, stream);
     if (pd.kind != kTilePass) return launch_line(prec, in, out, pd, table, stream);
     return prec == Precision::F64 ? launch_pass_t<double>(in, out, pd, table, stream)
                                   : launch_pass_t<float>(in, out, pd, table, stream);

@@ -28,18 +28,6 @@
 
 namespace fftu {
 
-template <int LOGL>
-struct LinePlan {
-    static constexpr int NS = line_stages_of(LOGL);   // radix stages
-    static constexpr int LOGE = line_loge(LOGL);      // log2 elements per thread
-    static constexpr int E = 1 << LOGE;
-    static constexpr int LOGTPL = LOGL - LOGE;                        // log2 threads per line
-    static constexpr int TPL = 1 << LOGTPL;
-    static constexpr int L = 1 << LOGL;
-    static constexpr int lr(int s) { return s < NS - 1 ? LOGE : LOGL - (NS - 1) * LOGE; }
-    static constexpr int lns(int s) { return s * LOGE; }
-};
-
 // LDS index of position x of line w. Strided layout: line positions are rows of W
 // (lanes run over w); contiguous layouts: one row per line, one pad element per 16
 // so that radix-16 scatters (stride 16) spread over the banks.
@@ -49,31 +37,14 @@ __device__ __forceinline__ int lidx(int x, int w, int pitch)
     return MODE == kLineStrided ? x * pitch + w : w * pitch + x + (x >> 4);
 }
 
-// Radix stage S on the thread's registers (register m <-> position j + TPL m).
-template <typename T, int LOGL, int S>
-__device__ __forceinline__ void line_compute(cx<T> (&v)[LinePlan<LOGL>::E], int j, const cx<T> *tw)
-{
-    using PL = LinePlan<LOGL>;
-    constexpr int LR = PL::lr(S), R = 1 << LR, LNS = PL::lns(S), NB = PL::E / R;
-#pragma unroll
-    for (int c = 0; c < NB; ++c) {
-        cx<T> x[R];
-#pragma unroll
-        for (int r = 0; r < R; ++r) x[r] = v[c + r * NB];
-        if constexpr (S > 0) {
-            const int jm = (j + c * PL::TPL) & ((1 << LNS) - 1);
-#pragma unroll
-            for (int r = 1; r < R; ++r) x[r] = cmul(x[r], tw[(r * jm) << (LOGL - LNS - LR)]);
-        }
-        Dft<T, R>::run(x);
-#pragma unroll
-        for (int r = 0; r < R; ++r) v[c + r * NB] = x[r];
-    }
-}
-
-// Write stage S's outputs to LDS at their Stockham positions.
-template <typename T, int LOGL, int S, int MODE>
-__device__ __forceinline__ void line_scatter(const cx<T> (&v)[LinePlan<LOGL>::E], int j, int w, int pitch, cx<T> *lds)
+// Exchange of a line through LDS between radix stage S and S+1: stage S's
+// outputs are written at their Stockham positions and the next stage's inputs
+// (register m <-> position j + TPL m) are read back. complex128 lines go through
+// LDS as two rounds of doubles (real parts, then imaginary parts) so that a tile
+// needs 8 bytes of LDS per element; complex64 lines go in one round.
+template <typename T, int LOGL, int S, int MODE, typename V, typename GET>
+__device__ __forceinline__ void line_scatter(const cx<T> (&v)[LinePlan<LOGL>::E], int j, int w, int pitch, V *lds,
+                                             GET get)
 {
     using PL = LinePlan<LOGL>;
     constexpr int LR = PL::lr(S), R = 1 << LR, LNS = PL::lns(S), NB = PL::E / R;
@@ -82,36 +53,52 @@ __device__ __forceinline__ void line_scatter(const cx<T> (&v)[LinePlan<LOGL>::E]
         const int jj = j + c * PL::TPL;
         const int ob = ((jj >> LNS) << (LNS + LR)) + (jj & ((1 << LNS) - 1));
 #pragma unroll
-        for (int r = 0; r < R; ++r) lds[lidx<MODE>(ob + (r << LNS), w, pitch)] = v[c + r * NB];
+        for (int r = 0; r < R; ++r) lds[lidx<MODE>(ob + (r << LNS), w, pitch)] = get(v[c + r * NB]);
     }
 }
 
-// Read the next stage's inputs: register m <-> position j + TPL m.
-template <typename T, int LOGL, int MODE>
-__device__ __forceinline__ void line_gather(cx<T> (&v)[LinePlan<LOGL>::E], int j, int w, int pitch, const cx<T> *lds)
+template <typename T, int LOGL, int MODE, typename V, typename PUT>
+__device__ __forceinline__ void line_gather(cx<T> (&v)[LinePlan<LOGL>::E], int j, int w, int pitch, const V *lds,
+                                            PUT put)
 {
     using PL = LinePlan<LOGL>;
 #pragma unroll
-    for (int m = 0; m < PL::E; ++m) v[m] = lds[lidx<MODE>(j + m * PL::TPL, w, pitch)];
+    for (int m = 0; m < PL::E; ++m) put(v[m], lds[lidx<MODE>(j + m * PL::TPL, w, pitch)]);
+}
+
+template <typename T, int LOGL, int S, int MODE>
+__device__ __forceinline__ void line_exchange(cx<T> (&v)[LinePlan<LOGL>::E], int j, int w, int pitch, void *smem)
+{
+    if constexpr (sizeof(T) == 8) {
+        T *lds = static_cast<T *>(smem);
+        line_scatter<T, LOGL, S, MODE>(v, j, w, pitch, lds, [](const cx<T> &a) { return a.x; });
+        __syncthreads();
+        line_gather<T, LOGL, MODE>(v, j, w, pitch, lds, [](cx<T> &a, T b) { a.x = b; });
+        __syncthreads();
+        line_scatter<T, LOGL, S, MODE>(v, j, w, pitch, lds, [](const cx<T> &a) { return a.y; });
+        __syncthreads();
+        line_gather<T, LOGL, MODE>(v, j, w, pitch, lds, [](cx<T> &a, T b) { a.y = b; });
+    } else {
+        cx<T> *lds = static_cast<cx<T> *>(smem);
+        line_scatter<T, LOGL, S, MODE>(v, j, w, pitch, lds, [](const cx<T> &a) { return a; });
+        __syncthreads();
+        line_gather<T, LOGL, MODE>(v, j, w, pitch, lds, [](cx<T> &a, cx<T> b) { a = b; });
+    }
 }
 
 template <typename T, int LOGL, int MODE>
-__device__ __forceinline__ void line_stages(cx<T> (&v)[LinePlan<LOGL>::E], int j, int w, int pitch, cx<T> *lds,
+__device__ __forceinline__ void line_stages(cx<T> (&v)[LinePlan<LOGL>::E], int j, int w, int pitch, void *smem,
                                             const cx<T> *tw)
 {
     using PL = LinePlan<LOGL>;
     line_compute<T, LOGL, 0>(v, j, tw);
     if constexpr (PL::NS > 1) {
-        line_scatter<T, LOGL, 0, MODE>(v, j, w, pitch, lds);
-        __syncthreads();
-        line_gather<T, LOGL, MODE>(v, j, w, pitch, lds);
+        line_exchange<T, LOGL, 0, MODE>(v, j, w, pitch, smem);
         line_compute<T, LOGL, 1>(v, j, tw);
     }
     if constexpr (PL::NS > 2) {
         __syncthreads();
-        line_scatter<T, LOGL, 1, MODE>(v, j, w, pitch, lds);
-        __syncthreads();
-        line_gather<T, LOGL, MODE>(v, j, w, pitch, lds);
+        line_exchange<T, LOGL, 1, MODE>(v, j, w, pitch, smem);
         line_compute<T, LOGL, 2>(v, j, tw);
     }
 }
@@ -159,14 +146,14 @@ __global__ __launch_bounds__(kLineMaxThreads) void k_line(const cx<T> *in, cx<T>
             for (int e = threadIdx.x; e < n; e += blockDim.x)
                 lds[lidx<MODE>(e & (PL::L - 1), e >> LOGL, pitch)] = conj_if(in[tbase + e], pd.conj_in);
             __syncthreads();
-            line_gather<T, LOGL, MODE>(v, j, w, pitch, lds);
+            line_gather<T, LOGL, MODE>(v, j, w, pitch, lds, [](cx<T> &a, cx<T> b) { a = b; });
             __syncthreads();
         } else {
 #pragma unroll
             for (int m = 0; m < PL::E; ++m) v[m] = conj_if(in[base + int64_t(j + m * PL::TPL) * xstride], pd.conj_in);
         }
 
-        line_stages<T, LOGL, MODE>(v, j, w, pitch, lds, tw);
+        line_stages<T, LOGL, MODE>(v, j, w, pitch, static_cast<void *>(lds), tw);
 
 #pragma unroll
         for (int m = 0; m < PL::E; ++m) {

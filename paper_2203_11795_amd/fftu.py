@@ -9,7 +9,6 @@ from __future__ import annotations
 
 import ctypes
 import os
-from dataclasses import dataclass
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfftu.so")
@@ -27,7 +26,9 @@ STATUS = {0: "FFTU_SUCCESS", 1: "FFTU_ERROR_INVALID_VALUE", 2: "FFTU_ERROR_NOT_D
 EXPORTS = ["fftu_version", "fftu_status_string", "fftu_last_error", "fftu_check", "fftu_describe", "fftu_plan",
            "fftu_get_plan_info", "fftu_plan_device_bytes", "fftu_execute", "fftu_stage_local_fft",
            "fftu_stage_twiddle", "fftu_stage_exchange", "fftu_stage_remaining_fft", "fftu_timing_begin",
-           "fftu_timing_end", "fftu_destroy"]
+           "fftu_timing_end", "fftu_set_tuning", "fftu_get_tuning", "fftu_destroy"]
+
+TUNE = {"line_strided_logw": 0, "line_contig_logw": 1, "line_pad": 2, "max_lds_kb": 3}
 
 
 class FftuError(RuntimeError):
@@ -85,6 +86,10 @@ def load_library(path: str = LIB_PATH):
     lib.fftu_timing_end.restype = ctypes.c_int
     lib.fftu_timing_end.argtypes = [vp, ctypes.POINTER(ctypes.c_float), ctypes.c_int,
                                     ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
+    lib.fftu_set_tuning.restype = ctypes.c_int
+    lib.fftu_set_tuning.argtypes = [ctypes.c_int, ctypes.c_int]
+    lib.fftu_get_tuning.restype = ctypes.c_int
+    lib.fftu_get_tuning.argtypes = [ctypes.c_int]
     lib.fftu_destroy.restype = None
     lib.fftu_destroy.argtypes = [vp]
     _lib = lib
@@ -123,10 +128,15 @@ def describe(n, p, dtype="complex128", direction=FORWARD) -> dict:
     return info.as_dict()
 
 
-@dataclass
-class _Shape:
-    n: tuple
-    p: tuple
+def set_tuning(name: str, value: int) -> None:
+    """Set a planner knob (see fftu_tune_param in include/fftu.h); -1 restores the default."""
+    st = load_library().fftu_set_tuning(TUNE[name], int(value))
+    if st != 0:
+        raise FftuError(st, f"fftu_set_tuning({name}={value})")
+
+
+def get_tuning(name: str) -> int:
+    return int(load_library().fftu_get_tuning(TUNE[name]))
 
 
 class Plan:
