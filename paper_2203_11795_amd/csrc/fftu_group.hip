@@ -112,6 +112,7 @@ __global__ __launch_bounds__(kLineMaxThreads) void k_group2(const cx<T> *in, cx<
             const int w = e >> LOGG, x1 = (e >> LOGL2) & (L1 - 1), x2 = e & (L2 - 1);
             tile[w * PG + x1 * P2 + x2] = conj_if(in[gbase + e], pd.conj_in);
         }
+        __syncthreads();   // the whole tile is in LDS before any line is read
         group_axis<T, LOGL2>(tile, base2, 1, j2, act2, tw2);
         group_axis<T, LOGL1>(tile, base1, P2, j1, act1, tw1);
         for (int e = tid; e < n; e += blockDim.x) {
