@@ -43,20 +43,15 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def kernel_symbols(info):
-    names = ["k_pass"] * info["s0_kernels"]
-    if info["exchange_fused"]:
-        names.append("k_exchange")
-    else:
-        names += ["k_twiddle", "k_permute"] + ["k_pass"] * (info["s2_kernels"] - 2)
-    return names
-
-
 def source_digest():
+    """Digest of every source the kernels are built from (counter summaries record it)."""
     h = hashlib.sha256()
-    for f in ["fftu_kernels.hip", "fftu_api.cpp", "fftu_internal.hpp"]:
-        with open(os.path.join(ROOT, "paper_2203_11795_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+    csrc = os.path.join(ROOT, "paper_2203_11795_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".hpp", ".cpp")):
+            with open(os.path.join(csrc, f), "rb") as fh:
+                h.update(f.encode())
+                h.update(fh.read())
     return h.hexdigest()
 
 
@@ -84,6 +79,8 @@ def main():
     ap.add_argument("--workload", default="512cube", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="time a plain device copy of the workload's N elements instead (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): this build has no multi-GPU path; "
@@ -101,6 +98,23 @@ def main():
     N = math.prod(n)
     esize = 16 if dtype == "complex128" else 8
     npdt = np.complex128 if dtype == "complex128" else np.complex64
+
+    if args.copy_calibration:
+        # A plain copy of N elements: its HBM counters read N*b fetched and N*b written.
+        src = torch.empty(N, dtype=torch.complex128 if esize == 16 else torch.complex64, device="cuda:0")
+        src.zero_()
+        dst = torch.empty_like(src)
+        for _ in range(args.warmup):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        print(json.dumps({"copy_bytes_each_way": N * esize, "ms": round(dt * 1e3, 4),
+                          "GBps": round(2 * N * esize / dt / 1e9, 1)}), flush=True)
+        return
 
     log(f"[bench] workload {args.workload}: generating input")
     gen = synth.uniform_complex if wl["dist"] == "uniform" else synth.normal_complex
@@ -135,7 +149,7 @@ def main():
 
     # Roofline of the dominant kernel: every launch reads and writes the N-element array once.
     alg_bytes = 2.0 * N * esize
-    syms = kernel_symbols(info)
+    syms = plan.launch_names()
     per_sym = {}
     for s, t in zip(syms, per_launch):
         tot, cnt = per_sym.get(s, (0.0, 0))
@@ -143,7 +157,7 @@ def main():
     dom = max(per_sym, key=lambda s: per_sym[s][0])
     dom_avg_ms = per_sym[dom][0] / per_sym[dom][1]
     achieved = alg_bytes / (dom_avg_ms * 1e-3) / 1e9
-    kname = f"{dom}<{'double' if esize == 16 else 'float'}>"
+    kname = dom
     traffic = measured_traffic(args.workload, kname)
     roofline = {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),

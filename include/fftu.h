@@ -150,6 +150,13 @@ fftu_plan_t fftu_plan(int d, const int64_t n[], const int64_t p[], fftu_dtype dt
 /* Fill *info for an existing plan. */
 fftu_status fftu_get_plan_info(fftu_plan_t plan, fftu_plan_info *info);
 
+/*
+ * Name of the kernel that fftu_execute launches at position i (0-based, i <
+ * launches), as the profiler reports it, e.g. "fftu::k_line<double, 7, 1>".
+ * The string is owned by the plan. NULL for a bad plan or index.
+ */
+const char *fftu_launch_name(fftu_plan_t plan, int i);
+
 /* Device bytes owned by the plan (table + workspace), for memory admission. */
 size_t fftu_plan_device_bytes(fftu_plan_t plan);
 

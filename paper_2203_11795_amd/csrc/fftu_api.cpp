@@ -13,6 +13,7 @@
 #include <cmath>
 #include <cstring>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "fftu_internal.hpp"
@@ -41,6 +42,7 @@ struct fftu_plan_s {
     bool fused = false;
     ExchangeDesc ex{};
     // per-kernel timing (fftu_timing_begin / fftu_timing_end)
+    std::vector<std::string> launch_names;   // kernel of each launch of fftu_execute
     std::vector<hipEvent_t> events;  // timing_max x (launches + 1)
     int timing_max = 0;
     int timing_used = 0;
@@ -475,6 +477,24 @@ void fill_info(const Geometry &G, const std::vector<PassDesc> &s0, bool fused, s
     info->table_bytes = (uint64_t(1) << G.lognmax) * esize;
 }
 
+// Profiler name of the kernel that runs a pass (matches the template arguments).
+std::string pass_kernel_name(const PassDesc &pd, fftu_dtype dt)
+{
+    const std::string t = dt == FFTU_C128 ? "double" : "float";
+    if (pd.kind == fftu::kGroup2)
+        return "fftu::k_group2<" + t + ", " + std::to_string(pd.loglen[0]) + ", " + std::to_string(pd.loglen[1]) + ">";
+    if (pd.kind == fftu::kTilePass) return "fftu::k_pass<" + t + ">";
+    return "fftu::k_line<" + t + ", " + std::to_string(pd.loglen[0]) + ", " + std::to_string(pd.kind) + ">";
+}
+
+std::string exchange_kernel_name(const ExchangeDesc &ex, fftu_dtype dt)
+{
+    const std::string t = dt == FFTU_C128 ? "double" : "float";
+    auto s = [](int v) { return std::to_string(v); };
+    const int lph = ex.nh ? ex.lph : 0, lpr = ex.nr ? ex.lpr : 0;
+    return "fftu::k_exchange<" + t + ", " + s(ex.nr) + ", " + s(lpr) + ", " + s(ex.nh) + ", " + s(lph) + ">";
+}
+
 fftu_status from_hip(hipError_t e)
 {
     if (e == hipSuccess) return FFTU_SUCCESS;
@@ -630,6 +650,15 @@ fftu_plan_t fftu_plan(int d, const int64_t n[], const int64_t p[], fftu_dtype dt
         fftu_plan_info info{};
         fill_info(G, pl->s0, pl->fused, pl->s2.size(), dtype, &info);
         pl->launches = info.launches;
+        for (const PassDesc &pd : pl->s0) pl->launch_names.push_back(pass_kernel_name(pd, dtype));
+        if (pl->fused) {
+            pl->launch_names.push_back(exchange_kernel_name(pl->ex, dtype));
+        } else {
+            const std::string t = dtype == FFTU_C128 ? "double" : "float";
+            pl->launch_names.push_back("fftu::k_twiddle<" + t + ">");
+            pl->launch_names.push_back("fftu::k_permute<" + t + ">");
+            for (const PassDesc &pd : pl->s2) pl->launch_names.push_back(pass_kernel_name(pd, dtype));
+        }
     }
 
     if (hipGetDevice(&pl->device) != hipSuccess) {
@@ -670,6 +699,16 @@ fftu_status fftu_get_plan_info(fftu_plan_t plan, fftu_plan_info *info)
     const Geometry G = geometry(plan->d, plan->n, plan->p);
     fill_info(G, plan->s0, plan->fused, plan->s2.size(), plan->dtype, info);
     return record(FFTU_SUCCESS);
+}
+
+const char *fftu_launch_name(fftu_plan_t plan, int i)
+{
+    if (!plan || i < 0 || i >= int(plan->launch_names.size())) {
+        record(FFTU_ERROR_INVALID_VALUE);
+        return nullptr;
+    }
+    record(FFTU_SUCCESS);
+    return plan->launch_names[size_t(i)].c_str();
 }
 
 size_t fftu_plan_device_bytes(fftu_plan_t plan)

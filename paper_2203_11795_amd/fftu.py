@@ -26,7 +26,7 @@ STATUS = {0: "FFTU_SUCCESS", 1: "FFTU_ERROR_INVALID_VALUE", 2: "FFTU_ERROR_NOT_D
 EXPORTS = ["fftu_version", "fftu_status_string", "fftu_last_error", "fftu_check", "fftu_describe", "fftu_plan",
            "fftu_get_plan_info", "fftu_plan_device_bytes", "fftu_execute", "fftu_stage_local_fft",
            "fftu_stage_twiddle", "fftu_stage_exchange", "fftu_stage_remaining_fft", "fftu_timing_begin",
-           "fftu_timing_end", "fftu_set_tuning", "fftu_get_tuning", "fftu_destroy"]
+           "fftu_timing_end", "fftu_set_tuning", "fftu_get_tuning", "fftu_launch_name", "fftu_destroy"]
 
 TUNE = {"line_strided_logw": 0, "line_contig_logw": 1, "line_pad": 2, "max_lds_kb": 3}
 
@@ -90,6 +90,8 @@ def load_library(path: str = LIB_PATH):
     lib.fftu_set_tuning.argtypes = [ctypes.c_int, ctypes.c_int]
     lib.fftu_get_tuning.restype = ctypes.c_int
     lib.fftu_get_tuning.argtypes = [ctypes.c_int]
+    lib.fftu_launch_name.restype = ctypes.c_char_p
+    lib.fftu_launch_name.argtypes = [vp, ctypes.c_int]
     lib.fftu_destroy.restype = None
     lib.fftu_destroy.argtypes = [vp]
     _lib = lib
@@ -173,6 +175,11 @@ class Plan:
         if st != 0:
             raise FftuError(st, "fftu_get_plan_info")
         return info.as_dict()
+
+    def launch_names(self):
+        """Profiler names of the kernels one execution launches, in order."""
+        n = self.info()["launches"]
+        return [self._lib.fftu_launch_name(self._h, i).decode() for i in range(n)]
 
     def device_bytes(self) -> int:
         return int(self._lib.fftu_plan_device_bytes(self._h))

@@ -121,3 +121,26 @@ def test_describe(n, p, dtype, s0, fused, launches):
 def test_info_struct_layout_matches_header():
     # int32 d, int64 N, P, M, 4 x int32, 2 x uint64
     assert ctypes.sizeof(binding.PlanInfo) == 4 + 4 + 8 * 3 + 4 * 4 + 8 * 2
+
+
+def test_tuning_knobs_roundtrip_and_ranges():
+    names = ["line_strided_logw", "line_contig_logw", "line_pad", "max_lds_kb"]
+    try:
+        for name in names:
+            assert fftu.get_tuning(name) == -1
+        fftu.set_tuning("line_strided_logw", 4)
+        assert fftu.get_tuning("line_strided_logw") == 4
+        for name, bad in [("line_strided_logw", 1), ("line_strided_logw", 7), ("line_pad", 5), ("max_lds_kb", 8),
+                          ("max_lds_kb", 161), ("line_contig_logw", 9)]:
+            with pytest.raises(fftu.FftuError):
+                fftu.set_tuning(name, bad)
+        lib = fftu.load_library()
+        assert lib.fftu_set_tuning(99, 1) == 1
+        assert lib.fftu_get_tuning(-1) == -1 and lib.fftu_last_error() == 1
+        # planning is unchanged in what it computes; only tiling moves
+        base = fftu.describe((512, 512, 512), (4, 4, 4))
+        fftu.set_tuning("line_strided_logw", 3)
+        assert fftu.describe((512, 512, 512), (4, 4, 4)) == base
+    finally:
+        for name in names:
+            fftu.set_tuning(name, -1)

@@ -204,3 +204,33 @@ def test_512_cubed_full_size(torch_dev):
     err = oracle.rel_l2(got, want)
     say(f"512^3 rel-L2 {err:.3e}")
     assert err <= 1e-12
+
+
+def test_launch_names(torch_dev):
+    import paper_2203_11795_amd as fftu
+    with fftu.Plan((512, 512, 512), (4, 4, 4), "complex128", FORWARD) as plan:
+        assert plan.launch_names() == ["fftu::k_line<double, 7, 2>", "fftu::k_line<double, 7, 1>",
+                                       "fftu::k_line<double, 7, 1>", "fftu::k_exchange<double, 2, 2, 1, 2>"]
+    with fftu.Plan((64,) * 5, (2,) * 5, "complex64", FORWARD) as plan:
+        names = plan.launch_names()
+        assert names[0] == "fftu::k_group2<float, 5, 5>" and names[-1] == "fftu::k_exchange<float, 5, 1, 0, 0>"
+    with fftu.Plan((64, 64, 64), (8, 8, 2), "complex128", FORWARD) as plan:
+        assert plan.launch_names()[-4:-2] == ["fftu::k_twiddle<double>", "fftu::k_permute<double>"]
+
+
+@pytest.mark.parametrize("knob,values", [("line_strided_logw", [2, 3, 4, 5]), ("line_contig_logw", [0, 1, 3, 5]),
+                                         ("line_pad", [0, 2, 4]), ("max_lds_kb", [16, 160])])
+def test_tuning_changes_tiling_not_results(torch_dev, knob, values):
+    """Tiling knobs move work between workgroups; every element sees the same arithmetic."""
+    import paper_2203_11795_amd as fftu
+    n, p = (64, 128, 256), (2, 2, 4)
+    D = synth.uniform_complex(int(np.prod(n)), 31)
+    base = run_plan(torch_dev, n, p, "complex128", FORWARD, D)
+    assert oracle.rel_l2(base, oracle.cyclic_dft(D, n, p)) <= 1e-12
+    try:
+        for v in values:
+            fftu.set_tuning(knob, v)
+            got = run_plan(torch_dev, n, p, "complex128", FORWARD, D)
+            assert oracle.rel_l2(got, base) <= 1e-15, (knob, v)
+    finally:
+        fftu.set_tuning(knob, -1)
