@@ -201,6 +201,46 @@ fftu_status fftu_stage_remaining_fft(fftu_plan_t plan, const void *in, void *out
 fftu_status fftu_timing_begin(fftu_plan_t plan, int max_calls);
 fftu_status fftu_timing_end(fftu_plan_t plan, float *avg_ms, int capacity, int *nkernels, int *ncalls);
 
+/*
+ * Batches (many independent transforms, uneven shapes, one persistent launch).
+ *
+ * fftu_plan_batch plans `count` transforms; transform i has d[i] dimensions,
+ * sizes n[i][0..d[i]-1] and grid p[i][0..d[i]-1], each a separate instance of
+ * Algorithm 2.3 with the buffer layout described above. All share dtype and
+ * direction. Supported members: every local length n_l/p_l <= 256 with local
+ * size M >= 2, and a grid whose length-p transforms fit one thread's registers
+ * (at most 16 complex128 / 32 complex64 points, equal sides); others give
+ * FFTU_ERROR_UNSUPPORTED. The plan owns one twiddle table, a workspace of
+ * sum_i N_i elements and the work list in device memory.
+ *
+ * fftu_execute_batch runs every transform: out[i] = F(in[i]); in and out are
+ * host arrays of `count` device pointers (in[i] == out[i] allowed). The
+ * pointers are bound to the plan's device work list; when they differ from the
+ * previous call the new ones are uploaded first, which waits for `stream` and
+ * copies the list synchronously. With unchanged pointers the call only enqueues
+ * two kernels (a counter reset and the persistent kernel) and returns.
+ *
+ * fftu_batch_error reports (after waiting for the device) whether the last
+ * batch on this plan hit its bounded dependency wait (1) or not (0).
+ */
+fftu_plan_t fftu_plan_batch(int count, const int d[], const int64_t *const n[], const int64_t *const p[],
+                            fftu_dtype dtype, fftu_direction direction);
+fftu_status fftu_execute_batch(fftu_plan_t plan, const void *const in[], void *const out[], hipStream_t stream);
+fftu_status fftu_batch_error(fftu_plan_t plan, int *flag);
+
+/*
+ * HIP graphs: fftu_graph_capture records the launches of one fftu_execute
+ * (count = 0, in/out point at one device pointer each) or one
+ * fftu_execute_batch (count = the batch size, in/out arrays of count device
+ * pointers) on a private stream and instantiates them. fftu_graph_launch
+ * replays the graph on `stream`; the buffers are the ones given at capture.
+ * The graph refers to the plan, which must outlive it. NULL on failure.
+ */
+typedef struct fftu_graph_s *fftu_graph_t;
+fftu_graph_t fftu_graph_capture(fftu_plan_t plan, int count, const void *const in[], void *const out[]);
+fftu_status fftu_graph_launch(fftu_graph_t graph, hipStream_t stream);
+void fftu_graph_destroy(fftu_graph_t graph);
+
 /* Release a plan and its device memory. NULL is ignored. The caller must make
  * sure no enqueued work still uses the plan. */
 void fftu_destroy(fftu_plan_t plan);

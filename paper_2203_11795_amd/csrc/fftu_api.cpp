@@ -43,6 +43,26 @@ struct fftu_plan_s {
     ExchangeDesc ex{};
     // per-kernel timing (fftu_timing_begin / fftu_timing_end)
     std::vector<std::string> launch_names;   // kernel of each launch of fftu_execute
+    // batch plans (fftu_plan_batch)
+    bool is_batch = false;
+    int count = 0;
+    std::vector<int64_t> member_N;             // elements of each transform
+    std::vector<uint64_t> member_ws;           // workspace offset (elements) of each transform
+    std::vector<fftu::BatchStage> hstages;     // host copy of the work list
+    std::vector<int> stage_member;             // transform of each descriptor
+    std::vector<int> stage_first;              // 1 if the descriptor reads the transform's input
+    std::vector<int> stage_last;               // 1 if it writes the transform's output
+    int64_t batch_items = 0;
+    uint32_t batch_blocks = 0;
+    uint32_t batch_lds = 0;
+    void *dstages = nullptr;
+    void *dstarts = nullptr;
+    void *ddep = nullptr;
+    void *ddone = nullptr;
+    void *dnext = nullptr;
+    void *derror = nullptr;
+    std::vector<const void *> bound_in;
+    std::vector<void *> bound_out;
     std::vector<hipEvent_t> events;  // timing_max x (launches + 1)
     int timing_max = 0;
     int timing_used = 0;
@@ -335,13 +355,6 @@ GridDesc make_grid(const Geometry &G)
     return g;
 }
 
-int bitrev(int x, int bits)
-{
-    int r = 0;
-    for (int i = 0; i < bits; ++i) r |= ((x >> i) & 1) << (bits - 1 - i);
-    return r;
-}
-
 // Split of the grid for k_exchange: the dimensions with p_l > 1, in order, become
 // nh leading wave dimensions (all of one size 2^lph, at most 2 bits in total) and
 // nr trailing register dimensions (all of one size 2^lpr, at most 16 complex128 or
@@ -557,7 +570,66 @@ fftu_status check_exec_args(const fftu_plan_s *plan, const void *in, const void 
     return FFTU_SUCCESS;
 }
 
+// ---------------------------------------------------------------------------
+// Batches
+// ---------------------------------------------------------------------------
+bool batch_exchange_ok(const ExchangeSplit &sp)
+{
+    if (sp.nh != 0) return false;
+    const int key = sp.nr * 8 + sp.lpr;
+    return key == 0 || key == 9 || key == 17 || key == 25 || key == 33 || key == 10 || key == 18 || key == 11 ||
+           key == 12;
+}
+
+void free_batch(fftu_plan_s *pl)
+{
+    for (void *ptr : {pl->dstages, pl->dstarts, pl->ddep, pl->ddone, pl->dnext, pl->derror})
+        if (ptr) (void)hipFree(ptr);
+    pl->dstages = pl->dstarts = pl->ddep = pl->ddone = pl->dnext = pl->derror = nullptr;
+}
+
+// Upload the work list with the given buffers (waits for `stream` first).
+fftu_status bind_batch(fftu_plan_s *pl, const void *const in[], void *const out[], hipStream_t stream)
+{
+    hipError_t e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return from_hip(e);
+    const size_t es = pl->esize;
+    for (size_t k = 0; k < pl->hstages.size(); ++k) {
+        const int f = pl->stage_member[k];
+        char *ws = static_cast<char *>(pl->ws) + pl->member_ws[size_t(f)] * es;
+        fftu::BatchStage &st = pl->hstages[k];
+        st.src = pl->stage_first[k] ? in[f] : ws;
+        st.dst = pl->stage_last[k] ? out[f] : static_cast<void *>(ws);
+    }
+    e = hipMemcpy(pl->dstages, pl->hstages.data(), pl->hstages.size() * sizeof(fftu::BatchStage),
+                  hipMemcpyHostToDevice);
+    if (e != hipSuccess) return from_hip(e);
+    pl->bound_in.assign(in, in + pl->count);
+    pl->bound_out.assign(out, out + pl->count);
+    return FFTU_SUCCESS;
+}
+
+fftu_status enqueue_batch(fftu_plan_s *pl, hipStream_t stream)
+{
+    fftu::BatchDesc bd{};
+    bd.nstages = int32_t(pl->hstages.size());
+    bd.spin_limit = 1 << 24;
+    bd.nitems = pl->batch_items;
+    bd.stages = static_cast<const fftu::BatchStage *>(pl->dstages);
+    bd.starts = static_cast<const int64_t *>(pl->dstarts);
+    bd.dep = static_cast<const int32_t *>(pl->ddep);
+    bd.done = static_cast<int32_t *>(pl->ddone);
+    bd.next = static_cast<unsigned long long *>(pl->dnext);
+    bd.error = static_cast<int32_t *>(pl->derror);
+    return from_hip(fftu::launch_batch(pl->prec, bd, pl->table, pl->batch_blocks, pl->batch_lds, stream));
+}
+
 }  // namespace
+
+struct fftu_graph_s {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
 
 extern "C" {
 
@@ -691,6 +763,266 @@ fftu_plan_t fftu_plan(int d, const int64_t n[], const int64_t p[], fftu_dtype dt
     }
     record(FFTU_SUCCESS);
     return pl;
+}
+
+fftu_plan_t fftu_plan_batch(int count, const int d[], const int64_t *const n[], const int64_t *const p[],
+                            fftu_dtype dtype, fftu_direction direction)
+{
+    if (count < 1 || !d || !n || !p) {
+        record(FFTU_ERROR_INVALID_VALUE);
+        return nullptr;
+    }
+    for (int f = 0; f < count; ++f) {
+        fftu_status s = validate(d[f], n[f], p[f], dtype, direction);
+        if (s != FFTU_SUCCESS) {
+            record(s);
+            return nullptr;
+        }
+    }
+    fftu_plan_s *pl = new (std::nothrow) fftu_plan_s();
+    if (!pl) {
+        record(FFTU_ERROR_OUT_OF_MEMORY);
+        return nullptr;
+    }
+    pl->is_batch = true;
+    pl->count = count;
+    pl->dtype = dtype;
+    pl->dir = direction;
+    pl->prec = dtype == FFTU_C128 ? Precision::F64 : Precision::F32;
+    pl->esize = dtype == FFTU_C128 ? 16 : 8;
+    const int inv = direction == FFTU_INVERSE ? 1 : 0;
+
+    // per-transform stages: line passes of Superstep 0, then the fused exchange
+    struct Member {
+        std::vector<PassDesc> s0;
+        ExchangeDesc ex;
+        int64_t M;
+    };
+    std::vector<Member> mem(static_cast<size_t>(count));
+    int lognmax = 0, smax = 0;
+    uint64_t ws_total = 0;
+    uint32_t tile_lds = 0;
+    fftu_status bad = FFTU_SUCCESS;
+    for (int f = 0; f < count && bad == FFTU_SUCCESS; ++f) {
+        const Geometry G = geometry(d[f], n[f], p[f]);
+        lognmax = std::max(lognmax, G.lognmax);
+        const GridDesc g = make_grid(G);
+        Member &m = mem[size_t(f)];
+        m.M = g.M;
+        for (int l = G.d - 1; l >= 0; --l) {
+            if (G.logm[l] == 0) continue;
+            int logA = G.logP, logB = 0;
+            for (int j = 0; j < l; ++j) logA += G.logm[j];
+            for (int j = l + 1; j < G.d; ++j) logB += G.logm[j];
+            PassDesc pd;
+            if (G.logm[l] > fftu::kBatchMaxLogLine || !make_line_pass(logA, G.logm[l], logB, dtype, G.lognmax, pd) ||
+                pd.threads > fftu::kBatchThreads) {
+                bad = FFTU_ERROR_UNSUPPORTED;
+                break;
+            }
+            tile_lds = std::max(tile_lds, uint32_t(pd.lds_bytes - (uint32_t(1) << G.logm[l]) * pl->esize));
+            m.s0.push_back(pd);
+        }
+        ExchangeSplit sp;
+        if (bad == FFTU_SUCCESS && (m.s0.empty() || !exchange_split(G, dtype, &sp) || !batch_exchange_ok(sp)))
+            bad = FFTU_ERROR_UNSUPPORTED;
+        if (bad != FFTU_SUCCESS) break;
+        m.ex = make_exchange(G, g, sp, dtype);
+        m.s0.front().conj_in = inv;
+        m.ex.g.conj_out = inv;
+        m.ex.g.scale = inv ? 1.0 / double(g.N) : 1.0;
+        pl->member_N.push_back(g.N);
+        pl->member_ws.push_back(ws_total);
+        ws_total += uint64_t(g.N);
+        smax = std::max(smax, int(m.s0.size()) + 1);
+    }
+    if (bad != FFTU_SUCCESS) {
+        delete pl;
+        record(bad);
+        return nullptr;
+    }
+    // stage-major work list
+    std::vector<int> last_desc(size_t(count), -1);
+    std::vector<int64_t> starts{0};
+    std::vector<int32_t> dep;
+    for (int s = 0; s < smax; ++s) {
+        for (int f = 0; f < count; ++f) {
+            const Member &m = mem[size_t(f)];
+            const int ns0 = int(m.s0.size());
+            if (s > ns0) continue;
+            fftu::BatchStage st{};
+            int64_t items;
+            if (s < ns0) {
+                st.kind = m.s0[size_t(s)].kind;
+                st.pd = m.s0[size_t(s)];
+                items = st.pd.tiles;
+            } else {
+                st.kind = fftu::kExchangeStage;
+                st.ex = m.ex;
+                const int64_t ngroups = (m.M + 63) / 64;
+                items = (ngroups + 3) / 4;
+            }
+            // every stage indexes the batch's one table of omega_{2^lognmax}
+            st.pd.lognmax = lognmax;
+            st.ex.g.lognmax = lognmax;
+            pl->hstages.push_back(st);
+            pl->stage_member.push_back(f);
+            pl->stage_first.push_back(s == 0 ? 1 : 0);
+            pl->stage_last.push_back(s == ns0 ? 1 : 0);
+            dep.push_back(last_desc[size_t(f)]);
+            last_desc[size_t(f)] = int(pl->hstages.size()) - 1;
+            starts.push_back(starts.back() + items);
+        }
+    }
+    pl->batch_items = starts.back();
+    pl->batch_lds = uint32_t(fftu::kBatchMaxLine) * uint32_t(pl->esize) + tile_lds;
+
+    hipError_t e = hipGetDevice(&pl->device);
+    const int64_t L = int64_t(1) << lognmax;
+    const std::vector<double> t64 = make_table_f64(lognmax);
+    pl->table_bytes = uint64_t(L) * pl->esize;
+    pl->ws_bytes = ws_total * pl->esize;
+    const size_t K = pl->hstages.size();
+    if (e == hipSuccess) e = hipMalloc(&pl->table, pl->table_bytes);
+    if (e == hipSuccess) e = hipMalloc(&pl->ws, pl->ws_bytes);
+    if (e == hipSuccess) e = hipMalloc(&pl->dstages, K * sizeof(fftu::BatchStage));
+    if (e == hipSuccess) e = hipMalloc(&pl->dstarts, (K + 1) * sizeof(int64_t));
+    if (e == hipSuccess) e = hipMalloc(&pl->ddep, K * sizeof(int32_t));
+    if (e == hipSuccess) e = hipMalloc(&pl->ddone, K * sizeof(int32_t));
+    if (e == hipSuccess) e = hipMalloc(&pl->dnext, sizeof(unsigned long long));
+    if (e == hipSuccess) e = hipMalloc(&pl->derror, sizeof(int32_t));
+    if (e == hipSuccess) e = hipMemcpy(pl->dstarts, starts.data(), (K + 1) * sizeof(int64_t), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(pl->ddep, dep.data(), K * sizeof(int32_t), hipMemcpyHostToDevice);
+    if (e == hipSuccess) {
+        if (dtype == FFTU_C128) {
+            e = hipMemcpy(pl->table, t64.data(), pl->table_bytes, hipMemcpyHostToDevice);
+        } else {
+            std::vector<float> t32(t64.size());
+            for (size_t i = 0; i < t64.size(); ++i) t32[i] = float(t64[i]);
+            e = hipMemcpy(pl->table, t32.data(), pl->table_bytes, hipMemcpyHostToDevice);
+        }
+    }
+    int cus = 0;
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, pl->device);
+    if (e != hipSuccess) {
+        fftu_status st = from_hip(e);
+        free_batch(pl);
+        if (pl->table) (void)hipFree(pl->table);
+        if (pl->ws) (void)hipFree(pl->ws);
+        delete pl;
+        record(st);
+        return nullptr;
+    }
+    const int64_t resident = int64_t(fftu::batch_blocks_per_cu(pl->prec, pl->batch_lds)) * int64_t(cus);
+    pl->batch_blocks = uint32_t(std::max<int64_t>(1, std::min<int64_t>(resident, pl->batch_items)));
+    pl->launches = 2;
+    pl->launch_names = {"fftu::k_batch_reset", std::string("fftu::k_batch<") +
+                                                   (dtype == FFTU_C128 ? "double" : "float") + ">"};
+    int64_t Ntot = 0;
+    for (int64_t v : pl->member_N) Ntot += v;
+    pl->grid.N = Ntot;
+    pl->d = 0;
+    record(FFTU_SUCCESS);
+    return pl;
+}
+
+fftu_status fftu_execute_batch(fftu_plan_t plan, const void *const in[], void *const out[], hipStream_t stream)
+{
+    if (!plan || !plan->is_batch || !in || !out) return record(FFTU_ERROR_INVALID_VALUE);
+    bool same = plan->bound_in.size() == size_t(plan->count);
+    for (int f = 0; f < plan->count; ++f) {
+        if (!in[f] || !out[f]) return record(FFTU_ERROR_INVALID_VALUE);
+        if (same && (plan->bound_in[size_t(f)] != in[f] || plan->bound_out[size_t(f)] != out[f])) same = false;
+    }
+    if (!same) {
+        fftu_status s = bind_batch(plan, in, out, stream);
+        if (s != FFTU_SUCCESS) return record(s);
+    }
+    Marker mk(plan, stream);
+    mk.mark();
+    fftu_status s = enqueue_batch(plan, stream);
+    if (s == FFTU_SUCCESS) {
+        mk.mark();
+        mk.mark();
+    }
+    return record(s);
+}
+
+fftu_status fftu_batch_error(fftu_plan_t plan, int *flag)
+{
+    if (!plan || !plan->is_batch || !flag) return record(FFTU_ERROR_INVALID_VALUE);
+    int32_t v = 0;
+    hipError_t e = hipMemcpy(&v, plan->derror, sizeof(v), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return record(from_hip(e));
+    *flag = v;
+    return record(FFTU_SUCCESS);
+}
+
+fftu_graph_t fftu_graph_capture(fftu_plan_t plan, int count, const void *const in[], void *const out[])
+{
+    if (!plan || !in || !out || count < 0 || (count > 0) != plan->is_batch || (count > 0 && count != plan->count)) {
+        record(FFTU_ERROR_INVALID_VALUE);
+        return nullptr;
+    }
+    hipStream_t s = nullptr;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+        record(FFTU_ERROR_DEVICE);
+        return nullptr;
+    }
+    fftu_status st = FFTU_SUCCESS;
+    if (count > 0) {
+        // bind outside the capture (the upload synchronises)
+        bool same = plan->bound_in.size() == size_t(count);
+        for (int f = 0; f < count && same; ++f)
+            same = plan->bound_in[size_t(f)] == in[f] && plan->bound_out[size_t(f)] == out[f];
+        if (!same) st = bind_batch(plan, in, out, s);
+    }
+    fftu_graph_s *gr = nullptr;
+    if (st == FFTU_SUCCESS) {
+        gr = new (std::nothrow) fftu_graph_s();
+        if (!gr) st = FFTU_ERROR_OUT_OF_MEMORY;
+    }
+    if (st == FFTU_SUCCESS) {
+        hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            const int saved_max = plan->timing_max;
+            plan->timing_max = 0;   // no timing events inside a graph
+            st = count > 0 ? enqueue_batch(plan, s) : fftu_execute(plan, in[0], out[0], s);
+            plan->timing_max = saved_max;
+            hipError_t e2 = hipStreamEndCapture(s, &gr->graph);
+            if (st == FFTU_SUCCESS && e2 != hipSuccess) st = from_hip(e2);
+        } else {
+            st = from_hip(e);
+        }
+        if (st == FFTU_SUCCESS) st = from_hip(hipGraphInstantiate(&gr->exec, gr->graph, nullptr, nullptr, 0));
+    }
+    (void)hipStreamDestroy(s);
+    if (st != FFTU_SUCCESS) {
+        if (gr) {
+            if (gr->exec) (void)hipGraphExecDestroy(gr->exec);
+            if (gr->graph) (void)hipGraphDestroy(gr->graph);
+            delete gr;
+        }
+        record(st);
+        return nullptr;
+    }
+    record(FFTU_SUCCESS);
+    return gr;
+}
+
+fftu_status fftu_graph_launch(fftu_graph_t graph, hipStream_t stream)
+{
+    if (!graph || !graph->exec) return record(FFTU_ERROR_INVALID_VALUE);
+    return record(from_hip(hipGraphLaunch(graph->exec, stream)));
+}
+
+void fftu_graph_destroy(fftu_graph_t graph)
+{
+    if (!graph) return;
+    if (graph->exec) (void)hipGraphExecDestroy(graph->exec);
+    if (graph->graph) (void)hipGraphDestroy(graph->graph);
+    delete graph;
+    record(FFTU_SUCCESS);
 }
 
 fftu_status fftu_get_plan_info(fftu_plan_t plan, fftu_plan_info *info)
@@ -856,6 +1188,7 @@ void fftu_destroy(fftu_plan_t plan)
     const bool have_cur = hipGetDevice(&cur) == hipSuccess;
     if (have_cur && cur != plan->device) (void)hipSetDevice(plan->device);
     for (hipEvent_t ev : plan->events) (void)hipEventDestroy(ev);
+    free_batch(plan);
     if (plan->table) (void)hipFree(plan->table);
     if (plan->ws) (void)hipFree(plan->ws);
     if (have_cur && cur != plan->device) (void)hipSetDevice(cur);

@@ -1,0 +1,181 @@
+// Persistent batch kernel: many independent transforms of uneven shapes (each
+// Algorithm 2.3 of arXiv 2203.11795 on its own grid) in one launch.
+//
+// The batch is a list of stage descriptors, one per (stage, transform), in
+// stage-major order: every transform's first Superstep-0 pass, then every
+// second pass, ..., then every exchange. Each descriptor owns a contiguous range
+// of work items (tiles of a k_line pass, or groups of the fused exchange).
+// Workgroups take items from one global counter in that order. Before an item
+// of a descriptor with a dependency (the previous stage of the same transform)
+// runs, its workgroup waits until every item of that dependency has finished;
+// because items are handed out in stage-major order, every dependency is
+// already held by a running workgroup, so the wait always ends. The wait is
+// bounded all the same: past spin_limit polls the workgroup records an error
+// flag and skips the item, so every workgroup reaches the end.
+//
+// Completion protocol: each thread's stores of a finished item are released
+// with a device-scope fence, then one thread increments the descriptor's
+// counter; a waiting workgroup reads the counter with device-scope acquire and
+// every thread issues a device-scope acquire fence before reading the data.
+// Counters are cleared by k_batch_reset (a kernel, so the pair can be captured
+// in a graph and replayed).
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "fftu_exchange.hpp"
+#include "fftu_line.hpp"
+
+namespace fftu {
+
+__global__ void k_batch_reset(BatchDesc bd)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < bd.nstages; i += gridDim.x * blockDim.x) bd.done[i] = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        *bd.next = 0;
+        *bd.error = 0;
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void run_line(const BatchStage &st, const cx<T> *__restrict__ table, cx<T> *tw,
+                                         cx<T> *tile, int64_t t, int tid)
+{
+    const cx<T> *in = static_cast<const cx<T> *>(st.src);
+    cx<T> *out = static_cast<cx<T> *>(st.dst);
+    const PassDesc &pd = st.pd;
+#define FFTU_LINE_CASE(LG, MD)                                                    \
+    case (LG) * 8 + (MD):                                                         \
+        line_twiddles<T, LG>(tw, table, pd.lognmax, tid);                         \
+        __syncthreads();                                                          \
+        line_tile<T, LG, MD>(in, out, pd, tw, tile, t, tid);                      \
+        break;
+#define FFTU_LINE_MODES(LG) FFTU_LINE_CASE(LG, kLineStrided) FFTU_LINE_CASE(LG, kLineContig) FFTU_LINE_CASE(LG, kLineStaged)
+    switch (pd.loglen[0] * 8 + pd.kind) {
+        FFTU_LINE_MODES(1)
+        FFTU_LINE_MODES(2)
+        FFTU_LINE_MODES(3)
+        FFTU_LINE_MODES(4)
+        FFTU_LINE_MODES(5)
+        FFTU_LINE_MODES(6)
+        FFTU_LINE_MODES(7)
+        FFTU_LINE_MODES(8)
+    default: break;
+    }
+#undef FFTU_LINE_MODES
+#undef FFTU_LINE_CASE
+}
+
+template <typename T>
+__device__ __forceinline__ void run_exchange(const BatchStage &st, const cx<T> *__restrict__ table,
+                                             unsigned char *smem, int64_t t, int tid)
+{
+    const cx<T> *Z = static_cast<const cx<T> *>(st.src);
+    cx<T> *V = static_cast<cx<T> *>(st.dst);
+    const ExchangeDesc &ex = st.ex;
+    const int64_t gb = t * (kExchangeThreads / 64);   // no wave dimensions in a batch: 4 groups per item
+#define FFTU_EX_CASE(NR, LPR)                                                     \
+    case (NR) * 8 + (LPR):                                                        \
+        exchange_group<T, NR, LPR, 0, 0>(Z, V, ex, table, smem, gb, tid);         \
+        break;
+    switch (ex.nr * 8 + ex.lpr) {
+        FFTU_EX_CASE(0, 0)
+        FFTU_EX_CASE(1, 1)
+        FFTU_EX_CASE(2, 1)
+        FFTU_EX_CASE(3, 1)
+        FFTU_EX_CASE(4, 1)
+        FFTU_EX_CASE(1, 2)
+        FFTU_EX_CASE(2, 2)
+        FFTU_EX_CASE(1, 3)
+        FFTU_EX_CASE(1, 4)
+    default: break;
+    }
+#undef FFTU_EX_CASE
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBatchThreads) void k_batch(const BatchDesc bd, const cx<T> *__restrict__ table)
+{
+    extern __shared__ unsigned char smem_raw[];
+    __shared__ int64_t s_item;
+    __shared__ int s_k;
+    __shared__ int s_skip;
+    cx<T> *tw = reinterpret_cast<cx<T> *>(smem_raw);       // omega_L, L <= kBatchMaxLine
+    cx<T> *tile = tw + kBatchMaxLine;
+    const int tid = threadIdx.x;
+    for (;;) {
+        if (tid == 0) {
+            const int64_t item = int64_t(atomicAdd(bd.next, 1ull));
+            int k = -1, skip = 0;
+            if (item < bd.nitems) {
+                // descriptor k owns items [starts[k], starts[k + 1])
+                int lo = 0, hi = bd.nstages - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (bd.starts[mid] <= item) lo = mid;
+                    else hi = mid - 1;
+                }
+                k = lo;
+                const int dep = bd.dep[k];
+                if (dep >= 0) {
+                    const int need = int(bd.starts[dep + 1] - bd.starts[dep]);
+                    int polls = 0;
+                    while (__hip_atomic_load(&bd.done[dep], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < need) {
+                        // give up past the poll limit, or at once once another wait has given up
+                        if (++polls > bd.spin_limit ||
+                            __hip_atomic_load(bd.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+                            atomicExch(bd.error, 1);
+                            skip = 1;
+                            break;
+                        }
+                        __builtin_amdgcn_s_sleep(2);
+                    }
+                }
+            }
+            s_item = item;
+            s_k = k;
+            s_skip = skip;
+        }
+        __syncthreads();
+        const int64_t item = s_item;
+        const int k = s_k;
+        const int skip = s_skip;
+        if (item >= bd.nitems) break;
+        if (bd.dep[k] >= 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        const BatchStage &st = bd.stages[k];
+        const int64_t t = item - bd.starts[k];
+        if (!skip) {
+            if (st.kind == kExchangeStage) run_exchange<T>(st, table, smem_raw + kBatchMaxLine * sizeof(cx<T>), t, tid);
+            else run_line<T>(st, table, tw, tile, t, tid);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __syncthreads();
+        if (tid == 0) __hip_atomic_fetch_add(&bd.done[k], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+int batch_blocks_per_cu(Precision prec, uint32_t lds_bytes)
+{
+    int nb = 0;
+    hipError_t e = prec == Precision::F64
+                       ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch<double>, kBatchThreads, lds_bytes)
+                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch<float>, kBatchThreads, lds_bytes);
+    return e == hipSuccess && nb > 0 ? nb : 1;
+}
+
+hipError_t launch_batch(Precision prec, const BatchDesc &bd, const void *table, uint32_t blocks, uint32_t lds_bytes,
+                        hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_batch_reset, dim3(uint32_t((bd.nstages + 255) / 256 + 1)), dim3(256), 0, stream, bd);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (prec == Precision::F64)
+        hipLaunchKernelGGL(k_batch<double>, dim3(blocks), dim3(kBatchThreads), lds_bytes, stream, bd,
+                           static_cast<const cx<double> *>(table));
+    else
+        hipLaunchKernelGGL(k_batch<float>, dim3(blocks), dim3(kBatchThreads), lds_bytes, stream, bd,
+                           static_cast<const cx<float> *>(table));
+    return hipGetLastError();
+}
+
+}  // namespace fftu

@@ -96,6 +96,33 @@ struct ExchangeDesc {
     uint32_t lds_bytes;
 };
 
+// Persistent batch (fftu_batch.hip). One descriptor per (stage, transform).
+constexpr int kBatchThreads = 256;
+constexpr int kBatchMaxLogLine = 8;     // longest Superstep-0 line of a batched transform: 2^8
+constexpr int kBatchMaxLine = 1 << kBatchMaxLogLine;
+constexpr int kExchangeStage = 8;       // BatchStage::kind of the fused exchange
+
+struct BatchStage {
+    int32_t kind;          // kLineStrided / kLineContig / kLineStaged, or kExchangeStage
+    int32_t reserved;
+    const void *src;
+    void *dst;
+    PassDesc pd;           // line passes
+    ExchangeDesc ex;       // the exchange (no wave dimensions)
+};
+
+struct BatchDesc {
+    int32_t nstages;             // descriptors
+    int32_t spin_limit;          // polls before a dependency wait gives up (error flag)
+    int64_t nitems;              // work items in total
+    const BatchStage *stages;    // [nstages], stage-major
+    const int64_t *starts;       // [nstages + 1] first item of each descriptor
+    const int32_t *dep;          // [nstages] descriptor that must finish first, or -1
+    int32_t *done;               // [nstages] finished items
+    unsigned long long *next;    // next item to hand out
+    int32_t *error;              // set when a wait gave up
+};
+
 enum class Precision { F32, F64 };
 
 // Launchers (fftu_kernels.hip). All return hipSuccess or the launch error.
@@ -105,6 +132,9 @@ hipError_t launch_line(Precision prec, const void *in, void *out, const PassDesc
                        hipStream_t stream);
 hipError_t launch_group2(Precision prec, const void *in, void *out, const PassDesc &pd, const void *table,
                          hipStream_t stream);
+hipError_t launch_batch(Precision prec, const BatchDesc &bd, const void *table, uint32_t blocks, uint32_t lds_bytes,
+                        hipStream_t stream);
+int batch_blocks_per_cu(Precision prec, uint32_t lds_bytes);
 hipError_t launch_twiddle(Precision prec, const void *in, void *out, const GridDesc &g, const void *table,
                           hipStream_t stream);
 hipError_t launch_permute(Precision prec, const void *in, void *out, const GridDesc &g, hipStream_t stream);

@@ -1,0 +1,167 @@
+// k_line device code (one tile at a time), shared by the k_line kernels and the
+// persistent batch kernel. See fftu_line.hip for the description of the pass.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "fftu_device.hpp"
+#include "fftu_internal.hpp"
+
+namespace fftu {
+
+
+// LDS index of position x of line w. Strided layout: line positions are rows of W
+// (lanes run over w); contiguous layouts: one row per line, one pad element per 16
+// so that radix-16 scatters (stride 16) spread over the banks.
+template <int MODE>
+__device__ __forceinline__ int lidx(int x, int w, int pitch)
+{
+    return MODE == kLineStrided ? x * pitch + w : w * pitch + x + (x >> 4);
+}
+
+// Exchange of a line through LDS between radix stage S and S+1: stage S's
+// outputs are written at their Stockham positions and the next stage's inputs
+// (register m <-> position j + TPL m) are read back. complex128 lines go through
+// LDS as two rounds of doubles (real parts, then imaginary parts) so that a tile
+// needs 8 bytes of LDS per element; complex64 lines go in one round.
+template <typename T, int LOGL, int S, int MODE, typename V, typename GET>
+__device__ __forceinline__ void line_scatter(const cx<T> (&v)[LinePlan<LOGL>::E], int j, int w, int pitch, V *lds,
+                                             GET get)
+{
+    using PL = LinePlan<LOGL>;
+    constexpr int LR = PL::lr(S), R = 1 << LR, LNS = PL::lns(S), NB = PL::E / R;
+#pragma unroll
+    for (int c = 0; c < NB; ++c) {
+        const int jj = j + c * PL::TPL;
+        const int ob = ((jj >> LNS) << (LNS + LR)) + (jj & ((1 << LNS) - 1));
+#pragma unroll
+        for (int r = 0; r < R; ++r) lds[lidx<MODE>(ob + (r << LNS), w, pitch)] = get(v[c + r * NB]);
+    }
+}
+
+template <typename T, int LOGL, int MODE, typename V, typename PUT>
+__device__ __forceinline__ void line_gather(cx<T> (&v)[LinePlan<LOGL>::E], int j, int w, int pitch, const V *lds,
+                                            PUT put)
+{
+    using PL = LinePlan<LOGL>;
+#pragma unroll
+    for (int m = 0; m < PL::E; ++m) put(v[m], lds[lidx<MODE>(j + m * PL::TPL, w, pitch)]);
+}
+
+template <typename T, int LOGL, int S, int MODE>
+__device__ __forceinline__ void line_exchange(cx<T> (&v)[LinePlan<LOGL>::E], int j, int w, int pitch, void *smem,
+                                              bool active)
+{
+    if constexpr (sizeof(T) == 8) {
+        T *lds = static_cast<T *>(smem);
+        if (active) line_scatter<T, LOGL, S, MODE>(v, j, w, pitch, lds, [](const cx<T> &a) { return a.x; });
+        __syncthreads();
+        if (active) line_gather<T, LOGL, MODE>(v, j, w, pitch, lds, [](cx<T> &a, T b) { a.x = b; });
+        __syncthreads();
+        if (active) line_scatter<T, LOGL, S, MODE>(v, j, w, pitch, lds, [](const cx<T> &a) { return a.y; });
+        __syncthreads();
+        if (active) line_gather<T, LOGL, MODE>(v, j, w, pitch, lds, [](cx<T> &a, T b) { a.y = b; });
+    } else {
+        cx<T> *lds = static_cast<cx<T> *>(smem);
+        if (active) line_scatter<T, LOGL, S, MODE>(v, j, w, pitch, lds, [](const cx<T> &a) { return a; });
+        __syncthreads();
+        if (active) line_gather<T, LOGL, MODE>(v, j, w, pitch, lds, [](cx<T> &a, cx<T> b) { a = b; });
+    }
+}
+
+template <typename T, int LOGL, int MODE>
+__device__ __forceinline__ void line_stages(cx<T> (&v)[LinePlan<LOGL>::E], int j, int w, int pitch, void *smem,
+                                            const cx<T> *tw, bool active)
+{
+    using PL = LinePlan<LOGL>;
+    if (active) line_compute<T, LOGL, 0>(v, j, tw);
+    if constexpr (PL::NS > 1) {
+        line_exchange<T, LOGL, 0, MODE>(v, j, w, pitch, smem, active);
+        if (active) line_compute<T, LOGL, 1>(v, j, tw);
+    }
+    if constexpr (PL::NS > 2) {
+        __syncthreads();
+        line_exchange<T, LOGL, 1, MODE>(v, j, w, pitch, smem, active);
+        if (active) line_compute<T, LOGL, 2>(v, j, tw);
+    }
+}
+
+// One tile of a k_line pass: W lines (see the layouts above) with pd.threads
+// working threads; threads with tid >= pd.threads (a larger workgroup) only join
+// the barriers. tw holds omega_L^e, e in [L]; lds is the tile's LDS.
+template <typename T, int LOGL, int MODE>
+__device__ __forceinline__ void line_tile(const cx<T> *in, cx<T> *out, const PassDesc &pd, const cx<T> *tw,
+                                          cx<T> *lds, int64_t t, int tid)
+{
+    using PL = LinePlan<LOGL>;
+    const int W = 1 << pd.logW;
+    const int pitch = pd.lw;
+    const bool active = tid < pd.threads;
+    int j, w;
+    if constexpr (MODE == kLineStrided) {
+        w = tid & (W - 1);
+        j = tid >> pd.logW;
+    } else {
+        j = tid & (PL::TPL - 1);
+        w = tid >> PL::LOGTPL;
+    }
+    const T scale = static_cast<T>(pd.scale);
+    cx<T> v[PL::E];
+    int64_t base;      // global offset of element 0 of this thread's line
+    int64_t xstride;   // global distance between consecutive line elements
+    if constexpr (MODE == kLineStrided) {
+        const int64_t a = t >> pd.logTPA;
+        const int64_t b0 = (t & ((int64_t(1) << pd.logTPA) - 1)) << pd.logW;
+        base = a * pd.GB + b0 + w;
+        xstride = int64_t(1) << pd.logB;
+    } else {
+        base = ((t << pd.logW) + w) << LOGL;
+        xstride = 1;
+    }
+
+    if constexpr (MODE == kLineStaged) {
+        const int64_t tbase = (t << pd.logW) << LOGL;
+        const int n = W << LOGL;
+        for (int e = tid; e < n; e += blockDim.x)
+            lds[lidx<MODE>(e & (PL::L - 1), e >> LOGL, pitch)] = conj_if(in[tbase + e], pd.conj_in);
+        __syncthreads();
+        if (active) line_gather<T, LOGL, MODE>(v, j, w, pitch, lds, [](cx<T> &a, cx<T> b) { a = b; });
+        __syncthreads();
+    } else if (active) {
+#pragma unroll
+        for (int m = 0; m < PL::E; ++m) v[m] = conj_if(in[base + int64_t(j + m * PL::TPL) * xstride], pd.conj_in);
+    }
+
+    line_stages<T, LOGL, MODE>(v, j, w, pitch, static_cast<void *>(lds), tw, active);
+
+#pragma unroll
+    for (int m = 0; m < PL::E; ++m) {
+        v[m] = conj_if(v[m], pd.conj_out);
+        if (pd.scale != 1.0) v[m] = {v[m].x * scale, v[m].y * scale};
+    }
+    if constexpr (MODE == kLineStaged) {
+        if constexpr (PL::NS > 1) __syncthreads();
+        if (active) {
+#pragma unroll
+            for (int m = 0; m < PL::E; ++m) lds[lidx<MODE>(j + m * PL::TPL, w, pitch)] = v[m];
+        }
+        __syncthreads();
+        const int64_t tbase = (t << pd.logW) << LOGL;
+        const int n = W << LOGL;
+        for (int e = tid; e < n; e += blockDim.x) out[tbase + e] = lds[lidx<MODE>(e & (PL::L - 1), e >> LOGL, pitch)];
+    } else if (active) {
+#pragma unroll
+        for (int m = 0; m < PL::E; ++m) out[base + int64_t(j + m * PL::TPL) * xstride] = v[m];
+    }
+}
+
+// omega_L^e for e in [L] into LDS (every thread of the block takes part).
+template <typename T, int LOGL>
+__device__ __forceinline__ void line_twiddles(cx<T> *tw, const cx<T> *__restrict__ table, int lognmax, int tid)
+{
+    for (int e = tid; e < (1 << LOGL); e += blockDim.x) tw[e] = table[e << (lognmax - LOGL)];
+}
+
+}  // namespace fftu

@@ -26,7 +26,8 @@ STATUS = {0: "FFTU_SUCCESS", 1: "FFTU_ERROR_INVALID_VALUE", 2: "FFTU_ERROR_NOT_D
 EXPORTS = ["fftu_version", "fftu_status_string", "fftu_last_error", "fftu_check", "fftu_describe", "fftu_plan",
            "fftu_get_plan_info", "fftu_plan_device_bytes", "fftu_execute", "fftu_stage_local_fft",
            "fftu_stage_twiddle", "fftu_stage_exchange", "fftu_stage_remaining_fft", "fftu_timing_begin",
-           "fftu_timing_end", "fftu_set_tuning", "fftu_get_tuning", "fftu_launch_name", "fftu_destroy"]
+           "fftu_timing_end", "fftu_set_tuning", "fftu_get_tuning", "fftu_launch_name", "fftu_plan_batch", "fftu_execute_batch", "fftu_batch_error",
+           "fftu_graph_capture", "fftu_graph_launch", "fftu_graph_destroy", "fftu_destroy"]
 
 TUNE = {"line_strided_logw": 0, "line_contig_logw": 1, "line_pad": 2, "max_lds_kb": 3}
 
@@ -92,6 +93,20 @@ def load_library(path: str = LIB_PATH):
     lib.fftu_get_tuning.argtypes = [ctypes.c_int]
     lib.fftu_launch_name.restype = ctypes.c_char_p
     lib.fftu_launch_name.argtypes = [vp, ctypes.c_int]
+    ptr_arr = ctypes.POINTER(ctypes.c_void_p)
+    lib.fftu_plan_batch.restype = vp
+    lib.fftu_plan_batch.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(i64p),
+                                    ctypes.POINTER(i64p), ctypes.c_int, ctypes.c_int]
+    lib.fftu_execute_batch.restype = ctypes.c_int
+    lib.fftu_execute_batch.argtypes = [vp, ptr_arr, ptr_arr, vp]
+    lib.fftu_batch_error.restype = ctypes.c_int
+    lib.fftu_batch_error.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
+    lib.fftu_graph_capture.restype = vp
+    lib.fftu_graph_capture.argtypes = [vp, ctypes.c_int, ptr_arr, ptr_arr]
+    lib.fftu_graph_launch.restype = ctypes.c_int
+    lib.fftu_graph_launch.argtypes = [vp, vp]
+    lib.fftu_graph_destroy.restype = None
+    lib.fftu_graph_destroy.argtypes = [vp]
     lib.fftu_destroy.restype = None
     lib.fftu_destroy.argtypes = [vp]
     _lib = lib
@@ -257,3 +272,139 @@ class Plan:
 
     def __exit__(self, *exc):
         self.close()
+
+
+def _ptrs(values):
+    return (ctypes.c_void_p * len(values))(*[ctypes.c_void_p(int(v)) for v in values])
+
+
+class BatchPlan:
+    """Many independent transforms of uneven shapes in one persistent launch
+    (fftu_plan_batch / fftu_execute_batch). shapes[i] and grids[i] give n and p
+    of transform i; all share dtype and direction."""
+
+    def __init__(self, shapes, grids, dtype="complex64", direction=FORWARD):
+        self.shapes = [tuple(int(v) for v in s) for s in shapes]
+        self.grids = [tuple(int(v) for v in g) for g in grids]
+        if len(self.shapes) != len(self.grids) or not self.shapes:
+            raise ValueError("shapes and grids must be non-empty lists of equal length")
+        self.dtype_code = _dtype_code(dtype)
+        self.direction = int(direction)
+        self._lib = load_library()
+        count = len(self.shapes)
+        ds = (ctypes.c_int * count)(*[len(s) for s in self.shapes])
+        self._keep = [_arr(s) for s in self.shapes] + [_arr(g) for g in self.grids]
+        i64p = ctypes.POINTER(ctypes.c_int64)
+        ns = (i64p * count)(*[ctypes.cast(a, i64p) for a in self._keep[:count]])
+        ps = (i64p * count)(*[ctypes.cast(a, i64p) for a in self._keep[count:]])
+        h = self._lib.fftu_plan_batch(count, ds, ns, ps, self.dtype_code, self.direction)
+        if not h:
+            raise FftuError(self._lib.fftu_last_error(), "fftu_plan_batch")
+        self._h = ctypes.c_void_p(h)
+        self.sizes = [_prod(s) for s in self.shapes]
+
+    @property
+    def torch_dtype(self):
+        import torch
+        return torch.complex128 if self.dtype_code == C128 else torch.complex64
+
+    def execute_ptrs(self, in_ptrs, out_ptrs, stream: int = 0) -> None:
+        st = self._lib.fftu_execute_batch(self._h, _ptrs(in_ptrs), _ptrs(out_ptrs), ctypes.c_void_p(stream))
+        if st != 0:
+            raise FftuError(st, "fftu_execute_batch")
+
+    def __call__(self, xs, outs=None, stream=None):
+        import torch
+        if len(xs) != len(self.sizes):
+            raise ValueError("one input tensor per transform")
+        for x, n in zip(xs, self.sizes):
+            if not x.is_cuda or x.dtype != self.torch_dtype or x.numel() != n or not x.is_contiguous():
+                raise ValueError(f"inputs must be contiguous {self.torch_dtype} device tensors of the planned sizes")
+        if outs is None:
+            outs = [torch.empty_like(x) for x in xs]
+        if stream is None:
+            stream = torch.cuda.current_stream(xs[0].device)
+        self.execute_ptrs([x.data_ptr() for x in xs], [o.data_ptr() for o in outs], int(stream.cuda_stream))
+        return outs
+
+    def error_flag(self) -> int:
+        v = ctypes.c_int(0)
+        st = self._lib.fftu_batch_error(self._h, ctypes.byref(v))
+        if st != 0:
+            raise FftuError(st, "fftu_batch_error")
+        return v.value
+
+    def timing_begin(self, max_calls: int) -> None:
+        st = self._lib.fftu_timing_begin(self._h, int(max_calls))
+        if st != 0:
+            raise FftuError(st, "fftu_timing_begin")
+
+    def timing_end(self):
+        buf = (ctypes.c_float * 8)()
+        nk, nc = ctypes.c_int(0), ctypes.c_int(0)
+        st = self._lib.fftu_timing_end(self._h, buf, 8, ctypes.byref(nk), ctypes.byref(nc))
+        if st != 0:
+            raise FftuError(st, "fftu_timing_end")
+        return [float(buf[i]) for i in range(nk.value)], nc.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.fftu_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def _prod(vals):
+    r = 1
+    for v in vals:
+        r *= int(v)
+    return r
+
+
+class Graph:
+    """A captured HIP graph of one execution (fftu_graph_capture): replay with launch()."""
+
+    def __init__(self, plan, xs, outs):
+        self._lib = load_library()
+        self.plan = plan                 # the plan must outlive the graph
+        if isinstance(plan, BatchPlan):
+            count = len(xs)
+        else:
+            count = 0
+            xs, outs = [xs], [outs]
+        self._bufs = (xs, outs)
+        h = self._lib.fftu_graph_capture(plan.handle if not isinstance(plan, BatchPlan) else plan._h, count,
+                                         _ptrs([x.data_ptr() for x in xs]), _ptrs([o.data_ptr() for o in outs]))
+        if not h:
+            raise FftuError(self._lib.fftu_last_error(), "fftu_graph_capture")
+        self._h = ctypes.c_void_p(h)
+
+    def launch(self, stream=None):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        st = self._lib.fftu_graph_launch(self._h, ctypes.c_void_p(int(stream.cuda_stream)))
+        if st != 0:
+            raise FftuError(st, "fftu_graph_launch")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.fftu_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -25,7 +25,35 @@ hipError_t launch_exchange(Precision, const void *, void *, const ExchangeDesc &
     if (ex.nh * ex.lph > kExchangeMaxWaveBits || ex.nr * ex.lpr > kExchangeRegBitsF32) std::abort();
     return hipSuccess;
 }
+hipError_t launch_batch(Precision, const BatchDesc &bd, const void *, uint32_t, uint32_t, hipStream_t)
+{
+    if (bd.nstages < 1 || bd.nitems < 1) std::abort();
+    return hipSuccess;
+}
+int batch_blocks_per_cu(Precision, uint32_t) { return 1; }
 }  // namespace fftu
+
+// Batch plans: the planner builds every descriptor before its first HIP call.
+static int check_batches()
+{
+    const int64_t n1[3] = {16, 256, 64}, p1[3] = {2, 2, 2};
+    const int64_t n2[3] = {256, 16, 32}, p2[3] = {2, 2, 2};
+    const int64_t n3[2] = {64, 128}, p3[2] = {2, 2};
+    const int64_t n4[3] = {1024, 16, 16}, p4[3] = {2, 2, 2};   // local length 512: outside a batch
+    const int d[3] = {3, 3, 2};
+    const int64_t *ns[3] = {n1, n2, n3}, *ps[3] = {p1, p2, p3};
+    int bad = 0;
+    for (fftu_dtype dt : {FFTU_C64, FFTU_C128}) {
+        fftu_plan_t pl = fftu_plan_batch(3, d, ns, ps, dt, FFTU_FORWARD);
+        std::printf("batch plan=%d\n", int(fftu_last_error()));
+        if (pl) fftu_destroy(pl);
+        else if (fftu_last_error() != FFTU_ERROR_DEVICE) ++bad;
+    }
+    const int d4[1] = {3};
+    const int64_t *ns4[1] = {n4}, *ps4[1] = {p4};
+    if (fftu_plan_batch(1, d4, ns4, ps4, FFTU_C64, FFTU_FORWARD) || fftu_last_error() != FFTU_ERROR_UNSUPPORTED) ++bad;
+    return bad;
+}
 
 int main()
 {
@@ -53,5 +81,5 @@ int main()
             if (s != FFTU_SUCCESS && s != FFTU_ERROR_UNSUPPORTED) ++bad;
         }
     }
-    return bad;
+    return bad + check_batches();
 }
