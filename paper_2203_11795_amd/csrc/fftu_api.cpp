@@ -55,6 +55,7 @@ struct fftu_plan_s {
     int64_t batch_items = 0;
     uint32_t batch_blocks = 0;
     uint32_t batch_lds = 0;
+    int64_t batch_wait_ticks = 0;          // bound of one dependency wait (about 2 s)
     void *dstages = nullptr;
     void *dstarts = nullptr;
     void *ddep = nullptr;
@@ -613,7 +614,7 @@ fftu_status enqueue_batch(fftu_plan_s *pl, hipStream_t stream)
 {
     fftu::BatchDesc bd{};
     bd.nstages = int32_t(pl->hstages.size());
-    bd.spin_limit = 1 << 24;
+    bd.wait_limit = pl->batch_wait_ticks;
     bd.nitems = pl->batch_items;
     bd.stages = static_cast<const fftu::BatchStage *>(pl->dstages);
     bd.starts = static_cast<const int64_t *>(pl->dstarts);
@@ -765,19 +766,116 @@ fftu_plan_t fftu_plan(int d, const int64_t n[], const int64_t p[], fftu_dtype dt
     return pl;
 }
 
+}  // extern "C"
+
+namespace fftu {
+// The work list of a batch (host side; see fftu_batch.hip): one descriptor per
+// (stage, transform) in stage-major order, the prefix sums of their work items,
+// and the descriptor each one waits for.
+fftu_status build_batch_worklist(int count, const int d[], const int64_t *const n[], const int64_t *const p[],
+                                 fftu_dtype dtype, fftu_direction direction, BatchWorklist &wl)
+{
+    if (count < 1 || !d || !n || !p) return FFTU_ERROR_INVALID_VALUE;
+    for (int f = 0; f < count; ++f) {
+        fftu_status s = validate(d[f], n[f], p[f], dtype, direction);
+        if (s != FFTU_SUCCESS) return s;
+    }
+    const size_t esize = dtype == FFTU_C128 ? 16 : 8;
+    const int inv = direction == FFTU_INVERSE ? 1 : 0;
+    // per-transform stages: line passes of Superstep 0, then the fused exchange
+    struct Member {
+        std::vector<PassDesc> s0;
+        ExchangeDesc ex;
+        int64_t M;
+    };
+    std::vector<Member> mem(static_cast<size_t>(count));
+    int lognmax = 0, smax = 0;
+    uint64_t ws_total = 0;
+    uint32_t tile_lds = 0;
+    wl = BatchWorklist{};
+    for (int f = 0; f < count; ++f) {
+        const Geometry G = geometry(d[f], n[f], p[f]);
+        lognmax = std::max(lognmax, G.lognmax);
+        const GridDesc g = make_grid(G);
+        Member &m = mem[size_t(f)];
+        m.M = g.M;
+        for (int l = G.d - 1; l >= 0; --l) {
+            if (G.logm[l] == 0) continue;
+            int logA = G.logP, logB = 0;
+            for (int j = 0; j < l; ++j) logA += G.logm[j];
+            for (int j = l + 1; j < G.d; ++j) logB += G.logm[j];
+            PassDesc pd;
+            if (G.logm[l] > kBatchMaxLogLine || !make_line_pass(logA, G.logm[l], logB, dtype, G.lognmax, pd) ||
+                pd.threads > kBatchThreads)
+                return FFTU_ERROR_UNSUPPORTED;
+            tile_lds = std::max(tile_lds, uint32_t(pd.lds_bytes - (uint32_t(1) << G.logm[l]) * esize));
+            m.s0.push_back(pd);
+        }
+        ExchangeSplit sp;
+        if (m.s0.empty() || !exchange_split(G, dtype, &sp) || !batch_exchange_ok(sp)) return FFTU_ERROR_UNSUPPORTED;
+        m.ex = make_exchange(G, g, sp, dtype);
+        m.s0.front().conj_in = inv;
+        m.ex.g.conj_out = inv;
+        m.ex.g.scale = inv ? 1.0 / double(g.N) : 1.0;
+        wl.N.push_back(g.N);
+        wl.ws.push_back(ws_total);
+        ws_total += uint64_t(g.N);
+        smax = std::max(smax, int(m.s0.size()) + 1);
+    }
+    std::vector<int> last_desc(size_t(count), -1);
+    wl.starts.assign(1, 0);
+    for (int s = 0; s < smax; ++s) {
+        for (int f = 0; f < count; ++f) {
+            const Member &m = mem[size_t(f)];
+            const int ns0 = int(m.s0.size());
+            if (s > ns0) continue;
+            BatchStage st{};
+            int64_t tile_elems;
+            if (s < ns0) {
+                st.kind = m.s0[size_t(s)].kind;
+                st.pd = m.s0[size_t(s)];
+                st.tiles = st.pd.tiles;
+                tile_elems = int64_t(1) << (st.pd.logW + st.pd.loglen[0]);
+            } else {
+                st.kind = kExchangeStage;
+                st.ex = m.ex;
+                const int64_t ngroups = (m.M + 63) / 64;
+                st.tiles = (ngroups + 3) / 4;             // 4 groups of 64 local indices (all P sources) per tile
+                tile_elems = int64_t(256) << (st.ex.nr * st.ex.lpr);
+            }
+            const int64_t per = std::max<int64_t>(1, (int64_t(1) << kBatchItemLog) / tile_elems);
+            st.per_item = int32_t(per);
+            const int64_t items = (st.tiles + per - 1) / per;
+            // every stage indexes the batch's one table of omega_{2^lognmax}
+            st.pd.lognmax = lognmax;
+            st.ex.g.lognmax = lognmax;
+            wl.stages.push_back(st);
+            wl.member.push_back(f);
+            wl.first.push_back(s == 0 ? 1 : 0);
+            wl.last.push_back(s == ns0 ? 1 : 0);
+            wl.dep.push_back(last_desc[size_t(f)]);
+            last_desc[size_t(f)] = int(wl.stages.size()) - 1;
+            wl.starts.push_back(wl.starts.back() + items);
+        }
+    }
+    wl.lognmax = lognmax;
+    wl.items = wl.starts.back();
+    wl.lds = uint32_t(kBatchMaxLine) * uint32_t(esize) + tile_lds;
+    wl.ws_total = ws_total;
+    return FFTU_SUCCESS;
+}
+}  // namespace fftu
+
+extern "C" {
+
 fftu_plan_t fftu_plan_batch(int count, const int d[], const int64_t *const n[], const int64_t *const p[],
                             fftu_dtype dtype, fftu_direction direction)
 {
-    if (count < 1 || !d || !n || !p) {
-        record(FFTU_ERROR_INVALID_VALUE);
+    fftu::BatchWorklist wl;
+    fftu_status bs = fftu::build_batch_worklist(count, d, n, p, dtype, direction, wl);
+    if (bs != FFTU_SUCCESS) {
+        record(bs);
         return nullptr;
-    }
-    for (int f = 0; f < count; ++f) {
-        fftu_status s = validate(d[f], n[f], p[f], dtype, direction);
-        if (s != FFTU_SUCCESS) {
-            record(s);
-            return nullptr;
-        }
     }
     fftu_plan_s *pl = new (std::nothrow) fftu_plan_s();
     if (!pl) {
@@ -790,93 +888,18 @@ fftu_plan_t fftu_plan_batch(int count, const int d[], const int64_t *const n[], 
     pl->dir = direction;
     pl->prec = dtype == FFTU_C128 ? Precision::F64 : Precision::F32;
     pl->esize = dtype == FFTU_C128 ? 16 : 8;
-    const int inv = direction == FFTU_INVERSE ? 1 : 0;
-
-    // per-transform stages: line passes of Superstep 0, then the fused exchange
-    struct Member {
-        std::vector<PassDesc> s0;
-        ExchangeDesc ex;
-        int64_t M;
-    };
-    std::vector<Member> mem(static_cast<size_t>(count));
-    int lognmax = 0, smax = 0;
-    uint64_t ws_total = 0;
-    uint32_t tile_lds = 0;
-    fftu_status bad = FFTU_SUCCESS;
-    for (int f = 0; f < count && bad == FFTU_SUCCESS; ++f) {
-        const Geometry G = geometry(d[f], n[f], p[f]);
-        lognmax = std::max(lognmax, G.lognmax);
-        const GridDesc g = make_grid(G);
-        Member &m = mem[size_t(f)];
-        m.M = g.M;
-        for (int l = G.d - 1; l >= 0; --l) {
-            if (G.logm[l] == 0) continue;
-            int logA = G.logP, logB = 0;
-            for (int j = 0; j < l; ++j) logA += G.logm[j];
-            for (int j = l + 1; j < G.d; ++j) logB += G.logm[j];
-            PassDesc pd;
-            if (G.logm[l] > fftu::kBatchMaxLogLine || !make_line_pass(logA, G.logm[l], logB, dtype, G.lognmax, pd) ||
-                pd.threads > fftu::kBatchThreads) {
-                bad = FFTU_ERROR_UNSUPPORTED;
-                break;
-            }
-            tile_lds = std::max(tile_lds, uint32_t(pd.lds_bytes - (uint32_t(1) << G.logm[l]) * pl->esize));
-            m.s0.push_back(pd);
-        }
-        ExchangeSplit sp;
-        if (bad == FFTU_SUCCESS && (m.s0.empty() || !exchange_split(G, dtype, &sp) || !batch_exchange_ok(sp)))
-            bad = FFTU_ERROR_UNSUPPORTED;
-        if (bad != FFTU_SUCCESS) break;
-        m.ex = make_exchange(G, g, sp, dtype);
-        m.s0.front().conj_in = inv;
-        m.ex.g.conj_out = inv;
-        m.ex.g.scale = inv ? 1.0 / double(g.N) : 1.0;
-        pl->member_N.push_back(g.N);
-        pl->member_ws.push_back(ws_total);
-        ws_total += uint64_t(g.N);
-        smax = std::max(smax, int(m.s0.size()) + 1);
-    }
-    if (bad != FFTU_SUCCESS) {
-        delete pl;
-        record(bad);
-        return nullptr;
-    }
-    // stage-major work list
-    std::vector<int> last_desc(size_t(count), -1);
-    std::vector<int64_t> starts{0};
-    std::vector<int32_t> dep;
-    for (int s = 0; s < smax; ++s) {
-        for (int f = 0; f < count; ++f) {
-            const Member &m = mem[size_t(f)];
-            const int ns0 = int(m.s0.size());
-            if (s > ns0) continue;
-            fftu::BatchStage st{};
-            int64_t items;
-            if (s < ns0) {
-                st.kind = m.s0[size_t(s)].kind;
-                st.pd = m.s0[size_t(s)];
-                items = st.pd.tiles;
-            } else {
-                st.kind = fftu::kExchangeStage;
-                st.ex = m.ex;
-                const int64_t ngroups = (m.M + 63) / 64;
-                items = (ngroups + 3) / 4;
-            }
-            // every stage indexes the batch's one table of omega_{2^lognmax}
-            st.pd.lognmax = lognmax;
-            st.ex.g.lognmax = lognmax;
-            pl->hstages.push_back(st);
-            pl->stage_member.push_back(f);
-            pl->stage_first.push_back(s == 0 ? 1 : 0);
-            pl->stage_last.push_back(s == ns0 ? 1 : 0);
-            dep.push_back(last_desc[size_t(f)]);
-            last_desc[size_t(f)] = int(pl->hstages.size()) - 1;
-            starts.push_back(starts.back() + items);
-        }
-    }
-    pl->batch_items = starts.back();
-    pl->batch_lds = uint32_t(fftu::kBatchMaxLine) * uint32_t(pl->esize) + tile_lds;
-
+    pl->hstages = wl.stages;
+    pl->stage_member = wl.member;
+    pl->stage_first = wl.first;
+    pl->stage_last = wl.last;
+    pl->member_N = wl.N;
+    pl->member_ws = wl.ws;
+    pl->batch_items = wl.items;
+    pl->batch_lds = wl.lds;
+    const int lognmax = wl.lognmax;
+    const uint64_t ws_total = wl.ws_total;
+    const std::vector<int64_t> &starts = wl.starts;
+    const std::vector<int32_t> &dep = wl.dep;
     hipError_t e = hipGetDevice(&pl->device);
     const int64_t L = int64_t(1) << lognmax;
     const std::vector<double> t64 = make_table_f64(lognmax);
@@ -902,8 +925,10 @@ fftu_plan_t fftu_plan_batch(int count, const int d[], const int64_t *const n[], 
             e = hipMemcpy(pl->table, t32.data(), pl->table_bytes, hipMemcpyHostToDevice);
         }
     }
-    int cus = 0;
+    int cus = 0, clock_khz = 0;
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, pl->device);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&clock_khz, hipDeviceAttributeWallClockRate, pl->device);
+    pl->batch_wait_ticks = int64_t(clock_khz > 0 ? clock_khz : 100000) * 2000;   // 2 s
     if (e != hipSuccess) {
         fftu_status st = from_hip(e);
         free_batch(pl);

@@ -5,18 +5,21 @@
 // stage-major order: every transform's first Superstep-0 pass, then every
 // second pass, ..., then every exchange. Each descriptor owns a contiguous range
 // of work items (tiles of a k_line pass, or groups of the fused exchange).
-// Workgroups take items from one global counter in that order. Before an item
-// of a descriptor with a dependency (the previous stage of the same transform)
-// runs, its workgroup waits until every item of that dependency has finished;
-// because items are handed out in stage-major order, every dependency is
-// already held by a running workgroup, so the wait always ends. The wait is
-// bounded all the same: past spin_limit polls the workgroup records an error
-// flag and skips the item, so every workgroup reaches the end.
+// Workgroups take items (runs of about 2^17 elements' worth of tiles) from one
+// global counter in that order. Before an item of a descriptor with a dependency
+// (the previous stage of the same transform) runs, its workgroup waits until
+// every item of that dependency has finished; because items are handed out in
+// stage-major order, every dependency is already held by a running workgroup,
+// so the wait always ends. The wait is bounded all the same (wait_limit ticks of
+// the real-time clock, or at once when another wait has given up): then the
+// workgroup records an error flag and skips the item, so every workgroup
+// reaches the end.
 //
 // Completion protocol: each thread's stores of a finished item are released
 // with a device-scope fence, then one thread increments the descriptor's
-// counter; a waiting workgroup reads the counter with device-scope acquire and
-// every thread issues a device-scope acquire fence before reading the data.
+// counter. A waiting workgroup polls the counter with relaxed device-scope
+// loads (no cache invalidation per poll) and, once it is complete, every thread
+// issues one device-scope acquire fence before reading the data.
 // Counters are cleared by k_batch_reset (a kernel, so the pair can be captured
 // in a graph and replayed).
 #include <hip/hip_runtime.h>
@@ -37,9 +40,10 @@ __global__ void k_batch_reset(BatchDesc bd)
     }
 }
 
+// Tiles [first, last) of a k_line pass; the block's twiddles are loaded once.
 template <typename T>
 __device__ __forceinline__ void run_line(const BatchStage &st, const cx<T> *__restrict__ table, cx<T> *tw,
-                                         cx<T> *tile, int64_t t, int tid)
+                                         cx<T> *tile, int64_t first, int64_t last, int tid)
 {
     const cx<T> *in = static_cast<const cx<T> *>(st.src);
     cx<T> *out = static_cast<cx<T> *>(st.dst);
@@ -47,8 +51,10 @@ __device__ __forceinline__ void run_line(const BatchStage &st, const cx<T> *__re
 #define FFTU_LINE_CASE(LG, MD)                                                    \
     case (LG) * 8 + (MD):                                                         \
         line_twiddles<T, LG>(tw, table, pd.lognmax, tid);                         \
-        __syncthreads();                                                          \
-        line_tile<T, LG, MD>(in, out, pd, tw, tile, t, tid);                      \
+        for (int64_t t = first; t < last; ++t) {                                  \
+            __syncthreads(); /* twiddles in; previous tile's LDS reads done */    \
+            line_tile<T, LG, MD>(in, out, pd, tw, tile, t, tid);                  \
+        }                                                                         \
         break;
 #define FFTU_LINE_MODES(LG) FFTU_LINE_CASE(LG, kLineStrided) FFTU_LINE_CASE(LG, kLineContig) FFTU_LINE_CASE(LG, kLineStaged)
     switch (pd.loglen[0] * 8 + pd.kind) {
@@ -66,17 +72,19 @@ __device__ __forceinline__ void run_line(const BatchStage &st, const cx<T> *__re
 #undef FFTU_LINE_CASE
 }
 
+// Tiles [first, last) of the fused exchange; a tile is 4 groups of 64 local
+// indices (no wave dimensions in a batch, so no LDS is shared between tiles).
 template <typename T>
 __device__ __forceinline__ void run_exchange(const BatchStage &st, const cx<T> *__restrict__ table,
-                                             unsigned char *smem, int64_t t, int tid)
+                                             unsigned char *smem, int64_t first, int64_t last, int tid)
 {
     const cx<T> *Z = static_cast<const cx<T> *>(st.src);
     cx<T> *V = static_cast<cx<T> *>(st.dst);
     const ExchangeDesc &ex = st.ex;
-    const int64_t gb = t * (kExchangeThreads / 64);   // no wave dimensions in a batch: 4 groups per item
 #define FFTU_EX_CASE(NR, LPR)                                                     \
     case (NR) * 8 + (LPR):                                                        \
-        exchange_group<T, NR, LPR, 0, 0>(Z, V, ex, table, smem, gb, tid);         \
+        for (int64_t t = first; t < last; ++t)                                    \
+            exchange_group<T, NR, LPR, 0, 0>(Z, V, ex, table, smem, t * (kExchangeThreads / 64), tid); \
         break;
     switch (ex.nr * 8 + ex.lpr) {
         FFTU_EX_CASE(0, 0)
@@ -119,16 +127,16 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(const BatchDesc bd, con
                 const int dep = bd.dep[k];
                 if (dep >= 0) {
                     const int need = int(bd.starts[dep + 1] - bd.starts[dep]);
-                    int polls = 0;
-                    while (__hip_atomic_load(&bd.done[dep], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < need) {
-                        // give up past the poll limit, or at once once another wait has given up
-                        if (++polls > bd.spin_limit ||
+                    const uint64_t t0 = wall_clock64();
+                    while (__hip_atomic_load(&bd.done[dep], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+                        // give up past the time limit, or at once when another wait has given up
+                        if (int64_t(wall_clock64() - t0) > bd.wait_limit ||
                             __hip_atomic_load(bd.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
                             atomicExch(bd.error, 1);
                             skip = 1;
                             break;
                         }
-                        __builtin_amdgcn_s_sleep(2);
+                        __builtin_amdgcn_s_sleep(8);
                     }
                 }
             }
@@ -143,10 +151,13 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(const BatchDesc bd, con
         if (item >= bd.nitems) break;
         if (bd.dep[k] >= 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         const BatchStage &st = bd.stages[k];
-        const int64_t t = item - bd.starts[k];
+        const int64_t first = (item - bd.starts[k]) * st.per_item;
+        const int64_t last = first + st.per_item < st.tiles ? first + st.per_item : st.tiles;
         if (!skip) {
-            if (st.kind == kExchangeStage) run_exchange<T>(st, table, smem_raw + kBatchMaxLine * sizeof(cx<T>), t, tid);
-            else run_line<T>(st, table, tw, tile, t, tid);
+            if (st.kind == kExchangeStage)
+                run_exchange<T>(st, table, smem_raw + kBatchMaxLine * sizeof(cx<T>), first, last, tid);
+            else
+                run_line<T>(st, table, tw, tile, first, last, tid);
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         __syncthreads();

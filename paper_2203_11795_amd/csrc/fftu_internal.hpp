@@ -101,10 +101,12 @@ constexpr int kBatchThreads = 256;
 constexpr int kBatchMaxLogLine = 8;     // longest Superstep-0 line of a batched transform: 2^8
 constexpr int kBatchMaxLine = 1 << kBatchMaxLogLine;
 constexpr int kExchangeStage = 8;       // BatchStage::kind of the fused exchange
+constexpr int kBatchItemLog = 17;       // about 2^17 elements per work item
 
 struct BatchStage {
     int32_t kind;          // kLineStrided / kLineContig / kLineStaged, or kExchangeStage
-    int32_t reserved;
+    int32_t per_item;      // tiles (line tiles, or exchange groups of 4 x 64 indices) per work item
+    int64_t tiles;
     const void *src;
     void *dst;
     PassDesc pd;           // line passes
@@ -113,7 +115,8 @@ struct BatchStage {
 
 struct BatchDesc {
     int32_t nstages;             // descriptors
-    int32_t spin_limit;          // polls before a dependency wait gives up (error flag)
+    int32_t reserved;
+    int64_t wait_limit;          // real-time-clock ticks a dependency wait may last (then: error flag)
     int64_t nitems;              // work items in total
     const BatchStage *stages;    // [nstages], stage-major
     const int64_t *starts;       // [nstages + 1] first item of each descriptor
@@ -122,6 +125,24 @@ struct BatchDesc {
     unsigned long long *next;    // next item to hand out
     int32_t *error;              // set when a wait gave up
 };
+
+// Host-side work list of a batch plan (built by build_batch_worklist in fftu_api.cpp).
+struct BatchWorklist {
+    std::vector<BatchStage> stages;   // stage-major
+    std::vector<int64_t> starts;      // stages.size() + 1
+    std::vector<int32_t> dep;         // descriptor each one waits for, or -1
+    std::vector<int> member;          // transform of each descriptor
+    std::vector<int> first;           // 1: reads the transform's input
+    std::vector<int> last;            // 1: writes the transform's output
+    std::vector<int64_t> N;           // elements of each transform
+    std::vector<uint64_t> ws;         // workspace offset of each transform (elements)
+    uint64_t ws_total = 0;
+    int lognmax = 0;
+    int64_t items = 0;
+    uint32_t lds = 0;                 // dynamic LDS of the persistent kernel
+};
+fftu_status build_batch_worklist(int count, const int d[], const int64_t *const n[], const int64_t *const p[],
+                                 fftu_dtype dtype, fftu_direction direction, BatchWorklist &wl);
 
 enum class Precision { F32, F64 };
 

@@ -33,6 +33,115 @@ hipError_t launch_batch(Precision, const BatchDesc &bd, const void *, uint32_t, 
 int batch_blocks_per_cu(Precision, uint32_t) { return 1; }
 }  // namespace fftu
 
+// Emulates the persistent batch kernel's schedule on the work list: `nwg`
+// workgroups take items from one counter in order, wait until the item's
+// dependency descriptor has finished every item, and finish after a random
+// number of steps. Fails on a deadlock, a miscount or an out-of-range tile.
+static int emulate_schedule(const fftu::BatchWorklist &wl, int nwg, unsigned seed)
+{
+    const int K = int(wl.stages.size());
+    std::vector<int> done(size_t(K), 0), handed(size_t(K), 0);
+    struct WG {
+        int64_t item = -1;
+        int k = -1;
+        int left = 0;
+        bool finished = false;
+    };
+    std::vector<WG> wgs(static_cast<size_t>(nwg));
+    int64_t next = 0, completed = 0;
+    unsigned rng = seed;
+    auto rnd = [&]() { rng = rng * 1664525u + 1013904223u; return rng >> 8; };
+    for (int64_t step = 0; step < 100000000; ++step) {
+        bool all_done = true;
+        for (WG &w : wgs) {
+            if (w.finished) continue;
+            all_done = false;
+            if (w.item < 0) {
+                w.item = next++;
+                if (w.item >= wl.items) {
+                    w.finished = true;
+                    continue;
+                }
+                int lo = 0, hi = K - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (wl.starts[size_t(mid)] <= w.item) lo = mid;
+                    else hi = mid - 1;
+                }
+                w.k = lo;
+                const int64_t t = w.item - wl.starts[size_t(lo)];
+                const fftu::BatchStage &st = wl.stages[size_t(lo)];
+                if (st.per_item < 1 || t * st.per_item >= st.tiles) return 101;
+                if (st.kind == fftu::kExchangeStage) {
+                    const int64_t M = st.ex.g.M;
+                    if (st.tiles * 4 * 64 < M || (st.tiles - 1) * 4 * 64 >= M) return 100;
+                } else if (st.tiles != st.pd.tiles) {
+                    return 104;
+                }
+                handed[size_t(lo)]++;
+                w.left = -1;   // not started: waiting on the dependency
+            }
+            if (w.left < 0) {
+                const int dep = wl.dep[size_t(w.k)];
+                if (dep >= 0 && done[size_t(dep)] < int(wl.starts[size_t(dep) + 1] - wl.starts[size_t(dep)])) continue;
+                w.left = int(rnd() % 5);
+            }
+            if (w.left-- == 0) {
+                done[size_t(w.k)]++;
+                ++completed;
+                w.item = -1;
+            }
+        }
+        if (all_done) break;
+    }
+    if (completed != wl.items) return 102;
+    for (int k = 0; k < K; ++k)
+        if (done[size_t(k)] != int(wl.starts[size_t(k) + 1] - wl.starts[size_t(k)]) || handed[size_t(k)] != done[size_t(k)])
+            return 103;
+    return 0;
+}
+
+static int check_worklists()
+{
+    int bad = 0;
+    unsigned rng = 12345u;
+    for (int trial = 0; trial < 6; ++trial) {
+        const int count = trial == 0 ? 1 : 3 + 40 * trial;
+        std::vector<std::vector<int64_t>> ns, ps;
+        std::vector<int> d;
+        for (int f = 0; f < count; ++f) {
+            std::vector<int64_t> n(3), p(3, 2);
+            for (int l = 0; l < 3; ++l) {
+                rng = rng * 1664525u + 1013904223u;
+                n[size_t(l)] = int64_t(1) << (4 + (rng >> 8) % 5);   // 16 .. 256
+            }
+            ns.push_back(n);
+            ps.push_back(p);
+            d.push_back(3);
+        }
+        std::vector<const int64_t *> np, pp;
+        for (int f = 0; f < count; ++f) {
+            np.push_back(ns[size_t(f)].data());
+            pp.push_back(ps[size_t(f)].data());
+        }
+        for (fftu_dtype dt : {FFTU_C64, FFTU_C128}) {
+            fftu::BatchWorklist wl;
+            if (fftu::build_batch_worklist(count, d.data(), np.data(), pp.data(), dt, FFTU_FORWARD, wl) !=
+                FFTU_SUCCESS) {
+                ++bad;
+                continue;
+            }
+            for (int nwg : {1, 3, 64, 700}) {
+                const int r = emulate_schedule(wl, nwg, 7u + unsigned(trial));
+                std::printf("worklist count=%d dt=%d items=%lld wgs=%d -> %d\n", count, int(dt),
+                            (long long)wl.items, nwg, r);
+                if (r) ++bad;
+            }
+        }
+    }
+    return bad;
+}
+
 // Batch plans: the planner builds every descriptor before its first HIP call.
 static int check_batches()
 {
@@ -81,5 +190,5 @@ int main()
             if (s != FFTU_SUCCESS && s != FFTU_ERROR_UNSUPPORTED) ++bad;
         }
     }
-    return bad + check_batches();
+    return bad + check_batches() + check_worklists();
 }
