@@ -16,8 +16,8 @@
 // reaches the end.
 //
 // Completion protocol: each thread's stores of a finished item are released
-// with a device-scope fence, then one thread increments the descriptor's
-// counter. A waiting workgroup polls the counter with relaxed device-scope
+// with a device-scope fence, then (after a barrier) thread 0 increments the
+// descriptor's counter before it takes the next item. A waiting workgroup polls the counter with relaxed device-scope
 // loads (no cache invalidation per poll) and, once it is complete, every thread
 // issues one device-scope acquire fence before reading the data.
 // Counters are cleared by k_batch_reset (a kernel, so the pair can be captured
@@ -41,8 +41,25 @@ __global__ void k_batch_reset(BatchDesc bd)
 }
 
 // Tiles [first, last) of a k_line pass; the block's twiddles are loaded once.
+// Values every lane of a wave holds alike, moved to scalar registers. The
+// persistent loop below decides its branches and loop bounds only on such values:
+// the compiler then keeps its control flow wave-uniform, so every thread of the
+// workgroup executes the same sequence of barriers. (Decided on per-lane copies
+// read from LDS, the loop was restructured so that thread 0 left it after each
+// item while the other lanes went straight back to the first barrier, and the
+// workgroup repeated one item forever.)
+__device__ __forceinline__ int uniform32(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t uniform64(int64_t v)
+{
+    const uint32_t lo = uint32_t(__builtin_amdgcn_readfirstlane(int(uint32_t(v))));
+    const uint32_t hi = uint32_t(__builtin_amdgcn_readfirstlane(int(uint32_t(uint64_t(v) >> 32))));
+    return int64_t((uint64_t(hi) << 32) | lo);
+}
+
+// Tiles [first, last) of a k_line pass; the block's twiddles are loaded once.
+// key = log2(line length) * 8 + pass kind, uniform.
 template <typename T>
-__device__ __forceinline__ void run_line(const BatchStage &st, const cx<T> *__restrict__ table, cx<T> *tw,
+__device__ __forceinline__ void run_line(const BatchStage &st, int key, const cx<T> *__restrict__ table, cx<T> *tw,
                                          cx<T> *tile, int64_t first, int64_t last, int tid)
 {
     const cx<T> *in = static_cast<const cx<T> *>(st.src);
@@ -57,7 +74,7 @@ __device__ __forceinline__ void run_line(const BatchStage &st, const cx<T> *__re
         }                                                                         \
         break;
 #define FFTU_LINE_MODES(LG) FFTU_LINE_CASE(LG, kLineStrided) FFTU_LINE_CASE(LG, kLineContig) FFTU_LINE_CASE(LG, kLineStaged)
-    switch (pd.loglen[0] * 8 + pd.kind) {
+    switch (key) {
         FFTU_LINE_MODES(1)
         FFTU_LINE_MODES(2)
         FFTU_LINE_MODES(3)
@@ -74,8 +91,9 @@ __device__ __forceinline__ void run_line(const BatchStage &st, const cx<T> *__re
 
 // Tiles [first, last) of the fused exchange; a tile is 4 groups of 64 local
 // indices (no wave dimensions in a batch, so no LDS is shared between tiles).
+// key = register dimensions * 8 + log2(their radix), uniform.
 template <typename T>
-__device__ __forceinline__ void run_exchange(const BatchStage &st, const cx<T> *__restrict__ table,
+__device__ __forceinline__ void run_exchange(const BatchStage &st, int key, const cx<T> *__restrict__ table,
                                              unsigned char *smem, int64_t first, int64_t last, int tid)
 {
     const cx<T> *Z = static_cast<const cx<T> *>(st.src);
@@ -86,7 +104,7 @@ __device__ __forceinline__ void run_exchange(const BatchStage &st, const cx<T> *
         for (int64_t t = first; t < last; ++t)                                    \
             exchange_group<T, NR, LPR, 0, 0>(Z, V, ex, table, smem, t * (kExchangeThreads / 64), tid); \
         break;
-    switch (ex.nr * 8 + ex.lpr) {
+    switch (key) {
         FFTU_EX_CASE(0, 0)
         FFTU_EX_CASE(1, 1)
         FFTU_EX_CASE(2, 1)
@@ -111,8 +129,13 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(const BatchDesc bd, con
     cx<T> *tw = reinterpret_cast<cx<T> *>(smem_raw);       // omega_L, L <= kBatchMaxLine
     cx<T> *tile = tw + kBatchMaxLine;
     const int tid = threadIdx.x;
+    int prev = -1;   // descriptor of the item this workgroup finished last (uniform)
     for (;;) {
+        // The previous item's stores (every thread's) are released before it is counted.
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __syncthreads();
         if (tid == 0) {
+            if (prev >= 0) __hip_atomic_fetch_add(&bd.done[prev], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
             const int64_t item = int64_t(atomicAdd(bd.next, 1ull));
             int k = -1, skip = 0;
             if (item < bd.nitems) {
@@ -145,23 +168,24 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(const BatchDesc bd, con
             s_skip = skip;
         }
         __syncthreads();
-        const int64_t item = s_item;
-        const int k = s_k;
-        const int skip = s_skip;
+        const int64_t item = uniform64(s_item);
         if (item >= bd.nitems) break;
-        if (bd.dep[k] >= 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        const int k = uniform32(s_k);
+        const int skip = uniform32(s_skip);
+        prev = k;
+        if (uniform32(bd.dep[k]) >= 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        if (skip) continue;
         const BatchStage &st = bd.stages[k];
-        const int64_t first = (item - bd.starts[k]) * st.per_item;
-        const int64_t last = first + st.per_item < st.tiles ? first + st.per_item : st.tiles;
-        if (!skip) {
-            if (st.kind == kExchangeStage)
-                run_exchange<T>(st, table, smem_raw + kBatchMaxLine * sizeof(cx<T>), first, last, tid);
-            else
-                run_line<T>(st, table, tw, tile, first, last, tid);
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        __syncthreads();
-        if (tid == 0) __hip_atomic_fetch_add(&bd.done[k], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        const int kind = uniform32(st.kind);
+        const int64_t per = uniform32(st.per_item);
+        const int64_t tiles = uniform64(st.tiles);
+        const int64_t first = (item - uniform64(bd.starts[k])) * per;
+        const int64_t last = first + per < tiles ? first + per : tiles;
+        if (kind == kExchangeStage)
+            run_exchange<T>(st, uniform32(st.ex.nr * 8 + st.ex.lpr), table,
+                            smem_raw + kBatchMaxLine * sizeof(cx<T>), first, last, tid);
+        else
+            run_line<T>(st, uniform32(st.pd.loglen[0] * 8 + kind), table, tw, tile, first, last, tid);
     }
 }
 
