@@ -215,7 +215,13 @@ def test_launch_names(torch_dev):
         names = plan.launch_names()
         assert names[0] == "fftu::k_group2<float, 5, 5>" and names[-1] == "fftu::k_exchange<float, 5, 1, 0, 0>"
     with fftu.Plan((64, 64, 64), (8, 8, 2), "complex128", FORWARD) as plan:
-        assert plan.launch_names()[-4:-2] == ["fftu::k_twiddle<double>", "fftu::k_permute<double>"]
+        # unfused exchange: Superstep 0 passes, twiddle, permutation, then Superstep 2 passes
+        names = plan.launch_names()
+        info = plan.info()
+        assert len(names) == info["launches"] and info["exchange_fused"] == 0
+        i = names.index("fftu::k_twiddle<double>")
+        assert i == info["s0_kernels"] and names[i + 1] == "fftu::k_permute<double>"
+        assert len(names) - i == info["s2_kernels"] > 2     # twiddle, permutation and the F_p passes
 
 
 @pytest.mark.parametrize("knob,values", [("line_strided_logw", [2, 3, 4, 5]), ("line_contig_logw", [0, 1, 3, 5]),
