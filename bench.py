@@ -10,7 +10,13 @@ the dominant kernel (HIP events on the execution stream, algorithmic bytes =
 one read and one write of the N-element array per launch), the oracle timed on
 the host cores, and the error of the timed output against the oracle.
 
+With the default workload the line also carries a "batch" object: 256 uneven
+3-D complex64 transforms (sides 2^4..2^8 per dimension, 2x2x2 grids) in one
+persistent launch, its HIP-graph replay, and the same 256 transforms as plain
+per-transform executions, after a measured tuning of the tiling knobs.
+
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload 512cube|64cube|64pow5]
+                    [--no-batch] [--retune]
 """
 from __future__ import annotations
 
@@ -71,6 +77,126 @@ def measured_traffic(workload, kernel):
     return float(k["hbm_bytes_per_launch"])
 
 
+def ideal_passes(n, p, esize, lds=160 * 1024):
+    """Fewest HBM passes a transform of this shape needs: local dimensions grouped
+    greedily from the innermost outwards, the innermost group holding at most
+    `lds` bytes and every strided group at most lds/8 (so that at least 8
+    contiguous columns can be staged), plus one pass for the exchange (twiddle,
+    permutation and the length-p transforms fused). A transform whose N elements
+    fit in `lds` needs one pass."""
+    m = [a // b for a, b in zip(n, p)]
+    if math.prod(n) * esize <= lds:
+        return 1
+    groups, l = 0, len(m) - 1
+    while l >= 0:
+        cap = lds if groups == 0 else lds // 8
+        prod = m[l]
+        l -= 1
+        while l >= 0 and prod * m[l] * esize <= cap:
+            prod *= m[l]
+            l -= 1
+        groups += 1
+    return groups + 1
+
+
+def run_batch(args, torch, np, fftu, synth, with_oracle):
+    """The batch workload: 256 uneven 3-D complex64 transforms on 2x2x2 grids."""
+    from paper_2203_11795_amd import autotune
+    count, seed = 256, 4
+    shapes = synth.batch_shapes(count, seed)
+    grids = [(2, 2, 2)] * count
+    sizes = [math.prod(s) for s in shapes]
+    dev = torch.device("cuda:0")
+    log(f"[bench] batch: {count} transforms, {sum(sizes)} elements; generating input")
+    xs = [torch.from_numpy(synth.uniform_complex(n, 4_000_000 + i, np.complex64)).to(dev) for i, n in enumerate(sizes)]
+    outs = [torch.empty_like(x) for x in xs]
+    flops = sum(5.0 * n * math.log2(n) for n in sizes)
+    esize = 8
+
+    tune = autotune.tune_batch(shapes, grids, "complex64", fftu.FORWARD, xs, outs, reps=3, use_cache=not args.retune)
+    log(f"[bench] batch knobs {tune['knobs']} (cached={tune['cached']})")
+    autotune.apply(tune["knobs"])
+    try:
+        bp = fftu.BatchPlan(shapes, grids, "complex64", fftu.FORWARD)
+    finally:
+        autotune.apply({})
+    stream = torch.cuda.current_stream(dev)
+    steps = max(3, args.steps // 2)
+
+    def timed(run, k, begin=None):
+        for _ in range(args.warmup):
+            run()
+        torch.cuda.synchronize()
+        if begin:
+            begin()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(k):
+            run()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / k
+
+    ms_persistent = timed(lambda: bp(xs, outs, stream=stream), steps, begin=lambda: bp.timing_begin(steps))
+    per_launch, _ = bp.timing_end()          # [reset kernel, persistent kernel]
+    assert bp.error_flag() == 0, "a dependency wait of the persistent kernel gave up"
+    g = fftu.Graph(bp, xs, outs)
+    ms_graph = timed(lambda: g.launch(stream), steps)
+    g.close()
+    log(f"[bench] batch persistent {ms_persistent:.3f} ms, graph {ms_graph:.3f} ms")
+
+    plans = {}
+    for s in shapes:
+        if s not in plans:
+            plans[s] = fftu.Plan(s, (2, 2, 2), "complex64", fftu.FORWARD)
+    outs_plain = [torch.empty_like(x) for x in xs]
+
+    def plain():
+        for x, o, s in zip(xs, outs_plain, shapes):
+            plans[s](x, o, stream=stream)
+    ms_plain = timed(plain, steps)
+    log(f"[bench] batch as {count} plain executions {ms_plain:.3f} ms")
+    # different pass structures (the plain plans fuse the two inner dimensions), so not bitwise
+    diff = max(float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b)) for a, b in zip(outs, outs_plain))
+
+    exec_passes = [sum(1 for a in s if a // 2 > 1) + 1 for s in shapes]
+    bytes_exec = sum(2.0 * esize * n * k for n, k in zip(sizes, exec_passes))
+    bytes_ideal = sum(2.0 * esize * n * ideal_passes(s, (2, 2, 2), esize) for n, s in zip(sizes, shapes))
+    k_ms = per_launch[1] if len(per_launch) > 1 else ms_persistent
+    res = {
+        "workload": f"{count} uneven 3-D complex64 forward DFTs, sides 2^4..2^8 per dimension (shapes seed {seed}), "
+                    "2x2x2 cyclic grids, one persistent launch",
+        "elements": sum(sizes), "gflop": round(flops / 1e9, 3),
+        "ms_persistent": round(ms_persistent, 4), "ms_graph": round(ms_graph, 4), "ms_plain": round(ms_plain, 4),
+        "GFLOPs_persistent": round(flops / (ms_persistent * 1e-3) / 1e9, 1),
+        "GFLOPs_graph": round(flops / (ms_graph * 1e-3) / 1e9, 1),
+        "GFLOPs_plain": round(flops / (ms_plain * 1e-3) / 1e9, 1),
+        "speedup_vs_plain": round(ms_plain / ms_graph, 3),
+        "roofline": {"bound": "hbm", "kernel": "fftu::k_batch<float>", "avg_launch_ms": round(k_ms, 4),
+                     "bytes_executed_passes": bytes_exec, "bytes_ideal_passes": bytes_ideal,
+                     "achieved": round(bytes_exec / (k_ms * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(bytes_exec / (k_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "frac_vs_ideal_passes": round(bytes_ideal / (k_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
+        "tuning": {"knobs": tune["knobs"], "cached": tune["cached"], "candidates": len(tune.get("candidates", []))},
+        "rel_l2_persistent_vs_plain_max": diff,
+    }
+    if with_oracle:
+        import oracle
+        order = np.argsort(sizes)
+        pick = sorted({int(order[0]), int(order[-1]), int(order[count // 2])})
+        errs = []
+        for i in pick:
+            want = oracle.cyclic_dft(xs[i].cpu().numpy().astype(np.complex128), shapes[i], grids[i])
+            errs.append(oracle.rel_l2(outs[i].cpu().numpy(), want))
+        res["rel_l2_vs_oracle_max"] = max(errs)
+        res["checked_members"] = pick
+    for pl in plans.values():
+        pl.close()
+    bp.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -79,6 +205,8 @@ def main():
     ap.add_argument("--workload", default="512cube", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batch workload")
+    ap.add_argument("--retune", action="store_true", help="measure the tiling knobs again instead of the cached ones")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="time a plain device copy of the workload's N elements instead (counter calibration)")
     args = ap.parse_args()
@@ -199,6 +327,10 @@ def main():
             got = out.cpu().numpy()
             result["rel_l2_vs_oracle"] = oracle.rel_l2(got, oracle.to_cyclic(Y, p))
     plan.close()
+    if args.workload == "512cube" and not args.no_batch:
+        del x, out
+        torch.cuda.empty_cache()
+        result["batch"] = run_batch(args, torch, np, fftu, synth, not args.no_check)
     print(json.dumps(result), flush=True)
 
 

@@ -1,0 +1,159 @@
+"""Measured tuning of the tiling knobs (fftu_set_tuning) for a plan or a batch.
+
+The knobs change how the local-FFT passes are tiled (lines per workgroup, LDS
+padding, the LDS budget per workgroup), never what is computed. A plan reads
+them when it is created, so tuning builds one plan per candidate setting, times
+its executions with HIP events on the current stream, and keeps the fastest.
+The search is coordinate descent: each knob in turn is swept with the others
+held at the best values found so far, starting from the library defaults (-1).
+
+Results are cached in a JSON file (``FFTU_WISDOM``, default
+``~/.cache/fftu/wisdom.json``) keyed by device name, kind, dtype, direction and
+the shapes and grids, so a later process can apply them without measuring.
+"""
+from __future__ import annotations
+
+import hashlib
+import json
+import os
+import statistics
+
+from . import fftu as _b
+
+KNOB_NAMES = ("line_strided_logw", "line_contig_logw", "line_pad", "max_lds_kb")
+CANDIDATES = {
+    "line_strided_logw": (-1, 2, 3, 4, 5, 6),
+    "line_contig_logw": (-1, 0, 1, 2, 3, 4),
+    "line_pad": (-1, 0, 2),
+    "max_lds_kb": (-1, 32, 96, 160),
+}
+
+
+def wisdom_path() -> str:
+    return os.environ.get("FFTU_WISDOM", os.path.join(os.path.expanduser("~"), ".cache", "fftu", "wisdom.json"))
+
+
+def _load_wisdom() -> dict:
+    try:
+        with open(wisdom_path()) as fh:
+            return json.load(fh)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store_wisdom(key: str, value: dict) -> None:
+    w = _load_wisdom()
+    w[key] = value
+    path = wisdom_path()
+    try:
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        tmp = path + ".tmp"
+        with open(tmp, "w") as fh:
+            json.dump(w, fh, indent=1, sort_keys=True)
+        os.replace(tmp, path)
+    except OSError:
+        pass   # a read-only home only loses the cache
+
+
+def _key(kind, shapes, grids, dtype, direction) -> str:
+    import torch
+    dev = torch.cuda.get_device_name(0) if torch.cuda.is_available() else "cpu"
+    h = hashlib.sha1(repr((list(map(tuple, shapes)), list(map(tuple, grids)))).encode()).hexdigest()[:16]
+    return f"{dev}|{kind}|{dtype}|{int(direction)}|{h}"
+
+
+def current() -> dict:
+    return {k: _b.get_tuning(k) for k in KNOB_NAMES}
+
+
+def apply(knobs: dict) -> None:
+    for k in KNOB_NAMES:
+        _b.set_tuning(k, int(knobs.get(k, -1)))
+
+
+def _time_ms(run, reps: int) -> float:
+    import torch
+    run()                                   # warm-up (and first-touch of the plan's buffers)
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        run()
+        e1.record()
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1))
+    return statistics.median(times)
+
+
+def _search(make_runner, reps: int):
+    """Coordinate descent over the knobs. make_runner() builds a plan under the
+    current knobs and returns (run, close), or raises FftuError if the setting
+    is not plannable."""
+    saved = current()
+    table = []
+    best = {k: -1 for k in KNOB_NAMES}
+    best_ms = None
+    tried = {}
+    try:
+        for knob in KNOB_NAMES:
+            for v in CANDIDATES[knob]:
+                cand = dict(best)
+                cand[knob] = v
+                key = tuple(cand[k] for k in KNOB_NAMES)
+                if key in tried:
+                    continue
+                try:
+                    apply(cand)
+                    run, close = make_runner()
+                except _b.FftuError:
+                    tried[key] = None
+                    continue
+                try:
+                    ms = _time_ms(run, reps)
+                finally:
+                    close()
+                tried[key] = ms
+                table.append({**cand, "ms": round(ms, 4)})
+                if best_ms is None or ms < best_ms:
+                    best_ms, best = ms, cand
+    finally:
+        apply(saved)
+    return best, best_ms, table
+
+
+def tune_batch(shapes, grids, dtype, direction, xs, outs, reps: int = 5, use_cache: bool = True) -> dict:
+    """Best knobs for a BatchPlan over these members (xs/outs: device tensors)."""
+    key = _key("batch", shapes, grids, dtype, direction)
+    if use_cache:
+        hit = _load_wisdom().get(key)
+        if hit:
+            return {**hit, "cached": True}
+
+    def make_runner():
+        bp = _b.BatchPlan(shapes, grids, dtype, direction)
+        return (lambda: bp(xs, outs)), bp.close
+
+    best, best_ms, table = _search(make_runner, reps)
+    res = {"knobs": best, "ms": round(best_ms, 4) if best_ms is not None else None, "candidates": table}
+    _store_wisdom(key, {"knobs": best, "ms": res["ms"]})
+    return {**res, "cached": False}
+
+
+def tune_plan(n, p, dtype, direction, x, out, reps: int = 5, use_cache: bool = True) -> dict:
+    """Best knobs for a single Plan (x/out: device tensors of N elements)."""
+    key = _key("plan", [n], [p], dtype, direction)
+    if use_cache:
+        hit = _load_wisdom().get(key)
+        if hit:
+            return {**hit, "cached": True}
+
+    def make_runner():
+        pl = _b.Plan(n, p, dtype, direction)
+        return (lambda: pl(x, out)), pl.close
+
+    best, best_ms, table = _search(make_runner, reps)
+    res = {"knobs": best, "ms": round(best_ms, 4) if best_ms is not None else None, "candidates": table}
+    _store_wisdom(key, {"knobs": best, "ms": res["ms"]})
+    return {**res, "cached": False}

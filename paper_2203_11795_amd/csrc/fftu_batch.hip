@@ -198,12 +198,15 @@ int batch_blocks_per_cu(Precision prec, uint32_t lds_bytes)
     return e == hipSuccess && nb > 0 ? nb : 1;
 }
 
+hipError_t launch_batch_reset(const BatchDesc &bd, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_batch_reset, dim3(uint32_t((bd.nstages + 255) / 256 + 1)), dim3(256), 0, stream, bd);
+    return hipGetLastError();
+}
+
 hipError_t launch_batch(Precision prec, const BatchDesc &bd, const void *table, uint32_t blocks, uint32_t lds_bytes,
                         hipStream_t stream)
 {
-    hipLaunchKernelGGL(k_batch_reset, dim3(uint32_t((bd.nstages + 255) / 256 + 1)), dim3(256), 0, stream, bd);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
     if (prec == Precision::F64)
         hipLaunchKernelGGL(k_batch<double>, dim3(blocks), dim3(kBatchThreads), lds_bytes, stream, bd,
                            static_cast<const cx<double> *>(table));

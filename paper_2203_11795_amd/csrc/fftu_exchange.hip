@@ -33,7 +33,8 @@ __global__ __launch_bounds__(kExchangeThreads) void k_exchange(const cx<T> *__re
     constexpr int KG = (kExchangeThreads / 64) >> (NH * LPH);
     extern __shared__ unsigned char smem_raw[];
     const int64_t ngroups = (ex.g.M + 63) >> 6;
-    for (int64_t gb = int64_t(blockIdx.x) * KG; gb < ngroups; gb += int64_t(gridDim.x) * KG)
+    const int64_t nblocks = __builtin_amdgcn_readfirstlane(int(gridDim.x));   // uniform loop (barriers inside)
+    for (int64_t gb = int64_t(blockIdx.x) * KG; gb < ngroups; gb += nblocks * KG)
         exchange_group<T, NR, LPR, NH, LPH>(Z, V, ex, table, smem_raw, gb, threadIdx.x);
 }
 

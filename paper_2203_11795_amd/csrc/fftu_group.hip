@@ -19,6 +19,8 @@
 
 namespace fftu {
 
+constexpr int kGroupUnroll = 8;
+
 // Stage S's outputs written back to their Stockham positions in the line.
 template <typename T, int LOGL, int S>
 __device__ __forceinline__ void group_scatter(const cx<T> (&v)[LinePlan<LOGL>::E], cx<T> *tile, int base, int stride,
@@ -91,8 +93,12 @@ __global__ __launch_bounds__(kLineMaxThreads) void k_group2(const cx<T> *in, cx<
     cx<T> *tile = tw2 + L2;
     const int W = 1 << pd.logW;
     const int tid = threadIdx.x;
-    for (int e = tid; e < L1; e += blockDim.x) tw1[e] = table[e << (pd.lognmax - LOGL1)];
-    for (int e = tid; e < L2; e += blockDim.x) tw2[e] = table[e << (pd.lognmax - LOGL2)];
+    // launch sizes in scalar registers, read before any divergent code, so that the
+    // tile loop (which holds barriers) is wave-uniform
+    const int nt = __builtin_amdgcn_readfirstlane(int(blockDim.x));
+    const int64_t nblocks = __builtin_amdgcn_readfirstlane(int(gridDim.x));
+    for (int e = tid; e < L1; e += nt) tw1[e] = table[e << (pd.lognmax - LOGL1)];
+    for (int e = tid; e < L2; e += nt) tw2[e] = table[e << (pd.lognmax - LOGL2)];
 
     // inner-dimension lines (w, x1): thread -> (line, j), j fastest
     const int u2 = tid >> P2L::LOGTPL, j2 = tid & (P2L::TPL - 1);
@@ -105,17 +111,28 @@ __global__ __launch_bounds__(kLineMaxThreads) void k_group2(const cx<T> *in, cx<
 
     const T scale = static_cast<T>(pd.scale);
     const int n = W << LOGG;
-    for (int64_t t = blockIdx.x; t < pd.tiles; t += gridDim.x) {
+    for (int64_t t = blockIdx.x; t < pd.tiles; t += nblocks) {
         __syncthreads();
         const int64_t gbase = (t << pd.logW) << LOGG;
-        for (int e = tid; e < n; e += blockDim.x) {
-            const int w = e >> LOGG, x1 = (e >> LOGL2) & (L1 - 1), x2 = e & (L2 - 1);
-            tile[w * PG + x1 * P2 + x2] = conj_if(in[gbase + e], pd.conj_in);
+        // loads in groups of kGroupUnroll per thread, all issued before the LDS writes
+        for (int e0 = tid; e0 < n; e0 += kGroupUnroll * nt) {
+            cx<T> r[kGroupUnroll];
+#pragma unroll
+            for (int u = 0; u < kGroupUnroll; ++u)
+                if (e0 + u * nt < n) r[u] = in[gbase + e0 + u * nt];
+#pragma unroll
+            for (int u = 0; u < kGroupUnroll; ++u) {
+                const int e = e0 + u * nt;
+                if (e < n) {
+                    const int w = e >> LOGG, x1 = (e >> LOGL2) & (L1 - 1), x2 = e & (L2 - 1);
+                    tile[w * PG + x1 * P2 + x2] = conj_if(r[u], pd.conj_in);
+                }
+            }
         }
         __syncthreads();   // the whole tile is in LDS before any line is read
         group_axis<T, LOGL2>(tile, base2, 1, j2, act2, tw2);
         group_axis<T, LOGL1>(tile, base1, P2, j1, act1, tw1);
-        for (int e = tid; e < n; e += blockDim.x) {
+        for (int e = tid; e < n; e += nt) {
             const int w = e >> LOGG, x1 = (e >> LOGL2) & (L1 - 1), x2 = e & (L2 - 1);
             cx<T> v = conj_if(tile[w * PG + x1 * P2 + x2], pd.conj_out);
             if (pd.scale != 1.0) v = {v.x * scale, v.y * scale};

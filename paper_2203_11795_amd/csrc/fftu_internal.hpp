@@ -52,7 +52,7 @@ struct PassDesc {
     int32_t logG;
     int32_t logW;
     int32_t logBt;         // log2 min(B, W)
-    int32_t logTPA;        // log2(B / W) when B >= W (tiles per outer block), else 0
+    int32_t logTPA;        // log2(B / W) when B >= W (tiles per outer block), else 0 (generic tile pass only)
     int32_t lw;            // LDS pitch in elements (tile: row of W plus padding; k_line: see fftu_line.hip)
     int32_t naxes;         // dimensions in the group, outermost first
     int32_t loglen[kMaxGroup];
@@ -153,6 +153,7 @@ hipError_t launch_line(Precision prec, const void *in, void *out, const PassDesc
                        hipStream_t stream);
 hipError_t launch_group2(Precision prec, const void *in, void *out, const PassDesc &pd, const void *table,
                          hipStream_t stream);
+hipError_t launch_batch_reset(const BatchDesc &bd, hipStream_t stream);   // counters to zero (a kernel)
 hipError_t launch_batch(Precision prec, const BatchDesc &bd, const void *table, uint32_t blocks, uint32_t lds_bytes,
                         hipStream_t stream);
 int batch_blocks_per_cu(Precision prec, uint32_t lds_bytes);

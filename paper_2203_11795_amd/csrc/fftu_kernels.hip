@@ -142,7 +142,8 @@ __global__ __launch_bounds__(kPassThreads) void k_pass(const cx<T> *in, cx<T> *o
 {
     extern __shared__ unsigned char smem_raw[];
     cx<T> *buf = reinterpret_cast<cx<T> *>(smem_raw);
-    for (int64_t t = blockIdx.x; t < pd.tiles; t += gridDim.x) {
+    const int64_t nblocks = __builtin_amdgcn_readfirstlane(int(gridDim.x));   // uniform loop (barriers inside)
+    for (int64_t t = blockIdx.x; t < pd.tiles; t += nblocks) {
         pass_tile(in, out, pd, table, buf, t);
         __syncthreads();
     }

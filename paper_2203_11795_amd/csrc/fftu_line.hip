@@ -11,14 +11,16 @@
 // with the twiddle omega_{Ns R}^{r (jj mod Ns)} read from an LDS copy of omega_L).
 //
 // Layouts:
-//   kLineStrided    lines are columns of an (A, L, B) array with B >= W; W lines
-//                   of consecutive b per workgroup; lanes run over b first, so each
-//                   load or store instruction covers W consecutive elements.
+//   kLineStrided    lines are columns of an (A, L, B) array: W consecutive lines
+//                   of the A*B (a, b) lines per workgroup (W > B spans several
+//                   outer blocks); lanes run over b first, so each load or store
+//                   instruction covers runs of min(W, B) consecutive elements.
 //   kLineContig     contiguous lines (B = 1), W consecutive lines per workgroup;
 //                   lanes run along the line, runs of TPL elements.
-//   kLineStaged     contiguous lines whose thread runs would be short: the W*L
-//                   contiguous elements go through LDS with linear coalesced
-//                   loads and stores.
+//   kLineStaged     a tile of W >= B lines that is one contiguous run of W*L
+//                   elements (contiguous lines whose thread runs would be short,
+//                   or columns of short rows): it goes through LDS with linear
+//                   coalesced loads and stores.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -35,8 +37,11 @@ __global__ __launch_bounds__(kLineMaxThreads) void k_line(const cx<T> *in, cx<T>
     extern __shared__ unsigned char smem_raw[];
     cx<T> *tw = reinterpret_cast<cx<T> *>(smem_raw);   // omega_L^e, e in [L]
     cx<T> *lds = tw + PL::L;                            // the tile
+    // grid size in a scalar register, read before any divergent code: the tile loop
+    // holds barriers and must be wave-uniform
+    const int64_t nblocks = __builtin_amdgcn_readfirstlane(int(gridDim.x));
     line_twiddles<T, LOGL>(tw, table, pd.lognmax, threadIdx.x);
-    for (int64_t t = blockIdx.x; t < pd.tiles; t += gridDim.x) {
+    for (int64_t t = blockIdx.x; t < pd.tiles; t += nblocks) {
         __syncthreads();   // twiddle copy done / previous tile's LDS reads done
         line_tile<T, LOGL, MODE>(in, out, pd, tw, lds, t, threadIdx.x);
     }

@@ -112,9 +112,10 @@ __device__ __forceinline__ void line_tile(const cx<T> *in, cx<T> *out, const Pas
     int64_t base;      // global offset of element 0 of this thread's line
     int64_t xstride;   // global distance between consecutive line elements
     if constexpr (MODE == kLineStrided) {
-        const int64_t a = t >> pd.logTPA;
-        const int64_t b0 = (t & ((int64_t(1) << pd.logTPA) - 1)) << pd.logW;
-        base = a * pd.GB + b0 + w;
+        // line u = t W + w of the (A, B) lines: outer block u / B, column u mod B (a tile
+        // may span several outer blocks when B < W)
+        const int64_t u = (t << pd.logW) + w;
+        base = (u >> pd.logB) * pd.GB + (u & ((int64_t(1) << pd.logB) - 1));
         xstride = int64_t(1) << pd.logB;
     } else {
         base = ((t << pd.logW) + w) << LOGL;
@@ -122,10 +123,21 @@ __device__ __forceinline__ void line_tile(const cx<T> *in, cx<T> *out, const Pas
     }
 
     if constexpr (MODE == kLineStaged) {
+        // the tile is W L contiguous elements: W / B outer blocks of L rows of B columns
         const int64_t tbase = (t << pd.logW) << LOGL;
-        const int n = W << LOGL;
-        for (int e = tid; e < n; e += blockDim.x)
-            lds[lidx<MODE>(e & (PL::L - 1), e >> LOGL, pitch)] = conj_if(in[tbase + e], pd.conj_in);
+        const int lb = pd.logB, bm = (1 << lb) - 1;
+        // W L = threads * E: every working thread * E: every working thread moves E elements, all loads issued first
+        if (active) {
+            cx<T> r[PL::E];
+#pragma unroll
+            for (int c = 0; c < PL::E; ++c) r[c] = in[tbase + tid + c * pd.threads];
+#pragma unroll
+            for (int c = 0; c < PL::E; ++c) {
+                const int e = tid + c * pd.threads;
+                lds[lidx<MODE>((e >> lb) & (PL::L - 1), ((e >> (lb + LOGL)) << lb) | (e & bm), pitch)] =
+                    conj_if(r[c], pd.conj_in);
+            }
+        }
         __syncthreads();
         if (active) line_gather<T, LOGL, MODE>(v, j, w, pitch, lds, [](cx<T> &a, cx<T> b) { a = b; });
         __syncthreads();
@@ -149,8 +161,14 @@ __device__ __forceinline__ void line_tile(const cx<T> *in, cx<T> *out, const Pas
         }
         __syncthreads();
         const int64_t tbase = (t << pd.logW) << LOGL;
-        const int n = W << LOGL;
-        for (int e = tid; e < n; e += blockDim.x) out[tbase + e] = lds[lidx<MODE>(e & (PL::L - 1), e >> LOGL, pitch)];
+        const int lb = pd.logB, bm = (1 << lb) - 1;
+        if (active) {
+#pragma unroll
+            for (int c = 0; c < PL::E; ++c) {
+                const int e = tid + c * pd.threads;
+                out[tbase + e] = lds[lidx<MODE>((e >> lb) & (PL::L - 1), ((e >> (lb + LOGL)) << lb) | (e & bm), pitch)];
+            }
+        }
     } else if (active) {
 #pragma unroll
         for (int m = 0; m < PL::E; ++m) out[base + int64_t(j + m * PL::TPL) * xstride] = v[m];

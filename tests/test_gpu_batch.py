@@ -143,3 +143,31 @@ def test_uneven_batch_of_256(torch):
     for i in pick:
         want = oracle.cyclic_dft(xs[i].cpu().numpy().astype(np.complex128), shapes[i], grids[i])
         assert oracle.rel_l2(outs[i].cpu().numpy(), want) <= 5e-6, (i, shapes[i])
+
+
+def test_autotune_batch_keeps_results_and_caches(torch, tmp_path, monkeypatch):
+    import paper_2203_11795_amd as fftu
+    from paper_2203_11795_amd import autotune
+    monkeypatch.setenv("FFTU_WISDOM", str(tmp_path / "wisdom.json"))
+    shapes, grids = members(5, 11)
+    xs_h = [synth.uniform_complex(int(np.prod(s)), 90 + i, np.complex64) for i, s in enumerate(shapes)]
+    xs = to_dev(torch, xs_h, "complex64")
+    outs = [torch.empty_like(x) for x in xs]
+    res = autotune.tune_batch(shapes, grids, "complex64", FORWARD, xs, outs, reps=2)
+    say(f"autotune: {res['knobs']} {res['ms']} ms over {len(res['candidates'])} candidates")
+    assert not res["cached"] and len(res["candidates"]) >= 5
+    assert all(fftu.get_tuning(k) == -1 for k in autotune.KNOB_NAMES)     # defaults restored
+    again = autotune.tune_batch(shapes, grids, "complex64", FORWARD, xs, outs)
+    assert again["cached"] and again["knobs"] == res["knobs"]
+    with fftu.BatchPlan(shapes, grids, "complex64", FORWARD) as bp:
+        base = [o.clone() for o in bp(xs)]
+    autotune.apply(res["knobs"])
+    try:
+        with fftu.BatchPlan(shapes, grids, "complex64", FORWARD) as bp:
+            tuned = bp(xs)
+            torch.cuda.synchronize()
+            assert bp.error_flag() == 0
+    finally:
+        autotune.apply({})
+    for a, b in zip(base, tuned):
+        assert torch.equal(a, b)
