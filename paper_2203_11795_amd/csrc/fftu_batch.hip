@@ -15,11 +15,14 @@
 // workgroup records an error flag and skips the item, so every workgroup
 // reaches the end.
 //
-// Completion protocol: each thread's stores of a finished item are released
-// with a device-scope fence, then (after a barrier) thread 0 increments the
-// descriptor's counter before it takes the next item. A waiting workgroup polls the counter with relaxed device-scope
-// loads (no cache invalidation per poll) and, once it is complete, every thread
-// issues one device-scope acquire fence before reading the data.
+// Completion protocol: a stage's results are stored device-coherently (relaxed
+// device-scope atomic stores, written through to the level all XCDs read from);
+// each thread waits for its stores to complete, then (after a barrier) thread 0
+// increments the descriptor's counter before it takes the next item. A waiting
+// workgroup polls the counter with relaxed device-scope loads (no cache
+// invalidation per poll) and, once it is complete, every thread issues one
+// device-scope acquire fence (which drops stale lines from its L2) before
+// reading the data.
 // Counters are cleared by k_batch_reset (a kernel, so the pair can be captured
 // in a graph and replayed).
 #include <hip/hip_runtime.h>
@@ -70,7 +73,7 @@ __device__ __forceinline__ void run_line(const BatchStage &st, int key, const cx
         line_twiddles<T, LG>(tw, table, pd.lognmax, tid);                         \
         for (int64_t t = first; t < last; ++t) {                                  \
             __syncthreads(); /* twiddles in; previous tile's LDS reads done */    \
-            line_tile<T, LG, MD>(in, out, pd, tw, tile, t, tid);                  \
+            line_tile<T, LG, MD, true>(in, out, pd, tw, tile, t, tid);            \
         }                                                                         \
         break;
 #define FFTU_LINE_MODES(LG) FFTU_LINE_CASE(LG, kLineStrided) FFTU_LINE_CASE(LG, kLineContig) FFTU_LINE_CASE(LG, kLineStaged)
@@ -102,7 +105,7 @@ __device__ __forceinline__ void run_exchange(const BatchStage &st, int key, cons
 #define FFTU_EX_CASE(NR, LPR)                                                     \
     case (NR) * 8 + (LPR):                                                        \
         for (int64_t t = first; t < last; ++t)                                    \
-            exchange_group<T, NR, LPR, 0, 0>(Z, V, ex, table, smem, t * (kExchangeThreads / 64), tid); \
+            exchange_group<T, NR, LPR, 0, 0, true>(Z, V, ex, table, smem, t * (kExchangeThreads / 64), tid); \
         break;
     switch (key) {
         FFTU_EX_CASE(0, 0)
@@ -131,11 +134,15 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(const BatchDesc bd, con
     const int tid = threadIdx.x;
     int prev = -1;   // descriptor of the item this workgroup finished last (uniform)
     for (;;) {
-        // The previous item's stores (every thread's) are released before it is counted.
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        // The previous item's results were stored device-coherently (written through
+        // to the level every XCD reads from): each thread waits until its stores have
+        // completed, and after the barrier thread 0 counts the item. This orders the
+        // data before the count without a write-back of the L2 (a device-scope
+        // release fence), which cost about a third of the batch time.
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         __syncthreads();
         if (tid == 0) {
-            if (prev >= 0) __hip_atomic_fetch_add(&bd.done[prev], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            if (prev >= 0) __hip_atomic_fetch_add(&bd.done[prev], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             const int64_t item = int64_t(atomicAdd(bd.next, 1ull));
             int k = -1, skip = 0;
             if (item < bd.nitems) {

@@ -145,4 +145,29 @@ __device__ __forceinline__ void line_compute(cx<T> (&v)[LinePlan<LOGL>::E], int 
     }
 }
 
+// Store of one element. With CO (device-coherent), the store is a device-scope
+// relaxed atomic: it is written through to the level that every workgroup of the
+// device reads from, so that once the storing thread has waited for its stores
+// to complete, other workgroups (on any XCD) can read the value after an
+// acquire, with no write-back of the storing XCD's L2. complex128 goes as two
+// 8-byte halves.
+template <bool CO, typename T>
+__device__ __forceinline__ void put(cx<T> *p, const cx<T> &v)
+{
+    if constexpr (!CO) {
+        *p = v;
+    } else if constexpr (sizeof(T) == 4) {
+        uint64_t u;
+        __builtin_memcpy(&u, &v, 8);
+        __hip_atomic_store(reinterpret_cast<uint64_t *>(p), u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+        uint64_t u0, u1;
+        __builtin_memcpy(&u0, &v.x, 8);
+        __builtin_memcpy(&u1, &v.y, 8);
+        uint64_t *q = reinterpret_cast<uint64_t *>(p);
+        __hip_atomic_store(q, u0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(q + 1, u1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
 }  // namespace fftu

@@ -64,7 +64,7 @@ __device__ __forceinline__ int64_t digit_offset(const int32_t *dims, const Excha
 
 // One group of KG x 64 consecutive local indices (starting at group gb): gather,
 // twiddle, transform, swap, transform, scatter. Needs kExchangeThreads threads.
-template <typename T, int NR, int LPR, int NH, int LPH>
+template <typename T, int NR, int LPR, int NH, int LPH, bool CO = false>
 __device__ __forceinline__ void exchange_group(const cx<T> *__restrict__ Z, cx<T> *__restrict__ V,
                                                const ExchangeDesc &ex, const cx<T> *__restrict__ table,
                                                unsigned char *smem_raw, int64_t gb, int tid)
@@ -132,7 +132,7 @@ __device__ __forceinline__ void exchange_group(const cx<T> *__restrict__ Z, cx<T
             for (int j = 0; j < R; ++j) {
                 cx<T> w = conj_if(v[j], g.conj_out);
                 if (g.scale != 1.0) w = {w.x * scale, w.y * scale};
-                if (valid) V[obase + digit_offset<NR, LPR>(ex.rdim, ex, j)] = w;
+                if (valid) put<CO>(&V[obase + digit_offset<NR, LPR>(ex.rdim, ex, j)], w);
             }
         } else {
             // Swap through LDS: register j of wave hw goes to the wave that owns slot j
@@ -178,7 +178,7 @@ __device__ __forceinline__ void exchange_group(const cx<T> *__restrict__ Z, cx<T
                     if (g.scale != 1.0) o = {o.x * scale, o.y * scale};
                     const int64_t off = digit_offset<NH, LPH>(ex.hdim, ex, x) +
                                         digit_offset<NR, LPR>(ex.rdim, ex, hw * U + u);
-                    if (valid) V[obase + off] = o;
+                    if (valid) put<CO>(&V[obase + off], o);
                 }
         }
     }

@@ -90,8 +90,9 @@ __device__ __forceinline__ void line_stages(cx<T> (&v)[LinePlan<LOGL>::E], int j
 
 // One tile of a k_line pass: W lines (see the layouts above) with pd.threads
 // working threads; threads with tid >= pd.threads (a larger workgroup) only join
-// the barriers. tw holds omega_L^e, e in [L]; lds is the tile's LDS.
-template <typename T, int LOGL, int MODE>
+// the barriers. tw holds omega_L^e, e in [L]; lds is the tile's LDS. CO: the
+// results are stored device-coherently (see put()).
+template <typename T, int LOGL, int MODE, bool CO = false>
 __device__ __forceinline__ void line_tile(const cx<T> *in, cx<T> *out, const PassDesc &pd, const cx<T> *tw,
                                           cx<T> *lds, int64_t t, int tid)
 {
@@ -166,12 +167,12 @@ __device__ __forceinline__ void line_tile(const cx<T> *in, cx<T> *out, const Pas
 #pragma unroll
             for (int c = 0; c < PL::E; ++c) {
                 const int e = tid + c * pd.threads;
-                out[tbase + e] = lds[lidx<MODE>((e >> lb) & (PL::L - 1), ((e >> (lb + LOGL)) << lb) | (e & bm), pitch)];
+                put<CO>(&out[tbase + e], lds[lidx<MODE>((e >> lb) & (PL::L - 1), ((e >> (lb + LOGL)) << lb) | (e & bm), pitch)]);
             }
         }
     } else if (active) {
 #pragma unroll
-        for (int m = 0; m < PL::E; ++m) out[base + int64_t(j + m * PL::TPL) * xstride] = v[m];
+        for (int m = 0; m < PL::E; ++m) put<CO>(&out[base + int64_t(j + m * PL::TPL) * xstride], v[m]);
     }
 }
 
