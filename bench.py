@@ -13,10 +13,12 @@ the host cores, and the error of the timed output against the oracle.
 With the default workload the line also carries a "batch" object: 256 uneven
 3-D complex64 transforms (sides 2^4..2^8 per dimension, 2x2x2 grids) in one
 persistent launch, its HIP-graph replay, and the same 256 transforms as plain
-per-transform executions, after a measured tuning of the tiling knobs.
+per-transform executions, after a measured tuning of the tiling knobs; and a
+"serving" object: p50/p99 latency of a real-time request stream served with
+continuous batching and with a plain one-at-a-time FIFO.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload 512cube|64cube|64pow5]
-                    [--no-batch] [--retune]
+                    [--no-batch] [--retune] [--no-serving] [--serving-seconds S]
 """
 from __future__ import annotations
 
@@ -197,6 +199,34 @@ def run_batch(args, torch, np, fftu, synth, with_oracle):
     return res
 
 
+def run_serving(args, torch, synth):
+    """The serving workload: a Poisson stream of 2-D/3-D/4-D requests (2000/s,
+    sides 2^5..2^10, at most 2^26 points, complex64/complex128, forward/inverse,
+    trace seed 5), served in real time with the continuous policy and with the
+    plain one-at-a-time FIFO, on the same arena, plan cache and kernels."""
+    from paper_2203_11795_amd import serving
+    secs = float(args.serving_seconds)
+    reqs = serving.requests_from_trace(synth.serving_trace(seed=5, rate=2000.0, duration=30.0), limit_seconds=secs)
+    log(f"[bench] serving: {len(reqs)} requests in the first {secs:g} s of the trace")
+    srv = serving.Server(arena_bytes=16 << 30, streams=4, seed=5)
+    try:
+        srv.warmup(reqs)
+        out = {"workload": f"first {secs:g} s of a Poisson trace at 2000 requests/s (seed 5): rank 2-4, sides "
+                           "2^5..2^10, <= 2^26 points, complex64/complex128, forward/inverse, p_l = 2; "
+                           "input generated on the device (Philox4x32-10, key (5, request id))",
+               "streams": srv.nstreams, "arena_GiB": srv.arena_bytes / 2 ** 30}
+        for policy in ("continuous", "fifo"):
+            res = srv.serve(reqs, policy, time_limit=3 * secs + 5)
+            out[policy] = serving.summarize(res, reqs)
+            log(f"[bench] serving {policy}: {out[policy]}")
+        c, f = out["continuous"], out["fifo"]
+        out["p99_speedup_vs_fifo"] = round(f["p99_ms"] / c["p99_ms"], 3) if c["p99_ms"] > 0 else None
+        out["p50_speedup_vs_fifo"] = round(f["p50_ms"] / c["p50_ms"], 3) if c["p50_ms"] > 0 else None
+    finally:
+        srv.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -206,6 +236,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batch workload")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving workload")
+    ap.add_argument("--serving-seconds", type=float, default=10.0,
+                    help="seconds of the 30 s request trace to serve (each policy runs it in real time)")
     ap.add_argument("--retune", action="store_true", help="measure the tiling knobs again instead of the cached ones")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="time a plain device copy of the workload's N elements instead (counter calibration)")
@@ -331,6 +364,9 @@ def main():
         del x, out
         torch.cuda.empty_cache()
         result["batch"] = run_batch(args, torch, np, fftu, synth, not args.no_check)
+    if args.workload == "512cube" and not args.no_serving:
+        torch.cuda.empty_cache()
+        result["serving"] = run_serving(args, torch, synth)
     print(json.dumps(result), flush=True)
 
 

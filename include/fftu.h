@@ -171,6 +171,26 @@ size_t fftu_plan_device_bytes(fftu_plan_t plan);
 fftu_status fftu_execute(fftu_plan_t plan, const void *in, void *out, hipStream_t stream);
 
 /*
+ * Plans that own no device memory, for callers that manage HBM themselves (a
+ * serving loop with its own arena). fftu_plan_external takes the same arguments
+ * and applies the same checks as fftu_plan, but allocates nothing for the plan:
+ * it uses a twiddle table shared by all external plans of the device and
+ * precision (omega_{2^K}^j for the largest K needed so far, at least 2^12; the
+ * first call, or one that needs a larger K, allocates and uploads that table,
+ * which then stays until the process ends). Results are bitwise those of a
+ * plan made by fftu_plan. fftu_plan_device_bytes of such a plan is 0.
+ *
+ * fftu_execute_ws runs the transform of any plan with the caller's workspace:
+ * `workspace` is a device buffer of at least N elements of the plan's dtype
+ * (workspace_bytes in fftu_plan_info), overlapping neither in nor out; it is
+ * free again once the enqueued work has finished. fftu_execute on an external
+ * plan returns FFTU_ERROR_INVALID_VALUE. Errors as for fftu_execute.
+ */
+fftu_plan_t fftu_plan_external(int d, const int64_t n[], const int64_t p[], fftu_dtype dtype,
+                               fftu_direction direction);
+fftu_status fftu_execute_ws(fftu_plan_t plan, const void *in, void *out, void *workspace, hipStream_t stream);
+
+/*
  * The supersteps one at a time, for checking each against its definition.
  * All use the plan's direction for every weight and none applies 1/N.
  * Same buffer rules as fftu_execute, except fftu_stage_exchange, which needs
@@ -240,6 +260,26 @@ typedef struct fftu_graph_s *fftu_graph_t;
 fftu_graph_t fftu_graph_capture(fftu_plan_t plan, int count, const void *const in[], void *const out[]);
 fftu_status fftu_graph_launch(fftu_graph_t graph, hipStream_t stream);
 void fftu_graph_destroy(fftu_graph_t graph);
+
+/*
+ * Seeded device input (used by the serving layer to generate request data next
+ * to the transform instead of copying it over PCIe).
+ *
+ * fftu_fill_uniform writes `count` complex elements of `dtype` to the device
+ * buffer `out` (interleaved re, im; the caller owns it): element e is
+ * Philox4x32-10 (Salmon et al., SC'11: 10 rounds, multipliers 0xD2511F53 and
+ * 0xCD9E8D57, key increments 0x9E3779B9 and 0xBB67AE85) of the counter
+ * (c mod 2^32, c div 2^32, 0, 0), c = counter_base + e, under the key
+ * (key0, key1), with the output words x0..x3 mapped exactly into [-1, 1):
+ *   FFTU_C64:  re = (x0 >> 8) 2^-23 - 1,  im = (x1 >> 8) 2^-23 - 1
+ *   FFTU_C128: re = (x0 2^21 + (x1 >> 11)) 2^-52 - 1,
+ *              im = (x2 2^21 + (x3 >> 11)) 2^-52 - 1
+ * so a host implementation of the same definition reproduces it bit for bit.
+ * Asynchronous on `stream`. count == 0 does nothing. Errors: INVALID_VALUE
+ * (NULL out with count > 0, count < 0, bad dtype), DEVICE.
+ */
+fftu_status fftu_fill_uniform(void *out, int64_t count, fftu_dtype dtype, uint32_t key0, uint32_t key1,
+                              uint64_t counter_base, hipStream_t stream);
 
 /* Release a plan and its device memory. NULL is ignored. The caller must make
  * sure no enqueued work still uses the plan. */

@@ -4,7 +4,8 @@ with a single all-to-all (Koopman & Bisseling, arXiv 2203.11795, Algorithm 2.3).
 The transform runs in the HIP kernels of ``libfftu.so`` (C ABI in
 ``include/fftu.h``); :mod:`.fftu` is its Python binding.
 """
-from .fftu import (C64, C128, FORWARD, INVERSE, BatchPlan, FftuError, Graph, Plan, check, describe, get_tuning,
-                   load_library, set_tuning)
+from .fftu import (C64, C128, FORWARD, INVERSE, BatchPlan, FftuError, Graph, Plan, check, describe, fill_uniform,
+                   get_tuning, load_library, set_tuning)
 
-__all__ = ["Plan", "BatchPlan", "Graph", "FftuError", "check", "describe", "load_library", "set_tuning", "get_tuning", "FORWARD", "INVERSE", "C64", "C128"]
+__all__ = ["Plan", "BatchPlan", "Graph", "FftuError", "check", "describe", "fill_uniform", "load_library",
+           "set_tuning", "get_tuning", "FORWARD", "INVERSE", "C64", "C128"]

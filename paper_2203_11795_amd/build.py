@@ -16,7 +16,8 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfftu.so")
 ARCH = "gfx950"
 
-SOURCES = ["fftu_api.cpp", "fftu_kernels.hip", "fftu_line.hip", "fftu_exchange.hip", "fftu_group.hip", "fftu_batch.hip"]
+SOURCES = ["fftu_api.cpp", "fftu_kernels.hip", "fftu_line.hip", "fftu_exchange.hip", "fftu_group.hip",
+           "fftu_batch.hip", "fftu_fill.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 COMMON = [

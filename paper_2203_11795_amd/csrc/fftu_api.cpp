@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -34,6 +35,7 @@ struct fftu_plan_s {
     int device = 0;
     void *table = nullptr;
     void *ws = nullptr;
+    bool external = false;           // fftu_plan_external: shared table, workspace given per call
     uint64_t table_bytes = 0;
     uint64_t ws_bytes = 0;
     GridDesc grid{};                 // geometry, no conjugation or scaling
@@ -654,12 +656,156 @@ fftu_status enqueue_batch(fftu_plan_s *pl, hipStream_t stream, Marker *mk = null
     return FFTU_SUCCESS;
 }
 
+fftu_status execute_with(fftu_plan_s *plan, const void *in, void *out, void *ws, hipStream_t stream);
+
 }  // namespace
 
 struct fftu_graph_s {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 };
+
+namespace {
+
+// Twiddle tables shared by external plans: one per (device, precision), the
+// table omega_{2^K}^j, j in [2^K], for the largest K asked for so far (at least
+// 2^12). A plan indexes it with its own lognmax = K; omega_n^j = omega_{2^K}^{j 2^K / n}
+// and the table's construction gives bitwise the same values for every K (the
+// angles reduce to the same fractions), so results do not depend on K. A table
+// that is outgrown is kept until the process ends: plans made earlier still use it.
+struct SharedTable {
+    int device;
+    Precision prec;
+    int logK;
+    void *ptr;
+};
+std::mutex g_tables_mutex;
+std::vector<SharedTable> g_tables;
+
+hipError_t upload_table(void **ptr, int logK, fftu_dtype dtype)
+{
+    const std::vector<double> t64 = make_table_f64(logK);
+    const uint64_t bytes = (uint64_t(1) << logK) * (dtype == FFTU_C128 ? 16 : 8);
+    hipError_t e = hipMalloc(ptr, bytes);
+    if (e != hipSuccess) return e;
+    if (dtype == FFTU_C128) {
+        e = hipMemcpy(*ptr, t64.data(), bytes, hipMemcpyHostToDevice);
+    } else {
+        std::vector<float> t32(t64.size());
+        for (size_t i = 0; i < t64.size(); ++i) t32[i] = float(t64[i]);   // rounded once
+        e = hipMemcpy(*ptr, t32.data(), bytes, hipMemcpyHostToDevice);
+    }
+    if (e != hipSuccess) {
+        (void)hipFree(*ptr);
+        *ptr = nullptr;
+    }
+    return e;
+}
+
+hipError_t shared_table(int device, fftu_dtype dtype, int need_log, void **ptr, int *logK)
+{
+    const Precision prec = dtype == FFTU_C128 ? Precision::F64 : Precision::F32;
+    std::lock_guard<std::mutex> lock(g_tables_mutex);
+    SharedTable *best = nullptr;
+    for (SharedTable &t : g_tables)
+        if (t.device == device && t.prec == prec && (!best || t.logK > best->logK)) best = &t;
+    if (best && best->logK >= need_log) {
+        *ptr = best->ptr;
+        *logK = best->logK;
+        return hipSuccess;
+    }
+    const int K = std::max(need_log, 12);
+    void *p = nullptr;
+    hipError_t e = upload_table(&p, K, dtype);
+    if (e != hipSuccess) return e;
+    g_tables.push_back({device, prec, K, p});
+    *ptr = p;
+    *logK = K;
+    return hipSuccess;
+}
+
+fftu_plan_s *build_plan(int d, const int64_t n[], const int64_t p[], fftu_dtype dtype, fftu_direction direction,
+                        bool external)
+{
+    fftu_status s = validate(d, n, p, dtype, direction);
+    if (s != FFTU_SUCCESS) {
+        record(s);
+        return nullptr;
+    }
+    int device = 0;
+    if (hipGetDevice(&device) != hipSuccess) {
+        record(FFTU_ERROR_DEVICE);
+        return nullptr;
+    }
+    Geometry G = geometry(d, n, p);
+    void *shared = nullptr;
+    if (external) {
+        int logK = 0;
+        hipError_t e = shared_table(device, dtype, G.lognmax, &shared, &logK);
+        if (e != hipSuccess) {
+            record(from_hip(e));
+            return nullptr;
+        }
+        G.lognmax = logK;
+    }
+    fftu_plan_s *pl = new (std::nothrow) fftu_plan_s();
+    if (!pl) {
+        record(FFTU_ERROR_OUT_OF_MEMORY);
+        return nullptr;
+    }
+    pl->d = d;
+    for (int l = 0; l < d; ++l) {
+        pl->n[l] = n[l];
+        pl->p[l] = p[l];
+    }
+    pl->dtype = dtype;
+    pl->dir = direction;
+    pl->prec = dtype == FFTU_C128 ? Precision::F64 : Precision::F32;
+    pl->esize = dtype == FFTU_C128 ? 16 : 8;
+    pl->device = device;
+    pl->external = external;
+    pl->grid = make_grid(G);
+    pl->s0 = plan_s0(G, dtype);
+    pl->s2 = plan_s2(G, dtype);
+    ExchangeSplit sp;
+    pl->fused = exchange_split(G, dtype, &sp);
+    if (pl->fused) pl->ex = make_exchange(G, pl->grid, sp, dtype);
+    {
+        fftu_plan_info info{};
+        fill_info(G, pl->s0, pl->fused, pl->s2.size(), dtype, &info);
+        pl->launches = info.launches;
+        for (const PassDesc &pd : pl->s0) pl->launch_names.push_back(pass_kernel_name(pd, dtype));
+        if (pl->fused) {
+            pl->launch_names.push_back(exchange_kernel_name(pl->ex, dtype));
+        } else {
+            const std::string t = dtype == FFTU_C128 ? "double" : "float";
+            pl->launch_names.push_back("fftu::k_twiddle<" + t + ">");
+            pl->launch_names.push_back("fftu::k_permute<" + t + ">");
+            for (const PassDesc &pd : pl->s2) pl->launch_names.push_back(pass_kernel_name(pd, dtype));
+        }
+    }
+    if (external) {
+        pl->table = shared;      // not owned
+        record(FFTU_SUCCESS);
+        return pl;
+    }
+    pl->table_bytes = (uint64_t(1) << G.lognmax) * pl->esize;
+    pl->ws_bytes = uint64_t(pl->grid.N) * pl->esize;
+    hipError_t e = upload_table(&pl->table, G.lognmax, dtype);
+    if (e == hipSuccess) e = hipMalloc(&pl->ws, pl->ws_bytes);
+    if (e != hipSuccess) {
+        fftu_status st = from_hip(e);
+        if (pl->table) (void)hipFree(pl->table);
+        if (pl->ws) (void)hipFree(pl->ws);
+        delete pl;
+        record(st);
+        return nullptr;
+    }
+    record(FFTU_SUCCESS);
+    return pl;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -722,77 +868,13 @@ fftu_status fftu_describe(int d, const int64_t n[], const int64_t p[], fftu_dtyp
 
 fftu_plan_t fftu_plan(int d, const int64_t n[], const int64_t p[], fftu_dtype dtype, fftu_direction direction)
 {
-    fftu_status s = validate(d, n, p, dtype, direction);
-    if (s != FFTU_SUCCESS) {
-        record(s);
-        return nullptr;
-    }
-    fftu_plan_s *pl = new (std::nothrow) fftu_plan_s();
-    if (!pl) {
-        record(FFTU_ERROR_OUT_OF_MEMORY);
-        return nullptr;
-    }
-    pl->d = d;
-    for (int l = 0; l < d; ++l) {
-        pl->n[l] = n[l];
-        pl->p[l] = p[l];
-    }
-    pl->dtype = dtype;
-    pl->dir = direction;
-    pl->prec = dtype == FFTU_C128 ? Precision::F64 : Precision::F32;
-    pl->esize = dtype == FFTU_C128 ? 16 : 8;
-    const Geometry G = geometry(d, n, p);
-    pl->grid = make_grid(G);
-    pl->s0 = plan_s0(G, dtype);
-    pl->s2 = plan_s2(G, dtype);
-    ExchangeSplit sp;
-    pl->fused = exchange_split(G, dtype, &sp);
-    if (pl->fused) pl->ex = make_exchange(G, pl->grid, sp, dtype);
-    {
-        fftu_plan_info info{};
-        fill_info(G, pl->s0, pl->fused, pl->s2.size(), dtype, &info);
-        pl->launches = info.launches;
-        for (const PassDesc &pd : pl->s0) pl->launch_names.push_back(pass_kernel_name(pd, dtype));
-        if (pl->fused) {
-            pl->launch_names.push_back(exchange_kernel_name(pl->ex, dtype));
-        } else {
-            const std::string t = dtype == FFTU_C128 ? "double" : "float";
-            pl->launch_names.push_back("fftu::k_twiddle<" + t + ">");
-            pl->launch_names.push_back("fftu::k_permute<" + t + ">");
-            for (const PassDesc &pd : pl->s2) pl->launch_names.push_back(pass_kernel_name(pd, dtype));
-        }
-    }
+    return build_plan(d, n, p, dtype, direction, false);
+}
 
-    if (hipGetDevice(&pl->device) != hipSuccess) {
-        delete pl;
-        record(FFTU_ERROR_DEVICE);
-        return nullptr;
-    }
-    const std::vector<double> t64 = make_table_f64(G.lognmax);
-    const int64_t L = int64_t(1) << G.lognmax;
-    pl->table_bytes = uint64_t(L) * pl->esize;
-    pl->ws_bytes = uint64_t(pl->grid.N) * pl->esize;
-    hipError_t e = hipMalloc(&pl->table, pl->table_bytes);
-    if (e == hipSuccess) e = hipMalloc(&pl->ws, pl->ws_bytes);
-    if (e == hipSuccess) {
-        if (dtype == FFTU_C128) {
-            e = hipMemcpy(pl->table, t64.data(), pl->table_bytes, hipMemcpyHostToDevice);
-        } else {
-            std::vector<float> t32(t64.size());
-            for (size_t i = 0; i < t64.size(); ++i) t32[i] = float(t64[i]);   // rounded once
-            e = hipMemcpy(pl->table, t32.data(), pl->table_bytes, hipMemcpyHostToDevice);
-        }
-    }
-    if (e != hipSuccess) {
-        fftu_status st = from_hip(e);
-        if (pl->table) (void)hipFree(pl->table);
-        if (pl->ws) (void)hipFree(pl->ws);
-        delete pl;
-        record(st);
-        return nullptr;
-    }
-    record(FFTU_SUCCESS);
-    return pl;
+fftu_plan_t fftu_plan_external(int d, const int64_t n[], const int64_t p[], fftu_dtype dtype,
+                               fftu_direction direction)
+{
+    return build_plan(d, n, p, dtype, direction, true);
 }
 
 }  // extern "C"
@@ -996,6 +1078,15 @@ fftu_status fftu_execute_batch(fftu_plan_t plan, const void *const in[], void *c
     return record(enqueue_batch(plan, stream, &mk));
 }
 
+fftu_status fftu_fill_uniform(void *out, int64_t count, fftu_dtype dtype, uint32_t key0, uint32_t key1,
+                              uint64_t counter_base, hipStream_t stream)
+{
+    if (count < 0 || (count > 0 && !out) || (dtype != FFTU_C64 && dtype != FFTU_C128))
+        return record(FFTU_ERROR_INVALID_VALUE);
+    const fftu::Precision prec = dtype == FFTU_C128 ? fftu::Precision::F64 : fftu::Precision::F32;
+    return record(from_hip(fftu::launch_fill_uniform(prec, out, count, key0, key1, counter_base, stream)));
+}
+
 fftu_status fftu_batch_error(fftu_plan_t plan, int *flag)
 {
     if (!plan || !plan->is_batch || !flag) return record(FFTU_ERROR_INVALID_VALUE);
@@ -1103,22 +1194,46 @@ size_t fftu_plan_device_bytes(fftu_plan_t plan)
 
 fftu_status fftu_execute(fftu_plan_t plan, const void *in, void *out, hipStream_t stream)
 {
+    if (plan && plan->external) return record(FFTU_ERROR_INVALID_VALUE);   // needs fftu_execute_ws
+    return record(execute_with(plan, in, out, plan ? plan->ws : nullptr, stream));
+}
+
+fftu_status fftu_execute_ws(fftu_plan_t plan, const void *in, void *out, void *workspace, hipStream_t stream)
+{
     fftu_status s = check_exec_args(plan, in, out);
     if (s != FFTU_SUCCESS) return record(s);
+    if (!workspace) return record(FFTU_ERROR_INVALID_VALUE);
+    const char *w = static_cast<const char *>(workspace);
+    const size_t bytes = size_t(plan->grid.N) * plan->esize;
+    for (const void *buf : {in, static_cast<const void *>(out)}) {
+        const char *b = static_cast<const char *>(buf);
+        if (w < b + bytes && b < w + bytes) return record(FFTU_ERROR_INVALID_VALUE);   // overlaps a buffer
+    }
+    return record(execute_with(plan, in, out, workspace, stream));
+}
+
+}  // extern "C"
+
+namespace {
+
+fftu_status execute_with(fftu_plan_s *plan, const void *in, void *out, void *ws, hipStream_t stream)
+{
+    fftu_status s = check_exec_args(plan, in, out);
+    if (s != FFTU_SUCCESS) return s;
     Marker mk(plan, stream);
     mk.mark();
     const int inv = plan->dir == FFTU_INVERSE ? 1 : 0;
     const double scale = inv ? 1.0 / double(plan->grid.N) : 1.0;
     const void *src = in;
     if (!plan->s0.empty()) {
-        s = run_passes(plan, plan->s0, in, plan->ws, inv, 0, 1.0, stream, &mk);
-        if (s != FFTU_SUCCESS) return record(s);
-        src = plan->ws;
+        s = run_passes(plan, plan->s0, in, ws, inv, 0, 1.0, stream, &mk);
+        if (s != FFTU_SUCCESS) return s;
+        src = ws;
     } else if (in == out) {
         // N = 1: the exchange below must not read and write the same buffer.
-        hipError_t e = hipMemcpyAsync(plan->ws, in, plan->grid.N * plan->esize, hipMemcpyDeviceToDevice, stream);
-        if (e != hipSuccess) return record(from_hip(e));
-        src = plan->ws;
+        hipError_t e = hipMemcpyAsync(ws, in, plan->grid.N * plan->esize, hipMemcpyDeviceToDevice, stream);
+        if (e != hipSuccess) return from_hip(e);
+        src = ws;
     }
     const int conj_first = plan->s0.empty() ? inv : 0;
     if (plan->fused) {
@@ -1128,19 +1243,23 @@ fftu_status fftu_execute(fftu_plan_t plan, const void *in, void *out, hipStream_
         ex.g.scale = scale;
         hipError_t e = fftu::launch_exchange(plan->prec, src, out, ex, plan->table, stream);
         if (e == hipSuccess) mk.mark();
-        return record(from_hip(e));
+        return from_hip(e);
     }
     GridDesc g = plan->grid;
     g.conj_in = conj_first;
-    hipError_t e = fftu::launch_twiddle(plan->prec, src, plan->ws, g, plan->table, stream);
+    hipError_t e = fftu::launch_twiddle(plan->prec, src, ws, g, plan->table, stream);
     if (e == hipSuccess) {
         mk.mark();
-        e = fftu::launch_permute(plan->prec, plan->ws, out, plan->grid, stream);
+        e = fftu::launch_permute(plan->prec, ws, out, plan->grid, stream);
     }
-    if (e != hipSuccess) return record(from_hip(e));
+    if (e != hipSuccess) return from_hip(e);
     mk.mark();
-    return record(run_passes(plan, plan->s2, out, out, 0, inv, scale, stream, &mk));
+    return run_passes(plan, plan->s2, out, out, 0, inv, scale, stream, &mk);
 }
+
+}  // namespace
+
+extern "C" {
 
 fftu_status fftu_timing_begin(fftu_plan_t plan, int max_calls)
 {
@@ -1237,7 +1356,7 @@ void fftu_destroy(fftu_plan_t plan)
     if (have_cur && cur != plan->device) (void)hipSetDevice(plan->device);
     for (hipEvent_t ev : plan->events) (void)hipEventDestroy(ev);
     free_batch(plan);
-    if (plan->table) (void)hipFree(plan->table);
+    if (plan->table && !plan->external) (void)hipFree(plan->table);
     if (plan->ws) (void)hipFree(plan->ws);
     if (have_cur && cur != plan->device) (void)hipSetDevice(cur);
     delete plan;

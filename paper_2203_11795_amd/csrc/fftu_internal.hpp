@@ -154,6 +154,8 @@ hipError_t launch_line(Precision prec, const void *in, void *out, const PassDesc
 hipError_t launch_group2(Precision prec, const void *in, void *out, const PassDesc &pd, const void *table,
                          hipStream_t stream);
 hipError_t launch_batch_reset(const BatchDesc &bd, hipStream_t stream);   // counters to zero (a kernel)
+hipError_t launch_fill_uniform(Precision prec, void *out, int64_t count, uint32_t k0, uint32_t k1, uint64_t base,
+                               hipStream_t stream);
 hipError_t launch_batch(Precision prec, const BatchDesc &bd, const void *table, uint32_t blocks, uint32_t lds_bytes,
                         hipStream_t stream);
 int batch_blocks_per_cu(Precision prec, uint32_t lds_bytes);

@@ -24,10 +24,11 @@ STATUS = {0: "FFTU_SUCCESS", 1: "FFTU_ERROR_INVALID_VALUE", 2: "FFTU_ERROR_NOT_D
 
 # Every entry point declared in include/fftu.h.
 EXPORTS = ["fftu_version", "fftu_status_string", "fftu_last_error", "fftu_check", "fftu_describe", "fftu_plan",
-           "fftu_get_plan_info", "fftu_plan_device_bytes", "fftu_execute", "fftu_stage_local_fft",
+           "fftu_get_plan_info", "fftu_plan_device_bytes", "fftu_execute", "fftu_plan_external", "fftu_execute_ws",
+           "fftu_stage_local_fft",
            "fftu_stage_twiddle", "fftu_stage_exchange", "fftu_stage_remaining_fft", "fftu_timing_begin",
            "fftu_timing_end", "fftu_set_tuning", "fftu_get_tuning", "fftu_launch_name", "fftu_plan_batch", "fftu_execute_batch", "fftu_batch_error",
-           "fftu_graph_capture", "fftu_graph_launch", "fftu_graph_destroy", "fftu_destroy"]
+           "fftu_graph_capture", "fftu_graph_launch", "fftu_graph_destroy", "fftu_fill_uniform", "fftu_destroy"]
 
 TUNE = {"line_strided_logw": 0, "line_contig_logw": 1, "line_pad": 2, "max_lds_kb": 3}
 
@@ -82,6 +83,10 @@ def load_library(path: str = LIB_PATH):
         fn = getattr(lib, name)
         fn.restype = ctypes.c_int
         fn.argtypes = [vp, vp, vp, vp]
+    lib.fftu_plan_external.restype = vp
+    lib.fftu_plan_external.argtypes = [ctypes.c_int, i64p, i64p, ctypes.c_int, ctypes.c_int]
+    lib.fftu_execute_ws.restype = ctypes.c_int
+    lib.fftu_execute_ws.argtypes = [vp, vp, vp, vp, vp]
     lib.fftu_timing_begin.restype = ctypes.c_int
     lib.fftu_timing_begin.argtypes = [vp, ctypes.c_int]
     lib.fftu_timing_end.restype = ctypes.c_int
@@ -107,6 +112,9 @@ def load_library(path: str = LIB_PATH):
     lib.fftu_graph_launch.argtypes = [vp, vp]
     lib.fftu_graph_destroy.restype = None
     lib.fftu_graph_destroy.argtypes = [vp]
+    lib.fftu_fill_uniform.restype = ctypes.c_int
+    lib.fftu_fill_uniform.argtypes = [vp, ctypes.c_int64, ctypes.c_int, ctypes.c_uint32, ctypes.c_uint32,
+                                      ctypes.c_uint64, vp]
     lib.fftu_destroy.restype = None
     lib.fftu_destroy.argtypes = [vp]
     _lib = lib
@@ -156,6 +164,29 @@ def get_tuning(name: str) -> int:
     return int(load_library().fftu_get_tuning(TUNE[name]))
 
 
+def fill_uniform(out, key0: int, key1: int, counter_base: int = 0, stream=None):
+    """Fill the contiguous complex device tensor `out` with Philox4x32-10 values in
+    [-1, 1) (fftu_fill_uniform): element e from counter counter_base + e under the
+    key (key0, key1). Asynchronous on `stream` (default: the current stream)."""
+    import torch
+    if not isinstance(out, torch.Tensor) or not out.is_cuda or not out.is_contiguous():
+        raise TypeError("out must be a contiguous device tensor")
+    if out.dtype == torch.complex64:
+        code = C64
+    elif out.dtype == torch.complex128:
+        code = C128
+    else:
+        raise TypeError("out must be complex64 or complex128")
+    if stream is None:
+        stream = torch.cuda.current_stream(out.device)
+    st = load_library().fftu_fill_uniform(ctypes.c_void_p(out.data_ptr()), out.numel(), code,
+                                          int(key0) & 0xFFFFFFFF, int(key1) & 0xFFFFFFFF, int(counter_base),
+                                          ctypes.c_void_p(int(stream.cuda_stream)))
+    if st != 0:
+        raise FftuError(st, "fftu_fill_uniform")
+    return out
+
+
 class Plan:
     """A plan for the cyclic-to-cyclic d-D FFT (Algorithm 2.3) of an n-array on a p-grid.
 
@@ -163,17 +194,21 @@ class Plan:
     in the cyclic buffer layout (processor-major; see include/fftu.h).
     """
 
-    def __init__(self, n, p, dtype="complex128", direction=FORWARD):
+    def __init__(self, n, p, dtype="complex128", direction=FORWARD, external=False):
+        """external=True: fftu_plan_external (no device memory of its own; run it
+        with a workspace, see execute_ws)."""
         self.n = tuple(int(v) for v in n)
         self.p = tuple(int(v) for v in p)
         if len(self.n) != len(self.p):
             raise ValueError("n and p must have the same length")
         self.dtype_code = _dtype_code(dtype)
         self.direction = int(direction)
+        self.external = bool(external)
         self._lib = load_library()
-        h = self._lib.fftu_plan(len(self.n), _arr(self.n), _arr(self.p), self.dtype_code, self.direction)
+        make = self._lib.fftu_plan_external if self.external else self._lib.fftu_plan
+        h = make(len(self.n), _arr(self.n), _arr(self.p), self.dtype_code, self.direction)
         if not h:
-            raise FftuError(self._lib.fftu_last_error(), "fftu_plan")
+            raise FftuError(self._lib.fftu_last_error(), "fftu_plan_external" if self.external else "fftu_plan")
         self._h = ctypes.c_void_p(h)
         self.N = 1
         for v in self.n:
@@ -211,6 +246,16 @@ class Plan:
         if st != 0:
             raise FftuError(st, entry)
 
+    def execute_ws_ptr(self, in_ptr: int, out_ptr: int, ws_ptr: int, stream: int = 0) -> None:
+        st = self._lib.fftu_execute_ws(self._h, ctypes.c_void_p(in_ptr), ctypes.c_void_p(out_ptr),
+                                       ctypes.c_void_p(ws_ptr), ctypes.c_void_p(stream))
+        if st != 0:
+            raise FftuError(st, "fftu_execute_ws")
+
+    @property
+    def workspace_bytes(self) -> int:
+        return self.N * (16 if self.dtype_code == C128 else 8)
+
     # -- execution on torch tensors
     def _check_tensor(self, t, name):
         import torch
@@ -230,9 +275,23 @@ class Plan:
         self.execute_ptr(x.data_ptr(), out.data_ptr(), int(stream.cuda_stream), entry)
         return out
 
-    def __call__(self, x, out=None, stream=None):
-        """out = F(x) (forward) or F^{-1}(x) (inverse), asynchronously on `stream`."""
-        return self._run("fftu_execute", x, out, stream)
+    def __call__(self, x, out=None, stream=None, workspace=None):
+        """out = F(x) (forward) or F^{-1}(x) (inverse), asynchronously on `stream`.
+        workspace: a device tensor of at least workspace_bytes (required for an
+        external plan; fftu_execute_ws)."""
+        if workspace is None:
+            return self._run("fftu_execute", x, out, stream)
+        import torch
+        self._check_tensor(x, "input")
+        if out is None:
+            out = torch.empty_like(x)
+        self._check_tensor(out, "output")
+        if not workspace.is_cuda or workspace.numel() * workspace.element_size() < self.workspace_bytes:
+            raise ValueError(f"workspace must be a device tensor of at least {self.workspace_bytes} bytes")
+        if stream is None:
+            stream = torch.cuda.current_stream(x.device)
+        self.execute_ws_ptr(x.data_ptr(), out.data_ptr(), workspace.data_ptr(), int(stream.cuda_stream))
+        return out
 
     def stage(self, name: str, x, out=None, stream=None):
         """Run one superstep: 'local_fft', 'twiddle', 'exchange' or 'remaining_fft'."""

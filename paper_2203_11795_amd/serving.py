@@ -1,0 +1,303 @@
+"""Serving a stream of transform requests on one GPU.
+
+A request names a shape (rank 2..4 here, every side split over a 2-processor
+cyclic grid, so p_l = 2), a dtype and a direction. Serving one request means:
+generate its input on the device (fftu_fill_uniform with key (seed, request
+id), so no data crosses PCIe and any result can be reproduced on the host),
+transform it in place with an external plan (fftu_plan_external +
+fftu_execute_ws: no allocation per request), and report it complete when its
+stream passes the event recorded after it. Latency is completion minus arrival,
+both on one clock: completion times come from the GPU timestamps of those events,
+placed on the host clock through one reference event.
+
+HBM admission: every request needs 2 N b bytes (its buffer and the plan's
+workspace). They are carved out of one device arena allocated up front; a
+request is admitted, in arrival order, only when both fit, and otherwise waits
+for running requests to release theirs. Plans hold no device memory, so the plan
+cache is an LRU of host objects.
+
+Two policies over the same arena, plan cache and kernels:
+  "continuous"  up to `streams` requests run at once, one per HIP stream (all of
+                default priority); a stream that finishes takes the next
+                admitted request at once, so small requests do not queue behind
+                a large one and no stream waits for the host.
+  "fifo"        one request at a time on one stream; the host waits for each to
+                finish before it starts the next (the plain baseline).
+"""
+from __future__ import annotations
+
+import bisect
+import collections
+import math
+import time
+from dataclasses import dataclass, field
+
+from . import fftu as _b
+
+ALIGN = 256
+
+
+@dataclass
+class Request:
+    rid: int
+    arrival: float           # seconds after the start of the run
+    shape: tuple
+    dtype: str               # "complex64" or "complex128"
+    direction: int           # -1 forward, +1 inverse
+
+    @property
+    def grid(self):
+        return (2,) * len(self.shape)
+
+    @property
+    def N(self) -> int:
+        return math.prod(self.shape)
+
+    @property
+    def esize(self) -> int:
+        return 16 if self.dtype == "complex128" else 8
+
+
+def requests_from_trace(trace, limit_seconds=None):
+    """Request objects from synth.serving_trace records (optionally the first seconds only)."""
+    import numpy as np
+    out = []
+    for r in trace:
+        if limit_seconds is not None and r["t"] >= limit_seconds:
+            break
+        dt = "complex128" if np.dtype(r["dtype"]) == np.complex128 else "complex64"
+        out.append(Request(int(r["id"]), float(r["t"]), tuple(r["shape"]), dt, int(r["direction"])))
+    return out
+
+
+class Arena:
+    """First-fit allocator over [0, capacity) with coalescing (offsets in bytes)."""
+
+    def __init__(self, capacity: int):
+        self.capacity = int(capacity)
+        self.free = [(0, self.capacity)]        # sorted, non-adjacent
+        self.used = 0
+
+    def alloc(self, nbytes: int):
+        need = (int(nbytes) + ALIGN - 1) // ALIGN * ALIGN
+        for i, (off, size) in enumerate(self.free):
+            if size >= need:
+                if size == need:
+                    self.free.pop(i)
+                else:
+                    self.free[i] = (off + need, size - need)
+                self.used += need
+                return off, need
+        return None
+
+    def release(self, off: int, need: int):
+        i = bisect.bisect_left(self.free, (off, 0))
+        self.free.insert(i, (off, need))
+        self.used -= need
+        # merge with the right, then the left neighbour
+        if i + 1 < len(self.free) and self.free[i][0] + self.free[i][1] == self.free[i + 1][0]:
+            self.free[i] = (off, self.free[i][1] + self.free[i + 1][1])
+            self.free.pop(i + 1)
+        if i > 0 and self.free[i - 1][0] + self.free[i - 1][1] == self.free[i][0]:
+            self.free[i - 1] = (self.free[i - 1][0], self.free[i - 1][1] + self.free[i][1])
+            self.free.pop(i)
+
+
+class PlanCache:
+    """LRU of external plans keyed by (shape, dtype, direction)."""
+
+    def __init__(self, capacity: int = 4096):
+        self.capacity = int(capacity)
+        self.plans = collections.OrderedDict()
+        self.hits = 0
+        self.misses = 0
+
+    def get(self, req: Request):
+        key = (req.shape, req.dtype, req.direction)
+        pl = self.plans.get(key)
+        if pl is not None:
+            self.plans.move_to_end(key)
+            self.hits += 1
+            return pl
+        self.misses += 1
+        pl = _b.Plan(req.shape, req.grid, req.dtype, req.direction, external=True)
+        self.plans[key] = pl
+        if len(self.plans) > self.capacity:
+            _, old = self.plans.popitem(last=False)
+            old.close()
+        return pl
+
+    def close(self):
+        for pl in self.plans.values():
+            pl.close()
+        self.plans.clear()
+
+
+@dataclass
+class _Running:
+    req: Request
+    blocks: list
+    end: object              # torch.cuda.Event
+    out: object              # the request's buffer (a view into the arena)
+
+
+@dataclass
+class ServeResult:
+    policy: str
+    latencies: dict = field(default_factory=dict)    # rid -> seconds
+    completed: int = 0
+    unfinished: int = 0
+    wall: float = 0.0
+    outputs: dict = field(default_factory=dict)      # rid -> host copy (numpy), for the rids asked for
+    plan_hits: int = 0
+    plan_misses: int = 0
+    peak_arena_bytes: int = 0
+
+
+class Server:
+    """Serves requests with one of the two policies over a shared arena and plan cache."""
+
+    def __init__(self, arena_bytes: int = 16 << 30, streams: int = 4, seed: int = 5, plan_cache: int = 4096):
+        import torch
+        self.torch = torch
+        self.dev = torch.device("cuda:0")
+        self.arena_bytes = int(arena_bytes)
+        self.mem = torch.empty(self.arena_bytes, dtype=torch.uint8, device=self.dev)
+        self.seed = int(seed)
+        self.nstreams = int(streams)
+        self.streams = [torch.cuda.Stream(self.dev) for _ in range(self.nstreams)]   # default priority
+        self.plans = PlanCache(plan_cache)
+
+    def close(self):
+        self.plans.close()
+        self.mem = None
+
+    def _view(self, off: int, req: Request):
+        t = self.torch.complex128 if req.dtype == "complex128" else self.torch.complex64
+        return self.mem[off:off + req.N * req.esize].view(t)
+
+    def _launch(self, req: Request, arena: Arena, stream):
+        nbytes = req.N * req.esize
+        a = arena.alloc(nbytes)
+        if a is None:
+            return None
+        b = arena.alloc(nbytes)
+        if b is None:
+            arena.release(*a)
+            return None
+        plan = self.plans.get(req)
+        buf = self._view(a[0], req)
+        ws = self._view(b[0], req)
+        _b.fill_uniform(buf, self.seed, req.rid, 0, stream=stream)
+        plan(buf, buf, stream=stream, workspace=ws)
+        end = self.torch.cuda.Event(enable_timing=True)
+        end.record(stream)
+        return _Running(req, [a, b], end, buf)
+
+    def warmup(self, requests, count: int = 8):
+        """Run the largest few requests untimed (first-use costs: the shared twiddle
+        tables, the kernels' first launches)."""
+        arena = Arena(self.arena_bytes)
+        for r in sorted(requests, key=lambda r: -r.N)[:count]:
+            run = self._launch(r, arena, self.streams[0])
+            run.end.synchronize()
+            for blk in run.blocks:
+                arena.release(*blk)
+        self.torch.cuda.synchronize()
+
+    def serve(self, requests, policy: str = "continuous", keep=(), time_limit: float = None) -> ServeResult:
+        """Serve `requests` (sorted by arrival) in real time. keep: rids whose outputs
+        are copied to the host. time_limit: stop admitting after this many seconds
+        (requests not done by then count as unfinished)."""
+        torch = self.torch
+        if policy not in ("continuous", "fifo"):
+            raise ValueError(policy)
+        reqs = sorted(requests, key=lambda r: r.arrival)
+        keep = set(keep)
+        nstreams = self.nstreams if policy == "continuous" else 1
+        arena = Arena(self.arena_bytes)
+        res = ServeResult(policy)
+        hits0, miss0 = self.plans.hits, self.plans.misses
+
+        torch.cuda.synchronize()
+        ref = torch.cuda.Event(enable_timing=True)
+        ref.record(self.streams[0])
+        ref.synchronize()
+        t0 = time.perf_counter()                  # host time of the reference event (to ~10 us)
+
+        def finish(run: _Running):
+            done = ref.elapsed_time(run.end) * 1e-3
+            res.latencies[run.req.rid] = done - run.req.arrival
+            res.completed += 1
+            if run.req.rid in keep:
+                res.outputs[run.req.rid] = run.out.cpu().numpy()
+            for blk in run.blocks:
+                arena.release(*blk)
+
+        queue = collections.deque()
+        running = [None] * nstreams
+        i = 0
+        n = len(reqs)
+        while True:
+            now = time.perf_counter() - t0
+            if time_limit is not None and now > time_limit:
+                break
+            while i < n and reqs[i].arrival <= now:
+                queue.append(reqs[i])
+                i += 1
+            progressed = False
+            for s in range(nstreams):
+                run = running[s]
+                if run is not None and run.end.query():
+                    finish(run)
+                    running[s] = None
+                    progressed = True
+            for s in range(nstreams):
+                if not queue:
+                    break
+                if running[s] is None:
+                    run = self._launch(queue[0], arena, self.streams[s])
+                    if run is None:
+                        break                     # HBM admission: wait for running requests
+                    queue.popleft()
+                    res.peak_arena_bytes = max(res.peak_arena_bytes, arena.used)
+                    running[s] = run
+                    progressed = True
+                    if policy == "fifo":
+                        run.end.synchronize()     # the host waits for each request
+            if i >= n and not queue and all(r is None for r in running):
+                break
+            if not progressed:
+                if all(r is None for r in running) and not queue and i < n:
+                    time.sleep(max(0.0, min(reqs[i].arrival - (time.perf_counter() - t0), 1e-3)))
+                else:
+                    time.sleep(2e-5)
+        for s in range(nstreams):
+            if running[s] is not None:
+                running[s].end.synchronize()
+                finish(running[s])
+        torch.cuda.synchronize()
+        res.wall = time.perf_counter() - t0
+        res.unfinished = len(reqs) - res.completed
+        res.plan_hits = self.plans.hits - hits0
+        res.plan_misses = self.plans.misses - miss0
+        return res
+
+
+def summarize(res: ServeResult, requests) -> dict:
+    """p50/p99 latency, offered and achieved rates and GFLOP/s (5 N log2 N) of a run."""
+    import numpy as np
+    byid = {r.rid: r for r in requests}
+    lat = np.array(sorted(res.latencies.values())) if res.latencies else np.array([float("nan")])
+    flops = sum(5.0 * byid[k].N * math.log2(byid[k].N) for k in res.latencies)
+    span = max(r.arrival for r in requests) if requests else 0.0
+    return {
+        "policy": res.policy, "requests": len(requests), "completed": res.completed, "unfinished": res.unfinished,
+        "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3), "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
+        "mean_ms": round(float(lat.mean()) * 1e3, 3), "max_ms": round(float(lat.max()) * 1e3, 3),
+        "offered_rps": round(len(requests) / span, 1) if span > 0 else None,
+        "achieved_rps": round(res.completed / res.wall, 1) if res.wall > 0 else None,
+        "GFLOPs": round(flops / res.wall / 1e9, 1) if res.wall > 0 else None,
+        "wall_s": round(res.wall, 3), "plan_hits": res.plan_hits, "plan_misses": res.plan_misses,
+        "peak_arena_GiB": round(res.peak_arena_bytes / 2 ** 30, 3),
+    }
