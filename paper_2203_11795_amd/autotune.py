@@ -8,7 +8,7 @@ The search is coordinate descent: each knob in turn is swept with the others
 held at the best values found so far, starting from the library defaults (-1).
 
 Results are cached in a JSON file (``FFTU_WISDOM``, default
-``~/.cache/fftu/wisdom.json``) keyed by device name, kind, dtype, direction and
+``~/.cache/fftu/wisdom.json``) keyed by GPU architecture and CU count, kind, dtype, direction and
 the shapes and grids, so a later process can apply them without measuring.
 """
 from __future__ import annotations
@@ -57,7 +57,11 @@ def _store_wisdom(key: str, value: dict) -> None:
 
 def _key(kind, shapes, grids, dtype, direction) -> str:
     import torch
-    dev = torch.cuda.get_device_name(0) if torch.cuda.is_available() else "cpu"
+    if torch.cuda.is_available():
+        props = torch.cuda.get_device_properties(0)   # the architecture and CU count, not the marketing name
+        dev = f"{getattr(props, 'gcnArchName', props.name)}/{props.multi_processor_count}cu"
+    else:
+        dev = "cpu"
     h = hashlib.sha1(repr((list(map(tuple, shapes)), list(map(tuple, grids)))).encode()).hexdigest()[:16]
     return f"{dev}|{kind}|{dtype}|{int(direction)}|{h}"
 
