@@ -199,6 +199,65 @@ def run_batch(args, torch, np, fftu, synth, with_oracle):
     return res
 
 
+def run_convolution(args, torch, np, fftu, synth, info):
+    """Circular convolution at the headline shape (512^3 complex128, 4x4x4 grid):
+    forward transform with the product by the filter spectrum fused into its
+    exchange, then the inverse transform; against the same three steps unfused
+    (forward, a pointwise pass, inverse)."""
+    n, p = (512, 512, 512), (4, 4, 4)
+    N = math.prod(n)
+    esize = 16
+    dev = torch.device("cuda:0")
+    log("[bench] convolution: generating input and filter")
+    x = torch.from_numpy(synth.uniform_complex(N, 41, np.complex128)).to(dev)
+    hh = torch.from_numpy(synth.uniform_complex(N, 42, np.complex128)).to(dev)
+    conv = fftu.ConvolutionPlan(n, p, "complex128")
+    hhat = conv(hh)
+    del hh
+    y = torch.empty_like(x)
+    inv = fftu.Plan(n, p, "complex128", fftu.INVERSE)
+    stream = torch.cuda.current_stream(dev)
+    steps = max(3, args.steps // 2)
+
+    def timed(run):
+        for _ in range(args.warmup):
+            run()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            run()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    ms_fused = timed(lambda: conv.convolve(x, hhat, out=y, stream=stream))
+    fused_out = y.clone()
+
+    def unfused():
+        conv(x, y, stream=stream)
+        fftu.pointwise_mul(y, hhat, out=y, stream=stream)
+        inv(y, y, stream=stream)
+    ms_unfused = timed(unfused)
+    diff = float(torch.linalg.vector_norm(fused_out - y) / torch.linalg.vector_norm(y))
+    passes = 2 * info["launches"]
+    bytes_fused = passes * 2.0 * N * esize + N * esize
+    flops = 2 * 5.0 * N * math.log2(N) + 6.0 * N
+    conv.close()
+    inv.close()
+    log(f"[bench] convolution fused {ms_fused:.3f} ms, unfused {ms_unfused:.3f} ms")
+    return {"workload": "circular convolution of 512x512x512 complex128 arrays in the 4x4x4 cyclic layout: "
+                        "forward transform x pointwise filter spectrum, inverse transform",
+            "ms_fused": round(ms_fused, 4), "ms_unfused": round(ms_unfused, 4),
+            "speedup_fused": round(ms_unfused / ms_fused, 3),
+            "GFLOPs_fused": round(flops / (ms_fused * 1e-3) / 1e9, 1),
+            "roofline": {"bound": "hbm", "algorithmic_bytes": bytes_fused,
+                         "achieved": round(bytes_fused / (ms_fused * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(bytes_fused / (ms_fused * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
+            "rel_l2_fused_vs_unfused": diff}
+
+
 def run_serving(args, torch, synth):
     """The serving workload: a Poisson stream of 2-D/3-D/4-D requests (2000/s,
     sides 2^5..2^10, at most 2^26 points, complex64/complex128, forward/inverse,
@@ -237,6 +296,7 @@ def main():
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batch workload")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving workload")
+    ap.add_argument("--no-convolution", action="store_true", help="skip the convolution workload")
     ap.add_argument("--serving-seconds", type=float, default=10.0,
                     help="seconds of the 30 s request trace to serve (each policy runs it in real time)")
     ap.add_argument("--retune", action="store_true", help="measure the tiling knobs again instead of the cached ones")
@@ -360,9 +420,13 @@ def main():
             got = out.cpu().numpy()
             result["rel_l2_vs_oracle"] = oracle.rel_l2(got, oracle.to_cyclic(Y, p))
     plan.close()
-    if args.workload == "512cube" and not args.no_batch:
+    if args.workload == "512cube":
         del x, out
         torch.cuda.empty_cache()
+    if args.workload == "512cube" and not args.no_convolution:
+        result["convolution"] = run_convolution(args, torch, np, fftu, synth, info)
+        torch.cuda.empty_cache()
+    if args.workload == "512cube" and not args.no_batch:
         result["batch"] = run_batch(args, torch, np, fftu, synth, not args.no_check)
     if args.workload == "512cube" and not args.no_serving:
         torch.cuda.empty_cache()

@@ -262,6 +262,32 @@ fftu_status fftu_graph_launch(fftu_graph_t graph, hipStream_t stream);
 void fftu_graph_destroy(fftu_graph_t graph);
 
 /*
+ * Circular convolution in the cyclic layout (the transform starts and ends in
+ * the same distribution, so a product of spectra needs no reordering):
+ *   out = F^{-1}( F(in) . filter_hat ),
+ * i.e. out[j] = sum_k in[k] h[(j - k) mod n] per dimension when filter_hat =
+ * F(h) (unnormalised forward transform, as fftu_execute of this plan computes).
+ *
+ * fftu_plan_convolution makes a forward plan of the given shape (it owns the
+ * table and an N-element workspace and may be passed to fftu_execute, e.g. to
+ * transform the filter once) together with an inverse plan that shares the
+ * workspace. fftu_execute_convolution enqueues the forward transform of `in`
+ * with the product by `filter_hat` fused into its exchange (when the exchange is
+ * fused; otherwise one pointwise pass follows), then the inverse transform, in
+ * place on `out`. in == out allowed; filter_hat (N elements, cyclic layout, the
+ * plan's dtype) must not overlap out. Errors as for fftu_execute, and
+ * INVALID_VALUE for a plan not made by fftu_plan_convolution.
+ *
+ * fftu_pointwise_mul: out[i] = a[i] b[i] scale for i < count, complex elements
+ * of `dtype`; out may alias a or b. Asynchronous on `stream`.
+ */
+fftu_plan_t fftu_plan_convolution(int d, const int64_t n[], const int64_t p[], fftu_dtype dtype);
+fftu_status fftu_execute_convolution(fftu_plan_t plan, const void *in, const void *filter_hat, void *out,
+                                     hipStream_t stream);
+fftu_status fftu_pointwise_mul(const void *a, const void *b, void *out, int64_t count, fftu_dtype dtype, double scale,
+                               hipStream_t stream);
+
+/*
  * Seeded device input (used by the serving layer to generate request data next
  * to the transform instead of copying it over PCIe).
  *

@@ -21,6 +21,10 @@ What it computes (Koopman & Bisseling, arXiv 2203.11795):
 * :func:`emulate` -- Algorithm 2.3 carried out literally, virtual processor by
   virtual processor, exposing the buffer after each superstep, so that each
   GPU stage can be checked on its own.
+* :func:`circular_convolution` -- the cyclic convolution of two arrays of one
+  shape, summed from its definition (the application that motivates keeping
+  input and output in the same distribution: forward transform, pointwise
+  product, inverse transform, with no reordering; Sections 1 and 2.2).
 
 Complex arrays are numpy complex128. Directions: FORWARD = -1 (omega_n =
 exp(-2 pi i / n), unnormalised), INVERSE = +1.
@@ -294,6 +298,21 @@ def emulate(D: np.ndarray, n, p, direction: int = FORWARD) -> dict:
     if direction == INVERSE:
         out *= 1.0 / V.size
     return {"S0": Y, "twiddle": Z, "S1": W, "S2": V, "out": out}
+
+
+def circular_convolution(x: np.ndarray, h: np.ndarray) -> np.ndarray:
+    """y[j] = sum_k x[k] h[(j - k) mod n], indices taken per dimension (natural
+    order, complex128), summed term by term over every k: O(N^2), small arrays only."""
+    x = np.asarray(x, dtype=np.complex128)
+    h = np.asarray(h, dtype=np.complex128)
+    if x.shape != h.shape:
+        raise ValueError("x and h must have the same shape")
+    axes = tuple(range(x.ndim))
+    y = np.zeros_like(x)
+    for k in np.ndindex(x.shape):
+        if x[k] != 0:
+            y += x[k] * np.roll(h, shift=k, axis=axes)     # roll(h, k)[j] = h[(j - k) mod n]
+    return y
 
 
 def rel_l2(y: np.ndarray, yref: np.ndarray) -> float:

@@ -36,6 +36,7 @@ struct fftu_plan_s {
     void *table = nullptr;
     void *ws = nullptr;
     bool external = false;           // fftu_plan_external: shared table, workspace given per call
+    fftu_plan_s *conv_inv = nullptr; // fftu_plan_convolution: the inverse plan (external, uses this plan's workspace)
     uint64_t table_bytes = 0;
     uint64_t ws_bytes = 0;
     GridDesc grid{};                 // geometry, no conjugation or scaling
@@ -656,7 +657,8 @@ fftu_status enqueue_batch(fftu_plan_s *pl, hipStream_t stream, Marker *mk = null
     return FFTU_SUCCESS;
 }
 
-fftu_status execute_with(fftu_plan_s *plan, const void *in, void *out, void *ws, hipStream_t stream);
+fftu_status execute_with(fftu_plan_s *plan, const void *in, void *out, void *ws, hipStream_t stream,
+                         const void *mul = nullptr);
 
 }  // namespace
 
@@ -1212,11 +1214,54 @@ fftu_status fftu_execute_ws(fftu_plan_t plan, const void *in, void *out, void *w
     return record(execute_with(plan, in, out, workspace, stream));
 }
 
+fftu_plan_t fftu_plan_convolution(int d, const int64_t n[], const int64_t p[], fftu_dtype dtype)
+{
+    fftu_plan_s *fwd = build_plan(d, n, p, dtype, FFTU_FORWARD, false);
+    if (!fwd) return nullptr;
+    fftu_plan_s *inv = build_plan(d, n, p, dtype, FFTU_INVERSE, true);
+    if (!inv) {
+        const fftu_status st = fftu_last_error();
+        fftu_destroy(fwd);
+        record(st);
+        return nullptr;
+    }
+    fwd->conv_inv = inv;
+    record(FFTU_SUCCESS);
+    return fwd;
+}
+
+fftu_status fftu_execute_convolution(fftu_plan_t plan, const void *in, const void *filter_hat, void *out,
+                                     hipStream_t stream)
+{
+    if (!plan || !plan->conv_inv || !filter_hat) return record(FFTU_ERROR_INVALID_VALUE);
+    fftu_status s = check_exec_args(plan, in, out);
+    if (s != FFTU_SUCCESS) return record(s);
+    const char *h = static_cast<const char *>(filter_hat);
+    const char *o = static_cast<const char *>(out);
+    const size_t bytes = size_t(plan->grid.N) * plan->esize;
+    if (h < o + bytes && o < h + bytes) return record(FFTU_ERROR_INVALID_VALUE);   // out must not overlap the filter
+    s = execute_with(plan, in, out, plan->ws, stream, filter_hat);
+    if (s != FFTU_SUCCESS) return record(s);
+    return record(execute_with(plan->conv_inv, out, out, plan->ws, stream));
+}
+
+fftu_status fftu_pointwise_mul(const void *a, const void *b, void *out, int64_t count, fftu_dtype dtype, double scale,
+                               hipStream_t stream)
+{
+    if (count < 0 || (count > 0 && (!a || !b || !out)) || (dtype != FFTU_C64 && dtype != FFTU_C128))
+        return record(FFTU_ERROR_INVALID_VALUE);
+    const fftu::Precision prec = dtype == FFTU_C128 ? fftu::Precision::F64 : fftu::Precision::F32;
+    return record(from_hip(fftu::launch_pointwise(prec, a, b, out, count, scale, stream)));
+}
+
 }  // extern "C"
 
 namespace {
 
-fftu_status execute_with(fftu_plan_s *plan, const void *in, void *out, void *ws, hipStream_t stream)
+// The transform of `plan` with workspace `ws`; mul (optional) multiplies the
+// output pointwise (fused into the exchange, or a separate pass when the
+// exchange is not fused).
+fftu_status execute_with(fftu_plan_s *plan, const void *in, void *out, void *ws, hipStream_t stream, const void *mul)
 {
     fftu_status s = check_exec_args(plan, in, out);
     if (s != FFTU_SUCCESS) return s;
@@ -1241,6 +1286,7 @@ fftu_status execute_with(fftu_plan_s *plan, const void *in, void *out, void *ws,
         ex.g.conj_in = conj_first;
         ex.g.conj_out = inv;
         ex.g.scale = scale;
+        ex.mul = mul;
         hipError_t e = fftu::launch_exchange(plan->prec, src, out, ex, plan->table, stream);
         if (e == hipSuccess) mk.mark();
         return from_hip(e);
@@ -1254,7 +1300,9 @@ fftu_status execute_with(fftu_plan_s *plan, const void *in, void *out, void *ws,
     }
     if (e != hipSuccess) return from_hip(e);
     mk.mark();
-    return run_passes(plan, plan->s2, out, out, 0, inv, scale, stream, &mk);
+    s = run_passes(plan, plan->s2, out, out, 0, inv, scale, stream, &mk);
+    if (s != FFTU_SUCCESS || !mul) return s;
+    return from_hip(fftu::launch_pointwise(plan->prec, out, mul, out, plan->grid.N, 1.0, stream));
 }
 
 }  // namespace
@@ -1351,6 +1399,10 @@ fftu_status fftu_stage_remaining_fft(fftu_plan_t plan, const void *in, void *out
 void fftu_destroy(fftu_plan_t plan)
 {
     if (!plan) return;
+    if (plan->conv_inv) {
+        fftu_destroy(plan->conv_inv);
+        plan->conv_inv = nullptr;
+    }
     int cur = 0;
     const bool have_cur = hipGetDevice(&cur) == hipSuccess;
     if (have_cur && cur != plan->device) (void)hipSetDevice(plan->device);

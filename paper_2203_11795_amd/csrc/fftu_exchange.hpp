@@ -64,6 +64,8 @@ __device__ __forceinline__ int64_t digit_offset(const int32_t *dims, const Excha
 
 // One group of KG x 64 consecutive local indices (starting at group gb): gather,
 // twiddle, transform, swap, transform, scatter. Needs kExchangeThreads threads.
+// With ex.mul set, every output is multiplied by the element of ex.mul at the
+// same position before it is stored (a pointwise product in the output layout).
 template <typename T, int NR, int LPR, int NH, int LPH, bool CO = false>
 __device__ __forceinline__ void exchange_group(const cx<T> *__restrict__ Z, cx<T> *__restrict__ V,
                                                const ExchangeDesc &ex, const cx<T> *__restrict__ table,
@@ -132,7 +134,11 @@ __device__ __forceinline__ void exchange_group(const cx<T> *__restrict__ Z, cx<T
             for (int j = 0; j < R; ++j) {
                 cx<T> w = conj_if(v[j], g.conj_out);
                 if (g.scale != 1.0) w = {w.x * scale, w.y * scale};
-                if (valid) put<CO>(&V[obase + digit_offset<NR, LPR>(ex.rdim, ex, j)], w);
+                const int64_t idx = obase + digit_offset<NR, LPR>(ex.rdim, ex, j);
+                if (valid) {
+                    if (ex.mul) w = cmul(w, static_cast<const cx<T> *>(ex.mul)[idx]);
+                    put<CO>(&V[idx], w);
+                }
             }
         } else {
             // Swap through LDS: register j of wave hw goes to the wave that owns slot j
@@ -176,9 +182,12 @@ __device__ __forceinline__ void exchange_group(const cx<T> *__restrict__ Z, cx<T
                 for (int u = 0; u < U; ++u) {
                     cx<T> o = conj_if(w[x * U + u], g.conj_out);
                     if (g.scale != 1.0) o = {o.x * scale, o.y * scale};
-                    const int64_t off = digit_offset<NH, LPH>(ex.hdim, ex, x) +
+                    const int64_t idx = obase + digit_offset<NH, LPH>(ex.hdim, ex, x) +
                                         digit_offset<NR, LPR>(ex.rdim, ex, hw * U + u);
-                    if (valid) put<CO>(&V[obase + off], o);
+                    if (valid) {
+                        if (ex.mul) o = cmul(o, static_cast<const cx<T> *>(ex.mul)[idx]);
+                        put<CO>(&V[idx], o);
+                    }
                 }
         }
     }

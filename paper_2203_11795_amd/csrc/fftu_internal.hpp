@@ -94,6 +94,7 @@ struct ExchangeDesc {
     int32_t hdim[kMaxDims];
     int32_t oshift[kMaxDims];
     uint32_t lds_bytes;
+    const void *mul;       // null, or N elements in the output layout that every output is multiplied by
 };
 
 // Persistent batch (fftu_batch.hip). One descriptor per (stage, transform).
@@ -154,6 +155,8 @@ hipError_t launch_line(Precision prec, const void *in, void *out, const PassDesc
 hipError_t launch_group2(Precision prec, const void *in, void *out, const PassDesc &pd, const void *table,
                          hipStream_t stream);
 hipError_t launch_batch_reset(const BatchDesc &bd, hipStream_t stream);   // counters to zero (a kernel)
+hipError_t launch_pointwise(Precision prec, const void *a, const void *b, void *out, int64_t count, double scale,
+                            hipStream_t stream);
 hipError_t launch_fill_uniform(Precision prec, void *out, int64_t count, uint32_t k0, uint32_t k1, uint64_t base,
                                hipStream_t stream);
 hipError_t launch_batch(Precision prec, const BatchDesc &bd, const void *table, uint32_t blocks, uint32_t lds_bytes,

@@ -28,7 +28,8 @@ EXPORTS = ["fftu_version", "fftu_status_string", "fftu_last_error", "fftu_check"
            "fftu_stage_local_fft",
            "fftu_stage_twiddle", "fftu_stage_exchange", "fftu_stage_remaining_fft", "fftu_timing_begin",
            "fftu_timing_end", "fftu_set_tuning", "fftu_get_tuning", "fftu_launch_name", "fftu_plan_batch", "fftu_execute_batch", "fftu_batch_error",
-           "fftu_graph_capture", "fftu_graph_launch", "fftu_graph_destroy", "fftu_fill_uniform", "fftu_destroy"]
+           "fftu_graph_capture", "fftu_graph_launch", "fftu_graph_destroy", "fftu_fill_uniform", "fftu_plan_convolution",
+           "fftu_execute_convolution", "fftu_pointwise_mul", "fftu_destroy"]
 
 TUNE = {"line_strided_logw": 0, "line_contig_logw": 1, "line_pad": 2, "max_lds_kb": 3}
 
@@ -115,6 +116,12 @@ def load_library(path: str = LIB_PATH):
     lib.fftu_fill_uniform.restype = ctypes.c_int
     lib.fftu_fill_uniform.argtypes = [vp, ctypes.c_int64, ctypes.c_int, ctypes.c_uint32, ctypes.c_uint32,
                                       ctypes.c_uint64, vp]
+    lib.fftu_plan_convolution.restype = vp
+    lib.fftu_plan_convolution.argtypes = [ctypes.c_int, i64p, i64p, ctypes.c_int]
+    lib.fftu_execute_convolution.restype = ctypes.c_int
+    lib.fftu_execute_convolution.argtypes = [vp, vp, vp, vp, vp]
+    lib.fftu_pointwise_mul.restype = ctypes.c_int
+    lib.fftu_pointwise_mul.argtypes = [vp, vp, vp, ctypes.c_int64, ctypes.c_int, ctypes.c_double, vp]
     lib.fftu_destroy.restype = None
     lib.fftu_destroy.argtypes = [vp]
     _lib = lib
@@ -331,6 +338,63 @@ class Plan:
 
     def __exit__(self, *exc):
         self.close()
+
+
+class ConvolutionPlan(Plan):
+    """Circular convolution in the cyclic layout (fftu_plan_convolution): as a Plan
+    it is the forward transform (use it to transform a filter once);
+    convolve(x, filter_hat) = F^{-1}(F(x) . filter_hat)."""
+
+    def __init__(self, n, p, dtype="complex128"):
+        self.n = tuple(int(v) for v in n)
+        self.p = tuple(int(v) for v in p)
+        if len(self.n) != len(self.p):
+            raise ValueError("n and p must have the same length")
+        self.dtype_code = _dtype_code(dtype)
+        self.direction = FORWARD
+        self.external = False
+        self._lib = load_library()
+        h = self._lib.fftu_plan_convolution(len(self.n), _arr(self.n), _arr(self.p), self.dtype_code)
+        if not h:
+            raise FftuError(self._lib.fftu_last_error(), "fftu_plan_convolution")
+        self._h = ctypes.c_void_p(h)
+        self.N = _prod(self.n)
+
+    def convolve(self, x, filter_hat, out=None, stream=None):
+        import torch
+        self._check_tensor(x, "input")
+        self._check_tensor(filter_hat, "filter_hat")
+        if out is None:
+            out = torch.empty_like(x)
+        self._check_tensor(out, "output")
+        if stream is None:
+            stream = torch.cuda.current_stream(x.device)
+        st = self._lib.fftu_execute_convolution(self._h, ctypes.c_void_p(x.data_ptr()),
+                                                ctypes.c_void_p(filter_hat.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                                ctypes.c_void_p(int(stream.cuda_stream)))
+        if st != 0:
+            raise FftuError(st, "fftu_execute_convolution")
+        return out
+
+
+def pointwise_mul(a, b, out=None, scale: float = 1.0, stream=None):
+    """out = a * b * scale elementwise on device (fftu_pointwise_mul); out may be a or b."""
+    import torch
+    if a.dtype != b.dtype or a.numel() != b.numel() or not (a.is_cuda and b.is_cuda):
+        raise ValueError("a and b must be device tensors of one complex dtype and size")
+    if out is None:
+        out = torch.empty_like(a)
+    code = C128 if a.dtype == torch.complex128 else C64 if a.dtype == torch.complex64 else None
+    if code is None or out.dtype != a.dtype or out.numel() != a.numel():
+        raise ValueError("complex64 or complex128 tensors of one size")
+    if stream is None:
+        stream = torch.cuda.current_stream(a.device)
+    st = load_library().fftu_pointwise_mul(ctypes.c_void_p(a.data_ptr()), ctypes.c_void_p(b.data_ptr()),
+                                           ctypes.c_void_p(out.data_ptr()), a.numel(), code, float(scale),
+                                           ctypes.c_void_p(int(stream.cuda_stream)))
+    if st != 0:
+        raise FftuError(st, "fftu_pointwise_mul")
+    return out
 
 
 def _ptrs(values):

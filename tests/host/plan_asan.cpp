@@ -27,6 +27,7 @@ hipError_t launch_exchange(Precision, const void *, void *, const ExchangeDesc &
 }
 hipError_t launch_batch_reset(const BatchDesc &, hipStream_t) { return hipSuccess; }
 hipError_t launch_fill_uniform(Precision, void *, int64_t, uint32_t, uint32_t, uint64_t, hipStream_t) { return hipSuccess; }
+hipError_t launch_pointwise(Precision, const void *, const void *, void *, int64_t, double, hipStream_t) { return hipSuccess; }
 hipError_t launch_batch(Precision, const BatchDesc &bd, const void *, uint32_t, uint32_t, hipStream_t)
 {
     if (bd.nstages < 1 || bd.nitems < 1) std::abort();
