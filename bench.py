@@ -166,6 +166,7 @@ def run_batch(args, torch, np, fftu, synth, with_oracle):
     bytes_exec = sum(2.0 * esize * n * k for n, k in zip(sizes, exec_passes))
     bytes_ideal = sum(2.0 * esize * n * ideal_passes(s, (2, 2, 2), esize) for n, s in zip(sizes, shapes))
     k_ms = per_launch[1] if len(per_launch) > 1 else ms_persistent
+    traffic = measured_traffic("512cube", "fftu::k_batch<float>")
     res = {
         "workload": f"{count} uneven 3-D complex64 forward DFTs, sides 2^4..2^8 per dimension (shapes seed {seed}), "
                     "2x2x2 cyclic grids, one persistent launch",
@@ -179,7 +180,8 @@ def run_batch(args, torch, np, fftu, synth, with_oracle):
                      "bytes_executed_passes": bytes_exec, "bytes_ideal_passes": bytes_ideal,
                      "achieved": round(bytes_exec / (k_ms * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(bytes_exec / (k_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                     "frac_vs_ideal_passes": round(bytes_ideal / (k_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
+                     "frac_vs_ideal_passes": round(bytes_ideal / (k_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "traffic": traffic},
         "tuning": {"knobs": tune["knobs"], "cached": tune["cached"], "candidates": len(tune.get("candidates", []))},
         "rel_l2_persistent_vs_plain_max": diff,
     }
