@@ -260,6 +260,58 @@ def run_convolution(args, torch, np, fftu, synth, info):
             "rel_l2_fused_vs_unfused": diff}
 
 
+def run_mixed(args, torch, np, fftu, synth, with_oracle):
+    """The mixed-radix path at full size: 480^3 complex128 (480 = 2^5 3 5) on a 4^3
+    grid (m = 120, q = 30), forward; per-kernel times from HIP events."""
+    n, p = (480, 480, 480), (4, 4, 4)
+    N = math.prod(n)
+    esize = 16
+    dev = torch.device("cuda:0")
+    log("[bench] mixed radix 480^3: generating input")
+    D = synth.uniform_complex(N, 6, np.complex128)
+    x = torch.from_numpy(D).to(dev)
+    out = torch.empty_like(x)
+    plan = fftu.Plan(n, p, "complex128", fftu.FORWARD)
+    info = plan.info()
+    stream = torch.cuda.current_stream(dev)
+    steps = max(3, args.steps // 2)
+    for _ in range(args.warmup):
+        plan(x, out, stream=stream)
+    torch.cuda.synchronize()
+    plan.timing_begin(steps)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        plan(x, out, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    per_launch, _ = plan.timing_end()
+    names = plan.launch_names()
+    alg = 2.0 * N * esize
+    flops = 5.0 * N * math.log2(N)
+    res = {"workload": "480x480x480 complex128 forward DFT (480 = 2^5 3 5), 4x4x4 cyclic grid, mixed-radix path",
+           "ms_per_transform": round(ms, 4), "GFLOPs": round(flops / (ms * 1e-3) / 1e9, 1),
+           "launches": info["launches"],
+           "roofline": {"bound": "hbm", "algorithmic_bytes": info["launches"] * alg,
+                        "achieved": round(info["launches"] * alg / (ms * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": round(info["launches"] * alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
+           "kernels": [{"kernel": k, "avg_ms": round(t, 4), "GBps_alg": round(alg / (t * 1e-3) / 1e9, 1)}
+                       for k, t in zip(names, per_launch)]}
+    if with_oracle:
+        import oracle
+        X = oracle.from_cyclic(D, n, p)
+        ks = [(0, 0, 0), (1, 2, 3), (479, 240, 17), (100, 333, 451)]
+        flat = [int(np.ravel_multi_index(k, n)) for k in ks]
+        want = oracle.dft_points(X, flat)
+        got = oracle.from_cyclic(out.cpu().numpy(), n, p).reshape(-1)[flat]
+        res["sampled_max_rel_error_vs_oracle"] = float(np.abs(got - want).max() / np.abs(want).max())
+    plan.close()
+    log(f"[bench] mixed 480^3: {ms:.3f} ms, {res['GFLOPs']} GFLOP/s")
+    return res
+
+
 def run_serving(args, torch, synth):
     """The serving workload: a Poisson stream of 2-D/3-D/4-D requests (2000/s,
     sides 2^5..2^10, at most 2^26 points, complex64/complex128, forward/inverse,
@@ -299,6 +351,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batch workload")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving workload")
     ap.add_argument("--no-convolution", action="store_true", help="skip the convolution workload")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-radix workload")
     ap.add_argument("--serving-seconds", type=float, default=10.0,
                     help="seconds of the 30 s request trace to serve (each policy runs it in real time)")
     ap.add_argument("--retune", action="store_true", help="measure the tiling knobs again instead of the cached ones")
@@ -427,6 +480,9 @@ def main():
         torch.cuda.empty_cache()
     if args.workload == "512cube" and not args.no_convolution:
         result["convolution"] = run_convolution(args, torch, np, fftu, synth, info)
+        torch.cuda.empty_cache()
+    if args.workload == "512cube" and not args.no_mixed:
+        result["mixed_radix"] = run_mixed(args, torch, np, fftu, synth, not args.no_check)
         torch.cuda.empty_cache()
     if args.workload == "512cube" and not args.no_batch:
         result["batch"] = run_batch(args, torch, np, fftu, synth, not args.no_check)

@@ -7,8 +7,10 @@ with the HIP library and never imports it.
 What it computes (Koopman & Bisseling, arXiv 2203.11795):
 
 * :func:`dft` -- the d-dimensional DFT of eq. (1.2) in natural row-major order,
-  by 1-D radix-2 FFTs along each axis (eq. (1.3)); the inverse conjugates every
-  weight and multiplies by 1/N (Section 1.3, last paragraph).
+  by 1-D DFTs along each axis (eq. (1.3)): radix-2 FFTs for power-of-two
+  lengths, the 1-D definition summed term by term for other lengths; the
+  inverse conjugates every weight and multiplies by 1/N (Section 1.3, last
+  paragraph).
 * :func:`dft_direct` / :func:`dft_points` -- eq. (1.2) summed term by term
   (all outputs of a tiny array, or chosen outputs of a large one).
 * :func:`to_cyclic` / :func:`from_cyclic` -- the d-dimensional cyclic
@@ -83,7 +85,8 @@ def _check_direction(direction):
 
 
 def fft_axes(x: np.ndarray, axes, direction: int = FORWARD, nthreads: int = 0) -> np.ndarray:
-    """Unnormalised 1-D DFTs along each axis in ``axes`` (radix-2, power-of-two lengths)."""
+    """Unnormalised 1-D DFTs along each axis in ``axes``: radix-2 FFTs for
+    power-of-two lengths, the 1-D definition summed term by term otherwise."""
     _check_direction(direction)
     y = np.ascontiguousarray(x, dtype=np.complex128).copy()
     if y.ndim == 0:

@@ -15,14 +15,16 @@
  *     O(N) per output, for spot checks of large arrays;
  *   - oracle_fft_axes: 1-D DFTs applied along chosen axes one after the other
  *     (the row-column factorisation of Section 1.2, eq. (1.3)), each 1-D DFT
- *     computed by the textbook iterative radix-2 Cooley-Tukey FFT.
+ *     computed by the textbook iterative radix-2 Cooley-Tukey FFT when its
+ *     length is a power of two, and otherwise summed term by term from the
+ *     1-D definition (O(L^2) per line, long double sums, exponents reduced
+ *     exactly).
  *
  * Sign convention (Section 1, eq. (1.1)): omega_n = exp(-2*pi*i/n) for the
  * forward transform; sign = +1 conjugates every weight (unnormalised inverse).
  * Complex arrays are interleaved (re, im) doubles.
  *
- * Status codes: 0 success, 1 invalid argument, 2 length not a power of two,
- * 3 out of memory.
+ * Status codes: 0 success, 1 invalid argument, 3 out of memory.
  */
 #include <math.h>
 #include <stdint.h>
@@ -112,6 +114,24 @@ static void fft1d_radix2(cplx *a, int64_t L, const cplx *w)
  * DFTs along each axis). Axes are processed from the last to the first.
  * nthreads <= 0 means "use the OpenMP default".
  */
+/* y[k] = sum_j x[j] w[(j k) mod L] for k in [L]: the 1-D DFT of eq. (1.1) by its
+ * definition, with w[e] = omega_L^e (sign included), long double sums. */
+static void dft1d_direct(const cplx *x, cplx *y, int64_t L, const cplx *w)
+{
+    for (int64_t k = 0; k < L; ++k) {
+        long double re = 0.0L, im = 0.0L;
+        int64_t e = 0;                       /* (j k) mod L, advanced by k per term */
+        for (int64_t j = 0; j < L; ++j) {
+            re += (long double)x[j].re * w[e].re - (long double)x[j].im * w[e].im;
+            im += (long double)x[j].re * w[e].im + (long double)x[j].im * w[e].re;
+            e += k;
+            if (e >= L) e -= L;
+        }
+        y[k].re = (double)re;
+        y[k].im = (double)im;
+    }
+}
+
 int oracle_fft_axes(int ndim, const int64_t *shape, uint32_t axes_mask, double *data, int sign,
                     int nthreads)
 {
@@ -121,9 +141,6 @@ int oracle_fft_axes(int ndim, const int64_t *shape, uint32_t axes_mask, double *
         if (shape[a] < 1) return 1;
         total *= shape[a];
     }
-    for (int a = 0; a < ndim; ++a)
-        if ((axes_mask >> a) & 1u)
-            if (!is_pow2(shape[a])) return 2;
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
 #else
@@ -137,13 +154,15 @@ int oracle_fft_axes(int ndim, const int64_t *shape, uint32_t axes_mask, double *
         int64_t stride = 1;
         for (int b = a + 1; b < ndim; ++b) stride *= shape[b];
         int64_t outer = total / (L * stride);
-        cplx *w = (cplx *)malloc(sizeof(cplx) * (size_t)(L / 2));
+        const int radix2 = is_pow2(L);
+        const int64_t nw = radix2 ? L / 2 : L;
+        cplx *w = (cplx *)malloc(sizeof(cplx) * (size_t)nw);
         if (!w) return 3;
-        for (int64_t e = 0; e < L / 2; ++e) w[e] = root_of_unity(L, e, sign);
+        for (int64_t e = 0; e < nw; ++e) w[e] = root_of_unity(L, e, sign);
         int failed = 0;
 #pragma omp parallel
         {
-            cplx *line = (cplx *)malloc(sizeof(cplx) * (size_t)L);
+            cplx *line = (cplx *)malloc(sizeof(cplx) * (size_t)(2 * L));
             if (!line) {
 #pragma omp atomic write
                 failed = 1;
@@ -153,7 +172,12 @@ int oracle_fft_axes(int ndim, const int64_t *shape, uint32_t axes_mask, double *
                     int64_t o = ln / stride, i = ln % stride;
                     cplx *base = x + o * L * stride + i;
                     for (int64_t j = 0; j < L; ++j) line[j] = base[j * stride];
-                    fft1d_radix2(line, L, w);
+                    if (radix2) {
+                        fft1d_radix2(line, L, w);
+                    } else {
+                        dft1d_direct(line, line + L, L, w);
+                        memcpy(line, line + L, sizeof(cplx) * (size_t)L);
+                    }
                     for (int64_t j = 0; j < L; ++j) base[j * stride] = line[j];
                 }
                 free(line);

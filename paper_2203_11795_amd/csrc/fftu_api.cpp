@@ -37,6 +37,11 @@ struct fftu_plan_s {
     void *ws = nullptr;
     bool external = false;           // fftu_plan_external: shared table, workspace given per call
     fftu_plan_s *conv_inv = nullptr; // fftu_plan_convolution: the inverse plan (external, uses this plan's workspace)
+    // mixed-radix plans (some side not a power of two)
+    bool mixed = false;
+    std::vector<fftu::MixedPassDesc> ms0, ms2;
+    fftu::MixedGridDesc mg{};
+    int64_t table_T = 0;             // entries of the twiddle table omega_T
     uint64_t table_bytes = 0;
     uint64_t ws_bytes = 0;
     GridDesc grid{};                 // geometry, no conjugation or scaling
@@ -92,6 +97,30 @@ fftu_status record(fftu_status s)
 
 bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
 
+// Only the prime factors 2, 3, 5 and 7 (the mixed-radix stages).
+bool is_smooth(int64_t v)
+{
+    if (v < 1) return false;
+    for (int f : {2, 3, 5, 7})
+        while (v % f == 0) v /= f;
+    return v == 1;
+}
+
+int64_t gcd64(int64_t a, int64_t b)
+{
+    while (b) {
+        const int64_t t = a % b;
+        a = b;
+        b = t;
+    }
+    return a;
+}
+
+int64_t lcm64(int64_t a, int64_t b) { return a / gcd64(a, b) * b; }
+
+// Longest line of the mixed-radix pass: two LDS buffers of a line plus its roots in 64 KiB.
+int64_t max_mixed_len(fftu_dtype dt) { return dt == FFTU_C128 ? 1024 : 2048; }
+
 int ilog2(int64_t v)
 {
     int r = 0;
@@ -115,14 +144,37 @@ fftu_status validate(int d, const int64_t n[], const int64_t p[], fftu_dtype dty
     // Algorithm 2.3, Input: p_l^2 | n_l.
     for (int l = 0; l < d; ++l)
         if (n[l] % p[l] != 0 || (n[l] / p[l]) % p[l] != 0) return FFTU_ERROR_NOT_DIVISIBLE;
-    int logN = 0;
-    for (int l = 0; l < d; ++l) {
-        if (!is_pow2(n[l]) || !is_pow2(p[l])) return FFTU_ERROR_UNSUPPORTED;
-        logN += ilog2(n[l]);
-        if (n[l] / p[l] > max_len(dtype) || p[l] > max_len(dtype)) return FFTU_ERROR_UNSUPPORTED;
+    bool all_pow2 = true;
+    for (int l = 0; l < d; ++l) all_pow2 = all_pow2 && is_pow2(n[l]) && is_pow2(p[l]);
+    if (all_pow2) {
+        int logN = 0;
+        for (int l = 0; l < d; ++l) {
+            logN += ilog2(n[l]);
+            if (n[l] / p[l] > max_len(dtype) || p[l] > max_len(dtype)) return FFTU_ERROR_UNSUPPORTED;
+        }
+        if (logN >= 40) return FFTU_ERROR_UNSUPPORTED;
+        return FFTU_SUCCESS;
     }
-    if (logN >= 40) return FFTU_ERROR_UNSUPPORTED;
+    // Mixed-radix path: prime factors 2, 3, 5, 7 only; lines up to the LDS tile;
+    // N < 2^31 (32-bit index arithmetic); table omega_T with T = lcm(n_l) <= 2^24.
+    int64_t N = 1, T = 1;
+    for (int l = 0; l < d; ++l) {
+        if (!is_smooth(n[l])) return FFTU_ERROR_UNSUPPORTED;
+        if (n[l] / p[l] > max_mixed_len(dtype) || p[l] > max_mixed_len(dtype)) return FFTU_ERROR_UNSUPPORTED;
+        if (N > (int64_t(1) << 31) / n[l]) return FFTU_ERROR_UNSUPPORTED;
+        N *= n[l];
+        T = lcm64(T, n[l]);
+        if (T > (int64_t(1) << 24)) return FFTU_ERROR_UNSUPPORTED;
+    }
+    if (N >= (int64_t(1) << 31)) return FFTU_ERROR_UNSUPPORTED;
     return FFTU_SUCCESS;
+}
+
+bool plan_is_mixed(int d, const int64_t n[], const int64_t p[])
+{
+    for (int l = 0; l < d; ++l)
+        if (!is_pow2(n[l]) || !is_pow2(p[l])) return true;
+    return false;
 }
 
 // Radix split of a length 2^logL into stages of at most 16, as even as possible.
@@ -498,6 +550,176 @@ std::vector<double> make_table_f64(int logL)
     return t;
 }
 
+// cos and sin of 2 pi j / L for any L: the half-turn symmetry (j > L/2 gives the
+// conjugate of L - j) is exact for every L, the quarter points are exact, and an
+// L divisible by 8 takes the octant reduction of cos_sin, so powers of two get
+// exactly the entries of make_table_f64.
+void cos_sin_general(int64_t L, int64_t j, long double &c, long double &s)
+{
+    if (L % 8 == 0) {
+        cos_sin(L, j, c, s);
+        return;
+    }
+    if (2 * j > L) {
+        cos_sin_general(L, L - j, c, s);
+        s = -s;
+        return;
+    }
+    if (j == 0) {
+        c = 1.0L;
+        s = 0.0L;
+        return;
+    }
+    if (2 * j == L) {
+        c = -1.0L;
+        s = 0.0L;
+        return;
+    }
+    if (4 * j == L) {
+        c = 0.0L;
+        s = 1.0L;
+        return;
+    }
+    const long double th = 2.0L * 3.14159265358979323846264338327950288L * (long double)j / (long double)L;
+    c = cosl(th);
+    s = sinl(th);
+}
+
+// omega_T^j = exp(-2 pi i j / T), j in [T], interleaved FP64.
+std::vector<double> make_table_general(int64_t T)
+{
+    std::vector<double> t(size_t(2 * T));
+    for (int64_t j = 0; j < T; ++j) {
+        long double c, s;
+        cos_sin_general(T, j, c, s);
+        t[size_t(2 * j)] = double(c);
+        t[size_t(2 * j + 1)] = -double(s);
+    }
+    return t;
+}
+
+// Radix stages of a mixed-radix line: 8s, then a 4 or a 2, then 7s, 5s, 3s.
+int mixed_radices(int64_t L, int32_t *out)
+{
+    int n = 0;
+    while (L % 8 == 0 && n < fftu::kMixedMaxStages) {
+        out[n++] = 8;
+        L /= 8;
+    }
+    if (L % 4 == 0) {
+        out[n++] = 4;
+        L /= 4;
+    }
+    if (L % 2 == 0) {
+        out[n++] = 2;
+        L /= 2;
+    }
+    for (int f : {7, 5, 3})
+        while (L % f == 0 && n < fftu::kMixedMaxStages) {
+            out[n++] = f;
+            L /= f;
+        }
+    return L == 1 ? n : -1;
+}
+
+bool make_mixed_pass(int64_t A, int64_t L, int64_t B, fftu_dtype dt, int64_t T, fftu::MixedPassDesc &pd)
+{
+    pd = fftu::MixedPassDesc{};
+    const int64_t esize = dt == FFTU_C128 ? 16 : 8;
+    const int64_t cap = 64 * 1024;
+    pd.nstages = mixed_radices(L, pd.radix);
+    if (pd.nstages < 0) return false;
+    const int64_t target = dt == FFTU_C128 ? 1024 : 2048;   // elements per tile
+    int64_t W = 1;
+    while (W * 2 * L <= target && W < 256) W *= 2;
+    const int64_t span = B > 1 ? B : A;
+    while (W > 1 && W / 2 >= span) W /= 2;                   // no tile much wider than the lines it can hold
+    while (W > 1 && (2 * W * L + L) * esize > cap) W /= 2;
+    if ((2 * W * L + L) * esize > cap) return false;
+    pd.A = A;
+    pd.B = B;
+    pd.L = int32_t(L);
+    pd.W = int32_t(W);
+    pd.logW = ilog2(W);
+    if (B > 1) {
+        pd.nbt = (B + W - 1) / W;
+        pd.tiles = A * pd.nbt;
+    } else {
+        pd.nbt = 1;
+        pd.tiles = (A + W - 1) / W;
+    }
+    pd.tstep = T / L;
+    pd.scale = 1.0;
+    pd.lds_bytes = uint32_t((2 * W * L + L) * esize);
+    return true;
+}
+
+struct MixedPlan {
+    std::vector<fftu::MixedPassDesc> s0, s2;
+    fftu::MixedGridDesc g{};
+    int64_t T = 1;
+};
+
+bool plan_mixed(int d, const int64_t n[], const int64_t p[], fftu_dtype dt, MixedPlan &mp)
+{
+    mp = MixedPlan{};
+    fftu::MixedGridDesc &g = mp.g;
+    g.d = d;
+    g.N = 1;
+    g.P = 1;
+    for (int l = 0; l < d; ++l) {
+        g.n[l] = int32_t(n[l]);
+        g.p[l] = int32_t(p[l]);
+        g.m[l] = int32_t(n[l] / p[l]);
+        g.q[l] = int32_t(n[l] / p[l] / p[l]);
+        g.N *= n[l];
+        g.P *= p[l];
+        mp.T = lcm64(mp.T, n[l]);
+    }
+    g.M = g.N / g.P;
+    g.T = mp.T;
+    for (int l = 0; l < d; ++l) g.tstep[l] = mp.T / n[l];
+    g.scale = 1.0;
+    // Superstep 0: one pass per local dimension, innermost first: (P prod_{j<l} m_j, m_l, prod_{j>l} m_j).
+    for (int l = d - 1; l >= 0; --l) {
+        if (g.m[l] == 1) continue;
+        int64_t A = g.P, B = 1;
+        for (int j = 0; j < l; ++j) A *= g.m[j];
+        for (int j = l + 1; j < d; ++j) B *= g.m[j];
+        fftu::MixedPassDesc pd;
+        if (!make_mixed_pass(A, g.m[l], B, dt, mp.T, pd)) return false;
+        mp.s0.push_back(pd);
+    }
+    // Superstep 2: local index k_l = t_l + k'_l q_l, lines along k'_l:
+    // (P prod_{j<l} m_j, p_l, q_l prod_{j>l} m_j).
+    for (int l = d - 1; l >= 0; --l) {
+        if (g.p[l] == 1) continue;
+        int64_t A = g.P, B = g.q[l];
+        for (int j = 0; j < l; ++j) A *= g.m[j];
+        for (int j = l + 1; j < d; ++j) B *= g.m[j];
+        fftu::MixedPassDesc pd;
+        if (!make_mixed_pass(A, g.p[l], B, dt, mp.T, pd)) return false;
+        mp.s2.push_back(pd);
+    }
+    return true;
+}
+
+void fill_info_mixed(const MixedPlan &mp, fftu_dtype dt, fftu_plan_info *info)
+{
+    const uint64_t esize = dt == FFTU_C128 ? 16 : 8;
+    *info = fftu_plan_info{};
+    info->d = mp.g.d;
+    info->N = mp.g.N;
+    info->P = mp.g.P;
+    info->M = mp.g.M;
+    info->s0_kernels = int32_t(mp.s0.size());
+    info->exchange_fused = 0;
+    info->s2_kernels = int32_t(2 + mp.s2.size());
+    info->launches = info->s0_kernels + info->s2_kernels;
+    info->workspace_bytes = uint64_t(mp.g.N) * esize;
+    info->table_bytes = uint64_t(mp.T) * esize;
+}
+
 void fill_info(const Geometry &G, const std::vector<PassDesc> &s0, bool fused, size_t nS2, fftu_dtype dt,
                fftu_plan_info *info)
 {
@@ -704,6 +926,52 @@ hipError_t upload_table(void **ptr, int logK, fftu_dtype dtype)
     return e;
 }
 
+hipError_t upload_table_general(void **ptr, int64_t T, fftu_dtype dtype)
+{
+    const std::vector<double> t64 = make_table_general(T);
+    const uint64_t bytes = uint64_t(T) * (dtype == FFTU_C128 ? 16 : 8);
+    hipError_t e = hipMalloc(ptr, bytes);
+    if (e != hipSuccess) return e;
+    if (dtype == FFTU_C128) {
+        e = hipMemcpy(*ptr, t64.data(), bytes, hipMemcpyHostToDevice);
+    } else {
+        std::vector<float> t32(t64.size());
+        for (size_t i = 0; i < t64.size(); ++i) t32[i] = float(t64[i]);   // rounded once
+        e = hipMemcpy(*ptr, t32.data(), bytes, hipMemcpyHostToDevice);
+    }
+    if (e != hipSuccess) {
+        (void)hipFree(*ptr);
+        *ptr = nullptr;
+    }
+    return e;
+}
+
+// Shared tables of mixed-radix external plans: one per (device, precision, T), exact T.
+struct SharedTableT {
+    int device;
+    Precision prec;
+    int64_t T;
+    void *ptr;
+};
+std::vector<SharedTableT> g_tables_T;
+
+hipError_t shared_table_exact(int device, fftu_dtype dtype, int64_t T, void **ptr)
+{
+    const Precision prec = dtype == FFTU_C128 ? Precision::F64 : Precision::F32;
+    std::lock_guard<std::mutex> lock(g_tables_mutex);
+    for (const SharedTableT &t : g_tables_T)
+        if (t.device == device && t.prec == prec && t.T == T) {
+            *ptr = t.ptr;
+            return hipSuccess;
+        }
+    void *p = nullptr;
+    hipError_t e = upload_table_general(&p, T, dtype);
+    if (e != hipSuccess) return e;
+    g_tables_T.push_back({device, prec, T, p});
+    *ptr = p;
+    return hipSuccess;
+}
+
 hipError_t shared_table(int device, fftu_dtype dtype, int need_log, void **ptr, int *logK)
 {
     const Precision prec = dtype == FFTU_C128 ? Precision::F64 : Precision::F32;
@@ -726,6 +994,65 @@ hipError_t shared_table(int device, fftu_dtype dtype, int need_log, void **ptr, 
     return hipSuccess;
 }
 
+fftu_plan_s *build_mixed_plan(int d, const int64_t n[], const int64_t p[], fftu_dtype dtype, fftu_direction direction,
+                              bool external, int device)
+{
+    MixedPlan mp;
+    if (!plan_mixed(d, n, p, dtype, mp)) {
+        record(FFTU_ERROR_UNSUPPORTED);
+        return nullptr;
+    }
+    fftu_plan_s *pl = new (std::nothrow) fftu_plan_s();
+    if (!pl) {
+        record(FFTU_ERROR_OUT_OF_MEMORY);
+        return nullptr;
+    }
+    pl->d = d;
+    for (int l = 0; l < d; ++l) {
+        pl->n[l] = n[l];
+        pl->p[l] = p[l];
+    }
+    pl->dtype = dtype;
+    pl->dir = direction;
+    pl->prec = dtype == FFTU_C128 ? Precision::F64 : Precision::F32;
+    pl->esize = dtype == FFTU_C128 ? 16 : 8;
+    pl->device = device;
+    pl->external = external;
+    pl->mixed = true;
+    pl->ms0 = mp.s0;
+    pl->ms2 = mp.s2;
+    pl->mg = mp.g;
+    pl->table_T = mp.T;
+    pl->grid.N = mp.g.N;
+    pl->grid.M = mp.g.M;
+    pl->grid.d = d;
+    pl->launches = int(mp.s0.size() + 2 + mp.s2.size());
+    const std::string t = dtype == FFTU_C128 ? "double" : "float";
+    for (size_t i = 0; i < mp.s0.size(); ++i) pl->launch_names.push_back("fftu::k_mline<" + t + ">");
+    pl->launch_names.push_back("fftu::k_mtwiddle<" + t + ">");
+    pl->launch_names.push_back("fftu::k_mpermute<" + t + ">");
+    for (size_t i = 0; i < mp.s2.size(); ++i) pl->launch_names.push_back("fftu::k_mline<" + t + ">");
+    hipError_t e = hipSuccess;
+    if (external) {
+        e = shared_table_exact(device, dtype, mp.T, &pl->table);
+    } else {
+        pl->table_bytes = uint64_t(mp.T) * pl->esize;
+        pl->ws_bytes = uint64_t(mp.g.N) * pl->esize;
+        e = upload_table_general(&pl->table, mp.T, dtype);
+        if (e == hipSuccess) e = hipMalloc(&pl->ws, pl->ws_bytes);
+    }
+    if (e != hipSuccess) {
+        const fftu_status st = from_hip(e);
+        if (!external && pl->table) (void)hipFree(pl->table);
+        if (pl->ws) (void)hipFree(pl->ws);
+        delete pl;
+        record(st);
+        return nullptr;
+    }
+    record(FFTU_SUCCESS);
+    return pl;
+}
+
 fftu_plan_s *build_plan(int d, const int64_t n[], const int64_t p[], fftu_dtype dtype, fftu_direction direction,
                         bool external)
 {
@@ -739,6 +1066,7 @@ fftu_plan_s *build_plan(int d, const int64_t n[], const int64_t p[], fftu_dtype 
         record(FFTU_ERROR_DEVICE);
         return nullptr;
     }
+    if (plan_is_mixed(d, n, p)) return build_mixed_plan(d, n, p, dtype, direction, external, device);
     Geometry G = geometry(d, n, p);
     void *shared = nullptr;
     if (external) {
@@ -859,6 +1187,12 @@ fftu_status fftu_describe(int d, const int64_t n[], const int64_t p[], fftu_dtyp
     fftu_status s = validate(d, n, p, dtype, direction);
     if (s != FFTU_SUCCESS) return record(s);
     if (!info) return record(FFTU_ERROR_INVALID_VALUE);
+    if (plan_is_mixed(d, n, p)) {
+        MixedPlan mp;
+        if (!plan_mixed(d, n, p, dtype, mp)) return record(FFTU_ERROR_UNSUPPORTED);
+        fill_info_mixed(mp, dtype, info);
+        return record(FFTU_SUCCESS);
+    }
     const Geometry G = geometry(d, n, p);
     const auto s0 = plan_s0(G, dtype);
     ExchangeSplit sp;
@@ -892,6 +1226,7 @@ fftu_status build_batch_worklist(int count, const int d[], const int64_t *const 
     for (int f = 0; f < count; ++f) {
         fftu_status s = validate(d[f], n[f], p[f], dtype, direction);
         if (s != FFTU_SUCCESS) return s;
+        if (plan_is_mixed(d[f], n[f], p[f])) return FFTU_ERROR_UNSUPPORTED;   // batches: powers of two only
     }
     const size_t esize = dtype == FFTU_C128 ? 16 : 8;
     const int inv = direction == FFTU_INVERSE ? 1 : 0;
@@ -1169,6 +1504,15 @@ void fftu_graph_destroy(fftu_graph_t graph)
 fftu_status fftu_get_plan_info(fftu_plan_t plan, fftu_plan_info *info)
 {
     if (!plan || !info) return record(FFTU_ERROR_INVALID_VALUE);
+    if (plan->mixed) {
+        MixedPlan mp;
+        mp.s0 = plan->ms0;
+        mp.s2 = plan->ms2;
+        mp.g = plan->mg;
+        mp.T = plan->table_T;
+        fill_info_mixed(mp, plan->dtype, info);
+        return record(FFTU_SUCCESS);
+    }
     const Geometry G = geometry(plan->d, plan->n, plan->p);
     fill_info(G, plan->s0, plan->fused, plan->s2.size(), plan->dtype, info);
     return record(FFTU_SUCCESS);
@@ -1261,11 +1605,71 @@ namespace {
 // The transform of `plan` with workspace `ws`; mul (optional) multiplies the
 // output pointwise (fused into the exchange, or a separate pass when the
 // exchange is not fused).
+// Mixed-radix passes from `in` into `out` (the first reads in, the rest work in
+// place on out); conj on the chain's first load and last store, scale on the last.
+fftu_status run_mixed_passes(const fftu_plan_s *pl, const std::vector<fftu::MixedPassDesc> &passes, const void *in,
+                             void *out, int conj_first, int conj_last, double scale_last, hipStream_t stream,
+                             Marker *mk = nullptr)
+{
+    if (passes.empty()) {
+        if (in != out)
+            return from_hip(hipMemcpyAsync(out, in, size_t(pl->mg.N) * pl->esize, hipMemcpyDeviceToDevice, stream));
+        return FFTU_SUCCESS;
+    }
+    const void *src = in;
+    for (size_t i = 0; i < passes.size(); ++i) {
+        fftu::MixedPassDesc pd = passes[i];
+        pd.conj_in = (i == 0) ? conj_first : 0;
+        pd.conj_out = (i + 1 == passes.size()) ? conj_last : 0;
+        pd.scale = (i + 1 == passes.size()) ? scale_last : 1.0;
+        hipError_t e = fftu::launch_mline(pl->prec, src, out, pd, pl->table, stream);
+        if (e != hipSuccess) return from_hip(e);
+        if (mk) mk->mark();
+        src = out;
+    }
+    return FFTU_SUCCESS;
+}
+
+// The mixed-radix transform: Superstep 0 passes (in -> ws, then in place), the
+// twiddle (in place on ws), the permutation (ws -> out), Superstep 2 passes in
+// place on out; conj(F(conj x))/N for the inverse; mul as in execute_with.
+fftu_status execute_mixed(fftu_plan_s *plan, const void *in, void *out, void *ws, hipStream_t stream,
+                          const void *mul, Marker &mk)
+{
+    const int inv = plan->dir == FFTU_INVERSE ? 1 : 0;
+    const double scale = inv ? 1.0 / double(plan->mg.N) : 1.0;
+    fftu_status s = run_mixed_passes(plan, plan->ms0, in, ws, inv, 0, 1.0, stream, &mk);
+    if (s != FFTU_SUCCESS) return s;
+    fftu::MixedGridDesc g = plan->mg;
+    g.conj_in = g.conj_out = 0;
+    g.scale = 1.0;
+    hipError_t e = fftu::launch_mtwiddle(plan->prec, ws, ws, g, plan->table, stream);
+    if (e != hipSuccess) return from_hip(e);
+    mk.mark();
+    if (plan->ms2.empty()) {
+        g.conj_out = inv;
+        g.scale = scale;
+    }
+    e = fftu::launch_mpermute(plan->prec, ws, out, g, stream);
+    if (e != hipSuccess) return from_hip(e);
+    mk.mark();
+    if (!plan->ms2.empty()) {
+        s = run_mixed_passes(plan, plan->ms2, out, out, 0, inv, scale, stream, &mk);
+        if (s != FFTU_SUCCESS) return s;
+    }
+    if (!mul) return FFTU_SUCCESS;
+    return from_hip(fftu::launch_pointwise(plan->prec, out, mul, out, plan->mg.N, 1.0, stream));
+}
+
 fftu_status execute_with(fftu_plan_s *plan, const void *in, void *out, void *ws, hipStream_t stream, const void *mul)
 {
     fftu_status s = check_exec_args(plan, in, out);
     if (s != FFTU_SUCCESS) return s;
     Marker mk(plan, stream);
+    if (plan->mixed) {
+        mk.mark();
+        return execute_mixed(plan, in, out, ws, stream, mul, mk);
+    }
     mk.mark();
     const int inv = plan->dir == FFTU_INVERSE ? 1 : 0;
     const double scale = inv ? 1.0 / double(plan->grid.N) : 1.0;
@@ -1368,6 +1772,7 @@ fftu_status fftu_stage_local_fft(fftu_plan_t plan, const void *in, void *out, hi
     fftu_status s = check_exec_args(plan, in, out);
     if (s != FFTU_SUCCESS) return record(s);
     const int inv = plan->dir == FFTU_INVERSE ? 1 : 0;
+    if (plan->mixed) return record(run_mixed_passes(plan, plan->ms0, in, out, inv, inv, 1.0, stream));
     return record(run_passes(plan, plan->s0, in, out, inv, inv, 1.0, stream));
 }
 
@@ -1375,6 +1780,12 @@ fftu_status fftu_stage_twiddle(fftu_plan_t plan, const void *in, void *out, hipS
 {
     fftu_status s = check_exec_args(plan, in, out);
     if (s != FFTU_SUCCESS) return record(s);
+    if (plan->mixed) {
+        fftu::MixedGridDesc mg = plan->mg;
+        mg.conj_in = mg.conj_out = plan->dir == FFTU_INVERSE ? 1 : 0;
+        mg.scale = 1.0;
+        return record(from_hip(fftu::launch_mtwiddle(plan->prec, in, out, mg, plan->table, stream)));
+    }
     GridDesc g = plan->grid;
     g.conj_in = g.conj_out = plan->dir == FFTU_INVERSE ? 1 : 0;
     return record(from_hip(fftu::launch_twiddle(plan->prec, in, out, g, plan->table, stream)));
@@ -1385,6 +1796,12 @@ fftu_status fftu_stage_exchange(fftu_plan_t plan, const void *in, void *out, hip
     fftu_status s = check_exec_args(plan, in, out);
     if (s != FFTU_SUCCESS) return record(s);
     if (in == out) return record(FFTU_ERROR_INVALID_VALUE);
+    if (plan->mixed) {
+        fftu::MixedGridDesc mg = plan->mg;
+        mg.conj_in = mg.conj_out = 0;
+        mg.scale = 1.0;
+        return record(from_hip(fftu::launch_mpermute(plan->prec, in, out, mg, stream)));
+    }
     return record(from_hip(fftu::launch_permute(plan->prec, in, out, plan->grid, stream)));
 }
 
@@ -1393,6 +1810,7 @@ fftu_status fftu_stage_remaining_fft(fftu_plan_t plan, const void *in, void *out
     fftu_status s = check_exec_args(plan, in, out);
     if (s != FFTU_SUCCESS) return record(s);
     const int inv = plan->dir == FFTU_INVERSE ? 1 : 0;
+    if (plan->mixed) return record(run_mixed_passes(plan, plan->ms2, in, out, inv, inv, 1.0, stream));
     return record(run_passes(plan, plan->s2, in, out, inv, inv, 1.0, stream));
 }
 

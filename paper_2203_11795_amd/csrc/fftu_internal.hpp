@@ -97,6 +97,38 @@ struct ExchangeDesc {
     const void *mul;       // null, or N elements in the output layout that every output is multiplied by
 };
 
+// Mixed-radix path (fftu_mixed.hip): sides with factors 2, 3, 5 and 7.
+constexpr int kMixedThreads = 256;
+constexpr int kMixedMaxStages = 24;
+
+// A pass of 1-D FFTs of length L over an array viewed as (A, L, B), B the
+// stride of a line. A tile holds W lines (a power of two): W consecutive b of
+// one a when B > 1, W consecutive a when B = 1.
+struct MixedPassDesc {
+    int64_t A, B;
+    int64_t tiles;         // A * nbt (B > 1), ceil(A / W) (B = 1)
+    int64_t nbt;           // tiles along b: ceil(B / W) (B > 1)
+    int32_t L;
+    int32_t W, logW;
+    int32_t nstages;
+    int32_t radix[kMixedMaxStages];
+    int64_t tstep;         // T / L: omega_L^j = table[j tstep], table = omega_T
+    int32_t conj_in, conj_out;
+    double scale;
+    uint32_t lds_bytes;
+};
+
+// Geometry for the twiddle and the permutation of the mixed-radix path.
+struct MixedGridDesc {
+    int32_t d;
+    int64_t N, M, P;
+    int32_t n[kMaxDims], p[kMaxDims], m[kMaxDims], q[kMaxDims];
+    int64_t tstep[kMaxDims];   // T / n_l
+    int64_t T;
+    int32_t conj_in, conj_out;
+    double scale;
+};
+
 // Persistent batch (fftu_batch.hip). One descriptor per (stage, transform).
 constexpr int kBatchThreads = 256;
 constexpr int kBatchMaxLogLine = 8;     // longest Superstep-0 line of a batched transform: 2^8
@@ -155,6 +187,11 @@ hipError_t launch_line(Precision prec, const void *in, void *out, const PassDesc
 hipError_t launch_group2(Precision prec, const void *in, void *out, const PassDesc &pd, const void *table,
                          hipStream_t stream);
 hipError_t launch_batch_reset(const BatchDesc &bd, hipStream_t stream);   // counters to zero (a kernel)
+hipError_t launch_mline(Precision prec, const void *in, void *out, const MixedPassDesc &pd, const void *table,
+                        hipStream_t stream);
+hipError_t launch_mtwiddle(Precision prec, const void *in, void *out, const MixedGridDesc &g, const void *table,
+                           hipStream_t stream);
+hipError_t launch_mpermute(Precision prec, const void *in, void *out, const MixedGridDesc &g, hipStream_t stream);
 hipError_t launch_pointwise(Precision prec, const void *a, const void *b, void *out, int64_t count, double scale,
                             hipStream_t stream);
 hipError_t launch_fill_uniform(Precision prec, void *out, int64_t count, uint32_t k0, uint32_t k1, uint64_t base,

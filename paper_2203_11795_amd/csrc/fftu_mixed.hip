@@ -1,0 +1,264 @@
+// Mixed-radix path of Algorithm 2.3 (arXiv 2203.11795) for sides whose prime
+// factors are 2, 3, 5 and 7: the method itself only needs p_l^2 | n_l. (The
+// paper's own code leaves the local FFTs to FFTW, which handles any size.)
+//
+//   k_mline      a pass of 1-D FFTs of length L (Superstep 0 along one local
+//                dimension, or Superstep 2 along one grid dimension). W lines
+//                are loaded into LDS, transformed by mixed-radix Stockham
+//                stages (radix 8, 4, 2, 7, 5, 3; stage s with radix R after
+//                Ns points reads j + r L/R, twiddles by omega_{Ns R}^{r (j mod Ns)}
+//                and writes (j div Ns) Ns R + j mod Ns + r Ns), ping-ponging
+//                between two LDS buffers, and stored. Roots come from an LDS
+//                copy of omega_L taken from the plan's FP64-generated table of
+//                omega_T, T = lcm(n_l).
+//   k_mtwiddle   Superstep 0's twiddle Z^(s)[k] = prod_l omega_{n_l}^{k_l s_l} Y^(s)[k],
+//                the exponent reduced exactly in integers (one table entry).
+//   k_mpermute   Superstep 1: W^(r)[s q + t] = Z^(s)[r + t p], per output element.
+//
+// The index arithmetic uses 32-bit divisions by runtime sizes, so this path
+// takes N < 2^31. Loops that hold barriers run on wave-uniform values.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "fftu_device.hpp"
+#include "fftu_internal.hpp"
+
+namespace fftu {
+
+namespace {
+
+// DFT of size R on registers x[0..R-1]: radix 2, 4, 8 with constant roots; 3, 5,
+// 7 from the roots omega_R^m = tw[m L / R] (tw = omega_L in LDS).
+template <typename T, int R>
+__device__ __forceinline__ void dft_small(cx<T> (&x)[8], const cx<T> *tw, int LperR)
+{
+    if constexpr (R == 2 || R == 4 || R == 8) {
+        Dft<T, R>::run(x);
+    } else {
+        cx<T> y[R];
+#pragma unroll
+        for (int c = 0; c < R; ++c) {
+            cx<T> acc = x[0];
+#pragma unroll
+            for (int r = 1; r < R; ++r) acc = acc + cmul(x[r], tw[((r * c) % R) * LperR]);
+            y[c] = acc;
+        }
+#pragma unroll
+        for (int c = 0; c < R; ++c) x[c] = y[c];
+    }
+}
+
+// One Stockham stage of radix R over `lines` lines of length L (src -> dst in LDS).
+template <typename T, int R>
+__device__ __forceinline__ void mixed_stage(const cx<T> *src, cx<T> *dst, const cx<T> *tw, int L, int Ns, int lines,
+                                            int tid, int nt)
+{
+    const int LR = L / R;
+    const int span = L / (Ns * R);          // omega_{Ns R} = omega_L^span
+    const int nb = lines * LR;
+    for (int bi = tid; bi < nb; bi += nt) {
+        const int w = bi / LR;
+        const int j = bi - w * LR;
+        const int jd = j / Ns;
+        const int k = j - jd * Ns;
+        const cx<T> *s = src + w * L + j;
+        cx<T> x[8];
+#pragma unroll
+        for (int r = 0; r < R; ++r) x[r] = s[r * LR];
+        if (Ns > 1) {
+#pragma unroll
+            for (int r = 1; r < R; ++r) x[r] = cmul(x[r], tw[r * k * span]);
+        }
+        dft_small<T, R>(x, tw, LR);
+        cx<T> *o = dst + w * L + jd * Ns * R + k;
+#pragma unroll
+        for (int r = 0; r < R; ++r) o[r * Ns] = x[r];
+    }
+}
+
+}  // namespace
+
+template <typename T>
+__global__ __launch_bounds__(kMixedThreads) void k_mline(const cx<T> *in, cx<T> *out, const MixedPassDesc pd,
+                                                         const cx<T> *__restrict__ table)
+{
+    extern __shared__ unsigned char smem_raw[];
+    const int L = pd.L, W = pd.W;
+    cx<T> *tw = reinterpret_cast<cx<T> *>(smem_raw);
+    cx<T> *buf0 = tw + L;
+    cx<T> *buf1 = buf0 + W * L;
+    const int tid = threadIdx.x;
+    // launch sizes in scalar registers: the tile loop holds barriers
+    const int nt = __builtin_amdgcn_readfirstlane(int(blockDim.x));
+    const int64_t nblocks = __builtin_amdgcn_readfirstlane(int(gridDim.x));
+    for (int j = tid; j < L; j += nt) tw[j] = table[int64_t(j) * pd.tstep];
+    const T scale = static_cast<T>(pd.scale);
+    for (int64_t t = blockIdx.x; t < pd.tiles; t += nblocks) {
+        // tile origin and the number of lines it holds (wave-uniform)
+        int64_t a0, b0;
+        int lines;
+        if (pd.B > 1) {
+            a0 = t / pd.nbt;
+            b0 = (t - a0 * pd.nbt) << pd.logW;
+            lines = int(pd.B - b0 < W ? pd.B - b0 : W);
+        } else {
+            a0 = t << pd.logW;
+            b0 = 0;
+            lines = int(pd.A - a0 < W ? pd.A - a0 : W);
+        }
+        __syncthreads();   // twiddle copy done / previous tile's LDS reads done
+        const int n = lines * L;
+        for (int e = tid; e < n; e += nt) {
+            int x, w;
+            int64_t addr;
+            if (pd.B > 1) {
+                x = e / lines;
+                w = e - x * lines;
+                addr = (a0 * L + x) * pd.B + b0 + w;   // lanes run over b: runs of `lines` elements
+            } else {
+                w = e / L;
+                x = e - w * L;
+                addr = a0 * L + e;                     // W whole lines, contiguous
+            }
+            buf0[w * L + x] = conj_if(in[addr], pd.conj_in);
+        }
+        __syncthreads();
+        cx<T> *src = buf0, *dst = buf1;
+        int Ns = 1;
+        for (int s = 0; s < pd.nstages; ++s) {
+            switch (pd.radix[s]) {
+            case 2: mixed_stage<T, 2>(src, dst, tw, L, Ns, lines, tid, nt); break;
+            case 3: mixed_stage<T, 3>(src, dst, tw, L, Ns, lines, tid, nt); break;
+            case 4: mixed_stage<T, 4>(src, dst, tw, L, Ns, lines, tid, nt); break;
+            case 5: mixed_stage<T, 5>(src, dst, tw, L, Ns, lines, tid, nt); break;
+            case 7: mixed_stage<T, 7>(src, dst, tw, L, Ns, lines, tid, nt); break;
+            case 8: mixed_stage<T, 8>(src, dst, tw, L, Ns, lines, tid, nt); break;
+            default: break;
+            }
+            __syncthreads();
+            cx<T> *tmp = src;
+            src = dst;
+            dst = tmp;
+            Ns *= pd.radix[s];
+        }
+        for (int e = tid; e < n; e += nt) {
+            int x, w;
+            int64_t addr;
+            if (pd.B > 1) {
+                x = e / lines;
+                w = e - x * lines;
+                addr = (a0 * L + x) * pd.B + b0 + w;
+            } else {
+                w = e / L;
+                x = e - w * L;
+                addr = a0 * L + e;
+            }
+            cx<T> v = conj_if(src[w * L + x], pd.conj_out);
+            if (pd.scale != 1.0) v = {v.x * scale, v.y * scale};
+            out[addr] = v;
+        }
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_mtwiddle(const cx<T> *in, cx<T> *out, const MixedGridDesc g,
+                                                  const cx<T> *__restrict__ table)
+{
+    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < g.N; i += stride) {
+        uint32_t rank = uint32_t(i / g.M);
+        uint32_t k = uint32_t(i - int64_t(rank) * g.M);
+        int64_t e = 0;
+        for (int l = g.d - 1; l >= 0; --l) {
+            const uint32_t sl = rank % uint32_t(g.p[l]);
+            rank /= uint32_t(g.p[l]);
+            const uint32_t kl = k % uint32_t(g.m[l]);
+            k /= uint32_t(g.m[l]);
+            e += int64_t(kl) * sl * g.tstep[l];      // k_l s_l < n_l, times T / n_l: below T
+        }
+        cx<T> v = conj_if(in[i], g.conj_in);
+        v = cmul(v, table[e % g.T]);
+        out[i] = conj_if(v, g.conj_out);
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_mpermute(const cx<T> *in, cx<T> *out, const MixedGridDesc g)
+{
+    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    const T scale = static_cast<T>(g.scale);
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < g.N; i += stride) {
+        uint32_t r = uint32_t(i / g.M);
+        uint32_t j = uint32_t(i - int64_t(r) * g.M);
+        int64_t src_rank = 0, src_k = 0, rmul = 1, kmul = 1;
+        for (int l = g.d - 1; l >= 0; --l) {
+            const uint32_t jl = j % uint32_t(g.m[l]);
+            j /= uint32_t(g.m[l]);
+            const uint32_t rl = r % uint32_t(g.p[l]);
+            r /= uint32_t(g.p[l]);
+            const uint32_t sl = jl / uint32_t(g.q[l]);          // j_l = s_l q_l + t_l
+            const uint32_t tl = jl - sl * uint32_t(g.q[l]);
+            src_rank += int64_t(sl) * rmul;
+            src_k += (int64_t(rl) + int64_t(tl) * g.p[l]) * kmul;  // k_l = r_l + t_l p_l
+            rmul *= g.p[l];
+            kmul *= g.m[l];
+        }
+        cx<T> v = conj_if(in[src_rank * g.M + src_k], g.conj_in);
+        v = conj_if(v, g.conj_out);
+        if (g.scale != 1.0) v = {v.x * scale, v.y * scale};
+        out[i] = v;
+    }
+}
+
+namespace {
+
+uint32_t grid_for(int64_t count)
+{
+    const int64_t want = (count + 255) / 256;
+    return uint32_t(want < (int64_t(1) << 18) ? (want > 0 ? want : 1) : (int64_t(1) << 18));
+}
+
+}  // namespace
+
+hipError_t launch_mline(Precision prec, const void *in, void *out, const MixedPassDesc &pd, const void *table,
+                        hipStream_t stream)
+{
+    const uint32_t blocks = uint32_t(pd.tiles < (int64_t(1) << 20) ? pd.tiles : (int64_t(1) << 20));
+    if (prec == Precision::F64)
+        hipLaunchKernelGGL(k_mline<double>, dim3(blocks), dim3(kMixedThreads), pd.lds_bytes, stream,
+                           static_cast<const cx<double> *>(in), static_cast<cx<double> *>(out), pd,
+                           static_cast<const cx<double> *>(table));
+    else
+        hipLaunchKernelGGL(k_mline<float>, dim3(blocks), dim3(kMixedThreads), pd.lds_bytes, stream,
+                           static_cast<const cx<float> *>(in), static_cast<cx<float> *>(out), pd,
+                           static_cast<const cx<float> *>(table));
+    return hipGetLastError();
+}
+
+hipError_t launch_mtwiddle(Precision prec, const void *in, void *out, const MixedGridDesc &g, const void *table,
+                           hipStream_t stream)
+{
+    if (prec == Precision::F64)
+        hipLaunchKernelGGL(k_mtwiddle<double>, dim3(grid_for(g.N)), dim3(256), 0, stream,
+                           static_cast<const cx<double> *>(in), static_cast<cx<double> *>(out), g,
+                           static_cast<const cx<double> *>(table));
+    else
+        hipLaunchKernelGGL(k_mtwiddle<float>, dim3(grid_for(g.N)), dim3(256), 0, stream,
+                           static_cast<const cx<float> *>(in), static_cast<cx<float> *>(out), g,
+                           static_cast<const cx<float> *>(table));
+    return hipGetLastError();
+}
+
+hipError_t launch_mpermute(Precision prec, const void *in, void *out, const MixedGridDesc &g, hipStream_t stream)
+{
+    if (prec == Precision::F64)
+        hipLaunchKernelGGL(k_mpermute<double>, dim3(grid_for(g.N)), dim3(256), 0, stream,
+                           static_cast<const cx<double> *>(in), static_cast<cx<double> *>(out), g);
+    else
+        hipLaunchKernelGGL(k_mpermute<float>, dim3(grid_for(g.N)), dim3(256), 0, stream,
+                           static_cast<const cx<float> *>(in), static_cast<cx<float> *>(out), g);
+    return hipGetLastError();
+}
+
+}  // namespace fftu

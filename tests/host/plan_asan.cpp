@@ -28,6 +28,9 @@ hipError_t launch_exchange(Precision, const void *, void *, const ExchangeDesc &
 hipError_t launch_batch_reset(const BatchDesc &, hipStream_t) { return hipSuccess; }
 hipError_t launch_fill_uniform(Precision, void *, int64_t, uint32_t, uint32_t, uint64_t, hipStream_t) { return hipSuccess; }
 hipError_t launch_pointwise(Precision, const void *, const void *, void *, int64_t, double, hipStream_t) { return hipSuccess; }
+hipError_t launch_mline(Precision, const void *, void *, const MixedPassDesc &, const void *, hipStream_t) { return hipSuccess; }
+hipError_t launch_mtwiddle(Precision, const void *, void *, const MixedGridDesc &, const void *, hipStream_t) { return hipSuccess; }
+hipError_t launch_mpermute(Precision, const void *, void *, const MixedGridDesc &, hipStream_t) { return hipSuccess; }
 hipError_t launch_batch(Precision, const BatchDesc &bd, const void *, uint32_t, uint32_t, hipStream_t)
 {
     if (bd.nstages < 1 || bd.nitems < 1) std::abort();
@@ -176,6 +179,8 @@ int main()
         {{512, 512, 512}, {4, 4, 4}}, {{64, 64, 64}, {8, 8, 2}}, {{4, 4, 4, 4, 4, 4, 4, 4}, {2, 2, 2, 2, 2, 2, 2, 2}},
         {{1024, 1024, 1024}, {32, 32, 32}}, {{1}, {1}}, {{2048}, {1}}, {{4096}, {64}}, {{64, 64, 64, 64, 64}, {2, 2, 2, 2, 2}},
         {{16, 16}, {4, 4}}, {{8, 1, 4}, {2, 1, 1}}, {{1 << 22, 64}, {2048, 8}}, {{256, 256, 256, 256}, {16, 16, 16, 16}},
+        // mixed radix (factors 2, 3, 5, 7), and one side with a factor 11 (unsupported)
+        {{60, 60}, {2, 2}}, {{49, 27, 8}, {7, 3, 2}}, {{1000}, {10}}, {{126, 12, 1}, {3, 2, 1}}, {{44, 12}, {2, 2}},
     };
     int bad = 0;
     for (const Case &c : cases) {

@@ -47,7 +47,10 @@ def test_version_and_status_strings():
     ((16,), (4,), 0),            # p^2 = n: q = 1
     ((8,), (4,), 2),             # 16 does not divide 8
     ((32, 32), (2, 8), 2),
-    ((12,), (2,), 3),            # p^2 | n holds, but 12 is not a power of two
+    ((12,), (2,), 0),            # mixed radix: 12 = 4 * 3
+    ((60, 36), (2, 3), 0),
+    ((44,), (2,), 3),            # p^2 | n holds, but 11 is not a radix of the mixed path
+    ((3 * 2048,), (1,), 3),      # mixed-radix line longer than one LDS tile (complex128)
     ((12,), (3,), 2),
     ((64,) * 9, (2,) * 9, 3),    # d > 8
     ((0,), (1,), 1),
@@ -102,6 +105,8 @@ def test_p_max_examples():
     ((64,) * 5, (2,) * 5, "complex64", 4, 1, 5),
     ((1024,) * 3, (16, 16, 16), "complex128", 3, 0, 8),
     ((1,), (1,), "complex128", 0, 1, 1),
+    ((60, 60), (2, 2), "complex128", 2, 0, 6),            # mixed radix: 2 passes, twiddle, permutation, 2 passes
+    ((49, 27, 8), (7, 3, 2), "complex64", 3, 0, 8),
 ])
 def test_describe(n, p, dtype, s0, fused, launches):
     info = fftu.describe(n, p, dtype)

@@ -1,0 +1,124 @@
+"""Mixed-radix path on the GPU (sides with prime factors 2, 3, 5, 7; grids with
+p_l^2 | n_l): the whole transform, each superstep against the oracle's
+emulation of Algorithm 2.3, external plans, convolution, and a full-size
+480^3 transform on sampled outputs."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import FORWARD, INVERSE
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"complex128": 1e-12, "complex64": 5e-6}
+NP = {"complex128": np.complex128, "complex64": np.complex64}
+
+CASES = [((12,), (2,)), ((36,), (3,)), ((100,), (5,)), ((1000,), (10,)), ((7,), (1,)), ((60, 60), (2, 2)),
+         ((126, 12), (3, 2)), ((49, 27), (7, 3)), ((18, 20, 12), (3, 2, 2)), ((96, 96), (4, 2)), ((45, 8), (3, 2)),
+         ((384,), (8,)), ((30, 30, 30), (1, 1, 1)), ((3072,), (4,))]
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available()
+    return t
+
+
+def say(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+@pytest.mark.parametrize("n,p", CASES)
+@pytest.mark.parametrize("dtype", ["complex64", "complex128"])
+@pytest.mark.parametrize("direction", [FORWARD, INVERSE])
+def test_mixed_transform_matches_oracle(torch, n, p, dtype, direction):
+    import paper_2203_11795_amd as fftu
+    N = int(np.prod(n))
+    D = synth.uniform_complex(N, 5, NP[dtype])
+    want = oracle.cyclic_dft(D.astype(np.complex128), n, p, direction)
+    with fftu.Plan(n, p, dtype, direction) as plan:
+        assert plan.info()["exchange_fused"] == 0 and "k_mline" in plan.launch_names()[0]
+        x = torch.from_numpy(D).cuda()
+        y = plan(x)
+        z = x.clone()
+        plan(z, z)                                         # in place
+        torch.cuda.synchronize()
+        got = y.cpu().numpy()
+        err = oracle.rel_l2(got.astype(np.complex128), want)
+        assert err <= TOL[dtype], (n, p, err)
+        assert torch.equal(y, z)
+        assert np.array_equal(x.cpu().numpy(), D)         # input unchanged
+
+
+@pytest.mark.parametrize("n,p", [((60, 60), (2, 2)), ((18, 20, 12), (3, 2, 2)), ((1000,), (10,))])
+@pytest.mark.parametrize("direction", [FORWARD, INVERSE])
+def test_mixed_stages_match_emulation(torch, n, p, direction):
+    import paper_2203_11795_amd as fftu
+    N = int(np.prod(n))
+    D = synth.uniform_complex(N, 6)
+    em = oracle.emulate(D, n, p, direction)
+    with fftu.Plan(n, p, "complex128", direction) as plan:
+        x = torch.from_numpy(D).cuda()
+        s0 = plan.stage("local_fft", x)
+        tw = plan.stage("twiddle", torch.from_numpy(em["S0"]).cuda())
+        ex = plan.stage("exchange", torch.from_numpy(em["twiddle"]).cuda())
+        s2 = plan.stage("remaining_fft", torch.from_numpy(em["S1"]).cuda())
+        torch.cuda.synchronize()
+        assert oracle.rel_l2(s0.cpu().numpy(), em["S0"]) <= 1e-12
+        assert oracle.rel_l2(tw.cpu().numpy(), em["twiddle"]) <= 1e-12
+        assert np.array_equal(ex.cpu().numpy(), em["S1"])                   # a permutation: bitwise
+        assert oracle.rel_l2(s2.cpu().numpy(), em["S2"]) <= 1e-12
+
+
+@pytest.mark.parametrize("dtype", ["complex64", "complex128"])
+def test_mixed_external_plan_and_convolution(torch, dtype):
+    import paper_2203_11795_amd as fftu
+    n, p = (60, 60), (2, 2)
+    N = 3600
+    x = synth.uniform_complex(N, 7, NP[dtype])
+    h = synth.uniform_complex(N, 8, NP[dtype])
+    dx = torch.from_numpy(x).cuda()
+    with fftu.Plan(n, p, dtype) as a, fftu.Plan(n, p, dtype, external=True) as b:
+        ws = torch.empty_like(dx)
+        assert b.device_bytes() == 0
+        assert torch.equal(a(dx), b(dx, workspace=ws))
+    X = oracle.from_cyclic(x.astype(np.complex128), n, p)
+    H = oracle.from_cyclic(h.astype(np.complex128), n, p)
+    want = oracle.circular_convolution(X, H)
+    with fftu.ConvolutionPlan(n, p, dtype) as conv:
+        hhat = conv(torch.from_numpy(h).cuda())
+        y = conv.convolve(dx, hhat)
+        got = oracle.from_cyclic(y.cpu().numpy().astype(np.complex128), n, p)
+        assert oracle.rel_l2(got, want) <= TOL[dtype]
+
+
+def test_mixed_full_size_sampled(torch):
+    """480^3 complex128 on a 4^3 grid (m = 120, q = 30; T = 480): outputs at
+    sampled indices against eq. (1.2) summed directly, and the round trip."""
+    import paper_2203_11795_amd as fftu
+    n, p = (480, 480, 480), (4, 4, 4)
+    N = 480 ** 3
+    say("480^3: generating input")
+    D = synth.uniform_complex(N, 9)
+    x = torch.from_numpy(D).cuda()
+    with fftu.Plan(n, p, "complex128") as fwd, fftu.Plan(n, p, "complex128", INVERSE) as inv:
+        y = fwd(x)
+        back = inv(y)
+        torch.cuda.synchronize()
+        err_rt = float(torch.linalg.vector_norm(back - x) / torch.linalg.vector_norm(x))
+        say(f"480^3 round trip rel-L2 {err_rt:.2e}")
+        assert err_rt <= 1e-12
+        X = oracle.from_cyclic(D, n, p)
+        rng = np.random.default_rng(3)
+        ks = [tuple(int(v) for v in rng.integers(0, 480, 3)) for _ in range(4)] + [(0, 0, 0), (479, 1, 240)]
+        flat = [np.ravel_multi_index(k, n) for k in ks]
+        want = oracle.dft_points(X, flat)
+        Y = oracle.from_cyclic(y.cpu().numpy(), n, p).reshape(-1)
+        got = Y[flat]
+        err = np.abs(got - want).max() / np.abs(want).max()
+        say(f"480^3 sampled max rel error {err:.2e}")
+        assert err <= 1e-12
