@@ -632,8 +632,7 @@ bool make_mixed_pass(int64_t A, int64_t L, int64_t B, fftu_dtype dt, int64_t T, 
     const int64_t target = dt == FFTU_C128 ? 1024 : 2048;   // elements per tile
     int64_t W = 1;
     while (W * 2 * L <= target && W < 256) W *= 2;
-    const int64_t span = B > 1 ? B : A;
-    while (W > 1 && W / 2 >= span) W /= 2;                   // no tile much wider than the lines it can hold
+    while (W > 1 && W / 2 >= A * B) W /= 2;                  // no tile much wider than the lines there are
     while (W > 1 && (2 * W * L + L) * esize > cap) W /= 2;
     if ((2 * W * L + L) * esize > cap) return false;
     pd.A = A;
@@ -641,13 +640,8 @@ bool make_mixed_pass(int64_t A, int64_t L, int64_t B, fftu_dtype dt, int64_t T, 
     pd.L = int32_t(L);
     pd.W = int32_t(W);
     pd.logW = ilog2(W);
-    if (B > 1) {
-        pd.nbt = (B + W - 1) / W;
-        pd.tiles = A * pd.nbt;
-    } else {
-        pd.nbt = 1;
-        pd.tiles = (A + W - 1) / W;
-    }
+    pd.nbt = 0;
+    pd.tiles = (A * B + W - 1) / W;
     pd.tstep = T / L;
     pd.scale = 1.0;
     pd.lds_bytes = uint32_t((2 * W * L + L) * esize);
@@ -714,7 +708,7 @@ void fill_info_mixed(const MixedPlan &mp, fftu_dtype dt, fftu_plan_info *info)
     info->M = mp.g.M;
     info->s0_kernels = int32_t(mp.s0.size());
     info->exchange_fused = 0;
-    info->s2_kernels = int32_t(2 + mp.s2.size());
+    info->s2_kernels = int32_t(1 + mp.s2.size());   // twiddle + permutation in one kernel, then the passes
     info->launches = info->s0_kernels + info->s2_kernels;
     info->workspace_bytes = uint64_t(mp.g.N) * esize;
     info->table_bytes = uint64_t(mp.T) * esize;
@@ -1026,10 +1020,9 @@ fftu_plan_s *build_mixed_plan(int d, const int64_t n[], const int64_t p[], fftu_
     pl->grid.N = mp.g.N;
     pl->grid.M = mp.g.M;
     pl->grid.d = d;
-    pl->launches = int(mp.s0.size() + 2 + mp.s2.size());
+    pl->launches = int(mp.s0.size() + 1 + mp.s2.size());
     const std::string t = dtype == FFTU_C128 ? "double" : "float";
     for (size_t i = 0; i < mp.s0.size(); ++i) pl->launch_names.push_back("fftu::k_mline<" + t + ">");
-    pl->launch_names.push_back("fftu::k_mtwiddle<" + t + ">");
     pl->launch_names.push_back("fftu::k_mpermute<" + t + ">");
     for (size_t i = 0; i < mp.s2.size(); ++i) pl->launch_names.push_back("fftu::k_mline<" + t + ">");
     hipError_t e = hipSuccess;
@@ -1631,7 +1624,7 @@ fftu_status run_mixed_passes(const fftu_plan_s *pl, const std::vector<fftu::Mixe
 }
 
 // The mixed-radix transform: Superstep 0 passes (in -> ws, then in place), the
-// twiddle (in place on ws), the permutation (ws -> out), Superstep 2 passes in
+// twiddle and the permutation in one pass (ws -> out), Superstep 2 passes in
 // place on out; conj(F(conj x))/N for the inverse; mul as in execute_with.
 fftu_status execute_mixed(fftu_plan_s *plan, const void *in, void *out, void *ws, hipStream_t stream,
                           const void *mul, Marker &mk)
@@ -1642,15 +1635,13 @@ fftu_status execute_mixed(fftu_plan_s *plan, const void *in, void *out, void *ws
     if (s != FFTU_SUCCESS) return s;
     fftu::MixedGridDesc g = plan->mg;
     g.conj_in = g.conj_out = 0;
+    g.twiddle = 1;
     g.scale = 1.0;
-    hipError_t e = fftu::launch_mtwiddle(plan->prec, ws, ws, g, plan->table, stream);
-    if (e != hipSuccess) return from_hip(e);
-    mk.mark();
     if (plan->ms2.empty()) {
         g.conj_out = inv;
         g.scale = scale;
     }
-    e = fftu::launch_mpermute(plan->prec, ws, out, g, stream);
+    hipError_t e = fftu::launch_mpermute(plan->prec, ws, out, g, plan->table, stream);
     if (e != hipSuccess) return from_hip(e);
     mk.mark();
     if (!plan->ms2.empty()) {
@@ -1799,8 +1790,9 @@ fftu_status fftu_stage_exchange(fftu_plan_t plan, const void *in, void *out, hip
     if (plan->mixed) {
         fftu::MixedGridDesc mg = plan->mg;
         mg.conj_in = mg.conj_out = 0;
+        mg.twiddle = 0;
         mg.scale = 1.0;
-        return record(from_hip(fftu::launch_mpermute(plan->prec, in, out, mg, stream)));
+        return record(from_hip(fftu::launch_mpermute(plan->prec, in, out, mg, plan->table, stream)));
     }
     return record(from_hip(fftu::launch_permute(plan->prec, in, out, plan->grid, stream)));
 }

@@ -102,12 +102,12 @@ constexpr int kMixedThreads = 256;
 constexpr int kMixedMaxStages = 24;
 
 // A pass of 1-D FFTs of length L over an array viewed as (A, L, B), B the
-// stride of a line. A tile holds W lines (a power of two): W consecutive b of
-// one a when B > 1, W consecutive a when B = 1.
+// stride of a line. A tile holds W (a power of two) consecutive lines of the A B
+// lines, line u = a B + b.
 struct MixedPassDesc {
     int64_t A, B;
-    int64_t tiles;         // A * nbt (B > 1), ceil(A / W) (B = 1)
-    int64_t nbt;           // tiles along b: ceil(B / W) (B > 1)
+    int64_t tiles;         // ceil(A B / W)
+    int64_t nbt;           // unused
     int32_t L;
     int32_t W, logW;
     int32_t nstages;
@@ -126,6 +126,7 @@ struct MixedGridDesc {
     int64_t tstep[kMaxDims];   // T / n_l
     int64_t T;
     int32_t conj_in, conj_out;
+    int32_t twiddle;           // k_mpermute: apply Superstep 0's twiddle on the way
     double scale;
 };
 
@@ -191,7 +192,8 @@ hipError_t launch_mline(Precision prec, const void *in, void *out, const MixedPa
                         hipStream_t stream);
 hipError_t launch_mtwiddle(Precision prec, const void *in, void *out, const MixedGridDesc &g, const void *table,
                            hipStream_t stream);
-hipError_t launch_mpermute(Precision prec, const void *in, void *out, const MixedGridDesc &g, hipStream_t stream);
+hipError_t launch_mpermute(Precision prec, const void *in, void *out, const MixedGridDesc &g, const void *table,
+                           hipStream_t stream);
 hipError_t launch_pointwise(Precision prec, const void *a, const void *b, void *out, int64_t count, double scale,
                             hipStream_t stream);
 hipError_t launch_fill_uniform(Precision prec, void *out, int64_t count, uint32_t k0, uint32_t k1, uint64_t base,

@@ -3,8 +3,8 @@
 // paper's own code leaves the local FFTs to FFTW, which handles any size.)
 //
 //   k_mline      a pass of 1-D FFTs of length L (Superstep 0 along one local
-//                dimension, or Superstep 2 along one grid dimension). W lines
-//                are loaded into LDS, transformed by mixed-radix Stockham
+//                dimension, or Superstep 2 along one grid dimension). W
+//                consecutive lines of the (A, B) lines are loaded into LDS, transformed by mixed-radix Stockham
 //                stages (radix 8, 4, 2, 7, 5, 3; stage s with radix R after
 //                Ns points reads j + r L/R, twiddles by omega_{Ns R}^{r (j mod Ns)}
 //                and writes (j div Ns) Ns R + j mod Ns + r Ns), ping-ponging
@@ -13,7 +13,9 @@
 //                omega_T, T = lcm(n_l).
 //   k_mtwiddle   Superstep 0's twiddle Z^(s)[k] = prod_l omega_{n_l}^{k_l s_l} Y^(s)[k],
 //                the exponent reduced exactly in integers (one table entry).
-//   k_mpermute   Superstep 1: W^(r)[s q + t] = Z^(s)[r + t p], per output element.
+//   k_mpermute   Superstep 1: W^(r)[s q + t] = Z^(s)[r + t p], per output element,
+//                optionally with the twiddle of the source element applied on
+//                the way (the whole transform runs twiddle and Put as one pass).
 //
 // The index arithmetic uses 32-bit divisions by runtime sizes, so this path
 // takes N < 2^31. Loops that hold barriers run on wave-uniform values.
@@ -94,34 +96,23 @@ __global__ __launch_bounds__(kMixedThreads) void k_mline(const cx<T> *in, cx<T> 
     const int64_t nblocks = __builtin_amdgcn_readfirstlane(int(gridDim.x));
     for (int j = tid; j < L; j += nt) tw[j] = table[int64_t(j) * pd.tstep];
     const T scale = static_cast<T>(pd.scale);
+    const uint32_t B = uint32_t(pd.B);
     for (int64_t t = blockIdx.x; t < pd.tiles; t += nblocks) {
-        // tile origin and the number of lines it holds (wave-uniform)
-        int64_t a0, b0;
-        int lines;
-        if (pd.B > 1) {
-            a0 = t / pd.nbt;
-            b0 = (t - a0 * pd.nbt) << pd.logW;
-            lines = int(pd.B - b0 < W ? pd.B - b0 : W);
-        } else {
-            a0 = t << pd.logW;
-            b0 = 0;
-            lines = int(pd.A - a0 < W ? pd.A - a0 : W);
-        }
+        // the tile holds lines u0 .. u0 + lines - 1 of the A B lines (line u = a B + b);
+        // `lines` is wave-uniform
+        const uint32_t u0 = uint32_t(t) << pd.logW;
+        const uint32_t total = uint32_t(pd.A) * B;
+        const int lines = int(total - u0 < uint32_t(W) ? total - u0 : uint32_t(W));
         __syncthreads();   // twiddle copy done / previous tile's LDS reads done
         const int n = lines * L;
         for (int e = tid; e < n; e += nt) {
-            int x, w;
-            int64_t addr;
-            if (pd.B > 1) {
-                x = e / lines;
-                w = e - x * lines;
-                addr = (a0 * L + x) * pd.B + b0 + w;   // lanes run over b: runs of `lines` elements
-            } else {
-                w = e / L;
-                x = e - w * L;
-                addr = a0 * L + e;                     // W whole lines, contiguous
-            }
-            buf0[w * L + x] = conj_if(in[addr], pd.conj_in);
+            // lanes run over consecutive lines (consecutive b: runs of up to min(W, B) elements)
+            const int x = e / lines;
+            const int w = e - x * lines;
+            const uint32_t u = u0 + uint32_t(w);
+            const uint32_t a = u / B;
+            const uint32_t b = u - a * B;
+            buf0[w * L + x] = conj_if(in[(int64_t(a) * L + x) * B + b], pd.conj_in);
         }
         __syncthreads();
         cx<T> *src = buf0, *dst = buf1;
@@ -143,17 +134,12 @@ __global__ __launch_bounds__(kMixedThreads) void k_mline(const cx<T> *in, cx<T> 
             Ns *= pd.radix[s];
         }
         for (int e = tid; e < n; e += nt) {
-            int x, w;
-            int64_t addr;
-            if (pd.B > 1) {
-                x = e / lines;
-                w = e - x * lines;
-                addr = (a0 * L + x) * pd.B + b0 + w;
-            } else {
-                w = e / L;
-                x = e - w * L;
-                addr = a0 * L + e;
-            }
+            const int x = e / lines;
+            const int w = e - x * lines;
+            const uint32_t u = u0 + uint32_t(w);
+            const uint32_t a = u / B;
+            const uint32_t b = u - a * B;
+            const int64_t addr = (int64_t(a) * L + x) * B + b;
             cx<T> v = conj_if(src[w * L + x], pd.conj_out);
             if (pd.scale != 1.0) v = {v.x * scale, v.y * scale};
             out[addr] = v;
@@ -183,15 +169,18 @@ __global__ __launch_bounds__(256) void k_mtwiddle(const cx<T> *in, cx<T> *out, c
     }
 }
 
+// With g.twiddle set, the element is also multiplied by Superstep 0's twiddle of
+// its source position, omega^(sum_l k_l s_l) (the twiddle and the Put in one pass).
 template <typename T>
-__global__ __launch_bounds__(256) void k_mpermute(const cx<T> *in, cx<T> *out, const MixedGridDesc g)
+__global__ __launch_bounds__(256) void k_mpermute(const cx<T> *in, cx<T> *out, const MixedGridDesc g,
+                                                  const cx<T> *__restrict__ table)
 {
     const int64_t stride = int64_t(gridDim.x) * blockDim.x;
     const T scale = static_cast<T>(g.scale);
     for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < g.N; i += stride) {
         uint32_t r = uint32_t(i / g.M);
         uint32_t j = uint32_t(i - int64_t(r) * g.M);
-        int64_t src_rank = 0, src_k = 0, rmul = 1, kmul = 1;
+        int64_t src_rank = 0, src_k = 0, rmul = 1, kmul = 1, e = 0;
         for (int l = g.d - 1; l >= 0; --l) {
             const uint32_t jl = j % uint32_t(g.m[l]);
             j /= uint32_t(g.m[l]);
@@ -199,12 +188,15 @@ __global__ __launch_bounds__(256) void k_mpermute(const cx<T> *in, cx<T> *out, c
             r /= uint32_t(g.p[l]);
             const uint32_t sl = jl / uint32_t(g.q[l]);          // j_l = s_l q_l + t_l
             const uint32_t tl = jl - sl * uint32_t(g.q[l]);
+            const int64_t kl = int64_t(rl) + int64_t(tl) * g.p[l];  // k_l = r_l + t_l p_l
             src_rank += int64_t(sl) * rmul;
-            src_k += (int64_t(rl) + int64_t(tl) * g.p[l]) * kmul;  // k_l = r_l + t_l p_l
+            src_k += kl * kmul;
+            e += kl * sl * g.tstep[l];
             rmul *= g.p[l];
             kmul *= g.m[l];
         }
         cx<T> v = conj_if(in[src_rank * g.M + src_k], g.conj_in);
+        if (g.twiddle) v = cmul(v, table[e % g.T]);
         v = conj_if(v, g.conj_out);
         if (g.scale != 1.0) v = {v.x * scale, v.y * scale};
         out[i] = v;
@@ -250,14 +242,17 @@ hipError_t launch_mtwiddle(Precision prec, const void *in, void *out, const Mixe
     return hipGetLastError();
 }
 
-hipError_t launch_mpermute(Precision prec, const void *in, void *out, const MixedGridDesc &g, hipStream_t stream)
+hipError_t launch_mpermute(Precision prec, const void *in, void *out, const MixedGridDesc &g, const void *table,
+                           hipStream_t stream)
 {
     if (prec == Precision::F64)
         hipLaunchKernelGGL(k_mpermute<double>, dim3(grid_for(g.N)), dim3(256), 0, stream,
-                           static_cast<const cx<double> *>(in), static_cast<cx<double> *>(out), g);
+                           static_cast<const cx<double> *>(in), static_cast<cx<double> *>(out), g,
+                           static_cast<const cx<double> *>(table));
     else
         hipLaunchKernelGGL(k_mpermute<float>, dim3(grid_for(g.N)), dim3(256), 0, stream,
-                           static_cast<const cx<float> *>(in), static_cast<cx<float> *>(out), g);
+                           static_cast<const cx<float> *>(in), static_cast<cx<float> *>(out), g,
+                           static_cast<const cx<float> *>(table));
     return hipGetLastError();
 }
 

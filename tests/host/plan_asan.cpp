@@ -30,7 +30,7 @@ hipError_t launch_fill_uniform(Precision, void *, int64_t, uint32_t, uint32_t, u
 hipError_t launch_pointwise(Precision, const void *, const void *, void *, int64_t, double, hipStream_t) { return hipSuccess; }
 hipError_t launch_mline(Precision, const void *, void *, const MixedPassDesc &, const void *, hipStream_t) { return hipSuccess; }
 hipError_t launch_mtwiddle(Precision, const void *, void *, const MixedGridDesc &, const void *, hipStream_t) { return hipSuccess; }
-hipError_t launch_mpermute(Precision, const void *, void *, const MixedGridDesc &, hipStream_t) { return hipSuccess; }
+hipError_t launch_mpermute(Precision, const void *, void *, const MixedGridDesc &, const void *, hipStream_t) { return hipSuccess; }
 hipError_t launch_batch(Precision, const BatchDesc &bd, const void *, uint32_t, uint32_t, hipStream_t)
 {
     if (bd.nstages < 1 || bd.nitems < 1) std::abort();
