@@ -312,6 +312,55 @@ def run_mixed(args, torch, np, fftu, synth, with_oracle):
     return res
 
 
+def run_small(args, torch, np, fftu, synth, with_oracle):
+    """The small case: 64^3 complex128 on a 2^3 grid, forward then inverse. 4 MiB
+    fits in the caches, so latency (HIP-graph replays, and plain calls) is the
+    measure here, not the HBM roofline."""
+    n, p = (64, 64, 64), (2, 2, 2)
+    N = math.prod(n)
+    dev = torch.device("cuda:0")
+    D = synth.uniform_complex(N, 1, np.complex128)
+    x = torch.from_numpy(D).to(dev)
+    y = torch.empty_like(x)
+    z = torch.empty_like(x)
+    fwd = fftu.Plan(n, p, "complex128", fftu.FORWARD)
+    inv = fftu.Plan(n, p, "complex128", fftu.INVERSE)
+    stream = torch.cuda.current_stream(dev)
+    gf = fftu.Graph(fwd, x, y)
+    gi = fftu.Graph(inv, y, z)
+    reps = 200
+
+    def timed(run):
+        for _ in range(10):
+            run()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            run()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps * 1e3
+
+    us_graph = timed(lambda: (gf.launch(stream), gi.launch(stream)))
+    us_plain = timed(lambda: (fwd(x, y, stream=stream), inv(y, z, stream=stream)))
+    res = {"workload": "64x64x64 complex128 forward then inverse DFT, 2x2x2 cyclic grid",
+           "us_fwd_inv_graph": round(us_graph, 2), "us_fwd_inv_plain": round(us_plain, 2),
+           "launches_fwd": fwd.info()["launches"]}
+    if with_oracle:
+        import oracle
+        want = oracle.cyclic_dft(D, n, p)
+        res["rel_l2_forward_vs_oracle"] = oracle.rel_l2(y.cpu().numpy(), want)
+        res["rel_l2_roundtrip"] = oracle.rel_l2(z.cpu().numpy(), D)
+    gf.close()
+    gi.close()
+    fwd.close()
+    inv.close()
+    log(f"[bench] small 64^3 fwd+inv: {us_graph:.1f} us (graphs), {us_plain:.1f} us (plain calls)")
+    return res
+
+
 def run_serving(args, torch, synth):
     """The serving workload: a Poisson stream of 2-D/3-D/4-D requests (2000/s,
     sides 2^5..2^10, at most 2^26 points, complex64/complex128, forward/inverse,
@@ -352,6 +401,7 @@ def main():
     ap.add_argument("--no-serving", action="store_true", help="skip the serving workload")
     ap.add_argument("--no-convolution", action="store_true", help="skip the convolution workload")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-radix workload")
+    ap.add_argument("--no-small", action="store_true", help="skip the 64^3 latency workload")
     ap.add_argument("--serving-seconds", type=float, default=10.0,
                     help="seconds of the 30 s request trace to serve (each policy runs it in real time)")
     ap.add_argument("--retune", action="store_true", help="measure the tiling knobs again instead of the cached ones")
@@ -478,6 +528,8 @@ def main():
     if args.workload == "512cube":
         del x, out
         torch.cuda.empty_cache()
+    if args.workload == "512cube" and not args.no_small:
+        result["small"] = run_small(args, torch, np, fftu, synth, not args.no_check)
     if args.workload == "512cube" and not args.no_convolution:
         result["convolution"] = run_convolution(args, torch, np, fftu, synth, info)
         torch.cuda.empty_cache()
