@@ -376,7 +376,8 @@ def run_serving(args, torch, synth):
         out = {"workload": f"first {secs:g} s of a Poisson trace at 2000 requests/s (seed 5): rank 2-4, sides "
                            "2^5..2^10, <= 2^26 points, complex64/complex128, forward/inverse, p_l = 2; "
                            "input generated on the device (Philox4x32-10, key (5, request id))",
-               "streams": srv.nstreams, "arena_GiB": srv.arena_bytes / 2 ** 30}
+               "streams": srv.nstreams, "large_lanes": srv.large_lanes, "large_MiB": srv.large_bytes >> 20,
+               "arena_GiB": srv.arena_bytes / 2 ** 30}
         for policy in ("continuous", "fifo"):
             res = srv.serve(reqs, policy, time_limit=3 * secs + 5)
             out[policy] = serving.summarize(res, reqs)

@@ -19,8 +19,13 @@ cache is an LRU of host objects.
 Two policies over the same arena, plan cache and kernels:
   "continuous"  up to `streams` requests run at once, one per HIP stream (all of
                 default priority); a stream that finishes takes the next
-                admitted request at once, so small requests do not queue behind
-                a large one and no stream waits for the host.
+                admitted request at once, and no stream waits for the host.
+                Requests of at least `large_bytes` go to `large_lanes` streams
+                of their own, in arrival order, so a large request shares HBM
+                bandwidth only with small ones (two large requests at once would
+                each take twice as long), while small requests never queue
+                behind a large one. A large lane with no large request waiting
+                takes a small one.
   "fifo"        one request at a time on one stream; the host waits for each to
                 finish before it starts the next (the plain baseline).
 """
@@ -157,7 +162,8 @@ class ServeResult:
 class Server:
     """Serves requests with one of the two policies over a shared arena and plan cache."""
 
-    def __init__(self, arena_bytes: int = 16 << 30, streams: int = 4, seed: int = 5, plan_cache: int = 4096):
+    def __init__(self, arena_bytes: int = 16 << 30, streams: int = 4, seed: int = 5, plan_cache: int = 4096,
+                 large_bytes: int = 64 << 20, large_lanes: int = 2):
         import torch
         self.torch = torch
         self.dev = torch.device("cuda:0")
@@ -167,6 +173,8 @@ class Server:
         self.nstreams = int(streams)
         self.streams = [torch.cuda.Stream(self.dev) for _ in range(self.nstreams)]   # default priority
         self.plans = PlanCache(plan_cache)
+        self.large_bytes = int(large_bytes)
+        self.large_lanes = max(1, min(int(large_lanes), self.nstreams))
 
     def close(self):
         self.plans.close()
@@ -234,16 +242,29 @@ class Server:
             for blk in run.blocks:
                 arena.release(*blk)
 
-        queue = collections.deque()
+        # continuous: streams [0, large_lanes) serve the large class first; fifo: one queue
+        small = collections.deque()
+        large = collections.deque()
+        lanes = self.large_lanes if policy == "continuous" else 0
         running = [None] * nstreams
         i = 0
         n = len(reqs)
+
+        def pick(s):
+            """Queue that stream s takes from next (None: nothing for it)."""
+            if s < lanes:
+                return large if large else (small if small else None)
+            if policy == "fifo":
+                return small if small else None
+            return small if small else None
+
         while True:
             now = time.perf_counter() - t0
             if time_limit is not None and now > time_limit:
                 break
             while i < n and reqs[i].arrival <= now:
-                queue.append(reqs[i])
+                r = reqs[i]
+                (large if lanes and r.N * r.esize >= self.large_bytes else small).append(r)
                 i += 1
             progressed = False
             for s in range(nstreams):
@@ -252,23 +273,27 @@ class Server:
                     finish(run)
                     running[s] = None
                     progressed = True
+            blocked = False
             for s in range(nstreams):
-                if not queue:
-                    break
-                if running[s] is None:
-                    run = self._launch(queue[0], arena, self.streams[s])
-                    if run is None:
-                        break                     # HBM admission: wait for running requests
-                    queue.popleft()
-                    res.peak_arena_bytes = max(res.peak_arena_bytes, arena.used)
-                    running[s] = run
-                    progressed = True
-                    if policy == "fifo":
-                        run.end.synchronize()     # the host waits for each request
-            if i >= n and not queue and all(r is None for r in running):
+                if running[s] is not None or blocked:
+                    continue
+                q = pick(s)
+                if q is None:
+                    continue
+                run = self._launch(q[0], arena, self.streams[s])
+                if run is None:
+                    blocked = True                # HBM admission: wait for running requests
+                    continue
+                q.popleft()
+                res.peak_arena_bytes = max(res.peak_arena_bytes, arena.used)
+                running[s] = run
+                progressed = True
+                if policy == "fifo":
+                    run.end.synchronize()         # the host waits for each request
+            if i >= n and not small and not large and all(r is None for r in running):
                 break
             if not progressed:
-                if all(r is None for r in running) and not queue and i < n:
+                if all(r is None for r in running) and not small and not large and i < n:
                     time.sleep(max(0.0, min(reqs[i].arrival - (time.perf_counter() - t0), 1e-3)))
                 else:
                     time.sleep(2e-5)
