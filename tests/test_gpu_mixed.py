@@ -96,6 +96,28 @@ def test_mixed_external_plan_and_convolution(torch, dtype):
         assert oracle.rel_l2(got, want) <= TOL[dtype]
 
 
+@pytest.mark.parametrize("n,p,dtype", [((2880,), (3,), "complex128"),      # m = 960: longest mixed line, FP64
+                                       ((9600,), (5,), "complex64"),       # m = 1920: longest mixed line, FP32
+                                       ((2880, 6), (3, 1), "complex128")])
+def test_mixed_longest_lines(torch, n, p, dtype):
+    import paper_2203_11795_amd as fftu
+    N = int(np.prod(n))
+    D = synth.uniform_complex(N, 10, NP[dtype])
+    want = oracle.cyclic_dft(D.astype(np.complex128), n, p)
+    with fftu.Plan(n, p, dtype) as plan:
+        got = plan(torch.from_numpy(D).cuda()).cpu().numpy()
+    assert oracle.rel_l2(got.astype(np.complex128), want) <= TOL[dtype]
+
+
+def test_mixed_limits_are_rejected(torch):
+    import paper_2203_11795_amd as fftu
+    assert fftu.check((3 * 2048,), (2,), "complex128") == 3        # m = 3072 > 1024
+    assert fftu.check((3 * 2048,), (2,), "complex64") == 3         # m = 3072 > 2048
+    assert fftu.check((2 * 11 * 4,), (2,)) == 3                    # prime factor 11
+    with pytest.raises(fftu.FftuError):
+        fftu.BatchPlan([(48, 16, 16)], [(2, 2, 2)], "complex64")     # batches: powers of two only
+
+
 def test_mixed_full_size_sampled(torch):
     """480^3 complex128 on a 4^3 grid (m = 120, q = 30; T = 480): outputs at
     sampled indices against eq. (1.2) summed directly, and the round trip."""
