@@ -75,6 +75,22 @@ def requests_from_trace(trace, limit_seconds=None):
     return out
 
 
+def request_class(req: Request, lanes: int, large_bytes: int) -> str:
+    """'large' when the continuous policy has large lanes and the request's buffer
+    is at least large_bytes; else 'small'."""
+    return "large" if lanes and req.N * req.esize >= large_bytes else "small"
+
+
+def next_queue(stream: int, lanes: int, large, small):
+    """The queue stream `stream` takes its next request from: the large lanes
+    (streams below `lanes`) take large requests first and small ones when no
+    large one waits; the other streams take small requests only. None: nothing
+    for this stream."""
+    if stream < lanes and large:
+        return large
+    return small if small else None
+
+
 class Arena:
     """First-fit allocator over [0, capacity) with coalescing (offsets in bytes)."""
 
@@ -250,21 +266,13 @@ class Server:
         i = 0
         n = len(reqs)
 
-        def pick(s):
-            """Queue that stream s takes from next (None: nothing for it)."""
-            if s < lanes:
-                return large if large else (small if small else None)
-            if policy == "fifo":
-                return small if small else None
-            return small if small else None
-
         while True:
             now = time.perf_counter() - t0
             if time_limit is not None and now > time_limit:
                 break
             while i < n and reqs[i].arrival <= now:
                 r = reqs[i]
-                (large if lanes and r.N * r.esize >= self.large_bytes else small).append(r)
+                (large if request_class(r, lanes, self.large_bytes) == "large" else small).append(r)
                 i += 1
             progressed = False
             for s in range(nstreams):
@@ -277,7 +285,7 @@ class Server:
             for s in range(nstreams):
                 if running[s] is not None or blocked:
                     continue
-                q = pick(s)
+                q = next_queue(s, lanes, large, small)
                 if q is None:
                     continue
                 run = self._launch(q[0], arena, self.streams[s])

@@ -55,3 +55,19 @@ def test_requests_from_trace():
     assert {r.dtype for r in reqs} == {"complex64", "complex128"} and {r.direction for r in reqs} == {-1, 1}
     head = serving.requests_from_trace(trace, limit_seconds=0.1)
     assert head == reqs[:len(head)] and all(r.arrival < 0.1 for r in head)
+
+
+def test_size_classes_and_lane_queues():
+    import collections
+    small_req = serving.Request(0, 0.0, (64, 64), "complex64", -1)           # 32 KiB
+    big_req = serving.Request(1, 0.0, (1024, 1024, 64), "complex128", 1)    # 1 GiB
+    assert serving.request_class(small_req, 2, 64 << 20) == "small"
+    assert serving.request_class(big_req, 2, 64 << 20) == "large"
+    assert serving.request_class(big_req, 0, 64 << 20) == "small"         # FIFO: one class
+    large, small = collections.deque([big_req]), collections.deque([small_req])
+    assert serving.next_queue(0, 2, large, small) is large                 # a large lane prefers large
+    assert serving.next_queue(1, 2, large, small) is large
+    assert serving.next_queue(2, 2, large, small) is small                 # small lanes never take large
+    assert serving.next_queue(2, 2, large, collections.deque()) is None
+    assert serving.next_queue(0, 2, collections.deque(), small) is small   # an idle large lane takes small
+    assert serving.next_queue(0, 0, large, small) is small                 # FIFO: no lanes
