@@ -312,6 +312,60 @@ def run_mixed(args, torch, np, fftu, synth, with_oracle):
     return res
 
 
+def run_precision(args, torch, np, fftu, synth, with_oracle):
+    """The precision pattern at 64^5 (2^30 points, 2^5 grid): the complex64 path
+    (FP32 butterflies, FP64-generated tables rounded once) timed, and its error
+    against the FP64 oracle with the complex128 path's error on the same input
+    (the N(0,1) draw rounded once to complex64, promoted exactly) beside it."""
+    n, p = (64,) * 5, (2,) * 5
+    N = math.prod(n)
+    dev = torch.device("cuda:0")
+    log("[bench] precision 64^5: generating input")
+    D32 = synth.normal_complex(N, 3, np.complex64)
+    x32 = torch.from_numpy(D32).to(dev)
+    y32 = torch.empty_like(x32)
+    plan32 = fftu.Plan(n, p, "complex64", fftu.FORWARD)
+    info = plan32.info()
+    stream = torch.cuda.current_stream(dev)
+    steps = max(3, args.steps // 4)
+    for _ in range(args.warmup):
+        plan32(x32, y32, stream=stream)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        plan32(x32, y32, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    plan32.close()
+    alg = info["launches"] * 2.0 * N * 8
+    res = {"workload": "64^5 complex64 forward DFT, 2^5 cyclic grid, N(0,1) input (seed 3)",
+           "ms_per_transform": round(ms, 4), "GFLOPs": round(5.0 * N * math.log2(N) / (ms * 1e-3) / 1e9, 1),
+           "roofline": {"bound": "hbm", "algorithmic_bytes": alg, "achieved": round(alg / (ms * 1e-3) / 1e9, 1),
+                        "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}}
+    if with_oracle:
+        import oracle
+        got32 = y32.cpu().numpy()
+        del x32, y32
+        torch.cuda.empty_cache()
+        D64 = D32.astype(np.complex128)
+        del D32
+        x64 = torch.from_numpy(D64).to(dev)
+        with fftu.Plan(n, p, "complex128", fftu.FORWARD) as plan64:
+            got64 = plan64(x64).cpu().numpy()
+        del x64
+        torch.cuda.empty_cache()
+        log("[bench] precision 64^5: FP64 oracle on the host")
+        want = oracle.to_cyclic(oracle.fft_axes(oracle.from_cyclic(D64, n, p), range(5), oracle.FORWARD), p)
+        res["rel_l2_complex64_vs_fp64_oracle"] = oracle.rel_l2(got32, want)
+        res["rel_l2_complex128_vs_fp64_oracle"] = oracle.rel_l2(got64, want)
+        res["tolerance_complex64"] = 5e-6
+    log(f"[bench] precision 64^5 complex64: {ms:.3f} ms")
+    return res
+
+
 def run_small(args, torch, np, fftu, synth, with_oracle):
     """The small case: 64^3 complex128 on a 2^3 grid, forward then inverse. 4 MiB
     fits in the caches, so latency (HIP-graph replays, and plain calls) is the
@@ -403,6 +457,7 @@ def main():
     ap.add_argument("--no-convolution", action="store_true", help="skip the convolution workload")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-radix workload")
     ap.add_argument("--no-small", action="store_true", help="skip the 64^3 latency workload")
+    ap.add_argument("--no-precision", action="store_true", help="skip the 64^5 complex64 precision workload")
     ap.add_argument("--serving-seconds", type=float, default=10.0,
                     help="seconds of the 30 s request trace to serve (each policy runs it in real time)")
     ap.add_argument("--retune", action="store_true", help="measure the tiling knobs again instead of the cached ones")
@@ -528,6 +583,9 @@ def main():
     plan.close()
     if args.workload == "512cube":
         del x, out
+        torch.cuda.empty_cache()
+    if args.workload == "512cube" and not args.no_precision:
+        result["precision"] = run_precision(args, torch, np, fftu, synth, not args.no_check)
         torch.cuda.empty_cache()
     if args.workload == "512cube" and not args.no_small:
         result["small"] = run_small(args, torch, np, fftu, synth, not args.no_check)
