@@ -1240,13 +1240,34 @@ fftu_status build_batch_worklist(int count, const int d[], const int64_t *const 
         const GridDesc g = make_grid(G);
         Member &m = mem[size_t(f)];
         m.M = g.M;
-        for (int l = G.d - 1; l >= 0; --l) {
-            if (G.logm[l] == 0) continue;
-            int logA = G.logP, logB = 0;
+        // as plan_s0: the two innermost dimensions share a k_group2 pass when their
+        // planes are small, every other dimension gets a line pass
+        std::vector<int> dims;   // dimensions with m_l > 1, innermost first
+        for (int l = G.d - 1; l >= 0; --l)
+            if (G.logm[l] > 0) dims.push_back(l);
+        auto outer_of = [&](int l) {
+            int logA = G.logP;
             for (int j = 0; j < l; ++j) logA += G.logm[j];
+            return logA;
+        };
+        size_t first_line = 0;
+        if (dims.size() >= 2) {
+            PassDesc pd;
+            const int li = dims[0], lo = dims[1];
+            if (make_group2_pass(outer_of(lo), G.logm[lo], G.logm[li], dtype, G.lognmax, pd) &&
+                pd.threads <= kBatchThreads) {
+                const uint32_t tw_bytes = ((uint32_t(1) << G.logm[lo]) + (uint32_t(1) << G.logm[li])) * uint32_t(esize);
+                tile_lds = std::max(tile_lds, uint32_t(pd.lds_bytes - tw_bytes));
+                m.s0.push_back(pd);
+                first_line = 2;
+            }
+        }
+        for (size_t i = first_line; i < dims.size(); ++i) {
+            const int l = dims[i];
+            int logB = 0;
             for (int j = l + 1; j < G.d; ++j) logB += G.logm[j];
             PassDesc pd;
-            if (G.logm[l] > kBatchMaxLogLine || !make_line_pass(logA, G.logm[l], logB, dtype, G.lognmax, pd, 8) ||
+            if (G.logm[l] > kBatchMaxLogLine || !make_line_pass(outer_of(l), G.logm[l], logB, dtype, G.lognmax, pd, 8) ||
                 pd.threads > kBatchThreads)
                 return FFTU_ERROR_UNSUPPORTED;
             tile_lds = std::max(tile_lds, uint32_t(pd.lds_bytes - (uint32_t(1) << G.logm[l]) * esize));
@@ -1276,7 +1297,7 @@ fftu_status build_batch_worklist(int count, const int d[], const int64_t *const 
                 st.kind = m.s0[size_t(s)].kind;
                 st.pd = m.s0[size_t(s)];
                 st.tiles = st.pd.tiles;
-                tile_elems = int64_t(1) << (st.pd.logW + st.pd.loglen[0]);
+                tile_elems = int64_t(1) << (st.pd.logW + st.pd.logG);   // W lines of L, or W planes of L1 L2
             } else {
                 st.kind = kExchangeStage;
                 st.ex = m.ex;

@@ -4,7 +4,8 @@
 // The batch is a list of stage descriptors, one per (stage, transform), in
 // stage-major order: every transform's first Superstep-0 pass, then every
 // second pass, ..., then every exchange. Each descriptor owns a contiguous range
-// of work items (tiles of a k_line pass, or groups of the fused exchange).
+// of work items (tiles of a k_line or k_group2 pass, or groups of the fused
+// exchange).
 // Workgroups take items (runs of about 2^17 elements' worth of tiles) from one
 // global counter in that order. Before an item of a descriptor with a dependency
 // (the previous stage of the same transform) runs, its workgroup waits until
@@ -30,6 +31,7 @@
 #include <cstdint>
 
 #include "fftu_exchange.hpp"
+#include "fftu_group.hpp"
 #include "fftu_line.hpp"
 
 namespace fftu {
@@ -90,6 +92,47 @@ __device__ __forceinline__ void run_line(const BatchStage &st, int key, const cx
     }
 #undef FFTU_LINE_MODES
 #undef FFTU_LINE_CASE
+}
+
+// Tiles [first, last) of a k_group2 pass (both innermost dimensions, whole planes)
+// with L1 = 2^A, L2 = 2^B; tw takes omega_L1 then omega_L2. A function of its own
+// (not inlined) for each plane shape: inlined, the 25 shapes raised the register
+// use of the whole persistent kernel.
+template <typename T, int A, int B>
+__device__ __noinline__ void group2_item(const BatchStage &st, const cx<T> *__restrict__ table, cx<T> *tw,
+                                         cx<T> *tile, int64_t first, int64_t last, int tid)
+{
+    const cx<T> *in = static_cast<const cx<T> *>(st.src);
+    cx<T> *out = static_cast<cx<T> *>(st.dst);
+    const PassDesc &pd = st.pd;
+    // arguments arrive in vector registers: the tile loop (which holds barriers)
+    // runs on scalar copies
+    const int64_t t0 = uniform64(first), t1 = uniform64(last);
+    for (int e = tid; e < (1 << A); e += kBatchThreads) tw[e] = table[e << (pd.lognmax - A)];
+    for (int e = tid; e < (1 << B); e += kBatchThreads) tw[(1 << A) + e] = table[e << (pd.lognmax - B)];
+    for (int64_t t = t0; t < t1; ++t) {
+        __syncthreads();
+        group2_tile<T, A, B, true>(in, out, pd, tw, tw + (1 << A), tile, t, tid, kBatchThreads);
+    }
+}
+
+// key = log2(L1) * 8 + log2(L2), uniform.
+template <typename T>
+__device__ __forceinline__ void run_group2(const BatchStage &st, int key, const cx<T> *__restrict__ table, cx<T> *tw,
+                                           cx<T> *tile, int64_t first, int64_t last, int tid)
+{
+#define FFTU_G2_CASE(A, B) case (A) * 8 + (B): group2_item<T, A, B>(st, table, tw, tile, first, last, tid); break;
+#define FFTU_G2_ROW(A) FFTU_G2_CASE(A, 2) FFTU_G2_CASE(A, 3) FFTU_G2_CASE(A, 4) FFTU_G2_CASE(A, 5) FFTU_G2_CASE(A, 6)
+    switch (key) {
+        FFTU_G2_ROW(2)
+        FFTU_G2_ROW(3)
+        FFTU_G2_ROW(4)
+        FFTU_G2_ROW(5)
+        FFTU_G2_ROW(6)
+    default: break;
+    }
+#undef FFTU_G2_ROW
+#undef FFTU_G2_CASE
 }
 
 // Tiles [first, last) of the fused exchange; a tile is 4 groups of 64 local
@@ -191,6 +234,8 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(const BatchDesc bd, con
         if (kind == kExchangeStage)
             run_exchange<T>(st, uniform32(st.ex.nr * 8 + st.ex.lpr), table,
                             smem_raw + kBatchMaxLine * sizeof(cx<T>), first, last, tid);
+        else if (kind == kGroup2)
+            run_group2<T>(st, uniform32(st.pd.loglen[0] * 8 + st.pd.loglen[1]), table, tw, tile, first, last, tid);
         else
             run_line<T>(st, uniform32(st.pd.loglen[0] * 8 + kind), table, tw, tile, first, last, tid);
     }
