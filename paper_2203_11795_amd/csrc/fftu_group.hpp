@@ -115,11 +115,26 @@ __device__ __forceinline__ void group2_tile(const cx<T> *in, cx<T> *out, const P
     __syncthreads();   // the whole tile is in LDS before any line is read
     group_axis<T, LOGL2>(tile, base2, 1, j2, act2, tw2);
     group_axis<T, LOGL1>(tile, base1, P2, j1, act1, tw1);
-    for (int e = tid; e < n; e += nt) {
-        const int w = e >> LOGG, x1 = (e >> LOGL2) & (L1 - 1), x2 = e & (L2 - 1);
-        cx<T> v = conj_if(tile[w * PG + x1 * P2 + x2], pd.conj_out);
-        if (pd.scale != 1.0) v = {v.x * scale, v.y * scale};
-        put<CO>(&out[gbase + e], v);
+    // stores in groups of kGroupUnroll per thread: the LDS reads first, then the stores
+    for (int e0 = tid; e0 < n; e0 += kGroupUnroll * nt) {
+        cx<T> r[kGroupUnroll];
+#pragma unroll
+        for (int u = 0; u < kGroupUnroll; ++u) {
+            const int e = e0 + u * nt;
+            if (e < n) {
+                const int w = e >> LOGG, x1 = (e >> LOGL2) & (L1 - 1), x2 = e & (L2 - 1);
+                r[u] = conj_if(tile[w * PG + x1 * P2 + x2], pd.conj_out);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kGroupUnroll; ++u) {
+            const int e = e0 + u * nt;
+            if (e < n) {
+                cx<T> v = r[u];
+                if (pd.scale != 1.0) v = {v.x * scale, v.y * scale};
+                put<CO>(&out[gbase + e], v);
+            }
+        }
     }
 }
 
