@@ -41,17 +41,23 @@ def _run(cmd, verbose):
         print(err, file=sys.stderr)
 
 
-def build(verbose: bool = False, resource_usage: bool = False) -> str:
-    """Compile every source for gfx950 and link libfftu.so; returns its path."""
+def build(verbose: bool = False, resource_usage: bool = False, jobs: int = 0) -> str:
+    """Compile every source for gfx950 (in parallel, `jobs` at a time; 0 = one per
+    source, at most 8) and link libfftu.so; returns its path."""
+    from concurrent.futures import ThreadPoolExecutor
     os.makedirs(BUILD, exist_ok=True)
-    objs = []
+    cmds, objs = [], []
     for src in SOURCES:
         obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
         cmd = [HIPCC, *COMMON, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
         if resource_usage and src.endswith(".hip"):
             cmd.append("-Rpass-analysis=kernel-resource-usage")
-        _run(cmd, verbose or resource_usage)
+        cmds.append(cmd)
         objs.append(obj)
+    workers = jobs if jobs > 0 else min(8, len(cmds))
+    with ThreadPoolExecutor(max_workers=workers) as pool:
+        for fut in [pool.submit(_run, c, verbose or resource_usage) for c in cmds]:
+            fut.result()
     tmp = LIB + ".tmp"
     _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp], verbose)
     os.replace(tmp, LIB)
