@@ -21,15 +21,19 @@
  * row-major array.
  *
  * Requirements on a plan (Algorithm 2.3, Input): p_l^2 divides n_l for every l.
- * This implementation also requires every n_l and p_l to be a power of two,
- * 1 <= d <= FFTU_MAX_DIMS, N < 2^40, n_l/p_l <= 2048 (complex128) or 4096
- * (complex64), and p_l <= 2048 / 4096 likewise.
+ * This implementation also requires 1 <= d <= FFTU_MAX_DIMS and either
+ *   - every n_l and p_l a power of two, N < 2^40, n_l/p_l and p_l <= 2048
+ *     (complex128) or 4096 (complex64); or
+ *   - every n_l with no prime factor other than 2, 3, 5, 7 (the mixed-radix
+ *     path), N < 2^31, n_l/p_l and p_l <= 1024 (complex128) or 2048
+ *     (complex64), lcm(n_1, ..., n_d) <= 2^24.
  *
  * Directions: FFTU_FORWARD uses omega_n = exp(-2 pi i / n) and is unnormalised;
  * FFTU_INVERSE conjugates every weight and multiplies by 1/N (Section 1.3,
  * last paragraph), so that inverse(forward(x)) = x.
  *
- * Ownership: the caller owns the input and output buffers (device memory). A
+ * Ownership: the caller owns the input and output buffers (device memory,
+ * aligned to the element size: 8 bytes for complex64, 16 for complex128). A
  * plan owns its twiddle table and a workspace of N elements in device memory,
  * allocated on the device that is current when the plan is created, and freed
  * by fftu_destroy. Execution calls never allocate and never synchronise.
@@ -38,10 +42,12 @@
  * fftu_last_error() returns the status of the last failing or succeeding call
  * on the calling thread. Argument errors are reported by fftu_plan/fftu_check;
  * execution calls report only FFTU_ERROR_INVALID_VALUE (NULL plan or buffer,
- * or a forbidden aliasing) and FFTU_ERROR_DEVICE (a HIP launch error).
+ * a buffer not aligned to the element size, or a forbidden aliasing) and
+ * FFTU_ERROR_DEVICE (a HIP launch error).
  *
  * Concurrency: a plan may be executed by one stream at a time (the workspace is
- * shared by its calls). Different plans are independent.
+ * shared by its calls). Different plans are independent. Planning may run on
+ * several threads; the tuning knobs (fftu_set_tuning) are process-wide.
  */
 #ifndef FFTU_H
 #define FFTU_H

@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <mutex>
@@ -83,11 +84,17 @@ namespace {
 thread_local fftu_status g_last = FFTU_SUCCESS;
 
 // Planner tuning knobs (fftu_set_tuning); -1 = default.
-int g_tune[FFTU_TUNE_COUNT] = {-1, -1, -1, -1};
+// Planner knobs (fftu_set_tuning): process-wide, read when a plan is made.
+std::atomic<int> g_tune[FFTU_TUNE_COUNT] = {{-1}, {-1}, {-1}, {-1}};
+int knob(int i) { return g_tune[i].load(std::memory_order_relaxed); }
 const int g_tune_min[FFTU_TUNE_COUNT] = {2, 0, 0, 16};
 const int g_tune_max[FFTU_TUNE_COUNT] = {6, 8, 4, 160};
 
-int64_t lds_cap() { return int64_t(g_tune[FFTU_TUNE_MAX_LDS_KB] >= 0 ? g_tune[FFTU_TUNE_MAX_LDS_KB] : 64) * 1024; }
+int64_t lds_cap()
+{
+    const int v = knob(FFTU_TUNE_MAX_LDS_KB);
+    return int64_t(v >= 0 ? v : 64) * 1024;
+}
 
 fftu_status record(fftu_status s)
 {
@@ -206,10 +213,12 @@ bool make_line_pass(int logA, int logL, int logB, fftu_dtype dt, int lognmax, Pa
     if (logB >= 2) {
         // columns: W consecutive lines of the (A, B) lines per workgroup, i.e. runs of
         // min(W, B) elements per row; W > B spans several outer blocks
-        int logW = g_tune[FFTU_TUNE_LINE_STRIDED_LOGW] >= 0 ? g_tune[FFTU_TUNE_LINE_STRIDED_LOGW] : log_wmax(dt);
+        const int kw = knob(FFTU_TUNE_LINE_STRIDED_LOGW);
+        int logW = kw >= 0 ? kw : log_wmax(dt);
         logW = std::max(logW, min_log_threads - logTPL);
         logW = std::min(logW, logA + logB);
-        const int pad = g_tune[FFTU_TUNE_LINE_PAD] >= 0 ? g_tune[FFTU_TUNE_LINE_PAD] : 1;
+        const int kp = knob(FFTU_TUNE_LINE_PAD);
+        const int pad = kp >= 0 ? kp : 1;
         while (logW > 0 && (((int64_t(1) << logW) + pad) * L * xbytes + L * esize) > cap) --logW;
         while (logW > 0 && (logW + logTPL) > 8) --logW;
         if (logW < 2) return false;
@@ -243,8 +252,8 @@ bool make_line_pass(int logA, int logL, int logB, fftu_dtype dt, int lognmax, Pa
     if (logB == 0) {
         // contiguous lines: about 2^9 (complex128) or 2^10 (complex64) elements per workgroup
         const int log_target = dt == FFTU_C128 ? 9 : 10;
-        int logW = g_tune[FFTU_TUNE_LINE_CONTIG_LOGW] >= 0 ? g_tune[FFTU_TUNE_LINE_CONTIG_LOGW]
-                                                           : std::max(0, log_target - logL);
+        const int kc = knob(FFTU_TUNE_LINE_CONTIG_LOGW);
+        int logW = kc >= 0 ? kc : std::max(0, log_target - logL);
         logW = std::max(logW, min_log_threads - logTPL);
         logW = std::min(logW, logA);
         while (logW > 0 && (logW + logTPL) > 8) --logW;
@@ -798,9 +807,13 @@ fftu_status run_passes(const fftu_plan_s *pl, const std::vector<PassDesc> &passe
     return FFTU_SUCCESS;
 }
 
+// Device buffers hold whole complex elements: 8- or 16-byte aligned.
+bool aligned(const void *p, size_t esize) { return (reinterpret_cast<uintptr_t>(p) & (esize - 1)) == 0; }
+
 fftu_status check_exec_args(const fftu_plan_s *plan, const void *in, const void *out)
 {
     if (!plan || !in || !out) return FFTU_ERROR_INVALID_VALUE;
+    if (!aligned(in, plan->esize) || !aligned(out, plan->esize)) return FFTU_ERROR_INVALID_VALUE;
     if (in != out) {
         const char *a = static_cast<const char *>(in);
         const char *b = static_cast<const char *>(out);
@@ -1154,7 +1167,7 @@ fftu_status fftu_set_tuning(fftu_tune_param param, int value)
     const int i = int(param);
     if (i < 0 || i >= FFTU_TUNE_COUNT) return record(FFTU_ERROR_INVALID_VALUE);
     if (value != -1 && (value < g_tune_min[i] || value > g_tune_max[i])) return record(FFTU_ERROR_INVALID_VALUE);
-    g_tune[i] = value;
+    g_tune[i].store(value, std::memory_order_relaxed);
     return record(FFTU_SUCCESS);
 }
 
@@ -1166,7 +1179,7 @@ int fftu_get_tuning(fftu_tune_param param)
         return -1;
     }
     record(FFTU_SUCCESS);
-    return g_tune[i];
+    return knob(i);
 }
 
 fftu_status fftu_check(int d, const int64_t n[], const int64_t p[], fftu_dtype dtype, fftu_direction direction)
@@ -1418,7 +1431,8 @@ fftu_status fftu_execute_batch(fftu_plan_t plan, const void *const in[], void *c
     if (!plan || !plan->is_batch || !in || !out) return record(FFTU_ERROR_INVALID_VALUE);
     bool same = plan->bound_in.size() == size_t(plan->count);
     for (int f = 0; f < plan->count; ++f) {
-        if (!in[f] || !out[f]) return record(FFTU_ERROR_INVALID_VALUE);
+        if (!in[f] || !out[f] || !aligned(in[f], plan->esize) || !aligned(out[f], plan->esize))
+            return record(FFTU_ERROR_INVALID_VALUE);
         if (same && (plan->bound_in[size_t(f)] != in[f] || plan->bound_out[size_t(f)] != out[f])) same = false;
     }
     if (!same) {
@@ -1434,6 +1448,7 @@ fftu_status fftu_fill_uniform(void *out, int64_t count, fftu_dtype dtype, uint32
 {
     if (count < 0 || (count > 0 && !out) || (dtype != FFTU_C64 && dtype != FFTU_C128))
         return record(FFTU_ERROR_INVALID_VALUE);
+    if (count > 0 && !aligned(out, dtype == FFTU_C128 ? 16 : 8)) return record(FFTU_ERROR_INVALID_VALUE);
     const fftu::Precision prec = dtype == FFTU_C128 ? fftu::Precision::F64 : fftu::Precision::F32;
     return record(from_hip(fftu::launch_fill_uniform(prec, out, count, key0, key1, counter_base, stream)));
 }
@@ -1562,7 +1577,7 @@ fftu_status fftu_execute_ws(fftu_plan_t plan, const void *in, void *out, void *w
 {
     fftu_status s = check_exec_args(plan, in, out);
     if (s != FFTU_SUCCESS) return record(s);
-    if (!workspace) return record(FFTU_ERROR_INVALID_VALUE);
+    if (!workspace || !aligned(workspace, plan->esize)) return record(FFTU_ERROR_INVALID_VALUE);
     const char *w = static_cast<const char *>(workspace);
     const size_t bytes = size_t(plan->grid.N) * plan->esize;
     for (const void *buf : {in, static_cast<const void *>(out)}) {
@@ -1591,7 +1606,8 @@ fftu_plan_t fftu_plan_convolution(int d, const int64_t n[], const int64_t p[], f
 fftu_status fftu_execute_convolution(fftu_plan_t plan, const void *in, const void *filter_hat, void *out,
                                      hipStream_t stream)
 {
-    if (!plan || !plan->conv_inv || !filter_hat) return record(FFTU_ERROR_INVALID_VALUE);
+    if (!plan || !plan->conv_inv || !filter_hat || !aligned(filter_hat, plan->esize))
+        return record(FFTU_ERROR_INVALID_VALUE);
     fftu_status s = check_exec_args(plan, in, out);
     if (s != FFTU_SUCCESS) return record(s);
     const char *h = static_cast<const char *>(filter_hat);
@@ -1608,6 +1624,8 @@ fftu_status fftu_pointwise_mul(const void *a, const void *b, void *out, int64_t 
 {
     if (count < 0 || (count > 0 && (!a || !b || !out)) || (dtype != FFTU_C64 && dtype != FFTU_C128))
         return record(FFTU_ERROR_INVALID_VALUE);
+    const size_t es = dtype == FFTU_C128 ? 16 : 8;
+    if (count > 0 && (!aligned(a, es) || !aligned(b, es) || !aligned(out, es))) return record(FFTU_ERROR_INVALID_VALUE);
     const fftu::Precision prec = dtype == FFTU_C128 ? fftu::Precision::F64 : fftu::Precision::F32;
     return record(from_hip(fftu::launch_pointwise(prec, a, b, out, count, scale, stream)));
 }

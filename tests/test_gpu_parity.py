@@ -240,3 +240,23 @@ def test_tuning_changes_tiling_not_results(torch_dev, knob, values):
             assert oracle.rel_l2(got, base) <= 1e-15, (knob, v)
     finally:
         fftu.set_tuning(knob, -1)
+
+
+def test_misaligned_buffers_are_rejected(torch_dev):
+    """Buffers hold whole complex elements: a pointer off the element size is refused
+    before any launch."""
+    import paper_2203_11795_amd as fftu
+    torch = torch_dev
+    with fftu.Plan((64, 64), (2, 2), "complex128") as plan:
+        x = torch.zeros(64 * 64 + 1, dtype=torch.complex128, device="cuda")
+        base = x.data_ptr()
+        with pytest.raises(fftu.FftuError):
+            plan.execute_ptr(base + 8, base + 8)           # in place, 8 bytes off
+        with pytest.raises(fftu.FftuError):
+            plan.execute_ptr(base, base + 8)
+        plan.execute_ptr(base, base)                       # aligned, in place: accepted
+        torch.cuda.synchronize()
+    lib = fftu.load_library()
+    y = torch.zeros(16, dtype=torch.complex64, device="cuda")
+    assert lib.fftu_fill_uniform(y.data_ptr() + 4, 4, 1, 0, 0, 0, None) == 1
+    assert lib.fftu_pointwise_mul(y.data_ptr() + 4, y.data_ptr(), y.data_ptr(), 4, 1, 1.0, None) == 1
