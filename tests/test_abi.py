@@ -149,3 +149,14 @@ def test_tuning_knobs_roundtrip_and_ranges():
     finally:
         for name in names:
             fftu.set_tuning(name, -1)
+
+
+def test_benchmark_ideal_pass_counts():
+    """The roofline's ideal pass count (local dimensions grouped greedily under
+    the LDS budget, plus one exchange pass) for the benchmarked shapes."""
+    import bench
+    assert bench.ideal_passes((512, 512, 512), (4, 4, 4), 16) == 4
+    assert bench.ideal_passes((64,) * 5, (2,) * 5, 8) == 4
+    assert bench.ideal_passes((64, 64, 64), (2, 2, 2), 16) == 3
+    assert bench.ideal_passes((16, 16, 16), (2, 2, 2), 8) == 1          # fits one workgroup's LDS
+    assert bench.ideal_passes((256, 256, 256), (2, 2, 2), 8) == 3
