@@ -96,7 +96,8 @@ typedef enum {
     FFTU_TUNE_LINE_CONTIG_LOGW = 1,  /* log2 lines per workgroup, contiguous single-dimension passes (0..8) */
     FFTU_TUNE_LINE_PAD = 2,          /* LDS padding (elements) per row of a strided pass tile (0..4) */
     FFTU_TUNE_MAX_LDS_KB = 3,        /* LDS budget per workgroup of a pass, KiB (16..160; default 64) */
-    FFTU_TUNE_COUNT = 4
+    FFTU_TUNE_FUSE_LAST = 4,         /* 0: never fuse the innermost dimension's lines into the exchange; 1 / -1: when possible */
+    FFTU_TUNE_COUNT = 5
 } fftu_tune_param;
 
 /* Set a tuning knob; FFTU_ERROR_INVALID_VALUE for an unknown knob or a value out of range. */
@@ -111,8 +112,9 @@ typedef struct {
     int64_t N;                /* total elements */
     int64_t P;                /* virtual processors p_1...p_d */
     int64_t M;                /* local elements per processor, N / P */
-    int32_t s0_kernels;       /* kernel launches of Superstep 0 (local FFTs) */
-    int32_t exchange_fused;   /* 1: twiddle, permutation, length-p FFTs and scaling run as one kernel */
+    int32_t s0_kernels;       /* separate kernel launches of Superstep 0 (local FFTs) */
+    int32_t exchange_fused;   /* 1: twiddle, permutation, length-p FFTs and scaling run as one kernel;
+                                 2: so do the innermost dimension's local FFTs (s0_kernels excludes them) */
     int32_t s2_kernels;       /* extra launches for Supersteps 1-2 when not fused (twiddle, permute, F_p passes) */
     int32_t launches;         /* kernel launches of one fftu_execute */
     uint64_t workspace_bytes; /* device workspace owned by the plan */

@@ -1,7 +1,8 @@
 """Measured tuning of the tiling knobs (fftu_set_tuning) for a plan or a batch.
 
 The knobs change how the local-FFT passes are tiled (lines per workgroup, LDS
-padding, the LDS budget per workgroup), never what is computed. A plan reads
+padding, the LDS budget per workgroup) and whether the innermost dimension's
+lines share a kernel with the exchange, never what is computed. A plan reads
 them when it is created, so tuning builds one plan per candidate setting, times
 its executions with HIP events on the current stream, and keeps the fastest.
 The search is coordinate descent: each knob in turn is swept with the others
@@ -20,12 +21,13 @@ import statistics
 
 from . import fftu as _b
 
-KNOB_NAMES = ("line_strided_logw", "line_contig_logw", "line_pad", "max_lds_kb")
+KNOB_NAMES = ("line_strided_logw", "line_contig_logw", "line_pad", "max_lds_kb", "fuse_last")
 CANDIDATES = {
     "line_strided_logw": (-1, 2, 3, 4, 5, 6),
     "line_contig_logw": (-1, 0, 1, 2, 3, 4),
     "line_pad": (-1, 0, 2),
     "max_lds_kb": (-1, 32, 96, 160),
+    "fuse_last": (-1, 0),
 }
 
 

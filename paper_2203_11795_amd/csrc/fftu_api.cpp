@@ -50,6 +50,9 @@ struct fftu_plan_s {
     std::vector<PassDesc> s2;        // Superstep 2 passes (unfused form)
     bool fused = false;
     ExchangeDesc ex{};
+    bool lastx = false;              // k_lastx: the innermost dimension's lines fused with the exchange
+    std::vector<PassDesc> s0x;       // the other Superstep 0 passes, run before k_lastx
+    fftu::LastxDesc lx{};
     // per-kernel timing (fftu_timing_begin / fftu_timing_end)
     std::vector<std::string> launch_names;   // kernel of each launch of fftu_execute
     // batch plans (fftu_plan_batch)
@@ -85,10 +88,10 @@ thread_local fftu_status g_last = FFTU_SUCCESS;
 
 // Planner tuning knobs (fftu_set_tuning); -1 = default.
 // Planner knobs (fftu_set_tuning): process-wide, read when a plan is made.
-std::atomic<int> g_tune[FFTU_TUNE_COUNT] = {{-1}, {-1}, {-1}, {-1}};
+std::atomic<int> g_tune[FFTU_TUNE_COUNT] = {{-1}, {-1}, {-1}, {-1}, {-1}};
 int knob(int i) { return g_tune[i].load(std::memory_order_relaxed); }
-const int g_tune_min[FFTU_TUNE_COUNT] = {2, 0, 0, 16};
-const int g_tune_max[FFTU_TUNE_COUNT] = {6, 8, 4, 160};
+const int g_tune_min[FFTU_TUNE_COUNT] = {2, 0, 0, 16, 0};
+const int g_tune_max[FFTU_TUNE_COUNT] = {6, 8, 4, 160, 1};
 
 int64_t lds_cap()
 {
@@ -462,7 +465,9 @@ bool wave_part_ok(int nh, int lph)
     return nh == 0 || (nh == 1 && (lph == 1 || lph == 2)) || (nh == 2 && lph == 1);
 }
 
-bool exchange_split(const Geometry &G, fftu_dtype dt, ExchangeSplit *out)
+// want_logr >= 0: only splits with exactly that many register bits that k_lastx
+// has compiled for a line of 2^logl (the first such split is taken).
+bool exchange_split(const Geometry &G, fftu_dtype dt, ExchangeSplit *out, int want_logr = -1, int logl = 0)
 {
     const int rmax = dt == FFTU_C128 ? fftu::kExchangeRegBitsF64 : fftu::kExchangeRegBitsF32;
     std::vector<int> dims;
@@ -489,6 +494,8 @@ bool exchange_split(const Geometry &G, fftu_dtype dt, ExchangeSplit *out)
         if (!uniform || logH > fftu::kExchangeMaxWaveBits) continue;
         if (!wave_part_ok(sp.nh, sp.lph) || !reg_part_ok(sp.nr, sp.lpr, rmax)) continue;
         if (logH > 0 && logH > logR) continue;
+        if (want_logr >= 0 && (logR != want_logr || !fftu::lastx_split_ok(logl, sp.nr, sp.lpr, sp.nh, sp.lph)))
+            continue;
         *out = sp;
         return true;
     }
@@ -510,6 +517,57 @@ ExchangeDesc make_exchange(const Geometry &G, const GridDesc &g, const ExchangeS
     const int logR = sp.nr * sp.lpr;   // the LDS swap moves one double (complex128: re, then im) or one complex64
     ex.lds_bytes = sp.nh > 0 ? uint32_t(fftu::kExchangeThreads / 64) * 64u * (1u << logR) * 8u : 0u;
     return ex;
+}
+
+// k_lastx: Superstep 0 of every dimension but the innermost as ordinary passes,
+// then the innermost dimension's lines, the twiddle, the exchange and the
+// length-p FFTs in one kernel. Taken when the innermost dimension would have had
+// a pass of its own (no k_group2 with its neighbour), k_lastx has a kernel for
+// its line length and the grid, and a tile's rows exist.
+bool plan_lastx(const Geometry &G, const GridDesc &g, fftu_dtype dt, std::vector<PassDesc> &s0x,
+                fftu::LastxDesc &lx)
+{
+    if (knob(FFTU_TUNE_FUSE_LAST) == 0) return false;
+    const int li = G.d - 1;
+    const int logl = G.logm[li];
+    if (logl < fftu::kLastxMinLogL || logl > fftu::kLastxMaxLogL) return false;
+    const std::vector<PassDesc> full = plan_s0(G, dt);
+    if (!full.empty() && full[0].kind == fftu::kGroup2) return false;
+    const int loge = fftu::line_loge(logl);
+    ExchangeSplit sp;
+    if (!exchange_split(G, dt, &sp, loge, logl)) return false;
+    const int logrw = fftu::kLastxLogThreads - (logl - loge) - G.logP;
+    if (G.logM - logl < logrw) return false;
+    const int esize = dt == FFTU_C128 ? 16 : 8;
+    const uint32_t lds = fftu::lastx_lds_bytes(logl, G.logP, esize);
+    if (lds > 160u * 1024u) return false;
+    if ((int64_t(1) << (G.logM - logrw - logl)) > fftu::kLastxMaxTiles) return false;
+    s0x.clear();
+    int logB = logl;
+    for (int l = G.d - 2; l >= 0; --l) {
+        if (G.logm[l] > 0) {
+            int logA = G.logP;
+            for (int j = 0; j < l; ++j) logA += G.logm[j];
+            s0x.push_back(make_pass(logA, {G.logm[l]}, logB, dt, G.lognmax));
+        }
+        logB += G.logm[l];
+    }
+    lx = fftu::LastxDesc{};
+    lx.ex = make_exchange(G, g, sp, dt);
+    lx.logl = logl;
+    lx.tiles = int64_t(1) << (G.logM - logrw - logl);
+    lx.lds_bytes = lds;
+    return true;
+}
+
+std::string lastx_kernel_name(const fftu::LastxDesc &lx, fftu_dtype dt)
+{
+    const std::string t = dt == FFTU_C128 ? "double" : "float";
+    auto s = [](int v) { return std::to_string(v); };
+    const ExchangeDesc &ex = lx.ex;
+    const int lph = ex.nh ? ex.lph : 0, lpr = ex.nr ? ex.lpr : 0;
+    return "fftu::k_lastx<" + t + ", " + s(lx.logl) + ", " + s(ex.nr) + ", " + s(lpr) + ", " + s(ex.nh) + ", " +
+           s(lph) + ">";
 }
 
 // omega_L^j = exp(-2 pi i j / L) for j in [L], L = 2^logL, in FP64. Each value is
@@ -724,7 +782,7 @@ void fill_info_mixed(const MixedPlan &mp, fftu_dtype dt, fftu_plan_info *info)
 }
 
 void fill_info(const Geometry &G, const std::vector<PassDesc> &s0, bool fused, size_t nS2, fftu_dtype dt,
-               fftu_plan_info *info)
+               fftu_plan_info *info, bool lastx = false)
 {
     const uint64_t esize = dt == FFTU_C128 ? 16 : 8;
     info->d = G.d;
@@ -735,6 +793,7 @@ void fill_info(const Geometry &G, const std::vector<PassDesc> &s0, bool fused, s
     info->exchange_fused = fused ? 1 : 0;
     info->s2_kernels = fused ? 0 : int32_t(2 + nS2);
     info->launches = info->s0_kernels + (fused ? 1 : info->s2_kernels);
+    if (lastx) info->exchange_fused = 2;   // s0 holds the passes before k_lastx
     info->workspace_bytes = uint64_t(info->N) * esize;
     info->table_bytes = (uint64_t(1) << G.lognmax) * esize;
 }
@@ -1106,7 +1165,14 @@ fftu_plan_s *build_plan(int d, const int64_t n[], const int64_t p[], fftu_dtype 
     ExchangeSplit sp;
     pl->fused = exchange_split(G, dtype, &sp);
     if (pl->fused) pl->ex = make_exchange(G, pl->grid, sp, dtype);
-    {
+    pl->lastx = plan_lastx(G, pl->grid, dtype, pl->s0x, pl->lx);
+    if (pl->lastx) {
+        fftu_plan_info info{};
+        fill_info(G, pl->s0x, true, 0, dtype, &info, true);
+        pl->launches = info.launches;
+        for (const PassDesc &pd : pl->s0x) pl->launch_names.push_back(pass_kernel_name(pd, dtype));
+        pl->launch_names.push_back(lastx_kernel_name(pl->lx, dtype));
+    } else {
         fftu_plan_info info{};
         fill_info(G, pl->s0, pl->fused, pl->s2.size(), dtype, &info);
         pl->launches = info.launches;
@@ -1200,6 +1266,12 @@ fftu_status fftu_describe(int d, const int64_t n[], const int64_t p[], fftu_dtyp
         return record(FFTU_SUCCESS);
     }
     const Geometry G = geometry(d, n, p);
+    std::vector<PassDesc> s0x;
+    fftu::LastxDesc lx;
+    if (plan_lastx(G, make_grid(G), dtype, s0x, lx)) {
+        fill_info(G, s0x, true, 0, dtype, info, true);
+        return record(FFTU_SUCCESS);
+    }
     const auto s0 = plan_s0(G, dtype);
     ExchangeSplit sp;
     const bool fused = exchange_split(G, dtype, &sp);
@@ -1543,7 +1615,10 @@ fftu_status fftu_get_plan_info(fftu_plan_t plan, fftu_plan_info *info)
         return record(FFTU_SUCCESS);
     }
     const Geometry G = geometry(plan->d, plan->n, plan->p);
-    fill_info(G, plan->s0, plan->fused, plan->s2.size(), plan->dtype, info);
+    if (plan->lastx)
+        fill_info(G, plan->s0x, true, 0, plan->dtype, info, true);
+    else
+        fill_info(G, plan->s0, plan->fused, plan->s2.size(), plan->dtype, info);
     return record(FFTU_SUCCESS);
 }
 
@@ -1704,6 +1779,27 @@ fftu_status execute_with(fftu_plan_s *plan, const void *in, void *out, void *ws,
     const int inv = plan->dir == FFTU_INVERSE ? 1 : 0;
     const double scale = inv ? 1.0 / double(plan->grid.N) : 1.0;
     const void *src = in;
+    if (plan->lastx) {
+        if (!plan->s0x.empty()) {
+            s = run_passes(plan, plan->s0x, in, ws, inv, 0, 1.0, stream, &mk);
+            if (s != FFTU_SUCCESS) return s;
+            src = ws;
+        } else if (in == out) {
+            // k_lastx reads every block of a tile before it writes: not in place
+            hipError_t e = hipMemcpyAsync(ws, in, plan->grid.N * plan->esize, hipMemcpyDeviceToDevice, stream);
+            if (e != hipSuccess) return from_hip(e);
+            src = ws;
+        }
+        fftu::LastxDesc lx = plan->lx;
+        lx.conj_in = plan->s0x.empty() ? inv : 0;
+        lx.ex.g.conj_in = 0;
+        lx.ex.g.conj_out = inv;
+        lx.ex.g.scale = scale;
+        lx.ex.mul = mul;
+        hipError_t e = fftu::launch_lastx(plan->prec, src, out, lx, plan->table, stream);
+        if (e == hipSuccess) mk.mark();
+        return from_hip(e);
+    }
     if (!plan->s0.empty()) {
         s = run_passes(plan, plan->s0, in, ws, inv, 0, 1.0, stream, &mk);
         if (s != FFTU_SUCCESS) return s;

@@ -124,7 +124,8 @@ struct LinePlan {
 };
 
 // Radix stage S on the thread's registers (register m <-> position j + TPL m).
-template <typename T, int LOGL, int S>
+// TWG > 0: at most TWG twiddle loads in flight (the caller's register budget).
+template <typename T, int LOGL, int S, int TWG = 0>
 __device__ __forceinline__ void line_compute(cx<T> (&v)[LinePlan<LOGL>::E], int j, const cx<T> *tw)
 {
     using PL = LinePlan<LOGL>;
@@ -137,7 +138,11 @@ __device__ __forceinline__ void line_compute(cx<T> (&v)[LinePlan<LOGL>::E], int 
         if constexpr (S > 0) {
             const int jm = (j + c * PL::TPL) & ((1 << LNS) - 1);
 #pragma unroll
-            for (int r = 1; r < R; ++r) x[r] = cmul(x[r], tw[(r * jm) << (LOGL - LNS - LR)]);
+            for (int r = 1; r < R; ++r) {
+                x[r] = cmul(x[r], tw[(r * jm) << (LOGL - LNS - LR)]);
+                if constexpr (TWG > 0)
+                    if (r % TWG == 0) __builtin_amdgcn_sched_barrier(0);
+            }
         }
         Dft<T, R>::run(x);
 #pragma unroll

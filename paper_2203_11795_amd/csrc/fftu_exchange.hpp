@@ -62,20 +62,21 @@ __device__ __forceinline__ int64_t digit_offset(const int32_t *dims, const Excha
     return off;
 }
 
-// One group of KG x 64 consecutive local indices (starting at group gb): gather,
-// twiddle, transform, swap, transform, scatter. Needs kExchangeThreads threads.
-// With ex.mul set, every output is multiplied by the element of ex.mul at the
-// same position before it is stored (a pointwise product in the output layout).
-template <typename T, int NR, int LPR, int NH, int LPH, bool CO = false>
-__device__ __forceinline__ void exchange_group(const cx<T> *__restrict__ Z, cx<T> *__restrict__ V,
-                                               const ExchangeDesc &ex, const cx<T> *__restrict__ table,
-                                               unsigned char *smem_raw, int64_t gb, int tid)
+// One group of KG x 64 consecutive local indices (starting at group gb) with NT
+// threads: gather, twiddle, transform, swap, transform, scatter. fetch(j, hw, k,
+// valid) returns Z^(s')[k] for the source s' = (hw, j). With ex.mul set, every
+// output is multiplied by the element of ex.mul at the same position before it
+// is stored (a pointwise product in the output layout).
+template <typename T, int NR, int LPR, int NH, int LPH, int NT, bool CO, int TWG, typename FETCH>
+__device__ __forceinline__ void exchange_core(cx<T> *__restrict__ V, const ExchangeDesc &ex,
+                                              const cx<T> *__restrict__ table, unsigned char *smem_raw, int64_t gb,
+                                              int tid, FETCH fetch)
 {
     constexpr int LOGR = NR * LPR, LOGH = NH * LPH;
     constexpr int R = 1 << LOGR;
     constexpr int H = 1 << LOGH;
-    constexpr int U = LOGH > 0 ? R / H : R;         // register slots per thread after the LDS swap
-    constexpr int KG = (kExchangeThreads / 64) / H;  // groups of 64 local indices per workgroup
+    constexpr int U = LOGH > 0 ? R / H : R;   // register slots per thread after the LDS swap
+    constexpr int KG = (NT / 64) / H;         // groups of 64 local indices per workgroup
     const GridDesc &g = ex.g;
     cx<T> *lds = reinterpret_cast<cx<T> *>(smem_raw);
     const int lane = tid & 63;
@@ -113,9 +114,8 @@ __device__ __forceinline__ void exchange_group(const cx<T> *__restrict__ Z, cx<T
 
         // Gather Z^(s')[k] for s' = (hw, j), j in [R], and twiddle.
         cx<T> v[R];
-        const cx<T> *src = Z + ((int64_t(hw) << LOGR) << logM) + k;
 #pragma unroll
-        for (int j = 0; j < R; ++j) v[j] = valid ? src[int64_t(j) << logM] : cx<T>{T(0), T(0)};
+        for (int j = 0; j < R; ++j) v[j] = fetch(j, hw, k, valid);
 #pragma unroll
         for (int j = 0; j < R; ++j) {
             uint32_t e = e_hi;
@@ -123,6 +123,9 @@ __device__ __forceinline__ void exchange_group(const cx<T> *__restrict__ Z, cx<T
             for (int dd = 0; dd < NR; ++dd) e += uint32_t((j >> (LPR * (NR - 1 - dd))) & ((1 << LPR) - 1)) * cr[dd];
             v[j] = conj_if(v[j], g.conj_in);
             if (LOGH > 0 || j > 0) v[j] = cmul(v[j], table[e & emask]);
+            // TWG > 0: at most TWG table loads in flight (register budget of the caller)
+            if constexpr (TWG > 0)
+                if ((j + 1) % TWG == 0) __builtin_amdgcn_sched_barrier(0);
         }
 
         // DFTs over the register dimensions (natural order out).
@@ -191,6 +194,20 @@ __device__ __forceinline__ void exchange_group(const cx<T> *__restrict__ Z, cx<T
                 }
         }
     }
+}
+
+// exchange_core over kExchangeThreads threads, gathering from the S0 output Z.
+template <typename T, int NR, int LPR, int NH, int LPH, bool CO = false>
+__device__ __forceinline__ void exchange_group(const cx<T> *__restrict__ Z, cx<T> *__restrict__ V,
+                                               const ExchangeDesc &ex, const cx<T> *__restrict__ table,
+                                               unsigned char *smem_raw, int64_t gb, int tid)
+{
+    const int logM = ex.g.logmstride[0] + ex.g.logm[0];
+    exchange_core<T, NR, LPR, NH, LPH, kExchangeThreads, CO, 0>(
+        V, ex, table, smem_raw, gb, tid, [&](int j, int hw, int64_t k, bool valid) {
+            const int64_t s = (int64_t(hw) << (NR * LPR)) + j;
+            return valid ? Z[(s << logM) + k] : cx<T>{T(0), T(0)};
+        });
 }
 
 }  // namespace fftu

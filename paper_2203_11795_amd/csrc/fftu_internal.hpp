@@ -97,6 +97,49 @@ struct ExchangeDesc {
     const void *mul;       // null, or N elements in the output layout that every output is multiplied by
 };
 
+// k_lastx (fftu_lastx.hpp): the innermost dimension's Superstep-0 lines fused with
+// the exchange. A workgroup of kLastxThreads threads holds RW rows of all P blocks;
+// its threads hold E = 2^logr elements in both the line plan (a line of 2^logl,
+// line_loge(logl) == logr) and the exchange (logr register bits, logh wave bits).
+constexpr int kLastxLogThreads = 9;
+constexpr int kLastxThreads = 1 << kLastxLogThreads;
+constexpr int kLastxMinLogL = 5;
+constexpr int kLastxMaxLogL = 8;
+constexpr int64_t kLastxMaxTiles = int64_t(1) << 23;   // one workgroup per tile: 2^23 x 512 threads per grid
+
+// Compiled register/wave splits: 2^3 = (2,2,2) or 2^4 = (2,2,2,2) / (4,4) in registers,
+// and none, one 2, two 2s or one 4 across waves.
+constexpr bool lastx_split_ok(int logl, int nr, int lpr, int nh, int lph)
+{
+    const int loge = line_loge(logl);
+    const bool reg = (loge == 3 && nr == 3 && lpr == 1) || (loge == 4 && ((nr == 4 && lpr == 1) || (nr == 2 && lpr == 2)));
+    const bool wave = (nh == 0) || (nh == 1 && (lph == 1 || lph == 2)) || (nh == 2 && lph == 1);
+    const int logh = nh * lph, logp = nr * lpr + logh;
+    const int logtpl = logl - loge;
+    const int logrw = kLastxLogThreads - logtpl - logp;
+    return logl >= kLastxMinLogL && logl <= kLastxMaxLogL && reg && wave && logh <= 2 && logrw >= 0 &&
+           logrw + logl >= 6;
+}
+
+// LDS bytes of k_lastx: omega_L table, then max(transpose, line stages) rows of 8-byte words.
+constexpr uint32_t lastx_lds_bytes(int logl, int logp, int esize)
+{
+    const int L = 1 << logl;
+    const int tpl = 1 << (logl - line_loge(logl));
+    const int lp = L + tpl, pitch = L + L / 16 + 1;
+    const int lines = 1 << (kLastxLogThreads - (logl - line_loge(logl)));
+    (void)logp;
+    return uint32_t(L * esize + lines * (lp > pitch ? lp : pitch) * 8);
+}
+
+struct LastxDesc {
+    ExchangeDesc ex;       // its conj_in must be 0: the lines take the input conjugation
+    int64_t tiles;         // M / (RW m_d)
+    int32_t logl;
+    int32_t conj_in;       // conjugate on load (the first kernel of a plan)
+    uint32_t lds_bytes;
+};
+
 // Mixed-radix path (fftu_mixed.hip): sides with factors 2, 3, 5 and 7.
 constexpr int kMixedThreads = 256;
 constexpr int kMixedMaxStages = 24;
@@ -206,5 +249,7 @@ hipError_t launch_twiddle(Precision prec, const void *in, void *out, const GridD
 hipError_t launch_permute(Precision prec, const void *in, void *out, const GridDesc &g, hipStream_t stream);
 hipError_t launch_exchange(Precision prec, const void *in, void *out, const ExchangeDesc &ex, const void *table,
                            hipStream_t stream);
+hipError_t launch_lastx(Precision prec, const void *in, void *out, const LastxDesc &lx, const void *table,
+                        hipStream_t stream);
 
 }  // namespace fftu

@@ -1,0 +1,186 @@
+// k_lastx: the innermost dimension's Superstep-0 FFTs, Superstep 0's twiddle,
+// Superstep 1 (the one all-to-all) and Superstep 2 (the length-p FFTs) of
+// Algorithm 2.3 (arXiv 2203.11795) in one pass over HBM.
+//
+// Superstep 0 is a d-D FFT per block and its dimensions may be taken in any
+// order (eq. (1.3)), so the other local dimensions run first as ordinary passes
+// and the innermost one comes last. A workgroup takes the same RW consecutive
+// rows (lines along the innermost dimension, fixed k_1 .. k_{d-1}) of every one of
+// the P blocks: P RW lines of m_d contiguous elements, which is all the sources
+// of RW m_d consecutive local indices k. It transforms the lines in registers
+// and LDS (the k_line contiguous layout), transposes through LDS so that each
+// thread holds, for one k, the sources of the exchange's register dimensions,
+// and finishes as k_exchange does: twiddle by prod_l omega_{n_l}^{k_l s'_l},
+// the length-p_l DFTs, and the scatter to V^(r)[t + k' q] (Theorem 2.1).
+//
+// The tile is kLastxThreads threads x E elements, E = 2^LOGR the register
+// sources per thread of the exchange and the elements per thread of the line
+// plan alike. complex128 goes through LDS as two rounds of doubles.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "fftu_device.hpp"
+#include "fftu_exchange.hpp"
+#include "fftu_internal.hpp"
+#include "fftu_line.hpp"
+
+namespace fftu {
+
+template <int LOGL, int LOGR, int LOGH>
+struct LastxShape {
+    using PL = LinePlan<LOGL>;
+    static constexpr int LOGNT = kLastxLogThreads;
+    static constexpr int LOGP = LOGR + LOGH;
+    static constexpr int LOGW = LOGNT - PL::LOGTPL;   // lines per tile: P x RW
+    static constexpr int LOGRW = LOGW - LOGP;         // rows per tile
+    static constexpr int LOGK = LOGRW + LOGL;         // local indices per tile
+    static constexpr int L = 1 << LOGL;
+    static constexpr int LP = L + PL::TPL;            // LDS row of the transpose (padded)
+    static constexpr int PITCH = L + L / 16 + 1;      // LDS row of the line stages (see lidx)
+    static constexpr int WORDS = (1 << LOGW) * (LP > PITCH ? LP : PITCH);   // 8-byte LDS words
+};
+
+// Two workgroups per CU: 4 waves per SIMD, at most 128 VGPRs.
+template <typename T, int LOGL, int NR, int LPR, int NH, int LPH>
+__global__ __launch_bounds__(kLastxThreads, 4) void k_lastx(const cx<T> *__restrict__ in, cx<T> *__restrict__ out,
+                                                         const LastxDesc lx, const cx<T> *__restrict__ table)
+{
+    constexpr int LOGR = NR * LPR, LOGH = NH * LPH;
+    using S = LastxShape<LOGL, LOGR, LOGH>;
+    using PL = typename S::PL;
+    static_assert(lastx_split_ok(LOGL, NR, LPR, NH, LPH), "k_lastx: no such split");
+    static_assert(PL::LOGE == LOGR && S::LOGRW >= 0, "k_lastx: the line plan and the exchange split disagree");
+    static_assert(lastx_lds_bytes(LOGL, S::LOGP, sizeof(cx<T>)) == S::L * sizeof(cx<T>) + S::WORDS * 8,
+                  "k_lastx: LDS size");
+    constexpr int R = 1 << LOGR;
+    constexpr int H = 1 << LOGH;
+    constexpr int KG = (kLastxThreads / 64) / H;
+    static_assert(KG * 64 == (1 << S::LOGK), "k_lastx: one tile is KG groups of 64 local indices");
+
+    extern __shared__ unsigned char smem_raw[];
+    cx<T> *tw = reinterpret_cast<cx<T> *>(smem_raw);
+    unsigned char *work = smem_raw + S::L * sizeof(cx<T>);
+    const int tid = threadIdx.x;
+    line_twiddles<T, LOGL>(tw, table, lx.ex.g.lognmax, tid);
+
+    // line layout: thread (w, j) holds line w = s RW + row, register m <-> position j + TPL m
+    const int j = tid & (PL::TPL - 1);
+    const int w = tid >> PL::LOGTPL;
+    const int s = w >> S::LOGRW;
+    const int row = w & ((1 << S::LOGRW) - 1);
+    // exchange layout: thread (grp, hw, lane) holds local index grp 64 + lane of the tile
+    // for the sources (hw, jj), jj in [R]
+    const int lane = tid & 63;
+    const int wv = tid >> 6;
+    const int hw = wv & (H - 1);
+    const int grp = wv >> LOGH;
+    const int kk = grp * 64 + lane;
+    const int rd = ((hw << LOGR) << S::LOGRW) * S::LP + (kk >> LOGL) * S::LP + (kk & (S::L - 1));
+    const int wr = w * S::LP + j;
+
+    const int logM = lx.ex.g.logmstride[0] + lx.ex.g.logm[0];
+    {
+        const int64_t tile = blockIdx.x;   // one tile per workgroup (the launcher checks the grid)
+        cx<T> v[PL::E];
+        const int64_t base = (int64_t(s) << logM) + (((tile << S::LOGRW) + row) << LOGL);
+#pragma unroll
+        for (int m = 0; m < PL::E; ++m) v[m] = conj_if(in[base + j + m * PL::TPL], lx.conj_in);
+        __syncthreads();   // the omega_L table is in LDS
+
+        line_stages<T, LOGL, kLineContig, 4>(v, j, w, S::PITCH, static_cast<void *>(work), tw, true);
+
+        // transpose: element (s, row, f) to LDS word (s RW + row) LP + f, read back as
+        // (hw R + jj, kk); the register index is the row of R LP RW words
+        cx<T> u[R];
+        __syncthreads();
+        if constexpr (sizeof(T) == 8) {
+            T *ld = reinterpret_cast<T *>(work);
+#pragma unroll
+            for (int m = 0; m < PL::E; ++m) ld[wr + m * PL::TPL] = v[m].x;
+            __syncthreads();
+#pragma unroll
+            for (int jj = 0; jj < R; ++jj) u[jj].x = ld[rd + (jj << S::LOGRW) * S::LP];
+            __syncthreads();
+#pragma unroll
+            for (int m = 0; m < PL::E; ++m) ld[wr + m * PL::TPL] = v[m].y;
+            __syncthreads();
+#pragma unroll
+            for (int jj = 0; jj < R; ++jj) u[jj].y = ld[rd + (jj << S::LOGRW) * S::LP];
+        } else {
+            cx<T> *ld = reinterpret_cast<cx<T> *>(work);
+#pragma unroll
+            for (int m = 0; m < PL::E; ++m) ld[wr + m * PL::TPL] = v[m];
+            __syncthreads();
+#pragma unroll
+            for (int jj = 0; jj < R; ++jj) u[jj] = ld[rd + (jj << S::LOGRW) * S::LP];
+        }
+
+        const int64_t gb = (tile << S::LOGK) >> 6;
+        exchange_core<T, NR, LPR, NH, LPH, kLastxThreads, false, 4>(
+            out, lx.ex, table, work, gb, tid, [&](int jj, int, int64_t, bool) { return u[jj]; });
+    }
+}
+
+namespace lastx_detail {
+
+template <typename T, int LOGL, int NR, int LPR, int NH, int LPH>
+hipError_t go(const void *in, void *out, const LastxDesc &lx, const void *table, hipStream_t stream)
+{
+    if constexpr (lastx_split_ok(LOGL, NR, LPR, NH, LPH)) {
+        if (lx.tiles < 1 || lx.tiles > kLastxMaxTiles) return hipErrorInvalidValue;
+        const uint32_t blocks = uint32_t(lx.tiles);
+        hipLaunchKernelGGL((k_lastx<T, LOGL, NR, LPR, NH, LPH>), dim3(blocks), dim3(kLastxThreads), lx.lds_bytes,
+                           stream, static_cast<const cx<T> *>(in), static_cast<cx<T> *>(out), lx,
+                           static_cast<const cx<T> *>(table));
+        return hipGetLastError();
+    }
+    return hipErrorInvalidValue;
+}
+
+template <typename T, int LOGL, int NR, int LPR>
+hipError_t waves(const void *in, void *out, const LastxDesc &lx, const void *table, hipStream_t stream)
+{
+    const ExchangeDesc &ex = lx.ex;
+    if (ex.nh == 0) return go<T, LOGL, NR, LPR, 0, 0>(in, out, lx, table, stream);
+    if (ex.nh == 1 && ex.lph == 1) return go<T, LOGL, NR, LPR, 1, 1>(in, out, lx, table, stream);
+    if (ex.nh == 1 && ex.lph == 2) return go<T, LOGL, NR, LPR, 1, 2>(in, out, lx, table, stream);
+    if (ex.nh == 2 && ex.lph == 1) return go<T, LOGL, NR, LPR, 2, 1>(in, out, lx, table, stream);
+    return hipErrorInvalidValue;
+}
+
+template <typename T, int LOGL>
+hipError_t regs(const void *in, void *out, const LastxDesc &lx, const void *table, hipStream_t stream)
+{
+    const ExchangeDesc &ex = lx.ex;
+    if constexpr (line_loge(LOGL) == 3) {
+        if (ex.nr == 3 && ex.lpr == 1) return waves<T, LOGL, 3, 1>(in, out, lx, table, stream);
+    } else if constexpr (line_loge(LOGL) == 4) {
+        if (ex.nr == 4 && ex.lpr == 1) return waves<T, LOGL, 4, 1>(in, out, lx, table, stream);
+        if (ex.nr == 2 && ex.lpr == 2) return waves<T, LOGL, 2, 2>(in, out, lx, table, stream);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace lastx_detail
+
+// Host launcher for one element type (instantiated in fftu_lastx_f32.hip / fftu_lastx_f64.hip).
+template <typename T>
+hipError_t launch_lastx_t(const void *in, void *out, const LastxDesc &lx, const void *table, hipStream_t stream)
+{
+    if (lx.ex.g.conj_in != 0) return hipErrorInvalidValue;
+    switch (lx.logl) {
+    case 5: return lastx_detail::regs<T, 5>(in, out, lx, table, stream);
+    case 6: return lastx_detail::regs<T, 6>(in, out, lx, table, stream);
+    case 7: return lastx_detail::regs<T, 7>(in, out, lx, table, stream);
+    case 8: return lastx_detail::regs<T, 8>(in, out, lx, table, stream);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_lastx_f32(const void *in, void *out, const LastxDesc &lx, const void *table, hipStream_t stream);
+hipError_t launch_lastx_f64(const void *in, void *out, const LastxDesc &lx, const void *table, hipStream_t stream);
+
+}  // namespace fftu

@@ -25,6 +25,17 @@ hipError_t launch_exchange(Precision, const void *, void *, const ExchangeDesc &
     if (ex.nh * ex.lph > kExchangeMaxWaveBits || ex.nr * ex.lpr > kExchangeRegBitsF32) std::abort();
     return hipSuccess;
 }
+hipError_t launch_lastx(Precision, const void *, void *, const LastxDesc &lx, const void *, hipStream_t)
+{
+    // a compiled split, a tile that divides the block, LDS within the CU, no input conjugation in the exchange
+    const ExchangeDesc &ex = lx.ex;
+    if (!lastx_split_ok(lx.logl, ex.nr, ex.lpr, ex.nh, ex.lph) || ex.g.conj_in != 0) std::abort();
+    const int logp = ex.nr * ex.lpr + ex.nh * ex.lph;
+    const int logrw = kLastxLogThreads - (lx.logl - line_loge(lx.logl)) - logp;
+    if ((lx.tiles << (logrw + lx.logl)) != ex.g.M || lx.lds_bytes > 160 * 1024) std::abort();
+    if (ex.g.logm[ex.g.d - 1] != lx.logl) std::abort();
+    return hipSuccess;
+}
 hipError_t launch_batch_reset(const BatchDesc &, hipStream_t) { return hipSuccess; }
 hipError_t launch_fill_uniform(Precision, void *, int64_t, uint32_t, uint32_t, uint64_t, hipStream_t) { return hipSuccess; }
 hipError_t launch_pointwise(Precision, const void *, const void *, void *, int64_t, double, hipStream_t) { return hipSuccess; }

@@ -100,7 +100,7 @@ def test_p_max_examples():
 
 
 @pytest.mark.parametrize("n,p,dtype,s0,fused,launches", [
-    ((512, 512, 512), (4, 4, 4), "complex128", 3, 1, 4),
+    ((512, 512, 512), (4, 4, 4), "complex128", 2, 2, 3),    # dims 2, 1 as passes; dim 3 fused with the exchange
     ((64, 64, 64), (2, 2, 2), "complex128", 2, 1, 3),
     ((64,) * 5, (2,) * 5, "complex64", 4, 1, 5),
     ((1024,) * 3, (16, 16, 16), "complex128", 3, 0, 8),
@@ -129,14 +129,14 @@ def test_info_struct_layout_matches_header():
 
 
 def test_tuning_knobs_roundtrip_and_ranges():
-    names = ["line_strided_logw", "line_contig_logw", "line_pad", "max_lds_kb"]
+    names = ["line_strided_logw", "line_contig_logw", "line_pad", "max_lds_kb", "fuse_last"]
     try:
         for name in names:
             assert fftu.get_tuning(name) == -1
         fftu.set_tuning("line_strided_logw", 4)
         assert fftu.get_tuning("line_strided_logw") == 4
         for name, bad in [("line_strided_logw", 1), ("line_strided_logw", 7), ("line_pad", 5), ("max_lds_kb", 8),
-                          ("max_lds_kb", 161), ("line_contig_logw", 9)]:
+                          ("max_lds_kb", 161), ("line_contig_logw", 9), ("fuse_last", 2)]:
             with pytest.raises(fftu.FftuError):
                 fftu.set_tuning(name, bad)
         lib = fftu.load_library()

@@ -209,8 +209,15 @@ def test_512_cubed_full_size(torch_dev):
 def test_launch_names(torch_dev):
     import paper_2203_11795_amd as fftu
     with fftu.Plan((512, 512, 512), (4, 4, 4), "complex128", FORWARD) as plan:
-        assert plan.launch_names() == ["fftu::k_line<double, 7, 2>", "fftu::k_line<double, 7, 1>",
-                                       "fftu::k_line<double, 7, 1>", "fftu::k_exchange<double, 2, 2, 1, 2>"]
+        assert plan.launch_names() == ["fftu::k_line<double, 7, 1>", "fftu::k_line<double, 7, 1>",
+                                       "fftu::k_lastx<double, 7, 2, 2, 1, 2>"]
+    fftu.set_tuning("fuse_last", 0)
+    try:
+        with fftu.Plan((512, 512, 512), (4, 4, 4), "complex128", FORWARD) as plan:
+            assert plan.launch_names() == ["fftu::k_line<double, 7, 2>", "fftu::k_line<double, 7, 1>",
+                                           "fftu::k_line<double, 7, 1>", "fftu::k_exchange<double, 2, 2, 1, 2>"]
+    finally:
+        fftu.set_tuning("fuse_last", -1)
     with fftu.Plan((64,) * 5, (2,) * 5, "complex64", FORWARD) as plan:
         names = plan.launch_names()
         assert names[0] == "fftu::k_group2<float, 5, 5>" and names[-1] == "fftu::k_exchange<float, 5, 1, 0, 0>"
