@@ -124,8 +124,7 @@ struct LinePlan {
 };
 
 // Radix stage S on the thread's registers (register m <-> position j + TPL m).
-// TWG > 0: at most TWG twiddle loads in flight (the caller's register budget).
-template <typename T, int LOGL, int S, int TWG = 0>
+template <typename T, int LOGL, int S>
 __device__ __forceinline__ void line_compute(cx<T> (&v)[LinePlan<LOGL>::E], int j, const cx<T> *tw)
 {
     using PL = LinePlan<LOGL>;
@@ -138,11 +137,7 @@ __device__ __forceinline__ void line_compute(cx<T> (&v)[LinePlan<LOGL>::E], int 
         if constexpr (S > 0) {
             const int jm = (j + c * PL::TPL) & ((1 << LNS) - 1);
 #pragma unroll
-            for (int r = 1; r < R; ++r) {
-                x[r] = cmul(x[r], tw[(r * jm) << (LOGL - LNS - LR)]);
-                if constexpr (TWG > 0)
-                    if (r % TWG == 0) __builtin_amdgcn_sched_barrier(0);
-            }
+            for (int r = 1; r < R; ++r) x[r] = cmul(x[r], tw[(r * jm) << (LOGL - LNS - LR)]);
         }
         Dft<T, R>::run(x);
 #pragma unroll

@@ -62,15 +62,45 @@ __device__ __forceinline__ int64_t digit_offset(const int32_t *dims, const Excha
     return off;
 }
 
-// One group of KG x 64 consecutive local indices (starting at group gb) with NT
-// threads: gather, twiddle, transform, swap, transform, scatter. fetch(j, hw, k,
-// valid) returns Z^(s')[k] for the source s' = (hw, j). With ex.mul set, every
-// output is multiplied by the element of ex.mul at the same position before it
-// is stored (a pointwise product in the output layout).
-template <typename T, int NR, int LPR, int NH, int LPH, int NT, bool CO, int TWG, typename FETCH>
+// Conjugation, scaling and the optional pointwise product of the outputs o[i],
+// stored at V[idx(i)]. MULM 0: the product when ex.mul is set, element by
+// element; 1: never; 2: always, with every multiplier loaded before the first
+// store (loads and stores share one wait counter, so a load issued after a
+// store waits for it).
+template <typename T, bool CO, int MULM, int NOUT, typename IDX>
+__device__ __forceinline__ void exchange_store(cx<T> *__restrict__ V, const ExchangeDesc &ex, cx<T> (&o)[NOUT],
+                                               IDX idx, bool valid)
+{
+    const GridDesc &g = ex.g;
+    const T scale = static_cast<T>(g.scale);
+    const cx<T> *mul = static_cast<const cx<T> *>(ex.mul);
+    cx<T> mv[MULM == 2 ? NOUT : 1];
+    if constexpr (MULM == 2) {
+#pragma unroll
+        for (int i = 0; i < NOUT; ++i) mv[i] = valid ? mul[idx(i)] : cx<T>{T(0), T(0)};
+    }
+#pragma unroll
+    for (int i = 0; i < NOUT; ++i) {
+        cx<T> w = conj_if(o[i], g.conj_out);
+        if (g.scale != 1.0) w = {w.x * scale, w.y * scale};
+        if (valid) {
+            if constexpr (MULM == 2) w = cmul(w, mv[i]);
+            if (MULM == 0 && mul) w = cmul(w, mul[idx(i)]);
+            put<CO>(&V[idx(i)], w);
+        }
+    }
+}
+
+// KG x 64 local indices with NT threads: gather, twiddle, transform, swap,
+// transform, scatter. Thread (grp, hw, lane) handles local index k, which must
+// be the same for every hw of a (grp, lane). fetch(j, hw, k, valid) returns
+// Z^(s')[k] for the source s' = (hw, j). With ex.mul set, every output is
+// multiplied by the element of ex.mul at the same position before it is stored
+// (a pointwise product in the output layout).
+template <typename T, int NR, int LPR, int NH, int LPH, int NT, bool CO, int MULM, typename FETCH>
 __device__ __forceinline__ void exchange_core(cx<T> *__restrict__ V, const ExchangeDesc &ex,
-                                              const cx<T> *__restrict__ table, unsigned char *smem_raw, int64_t gb,
-                                              int tid, FETCH fetch)
+                                              const cx<T> *__restrict__ table, unsigned char *smem_raw,
+                                              const int64_t k, int tid, FETCH fetch)
 {
     constexpr int LOGR = NR * LPR, LOGH = NH * LPH;
     constexpr int R = 1 << LOGR;
@@ -85,9 +115,7 @@ __device__ __forceinline__ void exchange_core(cx<T> *__restrict__ V, const Excha
     const int grp = wv >> LOGH;
     const int logM = g.logmstride[0] + g.logm[0];
     const uint32_t emask = (1u << g.lognmax) - 1;
-    const T scale = static_cast<T>(g.scale);
     {
-        const int64_t k = ((gb + grp) << 6) + lane;
         const bool valid = k < g.M;
 
         // k = r + t p per dimension; c_l = k_l 2^(lognmax - logn_l) is the twiddle step of s'_l.
@@ -123,9 +151,6 @@ __device__ __forceinline__ void exchange_core(cx<T> *__restrict__ V, const Excha
             for (int dd = 0; dd < NR; ++dd) e += uint32_t((j >> (LPR * (NR - 1 - dd))) & ((1 << LPR) - 1)) * cr[dd];
             v[j] = conj_if(v[j], g.conj_in);
             if (LOGH > 0 || j > 0) v[j] = cmul(v[j], table[e & emask]);
-            // TWG > 0: at most TWG table loads in flight (register budget of the caller)
-            if constexpr (TWG > 0)
-                if ((j + 1) % TWG == 0) __builtin_amdgcn_sched_barrier(0);
         }
 
         // DFTs over the register dimensions (natural order out).
@@ -133,16 +158,8 @@ __device__ __forceinline__ void exchange_core(cx<T> *__restrict__ V, const Excha
 
         const int64_t obase = (rank_r << logM) + dst_t;
         if constexpr (LOGH == 0) {
-#pragma unroll
-            for (int j = 0; j < R; ++j) {
-                cx<T> w = conj_if(v[j], g.conj_out);
-                if (g.scale != 1.0) w = {w.x * scale, w.y * scale};
-                const int64_t idx = obase + digit_offset<NR, LPR>(ex.rdim, ex, j);
-                if (valid) {
-                    if (ex.mul) w = cmul(w, static_cast<const cx<T> *>(ex.mul)[idx]);
-                    put<CO>(&V[idx], w);
-                }
-            }
+            exchange_store<T, CO, MULM>(
+                V, ex, v, [&](int j) { return obase + digit_offset<NR, LPR>(ex.rdim, ex, j); }, valid);
         } else {
             // Swap through LDS: register j of wave hw goes to the wave that owns slot j
             // (complex128 in two rounds of doubles, so the swap needs 8 bytes per value).
@@ -179,19 +196,13 @@ __device__ __forceinline__ void exchange_core(cx<T> *__restrict__ V, const Excha
             // DFTs over the wave dimensions, for each of this thread's U register outputs.
             dft_digits<T, NH, LPH, U, U>(w);
 
-#pragma unroll
-            for (int x = 0; x < H; ++x)
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    cx<T> o = conj_if(w[x * U + u], g.conj_out);
-                    if (g.scale != 1.0) o = {o.x * scale, o.y * scale};
-                    const int64_t idx = obase + digit_offset<NH, LPH>(ex.hdim, ex, x) +
-                                        digit_offset<NR, LPR>(ex.rdim, ex, hw * U + u);
-                    if (valid) {
-                        if (ex.mul) o = cmul(o, static_cast<const cx<T> *>(ex.mul)[idx]);
-                        put<CO>(&V[idx], o);
-                    }
-                }
+            exchange_store<T, CO, MULM>(
+                V, ex, w,
+                [&](int i) {
+                    return obase + digit_offset<NH, LPH>(ex.hdim, ex, i / U) +
+                           digit_offset<NR, LPR>(ex.rdim, ex, hw * U + i % U);
+                },
+                valid);
         }
     }
 }
@@ -203,8 +214,10 @@ __device__ __forceinline__ void exchange_group(const cx<T> *__restrict__ Z, cx<T
                                                unsigned char *smem_raw, int64_t gb, int tid)
 {
     const int logM = ex.g.logmstride[0] + ex.g.logm[0];
+    constexpr int H = 1 << (NH * LPH);
+    const int64_t k = ((gb + ((tid >> 6) / H)) << 6) + (tid & 63);   // group grp = wave / H, one index per lane
     exchange_core<T, NR, LPR, NH, LPH, kExchangeThreads, CO, 0>(
-        V, ex, table, smem_raw, gb, tid, [&](int j, int hw, int64_t k, bool valid) {
+        V, ex, table, smem_raw, k, tid, [&](int j, int hw, int64_t k, bool valid) {
             const int64_t s = (int64_t(hw) << (NR * LPR)) + j;
             return valid ? Z[(s << logM) + k] : cx<T>{T(0), T(0)};
         });

@@ -38,14 +38,16 @@ struct LastxShape {
     static constexpr int LOGRW = LOGW - LOGP;         // rows per tile
     static constexpr int LOGK = LOGRW + LOGL;         // local indices per tile
     static constexpr int L = 1 << LOGL;
-    static constexpr int LP = L + PL::TPL;            // LDS row of the transpose (padded)
+    static constexpr int LP = L + PL::TPL;            // LDS row of the transpose: L + L/32 swizzled words, padded
     static constexpr int PITCH = L + L / 16 + 1;      // LDS row of the line stages (see lidx)
     static constexpr int WORDS = (1 << LOGW) * (LP > PITCH ? LP : PITCH);   // 8-byte LDS words
 };
 
-// Two workgroups per CU: 4 waves per SIMD, at most 128 VGPRs.
-template <typename T, int LOGL, int NR, int LPR, int NH, int LPH>
-__global__ __launch_bounds__(kLastxThreads, 4) void k_lastx(const cx<T> *__restrict__ in, cx<T> *__restrict__ out,
+// Two workgroups per CU: 4 waves per SIMD, at most 128 VGPRs. MUL: every output is
+// multiplied by lx.ex.mul at its position (convolution); the multipliers are all
+// loaded before the stores, which takes more registers (one workgroup per CU).
+template <typename T, int LOGL, int NR, int LPR, int NH, int LPH, bool MUL>
+__global__ __launch_bounds__(kLastxThreads, MUL ? 2 : 4) void k_lastx(const cx<T> *__restrict__ in, cx<T> *__restrict__ out,
                                                          const LastxDesc lx, const cx<T> *__restrict__ table)
 {
     constexpr int LOGR = NR * LPR, LOGH = NH * LPH;
@@ -71,15 +73,20 @@ __global__ __launch_bounds__(kLastxThreads, 4) void k_lastx(const cx<T> *__restr
     const int w = tid >> PL::LOGTPL;
     const int s = w >> S::LOGRW;
     const int row = w & ((1 << S::LOGRW) - 1);
-    // exchange layout: thread (grp, hw, lane) holds local index grp 64 + lane of the tile
-    // for the sources (hw, jj), jj in [R]
+    // exchange layout: thread (grp, hw, lane) holds, for the sources (hw, jj), jj in [R],
+    // tile index i = grp 64 + lane taken as (row, r_d, t_d) with t_d fastest, i.e. the local
+    // index k_d = r_d + p_d t_d of that row, so that consecutive lanes store consecutive t_d
+    // (runs of q_d elements in one destination block)
     const int lane = tid & 63;
     const int wv = tid >> 6;
     const int hw = wv & (H - 1);
     const int grp = wv >> LOGH;
-    const int kk = grp * 64 + lane;
-    const int rd = ((hw << LOGR) << S::LOGRW) * S::LP + (kk >> LOGL) * S::LP + (kk & (S::L - 1));
-    const int wr = w * S::LP + j;
+    const int lpd = lx.ex.g.logp[lx.ex.g.d - 1];
+    const int i = grp * 64 + lane;
+    const int f = (((i & (S::L - 1)) & ((S::L >> lpd) - 1)) << lpd) + ((i & (S::L - 1)) >> (LOGL - lpd));
+    const int kk = (i & ~(S::L - 1)) + f;
+    // LDS word of line position x: x + x / 32 keeps reads at a stride of p_d on distinct banks
+    const int rd = ((hw << LOGR) << S::LOGRW) * S::LP + (kk >> LOGL) * S::LP + f + (f >> 5);
 
     const int logM = lx.ex.g.logmstride[0] + lx.ex.g.logm[0];
     {
@@ -90,37 +97,40 @@ __global__ __launch_bounds__(kLastxThreads, 4) void k_lastx(const cx<T> *__restr
         for (int m = 0; m < PL::E; ++m) v[m] = conj_if(in[base + j + m * PL::TPL], lx.conj_in);
         __syncthreads();   // the omega_L table is in LDS
 
-        line_stages<T, LOGL, kLineContig, 4>(v, j, w, S::PITCH, static_cast<void *>(work), tw, true);
+        line_stages<T, LOGL, kLineContig>(v, j, w, S::PITCH, static_cast<void *>(work), tw, true);
 
-        // transpose: element (s, row, f) to LDS word (s RW + row) LP + f, read back as
-        // (hw R + jj, kk); the register index is the row of R LP RW words
+        // transpose: element (s, row, x) to LDS word (s RW + row) LP + x + x / 32, read back
+        // as (hw R + jj, kk); the register index is the row of R LP RW words
         cx<T> u[R];
+        auto wr = [&](int m) {
+            const int x = j + m * PL::TPL;
+            return w * S::LP + x + (x >> 5);
+        };
         __syncthreads();
         if constexpr (sizeof(T) == 8) {
             T *ld = reinterpret_cast<T *>(work);
 #pragma unroll
-            for (int m = 0; m < PL::E; ++m) ld[wr + m * PL::TPL] = v[m].x;
+            for (int m = 0; m < PL::E; ++m) ld[wr(m)] = v[m].x;
             __syncthreads();
 #pragma unroll
             for (int jj = 0; jj < R; ++jj) u[jj].x = ld[rd + (jj << S::LOGRW) * S::LP];
             __syncthreads();
 #pragma unroll
-            for (int m = 0; m < PL::E; ++m) ld[wr + m * PL::TPL] = v[m].y;
+            for (int m = 0; m < PL::E; ++m) ld[wr(m)] = v[m].y;
             __syncthreads();
 #pragma unroll
             for (int jj = 0; jj < R; ++jj) u[jj].y = ld[rd + (jj << S::LOGRW) * S::LP];
         } else {
             cx<T> *ld = reinterpret_cast<cx<T> *>(work);
 #pragma unroll
-            for (int m = 0; m < PL::E; ++m) ld[wr + m * PL::TPL] = v[m];
+            for (int m = 0; m < PL::E; ++m) ld[wr(m)] = v[m];
             __syncthreads();
 #pragma unroll
             for (int jj = 0; jj < R; ++jj) u[jj] = ld[rd + (jj << S::LOGRW) * S::LP];
         }
 
-        const int64_t gb = (tile << S::LOGK) >> 6;
-        exchange_core<T, NR, LPR, NH, LPH, kLastxThreads, false, 4>(
-            out, lx.ex, table, work, gb, tid, [&](int jj, int, int64_t, bool) { return u[jj]; });
+        exchange_core<T, NR, LPR, NH, LPH, kLastxThreads, false, MUL ? 2 : 1>(
+            out, lx.ex, table, work, (tile << S::LOGK) + kk, tid, [&](int jj, int, int64_t, bool) { return u[jj]; });
     }
 }
 
@@ -132,9 +142,14 @@ hipError_t go(const void *in, void *out, const LastxDesc &lx, const void *table,
     if constexpr (lastx_split_ok(LOGL, NR, LPR, NH, LPH)) {
         if (lx.tiles < 1 || lx.tiles > kLastxMaxTiles) return hipErrorInvalidValue;
         const uint32_t blocks = uint32_t(lx.tiles);
-        hipLaunchKernelGGL((k_lastx<T, LOGL, NR, LPR, NH, LPH>), dim3(blocks), dim3(kLastxThreads), lx.lds_bytes,
-                           stream, static_cast<const cx<T> *>(in), static_cast<cx<T> *>(out), lx,
-                           static_cast<const cx<T> *>(table));
+        if (lx.ex.mul)
+            hipLaunchKernelGGL((k_lastx<T, LOGL, NR, LPR, NH, LPH, true>), dim3(blocks), dim3(kLastxThreads),
+                               lx.lds_bytes, stream, static_cast<const cx<T> *>(in), static_cast<cx<T> *>(out), lx,
+                               static_cast<const cx<T> *>(table));
+        else
+            hipLaunchKernelGGL((k_lastx<T, LOGL, NR, LPR, NH, LPH, false>), dim3(blocks), dim3(kLastxThreads),
+                               lx.lds_bytes, stream, static_cast<const cx<T> *>(in), static_cast<cx<T> *>(out), lx,
+                               static_cast<const cx<T> *>(table));
         return hipGetLastError();
     }
     return hipErrorInvalidValue;

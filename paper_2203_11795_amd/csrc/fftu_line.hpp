@@ -71,20 +71,20 @@ __device__ __forceinline__ void line_exchange(cx<T> (&v)[LinePlan<LOGL>::E], int
     }
 }
 
-template <typename T, int LOGL, int MODE, int TWG = 0>
+template <typename T, int LOGL, int MODE>
 __device__ __forceinline__ void line_stages(cx<T> (&v)[LinePlan<LOGL>::E], int j, int w, int pitch, void *smem,
                                             const cx<T> *tw, bool active)
 {
     using PL = LinePlan<LOGL>;
-    if (active) line_compute<T, LOGL, 0, TWG>(v, j, tw);
+    if (active) line_compute<T, LOGL, 0>(v, j, tw);
     if constexpr (PL::NS > 1) {
         line_exchange<T, LOGL, 0, MODE>(v, j, w, pitch, smem, active);
-        if (active) line_compute<T, LOGL, 1, TWG>(v, j, tw);
+        if (active) line_compute<T, LOGL, 1>(v, j, tw);
     }
     if constexpr (PL::NS > 2) {
         __syncthreads();
         line_exchange<T, LOGL, 1, MODE>(v, j, w, pitch, smem, active);
-        if (active) line_compute<T, LOGL, 2, TWG>(v, j, tw);
+        if (active) line_compute<T, LOGL, 2>(v, j, tw);
     }
 }
 

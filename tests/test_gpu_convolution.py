@@ -104,3 +104,30 @@ def test_pointwise_product(torch, dtype):
     fftu.pointwise_mul(da, db, out=da)                        # in place on a
     torch.cuda.synchronize()
     assert np.abs(da.cpu().numpy().astype(np.complex128) - 2 * want).max() <= 8 * eps
+
+
+@pytest.mark.parametrize("n,p", [((16, 32, 512), (4, 4, 4)), ((4, 4, 4, 4, 64), (2, 2, 2, 2, 2))])
+@pytest.mark.parametrize("dtype", ["complex64", "complex128"])
+def test_convolution_through_fused_last_dimension(torch, n, p, dtype):
+    """Forward plans whose innermost dimension is fused with the exchange (k_lastx)
+    carry the pointwise product in that kernel. x has 40 nonzeros so that the direct
+    sum of the definition stays cheap; its transform is dense all the same."""
+    import paper_2203_11795_amd as fftu
+    N = int(np.prod(n))
+    rng = np.random.default_rng(41)
+    x = np.zeros(N, np.complex128)
+    pos = rng.choice(N, 40, replace=False)
+    x[pos] = rng.uniform(-1, 1, 40) + 1j * rng.uniform(-1, 1, 40)
+    x = x.astype(NP[dtype]).reshape(n)
+    h = synth.uniform_complex(N, 42, NP[dtype]).reshape(n)
+    want = oracle.circular_convolution(x.astype(np.complex128), h.astype(np.complex128))
+    with fftu.ConvolutionPlan(n, p, dtype) as plan:
+        assert plan.info()["exchange_fused"] == 2
+        xc = dev(torch, oracle.to_cyclic(x, p).astype(NP[dtype]))
+        hhat = plan(dev(torch, oracle.to_cyclic(h, p).astype(NP[dtype])))
+        y = plan.convolve(xc, hhat)
+        torch.cuda.synchronize()
+        got = oracle.from_cyclic(y.cpu().numpy().astype(np.complex128), n, p)
+        err = oracle.rel_l2(got, want)
+        say(f"convolution (fused last dimension) {n} over {p} {dtype}: rel-L2 {err:.2e}")
+        assert err <= TOL[dtype]
