@@ -145,17 +145,35 @@ __device__ __forceinline__ void line_compute(cx<T> (&v)[LinePlan<LOGL>::E], int 
     }
 }
 
-// Store of one element. With CO (device-coherent), the store is a device-scope
-// relaxed atomic: it is written through to the level that every workgroup of the
-// device reads from, so that once the storing thread has waited for its stores
-// to complete, other workgroups (on any XCD) can read the value after an
-// acquire, with no write-back of the storing XCD's L2. complex128 goes as two
-// 8-byte halves.
+// Load of one element of a pass's input. Each pass streams its array through
+// once, so the load is non-temporal (the caches need not keep the line); this
+// measured several per cent faster per pass than plain loads. CO: a plain load
+// (the persistent batch kernel reads what other workgroups wrote).
+template <bool CO = false, typename T>
+__device__ __forceinline__ cx<T> get(const cx<T> *p)
+{
+    if constexpr (CO) {
+        return *p;
+    } else {
+        typedef T v2 __attribute__((ext_vector_type(2)));
+        const v2 r = __builtin_nontemporal_load(reinterpret_cast<const v2 *>(p));
+        return cx<T>{r.x, r.y};
+    }
+}
+
+// Store of one element: non-temporal, as get(). With CO (device-coherent), the
+// store is a device-scope relaxed atomic instead: it is written through to the
+// level that every workgroup of the device reads from, so that once the storing
+// thread has waited for its stores to complete, other workgroups (on any XCD)
+// can read the value after an acquire, with no write-back of the storing XCD's
+// L2. complex128 goes as two 8-byte halves.
 template <bool CO, typename T>
 __device__ __forceinline__ void put(cx<T> *p, const cx<T> &v)
 {
     if constexpr (!CO) {
-        *p = v;
+        typedef T v2 __attribute__((ext_vector_type(2)));
+        const v2 val = {v.x, v.y};
+        __builtin_nontemporal_store(val, reinterpret_cast<v2 *>(p));
     } else if constexpr (sizeof(T) == 4) {
         uint64_t u;
         __builtin_memcpy(&u, &v, 8);

@@ -219,7 +219,7 @@ __device__ __forceinline__ void exchange_group(const cx<T> *__restrict__ Z, cx<T
     exchange_core<T, NR, LPR, NH, LPH, kExchangeThreads, CO, 0>(
         V, ex, table, smem_raw, k, tid, [&](int j, int hw, int64_t k, bool valid) {
             const int64_t s = (int64_t(hw) << (NR * LPR)) + j;
-            return valid ? Z[(s << logM) + k] : cx<T>{T(0), T(0)};
+            return valid ? get<CO>(&Z[(s << logM) + k]) : cx<T>{T(0), T(0)};
         });
 }
 

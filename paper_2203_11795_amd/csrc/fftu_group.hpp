@@ -102,7 +102,7 @@ __device__ __forceinline__ void group2_tile(const cx<T> *in, cx<T> *out, const P
         cx<T> r[kGroupUnroll];
 #pragma unroll
         for (int u = 0; u < kGroupUnroll; ++u)
-            if (e0 + u * nt < n) r[u] = in[gbase + e0 + u * nt];
+            if (e0 + u * nt < n) r[u] = get<CO>(&in[gbase + e0 + u * nt]);
 #pragma unroll
         for (int u = 0; u < kGroupUnroll; ++u) {
             const int e = e0 + u * nt;

@@ -104,7 +104,7 @@ __device__ __forceinline__ void pass_tile(const cx<T> *in, cx<T> *out, const Pas
         const int pos = (e >> pd.logBt) & gmask;
         const int ap = e >> (pd.logBt + pd.logG);
         const int64_t goff = gbase + int64_t(ap) * pd.GB + (int64_t(pos) << pd.logB) + b;
-        buf[pos * pd.lw + ((ap << pd.logBt) | b)] = conj_if(in[goff], pd.conj_in);
+        buf[pos * pd.lw + ((ap << pd.logBt) | b)] = conj_if(get(&in[goff]), pd.conj_in);
     }
     __syncthreads();
 
@@ -131,7 +131,7 @@ __device__ __forceinline__ void pass_tile(const cx<T> *in, cx<T> *out, const Pas
         const int64_t goff = gbase + int64_t(ap) * pd.GB + (int64_t(pos) << pd.logB) + b;
         cx<T> v = conj_if(buf[pos * pd.lw + ((ap << pd.logBt) | b)], pd.conj_out);
         if (pd.scale != 1.0) v = {v.x * scale, v.y * scale};
-        out[goff] = v;
+        put<false>(&out[goff], v);
     }
 }
 
@@ -174,8 +174,8 @@ __global__ __launch_bounds__(kPointwiseThreads) void k_twiddle(const cx<T> *in, 
     const int logM = g.logmstride[0] + g.logm[0];
     for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < g.N; i += stride) {
         const int64_t s = i >> logM, k = i & ((int64_t(1) << logM) - 1);
-        cx<T> v = cmul(conj_if(in[i], g.conj_in), table[twiddle_exponent(g, s, k)]);
-        out[i] = conj_if(v, g.conj_out);
+        cx<T> v = cmul(conj_if(get(&in[i]), g.conj_in), table[twiddle_exponent(g, s, k)]);
+        put<false>(&out[i], conj_if(v, g.conj_out));
     }
 }
 
@@ -198,7 +198,7 @@ __global__ __launch_bounds__(kPointwiseThreads) void k_permute(const cx<T> *__re
             s += sl << g.logpstride[l];
             src += (rl + (tl << g.logp[l])) << g.logmstride[l];
         }
-        out[j] = in[(s << logM) + src];
+        put<false>(&out[j], get(&in[(s << logM) + src]));
     }
 }
 

@@ -94,7 +94,7 @@ __global__ __launch_bounds__(kLastxThreads, MUL ? 2 : 4) void k_lastx(const cx<T
         cx<T> v[PL::E];
         const int64_t base = (int64_t(s) << logM) + (((tile << S::LOGRW) + row) << LOGL);
 #pragma unroll
-        for (int m = 0; m < PL::E; ++m) v[m] = conj_if(in[base + j + m * PL::TPL], lx.conj_in);
+        for (int m = 0; m < PL::E; ++m) v[m] = conj_if(get(&in[base + j + m * PL::TPL]), lx.conj_in);
         __syncthreads();   // the omega_L table is in LDS
 
         line_stages<T, LOGL, kLineContig>(v, j, w, S::PITCH, static_cast<void *>(work), tw, true);

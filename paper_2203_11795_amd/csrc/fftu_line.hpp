@@ -131,7 +131,7 @@ __device__ __forceinline__ void line_tile(const cx<T> *in, cx<T> *out, const Pas
         if (active) {
             cx<T> r[PL::E];
 #pragma unroll
-            for (int c = 0; c < PL::E; ++c) r[c] = in[tbase + tid + c * pd.threads];
+            for (int c = 0; c < PL::E; ++c) r[c] = get<CO>(&in[tbase + tid + c * pd.threads]);
 #pragma unroll
             for (int c = 0; c < PL::E; ++c) {
                 const int e = tid + c * pd.threads;
@@ -144,7 +144,7 @@ __device__ __forceinline__ void line_tile(const cx<T> *in, cx<T> *out, const Pas
         __syncthreads();
     } else if (active) {
 #pragma unroll
-        for (int m = 0; m < PL::E; ++m) v[m] = conj_if(in[base + int64_t(j + m * PL::TPL) * xstride], pd.conj_in);
+        for (int m = 0; m < PL::E; ++m) v[m] = conj_if(get<CO>(&in[base + int64_t(j + m * PL::TPL) * xstride]), pd.conj_in);
     }
 
     line_stages<T, LOGL, MODE>(v, j, w, pitch, static_cast<void *>(lds), tw, active);

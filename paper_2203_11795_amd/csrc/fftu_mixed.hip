@@ -112,7 +112,7 @@ __global__ __launch_bounds__(kMixedThreads) void k_mline(const cx<T> *in, cx<T> 
             const uint32_t u = u0 + uint32_t(w);
             const uint32_t a = u / B;
             const uint32_t b = u - a * B;
-            buf0[w * L + x] = conj_if(in[(int64_t(a) * L + x) * B + b], pd.conj_in);
+            buf0[w * L + x] = conj_if(get(&in[(int64_t(a) * L + x) * B + b]), pd.conj_in);
         }
         __syncthreads();
         cx<T> *src = buf0, *dst = buf1;
@@ -142,7 +142,7 @@ __global__ __launch_bounds__(kMixedThreads) void k_mline(const cx<T> *in, cx<T> 
             const int64_t addr = (int64_t(a) * L + x) * B + b;
             cx<T> v = conj_if(src[w * L + x], pd.conj_out);
             if (pd.scale != 1.0) v = {v.x * scale, v.y * scale};
-            out[addr] = v;
+            put<false>(&out[addr], v);
         }
     }
 }
@@ -163,9 +163,9 @@ __global__ __launch_bounds__(256) void k_mtwiddle(const cx<T> *in, cx<T> *out, c
             k /= uint32_t(g.m[l]);
             e += int64_t(kl) * sl * g.tstep[l];      // k_l s_l < n_l, times T / n_l: below T
         }
-        cx<T> v = conj_if(in[i], g.conj_in);
+        cx<T> v = conj_if(get(&in[i]), g.conj_in);
         v = cmul(v, table[e % g.T]);
-        out[i] = conj_if(v, g.conj_out);
+        put<false>(&out[i], conj_if(v, g.conj_out));
     }
 }
 
@@ -195,11 +195,11 @@ __global__ __launch_bounds__(256) void k_mpermute(const cx<T> *in, cx<T> *out, c
             rmul *= g.p[l];
             kmul *= g.m[l];
         }
-        cx<T> v = conj_if(in[src_rank * g.M + src_k], g.conj_in);
+        cx<T> v = conj_if(get(&in[src_rank * g.M + src_k]), g.conj_in);
         if (g.twiddle) v = cmul(v, table[e % g.T]);
         v = conj_if(v, g.conj_out);
         if (g.scale != 1.0) v = {v.x * scale, v.y * scale};
-        out[i] = v;
+        put<false>(&out[i], v);
     }
 }
 
