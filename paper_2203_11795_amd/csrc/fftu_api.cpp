@@ -40,6 +40,7 @@ struct fftu_plan_s {
     fftu_plan_s *conv_inv = nullptr; // fftu_plan_convolution: the inverse plan (external, uses this plan's workspace)
     // mixed-radix plans (some side not a power of two)
     bool mixed = false;
+    bool mfused = false;             // mixed radix with k_mexchange
     std::vector<fftu::MixedPassDesc> ms0, ms2;
     fftu::MixedGridDesc mg{};
     int64_t table_T = 0;             // entries of the twiddle table omega_T
@@ -719,6 +720,7 @@ struct MixedPlan {
     std::vector<fftu::MixedPassDesc> s0, s2;
     fftu::MixedGridDesc g{};
     int64_t T = 1;
+    bool fused = false;   // k_mexchange: twiddle, Put and Superstep 2 in one kernel
 };
 
 bool plan_mixed(int d, const int64_t n[], const int64_t p[], fftu_dtype dt, MixedPlan &mp)
@@ -762,6 +764,8 @@ bool plan_mixed(int d, const int64_t n[], const int64_t p[], fftu_dtype dt, Mixe
         if (!make_mixed_pass(A, g.p[l], B, dt, mp.T, pd)) return false;
         mp.s2.push_back(pd);
     }
+    mp.fused = g.P <= fftu::kMexMaxP;
+    for (int l = 0; l < d; ++l) mp.fused = mp.fused && fftu::mexchange_radix_ok(g.p[l]);
     return true;
 }
 
@@ -774,9 +778,10 @@ void fill_info_mixed(const MixedPlan &mp, fftu_dtype dt, fftu_plan_info *info)
     info->P = mp.g.P;
     info->M = mp.g.M;
     info->s0_kernels = int32_t(mp.s0.size());
-    info->exchange_fused = 0;
-    info->s2_kernels = int32_t(1 + mp.s2.size());   // twiddle + permutation in one kernel, then the passes
-    info->launches = info->s0_kernels + info->s2_kernels;
+    info->exchange_fused = mp.fused ? 1 : 0;
+    // fused: one k_mexchange; else twiddle + permutation in one kernel, then the passes
+    info->s2_kernels = mp.fused ? 0 : int32_t(1 + mp.s2.size());
+    info->launches = info->s0_kernels + (mp.fused ? 1 : info->s2_kernels);
     info->workspace_bytes = uint64_t(mp.g.N) * esize;
     info->table_bytes = uint64_t(mp.T) * esize;
 }
@@ -1092,11 +1097,16 @@ fftu_plan_s *build_mixed_plan(int d, const int64_t n[], const int64_t p[], fftu_
     pl->grid.N = mp.g.N;
     pl->grid.M = mp.g.M;
     pl->grid.d = d;
-    pl->launches = int(mp.s0.size() + 1 + mp.s2.size());
+    pl->mfused = mp.fused;
+    pl->launches = int(mp.s0.size() + 1 + (mp.fused ? 0 : mp.s2.size()));
     const std::string t = dtype == FFTU_C128 ? "double" : "float";
     for (size_t i = 0; i < mp.s0.size(); ++i) pl->launch_names.push_back("fftu::k_mline<" + t + ">");
-    pl->launch_names.push_back("fftu::k_mpermute<" + t + ">");
-    for (size_t i = 0; i < mp.s2.size(); ++i) pl->launch_names.push_back("fftu::k_mline<" + t + ">");
+    if (mp.fused) {
+        pl->launch_names.push_back("fftu::k_mexchange<" + t + ">");
+    } else {
+        pl->launch_names.push_back("fftu::k_mpermute<" + t + ">");
+        for (size_t i = 0; i < mp.s2.size(); ++i) pl->launch_names.push_back("fftu::k_mline<" + t + ">");
+    }
     hipError_t e = hipSuccess;
     if (external) {
         e = shared_table_exact(device, dtype, mp.T, &pl->table);
@@ -1611,6 +1621,7 @@ fftu_status fftu_get_plan_info(fftu_plan_t plan, fftu_plan_info *info)
         mp.s2 = plan->ms2;
         mp.g = plan->mg;
         mp.T = plan->table_T;
+        mp.fused = plan->mfused;
         fill_info_mixed(mp, plan->dtype, info);
         return record(FFTU_SUCCESS);
     }
@@ -1751,6 +1762,18 @@ fftu_status execute_mixed(fftu_plan_s *plan, const void *in, void *out, void *ws
     g.conj_in = g.conj_out = 0;
     g.twiddle = 1;
     g.scale = 1.0;
+    g.mul = nullptr;
+    if (plan->mfused) {
+        g.conj_in = plan->ms0.empty() ? inv : 0;
+        g.conj_out = inv;
+        g.scale = scale;
+        g.mul = mul;
+        const void *src = ws;
+        if (plan->ms0.empty() && in != out) src = in;
+        hipError_t e = fftu::launch_mexchange(plan->prec, src, out, g, plan->table, stream);
+        if (e == hipSuccess) mk.mark();
+        return from_hip(e);
+    }
     if (plan->ms2.empty()) {
         g.conj_out = inv;
         g.scale = scale;

@@ -142,6 +142,7 @@ struct LastxDesc {
 
 // Mixed-radix path (fftu_mixed.hip): sides with factors 2, 3, 5 and 7.
 constexpr int kMixedThreads = 256;
+constexpr int kMixedBatch = 4;         // global loads per thread in flight in k_mline
 constexpr int kMixedMaxStages = 24;
 
 // A pass of 1-D FFTs of length L over an array viewed as (A, L, B), B the
@@ -169,9 +170,19 @@ struct MixedGridDesc {
     int64_t tstep[kMaxDims];   // T / n_l
     int64_t T;
     int32_t conj_in, conj_out;
-    int32_t twiddle;           // k_mpermute: apply Superstep 0's twiddle on the way
+    int32_t twiddle;           // k_mpermute / k_mexchange: apply Superstep 0's twiddle on the way
     double scale;
+    const void *mul;           // k_mexchange: null, or N elements in the output layout to multiply by
 };
+
+// k_mexchange: P sources of 64 local indices in LDS, grid sides of one radix stage.
+constexpr int64_t kMexMaxP = 64;
+constexpr int kMexThreads = 512;
+constexpr int kMexBatch = 8;           // source loads per lane in flight
+constexpr bool mexchange_radix_ok(int p)
+{
+    return p == 1 || p == 2 || p == 3 || p == 4 || p == 5 || p == 7 || p == 8;
+}
 
 // Persistent batch (fftu_batch.hip). One descriptor per (stage, transform).
 constexpr int kBatchThreads = 256;
@@ -237,6 +248,8 @@ hipError_t launch_mtwiddle(Precision prec, const void *in, void *out, const Mixe
                            hipStream_t stream);
 hipError_t launch_mpermute(Precision prec, const void *in, void *out, const MixedGridDesc &g, const void *table,
                            hipStream_t stream);
+hipError_t launch_mexchange(Precision prec, const void *in, void *out, const MixedGridDesc &g, const void *table,
+                            hipStream_t stream);
 hipError_t launch_pointwise(Precision prec, const void *a, const void *b, void *out, int64_t count, double scale,
                             hipStream_t stream);
 hipError_t launch_fill_uniform(Precision prec, void *out, int64_t count, uint32_t k0, uint32_t k1, uint64_t base,

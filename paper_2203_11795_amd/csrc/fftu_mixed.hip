@@ -105,14 +105,34 @@ __global__ __launch_bounds__(kMixedThreads) void k_mline(const cx<T> *in, cx<T> 
         const int lines = int(total - u0 < uint32_t(W) ? total - u0 : uint32_t(W));
         __syncthreads();   // twiddle copy done / previous tile's LDS reads done
         const int n = lines * L;
-        for (int e = tid; e < n; e += nt) {
-            // lanes run over consecutive lines (consecutive b: runs of up to min(W, B) elements)
+        // element e of the tile: LDS offset (line w, position x) and global offset. With
+        // B = 1 the tile's lines are contiguous in memory and e runs along them; otherwise
+        // lanes run over consecutive lines (consecutive b: runs of up to min(W, B) elements).
+        auto where = [&](int e, int &off) -> int64_t {
+            if (B == 1) {
+                off = e;
+                return int64_t(u0) * L + e;
+            }
             const int x = e / lines;
             const int w = e - x * lines;
+            off = w * L + x;
             const uint32_t u = u0 + uint32_t(w);
             const uint32_t a = u / B;
             const uint32_t b = u - a * B;
-            buf0[w * L + x] = conj_if(get(&in[(int64_t(a) * L + x) * B + b]), pd.conj_in);
+            return (int64_t(a) * L + x) * B + b;
+        };
+        // kMixedBatch loads per thread in flight, then their LDS stores
+        for (int e0 = tid; e0 < n; e0 += kMixedBatch * nt) {
+            cx<T> r[kMixedBatch];
+            int off[kMixedBatch];
+#pragma unroll
+            for (int i = 0; i < kMixedBatch; ++i) {
+                const int e = e0 + i * nt;
+                if (e < n) r[i] = get(&in[where(e, off[i])]);
+            }
+#pragma unroll
+            for (int i = 0; i < kMixedBatch; ++i)
+                if (e0 + i * nt < n) buf0[off[i]] = conj_if(r[i], pd.conj_in);
         }
         __syncthreads();
         cx<T> *src = buf0, *dst = buf1;
@@ -133,16 +153,18 @@ __global__ __launch_bounds__(kMixedThreads) void k_mline(const cx<T> *in, cx<T> 
             dst = tmp;
             Ns *= pd.radix[s];
         }
-        for (int e = tid; e < n; e += nt) {
-            const int x = e / lines;
-            const int w = e - x * lines;
-            const uint32_t u = u0 + uint32_t(w);
-            const uint32_t a = u / B;
-            const uint32_t b = u - a * B;
-            const int64_t addr = (int64_t(a) * L + x) * B + b;
-            cx<T> v = conj_if(src[w * L + x], pd.conj_out);
-            if (pd.scale != 1.0) v = {v.x * scale, v.y * scale};
-            put<false>(&out[addr], v);
+        for (int e0 = tid; e0 < n; e0 += kMixedBatch * nt) {
+#pragma unroll
+            for (int i = 0; i < kMixedBatch; ++i) {
+                const int e = e0 + i * nt;
+                if (e < n) {
+                    int off;
+                    const int64_t addr = where(e, off);
+                    cx<T> v = conj_if(src[off], pd.conj_out);
+                    if (pd.scale != 1.0) v = {v.x * scale, v.y * scale};
+                    put<false>(&out[addr], v);
+                }
+            }
         }
     }
 }
@@ -203,6 +225,149 @@ __global__ __launch_bounds__(256) void k_mpermute(const cx<T> *in, cx<T> *out, c
     }
 }
 
+// Superstep 0's twiddle, Superstep 1 and Superstep 2 in one pass (the mixed-radix
+// counterpart of k_exchange): for a local index k = r + t p (per dimension) the
+// values Z^(s)[k] of all P sources are the inputs of one F_{p_1} x ... x F_{p_d}
+// whose output k' lands in V^(r)[t + k' q] (Theorem 2.1). A workgroup takes 64
+// consecutive k (one per lane) of every block: each wave gathers a share of the
+// sources (one load instruction reads 64 consecutive elements of one block),
+// twiddles by omega_T^e, e = sum_l s_l k_l T / n_l (each term below T, so the sum
+// is reduced exactly with one quotient estimate), stores to LDS as [s][lane], runs
+// the length-p_l DFTs along each grid digit of s in LDS, and scatters. The grid
+// sides must be 1, 2, 3, 4, 5, 7 or 8 (one radix stage each), P <= kMexMaxP.
+template <typename T>
+__global__ __launch_bounds__(kMexThreads) void k_mexchange(const cx<T> *__restrict__ in, cx<T> *__restrict__ out,
+                                                           const MixedGridDesc g, const cx<T> *__restrict__ table)
+{
+    extern __shared__ unsigned char smem_raw[];
+    constexpr int NW = kMexThreads / 64;
+    const int P = int(g.P);
+    cx<T> *buf = reinterpret_cast<cx<T> *>(smem_raw);                     // [P][64]
+    uint32_t *sdig = reinterpret_cast<uint32_t *>(buf + P * 64);         // digits of s, 4 bits each
+    uint32_t *soff = sdig + P;                                          // output offset of k' = s
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int d = g.d;
+    const uint32_t M = uint32_t(g.M);
+    const uint32_t tn = uint32_t(g.T);   // table size T
+    const float inv_tn = 1.0f / float(tn);
+    const T scale = static_cast<T>(g.scale);
+    const cx<T> *mul = static_cast<const cx<T> *>(g.mul);
+    // per source s: its digits (row-major over p) and the offset sum_l s_l q_l mstride_l
+    // of output k' = s inside a destination block
+    for (int s = tid; s < P; s += kMexThreads) {
+        uint32_t dig = 0, off = 0, mstride = 1;
+        int rs = s;
+        for (int l = d - 1; l >= 0; --l) {
+            const int sl = rs % g.p[l];
+            rs /= g.p[l];
+            dig |= uint32_t(sl) << (4 * l);
+            off += uint32_t(sl) * uint32_t(g.q[l]) * mstride;
+            mstride *= uint32_t(g.m[l]);
+        }
+        sdig[s] = dig;
+        soff[s] = off;
+    }
+    const int64_t ngroups = (int64_t(M) + 63) >> 6;
+    const int64_t nblocks = __builtin_amdgcn_readfirstlane(int(gridDim.x));   // uniform loop (barriers inside)
+    for (int64_t grp = blockIdx.x; grp < ngroups; grp += nblocks) {
+        const uint32_t k = uint32_t(grp << 6) + uint32_t(lane);
+        const bool valid = k < M;
+        // digits k_l of k (row-major over m), c_l = k_l T / n_l < T / p_l, and the
+        // destination of output k' = 0: block rank(r), offset sum_l t_l mstride_l
+        uint32_t c[kMaxDims];
+        uint32_t rank = 0, obase = 0;
+        {
+            uint32_t rem = valid ? k : 0, mstride = 1, pstride = 1;
+#pragma unroll
+            for (int l = kMaxDims - 1; l >= 0; --l) {
+                c[l] = 0;
+                if (l < d) {
+                    const uint32_t ml = uint32_t(g.m[l]), pl = uint32_t(g.p[l]);
+                    const uint32_t kl = rem % ml;
+                    rem /= ml;
+                    c[l] = kl * uint32_t(g.tstep[l]);
+                    const uint32_t rl = kl % pl, tl = kl / pl;
+                    rank += rl * pstride;
+                    obase += tl * mstride;
+                    mstride *= ml;
+                    pstride *= pl;
+                }
+            }
+        }
+        const int64_t dbase = int64_t(rank) * M + obase;
+        __syncthreads();   // the previous group is out of LDS (and the digit tables are in)
+        // gather and twiddle: wave wv takes sources wv + i NW, all its loads in flight
+        for (int s0 = wv; s0 < P; s0 += kMexBatch * NW) {
+            cx<T> v[kMexBatch];
+#pragma unroll
+            for (int i = 0; i < kMexBatch; ++i) {
+                const int s = s0 + i * NW;
+                v[i] = (valid && s < P) ? get(&in[int64_t(s) * M + k]) : cx<T>{T(0), T(0)};
+            }
+#pragma unroll
+            for (int i = 0; i < kMexBatch; ++i) {
+                const int s = s0 + i * NW;
+                if (s < P) {
+                    const uint32_t dig = sdig[s];
+                    uint32_t e = 0;
+#pragma unroll
+                    for (int l = 0; l < kMaxDims; ++l)
+                        if (l < d) e += ((dig >> (4 * l)) & 15u) * c[l];
+                    // e < d T: one quotient estimate and a correction each way
+                    int32_t r = int32_t(e - uint32_t(float(e) * inv_tn) * tn);
+                    r += r < 0 ? int32_t(tn) : 0;
+                    r -= r >= int32_t(tn) ? int32_t(tn) : 0;
+                    cx<T> x = conj_if(v[i], g.conj_in);
+                    if (g.twiddle) x = cmul(x, table[r]);
+                    buf[s * 64 + lane] = x;
+                }
+            }
+        }
+        __syncthreads();
+        // Superstep 2: the DFT of length p_l along digit l of s (stride pstride_l), in place
+        int pstride = 1;
+        for (int l = d - 1; l >= 0; --l) {
+            const int pl = g.p[l];
+            if (pl > 1) {
+                const int nlines = P / pl;
+                const int LperR = int(tn) / pl;
+                for (int ln = wv; ln < nlines; ln += NW) {
+                    const int sb = (ln / pstride) * pstride * pl + ln % pstride;
+                    cx<T> x[8];
+#pragma unroll
+                    for (int i = 0; i < 8; ++i)
+                        if (i < pl) x[i] = buf[(sb + i * pstride) * 64 + lane];
+                    switch (pl) {
+                    case 2: dft_small<T, 2>(x, table, LperR); break;
+                    case 3: dft_small<T, 3>(x, table, LperR); break;
+                    case 4: dft_small<T, 4>(x, table, LperR); break;
+                    case 5: dft_small<T, 5>(x, table, LperR); break;
+                    case 7: dft_small<T, 7>(x, table, LperR); break;
+                    default: dft_small<T, 8>(x, table, LperR); break;
+                    }
+#pragma unroll
+                    for (int i = 0; i < 8; ++i)
+                        if (i < pl) buf[(sb + i * pstride) * 64 + lane] = x[i];
+                }
+                __syncthreads();
+            }
+            pstride *= pl;
+        }
+        // scatter: output k' (the digits of s after the DFTs) to dbase + soff[k']
+        if (valid) {
+            for (int s = wv; s < P; s += NW) {
+                const int64_t idx = dbase + soff[s];
+                cx<T> w = conj_if(buf[s * 64 + lane], g.conj_out);
+                if (g.scale != 1.0) w = {w.x * scale, w.y * scale};
+                if (mul) w = cmul(w, mul[idx]);
+                put<false>(&out[idx], w);
+            }
+        }
+    }
+}
+
 namespace {
 
 uint32_t grid_for(int64_t count)
@@ -251,6 +416,27 @@ hipError_t launch_mpermute(Precision prec, const void *in, void *out, const Mixe
                            static_cast<const cx<double> *>(table));
     else
         hipLaunchKernelGGL(k_mpermute<float>, dim3(grid_for(g.N)), dim3(256), 0, stream,
+                           static_cast<const cx<float> *>(in), static_cast<cx<float> *>(out), g,
+                           static_cast<const cx<float> *>(table));
+    return hipGetLastError();
+}
+
+hipError_t launch_mexchange(Precision prec, const void *in, void *out, const MixedGridDesc &g, const void *table,
+                            hipStream_t stream)
+{
+    if (g.P < 1 || g.P > kMexMaxP || g.T > (int64_t(1) << 24) || g.N >= (int64_t(1) << 31) || g.d > 8)
+        return hipErrorInvalidValue;
+    for (int l = 0; l < g.d; ++l)
+        if (!mexchange_radix_ok(g.p[l])) return hipErrorInvalidValue;
+    const int64_t groups = (g.M + 63) >> 6;
+    const uint32_t blocks = uint32_t(groups < (int64_t(1) << 20) ? groups : (int64_t(1) << 20));
+    const size_t lds = size_t(g.P) * (64 * (prec == Precision::F64 ? 16 : 8) + 8);
+    if (prec == Precision::F64)
+        hipLaunchKernelGGL(k_mexchange<double>, dim3(blocks), dim3(kMexThreads), lds, stream,
+                           static_cast<const cx<double> *>(in), static_cast<cx<double> *>(out), g,
+                           static_cast<const cx<double> *>(table));
+    else
+        hipLaunchKernelGGL(k_mexchange<float>, dim3(blocks), dim3(kMexThreads), lds, stream,
                            static_cast<const cx<float> *>(in), static_cast<cx<float> *>(out), g,
                            static_cast<const cx<float> *>(table));
     return hipGetLastError();

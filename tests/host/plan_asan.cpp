@@ -42,6 +42,13 @@ hipError_t launch_pointwise(Precision, const void *, const void *, void *, int64
 hipError_t launch_mline(Precision, const void *, void *, const MixedPassDesc &, const void *, hipStream_t) { return hipSuccess; }
 hipError_t launch_mtwiddle(Precision, const void *, void *, const MixedGridDesc &, const void *, hipStream_t) { return hipSuccess; }
 hipError_t launch_mpermute(Precision, const void *, void *, const MixedGridDesc &, const void *, hipStream_t) { return hipSuccess; }
+hipError_t launch_mexchange(Precision, const void *, void *, const MixedGridDesc &g, const void *, hipStream_t)
+{
+    if (g.P > kMexMaxP || g.T > (int64_t(1) << 24)) std::abort();
+    for (int l = 0; l < g.d; ++l)
+        if (!mexchange_radix_ok(g.p[l])) std::abort();
+    return hipSuccess;
+}
 hipError_t launch_batch(Precision, const BatchDesc &bd, const void *, uint32_t, uint32_t, hipStream_t)
 {
     if (bd.nstages < 1 || bd.nitems < 1) std::abort();

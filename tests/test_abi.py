@@ -105,8 +105,9 @@ def test_p_max_examples():
     ((64,) * 5, (2,) * 5, "complex64", 4, 1, 5),
     ((1024,) * 3, (16, 16, 16), "complex128", 3, 0, 8),
     ((1,), (1,), "complex128", 0, 1, 1),
-    ((60, 60), (2, 2), "complex128", 2, 0, 5),            # mixed radix: 2 passes, twiddle + permutation, 2 passes
-    ((49, 27, 8), (7, 3, 2), "complex64", 3, 0, 7),
+    ((60, 60), (2, 2), "complex128", 2, 1, 3),            # mixed radix: 2 passes, then k_mexchange
+    ((49, 27, 8), (7, 3, 2), "complex64", 3, 1, 4),
+    ((1000, 60), (10, 2), "complex128", 2, 0, 5),         # p = 10: twiddle + permutation, then 2 passes
 ])
 def test_describe(n, p, dtype, s0, fused, launches):
     info = fftu.describe(n, p, dtype)

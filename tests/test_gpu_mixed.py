@@ -18,7 +18,9 @@ NP = {"complex128": np.complex128, "complex64": np.complex64}
 
 CASES = [((12,), (2,)), ((36,), (3,)), ((100,), (5,)), ((1000,), (10,)), ((7,), (1,)), ((60, 60), (2, 2)),
          ((126, 12), (3, 2)), ((49, 27), (7, 3)), ((18, 20, 12), (3, 2, 2)), ((96, 96), (4, 2)), ((45, 8), (3, 2)),
-         ((384,), (8,)), ((30, 30, 30), (1, 1, 1)), ((3072,), (4,))]
+         ((384,), (8,)), ((30, 30, 30), (1, 1, 1)), ((3072,), (4,)),
+         ((48, 48, 48), (4, 4, 4)),          # P = 64 in k_mexchange, the 480^3 benchmark's grid
+         ((192, 64), (8, 8)), ((75, 98), (5, 7)), ((36, 36, 36), (6, 3, 2))]   # p = 6: unfused
 
 
 @pytest.fixture(scope="module")
@@ -41,7 +43,15 @@ def test_mixed_transform_matches_oracle(torch, n, p, dtype, direction):
     D = synth.uniform_complex(N, 5, NP[dtype])
     want = oracle.cyclic_dft(D.astype(np.complex128), n, p, direction)
     with fftu.Plan(n, p, dtype, direction) as plan:
-        assert plan.info()["exchange_fused"] == 0 and "k_mline" in plan.launch_names()[0]
+        info, names = plan.info(), plan.launch_names()
+        fused = all(v in (1, 2, 3, 4, 5, 7, 8) for v in p) and int(np.prod(p)) <= 64
+        assert info["exchange_fused"] == (1 if fused else 0)
+        t = "double" if dtype == "complex128" else "float"
+        if fused:
+            assert names[-1] == f"fftu::k_mexchange<{t}>" and len(names) == info["s0_kernels"] + 1
+        else:
+            assert f"fftu::k_mpermute<{t}>" in names
+        assert "k_mline" in names[0] or info["s0_kernels"] == 0
         x = torch.from_numpy(D).cuda()
         y = plan(x)
         z = x.clone()
