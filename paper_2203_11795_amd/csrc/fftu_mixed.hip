@@ -30,25 +30,68 @@ namespace fftu {
 
 namespace {
 
-// DFT of size R on registers x[0..R-1]: radix 2, 4, 8 with constant roots; 3, 5,
-// 7 from the roots omega_R^m = tw[m L / R] (tw = omega_L in LDS).
+// Roots omega_R^m, m in [R], from a table of omega_L (stride L / R): loaded once
+// by a caller that runs many DFTs of size R (only the odd radices use them).
 template <typename T, int R>
-__device__ __forceinline__ void dft_small(cx<T> (&x)[8], const cx<T> *tw, int LperR)
+__device__ __forceinline__ void load_roots(cx<T> (&w)[R], const cx<T> *tw, int LperR)
+{
+    if constexpr (R == 3 || R == 5 || R == 7) {
+#pragma unroll
+        for (int m = 0; m < R; ++m) w[m] = tw[m * LperR];
+    }
+}
+
+// DFT of size R on registers x[0..R-1], natural order: radix 2, 4, 8 with constant
+// roots; 3, 5, 7 from omega_R^m = w[m * ws] (a load_roots array with ws = 1, or a
+// table of omega_L with ws = L / R). For odd R the inputs pair as a_r = x_r +
+// x_{R-r}, b_r = x_r - x_{R-r}, since omega^{(R-r) c} is the conjugate of
+// omega^{r c} = C + iS: then y_c = x_0 + sum_r (C a_r + i S b_r), and y_{R-c}
+// takes the same sums with the sign of the i S b_r part flipped.
+template <typename T, int R>
+__device__ __forceinline__ void dft_small(cx<T> (&x)[8], const cx<T> *w, int ws)
 {
     if constexpr (R == 2 || R == 4 || R == 8) {
         Dft<T, R>::run(x);
     } else {
+        constexpr int H = (R - 1) / 2;
+        cx<T> a[H + 1], b[H + 1];
+        cx<T> y0 = x[0];
+#pragma unroll
+        for (int r = 1; r <= H; ++r) {
+            a[r] = x[r] + x[R - r];
+            b[r] = x[r] - x[R - r];
+            y0 = y0 + a[r];
+        }
         cx<T> y[R];
+        y[0] = y0;
 #pragma unroll
-        for (int c = 0; c < R; ++c) {
-            cx<T> acc = x[0];
+        for (int c = 1; c <= H; ++c) {
+            cx<T> A = x[0];
+            T bx = T(0), by = T(0);
 #pragma unroll
-            for (int r = 1; r < R; ++r) acc = acc + cmul(x[r], tw[((r * c) % R) * LperR]);
-            y[c] = acc;
+            for (int r = 1; r <= H; ++r) {
+                const cx<T> wr = w[((r * c) % R) * ws];
+                A = {A.x + wr.x * a[r].x, A.y + wr.x * a[r].y};
+                bx += wr.y * b[r].x;
+                by += wr.y * b[r].y;
+            }
+            y[c] = {A.x - by, A.y + bx};        // A + i (bx + i by)
+            y[R - c] = {A.x + by, A.y - bx};
         }
 #pragma unroll
         for (int c = 0; c < R; ++c) x[c] = y[c];
     }
+}
+
+// n / d for n < 2^22 and a wave-uniform d with inv = 1 / d: one float estimate,
+// corrected by one step either way.
+__device__ __forceinline__ int div_small(int n, int d, float inv)
+{
+    int q = int(float(n) * inv);
+    const int r = n - q * d;
+    q += r >= d ? 1 : 0;
+    q -= r < 0 ? 1 : 0;
+    return q;
 }
 
 // One Stockham stage of radix R over `lines` lines of length L (src -> dst in LDS).
@@ -59,12 +102,15 @@ __device__ __forceinline__ void mixed_stage(const cx<T> *src, cx<T> *dst, const 
     const int LR = L / R;
     const int span = L / (Ns * R);          // omega_{Ns R} = omega_L^span
     const int nb = lines * LR;
+    const float inv_lr = 1.0f / float(LR), inv_ns = 1.0f / float(Ns);
+    cx<T> w[R];
+    load_roots<T, R>(w, tw, LR);
     for (int bi = tid; bi < nb; bi += nt) {
-        const int w = bi / LR;
-        const int j = bi - w * LR;
-        const int jd = j / Ns;
+        const int wl = div_small(bi, LR, inv_lr);
+        const int j = bi - wl * LR;
+        const int jd = div_small(j, Ns, inv_ns);
         const int k = j - jd * Ns;
-        const cx<T> *s = src + w * L + j;
+        const cx<T> *s = src + wl * L + j;
         cx<T> x[8];
 #pragma unroll
         for (int r = 0; r < R; ++r) x[r] = s[r * LR];
@@ -72,8 +118,8 @@ __device__ __forceinline__ void mixed_stage(const cx<T> *src, cx<T> *dst, const 
 #pragma unroll
             for (int r = 1; r < R; ++r) x[r] = cmul(x[r], tw[r * k * span]);
         }
-        dft_small<T, R>(x, tw, LR);
-        cx<T> *o = dst + w * L + jd * Ns * R + k;
+        dft_small<T, R>(x, w, 1);
+        cx<T> *o = dst + wl * L + jd * Ns * R + k;
 #pragma unroll
         for (int r = 0; r < R; ++r) o[r * Ns] = x[r];
     }
