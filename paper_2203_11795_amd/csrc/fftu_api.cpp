@@ -561,14 +561,15 @@ bool plan_lastx(const Geometry &G, const GridDesc &g, fftu_dtype dt, std::vector
     return true;
 }
 
-std::string lastx_kernel_name(const fftu::LastxDesc &lx, fftu_dtype dt)
+// MUL: the instantiation that multiplies by a spectrum on the store (convolution plans).
+std::string lastx_kernel_name(const fftu::LastxDesc &lx, fftu_dtype dt, bool mul = false)
 {
     const std::string t = dt == FFTU_C128 ? "double" : "float";
     auto s = [](int v) { return std::to_string(v); };
     const ExchangeDesc &ex = lx.ex;
     const int lph = ex.nh ? ex.lph : 0, lpr = ex.nr ? ex.lpr : 0;
     return "fftu::k_lastx<" + t + ", " + s(lx.logl) + ", " + s(ex.nr) + ", " + s(lpr) + ", " + s(ex.nh) + ", " +
-           s(lph) + ">";
+           s(lph) + (mul ? ", true>" : ", false>");
 }
 
 // omega_L^j = exp(-2 pi i j / L) for j in [L], L = 2^logL, in FP64. Each value is
@@ -1685,6 +1686,7 @@ fftu_plan_t fftu_plan_convolution(int d, const int64_t n[], const int64_t p[], f
         return nullptr;
     }
     fwd->conv_inv = inv;
+    if (fwd->lastx) fwd->launch_names.back() = lastx_kernel_name(fwd->lx, dtype, true);
     record(FFTU_SUCCESS);
     return fwd;
 }
