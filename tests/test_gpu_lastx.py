@@ -130,3 +130,49 @@ def test_lastx_writes_every_output(torch_dev):
         plan(x, out)
     torch.cuda.synchronize()
     assert not torch.isnan(out).any().item()
+
+
+@pytest.mark.parametrize("dtype", ["complex128", "complex64"])
+def test_lastx_external_plan_with_workspace(torch_dev, dtype):
+    """An external plan (shared table, workspace given per call) runs k_lastx with the
+    same results as a plan that owns its workspace, bit for bit, in place as well."""
+    import paper_2203_11795_amd as fftu
+    torch = torch_dev
+    n, p = (16, 32, 512), (4, 4, 4)
+    N = int(np.prod(n))
+    D = synth.uniform_complex(N, 12, NP_DTYPE[dtype])
+    x = torch.from_numpy(D).to("cuda")
+    with fftu.Plan(n, p, dtype) as own, fftu.Plan(n, p, dtype, external=True) as ext:
+        assert ext.info()["exchange_fused"] == 2 and ext.device_bytes() == 0
+        ws = torch.empty_like(x)
+        a = own(x)
+        b = ext(x, workspace=ws)
+        c = x.clone()
+        ext(c, c, workspace=ws)
+        torch.cuda.synchronize()
+        assert torch.equal(a, b) and torch.equal(a, c)
+
+
+def test_lastx_graph_replays(torch_dev):
+    """A captured k_lastx plan replays correctly several times, with eager work and
+    synchronisation between the replays (no memset nodes are recorded)."""
+    import paper_2203_11795_amd as fftu
+    torch = torch_dev
+    n, p = (64, 64, 512), (4, 4, 4)
+    N = int(np.prod(n))
+    x = torch.from_numpy(synth.uniform_complex(N, 13)).to("cuda")
+    y = torch.empty_like(x)
+    with fftu.Plan(n, p, "complex128") as plan:
+        want = plan(x)
+        torch.cuda.synchronize()
+        g = fftu.Graph(plan, x, y)
+        try:
+            for _ in range(3):
+                y.zero_()
+                g.launch()
+                torch.cuda.synchronize()
+                assert torch.equal(y, want)
+                plan(x, torch.empty_like(x))          # eager work between replays
+                torch.cuda.synchronize()
+        finally:
+            g.close()
