@@ -540,7 +540,7 @@ bool plan_lastx(const Geometry &G, const GridDesc &g, fftu_dtype dt, std::vector
     const int logrw = fftu::kLastxLogThreads - (logl - loge) - G.logP;
     if (G.logM - logl < logrw) return false;
     const int esize = dt == FFTU_C128 ? 16 : 8;
-    const uint32_t lds = fftu::lastx_lds_bytes(logl, G.logP, esize);
+    const uint32_t lds = fftu::lastx_lds_bytes(logl, esize);
     if (lds > 160u * 1024u) return false;
     if ((int64_t(1) << (G.logM - logrw - logl)) > fftu::kLastxMaxTiles) return false;
     s0x.clear();

@@ -122,13 +122,12 @@ constexpr bool lastx_split_ok(int logl, int nr, int lpr, int nh, int lph)
 }
 
 // LDS bytes of k_lastx: omega_L table, then max(transpose, line stages) rows of 8-byte words.
-constexpr uint32_t lastx_lds_bytes(int logl, int logp, int esize)
+constexpr uint32_t lastx_lds_bytes(int logl, int esize)
 {
     const int L = 1 << logl;
     const int tpl = 1 << (logl - line_loge(logl));
     const int lp = L + tpl, pitch = L + L / 16 + 1;
     const int lines = 1 << (kLastxLogThreads - (logl - line_loge(logl)));
-    (void)logp;
     return uint32_t(L * esize + lines * (lp > pitch ? lp : pitch) * 8);
 }
 

@@ -55,7 +55,7 @@ __global__ __launch_bounds__(kLastxThreads, MUL ? 2 : 4) void k_lastx(const cx<T
     using PL = typename S::PL;
     static_assert(lastx_split_ok(LOGL, NR, LPR, NH, LPH), "k_lastx: no such split");
     static_assert(PL::LOGE == LOGR && S::LOGRW >= 0, "k_lastx: the line plan and the exchange split disagree");
-    static_assert(lastx_lds_bytes(LOGL, S::LOGP, sizeof(cx<T>)) == S::L * sizeof(cx<T>) + S::WORDS * 8,
+    static_assert(lastx_lds_bytes(LOGL, sizeof(cx<T>)) == S::L * sizeof(cx<T>) + S::WORDS * 8,
                   "k_lastx: LDS size");
     constexpr int R = 1 << LOGR;
     constexpr int H = 1 << LOGH;
