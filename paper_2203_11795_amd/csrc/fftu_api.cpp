@@ -543,15 +543,16 @@ bool plan_lastx(const Geometry &G, const GridDesc &g, fftu_dtype dt, std::vector
     const uint32_t lds = fftu::lastx_lds_bytes(logl, esize);
     if (lds > 160u * 1024u) return false;
     if ((int64_t(1) << (G.logM - logrw - logl)) > fftu::kLastxMaxTiles) return false;
+    // the other dimensions outermost first (measured about 1% faster at 512^3 than
+    // innermost first: the longest stride then reads the input buffer)
     s0x.clear();
-    int logB = logl;
-    for (int l = G.d - 2; l >= 0; --l) {
+    for (int l = 0; l <= G.d - 2; ++l) {
         if (G.logm[l] > 0) {
-            int logA = G.logP;
+            int logA = G.logP, logB = 0;
             for (int j = 0; j < l; ++j) logA += G.logm[j];
+            for (int j = l + 1; j < G.d; ++j) logB += G.logm[j];
             s0x.push_back(make_pass(logA, {G.logm[l]}, logB, dt, G.lognmax));
         }
-        logB += G.logm[l];
     }
     lx = fftu::LastxDesc{};
     lx.ex = make_exchange(G, g, sp, dt);
