@@ -1104,7 +1104,8 @@ fftu_plan_s *build_mixed_plan(int d, const int64_t n[], const int64_t p[], fftu_
     const std::string t = dtype == FFTU_C128 ? "double" : "float";
     for (size_t i = 0; i < mp.s0.size(); ++i) pl->launch_names.push_back("fftu::k_mline<" + t + ">");
     if (mp.fused) {
-        pl->launch_names.push_back("fftu::k_mexchange<" + t + ">");
+        const bool tl = fftu::mexchange_table_in_lds(mp.g.P, mp.T, int(pl->esize));
+        pl->launch_names.push_back("fftu::k_mexchange<" + t + (tl ? ", true>" : ", false>"));
     } else {
         pl->launch_names.push_back("fftu::k_mpermute<" + t + ">");
         for (size_t i = 0; i < mp.s2.size(); ++i) pl->launch_names.push_back("fftu::k_mline<" + t + ">");

@@ -178,6 +178,12 @@ struct MixedGridDesc {
 constexpr int64_t kMexMaxP = 64;
 constexpr int kMexThreads = 512;
 constexpr int kMexBatch = 8;           // source loads per lane in flight
+constexpr size_t kMexTableLdsMax = 80 * 1024;   // LDS for tile + digit tables + the omega_T copy
+// k_mexchange keeps its twiddle table in LDS when two workgroups per CU still fit.
+constexpr bool mexchange_table_in_lds(int64_t P, int64_t T, int esize)
+{
+    return size_t(P) * (64 * size_t(esize) + 8) + size_t(T) * size_t(esize) <= kMexTableLdsMax;
+}
 constexpr bool mexchange_radix_ok(int p)
 {
     return p == 1 || p == 2 || p == 3 || p == 4 || p == 5 || p == 7 || p == 8;

@@ -281,7 +281,8 @@ __global__ __launch_bounds__(256) void k_mpermute(const cx<T> *in, cx<T> *out, c
 // is reduced exactly with one quotient estimate), stores to LDS as [s][lane], runs
 // the length-p_l DFTs along each grid digit of s in LDS, and scatters. The grid
 // sides must be 1, 2, 3, 4, 5, 7 or 8 (one radix stage each), P <= kMexMaxP.
-template <typename T>
+// TL: the twiddles come from an LDS copy of the table (when it fits beside the tile).
+template <typename T, bool TL>
 __global__ __launch_bounds__(kMexThreads) void k_mexchange(const cx<T> *__restrict__ in, cx<T> *__restrict__ out,
                                                            const MixedGridDesc g, const cx<T> *__restrict__ table)
 {
@@ -291,6 +292,9 @@ __global__ __launch_bounds__(kMexThreads) void k_mexchange(const cx<T> *__restri
     cx<T> *buf = reinterpret_cast<cx<T> *>(smem_raw);                     // [P][64]
     uint32_t *sdig = reinterpret_cast<uint32_t *>(buf + P * 64);         // digits of s, 4 bits each
     uint32_t *soff = sdig + P;                                          // output offset of k' = s
+    cx<T> *tlds = reinterpret_cast<cx<T> *>(soff + P);                  // omega_T (TL)
+    if constexpr (TL)
+        for (int e = threadIdx.x; e < int(g.T); e += kMexThreads) tlds[e] = table[e];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -366,7 +370,7 @@ __global__ __launch_bounds__(kMexThreads) void k_mexchange(const cx<T> *__restri
                     r += r < 0 ? int32_t(tn) : 0;
                     r -= r >= int32_t(tn) ? int32_t(tn) : 0;
                     cx<T> x = conj_if(v[i], g.conj_in);
-                    if (g.twiddle) x = cmul(x, table[r]);
+                    if (g.twiddle) x = cmul(x, TL ? tlds[r] : table[r]);
                     buf[s * 64 + lane] = x;
                 }
             }
@@ -476,15 +480,26 @@ hipError_t launch_mexchange(Precision prec, const void *in, void *out, const Mix
         if (!mexchange_radix_ok(g.p[l])) return hipErrorInvalidValue;
     const int64_t groups = (g.M + 63) >> 6;
     const uint32_t blocks = uint32_t(groups < (int64_t(1) << 20) ? groups : (int64_t(1) << 20));
-    const size_t lds = size_t(g.P) * (64 * (prec == Precision::F64 ? 16 : 8) + 8);
-    if (prec == Precision::F64)
-        hipLaunchKernelGGL(k_mexchange<double>, dim3(blocks), dim3(kMexThreads), lds, stream,
-                           static_cast<const cx<double> *>(in), static_cast<cx<double> *>(out), g,
-                           static_cast<const cx<double> *>(table));
-    else
-        hipLaunchKernelGGL(k_mexchange<float>, dim3(blocks), dim3(kMexThreads), lds, stream,
-                           static_cast<const cx<float> *>(in), static_cast<cx<float> *>(out), g,
-                           static_cast<const cx<float> *>(table));
+    const size_t esize = prec == Precision::F64 ? 16 : 8;
+    const size_t lds = size_t(g.P) * (64 * esize + 8);
+    // the table in LDS when two workgroups per CU still fit (measured 7% faster at 480^3)
+    const bool tl = mexchange_table_in_lds(g.P, g.T, int(esize));
+    const size_t bytes = tl ? lds + size_t(g.T) * esize : lds;
+    if (prec == Precision::F64) {
+        const cx<double> *a = static_cast<const cx<double> *>(in), *tab = static_cast<const cx<double> *>(table);
+        cx<double> *b = static_cast<cx<double> *>(out);
+        if (tl)
+            hipLaunchKernelGGL((k_mexchange<double, true>), dim3(blocks), dim3(kMexThreads), bytes, stream, a, b, g, tab);
+        else
+            hipLaunchKernelGGL((k_mexchange<double, false>), dim3(blocks), dim3(kMexThreads), bytes, stream, a, b, g, tab);
+    } else {
+        const cx<float> *a = static_cast<const cx<float> *>(in), *tab = static_cast<const cx<float> *>(table);
+        cx<float> *b = static_cast<cx<float> *>(out);
+        if (tl)
+            hipLaunchKernelGGL((k_mexchange<float, true>), dim3(blocks), dim3(kMexThreads), bytes, stream, a, b, g, tab);
+        else
+            hipLaunchKernelGGL((k_mexchange<float, false>), dim3(blocks), dim3(kMexThreads), bytes, stream, a, b, g, tab);
+    }
     return hipGetLastError();
 }
 
