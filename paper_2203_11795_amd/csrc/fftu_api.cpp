@@ -558,11 +558,13 @@ bool plan_lastx(const Geometry &G, const GridDesc &g, fftu_dtype dt, std::vector
     lx.ex = make_exchange(G, g, sp, dt);
     lx.logl = logl;
     lx.tiles = int64_t(1) << (G.logM - logrw - logl);
-    lx.lds_bytes = lds;
+    lx.table_lds = fftu::lastx_table_in_lds(logl, G.lognmax, esize) ? 1 : 0;
+    lx.lds_bytes = lds + (lx.table_lds ? uint32_t(esize) << G.lognmax : 0u);
     return true;
 }
 
-// MUL: the instantiation that multiplies by a spectrum on the store (convolution plans).
+// MUL: the instantiation that multiplies by a spectrum on the store (convolution
+// plans; their table stays in HBM).
 std::string lastx_kernel_name(const fftu::LastxDesc &lx, fftu_dtype dt, bool mul = false)
 {
     const std::string t = dt == FFTU_C128 ? "double" : "float";
@@ -570,7 +572,7 @@ std::string lastx_kernel_name(const fftu::LastxDesc &lx, fftu_dtype dt, bool mul
     const ExchangeDesc &ex = lx.ex;
     const int lph = ex.nh ? ex.lph : 0, lpr = ex.nr ? ex.lpr : 0;
     return "fftu::k_lastx<" + t + ", " + s(lx.logl) + ", " + s(ex.nr) + ", " + s(lpr) + ", " + s(ex.nh) + ", " +
-           s(lph) + (mul ? ", true>" : ", false>");
+           s(lph) + (mul ? ", true, false>" : (lx.table_lds ? ", false, true>" : ", false, false>"));
 }
 
 // omega_L^j = exp(-2 pi i j / L) for j in [L], L = 2^logL, in FP64. Each value is
@@ -1823,6 +1825,10 @@ fftu_status execute_with(fftu_plan_s *plan, const void *in, void *out, void *ws,
         lx.ex.g.conj_out = inv;
         lx.ex.g.scale = scale;
         lx.ex.mul = mul;
+        if (mul) {   // the multiplying instantiation keeps the table in HBM
+            lx.table_lds = 0;
+            lx.lds_bytes = fftu::lastx_lds_bytes(lx.logl, int(plan->esize));
+        }
         hipError_t e = fftu::launch_lastx(plan->prec, src, out, lx, plan->table, stream);
         if (e == hipSuccess) mk.mark();
         return from_hip(e);

@@ -131,12 +131,20 @@ constexpr uint32_t lastx_lds_bytes(int logl, int esize)
     return uint32_t(L * esize + lines * (lp > pitch ? lp : pitch) * 8);
 }
 
+// k_lastx copies the omega table into LDS when two workgroups per CU still fit.
+constexpr uint32_t kLastxTableLdsMax = 80 * 1024;
+constexpr bool lastx_table_in_lds(int logl, int lognmax, int esize)
+{
+    return uint64_t(lastx_lds_bytes(logl, esize)) + (uint64_t(esize) << lognmax) <= kLastxTableLdsMax;
+}
+
 struct LastxDesc {
     ExchangeDesc ex;       // its conj_in must be 0: the lines take the input conjugation
     int64_t tiles;         // M / (RW m_d)
     int32_t logl;
     int32_t conj_in;       // conjugate on load (the first kernel of a plan)
-    uint32_t lds_bytes;
+    int32_t table_lds;     // the omega table in LDS (plain plans; convolution keeps it in HBM)
+    uint32_t lds_bytes;    // with table_lds: lastx_lds_bytes + the table
 };
 
 // Mixed-radix path (fftu_mixed.hip): sides with factors 2, 3, 5 and 7.

@@ -46,7 +46,9 @@ struct LastxShape {
 // Two workgroups per CU: 4 waves per SIMD, at most 128 VGPRs. MUL: every output is
 // multiplied by lx.ex.mul at its position (convolution); the multipliers are all
 // loaded before the stores, which takes more registers (one workgroup per CU).
-template <typename T, int LOGL, int NR, int LPR, int NH, int LPH, bool MUL>
+// TL: the exchange's twiddles come from an LDS copy of the omega table, placed
+// after the work area (the planner takes it when two workgroups per CU still fit).
+template <typename T, int LOGL, int NR, int LPR, int NH, int LPH, bool MUL, bool TL>
 __global__ __launch_bounds__(kLastxThreads, MUL ? 2 : 4) void k_lastx(const cx<T> *__restrict__ in, cx<T> *__restrict__ out,
                                                          const LastxDesc lx, const cx<T> *__restrict__ table)
 {
@@ -67,6 +69,9 @@ __global__ __launch_bounds__(kLastxThreads, MUL ? 2 : 4) void k_lastx(const cx<T
     unsigned char *work = smem_raw + S::L * sizeof(cx<T>);
     const int tid = threadIdx.x;
     line_twiddles<T, LOGL>(tw, table, lx.ex.g.lognmax, tid);
+    cx<T> *ttab = reinterpret_cast<cx<T> *>(work + S::WORDS * 8);
+    if constexpr (TL)
+        for (int e = tid; e < (1 << lx.ex.g.lognmax); e += kLastxThreads) ttab[e] = table[e];
 
     // line layout: thread (w, j) holds line w = s RW + row, register m <-> position j + TPL m
     const int j = tid & (PL::TPL - 1);
@@ -130,7 +135,7 @@ __global__ __launch_bounds__(kLastxThreads, MUL ? 2 : 4) void k_lastx(const cx<T
         }
 
         exchange_core<T, NR, LPR, NH, LPH, kLastxThreads, false, MUL ? 2 : 1>(
-            out, lx.ex, table, work, (tile << S::LOGK) + kk, tid, [&](int jj, int, int64_t, bool) { return u[jj]; });
+            out, lx.ex, TL ? ttab : table, work, (tile << S::LOGK) + kk, tid, [&](int jj, int, int64_t, bool) { return u[jj]; });
     }
 }
 
@@ -142,14 +147,22 @@ hipError_t go(const void *in, void *out, const LastxDesc &lx, const void *table,
     if constexpr (lastx_split_ok(LOGL, NR, LPR, NH, LPH)) {
         if (lx.tiles < 1 || lx.tiles > kLastxMaxTiles) return hipErrorInvalidValue;
         const uint32_t blocks = uint32_t(lx.tiles);
-        if (lx.ex.mul)
-            hipLaunchKernelGGL((k_lastx<T, LOGL, NR, LPR, NH, LPH, true>), dim3(blocks), dim3(kLastxThreads),
-                               lx.lds_bytes, stream, static_cast<const cx<T> *>(in), static_cast<cx<T> *>(out), lx,
-                               static_cast<const cx<T> *>(table));
-        else
-            hipLaunchKernelGGL((k_lastx<T, LOGL, NR, LPR, NH, LPH, false>), dim3(blocks), dim3(kLastxThreads),
-                               lx.lds_bytes, stream, static_cast<const cx<T> *>(in), static_cast<cx<T> *>(out), lx,
-                               static_cast<const cx<T> *>(table));
+        const cx<T> *a = static_cast<const cx<T> *>(in), *tab = static_cast<const cx<T> *>(table);
+        cx<T> *b = static_cast<cx<T> *>(out);
+        const uint32_t base = lastx_lds_bytes(LOGL, sizeof(cx<T>));
+        if (lx.ex.mul) {
+            if (lx.lds_bytes != base) return hipErrorInvalidValue;
+            hipLaunchKernelGGL((k_lastx<T, LOGL, NR, LPR, NH, LPH, true, false>), dim3(blocks),
+                               dim3(kLastxThreads), lx.lds_bytes, stream, a, b, lx, tab);
+        } else if (lx.table_lds) {
+            if (lx.lds_bytes != base + (uint32_t(sizeof(cx<T>)) << lx.ex.g.lognmax)) return hipErrorInvalidValue;
+            hipLaunchKernelGGL((k_lastx<T, LOGL, NR, LPR, NH, LPH, false, true>), dim3(blocks),
+                               dim3(kLastxThreads), lx.lds_bytes, stream, a, b, lx, tab);
+        } else {
+            if (lx.lds_bytes != base) return hipErrorInvalidValue;
+            hipLaunchKernelGGL((k_lastx<T, LOGL, NR, LPR, NH, LPH, false, false>), dim3(blocks),
+                               dim3(kLastxThreads), lx.lds_bytes, stream, a, b, lx, tab);
+        }
         return hipGetLastError();
     }
     return hipErrorInvalidValue;

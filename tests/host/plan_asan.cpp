@@ -33,6 +33,7 @@ hipError_t launch_lastx(Precision, const void *, void *, const LastxDesc &lx, co
     const int logp = ex.nr * ex.lpr + ex.nh * ex.lph;
     const int logrw = kLastxLogThreads - (lx.logl - line_loge(lx.logl)) - logp;
     if ((lx.tiles << (logrw + lx.logl)) != ex.g.M || lx.lds_bytes > 160 * 1024) std::abort();
+    if (lx.table_lds && (ex.mul || lx.lds_bytes > kLastxTableLdsMax)) std::abort();
     if (ex.g.logm[ex.g.d - 1] != lx.logl) std::abort();
     return hipSuccess;
 }
