@@ -45,12 +45,13 @@ struct LastxShape {
 
 // Two workgroups per CU: 4 waves per SIMD, at most 128 VGPRs. MUL: every output is
 // multiplied by lx.ex.mul at its position (convolution); the multipliers are all
-// loaded before the stores, which takes more registers (one workgroup per CU).
+// loaded before the stores, so its bound leaves the compiler up to 256 VGPRs.
 // TL: the exchange's twiddles come from an LDS copy of the omega table, placed
 // after the work area (the planner takes it when two workgroups per CU still fit).
 template <typename T, int LOGL, int NR, int LPR, int NH, int LPH, bool MUL, bool TL>
-__global__ __launch_bounds__(kLastxThreads, MUL ? 2 : 4) void k_lastx(const cx<T> *__restrict__ in, cx<T> *__restrict__ out,
-                                                         const LastxDesc lx, const cx<T> *__restrict__ table)
+__global__ __launch_bounds__(kLastxThreads, MUL ? 2 : 4) void k_lastx(const cx<T> *__restrict__ in,
+                                                                      cx<T> *__restrict__ out, const LastxDesc lx,
+                                                                      const cx<T> *__restrict__ table)
 {
     constexpr int LOGR = NR * LPR, LOGH = NH * LPH;
     using S = LastxShape<LOGL, LOGR, LOGH>;
@@ -135,7 +136,8 @@ __global__ __launch_bounds__(kLastxThreads, MUL ? 2 : 4) void k_lastx(const cx<T
         }
 
         exchange_core<T, NR, LPR, NH, LPH, kLastxThreads, false, MUL ? 2 : 1>(
-            out, lx.ex, TL ? ttab : table, work, (tile << S::LOGK) + kk, tid, [&](int jj, int, int64_t, bool) { return u[jj]; });
+            out, lx.ex, TL ? ttab : table, work, (tile << S::LOGK) + kk, tid,
+            [&](int jj, int, int64_t, bool) { return u[jj]; });
     }
 }
 
