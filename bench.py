@@ -314,6 +314,59 @@ def run_mixed(args, torch, np, fftu, synth, with_oracle):
     return res
 
 
+def run_paper_workloads(args, torch, fftu):
+    """The paper's own test sizes on one GPU: 1024^3 complex128 (4^3 grid, the fused
+    exchange) and the very rectangular 16,777,216 x 64 (complex64 on a 4096 x 8 grid:
+    the only grids for it have a local line of 4096, and P = 32768 takes the unfused
+    exchange). Input from the device generator; checked by the round trip (forward,
+    then inverse, against the input) on the device."""
+    res = []
+    for n, p, dt in [((1024, 1024, 1024), (4, 4, 4), "complex128"), ((1 << 24, 64), (4096, 8), "complex64")]:
+        N = math.prod(n)
+        tdt = torch.complex128 if dt == "complex128" else torch.complex64
+        log(f"[bench] paper workload {'x'.join(map(str, n))} {dt}")
+        x = torch.empty(N, dtype=tdt, device="cuda:0")
+        fftu.fill_uniform(x, 7, 0)
+        y = torch.empty_like(x)
+        fwd = fftu.Plan(n, p, dt, fftu.FORWARD)
+        stream = torch.cuda.current_stream()
+        fwd(x, y, stream=stream)
+        torch.cuda.synchronize()
+        steps = 3
+        fwd.timing_begin(steps)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            fwd(x, y, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        per_launch, _ = fwd.timing_end()
+        names = fwd.launch_names()
+        info = fwd.info()
+        fwd.close()
+        inv = fftu.Plan(n, p, dt, fftu.INVERSE)
+        inv(y, y, stream=stream)                 # in place: y becomes the round trip
+        torch.cuda.synchronize()
+        inv.close()
+        rt = (torch.linalg.vector_norm(y - x) / torch.linalg.vector_norm(x)).item()
+        esize = 16 if dt == "complex128" else 8
+        alg = info["launches"] * 2.0 * N * esize
+        res.append({"workload": f"{'x'.join(map(str, n))} {dt} forward DFT, {'x'.join(map(str, p))} cyclic grid",
+                    "ms_per_transform": round(ms, 3), "GFLOPs": round(5.0 * N * math.log2(N) / (ms * 1e-3) / 1e9, 1),
+                    "launches": info["launches"], "exchange_fused": info["exchange_fused"],
+                    "roofline": {"bound": "hbm", "algorithmic_bytes": alg, "unit": "GB/s", "peak": HBM_PEAK_GBS,
+                                 "achieved": round(alg / (ms * 1e-3) / 1e9, 1),
+                                 "frac": round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
+                    "rel_l2_roundtrip": rt,
+                    "kernels": [{"kernel": k, "avg_ms": round(t, 3)} for k, t in zip(names, per_launch)]})
+        del x, y
+        torch.cuda.empty_cache()
+        log(f"[bench] paper workload {'x'.join(map(str, n))}: {ms:.2f} ms, {res[-1]['GFLOPs']} GFLOP/s")
+    return res
+
+
 def run_precision(args, torch, np, fftu, synth, with_oracle):
     """The precision pattern at 64^5 (2^30 points, 2^5 grid): the complex64 path
     (FP32 butterflies, FP64-generated tables rounded once) timed, and its error
@@ -458,6 +511,8 @@ def main():
     ap.add_argument("--no-serving", action="store_true", help="skip the serving workload")
     ap.add_argument("--no-convolution", action="store_true", help="skip the convolution workload")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-radix workload")
+    ap.add_argument("--no-paper", action="store_true",
+                    help="skip the paper's own sizes (1024^3 complex128, 16777216 x 64 complex64)")
     ap.add_argument("--no-small", action="store_true", help="skip the 64^3 latency workload")
     ap.add_argument("--no-precision", action="store_true", help="skip the 64^5 complex64 precision workload")
     ap.add_argument("--serving-seconds", type=float, default=10.0,
@@ -593,6 +648,9 @@ def main():
         result["small"] = run_small(args, torch, np, fftu, synth, not args.no_check)
     if args.workload == "512cube" and not args.no_convolution:
         result["convolution"] = run_convolution(args, torch, np, fftu, synth, info)
+        torch.cuda.empty_cache()
+    if args.workload == "512cube" and not args.no_paper:
+        result["paper_workloads"] = run_paper_workloads(args, torch, fftu)
         torch.cuda.empty_cache()
     if args.workload == "512cube" and not args.no_mixed:
         result["mixed_radix"] = run_mixed(args, torch, np, fftu, synth, not args.no_check)
