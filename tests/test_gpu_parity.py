@@ -267,3 +267,58 @@ def test_misaligned_buffers_are_rejected(torch_dev):
     y = torch.zeros(16, dtype=torch.complex64, device="cuda")
     assert lib.fftu_fill_uniform(y.data_ptr() + 4, 4, 1, 0, 0, 0, None) == 1
     assert lib.fftu_pointwise_mul(y.data_ptr() + 4, y.data_ptr(), y.data_ptr(), 4, 1, 1.0, None) == 1
+
+
+def _cyclic_position(j, n, p):
+    """Buffer position of natural index j (a d-tuple) in the cyclic layout
+    (Section 1.1): processor s = j mod p, local index k = j div p, position
+    rank(s) M + lin(k), both row-major."""
+    m = [a // b for a, b in zip(n, p)]
+    rank = lin = 0
+    for l in range(len(n)):
+        rank = rank * p[l] + j[l] % p[l]
+        lin = lin * m[l] + j[l] // p[l]
+    return rank * int(np.prod(m)) + lin
+
+
+def test_64pow5_full_size_sparse_and_properties(torch_dev):
+    """The 64^5 complex64 configuration on the 2^5 grid at full size, in the launch
+    configuration the benchmark times. (1) A sparse input (40 nonzeros) has a dense
+    transform whose every output is a 40-term sum of eq. (1.2): 2000 sampled outputs
+    are checked against it in FP64. (2) Parseval and the round trip on a dense input
+    from the device generator hold at any size."""
+    import paper_2203_11795_amd as fftu
+    torch = torch_dev
+    n, p = (64,) * 5, (2,) * 5
+    N = 64 ** 5
+    rng = np.random.default_rng(53)
+    js = np.unique(rng.integers(0, 64, size=(40, 5)), axis=0)      # distinct positions
+    vals = (rng.uniform(-1, 1, len(js)) + 1j * rng.uniform(-1, 1, len(js))).astype(np.complex64)
+    x = torch.zeros(N, dtype=torch.complex64, device="cuda")
+    pos = torch.tensor([_cyclic_position(tuple(j), n, p) for j in js], device="cuda")
+    x[pos] = torch.from_numpy(vals).to("cuda")
+    with fftu.Plan(n, p, "complex64", FORWARD) as plan:
+        y = plan(x)
+        torch.cuda.synchronize()
+        ks = rng.integers(0, 64, size=(2000, 5))
+        kpos = torch.tensor([_cyclic_position(tuple(k), n, p) for k in ks], device="cuda")
+        got = y[kpos].cpu().numpy().astype(np.complex128)
+        # eq. (1.2) over the nonzeros, in FP64, with exact integer phases mod 64
+        phase = (ks @ js.T) % 64
+        want = (np.exp(-2j * np.pi * phase / 64.0) * vals.astype(np.complex128)[None, :]).sum(axis=1)
+        err = np.abs(got - want).max() / np.abs(want).max()
+        say(f"64^5 sparse input: max rel error {err:.2e} over 2000 sampled outputs")
+        assert err <= 5e-6
+        # dense input: Parseval (||F x||^2 = N ||x||^2) and the round trip
+        xd = torch.empty(N, dtype=torch.complex64, device="cuda")
+        fftu.fill_uniform(xd, 3, 0)
+        yd = plan(xd)
+        with fftu.Plan(n, p, "complex64", INVERSE) as inv:
+            zd = inv(yd)
+        torch.cuda.synchronize()
+        nx = torch.linalg.vector_norm(xd.to(torch.complex128)).item()
+        ny = torch.linalg.vector_norm(yd.to(torch.complex128)).item()
+        assert abs(ny * ny / (N * nx * nx) - 1.0) <= 1e-5
+        rt = (torch.linalg.vector_norm((zd - xd).to(torch.complex128)) / nx).item()
+        say(f"64^5 dense input: Parseval ratio {ny * ny / (N * nx * nx):.8f}, round trip {rt:.2e}")
+        assert rt <= 5e-6
