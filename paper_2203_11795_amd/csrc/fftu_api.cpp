@@ -467,8 +467,9 @@ bool wave_part_ok(int nh, int lph)
 }
 
 // want_logr >= 0: only splits with exactly that many register bits that k_lastx
-// has compiled for a line of 2^logl (the first such split is taken).
-bool exchange_split(const Geometry &G, fftu_dtype dt, ExchangeSplit *out, int want_logr = -1, int logl = 0)
+// has compiled for a line of 2^logl and 2^lognt threads (the first such split is taken).
+bool exchange_split(const Geometry &G, fftu_dtype dt, ExchangeSplit *out, int want_logr = -1, int logl = 0,
+                    int lognt = fftu::kLastxLogThreads)
 {
     const int rmax = dt == FFTU_C128 ? fftu::kExchangeRegBitsF64 : fftu::kExchangeRegBitsF32;
     std::vector<int> dims;
@@ -495,7 +496,7 @@ bool exchange_split(const Geometry &G, fftu_dtype dt, ExchangeSplit *out, int wa
         if (!uniform || logH > fftu::kExchangeMaxWaveBits) continue;
         if (!wave_part_ok(sp.nh, sp.lph) || !reg_part_ok(sp.nr, sp.lpr, rmax)) continue;
         if (logH > 0 && logH > logR) continue;
-        if (want_logr >= 0 && (logR != want_logr || !fftu::lastx_split_ok(logl, sp.nr, sp.lpr, sp.nh, sp.lph)))
+        if (want_logr >= 0 && (logR != want_logr || !fftu::lastx_split_ok(logl, sp.nr, sp.lpr, sp.nh, sp.lph, lognt)))
             continue;
         *out = sp;
         return true;
@@ -535,14 +536,21 @@ bool plan_lastx(const Geometry &G, const GridDesc &g, fftu_dtype dt, std::vector
     const std::vector<PassDesc> full = plan_s0(G, dt);
     if (!full.empty() && full[0].kind == fftu::kGroup2) return false;
     const int loge = fftu::line_loge(logl);
+    // 512 threads per workgroup, or 1024 where 512 cannot hold a row of every block
     ExchangeSplit sp;
-    if (!exchange_split(G, dt, &sp, loge, logl)) return false;
-    const int logrw = fftu::kLastxLogThreads - (logl - loge) - G.logP;
+    int lognt = fftu::kLastxLogThreads;
+    if (!exchange_split(G, dt, &sp, loge, logl, lognt)) {
+        lognt = fftu::kLastxMaxLogThreads;
+        if (!exchange_split(G, dt, &sp, loge, logl, lognt) ||
+            !fftu::lastx_split_needs_1024(logl, sp.nr, sp.lpr, sp.nh, sp.lph))
+            return false;
+    }
+    const int logrw = lognt - (logl - loge) - G.logP;
     if (G.logM - logl < logrw) return false;
     const int esize = dt == FFTU_C128 ? 16 : 8;
-    const uint32_t lds = fftu::lastx_lds_bytes(logl, esize);
+    const uint32_t lds = fftu::lastx_lds_bytes(logl, esize, lognt);
     if (lds > 160u * 1024u) return false;
-    if ((int64_t(1) << (G.logM - logrw - logl)) > fftu::kLastxMaxTiles) return false;
+    if ((int64_t(1) << (G.logM - logrw - logl)) > fftu::lastx_max_tiles(lognt)) return false;
     // the other dimensions outermost first (measured about 1% faster at 512^3 than
     // innermost first: the longest stride then reads the input buffer)
     s0x.clear();
@@ -557,8 +565,9 @@ bool plan_lastx(const Geometry &G, const GridDesc &g, fftu_dtype dt, std::vector
     lx = fftu::LastxDesc{};
     lx.ex = make_exchange(G, g, sp, dt);
     lx.logl = logl;
+    lx.lognt = lognt;
     lx.tiles = int64_t(1) << (G.logM - logrw - logl);
-    lx.table_lds = fftu::lastx_table_in_lds(logl, G.lognmax, esize) ? 1 : 0;
+    lx.table_lds = fftu::lastx_table_in_lds(logl, G.lognmax, esize, lognt) ? 1 : 0;
     lx.lds_bytes = lds + (lx.table_lds ? uint32_t(esize) << G.lognmax : 0u);
     return true;
 }
@@ -572,7 +581,8 @@ std::string lastx_kernel_name(const fftu::LastxDesc &lx, fftu_dtype dt, bool mul
     const ExchangeDesc &ex = lx.ex;
     const int lph = ex.nh ? ex.lph : 0, lpr = ex.nr ? ex.lpr : 0;
     return "fftu::k_lastx<" + t + ", " + s(lx.logl) + ", " + s(ex.nr) + ", " + s(lpr) + ", " + s(ex.nh) + ", " +
-           s(lph) + (mul ? ", true, false>" : (lx.table_lds ? ", false, true>" : ", false, false>"));
+           s(lph) + (mul ? ", true, false, " : (lx.table_lds ? ", false, true, " : ", false, false, ")) + s(lx.lognt) +
+           ">";
 }
 
 // omega_L^j = exp(-2 pi i j / L) for j in [L], L = 2^logL, in FP64. Each value is
@@ -1827,7 +1837,7 @@ fftu_status execute_with(fftu_plan_s *plan, const void *in, void *out, void *ws,
         lx.ex.mul = mul;
         if (mul) {   // the multiplying instantiation keeps the table in HBM
             lx.table_lds = 0;
-            lx.lds_bytes = fftu::lastx_lds_bytes(lx.logl, int(plan->esize));
+            lx.lds_bytes = fftu::lastx_lds_bytes(lx.logl, int(plan->esize), lx.lognt);
         }
         hipError_t e = fftu::launch_lastx(plan->prec, src, out, lx, plan->table, stream);
         if (e == hipSuccess) mk.mark();

@@ -98,50 +98,62 @@ struct ExchangeDesc {
 };
 
 // k_lastx (fftu_lastx.hpp): the innermost dimension's Superstep-0 lines fused with
-// the exchange. A workgroup of kLastxThreads threads holds RW rows of all P blocks;
-// its threads hold E = 2^logr elements in both the line plan (a line of 2^logl,
+// the exchange. A workgroup of 2^lognt threads holds RW rows of all P blocks; its
+// threads hold E = 2^logr elements in both the line plan (a line of 2^logl,
 // line_loge(logl) == logr) and the exchange (logr register bits, logh wave bits).
+// lognt is 9, or 10 where 512 threads cannot hold one row of every block (a line
+// of 256 over 64 blocks).
 constexpr int kLastxLogThreads = 9;
-constexpr int kLastxThreads = 1 << kLastxLogThreads;
+constexpr int kLastxMaxLogThreads = 10;
 constexpr int kLastxMinLogL = 5;
 constexpr int kLastxMaxLogL = 8;
-constexpr int64_t kLastxMaxTiles = int64_t(1) << 23;   // one workgroup per tile: 2^23 x 512 threads per grid
+// one workgroup per tile, at most 2^31 threads per grid
+constexpr int64_t lastx_max_tiles(int lognt) { return int64_t(1) << (31 - lognt); }
 
 // Compiled register/wave splits: 2^3 = (2,2,2) or 2^4 = (2,2,2,2) / (4,4) in registers,
 // and none, one 2, two 2s or one 4 across waves.
-constexpr bool lastx_split_ok(int logl, int nr, int lpr, int nh, int lph)
+constexpr bool lastx_split_ok(int logl, int nr, int lpr, int nh, int lph, int lognt = kLastxLogThreads)
 {
     const int loge = line_loge(logl);
     const bool reg = (loge == 3 && nr == 3 && lpr == 1) || (loge == 4 && ((nr == 4 && lpr == 1) || (nr == 2 && lpr == 2)));
     const bool wave = (nh == 0) || (nh == 1 && (lph == 1 || lph == 2)) || (nh == 2 && lph == 1);
     const int logh = nh * lph, logp = nr * lpr + logh;
     const int logtpl = logl - loge;
-    const int logrw = kLastxLogThreads - logtpl - logp;
+    const int logrw = lognt - logtpl - logp;
     return logl >= kLastxMinLogL && logl <= kLastxMaxLogL && reg && wave && logh <= 2 && logrw >= 0 &&
-           logrw + logl >= 6;
+           logrw + logl >= 6 && (lognt == kLastxLogThreads || lognt == kLastxMaxLogThreads);
+}
+
+// The 1024-thread kernel exists only for the splits that 512 threads cannot hold.
+constexpr bool lastx_split_needs_1024(int logl, int nr, int lpr, int nh, int lph)
+{
+    return !lastx_split_ok(logl, nr, lpr, nh, lph, kLastxLogThreads) &&
+           lastx_split_ok(logl, nr, lpr, nh, lph, kLastxMaxLogThreads);
 }
 
 // LDS bytes of k_lastx: omega_L table, then max(transpose, line stages) rows of 8-byte words.
-constexpr uint32_t lastx_lds_bytes(int logl, int esize)
+constexpr uint32_t lastx_lds_bytes(int logl, int esize, int lognt = kLastxLogThreads)
 {
     const int L = 1 << logl;
     const int tpl = 1 << (logl - line_loge(logl));
     const int lp = L + tpl, pitch = L + L / 16 + 1;
-    const int lines = 1 << (kLastxLogThreads - (logl - line_loge(logl)));
+    const int lines = 1 << (lognt - (logl - line_loge(logl)));
     return uint32_t(L * esize + lines * (lp > pitch ? lp : pitch) * 8);
 }
 
-// k_lastx copies the omega table into LDS when two workgroups per CU still fit.
+// k_lastx copies the omega table into LDS when two 512-thread workgroups per CU still fit.
 constexpr uint32_t kLastxTableLdsMax = 80 * 1024;
-constexpr bool lastx_table_in_lds(int logl, int lognmax, int esize)
+constexpr bool lastx_table_in_lds(int logl, int lognmax, int esize, int lognt = kLastxLogThreads)
 {
-    return uint64_t(lastx_lds_bytes(logl, esize)) + (uint64_t(esize) << lognmax) <= kLastxTableLdsMax;
+    return lognt == kLastxLogThreads &&
+           uint64_t(lastx_lds_bytes(logl, esize, lognt)) + (uint64_t(esize) << lognmax) <= kLastxTableLdsMax;
 }
 
 struct LastxDesc {
     ExchangeDesc ex;       // its conj_in must be 0: the lines take the input conjugation
     int64_t tiles;         // M / (RW m_d)
     int32_t logl;
+    int32_t lognt;         // log2 threads per workgroup (9 or 10)
     int32_t conj_in;       // conjugate on load (the first kernel of a plan)
     int32_t table_lds;     // the omega table in LDS (plain plans; convolution keeps it in HBM)
     uint32_t lds_bytes;    // with table_lds: lastx_lds_bytes + the table

@@ -13,9 +13,9 @@
 // and finishes as k_exchange does: twiddle by prod_l omega_{n_l}^{k_l s'_l},
 // the length-p_l DFTs, and the scatter to V^(r)[t + k' q] (Theorem 2.1).
 //
-// The tile is kLastxThreads threads x E elements, E = 2^LOGR the register
-// sources per thread of the exchange and the elements per thread of the line
-// plan alike. complex128 goes through LDS as two rounds of doubles.
+// The tile is 2^LOGNT threads x E elements, E = 2^LOGR the register sources per
+// thread of the exchange and the elements per thread of the line plan alike.
+// complex128 goes through LDS as two rounds of doubles.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -29,10 +29,9 @@
 
 namespace fftu {
 
-template <int LOGL, int LOGR, int LOGH>
+template <int LOGL, int LOGR, int LOGH, int LOGNT>
 struct LastxShape {
     using PL = LinePlan<LOGL>;
-    static constexpr int LOGNT = kLastxLogThreads;
     static constexpr int LOGP = LOGR + LOGH;
     static constexpr int LOGW = LOGNT - PL::LOGTPL;   // lines per tile: P x RW
     static constexpr int LOGRW = LOGW - LOGP;         // rows per tile
@@ -43,26 +42,29 @@ struct LastxShape {
     static constexpr int WORDS = (1 << LOGW) * (LP > PITCH ? LP : PITCH);   // 8-byte LDS words
 };
 
-// Two workgroups per CU: 4 waves per SIMD, at most 128 VGPRs. MUL: every output is
-// multiplied by lx.ex.mul at its position (convolution); the multipliers are all
-// loaded before the stores, so its bound leaves the compiler up to 256 VGPRs.
-// TL: the exchange's twiddles come from an LDS copy of the omega table, placed
-// after the work area (the planner takes it when two workgroups per CU still fit).
-template <typename T, int LOGL, int NR, int LPR, int NH, int LPH, bool MUL, bool TL>
-__global__ __launch_bounds__(kLastxThreads, MUL ? 2 : 4) void k_lastx(const cx<T> *__restrict__ in,
+// 512 threads: two workgroups per CU, 4 waves per SIMD, at most 128 VGPRs. 1024
+// threads: one workgroup of 16 waves per CU, the same register bound. MUL: every
+// output is multiplied by lx.ex.mul at its position (convolution); the multipliers
+// are all loaded before the stores, so the 512-thread bound leaves the compiler up
+// to 256 VGPRs. TL: the exchange's twiddles come from an LDS copy of the omega
+// table, placed after the work area (the planner takes it when two 512-thread
+// workgroups per CU still fit).
+template <typename T, int LOGL, int NR, int LPR, int NH, int LPH, bool MUL, bool TL, int LOGNT>
+__global__ __launch_bounds__(1 << LOGNT, (MUL && LOGNT == 9) ? 2 : 4) void k_lastx(const cx<T> *__restrict__ in,
                                                                       cx<T> *__restrict__ out, const LastxDesc lx,
                                                                       const cx<T> *__restrict__ table)
 {
     constexpr int LOGR = NR * LPR, LOGH = NH * LPH;
-    using S = LastxShape<LOGL, LOGR, LOGH>;
+    constexpr int NT = 1 << LOGNT;
+    using S = LastxShape<LOGL, LOGR, LOGH, LOGNT>;
     using PL = typename S::PL;
-    static_assert(lastx_split_ok(LOGL, NR, LPR, NH, LPH), "k_lastx: no such split");
+    static_assert(lastx_split_ok(LOGL, NR, LPR, NH, LPH, LOGNT), "k_lastx: no such split");
     static_assert(PL::LOGE == LOGR && S::LOGRW >= 0, "k_lastx: the line plan and the exchange split disagree");
-    static_assert(lastx_lds_bytes(LOGL, sizeof(cx<T>)) == S::L * sizeof(cx<T>) + S::WORDS * 8,
+    static_assert(lastx_lds_bytes(LOGL, sizeof(cx<T>), LOGNT) == S::L * sizeof(cx<T>) + S::WORDS * 8,
                   "k_lastx: LDS size");
     constexpr int R = 1 << LOGR;
     constexpr int H = 1 << LOGH;
-    constexpr int KG = (kLastxThreads / 64) / H;
+    constexpr int KG = (NT / 64) / H;
     static_assert(KG * 64 == (1 << S::LOGK), "k_lastx: one tile is KG groups of 64 local indices");
 
     extern __shared__ unsigned char smem_raw[];
@@ -72,7 +74,7 @@ __global__ __launch_bounds__(kLastxThreads, MUL ? 2 : 4) void k_lastx(const cx<T
     line_twiddles<T, LOGL>(tw, table, lx.ex.g.lognmax, tid);
     cx<T> *ttab = reinterpret_cast<cx<T> *>(work + S::WORDS * 8);
     if constexpr (TL)
-        for (int e = tid; e < (1 << lx.ex.g.lognmax); e += kLastxThreads) ttab[e] = table[e];
+        for (int e = tid; e < (1 << lx.ex.g.lognmax); e += NT) ttab[e] = table[e];
 
     // line layout: thread (w, j) holds line w = s RW + row, register m <-> position j + TPL m
     const int j = tid & (PL::TPL - 1);
@@ -135,7 +137,7 @@ __global__ __launch_bounds__(kLastxThreads, MUL ? 2 : 4) void k_lastx(const cx<T
             for (int jj = 0; jj < R; ++jj) u[jj] = ld[rd + (jj << S::LOGRW) * S::LP];
         }
 
-        exchange_core<T, NR, LPR, NH, LPH, kLastxThreads, false, MUL ? 2 : 1>(
+        exchange_core<T, NR, LPR, NH, LPH, NT, false, MUL ? 2 : 1>(
             out, lx.ex, TL ? ttab : table, work, (tile << S::LOGK) + kk, tid,
             [&](int jj, int, int64_t, bool) { return u[jj]; });
     }
@@ -143,29 +145,43 @@ __global__ __launch_bounds__(kLastxThreads, MUL ? 2 : 4) void k_lastx(const cx<T
 
 namespace lastx_detail {
 
+template <typename T, int LOGL, int NR, int LPR, int NH, int LPH, int LOGNT>
+hipError_t go_nt(const void *in, void *out, const LastxDesc &lx, const void *table, hipStream_t stream)
+{
+    if (lx.tiles < 1 || lx.tiles > lastx_max_tiles(LOGNT)) return hipErrorInvalidValue;
+    const uint32_t blocks = uint32_t(lx.tiles);
+    const dim3 threads(1u << LOGNT);
+    const cx<T> *a = static_cast<const cx<T> *>(in), *tab = static_cast<const cx<T> *>(table);
+    cx<T> *b = static_cast<cx<T> *>(out);
+    const uint32_t base = lastx_lds_bytes(LOGL, sizeof(cx<T>), LOGNT);
+    if (lx.ex.mul) {
+        if (lx.lds_bytes != base) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_lastx<T, LOGL, NR, LPR, NH, LPH, true, false, LOGNT>), dim3(blocks), threads,
+                           lx.lds_bytes, stream, a, b, lx, tab);
+    } else if (lx.table_lds) {
+        if constexpr (LOGNT == kLastxLogThreads) {
+            if (lx.lds_bytes != base + (uint32_t(sizeof(cx<T>)) << lx.ex.g.lognmax)) return hipErrorInvalidValue;
+            hipLaunchKernelGGL((k_lastx<T, LOGL, NR, LPR, NH, LPH, false, true, LOGNT>), dim3(blocks), threads,
+                               lx.lds_bytes, stream, a, b, lx, tab);
+        } else {
+            return hipErrorInvalidValue;
+        }
+    } else {
+        if (lx.lds_bytes != base) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_lastx<T, LOGL, NR, LPR, NH, LPH, false, false, LOGNT>), dim3(blocks), threads,
+                           lx.lds_bytes, stream, a, b, lx, tab);
+    }
+    return hipGetLastError();
+}
+
 template <typename T, int LOGL, int NR, int LPR, int NH, int LPH>
 hipError_t go(const void *in, void *out, const LastxDesc &lx, const void *table, hipStream_t stream)
 {
-    if constexpr (lastx_split_ok(LOGL, NR, LPR, NH, LPH)) {
-        if (lx.tiles < 1 || lx.tiles > kLastxMaxTiles) return hipErrorInvalidValue;
-        const uint32_t blocks = uint32_t(lx.tiles);
-        const cx<T> *a = static_cast<const cx<T> *>(in), *tab = static_cast<const cx<T> *>(table);
-        cx<T> *b = static_cast<cx<T> *>(out);
-        const uint32_t base = lastx_lds_bytes(LOGL, sizeof(cx<T>));
-        if (lx.ex.mul) {
-            if (lx.lds_bytes != base) return hipErrorInvalidValue;
-            hipLaunchKernelGGL((k_lastx<T, LOGL, NR, LPR, NH, LPH, true, false>), dim3(blocks),
-                               dim3(kLastxThreads), lx.lds_bytes, stream, a, b, lx, tab);
-        } else if (lx.table_lds) {
-            if (lx.lds_bytes != base + (uint32_t(sizeof(cx<T>)) << lx.ex.g.lognmax)) return hipErrorInvalidValue;
-            hipLaunchKernelGGL((k_lastx<T, LOGL, NR, LPR, NH, LPH, false, true>), dim3(blocks),
-                               dim3(kLastxThreads), lx.lds_bytes, stream, a, b, lx, tab);
-        } else {
-            if (lx.lds_bytes != base) return hipErrorInvalidValue;
-            hipLaunchKernelGGL((k_lastx<T, LOGL, NR, LPR, NH, LPH, false, false>), dim3(blocks),
-                               dim3(kLastxThreads), lx.lds_bytes, stream, a, b, lx, tab);
-        }
-        return hipGetLastError();
+    if constexpr (lastx_split_ok(LOGL, NR, LPR, NH, LPH, kLastxLogThreads)) {
+        if (lx.lognt == kLastxLogThreads) return go_nt<T, LOGL, NR, LPR, NH, LPH, kLastxLogThreads>(in, out, lx, table, stream);
+    } else if constexpr (lastx_split_needs_1024(LOGL, NR, LPR, NH, LPH)) {
+        if (lx.lognt == kLastxMaxLogThreads)
+            return go_nt<T, LOGL, NR, LPR, NH, LPH, kLastxMaxLogThreads>(in, out, lx, table, stream);
     }
     return hipErrorInvalidValue;
 }

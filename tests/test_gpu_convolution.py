@@ -123,7 +123,7 @@ def test_convolution_through_fused_last_dimension(torch, n, p, dtype):
     want = oracle.circular_convolution(x.astype(np.complex128), h.astype(np.complex128))
     with fftu.ConvolutionPlan(n, p, dtype) as plan:
         assert plan.info()["exchange_fused"] == 2
-        assert plan.launch_names()[-1].startswith("fftu::k_lastx<") and plan.launch_names()[-1].endswith(", true, false>")
+        assert plan.launch_names()[-1].startswith("fftu::k_lastx<") and plan.launch_names()[-1].endswith(", true, false, 9>")
         xc = dev(torch, oracle.to_cyclic(x, p).astype(NP[dtype]))
         hhat = plan(dev(torch, oracle.to_cyclic(h, p).astype(NP[dtype])))
         y = plan.convolve(xc, hhat)

@@ -39,6 +39,11 @@ CASES = [
     ((4, 4, 4, 4, 512), (2, 2, 2, 2, 2), (8, 4, 1, 1, 1)),
     ((16, 1024), (4, 4), (8, 2, 2, 0, 0)),
     ((8, 16, 1024), (2, 4, 4), (8, 2, 2, 1, 1)),
+    # 1024-thread tiles: a row of 256 in each of 64 blocks (the 1024^3 / 4x4x4 kernel)
+    ((16, 16, 1024), (4, 4, 4), (8, 2, 2, 1, 2)),
+    ((4, 4, 16, 1024), (2, 2, 4, 4), (8, 2, 2, 2, 1)),
+    ((16, 4, 4, 4, 512), (4, 2, 2, 2, 2), (8, 4, 1, 1, 2)),
+    ((4, 4, 4, 4, 4, 512), (2, 2, 2, 2, 2, 2), (8, 4, 1, 2, 1)),
 ]
 IDS = [f"{'x'.join(map(str, n))}-p{'x'.join(map(str, p))}" for n, p, _ in CASES]
 
@@ -83,6 +88,8 @@ def test_lastx_matches_oracle(torch_dev, n, p, split, dtype, direction):
     t = "double" if dtype == "complex128" else "float"
     assert info["exchange_fused"] == 2 and info["launches"] == info["s0_kernels"] + 1
     assert names[-1].startswith(f"fftu::k_lastx<{t}, {', '.join(map(str, split))}, false, ")
+    lognt = 10 if (split[0], split[3] * split[4]) == (8, 2) else 9     # rows of 256 over 2 wave bits: 1024
+    assert names[-1].endswith(f", {lognt}>")
     want = oracle.cyclic_dft(D.astype(np.complex128), n, p, direction)
     err = oracle.rel_l2(got, want)
     assert err <= TOL[dtype], f"rel-L2 {err:.3e}"

@@ -210,7 +210,7 @@ def test_launch_names(torch_dev):
     import paper_2203_11795_amd as fftu
     with fftu.Plan((512, 512, 512), (4, 4, 4), "complex128", FORWARD) as plan:
         assert plan.launch_names() == ["fftu::k_line<double, 7, 1>", "fftu::k_line<double, 7, 1>",
-                                       "fftu::k_lastx<double, 7, 2, 2, 1, 2, false, true>"]
+                                       "fftu::k_lastx<double, 7, 2, 2, 1, 2, false, true, 9>"]
     fftu.set_tuning("fuse_last", 0)
     try:
         with fftu.Plan((512, 512, 512), (4, 4, 4), "complex128", FORWARD) as plan:
