@@ -162,9 +162,17 @@ def run_batch(args, torch, np, fftu, synth, with_oracle):
     # different pass structures (the plain plans fuse the two inner dimensions), so not bitwise
     diff = max(float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b)) for a, b in zip(outs, outs_plain))
 
-    # passes each member runs in the batch: its Superstep-0 passes (the batch groups the
-    # two inner dimensions under the same rule as a single plan) plus the exchange
-    exec_passes = [fftu.describe(s, (2, 2, 2), "complex64")["s0_kernels"] + 1 for s in shapes]
+    # passes each member runs in the batch: its Superstep-0 passes plus the exchange. The
+    # batch groups the two inner dimensions under the single-plan rule but has neither
+    # k_pair passes nor the fused innermost dimension, so those are off while counting.
+    saved = {k: fftu.get_tuning(k) for k in ("fuse_last", "pair")}
+    try:
+        for k in saved:
+            fftu.set_tuning(k, 0)
+        exec_passes = [fftu.describe(s, (2, 2, 2), "complex64")["s0_kernels"] + 1 for s in shapes]
+    finally:
+        for k, v in saved.items():
+            fftu.set_tuning(k, v)
     bytes_exec = sum(2.0 * esize * n * k for n, k in zip(sizes, exec_passes))
     bytes_ideal = sum(2.0 * esize * n * ideal_passes(s, (2, 2, 2), esize) for n, s in zip(sizes, shapes))
     k_ms = per_launch[1] if len(per_launch) > 1 else ms_persistent

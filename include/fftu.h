@@ -97,7 +97,8 @@ typedef enum {
     FFTU_TUNE_LINE_PAD = 2,          /* LDS padding (elements) per row of a strided pass tile (0..4) */
     FFTU_TUNE_MAX_LDS_KB = 3,        /* LDS budget per workgroup of a pass, KiB (16..160; default 64) */
     FFTU_TUNE_FUSE_LAST = 4,         /* 0: never fuse the innermost dimension's lines into the exchange; 1 / -1: when possible */
-    FFTU_TUNE_COUNT = 5
+    FFTU_TUNE_PAIR = 5,              /* 0: one pass per strided dimension; 1 / -1: two adjacent dimensions of 8..32-point lines share a pass */
+    FFTU_TUNE_COUNT = 6
 } fftu_tune_param;
 
 /* Set a tuning knob; FFTU_ERROR_INVALID_VALUE for an unknown knob or a value out of range. */

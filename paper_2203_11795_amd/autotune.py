@@ -21,13 +21,14 @@ import statistics
 
 from . import fftu as _b
 
-KNOB_NAMES = ("line_strided_logw", "line_contig_logw", "line_pad", "max_lds_kb", "fuse_last")
+KNOB_NAMES = ("line_strided_logw", "line_contig_logw", "line_pad", "max_lds_kb", "fuse_last", "pair")
 CANDIDATES = {
     "line_strided_logw": (-1, 2, 3, 4, 5, 6),
     "line_contig_logw": (-1, 0, 1, 2, 3, 4),
     "line_pad": (-1, 0, 2),
     "max_lds_kb": (-1, 32, 96, 160),
     "fuse_last": (-1, 0),
+    "pair": (-1, 0),
 }
 
 

@@ -89,10 +89,10 @@ thread_local fftu_status g_last = FFTU_SUCCESS;
 
 // Planner tuning knobs (fftu_set_tuning); -1 = default.
 // Planner knobs (fftu_set_tuning): process-wide, read when a plan is made.
-std::atomic<int> g_tune[FFTU_TUNE_COUNT] = {{-1}, {-1}, {-1}, {-1}, {-1}};
+std::atomic<int> g_tune[FFTU_TUNE_COUNT] = {{-1}, {-1}, {-1}, {-1}, {-1}, {-1}};
 int knob(int i) { return g_tune[i].load(std::memory_order_relaxed); }
-const int g_tune_min[FFTU_TUNE_COUNT] = {2, 0, 0, 16, 0};
-const int g_tune_max[FFTU_TUNE_COUNT] = {6, 8, 4, 160, 1};
+const int g_tune_min[FFTU_TUNE_COUNT] = {2, 0, 0, 16, 0, 0};
+const int g_tune_max[FFTU_TUNE_COUNT] = {6, 8, 4, 160, 1, 1};
 
 int64_t lds_cap()
 {
@@ -371,10 +371,45 @@ bool make_group2_pass(int logA, int logL1, int logL2, fftu_dtype dt, int lognmax
     return pd.lds_bytes <= lds_cap();
 }
 
+// k_pair: two adjacent dimensions (outer lines of 2^logLA, inner lines of 2^logLB,
+// B = 2^logB elements after them, A = 2^logA outer blocks) in one strided pass.
+// Needs lines of 8..32 points and whole tiles of W columns inside B.
+bool make_pair_pass(int logA, int logLA, int logLB, int logB, fftu_dtype dt, int lognmax, PassDesc &pd)
+{
+    if (knob(FFTU_TUNE_PAIR) == 0) return false;
+    if (logLA < fftu::kPairMinLogL || logLA > fftu::kPairMaxLogL || logLB < fftu::kPairMinLogL ||
+        logLB > fftu::kPairMaxLogL)
+        return false;
+    const int esize = dt == FFTU_C128 ? 16 : 8;
+    const int logW = fftu::pair_logw(logLA, logLB, esize);
+    if (logB < logW) return false;
+    const int64_t tiles = int64_t(1) << (logA + logB - logW);
+    if (tiles > fftu::pair_max_tiles(esize)) return false;
+    pd = PassDesc{};
+    pd.kind = fftu::kPair;
+    pd.threads = 1 << fftu::pair_lognt(esize);
+    pd.tiles = tiles;
+    pd.naxes = 2;
+    pd.loglen[0] = logLA;
+    pd.loglen[1] = logLB;
+    pd.logG = logLA + logLB;
+    pd.logB = logB;
+    pd.GB = int64_t(1) << (pd.logG + logB);
+    pd.logW = logW;
+    pd.logBt = logW;
+    pd.logTPA = logB - logW;
+    pd.lw = fftu::pair_pitch(logLA, logLB, esize);
+    pd.lognmax = lognmax;
+    pd.scale = 1.0;
+    pd.lds_bytes = fftu::pair_lds_bytes(logLA, logLB, esize);
+    return true;
+}
+
 // Superstep 0: the local d-D FFT as a sequence of passes, innermost dimension
 // first (the order is free: the DFT factorises over dimensions, eq. (1.3)).
 // The two innermost dimensions share one k_group2 pass when their planes are
-// small; every other dimension gets its own pass.
+// small; further dimensions share k_pair passes two by two where their lines
+// are short, and the rest get one pass each.
 std::vector<PassDesc> plan_s0(const Geometry &G, fftu_dtype dt)
 {
     std::vector<PassDesc> passes;
@@ -402,6 +437,13 @@ std::vector<PassDesc> plan_s0(const Geometry &G, fftu_dtype dt)
     }
     for (size_t i = first; i < dims.size(); ++i) {
         const int l = dims[i];
+        PassDesc pd;
+        if (i + 1 < dims.size() &&
+            make_pair_pass(outer_of(dims[i + 1]), G.logm[dims[i + 1]], G.logm[l], inner_of(l), dt, G.lognmax, pd)) {
+            passes.push_back(pd);
+            ++i;
+            continue;
+        }
         passes.push_back(make_pass(outer_of(l), {G.logm[l]}, inner_of(l), dt, G.lognmax));
     }
     return passes;
@@ -521,11 +563,12 @@ ExchangeDesc make_exchange(const Geometry &G, const GridDesc &g, const ExchangeS
     return ex;
 }
 
-// k_lastx: Superstep 0 of every dimension but the innermost as ordinary passes,
-// then the innermost dimension's lines, the twiddle, the exchange and the
-// length-p FFTs in one kernel. Taken when the innermost dimension would have had
-// a pass of its own (no k_group2 with its neighbour), k_lastx has a kernel for
-// its line length and the grid, and a tile's rows exist.
+// k_lastx: Superstep 0 of every dimension but the innermost as ordinary passes
+// (k_pair for adjacent short lines), then the innermost dimension's lines, the
+// twiddle, the exchange and the length-p FFTs in one kernel. Taken when k_lastx
+// has a kernel for the line length and the grid and a tile's rows exist, and,
+// where the innermost two dimensions would share a k_group2 pass, when it saves
+// a pass over that plan.
 bool plan_lastx(const Geometry &G, const GridDesc &g, fftu_dtype dt, std::vector<PassDesc> &s0x,
                 fftu::LastxDesc &lx)
 {
@@ -533,8 +576,6 @@ bool plan_lastx(const Geometry &G, const GridDesc &g, fftu_dtype dt, std::vector
     const int li = G.d - 1;
     const int logl = G.logm[li];
     if (logl < fftu::kLastxMinLogL || logl > fftu::kLastxMaxLogL) return false;
-    const std::vector<PassDesc> full = plan_s0(G, dt);
-    if (!full.empty() && full[0].kind == fftu::kGroup2) return false;
     const int loge = fftu::line_loge(logl);
     // 512 threads per workgroup, or 1024 where 512 cannot hold a row of every block
     ExchangeSplit sp;
@@ -553,15 +594,34 @@ bool plan_lastx(const Geometry &G, const GridDesc &g, fftu_dtype dt, std::vector
     if ((int64_t(1) << (G.logM - logrw - logl)) > fftu::lastx_max_tiles(lognt)) return false;
     // the other dimensions outermost first (measured about 1% faster at 512^3 than
     // innermost first: the longest stride then reads the input buffer)
-    s0x.clear();
-    for (int l = 0; l <= G.d - 2; ++l) {
-        if (G.logm[l] > 0) {
-            int logA = G.logP, logB = 0;
-            for (int j = 0; j < l; ++j) logA += G.logm[j];
-            for (int j = l + 1; j < G.d; ++j) logB += G.logm[j];
-            s0x.push_back(make_pass(logA, {G.logm[l]}, logB, dt, G.lognmax));
+    std::vector<int> od;   // the other dimensions with m_l > 1, outermost first
+    for (int l = 0; l <= G.d - 2; ++l)
+        if (G.logm[l] > 0) od.push_back(l);
+    auto outer_of = [&](int l) {
+        int logA = G.logP;
+        for (int j = 0; j < l; ++j) logA += G.logm[j];
+        return logA;
+    };
+    auto inner_of = [&](int l) {
+        int logB = 0;
+        for (int j = l + 1; j < G.d; ++j) logB += G.logm[j];
+        return logB;
+    };
+    std::vector<PassDesc> passes;
+    for (size_t i = 0; i < od.size(); ++i) {
+        const int l = od[i];
+        PassDesc pd;
+        if (i + 1 < od.size() &&
+            make_pair_pass(outer_of(l), G.logm[l], G.logm[od[i + 1]], inner_of(od[i + 1]), dt, G.lognmax, pd)) {
+            passes.push_back(pd);
+            ++i;
+            continue;
         }
+        passes.push_back(make_pass(outer_of(l), {G.logm[l]}, inner_of(l), dt, G.lognmax));
     }
+    const std::vector<PassDesc> full = plan_s0(G, dt);
+    if (!full.empty() && full[0].kind == fftu::kGroup2 && passes.size() >= full.size()) return false;
+    s0x = passes;
     lx = fftu::LastxDesc{};
     lx.ex = make_exchange(G, g, sp, dt);
     lx.logl = logl;
@@ -823,6 +883,8 @@ std::string pass_kernel_name(const PassDesc &pd, fftu_dtype dt)
     const std::string t = dt == FFTU_C128 ? "double" : "float";
     if (pd.kind == fftu::kGroup2)
         return "fftu::k_group2<" + t + ", " + std::to_string(pd.loglen[0]) + ", " + std::to_string(pd.loglen[1]) + ">";
+    if (pd.kind == fftu::kPair)
+        return "fftu::k_pair<" + t + ", " + std::to_string(pd.loglen[0]) + ", " + std::to_string(pd.loglen[1]) + ">";
     if (pd.kind == fftu::kTilePass) return "fftu::k_pass<" + t + ">";
     return "fftu::k_line<" + t + ", " + std::to_string(pd.loglen[0]) + ", " + std::to_string(pd.kind) + ">";
 }

@@ -32,6 +32,7 @@ constexpr int kLineStrided = 1;
 constexpr int kLineContig = 2;
 constexpr int kLineStaged = 3;
 constexpr int kGroup2 = 4;             // k_group2: two innermost dimensions of small contiguous planes
+constexpr int kPair = 5;               // k_pair: two adjacent strided dimensions of short lines (fftu_pair.hip)
 constexpr int kLineMaxThreads = 256;   // k_line workgroup bound (register budget per thread)
 
 // Radix split of k_line for a line of 2^logl: 1, 2 or 3 stages of 2^line_loge
@@ -96,6 +97,28 @@ struct ExchangeDesc {
     uint32_t lds_bytes;
     const void *mul;       // null, or N elements in the output layout that every output is multiplied by
 };
+
+// k_pair (fftu_pair.hip): lines of 2^3..2^5 points along two adjacent dimensions,
+// one whole line per thread. 512 threads (complex64) or 256 (complex128); a tile
+// is W = threads / max(LA, LB) columns, W * esize = 128 bytes or more.
+constexpr int kPairMinLogL = 3;
+constexpr int kPairMaxLogL = 5;
+constexpr int pair_lognt(int esize) { return esize == 16 ? 8 : 9; }
+constexpr int pair_logw(int logla, int loglb, int esize)
+{
+    return pair_lognt(esize) - (logla > loglb ? logla : loglb);
+}
+// words (one real part) per inner position of the LDS transpose: LA W plus W of
+// padding, so that the column reads of a wave fall in distinct banks
+constexpr int pair_pitch(int logla, int loglb, int esize)
+{
+    return ((1 << logla) + 1) << pair_logw(logla, loglb, esize);
+}
+constexpr uint32_t pair_lds_bytes(int logla, int loglb, int esize)
+{
+    return uint32_t((1 << loglb) * pair_pitch(logla, loglb, esize) * (esize / 2));
+}
+constexpr int64_t pair_max_tiles(int esize) { return int64_t(1) << (31 - pair_lognt(esize)); }
 
 // k_lastx (fftu_lastx.hpp): the innermost dimension's Superstep-0 lines fused with
 // the exchange. A workgroup of 2^lognt threads holds RW rows of all P blocks; its
@@ -287,6 +310,7 @@ hipError_t launch_twiddle(Precision prec, const void *in, void *out, const GridD
 hipError_t launch_permute(Precision prec, const void *in, void *out, const GridDesc &g, hipStream_t stream);
 hipError_t launch_exchange(Precision prec, const void *in, void *out, const ExchangeDesc &ex, const void *table,
                            hipStream_t stream);
+hipError_t launch_pair(Precision prec, const void *in, void *out, const PassDesc &pd, hipStream_t stream);
 hipError_t launch_lastx(Precision prec, const void *in, void *out, const LastxDesc &lx, const void *table,
                         hipStream_t stream);
 

@@ -11,6 +11,17 @@
 namespace fftu {
 hipError_t launch_pass(Precision, const void *, void *, const PassDesc &pd, const void *, hipStream_t)
 {
+    if (pd.kind == kPair) {
+        // a compiled pair of line lengths, whole tiles of columns inside B, LDS within the CU
+        const int esize = pd.threads == (1 << pair_lognt(16)) ? 16 : 8;
+        if (pd.naxes != 2 || pd.loglen[0] < kPairMinLogL || pd.loglen[0] > kPairMaxLogL ||
+            pd.loglen[1] < kPairMinLogL || pd.loglen[1] > kPairMaxLogL) std::abort();
+        if (pd.logW != pair_logw(pd.loglen[0], pd.loglen[1], esize) || pd.logB < pd.logW ||
+            pd.logTPA != pd.logB - pd.logW || pd.tiles > pair_max_tiles(esize) ||
+            pd.lds_bytes != pair_lds_bytes(pd.loglen[0], pd.loglen[1], esize) || pd.lds_bytes > 80 * 1024)
+            std::abort();
+        return hipSuccess;
+    }
     // every tile of the pass must fit the LDS tile the kernel is compiled for
     if ((int64_t(1) << (pd.logG + pd.logW)) > (int64_t(1) << kLogTileF32)) std::abort();
     return hipSuccess;

@@ -101,8 +101,9 @@ def test_p_max_examples():
 
 @pytest.mark.parametrize("n,p,dtype,s0,fused,launches", [
     ((512, 512, 512), (4, 4, 4), "complex128", 2, 2, 3),    # dims 2, 1 as passes; dim 3 fused with the exchange
-    ((64, 64, 64), (2, 2, 2), "complex128", 2, 1, 3),
-    ((64,) * 5, (2,) * 5, "complex64", 4, 1, 5),
+    ((64, 64, 64), (2, 2, 2), "complex128", 1, 2, 2),      # dims 1, 2 in one k_pair pass; dim 3 fused
+    ((64,) * 5, (2,) * 5, "complex64", 2, 2, 3),            # k_pair (1, 2), k_pair (3, 4); dim 5 fused
+    ((32,) * 4, (2,) * 4, "complex64", 2, 1, 3),            # k_pair (1, 2), k_group2 (3, 4), k_exchange
     ((1024,) * 3, (16, 16, 16), "complex128", 3, 0, 8),
     ((1,), (1,), "complex128", 0, 1, 1),
     ((60, 60), (2, 2), "complex128", 2, 1, 3),            # mixed radix: 2 passes, then k_mexchange
@@ -130,14 +131,14 @@ def test_info_struct_layout_matches_header():
 
 
 def test_tuning_knobs_roundtrip_and_ranges():
-    names = ["line_strided_logw", "line_contig_logw", "line_pad", "max_lds_kb", "fuse_last"]
+    names = ["line_strided_logw", "line_contig_logw", "line_pad", "max_lds_kb", "fuse_last", "pair"]
     try:
         for name in names:
             assert fftu.get_tuning(name) == -1
         fftu.set_tuning("line_strided_logw", 4)
         assert fftu.get_tuning("line_strided_logw") == 4
         for name, bad in [("line_strided_logw", 1), ("line_strided_logw", 7), ("line_pad", 5), ("max_lds_kb", 8),
-                          ("max_lds_kb", 161), ("line_contig_logw", 9), ("fuse_last", 2)]:
+                          ("max_lds_kb", 161), ("line_contig_logw", 9), ("fuse_last", 2), ("pair", 2), ("pair", -2)]:
             with pytest.raises(fftu.FftuError):
                 fftu.set_tuning(name, bad)
         lib = fftu.load_library()

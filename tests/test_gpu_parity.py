@@ -219,8 +219,19 @@ def test_launch_names(torch_dev):
     finally:
         fftu.set_tuning("fuse_last", -1)
     with fftu.Plan((64,) * 5, (2,) * 5, "complex64", FORWARD) as plan:
-        names = plan.launch_names()
-        assert names[0] == "fftu::k_group2<float, 5, 5>" and names[-1] == "fftu::k_exchange<float, 5, 1, 0, 0>"
+        # dimensions (1, 2) and (3, 4) in k_pair passes, dimension 5 fused with the exchange
+        assert plan.launch_names() == ["fftu::k_pair<float, 5, 5>", "fftu::k_pair<float, 5, 5>",
+                                       "fftu::k_lastx<float, 5, 3, 1, 2, 1, false, true, 9>"]
+    fftu.set_tuning("fuse_last", 0)
+    fftu.set_tuning("pair", 0)
+    try:
+        with fftu.Plan((64,) * 5, (2,) * 5, "complex64", FORWARD) as plan:
+            names = plan.launch_names()
+            assert names[0] == "fftu::k_group2<float, 5, 5>" and names[-1] == "fftu::k_exchange<float, 5, 1, 0, 0>"
+            assert len(names) == 5
+    finally:
+        fftu.set_tuning("fuse_last", -1)
+        fftu.set_tuning("pair", -1)
     with fftu.Plan((64, 64, 64), (8, 8, 2), "complex128", FORWARD) as plan:
         # unfused exchange: Superstep 0 passes, twiddle, permutation, then Superstep 2 passes
         names = plan.launch_names()
