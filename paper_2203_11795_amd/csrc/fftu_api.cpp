@@ -381,13 +381,14 @@ bool make_pair_pass(int logA, int logLA, int logLB, int logB, fftu_dtype dt, int
         logLB > fftu::kPairMaxLogL)
         return false;
     const int esize = dt == FFTU_C128 ? 16 : 8;
-    const int logW = fftu::pair_logw(logLA, logLB, esize);
+    const int lognt = fftu::pair_lognt(logLA, logLB, logB, esize);
+    const int logW = fftu::pair_logw(logLA, logLB, lognt);
     if (logB < logW) return false;
     const int64_t tiles = int64_t(1) << (logA + logB - logW);
-    if (tiles > fftu::pair_max_tiles(esize)) return false;
+    if (tiles > fftu::pair_max_tiles(lognt)) return false;
     pd = PassDesc{};
     pd.kind = fftu::kPair;
-    pd.threads = 1 << fftu::pair_lognt(esize);
+    pd.threads = 1 << lognt;
     pd.tiles = tiles;
     pd.naxes = 2;
     pd.loglen[0] = logLA;
@@ -398,10 +399,10 @@ bool make_pair_pass(int logA, int logLA, int logLB, int logB, fftu_dtype dt, int
     pd.logW = logW;
     pd.logBt = logW;
     pd.logTPA = logB - logW;
-    pd.lw = fftu::pair_pitch(logLA, logLB, esize);
+    pd.lw = fftu::pair_pitch(logLA, logLB, lognt);
     pd.lognmax = lognmax;
     pd.scale = 1.0;
-    pd.lds_bytes = fftu::pair_lds_bytes(logLA, logLB, esize);
+    pd.lds_bytes = fftu::pair_lds_bytes(logLA, logLB, lognt, esize);
     return true;
 }
 
@@ -884,7 +885,8 @@ std::string pass_kernel_name(const PassDesc &pd, fftu_dtype dt)
     if (pd.kind == fftu::kGroup2)
         return "fftu::k_group2<" + t + ", " + std::to_string(pd.loglen[0]) + ", " + std::to_string(pd.loglen[1]) + ">";
     if (pd.kind == fftu::kPair)
-        return "fftu::k_pair<" + t + ", " + std::to_string(pd.loglen[0]) + ", " + std::to_string(pd.loglen[1]) + ">";
+        return "fftu::k_pair<" + t + ", " + std::to_string(pd.loglen[0]) + ", " + std::to_string(pd.loglen[1]) + ", " +
+               std::to_string(__builtin_ctz(unsigned(pd.threads))) + ">";
     if (pd.kind == fftu::kTilePass) return "fftu::k_pass<" + t + ">";
     return "fftu::k_line<" + t + ", " + std::to_string(pd.loglen[0]) + ", " + std::to_string(pd.kind) + ">";
 }

@@ -99,26 +99,25 @@ struct ExchangeDesc {
 };
 
 // k_pair (fftu_pair.hip): lines of 2^3..2^5 points along two adjacent dimensions,
-// one whole line per thread. 512 threads (complex64) or 256 (complex128); a tile
-// is W = threads / max(LA, LB) columns, W * esize = 128 bytes or more.
+// one whole line per thread. 2^lognt threads: 256 (complex128) or 512 (complex64),
+// or 1024 for complex64 lines of 32 whose rows lie 64 KiB or more apart (then the
+// tile's W = 32 columns halve the pages and DRAM rows opened per byte). A tile is
+// W = threads / max(LA, LB) columns, W * esize = 128 bytes or more.
 constexpr int kPairMinLogL = 3;
 constexpr int kPairMaxLogL = 5;
-constexpr int pair_lognt(int esize) { return esize == 16 ? 8 : 9; }
-constexpr int pair_logw(int logla, int loglb, int esize)
+constexpr int pair_lognt(int logla, int loglb, int logb, int esize)
 {
-    return pair_lognt(esize) - (logla > loglb ? logla : loglb);
+    return esize == 16 ? 8 : ((logla == 5 || loglb == 5) && logb + 3 >= 16 ? 10 : 9);
 }
+constexpr int pair_logw(int logla, int loglb, int lognt) { return lognt - (logla > loglb ? logla : loglb); }
 // words (one real part) per inner position of the LDS transpose: LA W plus W of
 // padding, so that the column reads of a wave fall in distinct banks
-constexpr int pair_pitch(int logla, int loglb, int esize)
+constexpr int pair_pitch(int logla, int loglb, int lognt) { return ((1 << logla) + 1) << pair_logw(logla, loglb, lognt); }
+constexpr uint32_t pair_lds_bytes(int logla, int loglb, int lognt, int esize)
 {
-    return ((1 << logla) + 1) << pair_logw(logla, loglb, esize);
+    return uint32_t((1 << loglb) * pair_pitch(logla, loglb, lognt) * (esize / 2));
 }
-constexpr uint32_t pair_lds_bytes(int logla, int loglb, int esize)
-{
-    return uint32_t((1 << loglb) * pair_pitch(logla, loglb, esize) * (esize / 2));
-}
-constexpr int64_t pair_max_tiles(int esize) { return int64_t(1) << (31 - pair_lognt(esize)); }
+constexpr int64_t pair_max_tiles(int lognt) { return int64_t(1) << (31 - lognt); }
 
 // k_lastx (fftu_lastx.hpp): the innermost dimension's Superstep-0 lines fused with
 // the exchange. A workgroup of 2^lognt threads holds RW rows of all P blocks; its
@@ -152,6 +151,13 @@ constexpr bool lastx_split_needs_1024(int logl, int nr, int lpr, int nh, int lph
 {
     return !lastx_split_ok(logl, nr, lpr, nh, lph, kLastxLogThreads) &&
            lastx_split_ok(logl, nr, lpr, nh, lph, kLastxMaxLogThreads);
+}
+
+// k_lastx reads its tile linearly and regroups it through LDS when one thread's run
+// of a line (TPL = L / E elements) is shorter than 128 bytes.
+constexpr bool lastx_staged_load(int logl, int esize)
+{
+    return (int64_t(1) << (logl - line_loge(logl))) * esize < 128;
 }
 
 // LDS bytes of k_lastx: omega_L table, then max(transpose, line stages) rows of 8-byte words.

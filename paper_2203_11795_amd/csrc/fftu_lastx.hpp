@@ -100,10 +100,49 @@ __global__ __launch_bounds__(1 << LOGNT, (MUL && LOGNT == 9) ? 2 : 4) void k_las
     {
         const int64_t tile = blockIdx.x;   // one tile per workgroup (the launcher checks the grid)
         cx<T> v[PL::E];
-        const int64_t base = (int64_t(s) << logM) + (((tile << S::LOGRW) + row) << LOGL);
+        if constexpr (lastx_staged_load(LOGL, sizeof(cx<T>))) {
+            // a thread's run of a line (TPL elements) is under 128 bytes: read the tile's
+            // RW L contiguous elements of each block linearly instead (64 consecutive
+            // elements per wave instruction) and hand each thread its line positions
+            // through LDS, as k_line's staged layout does
+            cx<T> r[PL::E];
 #pragma unroll
-        for (int m = 0; m < PL::E; ++m) v[m] = conj_if(get(&in[base + j + m * PL::TPL]), lx.conj_in);
-        __syncthreads();   // the omega_L table is in LDS
+            for (int c = 0; c < PL::E; ++c) {
+                const int e = tid + c * NT;
+                r[c] = conj_if(get(&in[(int64_t(e >> S::LOGK) << logM) + (tile << S::LOGK) + (e & ((1 << S::LOGK) - 1))]),
+                               lx.conj_in);
+            }
+            // element e is position e mod L of line e / L
+            auto at = [&](int e) { return lidx<kLineContig>(e & (S::L - 1), e >> LOGL, S::PITCH); };
+            auto mine = [&](int m) { return lidx<kLineContig>(j + m * PL::TPL, w, S::PITCH); };
+            if constexpr (sizeof(T) == 8) {
+                T *ld = reinterpret_cast<T *>(work);
+#pragma unroll
+                for (int c = 0; c < PL::E; ++c) ld[at(tid + c * NT)] = r[c].x;
+                __syncthreads();
+#pragma unroll
+                for (int m = 0; m < PL::E; ++m) v[m].x = ld[mine(m)];
+                __syncthreads();
+#pragma unroll
+                for (int c = 0; c < PL::E; ++c) ld[at(tid + c * NT)] = r[c].y;
+                __syncthreads();
+#pragma unroll
+                for (int m = 0; m < PL::E; ++m) v[m].y = ld[mine(m)];
+            } else {
+                cx<T> *ld = reinterpret_cast<cx<T> *>(work);
+#pragma unroll
+                for (int c = 0; c < PL::E; ++c) ld[at(tid + c * NT)] = r[c];
+                __syncthreads();
+#pragma unroll
+                for (int m = 0; m < PL::E; ++m) v[m] = ld[mine(m)];
+            }
+            __syncthreads();   // the gathers are done before line_stages reuses the area
+        } else {
+            const int64_t base = (int64_t(s) << logM) + (((tile << S::LOGRW) + row) << LOGL);
+#pragma unroll
+            for (int m = 0; m < PL::E; ++m) v[m] = conj_if(get(&in[base + j + m * PL::TPL]), lx.conj_in);
+            __syncthreads();   // the omega_L table is in LDS
+        }
 
         line_stages<T, LOGL, kLineContig>(v, j, w, S::PITCH, static_cast<void *>(work), tw, true);
 

@@ -6,7 +6,11 @@
 // The array is viewed as (A, LA, LB, B) row-major: lines of LA points along the
 // outer dimension of the pair (stride LB B) and of LB points along the inner one
 // (stride B). A workgroup of NT threads takes one tile: one outer index a and
-// W = NT / max(LA, LB) consecutive columns c of B, i.e. LA LB W elements.
+// W = NT / max(LA, LB) consecutive columns c of B, i.e. LA LB W elements. NT is
+// 256 for complex128 and 512 for complex64, or 1024 where a line of 32 has rows
+// 64 KiB or more apart: the tile's 1024 rows then span many pages, and twice
+// the columns per tile halve the pages and DRAM rows opened per byte (one
+// workgroup per CU then, so nearby rows keep 512 threads and two per CU).
 //   1. Thread (x, w), x < LA, loads the whole inner line (a, x, :, c0 + w) into
 //      registers (lanes run over w, so every load instruction covers runs of W
 //      consecutive elements) and transforms it with the in-register DFT, whose
@@ -24,16 +28,14 @@
 
 namespace fftu {
 
-template <typename T, int LOGLA, int LOGLB>
-__global__ __launch_bounds__(1 << pair_lognt(sizeof(T) * 2)) void k_pair(const cx<T> *in, cx<T> *out,
-                                                                         const PassDesc pd)
+template <typename T, int LOGLA, int LOGLB, int LOGNT>
+__global__ __launch_bounds__(1 << LOGNT) void k_pair(const cx<T> *in, cx<T> *out, const PassDesc pd)
 {
-    constexpr int LOGNT = pair_lognt(sizeof(T) * 2);
     constexpr int LA = 1 << LOGLA, LB = 1 << LOGLB;
     constexpr int LMAX = LA > LB ? LA : LB;
-    constexpr int LOGW = pair_logw(LOGLA, LOGLB, sizeof(T) * 2);
+    constexpr int LOGW = pair_logw(LOGLA, LOGLB, LOGNT);
     constexpr int W = 1 << LOGW;
-    constexpr int PITCH = pair_pitch(LOGLA, LOGLB, sizeof(T) * 2);   // words per inner position
+    constexpr int PITCH = pair_pitch(LOGLA, LOGLB, LOGNT);   // words per inner position
     static_assert(LMAX * W == (1 << LOGNT), "one line per thread in the larger phase");
     extern __shared__ unsigned char smem_raw[];
     T *lds = reinterpret_cast<T *>(smem_raw);
@@ -88,26 +90,40 @@ __global__ __launch_bounds__(1 << pair_lognt(sizeof(T) * 2)) void k_pair(const c
 
 namespace {
 
-template <typename T, int LOGLA, int LOGLB>
+template <typename T, int LOGLA, int LOGLB, int LOGNT>
 hipError_t launch_pair_t(const void *in, void *out, const PassDesc &pd, hipStream_t stream)
 {
     const int esize = int(sizeof(T) * 2);
-    if (pd.logW != pair_logw(LOGLA, LOGLB, esize) || pd.threads != (1 << pair_lognt(esize)) ||
-        pd.tiles < 1 || pd.tiles > pair_max_tiles(esize) || pd.logB < pd.logW || pd.logTPA != pd.logB - pd.logW ||
-        pd.GB != (int64_t(1) << (LOGLA + LOGLB + pd.logB)) || pd.lds_bytes != pair_lds_bytes(LOGLA, LOGLB, esize))
+    if (pd.logW != pair_logw(LOGLA, LOGLB, LOGNT) || pd.tiles < 1 || pd.tiles > pair_max_tiles(LOGNT) ||
+        pd.logB < pd.logW || pd.logTPA != pd.logB - pd.logW || pd.GB != (int64_t(1) << (LOGLA + LOGLB + pd.logB)) ||
+        pd.lds_bytes != pair_lds_bytes(LOGLA, LOGLB, LOGNT, esize))
         return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_pair<T, LOGLA, LOGLB>), dim3(uint32_t(pd.tiles)), dim3(uint32_t(pd.threads)), pd.lds_bytes,
-                       stream, static_cast<const cx<T> *>(in), static_cast<cx<T> *>(out), pd);
+    hipLaunchKernelGGL((k_pair<T, LOGLA, LOGLB, LOGNT>), dim3(uint32_t(pd.tiles)), dim3(uint32_t(pd.threads)),
+                       pd.lds_bytes, stream, static_cast<const cx<T> *>(in), static_cast<cx<T> *>(out), pd);
     return hipGetLastError();
+}
+
+// the thread count is the planner's (pair_lognt); only its instantiations exist
+template <typename T, int LOGLA, int LOGLB>
+hipError_t launch_pair_nt(const void *in, void *out, const PassDesc &pd, hipStream_t stream)
+{
+    if constexpr (sizeof(T) == 8) {
+        if (pd.threads == 256) return launch_pair_t<T, LOGLA, LOGLB, 8>(in, out, pd, stream);
+    } else {
+        if (pd.threads == 512) return launch_pair_t<T, LOGLA, LOGLB, 9>(in, out, pd, stream);
+        if constexpr (LOGLA == 5 || LOGLB == 5)
+            if (pd.threads == 1024) return launch_pair_t<T, LOGLA, LOGLB, 10>(in, out, pd, stream);
+    }
+    return hipErrorInvalidValue;
 }
 
 template <typename T, int LOGLA>
 hipError_t launch_pair_b(const void *in, void *out, const PassDesc &pd, hipStream_t stream)
 {
     switch (pd.loglen[1]) {
-    case 3: return launch_pair_t<T, LOGLA, 3>(in, out, pd, stream);
-    case 4: return launch_pair_t<T, LOGLA, 4>(in, out, pd, stream);
-    case 5: return launch_pair_t<T, LOGLA, 5>(in, out, pd, stream);
+    case 3: return launch_pair_nt<T, LOGLA, 3>(in, out, pd, stream);
+    case 4: return launch_pair_nt<T, LOGLA, 4>(in, out, pd, stream);
+    case 5: return launch_pair_nt<T, LOGLA, 5>(in, out, pd, stream);
     default: return hipErrorInvalidValue;
     }
 }

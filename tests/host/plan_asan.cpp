@@ -13,12 +13,15 @@ hipError_t launch_pass(Precision, const void *, void *, const PassDesc &pd, cons
 {
     if (pd.kind == kPair) {
         // a compiled pair of line lengths, whole tiles of columns inside B, LDS within the CU
-        const int esize = pd.threads == (1 << pair_lognt(16)) ? 16 : 8;
+        const int esize = pd.threads == 256 ? 16 : 8;
+        const int lognt = __builtin_ctz(unsigned(pd.threads));
         if (pd.naxes != 2 || pd.loglen[0] < kPairMinLogL || pd.loglen[0] > kPairMaxLogL ||
             pd.loglen[1] < kPairMinLogL || pd.loglen[1] > kPairMaxLogL) std::abort();
-        if (pd.logW != pair_logw(pd.loglen[0], pd.loglen[1], esize) || pd.logB < pd.logW ||
-            pd.logTPA != pd.logB - pd.logW || pd.tiles > pair_max_tiles(esize) ||
-            pd.lds_bytes != pair_lds_bytes(pd.loglen[0], pd.loglen[1], esize) || pd.lds_bytes > 80 * 1024)
+        if (lognt != pair_lognt(pd.loglen[0], pd.loglen[1], pd.logB, esize)) std::abort();
+        if (pd.logW != pair_logw(pd.loglen[0], pd.loglen[1], lognt) || pd.logB < pd.logW ||
+            pd.logTPA != pd.logB - pd.logW || pd.tiles > pair_max_tiles(lognt) ||
+            pd.lds_bytes != pair_lds_bytes(pd.loglen[0], pd.loglen[1], lognt, esize) ||
+            pd.lds_bytes > (lognt == 10 ? 160u : 80u) * 1024u)
             std::abort();
         return hipSuccess;
     }

@@ -24,6 +24,7 @@ pytestmark = pytest.mark.gpu
 TOL = {"complex128": 1e-12, "complex64": 5e-6}
 NP_DTYPE = {"complex128": np.complex128, "complex64": np.complex64}
 TNAME = {"complex128": "double", "complex64": "float"}
+NT = {"complex128": 8, "complex64": 9}       # log2 threads of k_pair where rows are near each other
 LENS = [8, 16, 32]
 
 
@@ -66,7 +67,7 @@ def test_local_fft_stage_with_pair(torch_dev, la, lb, dtype, direction):
             names = plan.launch_names()
             lla, llb = la.bit_length() - 1, lb.bit_length() - 1
             assert names[:2] == [f"fftu::k_group2<{TNAME[dtype]}, 3, 3>",
-                                 f"fftu::k_pair<{TNAME[dtype]}, {lla}, {llb}>"], names
+                                 f"fftu::k_pair<{TNAME[dtype]}, {lla}, {llb}, {NT[dtype]}>"], names
             got = run(torch_dev, plan, D, dtype, "local_fft")
     finally:
         fftu.set_tuning("fuse_last", -1)
@@ -85,7 +86,7 @@ def test_transform_pair_then_fused_last(torch_dev, la, lb, dtype, direction):
     with fftu.Plan(n, p, dtype, direction) as plan:
         names = plan.launch_names()
         lla, llb = la.bit_length() - 1, lb.bit_length() - 1
-        assert len(names) == 2 and names[0] == f"fftu::k_pair<{TNAME[dtype]}, {lla}, {llb}>", names
+        assert len(names) == 2 and names[0] == f"fftu::k_pair<{TNAME[dtype]}, {lla}, {llb}, {NT[dtype]}>", names
         assert names[1].startswith(f"fftu::k_lastx<{TNAME[dtype]}, 6,"), names
         got = run(torch_dev, plan, D, dtype)
         again = run(torch_dev, plan, D, dtype, inplace=True)
@@ -113,6 +114,26 @@ def test_whole_transforms_with_pairs(torch_dev, n, p, kernels, dtype):
         assert [s.split("<")[0] for s in names] == ["fftu::" + k for k in kernels], names
         Y = run(torch_dev, fwd, D, dtype)
         X = run(torch_dev, inv, Y, dtype)
+    assert oracle.rel_l2(Y, oracle.cyclic_dft(D, n, p)) <= TOL[dtype]
+    assert oracle.rel_l2(X, D) <= 2 * TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", ["complex128", "complex64"])
+@pytest.mark.parametrize("la,lb", [(32, 32), (8, 32), (32, 16)])
+def test_far_rows_take_the_wide_tile(torch_dev, la, lb, dtype):
+    """Rows 64 KiB apart (B = 8192 complex64 columns): complex64 pairs with a line
+    of 32 take 1024 threads and 32 columns per tile; complex128 keeps 256."""
+    import paper_2203_11795_amd as fftu
+    n, p = (la, lb, 64, 128), (1, 1, 1, 1)
+    say(f"far rows n={n} {dtype}")
+    D = synth.uniform_complex(int(np.prod(n)), 25, NP_DTYPE[dtype]).astype(np.complex128)
+    lla, llb = la.bit_length() - 1, lb.bit_length() - 1
+    nt = 10 if dtype == "complex64" else 8
+    with fftu.Plan(n, p, dtype, FORWARD) as fwd, fftu.Plan(n, p, dtype, INVERSE) as inv:
+        names = fwd.launch_names()
+        assert f"fftu::k_pair<{TNAME[dtype]}, {lla}, {llb}, {nt}>" in names, names
+        Y = run(torch_dev, fwd, D, dtype)
+        X = run(torch_dev, inv, Y, dtype, inplace=True)
     assert oracle.rel_l2(Y, oracle.cyclic_dft(D, n, p)) <= TOL[dtype]
     assert oracle.rel_l2(X, D) <= 2 * TOL[dtype]
 

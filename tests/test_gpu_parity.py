@@ -220,7 +220,8 @@ def test_launch_names(torch_dev):
         fftu.set_tuning("fuse_last", -1)
     with fftu.Plan((64,) * 5, (2,) * 5, "complex64", FORWARD) as plan:
         # dimensions (1, 2) and (3, 4) in k_pair passes, dimension 5 fused with the exchange
-        assert plan.launch_names() == ["fftu::k_pair<float, 5, 5>", "fftu::k_pair<float, 5, 5>",
+        # (rows 256 KiB apart in the first pair: 1024 threads; 256 bytes apart in the second: 512)
+        assert plan.launch_names() == ["fftu::k_pair<float, 5, 5, 10>", "fftu::k_pair<float, 5, 5, 9>",
                                        "fftu::k_lastx<float, 5, 3, 1, 2, 1, false, true, 9>"]
     fftu.set_tuning("fuse_last", 0)
     fftu.set_tuning("pair", 0)
