@@ -278,10 +278,40 @@ bool make_line_pass(int logA, int logL, int logB, fftu_dtype dt, int lognmax, Pa
 }
 
 // A pass over an array viewed as (A, group..., B).
+// k_long: lines of 2^11 / 2^12 points whose rows of B columns fit a tile of W whole
+// lines (B <= W), where k_line has no per-thread split.
+bool make_long_pass(int logA, int logL, int logB, fftu_dtype dt, int lognmax, PassDesc &pd)
+{
+    const int esize = dt == FFTU_C128 ? 16 : 8;
+    if (logL < fftu::kLongMinLogL || logL > fftu::kLongMaxLogL || (esize == 16 && logL != 11)) return false;
+    const int logW = fftu::long_logw(logL, esize);
+    if (logB > logW || logA + logB < logW) return false;
+    const int64_t tiles = int64_t(1) << (logA + logB - logW);
+    if (tiles > fftu::kLongMaxTiles) return false;
+    pd = PassDesc{};
+    pd.kind = fftu::kLong;
+    pd.threads = fftu::kLongThreads;
+    pd.naxes = 1;
+    pd.loglen[0] = logL;
+    pd.logG = logL;
+    pd.logB = logB;
+    pd.GB = int64_t(1) << (logL + logB);
+    pd.logW = logW;
+    pd.logBt = logB;
+    pd.logTPA = 0;
+    pd.lw = fftu::long_pitch(logL);
+    pd.tiles = tiles;
+    pd.lognmax = lognmax;
+    pd.scale = 1.0;
+    pd.lds_bytes = fftu::long_lds_bytes(logL, logW, esize);
+    return true;
+}
+
 PassDesc make_pass(int logA, const std::vector<int> &loglens, int logB, fftu_dtype dt, int lognmax)
 {
     PassDesc pd{};
     if (loglens.size() == 1 && make_line_pass(logA, loglens[0], logB, dt, lognmax, pd)) return pd;
+    if (loglens.size() == 1 && make_long_pass(logA, loglens[0], logB, dt, lognmax, pd)) return pd;
     pd.kind = fftu::kTilePass;
     pd.threads = fftu::kPassThreads;
     int logG = 0;
@@ -887,6 +917,8 @@ std::string pass_kernel_name(const PassDesc &pd, fftu_dtype dt)
     if (pd.kind == fftu::kPair)
         return "fftu::k_pair<" + t + ", " + std::to_string(pd.loglen[0]) + ", " + std::to_string(pd.loglen[1]) + ", " +
                std::to_string(__builtin_ctz(unsigned(pd.threads))) + ">";
+    if (pd.kind == fftu::kLong)
+        return "fftu::k_long<" + t + ", " + std::to_string(pd.loglen[0]) + ", " + std::to_string(pd.logW) + ">";
     if (pd.kind == fftu::kTilePass) return "fftu::k_pass<" + t + ">";
     return "fftu::k_line<" + t + ", " + std::to_string(pd.loglen[0]) + ", " + std::to_string(pd.kind) + ">";
 }

@@ -33,6 +33,7 @@ constexpr int kLineContig = 2;
 constexpr int kLineStaged = 3;
 constexpr int kGroup2 = 4;             // k_group2: two innermost dimensions of small contiguous planes
 constexpr int kPair = 5;               // k_pair: two adjacent strided dimensions of short lines (fftu_pair.hip)
+constexpr int kLong = 6;               // k_long: lines of 2^11 / 2^12 over short rows (fftu_long.hip)
 constexpr int kLineMaxThreads = 256;   // k_line workgroup bound (register budget per thread)
 
 // Radix split of k_line for a line of 2^logl: 1, 2 or 3 stages of 2^line_loge
@@ -118,6 +119,24 @@ constexpr uint32_t pair_lds_bytes(int logla, int loglb, int lognt, int esize)
     return uint32_t((1 << loglb) * pair_pitch(logla, loglb, lognt) * (esize / 2));
 }
 constexpr int64_t pair_max_tiles(int lognt) { return int64_t(1) << (31 - lognt); }
+
+// k_long (fftu_long.hip): 1024 threads hold W whole lines of L = 2^11 or 2^12 points
+// (W L contiguous elements: rows of B <= W columns), E = 2^long_loge elements per
+// thread: 32 complex64 (W = 8 for L = 4096, 16 for L = 2048) or 16 complex128
+// (W = 8, L = 2048). LDS: two twiddle tables of 64 and L / 64 entries, then W rows
+// of long_pitch words of one real part.
+constexpr int kLongLogThreads = 10;
+constexpr int kLongThreads = 1 << kLongLogThreads;
+constexpr int kLongMinLogL = 11;
+constexpr int kLongMaxLogL = 12;
+constexpr int64_t kLongMaxTiles = int64_t(1) << (31 - kLongLogThreads);
+constexpr int long_loge(int esize) { return esize == 16 ? 4 : 5; }
+constexpr int long_logw(int logl, int esize) { return kLongLogThreads - (logl - long_loge(esize)); }
+constexpr int long_pitch(int logl) { return (1 << logl) + (1 << (logl - 4)) + 8; }
+constexpr uint32_t long_lds_bytes(int logl, int logw, int esize)
+{
+    return uint32_t((64 + (1 << (logl - 6))) * esize + (1 << logw) * long_pitch(logl) * (esize / 2));
+}
 
 // k_lastx (fftu_lastx.hpp): the innermost dimension's Superstep-0 lines fused with
 // the exchange. A workgroup of 2^lognt threads holds RW rows of all P blocks; its
@@ -317,6 +336,8 @@ hipError_t launch_permute(Precision prec, const void *in, void *out, const GridD
 hipError_t launch_exchange(Precision prec, const void *in, void *out, const ExchangeDesc &ex, const void *table,
                            hipStream_t stream);
 hipError_t launch_pair(Precision prec, const void *in, void *out, const PassDesc &pd, hipStream_t stream);
+hipError_t launch_long(Precision prec, const void *in, void *out, const PassDesc &pd, const void *table,
+                       hipStream_t stream);
 hipError_t launch_lastx(Precision prec, const void *in, void *out, const LastxDesc &lx, const void *table,
                         hipStream_t stream);
 

@@ -231,6 +231,7 @@ hipError_t launch_pass(Precision prec, const void *in, void *out, const PassDesc
 {
     if (pd.kind == kGroup2) return launch_group2(prec, in, out, pd, table, stream);
     if (pd.kind == kPair) return launch_pair(prec, in, out, pd, stream);
+    if (pd.kind == kLong) return launch_long(prec, in, out, pd, table, stream);
     if (pd.kind != kTilePass) return launch_line(prec, in, out, pd, table, stream);
     return prec == Precision::F64 ? launch_pass_t<double>(in, out, pd, table, stream)
                                   : launch_pass_t<float>(in, out, pd, table, stream);

@@ -1,0 +1,225 @@
+// k_long: batched 1-D FFTs of long lines (2^11 or 2^12 points) along a dimension
+// whose rows are short (B <= W elements after it), for Superstep 0 (and the
+// unfused Superstep 2) of Algorithm 2.3 (arXiv 2203.11795) where no per-thread
+// split of k_line fits: a line of 4096 complex64 spans 32 KiB, so a tile of W
+// whole lines cannot sit in LDS at one complex per word.
+//
+// A workgroup of 1024 threads takes W L contiguous elements: W / B outer blocks
+// of L rows of B columns, i.e. W whole lines. It
+//   1. loads the tile linearly (64 consecutive elements per wave instruction);
+//   2. regroups it through LDS so that thread j of line w holds positions
+//      j + TPL m, m in [E] (E = L / TPL elements in registers);
+//   3. runs radix-16 stages (the last one may be smaller; Stockham autosort,
+//      in-register DFTs with exact roots), exchanging through LDS between stages;
+//   4. regroups through LDS once more and stores the tile linearly.
+// LDS holds one word per element (real parts, then imaginary parts), rows of
+// L + L/16 + 8 words per line: one pad word per 16 positions spreads the radix
+// scatters over the banks, and a row length of 8 mod 64 words spreads the
+// linear accesses (8 lines x 8 positions per wave). The stage twiddles
+// omega_L^e come from two small LDS tables, omega_L^(e mod 64) and
+// omega_L^(64 (e div 64)), multiplied: the full table of L entries would not fit
+// beside the tile.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "fftu_device.hpp"
+#include "fftu_internal.hpp"
+
+namespace fftu {
+
+// E = 2^LOGE elements per thread, stages of radix 2^LOGR (the last one smaller):
+// a thread runs E / R butterflies per stage
+template <int LOGL, int LOGE, int LOGR>
+struct LongPlan {
+    static constexpr int L = 1 << LOGL;
+    static constexpr int E = 1 << LOGE;
+    static constexpr int LOGTPL = LOGL - LOGE;
+    static constexpr int TPL = 1 << LOGTPL;
+    static constexpr int NS = (LOGL + LOGR - 1) / LOGR;
+    static constexpr int lr(int s) { return s < NS - 1 ? LOGR : LOGL - (NS - 1) * LOGR; }
+    static constexpr int lns(int s) { return s * LOGR; }
+};
+
+// LDS word of position x of tile line w
+template <int LOGL>
+__device__ __forceinline__ int long_word(int x, int w)
+{
+    return w * long_pitch(LOGL) + x + (x >> 4);
+}
+
+template <typename T, int LOGL>
+__device__ __forceinline__ cx<T> long_root(int e, const cx<T> *lo, const cx<T> *hi)
+{
+    return cmul(hi[e >> 6], lo[e & 63]);
+}
+
+// radix stage S on registers v (register m <-> position j + TPL m)
+template <typename T, typename PL, int LOGL, int S>
+__device__ __forceinline__ void long_compute(cx<T> (&v)[PL::E], int j, const cx<T> *lo, const cx<T> *hi)
+{
+    constexpr int LR = PL::lr(S), R = 1 << LR, LNS = PL::lns(S), NB = PL::E / R;
+#pragma unroll
+    for (int c = 0; c < NB; ++c) {
+        cx<T> x[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) x[r] = v[c + r * NB];
+        if constexpr (S > 0) {
+            const int jm = (j + c * PL::TPL) & ((1 << LNS) - 1);
+#pragma unroll
+            for (int r = 1; r < R; ++r) x[r] = cmul(x[r], long_root<T, LOGL>((r * jm) << (LOGL - LNS - LR), lo, hi));
+        }
+        Dft<T, R>::run(x);
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[c + r * NB] = x[r];
+    }
+}
+
+// stage S's outputs to their Stockham positions, one part (real or imaginary) per round
+template <typename T, typename PL, int LOGL, int S, typename GET>
+__device__ __forceinline__ void long_scatter(const cx<T> (&v)[PL::E], int j, int w, T *ld, GET part)
+{
+    constexpr int LR = PL::lr(S), R = 1 << LR, LNS = PL::lns(S), NB = PL::E / R;
+#pragma unroll
+    for (int c = 0; c < NB; ++c) {
+        const int jj = j + c * PL::TPL;
+        const int ob = ((jj >> LNS) << (LNS + LR)) + (jj & ((1 << LNS) - 1));
+#pragma unroll
+        for (int r = 0; r < R; ++r) ld[long_word<LOGL>(ob + (r << LNS), w)] = part(v[c + r * NB]);
+    }
+}
+
+template <typename T, typename PL, int LOGL, int S>
+__device__ __forceinline__ void long_exchange(cx<T> (&v)[PL::E], int j, int w, T *ld)
+{
+    long_scatter<T, PL, LOGL, S>(v, j, w, ld, [](const cx<T> &a) { return a.x; });
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < PL::E; ++m) v[m].x = ld[long_word<LOGL>(j + m * PL::TPL, w)];
+    __syncthreads();
+    long_scatter<T, PL, LOGL, S>(v, j, w, ld, [](const cx<T> &a) { return a.y; });
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < PL::E; ++m) v[m].y = ld[long_word<LOGL>(j + m * PL::TPL, w)];
+    __syncthreads();
+}
+
+template <typename T, int LOGL, int LOGW, int LOGB>
+__global__ __launch_bounds__(kLongThreads) void k_long(const cx<T> *in, cx<T> *out, const PassDesc pd,
+                                                       const cx<T> *__restrict__ table)
+{
+    constexpr int NT = kLongThreads;
+    constexpr int LOGTPL = kLongLogThreads - LOGW;
+    using PL = LongPlan<LOGL, LOGL - LOGTPL, 4>;   // radix-16 stages keep the DFT temporaries small
+    constexpr int E = PL::E, L = PL::L, TPL = PL::TPL;
+    static_assert(E * NT == (L << LOGW), "the tile is W whole lines");
+    extern __shared__ unsigned char smem_raw[];
+    cx<T> *lo = reinterpret_cast<cx<T> *>(smem_raw);   // omega_L^e, e in [64]
+    cx<T> *hi = lo + 64;                               // omega_L^(64 i), i in [L / 64]
+    T *ld = reinterpret_cast<T *>(hi + L / 64);        // the tile, one part at a time
+    const int tid = threadIdx.x;
+    for (int e = tid; e < 64 + L / 64; e += NT) {
+        const int ex = e < 64 ? e : (e - 64) << 6;
+        lo[e] = table[int64_t(ex) << (pd.lognmax - LOGL)];
+    }
+    const int j = tid & (TPL - 1), w = tid >> LOGTPL;
+    constexpr int lb = LOGB;   // compile-time, so that the staged LDS addresses fold into offsets
+    const int64_t tbase = int64_t(blockIdx.x) << (LOGW + LOGL);
+    // element e of the tile: outer block e / (L B), row x, column c; its line is (block, c)
+    auto at = [&](int e) {
+        const int x = (e >> lb) & (L - 1);
+        const int ln = ((e >> (lb + LOGL)) << lb) | (e & ((1 << lb) - 1));
+        return long_word<LOGL>(x, ln);
+    };
+
+    cx<T> r[E];
+#pragma unroll
+    for (int c = 0; c < E; ++c) r[c] = conj_if(get(&in[tbase + tid + c * NT]), pd.conj_in);
+    cx<T> v[E];
+#pragma unroll
+    for (int c = 0; c < E; ++c) ld[at(tid + c * NT)] = r[c].x;
+    __syncthreads();   // also: the twiddle tables are in LDS
+#pragma unroll
+    for (int m = 0; m < E; ++m) v[m].x = ld[long_word<LOGL>(j + m * TPL, w)];
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < E; ++c) ld[at(tid + c * NT)] = r[c].y;
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < E; ++m) v[m].y = ld[long_word<LOGL>(j + m * TPL, w)];
+    __syncthreads();
+
+    long_compute<T, PL, LOGL, 0>(v, j, lo, hi);
+    if constexpr (PL::NS > 1) {
+        long_exchange<T, PL, LOGL, 0>(v, j, w, ld);
+        long_compute<T, PL, LOGL, 1>(v, j, lo, hi);
+    }
+    if constexpr (PL::NS > 2) {
+        long_exchange<T, PL, LOGL, 1>(v, j, w, ld);
+        long_compute<T, PL, LOGL, 2>(v, j, lo, hi);
+    }
+    static_assert(PL::NS <= 3, "at most three radix stages");
+
+    // after the last stage register m holds position j + TPL m again
+    const T scale = static_cast<T>(pd.scale);
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        v[m] = conj_if(v[m], pd.conj_out);
+        if (pd.scale != 1.0) v[m] = {v[m].x * scale, v[m].y * scale};
+    }
+#pragma unroll
+    for (int m = 0; m < E; ++m) ld[long_word<LOGL>(j + m * TPL, w)] = v[m].x;
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < E; ++c) r[c].x = ld[at(tid + c * NT)];
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < E; ++m) ld[long_word<LOGL>(j + m * TPL, w)] = v[m].y;
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < E; ++c) {
+        r[c].y = ld[at(tid + c * NT)];
+        put<false>(&out[tbase + tid + c * NT], r[c]);
+    }
+}
+
+namespace {
+
+template <typename T, int LOGL, int LOGW, int LOGB>
+hipError_t launch_long_t(const void *in, void *out, const PassDesc &pd, const void *table, hipStream_t stream)
+{
+    if (pd.logW != LOGW || pd.logB != LOGB || pd.threads != kLongThreads || pd.tiles < 1 ||
+        pd.tiles > kLongMaxTiles || pd.lds_bytes != long_lds_bytes(LOGL, LOGW, int(sizeof(T) * 2)) ||
+        pd.lognmax < LOGL)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_long<T, LOGL, LOGW, LOGB>), dim3(uint32_t(pd.tiles)), dim3(kLongThreads), pd.lds_bytes,
+                       stream, static_cast<const cx<T> *>(in), static_cast<cx<T> *>(out), pd,
+                       static_cast<const cx<T> *>(table));
+    return hipGetLastError();
+}
+
+template <typename T, int LOGL, int LOGW, int LOGB = 0>
+hipError_t launch_long_b(const void *in, void *out, const PassDesc &pd, const void *table, hipStream_t stream)
+{
+    if (pd.logB == LOGB) return launch_long_t<T, LOGL, LOGW, LOGB>(in, out, pd, table, stream);
+    if constexpr (LOGB < LOGW) return launch_long_b<T, LOGL, LOGW, LOGB + 1>(in, out, pd, table, stream);
+    return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+hipError_t launch_long(Precision prec, const void *in, void *out, const PassDesc &pd, const void *table,
+                       hipStream_t stream)
+{
+    if (pd.kind != kLong || pd.naxes != 1) return hipErrorInvalidValue;
+    const int logL = pd.loglen[0];
+    if (prec == Precision::F64) {
+        if (logL == 11) return launch_long_b<double, 11, long_logw(11, 16)>(in, out, pd, table, stream);
+    } else {
+        if (logL == 12) return launch_long_b<float, 12, long_logw(12, 8)>(in, out, pd, table, stream);
+        if (logL == 11) return launch_long_b<float, 11, long_logw(11, 8)>(in, out, pd, table, stream);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace fftu

@@ -25,6 +25,16 @@ hipError_t launch_pass(Precision, const void *, void *, const PassDesc &pd, cons
             std::abort();
         return hipSuccess;
     }
+    if (pd.kind == kLong) {
+        // a compiled line length and tile, whole outer blocks per tile, LDS within the CU
+        const int esize = pd.lds_bytes == long_lds_bytes(pd.loglen[0], pd.logW, 16) ? 16 : 8;
+        if (pd.naxes != 1 || pd.loglen[0] < kLongMinLogL || pd.loglen[0] > kLongMaxLogL ||
+            pd.logW != long_logw(pd.loglen[0], esize) || pd.logB > pd.logW || pd.tiles > kLongMaxTiles ||
+            pd.lds_bytes != long_lds_bytes(pd.loglen[0], pd.logW, esize) || pd.lds_bytes > 160u * 1024u ||
+            pd.threads != kLongThreads)
+            std::abort();
+        return hipSuccess;
+    }
     // every tile of the pass must fit the LDS tile the kernel is compiled for
     if ((int64_t(1) << (pd.logG + pd.logW)) > (int64_t(1) << kLogTileF32)) std::abort();
     return hipSuccess;
