@@ -116,7 +116,8 @@ typedef struct {
     int32_t s0_kernels;       /* separate kernel launches of Superstep 0 (local FFTs) */
     int32_t exchange_fused;   /* 1: twiddle, permutation, length-p FFTs and scaling run as one kernel;
                                  2: so do the innermost dimension's local FFTs (s0_kernels excludes them) */
-    int32_t s2_kernels;       /* extra launches for Supersteps 1-2 when not fused (twiddle, permute, F_p passes) */
+    int32_t s2_kernels;       /* extra launches for Supersteps 1-2 when not fused: twiddle and permutation (one
+                                 tiled transpose where every q_l = 1), then the F_p passes */
     int32_t launches;         /* kernel launches of one fftu_execute */
     uint64_t workspace_bytes; /* device workspace owned by the plan */
     uint64_t table_bytes;     /* device twiddle table owned by the plan */

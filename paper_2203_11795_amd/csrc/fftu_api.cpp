@@ -50,6 +50,7 @@ struct fftu_plan_s {
     std::vector<PassDesc> s0;        // Superstep 0 local FFT passes
     std::vector<PassDesc> s2;        // Superstep 2 passes (unfused form)
     bool fused = false;
+    bool ttrans = false;             // unfused, every q_l = 1: twiddle and permutation as one k_ttranspose
     ExchangeDesc ex{};
     bool lastx = false;              // k_lastx: the innermost dimension's lines fused with the exchange
     std::vector<PassDesc> s0x;       // the other Superstep 0 passes, run before k_lastx
@@ -891,6 +892,16 @@ void fill_info_mixed(const MixedPlan &mp, fftu_dtype dt, fftu_plan_info *info)
     info->table_bytes = uint64_t(mp.T) * esize;
 }
 
+// The unfused exchange of a grid with every q_l = 1 (m = p, so M = P) is a transpose
+// of the P x M matrix of blocks: k_ttranspose applies the twiddle and moves 64 x 64
+// tiles in one pass, instead of k_twiddle and k_permute.
+bool transpose_exchange(const Geometry &G)
+{
+    for (int l = 0; l < G.d; ++l)
+        if (G.logq[l] != 0) return false;
+    return G.logM >= 6 && 2 * G.logM - 12 <= 31 - 8;
+}
+
 void fill_info(const Geometry &G, const std::vector<PassDesc> &s0, bool fused, size_t nS2, fftu_dtype dt,
                fftu_plan_info *info, bool lastx = false)
 {
@@ -901,7 +912,7 @@ void fill_info(const Geometry &G, const std::vector<PassDesc> &s0, bool fused, s
     info->M = int64_t(1) << G.logM;
     info->s0_kernels = int32_t(s0.size());
     info->exchange_fused = fused ? 1 : 0;
-    info->s2_kernels = fused ? 0 : int32_t(2 + nS2);
+    info->s2_kernels = fused ? 0 : int32_t((transpose_exchange(G) ? 1 : 2) + nS2);
     info->launches = info->s0_kernels + (fused ? 1 : info->s2_kernels);
     if (lastx) info->exchange_fused = 2;   // s0 holds the passes before k_lastx
     info->workspace_bytes = uint64_t(info->N) * esize;
@@ -1302,8 +1313,13 @@ fftu_plan_s *build_plan(int d, const int64_t n[], const int64_t p[], fftu_dtype 
             pl->launch_names.push_back(exchange_kernel_name(pl->ex, dtype));
         } else {
             const std::string t = dtype == FFTU_C128 ? "double" : "float";
-            pl->launch_names.push_back("fftu::k_twiddle<" + t + ">");
-            pl->launch_names.push_back("fftu::k_permute<" + t + ">");
+            pl->ttrans = transpose_exchange(G);
+            if (pl->ttrans) {
+                pl->launch_names.push_back("fftu::k_ttranspose<" + t + ">");
+            } else {
+                pl->launch_names.push_back("fftu::k_twiddle<" + t + ">");
+                pl->launch_names.push_back("fftu::k_permute<" + t + ">");
+            }
             for (const PassDesc &pd : pl->s2) pl->launch_names.push_back(pass_kernel_name(pd, dtype));
         }
     }
@@ -1962,10 +1978,16 @@ fftu_status execute_with(fftu_plan_s *plan, const void *in, void *out, void *ws,
     }
     GridDesc g = plan->grid;
     g.conj_in = conj_first;
-    hipError_t e = fftu::launch_twiddle(plan->prec, src, ws, g, plan->table, stream);
-    if (e == hipSuccess) {
-        mk.mark();
-        e = fftu::launch_permute(plan->prec, ws, out, plan->grid, stream);
+    hipError_t e;
+    if (plan->ttrans) {
+        // src is the workspace, or the input when it differs from out
+        e = fftu::launch_ttranspose(plan->prec, src, out, g, plan->table, stream);
+    } else {
+        e = fftu::launch_twiddle(plan->prec, src, ws, g, plan->table, stream);
+        if (e == hipSuccess) {
+            mk.mark();
+            e = fftu::launch_permute(plan->prec, ws, out, plan->grid, stream);
+        }
     }
     if (e != hipSuccess) return from_hip(e);
     mk.mark();

@@ -336,6 +336,10 @@ hipError_t launch_permute(Precision prec, const void *in, void *out, const GridD
 hipError_t launch_exchange(Precision prec, const void *in, void *out, const ExchangeDesc &ex, const void *table,
                            hipStream_t stream);
 hipError_t launch_pair(Precision prec, const void *in, void *out, const PassDesc &pd, hipStream_t stream);
+// Superstep 0's twiddle and Superstep 1 as one tiled transpose, for grids with every
+// q_l = 1 (m = p) and M >= 64; in and out must differ.
+hipError_t launch_ttranspose(Precision prec, const void *in, void *out, const GridDesc &g, const void *table,
+                             hipStream_t stream);
 hipError_t launch_long(Precision prec, const void *in, void *out, const PassDesc &pd, const void *table,
                        hipStream_t stream);
 hipError_t launch_lastx(Precision prec, const void *in, void *out, const LastxDesc &lx, const void *table,

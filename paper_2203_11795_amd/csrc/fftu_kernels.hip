@@ -202,6 +202,74 @@ __global__ __launch_bounds__(kPointwiseThreads) void k_permute(const cx<T> *__re
     }
 }
 
+// Superstep 0's twiddle and Superstep 1 together where every q_l = n_l / p_l^2 is 1.
+// Then m = p, M = P and t = 0, so W^(r)[s] = Z^(s)[r]: the exchange is the transpose
+// of the P x M matrix of blocks. A workgroup moves one 64 x 64 tile (processors
+// s0 + ds, local indices k0 + dk) through LDS, reading rows of 64 consecutive k and
+// writing rows of 64 consecutive s. The twiddle prod_l omega_{n_l}^{k_l s_l} is a
+// product of one factor per dimension; within a 64-aligned tile digit l of k is
+// k_l0 + dk_l with dk_l < 2^b_l (b_l of the low 6 index bits belong to dimension l,
+// the same for s since m = p), so each dimension needs only 2^(2 b_l) factors. The
+// workgroup reads those from the omega table into LDS first (k_l s_l < n_l, no
+// reduction), instead of one scattered table read per element.
+constexpr int kTransposeTile = 64;
+
+template <typename T>
+__global__ __launch_bounds__(kPointwiseThreads) void k_ttranspose(const cx<T> *__restrict__ in,
+                                                                  cx<T> *__restrict__ out, const GridDesc g,
+                                                                  const cx<T> *__restrict__ table)
+{
+    constexpr int TT = kTransposeTile;
+    extern __shared__ unsigned char smem_raw[];
+    cx<T> *tile = reinterpret_cast<cx<T> *>(smem_raw);   // [ds][dk], rows of TT + 1
+    cx<T> *fac = tile + TT * (TT + 1);                    // per-dimension factor tables
+    const int logM = g.logmstride[0] + g.logm[0];
+    const int64_t tk = int64_t(blockIdx.x) & ((int64_t(1) << (logM - 6)) - 1);
+    const int64_t ts = int64_t(blockIdx.x) >> (logM - 6);
+    const int64_t k0 = tk << 6, s0 = ts << 6;
+    const int tid = threadIdx.x;
+    // factor tables: dimension l holds omega_{n_l}^{(k_l0 + a)(s_l0 + b)} at off_l + a 2^b_l + b,
+    // b_l = the low 6 index bits that belong to dimension l, off_l = sum_{j<l} 4^b_j
+    auto lowbits = [&](int l) {
+        const int b = 6 - g.logmstride[l];
+        return b <= 0 ? 0 : (b < g.logm[l] ? b : g.logm[l]);
+    };
+    int total = 0;
+    for (int l = 0; l < g.d; ++l) total += 1 << (2 * lowbits(l));
+    for (int i = tid; i < total; i += kPointwiseThreads) {
+        int l = 0, off = 0;
+        while (i >= off + (1 << (2 * lowbits(l)))) {
+            off += 1 << (2 * lowbits(l));
+            ++l;
+        }
+        const int bl = lowbits(l);
+        const int a = (i - off) >> bl, b = (i - off) & ((1 << bl) - 1);
+        const uint32_t kl = uint32_t((k0 >> g.logmstride[l]) & ((int64_t(1) << g.logm[l]) - 1)) + uint32_t(a);
+        const uint32_t sl = uint32_t((s0 >> g.logpstride[l]) & ((int64_t(1) << g.logp[l]) - 1)) + uint32_t(b);
+        fac[i] = table[(kl * sl) << (g.lognmax - g.logn[l])];
+    }
+    __syncthreads();
+    const int dk = tid & (TT - 1);
+#pragma unroll 4
+    for (int ds = tid >> 6; ds < TT; ds += kPointwiseThreads / TT) {
+        cx<T> v = conj_if(get(&in[((s0 + ds) << logM) + k0 + dk]), g.conj_in);
+        int off = 0;
+        for (int l = 0; l < g.d; ++l) {
+            const int bl = lowbits(l);
+            const int a = (dk >> g.logmstride[l]) & ((1 << bl) - 1);
+            const int b = (ds >> g.logpstride[l]) & ((1 << bl) - 1);
+            v = cmul(v, fac[off + (a << bl) + b]);
+            off += 1 << (2 * bl);
+        }
+        tile[ds * (TT + 1) + dk] = v;
+    }
+    __syncthreads();
+    const int ds = tid & (TT - 1);
+#pragma unroll 4
+    for (int dk2 = tid >> 6; dk2 < TT; dk2 += kPointwiseThreads / TT)
+        put<false>(&out[((k0 + dk2) << logM) + s0 + ds], tile[ds * (TT + 1) + dk2]);
+}
+
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
@@ -261,6 +329,40 @@ hipError_t launch_permute(Precision prec, const void *in, void *out, const GridD
     else
         hipLaunchKernelGGL(k_permute<float>, dim3(blocks), dim3(kPointwiseThreads), 0, stream,
                            static_cast<const cx<float> *>(in), static_cast<cx<float> *>(out), g);
+    return hipGetLastError();
+}
+
+// bytes of LDS for k_ttranspose: the tile and the factor tables (at most 4^6 entries)
+uint32_t ttranspose_lds_bytes(const GridDesc &g, int esize)
+{
+    int total = 0;
+    for (int l = 0; l < g.d; ++l) {
+        const int b = 6 - g.logmstride[l];
+        const int bl = b <= 0 ? 0 : (b < g.logm[l] ? b : g.logm[l]);
+        total += 1 << (2 * bl);
+    }
+    return uint32_t((kTransposeTile * (kTransposeTile + 1) + total) * esize);
+}
+
+hipError_t launch_ttranspose(Precision prec, const void *in, void *out, const GridDesc &g, const void *table,
+                             hipStream_t stream)
+{
+    const int logM = g.logmstride[0] + g.logm[0];
+    for (int l = 0; l < g.d; ++l)
+        if (g.logm[l] != g.logp[l] || g.logmstride[l] != g.logpstride[l]) return hipErrorInvalidValue;
+    if (logM < 6 || g.N != (int64_t(1) << (2 * logM)) || in == out) return hipErrorInvalidValue;
+    const int64_t tiles = int64_t(1) << (2 * logM - 12);
+    if (tiles > (int64_t(1) << 31) / kPointwiseThreads) return hipErrorInvalidValue;
+    const int esize = prec == Precision::F64 ? 16 : 8;
+    const uint32_t lds = ttranspose_lds_bytes(g, esize);
+    if (prec == Precision::F64)
+        hipLaunchKernelGGL(k_ttranspose<double>, dim3(uint32_t(tiles)), dim3(kPointwiseThreads), lds, stream,
+                           static_cast<const cx<double> *>(in), static_cast<cx<double> *>(out), g,
+                           static_cast<const cx<double> *>(table));
+    else
+        hipLaunchKernelGGL(k_ttranspose<float>, dim3(uint32_t(tiles)), dim3(kPointwiseThreads), lds, stream,
+                           static_cast<const cx<float> *>(in), static_cast<cx<float> *>(out), g,
+                           static_cast<const cx<float> *>(table));
     return hipGetLastError();
 }
 

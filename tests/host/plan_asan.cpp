@@ -44,6 +44,15 @@ hipError_t launch_twiddle(Precision, const void *, void *, const GridDesc &, con
     return hipSuccess;
 }
 hipError_t launch_permute(Precision, const void *, void *, const GridDesc &, hipStream_t) { return hipSuccess; }
+hipError_t launch_ttranspose(Precision, const void *in, void *out, const GridDesc &g, const void *, hipStream_t)
+{
+    // every q_l = 1, a whole number of 64 x 64 tiles, distinct buffers
+    for (int l = 0; l < g.d; ++l)
+        if (g.logm[l] != g.logp[l]) std::abort();
+    const int logM = g.logmstride[0] + g.logm[0];
+    if (logM < 6 || g.N != (int64_t(1) << (2 * logM)) || in == out) std::abort();
+    return hipSuccess;
+}
 hipError_t launch_exchange(Precision, const void *, void *, const ExchangeDesc &ex, const void *, hipStream_t)
 {
     if (ex.nh * ex.lph > kExchangeMaxWaveBits || ex.nr * ex.lpr > kExchangeRegBitsF32) std::abort();
