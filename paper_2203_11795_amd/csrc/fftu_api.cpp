@@ -286,7 +286,7 @@ bool make_long_pass(int logA, int logL, int logB, fftu_dtype dt, int lognmax, Pa
     const int esize = dt == FFTU_C128 ? 16 : 8;
     if (logL < fftu::kLongMinLogL || logL > fftu::kLongMaxLogL || (esize == 16 && logL != 11)) return false;
     const int logW = fftu::long_logw(logL, esize);
-    if (logB > logW || logA + logB < logW) return false;
+    if (logB > logW + 1 || logA + logB < logW) return false;
     const int64_t tiles = int64_t(1) << (logA + logB - logW);
     if (tiles > fftu::kLongMaxTiles) return false;
     pd = PassDesc{};
@@ -300,11 +300,11 @@ bool make_long_pass(int logA, int logL, int logB, fftu_dtype dt, int lognmax, Pa
     pd.logW = logW;
     pd.logBt = logB;
     pd.logTPA = 0;
-    pd.lw = fftu::long_pitch(logL);
+    pd.lw = fftu::long_pitch(logL, esize);
     pd.tiles = tiles;
     pd.lognmax = lognmax;
     pd.scale = 1.0;
-    pd.lds_bytes = fftu::long_lds_bytes(logL, logW, esize);
+    pd.lds_bytes = fftu::long_lds_bytes(logL, esize);
     return true;
 }
 

@@ -120,22 +120,29 @@ constexpr uint32_t pair_lds_bytes(int logla, int loglb, int lognt, int esize)
 }
 constexpr int64_t pair_max_tiles(int lognt) { return int64_t(1) << (31 - lognt); }
 
-// k_long (fftu_long.hip): 1024 threads hold W whole lines of L = 2^11 or 2^12 points
-// (W L contiguous elements: rows of B <= W columns), E = 2^long_loge elements per
-// thread: 32 complex64 (W = 8 for L = 4096, 16 for L = 2048) or 16 complex128
-// (W = 8, L = 2048). LDS: two twiddle tables of 64 and L / 64 entries, then W rows
-// of long_pitch words of one real part.
+// k_long (fftu_long.hip): 1024 threads hold W whole lines of L = 2^11 or 2^12 points,
+// E elements per thread: 16 complex64 (W = 4 for L = 4096, 8 for L = 2048) or 8
+// complex128 (W = 4, L = 2048), within 128 VGPRs without spills. A tile is W / B
+// whole outer blocks when rows have B <= W columns, or W of the B columns of one
+// outer block when B = 2 W. LDS: two twiddle tables of 64 and L / 64 entries, then W
+// rows of long_pitch words of one real part.
 constexpr int kLongLogThreads = 10;
 constexpr int kLongThreads = 1 << kLongLogThreads;
 constexpr int kLongMinLogL = 11;
 constexpr int kLongMaxLogL = 12;
 constexpr int64_t kLongMaxTiles = int64_t(1) << (31 - kLongLogThreads);
-constexpr int long_loge(int esize) { return esize == 16 ? 4 : 5; }
+constexpr int long_loge(int esize) { return esize == 16 ? 3 : 4; }
 constexpr int long_logw(int logl, int esize) { return kLongLogThreads - (logl - long_loge(esize)); }
-constexpr int long_pitch(int logl) { return (1 << logl) + (1 << (logl - 4)) + 8; }
-constexpr uint32_t long_lds_bytes(int logl, int logw, int esize)
+// L + L/16 words per line, plus 64 / W so that a wave's linear accesses (W lines x
+// 64 / W positions) fall in distinct banks
+constexpr int long_pitch(int logl, int esize)
 {
-    return uint32_t((64 + (1 << (logl - 6))) * esize + (1 << logw) * long_pitch(logl) * (esize / 2));
+    return (1 << logl) + (1 << (logl - 4)) + (64 >> long_logw(logl, esize));
+}
+constexpr uint32_t long_lds_bytes(int logl, int esize)
+{
+    return uint32_t((64 + (1 << (logl - 6))) * esize +
+                    (1 << long_logw(logl, esize)) * long_pitch(logl, esize) * (esize / 2));
 }
 
 // k_lastx (fftu_lastx.hpp): the innermost dimension's Superstep-0 lines fused with

@@ -210,8 +210,12 @@ __global__ __launch_bounds__(kPointwiseThreads) void k_permute(const cx<T> *__re
 // product of one factor per dimension; within a 64-aligned tile digit l of k is
 // k_l0 + dk_l with dk_l < 2^b_l (b_l of the low 6 index bits belong to dimension l,
 // the same for s since m = p), so each dimension needs only 2^(2 b_l) factors. The
-// workgroup reads those from the omega table into LDS first (k_l s_l < n_l, no
-// reduction), instead of one scattered table read per element.
+// workgroup builds those in LDS (k_l s_l < n_l, no reduction) instead of reading the
+// table once per element. A factor omega_T^e is read as omega_T^(e - e mod 2^h)
+// omega_T^(e mod 2^h), h = ceil(log2(T) / 2): both reads fall in 2^h entries that
+// stay in cache, where the exponents k_l s_l of a large n_l would scatter over the
+// whole table (2^24 entries for the 2^24 x 64 shape). The tile's loads are issued
+// before the factors are built.
 constexpr int kTransposeTile = 64;
 
 template <typename T>
@@ -228,6 +232,14 @@ __global__ __launch_bounds__(kPointwiseThreads) void k_ttranspose(const cx<T> *_
     const int64_t ts = int64_t(blockIdx.x) >> (logM - 6);
     const int64_t k0 = tk << 6, s0 = ts << 6;
     const int tid = threadIdx.x;
+    const int dk = tid & (TT - 1);
+    constexpr int PER = TT * TT / kPointwiseThreads;   // elements per thread
+    cx<T> r[PER];
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int ds = (tid >> 6) + i * (kPointwiseThreads / TT);
+        r[i] = conj_if(get(&in[((s0 + ds) << logM) + k0 + dk]), g.conj_in);
+    }
     // factor tables: dimension l holds omega_{n_l}^{(k_l0 + a)(s_l0 + b)} at off_l + a 2^b_l + b,
     // b_l = the low 6 index bits that belong to dimension l, off_l = sum_{j<l} 4^b_j
     auto lowbits = [&](int l) {
@@ -246,13 +258,15 @@ __global__ __launch_bounds__(kPointwiseThreads) void k_ttranspose(const cx<T> *_
         const int a = (i - off) >> bl, b = (i - off) & ((1 << bl) - 1);
         const uint32_t kl = uint32_t((k0 >> g.logmstride[l]) & ((int64_t(1) << g.logm[l]) - 1)) + uint32_t(a);
         const uint32_t sl = uint32_t((s0 >> g.logpstride[l]) & ((int64_t(1) << g.logp[l]) - 1)) + uint32_t(b);
-        fac[i] = table[(kl * sl) << (g.lognmax - g.logn[l])];
+        const uint32_t e = (kl * sl) << (g.lognmax - g.logn[l]);
+        const int h = (g.lognmax + 1) >> 1;
+        fac[i] = cmul(table[e & ~((uint32_t(1) << h) - 1)], table[e & ((uint32_t(1) << h) - 1)]);
     }
     __syncthreads();
-    const int dk = tid & (TT - 1);
-#pragma unroll 4
-    for (int ds = tid >> 6; ds < TT; ds += kPointwiseThreads / TT) {
-        cx<T> v = conj_if(get(&in[((s0 + ds) << logM) + k0 + dk]), g.conj_in);
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int ds = (tid >> 6) + i * (kPointwiseThreads / TT);
+        cx<T> v = r[i];
         int off = 0;
         for (int l = 0; l < g.d; ++l) {
             const int bl = lowbits(l);

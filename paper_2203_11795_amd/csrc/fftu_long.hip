@@ -1,24 +1,27 @@
 // k_long: batched 1-D FFTs of long lines (2^11 or 2^12 points) along a dimension
-// whose rows are short (B <= W elements after it), for Superstep 0 (and the
-// unfused Superstep 2) of Algorithm 2.3 (arXiv 2203.11795) where no per-thread
-// split of k_line fits: a line of 4096 complex64 spans 32 KiB, so a tile of W
-// whole lines cannot sit in LDS at one complex per word.
+// whose rows are short (B elements after it), for Superstep 0 (and the unfused
+// Superstep 2) of Algorithm 2.3 (arXiv 2203.11795) where no per-thread split of
+// k_line fits: a line of 4096 complex64 spans 32 KiB.
 //
-// A workgroup of 1024 threads takes W L contiguous elements: W / B outer blocks
-// of L rows of B columns, i.e. W whole lines. It
-//   1. loads the tile linearly (64 consecutive elements per wave instruction);
+// A workgroup of 1024 threads takes W whole lines (E = 16 complex64 or 8 complex128
+// elements per thread):
+// W / B whole outer blocks of L rows of B columns when B <= W (one contiguous run),
+// or W of the B = 2W columns of one outer block. It
+//   1. loads the tile linearly (consecutive lanes on consecutive addresses);
 //   2. regroups it through LDS so that thread j of line w holds positions
-//      j + TPL m, m in [E] (E = L / TPL elements in registers);
-//   3. runs radix-16 stages (the last one may be smaller; Stockham autosort,
+//      j + TPL m, m in [E];
+//   3. runs radix-E stages (the last one may be smaller; Stockham autosort,
 //      in-register DFTs with exact roots), exchanging through LDS between stages;
 //   4. regroups through LDS once more and stores the tile linearly.
+// With B = 2W the two tiles of an outer block share every 128-byte line; they are
+// dispatched to the same XCD one after the other (workgroups go to the 8 XCDs
+// round-robin), so the second reads the lines from that XCD's L2.
 // LDS holds one word per element (real parts, then imaginary parts), rows of
-// L + L/16 + 8 words per line: one pad word per 16 positions spreads the radix
-// scatters over the banks, and a row length of 8 mod 64 words spreads the
-// linear accesses (8 lines x 8 positions per wave). The stage twiddles
-// omega_L^e come from two small LDS tables, omega_L^(e mod 64) and
-// omega_L^(64 (e div 64)), multiplied: the full table of L entries would not fit
-// beside the tile.
+// L + L/16 + 64/W words per line: one pad word per 16 positions spreads the radix
+// scatters over the banks, and the row length spreads the linear accesses. The
+// stage twiddles omega_L^e are products of two small LDS tables,
+// omega_L^(e mod 64) and omega_L^(64 (e div 64)): the full table of L entries would
+// not fit beside the tile.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -42,10 +45,10 @@ struct LongPlan {
 };
 
 // LDS word of position x of tile line w
-template <int LOGL>
+template <int LOGL, int ESIZE>
 __device__ __forceinline__ int long_word(int x, int w)
 {
-    return w * long_pitch(LOGL) + x + (x >> 4);
+    return w * long_pitch(LOGL, ESIZE) + x + (x >> 4);
 }
 
 template <typename T, int LOGL>
@@ -85,7 +88,7 @@ __device__ __forceinline__ void long_scatter(const cx<T> (&v)[PL::E], int j, int
         const int jj = j + c * PL::TPL;
         const int ob = ((jj >> LNS) << (LNS + LR)) + (jj & ((1 << LNS) - 1));
 #pragma unroll
-        for (int r = 0; r < R; ++r) ld[long_word<LOGL>(ob + (r << LNS), w)] = part(v[c + r * NB]);
+        for (int r = 0; r < R; ++r) ld[long_word<LOGL, int(sizeof(T) * 2)>(ob + (r << LNS), w)] = part(v[c + r * NB]);
     }
 }
 
@@ -95,22 +98,24 @@ __device__ __forceinline__ void long_exchange(cx<T> (&v)[PL::E], int j, int w, T
     long_scatter<T, PL, LOGL, S>(v, j, w, ld, [](const cx<T> &a) { return a.x; });
     __syncthreads();
 #pragma unroll
-    for (int m = 0; m < PL::E; ++m) v[m].x = ld[long_word<LOGL>(j + m * PL::TPL, w)];
+    for (int m = 0; m < PL::E; ++m) v[m].x = ld[long_word<LOGL, int(sizeof(T) * 2)>(j + m * PL::TPL, w)];
     __syncthreads();
     long_scatter<T, PL, LOGL, S>(v, j, w, ld, [](const cx<T> &a) { return a.y; });
     __syncthreads();
 #pragma unroll
-    for (int m = 0; m < PL::E; ++m) v[m].y = ld[long_word<LOGL>(j + m * PL::TPL, w)];
+    for (int m = 0; m < PL::E; ++m) v[m].y = ld[long_word<LOGL, int(sizeof(T) * 2)>(j + m * PL::TPL, w)];
     __syncthreads();
 }
 
-template <typename T, int LOGL, int LOGW, int LOGB>
+template <typename T, int LOGL, int LOGB>
 __global__ __launch_bounds__(kLongThreads) void k_long(const cx<T> *in, cx<T> *out, const PassDesc pd,
                                                        const cx<T> *__restrict__ table)
 {
     constexpr int NT = kLongThreads;
+    constexpr int LOGW = long_logw(LOGL, int(sizeof(T) * 2));
     constexpr int LOGTPL = kLongLogThreads - LOGW;
-    using PL = LongPlan<LOGL, LOGL - LOGTPL, 4>;   // radix-16 stages keep the DFT temporaries small
+    static_assert(LOGB <= LOGW + 1, "rows of at most 2 W columns");
+    using PL = LongPlan<LOGL, LOGL - LOGTPL, LOGL - LOGTPL>;
     constexpr int E = PL::E, L = PL::L, TPL = PL::TPL;
     static_assert(E * NT == (L << LOGW), "the tile is W whole lines");
     extern __shared__ unsigned char smem_raw[];
@@ -124,29 +129,46 @@ __global__ __launch_bounds__(kLongThreads) void k_long(const cx<T> *in, cx<T> *o
     }
     const int j = tid & (TPL - 1), w = tid >> LOGTPL;
     constexpr int lb = LOGB;   // compile-time, so that the staged LDS addresses fold into offsets
-    const int64_t tbase = int64_t(blockIdx.x) << (LOGW + LOGL);
-    // element e of the tile: outer block e / (L B), row x, column c; its line is (block, c)
+    // tile index: with B = 2W the two tiles of a block go to one XCD in a row
+    int64_t t = blockIdx.x;
+    if constexpr (LOGB > LOGW) {
+        const int64_t nb = gridDim.x;
+        if ((nb & 15) == 0) t = ((((t >> 3) >> 1) << 3 | (t & 7)) << 1) | ((t >> 3) & 1);
+    }
+    // element e of the tile -> (global offset, LDS word). B <= W: outer block e / (L B),
+    // row x, column c, line (block, c). B = 2W: row e / W, column (t mod 2) W + e mod W.
+    auto goff = [&](int e) -> int64_t {
+        if constexpr (LOGB <= LOGW) {
+            return (t << (LOGW + LOGL)) + e;
+        } else {
+            return ((t >> 1) << (LOGL + LOGB)) + (int64_t(e >> LOGW) << LOGB) + ((t & 1) << LOGW) + (e & ((1 << LOGW) - 1));
+        }
+    };
     auto at = [&](int e) {
-        const int x = (e >> lb) & (L - 1);
-        const int ln = ((e >> (lb + LOGL)) << lb) | (e & ((1 << lb) - 1));
-        return long_word<LOGL>(x, ln);
+        if constexpr (LOGB <= LOGW) {
+            const int x = (e >> lb) & (L - 1);
+            const int ln = ((e >> (lb + LOGL)) << lb) | (e & ((1 << lb) - 1));
+            return long_word<LOGL, int(sizeof(T) * 2)>(x, ln);
+        } else {
+            return long_word<LOGL, int(sizeof(T) * 2)>(e >> LOGW, e & ((1 << LOGW) - 1));
+        }
     };
 
     cx<T> r[E];
 #pragma unroll
-    for (int c = 0; c < E; ++c) r[c] = conj_if(get(&in[tbase + tid + c * NT]), pd.conj_in);
+    for (int c = 0; c < E; ++c) r[c] = conj_if(get(&in[goff(tid + c * NT)]), pd.conj_in);
     cx<T> v[E];
 #pragma unroll
     for (int c = 0; c < E; ++c) ld[at(tid + c * NT)] = r[c].x;
     __syncthreads();   // also: the twiddle tables are in LDS
 #pragma unroll
-    for (int m = 0; m < E; ++m) v[m].x = ld[long_word<LOGL>(j + m * TPL, w)];
+    for (int m = 0; m < E; ++m) v[m].x = ld[long_word<LOGL, int(sizeof(T) * 2)>(j + m * TPL, w)];
     __syncthreads();
 #pragma unroll
     for (int c = 0; c < E; ++c) ld[at(tid + c * NT)] = r[c].y;
     __syncthreads();
 #pragma unroll
-    for (int m = 0; m < E; ++m) v[m].y = ld[long_word<LOGL>(j + m * TPL, w)];
+    for (int m = 0; m < E; ++m) v[m].y = ld[long_word<LOGL, int(sizeof(T) * 2)>(j + m * TPL, w)];
     __syncthreads();
 
     long_compute<T, PL, LOGL, 0>(v, j, lo, hi);
@@ -158,7 +180,11 @@ __global__ __launch_bounds__(kLongThreads) void k_long(const cx<T> *in, cx<T> *o
         long_exchange<T, PL, LOGL, 1>(v, j, w, ld);
         long_compute<T, PL, LOGL, 2>(v, j, lo, hi);
     }
-    static_assert(PL::NS <= 3, "at most three radix stages");
+    if constexpr (PL::NS > 3) {
+        long_exchange<T, PL, LOGL, 2>(v, j, w, ld);
+        long_compute<T, PL, LOGL, 3>(v, j, lo, hi);
+    }
+    static_assert(PL::NS <= 4, "at most four radix stages");
 
     // after the last stage register m holds position j + TPL m again
     const T scale = static_cast<T>(pd.scale);
@@ -168,41 +194,41 @@ __global__ __launch_bounds__(kLongThreads) void k_long(const cx<T> *in, cx<T> *o
         if (pd.scale != 1.0) v[m] = {v[m].x * scale, v[m].y * scale};
     }
 #pragma unroll
-    for (int m = 0; m < E; ++m) ld[long_word<LOGL>(j + m * TPL, w)] = v[m].x;
+    for (int m = 0; m < E; ++m) ld[long_word<LOGL, int(sizeof(T) * 2)>(j + m * TPL, w)] = v[m].x;
     __syncthreads();
 #pragma unroll
     for (int c = 0; c < E; ++c) r[c].x = ld[at(tid + c * NT)];
     __syncthreads();
 #pragma unroll
-    for (int m = 0; m < E; ++m) ld[long_word<LOGL>(j + m * TPL, w)] = v[m].y;
+    for (int m = 0; m < E; ++m) ld[long_word<LOGL, int(sizeof(T) * 2)>(j + m * TPL, w)] = v[m].y;
     __syncthreads();
 #pragma unroll
     for (int c = 0; c < E; ++c) {
         r[c].y = ld[at(tid + c * NT)];
-        put<false>(&out[tbase + tid + c * NT], r[c]);
+        put<false>(&out[goff(tid + c * NT)], r[c]);
     }
 }
 
 namespace {
 
-template <typename T, int LOGL, int LOGW, int LOGB>
+template <typename T, int LOGL, int LOGB>
 hipError_t launch_long_t(const void *in, void *out, const PassDesc &pd, const void *table, hipStream_t stream)
 {
-    if (pd.logW != LOGW || pd.logB != LOGB || pd.threads != kLongThreads || pd.tiles < 1 ||
-        pd.tiles > kLongMaxTiles || pd.lds_bytes != long_lds_bytes(LOGL, LOGW, int(sizeof(T) * 2)) ||
-        pd.lognmax < LOGL)
+    if (pd.logW != long_logw(LOGL, int(sizeof(T) * 2)) || pd.logB != LOGB || pd.threads != kLongThreads || pd.tiles < 1 ||
+        pd.tiles > kLongMaxTiles || pd.lds_bytes != long_lds_bytes(LOGL, int(sizeof(T) * 2)) || pd.lognmax < LOGL)
         return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_long<T, LOGL, LOGW, LOGB>), dim3(uint32_t(pd.tiles)), dim3(kLongThreads), pd.lds_bytes,
-                       stream, static_cast<const cx<T> *>(in), static_cast<cx<T> *>(out), pd,
+    hipLaunchKernelGGL((k_long<T, LOGL, LOGB>), dim3(uint32_t(pd.tiles)), dim3(kLongThreads), pd.lds_bytes, stream,
+                       static_cast<const cx<T> *>(in), static_cast<cx<T> *>(out), pd,
                        static_cast<const cx<T> *>(table));
     return hipGetLastError();
 }
 
-template <typename T, int LOGL, int LOGW, int LOGB = 0>
+template <typename T, int LOGL, int LOGB = 0>
 hipError_t launch_long_b(const void *in, void *out, const PassDesc &pd, const void *table, hipStream_t stream)
 {
-    if (pd.logB == LOGB) return launch_long_t<T, LOGL, LOGW, LOGB>(in, out, pd, table, stream);
-    if constexpr (LOGB < LOGW) return launch_long_b<T, LOGL, LOGW, LOGB + 1>(in, out, pd, table, stream);
+    if (pd.logB == LOGB) return launch_long_t<T, LOGL, LOGB>(in, out, pd, table, stream);
+    if constexpr (LOGB <= long_logw(LOGL, int(sizeof(T) * 2)))
+        return launch_long_b<T, LOGL, LOGB + 1>(in, out, pd, table, stream);
     return hipErrorInvalidValue;
 }
 
@@ -214,10 +240,10 @@ hipError_t launch_long(Precision prec, const void *in, void *out, const PassDesc
     if (pd.kind != kLong || pd.naxes != 1) return hipErrorInvalidValue;
     const int logL = pd.loglen[0];
     if (prec == Precision::F64) {
-        if (logL == 11) return launch_long_b<double, 11, long_logw(11, 16)>(in, out, pd, table, stream);
+        if (logL == 11) return launch_long_b<double, 11>(in, out, pd, table, stream);
     } else {
-        if (logL == 12) return launch_long_b<float, 12, long_logw(12, 8)>(in, out, pd, table, stream);
-        if (logL == 11) return launch_long_b<float, 11, long_logw(11, 8)>(in, out, pd, table, stream);
+        if (logL == 12) return launch_long_b<float, 12>(in, out, pd, table, stream);
+        if (logL == 11) return launch_long_b<float, 11>(in, out, pd, table, stream);
     }
     return hipErrorInvalidValue;
 }

@@ -26,11 +26,11 @@ hipError_t launch_pass(Precision, const void *, void *, const PassDesc &pd, cons
         return hipSuccess;
     }
     if (pd.kind == kLong) {
-        // a compiled line length and tile, whole outer blocks per tile, LDS within the CU
-        const int esize = pd.lds_bytes == long_lds_bytes(pd.loglen[0], pd.logW, 16) ? 16 : 8;
+        // a compiled line length, rows of at most 2 W columns, LDS within the CU
+        const int esize = pd.lds_bytes == long_lds_bytes(pd.loglen[0], 16) ? 16 : 8;
         if (pd.naxes != 1 || pd.loglen[0] < kLongMinLogL || pd.loglen[0] > kLongMaxLogL ||
-            pd.logW != long_logw(pd.loglen[0], esize) || pd.logB > pd.logW || pd.tiles > kLongMaxTiles ||
-            pd.lds_bytes != long_lds_bytes(pd.loglen[0], pd.logW, esize) || pd.lds_bytes > 160u * 1024u ||
+            pd.logW != long_logw(pd.loglen[0], esize) || pd.logB > pd.logW + 1 || pd.tiles > kLongMaxTiles ||
+            pd.lds_bytes != long_lds_bytes(pd.loglen[0], esize) || pd.lds_bytes > 160u * 1024u ||
             pd.threads != kLongThreads)
             std::abort();
         return hipSuccess;

@@ -3,9 +3,9 @@ per-thread split of k_line fits.
 
 Checked against the FP64 oracle through the C ABI: the local-FFT stage alone
 (against the oracle's per-block local FFT) and whole transforms, forward and
-inverse, for every compiled line length and tile width, rows of B = 2..8 (one
-or several outer blocks per tile), and the unfused Superstep 2 of a grid with
-p_1 = 2048. Tolerances (relative L2): 1e-12 complex128, 5e-6 complex64.
+inverse, for every compiled line length, rows of B = 2..16 (several outer blocks
+per tile, one, or half of one with the two halves paired on an XCD), and the
+unfused Superstep 2 of a grid with p_1 = 2048. Tolerances (relative L2): 1e-12 complex128, 5e-6 complex64.
 """
 import sys
 
@@ -24,12 +24,15 @@ TNAME = {"complex128": "double", "complex64": "float"}
 
 # (n, p, dtype, the k_long launch expected: (log2 L, log2 W))
 CASES = [
-    ((8192, 16), (2, 2), "complex64", (12, 3)),      # lines of 4096, rows of 8: one block per tile
-    ((8192, 8), (2, 2), "complex64", (12, 3)),       # rows of 4: two blocks per tile
-    ((8192, 4), (2, 2), "complex64", (12, 3)),       # rows of 2: four blocks per tile
-    ((4096, 16), (2, 2), "complex64", (11, 4)),      # lines of 2048 over 16 lines per tile
-    ((4096, 16), (2, 2), "complex128", (11, 3)),
-    ((2048, 8), (1, 2), "complex128", (11, 3)),      # p_1 = 1, rows of 4
+    ((8192, 16), (2, 2), "complex64", (12, 2)),      # lines of 4096, rows of 8 = 2 W: half a row per tile
+    ((8, 8192, 16), (2, 2, 2), "complex64", (12, 2)),  # the same over 64 tiles: paired tiles on one XCD
+    ((8192, 8), (2, 2), "complex64", (12, 2)),       # rows of 4 = W: one block per tile
+    ((8192, 4), (2, 2), "complex64", (12, 2)),       # rows of 2: two blocks per tile
+    ((4096, 16), (2, 2), "complex64", (11, 3)),      # lines of 2048 over 8 lines per tile
+    ((4096, 32), (2, 2), "complex64", (11, 3)),      # rows of 16 = 2 W
+    ((4096, 16), (2, 2), "complex128", (11, 2)),     # rows of 8 = 2 W
+    ((8, 4096, 16), (2, 2, 2), "complex128", (11, 2)),
+    ((2048, 8), (1, 2), "complex128", (11, 2)),      # p_1 = 1, rows of 4 = W
 ]
 IDS = [f"{'x'.join(map(str, n))}-p{'x'.join(map(str, p))}-{dt}" for n, p, dt, _ in CASES]
 
@@ -86,7 +89,7 @@ def test_unfused_superstep2_with_long_lines(torch_dev):
     D = synth.uniform_complex(N, 32, np.complex64).astype(np.complex128)
     with fftu.Plan(n, p, "complex64", FORWARD) as plan:
         names = plan.launch_names()
-        assert names.count("fftu::k_long<float, 11, 4>") == 2, names
+        assert names.count("fftu::k_long<float, 11, 3>") == 2, names
         assert plan.info()["exchange_fused"] == 0
         got = run(torch_dev, plan, D, "complex64")
     assert oracle.rel_l2(got, oracle.cyclic_dft(D, n, p)) <= TOL["complex64"]
