@@ -232,6 +232,10 @@ int main()
         {{512, 512, 512}, {4, 4, 4}}, {{64, 64, 64}, {8, 8, 2}}, {{4, 4, 4, 4, 4, 4, 4, 4}, {2, 2, 2, 2, 2, 2, 2, 2}},
         {{1024, 1024, 1024}, {32, 32, 32}}, {{1}, {1}}, {{2048}, {1}}, {{4096}, {64}}, {{64, 64, 64, 64, 64}, {2, 2, 2, 2, 2}},
         {{16, 16}, {4, 4}}, {{8, 1, 4}, {2, 1, 1}}, {{1 << 22, 64}, {2048, 8}}, {{256, 256, 256, 256}, {16, 16, 16, 16}},
+        // k_pair, k_long and k_ttranspose plans
+        {{16, 16, 16, 32, 64}, {2, 2, 2, 2, 2}}, {{64, 64, 32, 64}, {2, 2, 2, 2}}, {{32, 32, 64, 128}, {1, 1, 1, 1}},
+        {{1 << 24, 64}, {4096, 8}}, {{8192, 16}, {2, 2}}, {{4096, 32}, {2, 2}}, {{8, 4096, 16}, {2, 2, 2}},
+        {{1024, 64}, {32, 8}}, {{64, 64, 64}, {8, 8, 8}},
         // mixed radix (factors 2, 3, 5, 7), and one side with a factor 11 (unsupported)
         {{60, 60}, {2, 2}}, {{49, 27, 8}, {7, 3, 2}}, {{1000}, {10}}, {{126, 12, 1}, {3, 2, 1}}, {{44, 12}, {2, 2}},
     };
