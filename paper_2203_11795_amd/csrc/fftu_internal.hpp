@@ -141,7 +141,8 @@ constexpr int long_pitch(int logl, int esize)
 }
 constexpr uint32_t long_lds_bytes(int logl, int esize)
 {
-    return uint32_t((1 << logl) * esize + (1 << long_logw(logl, esize)) * long_pitch(logl, esize) * (esize / 2));
+    return uint32_t((64 + (1 << (logl - 6))) * esize +
+                    (1 << long_logw(logl, esize)) * long_pitch(logl, esize) * (esize / 2));
 }
 
 // k_lastx (fftu_lastx.hpp): the innermost dimension's Superstep-0 lines fused with

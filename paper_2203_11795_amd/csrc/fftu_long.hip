@@ -16,10 +16,12 @@
 // With B = 2W the two tiles of an outer block share every 128-byte line; they are
 // dispatched to the same XCD one after the other (workgroups go to the 8 XCDs
 // round-robin), so the second reads the lines from that XCD's L2.
-// LDS holds the omega_L table and one word per element of the tile (real parts,
-// then imaginary parts), rows of L + L/16 + 64/W words per line: one pad word per
-// 16 positions spreads the radix scatters over the banks, and the row length
-// spreads the linear accesses.
+// LDS holds one word per element (real parts, then imaginary parts), rows of
+// L + L/16 + 64/W words per line: one pad word per 16 positions spreads the radix
+// scatters over the banks, and the row length spreads the linear accesses. The
+// stage twiddles omega_L^e are products of two small LDS tables,
+// omega_L^(e mod 64) and omega_L^(64 (e div 64)): the full table of L entries would
+// not fit beside the tile.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -49,11 +51,15 @@ __device__ __forceinline__ int long_word(int x, int w)
     return w * long_pitch(LOGL, ESIZE) + x + (x >> 4);
 }
 
-
+template <typename T, int LOGL>
+__device__ __forceinline__ cx<T> long_root(int e, const cx<T> *lo, const cx<T> *hi)
+{
+    return cmul(hi[e >> 6], lo[e & 63]);
+}
 
 // radix stage S on registers v (register m <-> position j + TPL m)
 template <typename T, typename PL, int LOGL, int S>
-__device__ __forceinline__ void long_compute(cx<T> (&v)[PL::E], int j, const cx<T> *tw)
+__device__ __forceinline__ void long_compute(cx<T> (&v)[PL::E], int j, const cx<T> *lo, const cx<T> *hi)
 {
     constexpr int LR = PL::lr(S), R = 1 << LR, LNS = PL::lns(S), NB = PL::E / R;
 #pragma unroll
@@ -64,7 +70,7 @@ __device__ __forceinline__ void long_compute(cx<T> (&v)[PL::E], int j, const cx<
         if constexpr (S > 0) {
             const int jm = (j + c * PL::TPL) & ((1 << LNS) - 1);
 #pragma unroll
-            for (int r = 1; r < R; ++r) x[r] = cmul(x[r], tw[(r * jm) << (LOGL - LNS - LR)]);
+            for (int r = 1; r < R; ++r) x[r] = cmul(x[r], long_root<T, LOGL>((r * jm) << (LOGL - LNS - LR), lo, hi));
         }
         Dft<T, R>::run(x);
 #pragma unroll
@@ -113,10 +119,14 @@ __global__ __launch_bounds__(kLongThreads) void k_long(const cx<T> *in, cx<T> *o
     constexpr int E = PL::E, L = PL::L, TPL = PL::TPL;
     static_assert(E * NT == (L << LOGW), "the tile is W whole lines");
     extern __shared__ unsigned char smem_raw[];
-    cx<T> *tw = reinterpret_cast<cx<T> *>(smem_raw);   // omega_L^e, e in [L]
-    T *ld = reinterpret_cast<T *>(tw + L);             // the tile, one part at a time
+    cx<T> *lo = reinterpret_cast<cx<T> *>(smem_raw);   // omega_L^e, e in [64]
+    cx<T> *hi = lo + 64;                               // omega_L^(64 i), i in [L / 64]
+    T *ld = reinterpret_cast<T *>(hi + L / 64);        // the tile, one part at a time
     const int tid = threadIdx.x;
-    for (int e = tid; e < L; e += NT) tw[e] = table[int64_t(e) << (pd.lognmax - LOGL)];
+    for (int e = tid; e < 64 + L / 64; e += NT) {
+        const int ex = e < 64 ? e : (e - 64) << 6;
+        lo[e] = table[int64_t(ex) << (pd.lognmax - LOGL)];
+    }
     const int j = tid & (TPL - 1), w = tid >> LOGTPL;
     constexpr int lb = LOGB;   // compile-time, so that the staged LDS addresses fold into offsets
     // tile index: with B = 2W the two tiles of a block go to one XCD in a row
@@ -161,18 +171,18 @@ __global__ __launch_bounds__(kLongThreads) void k_long(const cx<T> *in, cx<T> *o
     for (int m = 0; m < E; ++m) v[m].y = ld[long_word<LOGL, int(sizeof(T) * 2)>(j + m * TPL, w)];
     __syncthreads();
 
-    long_compute<T, PL, LOGL, 0>(v, j, tw);
+    long_compute<T, PL, LOGL, 0>(v, j, lo, hi);
     if constexpr (PL::NS > 1) {
         long_exchange<T, PL, LOGL, 0>(v, j, w, ld);
-        long_compute<T, PL, LOGL, 1>(v, j, tw);
+        long_compute<T, PL, LOGL, 1>(v, j, lo, hi);
     }
     if constexpr (PL::NS > 2) {
         long_exchange<T, PL, LOGL, 1>(v, j, w, ld);
-        long_compute<T, PL, LOGL, 2>(v, j, tw);
+        long_compute<T, PL, LOGL, 2>(v, j, lo, hi);
     }
     if constexpr (PL::NS > 3) {
         long_exchange<T, PL, LOGL, 2>(v, j, w, ld);
-        long_compute<T, PL, LOGL, 3>(v, j, tw);
+        long_compute<T, PL, LOGL, 3>(v, j, lo, hi);
     }
     static_assert(PL::NS <= 4, "at most four radix stages");
 
