@@ -51,6 +51,8 @@ struct fftu_plan_s {
     std::vector<PassDesc> s2;        // Superstep 2 passes (unfused form)
     bool fused = false;
     bool ttrans = false;             // unfused, every q_l = 1: twiddle and permutation as one k_ttranspose
+    int ttrans_ld = 0;               // > 0: k_ttranspose also runs the innermost dimension's FFTs of Supersteps 0, 2
+    std::vector<PassDesc> s0t, s2t;  // with ttrans_ld: Superstep 0 and 2 passes without the innermost dimension
     ExchangeDesc ex{};
     bool lastx = false;              // k_lastx: the innermost dimension's lines fused with the exchange
     std::vector<PassDesc> s0x;       // the other Superstep 0 passes, run before k_lastx
@@ -442,11 +444,12 @@ bool make_pair_pass(int logA, int logLA, int logLB, int logB, fftu_dtype dt, int
 // The two innermost dimensions share one k_group2 pass when their planes are
 // small; further dimensions share k_pair passes two by two where their lines
 // are short, and the rest get one pass each.
-std::vector<PassDesc> plan_s0(const Geometry &G, fftu_dtype dt)
+// skip_last: leave the innermost dimension out (k_ttranspose runs it).
+std::vector<PassDesc> plan_s0(const Geometry &G, fftu_dtype dt, bool skip_last = false)
 {
     std::vector<PassDesc> passes;
     std::vector<int> dims;   // dimensions with m_l > 1, innermost first
-    for (int l = G.d - 1; l >= 0; --l)
+    for (int l = G.d - 1 - (skip_last ? 1 : 0); l >= 0; --l)
         if (G.logm[l] > 0) dims.push_back(l);
     auto outer_of = [&](int l) {
         int logA = G.logP;
@@ -459,7 +462,7 @@ std::vector<PassDesc> plan_s0(const Geometry &G, fftu_dtype dt)
         return logB;
     };
     size_t first = 0;
-    if (dims.size() >= 2) {
+    if (dims.size() >= 2 && !skip_last) {
         PassDesc pd;
         const int li = dims[0], lo = dims[1];
         if (make_group2_pass(outer_of(lo), G.logm[lo], G.logm[li], dt, G.lognmax, pd)) {
@@ -483,10 +486,10 @@ std::vector<PassDesc> plan_s0(const Geometry &G, fftu_dtype dt)
 
 // Superstep 2 in unfused form: one pass per grid dimension with p_l > 1; inside a
 // destination block the local index splits as (s'_1, t_1, ..., s'_d, t_d).
-std::vector<PassDesc> plan_s2(const Geometry &G, fftu_dtype dt)
+std::vector<PassDesc> plan_s2(const Geometry &G, fftu_dtype dt, bool skip_last = false)
 {
     std::vector<PassDesc> passes;
-    for (int l = G.d - 1; l >= 0; --l) {
+    for (int l = G.d - 1 - (skip_last ? 1 : 0); l >= 0; --l) {
         if (G.logp[l] == 0) continue;
         int logA = G.logP, logB = G.logq[l];
         for (int j = 0; j < l; ++j) logA += G.logm[j];
@@ -902,6 +905,14 @@ bool transpose_exchange(const Geometry &G)
     return G.logM >= 6 && 2 * G.logM - 12 <= 31 - 8;
 }
 
+// log2 of the innermost side when k_ttranspose also takes its FFTs (2..32 points), else 0
+int transpose_fused_ld(const Geometry &G)
+{
+    if (!transpose_exchange(G)) return 0;
+    const int ld = G.logm[G.d - 1];
+    return ld >= 1 && ld <= 5 ? ld : 0;
+}
+
 void fill_info(const Geometry &G, const std::vector<PassDesc> &s0, bool fused, size_t nS2, fftu_dtype dt,
                fftu_plan_info *info, bool lastx = false)
 {
@@ -913,6 +924,11 @@ void fill_info(const Geometry &G, const std::vector<PassDesc> &s0, bool fused, s
     info->s0_kernels = int32_t(s0.size());
     info->exchange_fused = fused ? 1 : 0;
     info->s2_kernels = fused ? 0 : int32_t((transpose_exchange(G) ? 1 : 2) + nS2);
+    if (!fused && transpose_fused_ld(G) > 0) {
+        // k_ttranspose takes the innermost dimension's passes of Supersteps 0 and 2
+        info->s0_kernels = int32_t(plan_s0(G, dt, true).size());
+        info->s2_kernels = int32_t(1 + plan_s2(G, dt, true).size());
+    }
     info->launches = info->s0_kernels + (fused ? 1 : info->s2_kernels);
     if (lastx) info->exchange_fused = 2;   // s0 holds the passes before k_lastx
     info->workspace_bytes = uint64_t(info->N) * esize;
@@ -1308,19 +1324,26 @@ fftu_plan_s *build_plan(int d, const int64_t n[], const int64_t p[], fftu_dtype 
         fftu_plan_info info{};
         fill_info(G, pl->s0, pl->fused, pl->s2.size(), dtype, &info);
         pl->launches = info.launches;
-        for (const PassDesc &pd : pl->s0) pl->launch_names.push_back(pass_kernel_name(pd, dtype));
+        pl->ttrans = !pl->fused && transpose_exchange(G);
+        pl->ttrans_ld = pl->fused ? 0 : transpose_fused_ld(G);
+        if (pl->ttrans_ld > 0) {
+            pl->s0t = plan_s0(G, dtype, true);
+            pl->s2t = plan_s2(G, dtype, true);
+        }
+        for (const PassDesc &pd : (pl->ttrans_ld > 0 ? pl->s0t : pl->s0))
+            pl->launch_names.push_back(pass_kernel_name(pd, dtype));
         if (pl->fused) {
             pl->launch_names.push_back(exchange_kernel_name(pl->ex, dtype));
         } else {
             const std::string t = dtype == FFTU_C128 ? "double" : "float";
-            pl->ttrans = transpose_exchange(G);
             if (pl->ttrans) {
-                pl->launch_names.push_back("fftu::k_ttranspose<" + t + ">");
+                pl->launch_names.push_back("fftu::k_ttranspose<" + t + ", " + std::to_string(pl->ttrans_ld) + ">");
             } else {
                 pl->launch_names.push_back("fftu::k_twiddle<" + t + ">");
                 pl->launch_names.push_back("fftu::k_permute<" + t + ">");
             }
-            for (const PassDesc &pd : pl->s2) pl->launch_names.push_back(pass_kernel_name(pd, dtype));
+            for (const PassDesc &pd : (pl->ttrans_ld > 0 ? pl->s2t : pl->s2))
+                pl->launch_names.push_back(pass_kernel_name(pd, dtype));
         }
     }
     if (external) {
@@ -1955,17 +1978,20 @@ fftu_status execute_with(fftu_plan_s *plan, const void *in, void *out, void *ws,
         if (e == hipSuccess) mk.mark();
         return from_hip(e);
     }
-    if (!plan->s0.empty()) {
-        s = run_passes(plan, plan->s0, in, ws, inv, 0, 1.0, stream, &mk);
+    // with ttrans_ld, k_ttranspose runs the innermost dimension's passes of Supersteps 0 and 2
+    const std::vector<PassDesc> &s0 = plan->ttrans_ld > 0 ? plan->s0t : plan->s0;
+    const std::vector<PassDesc> &s2 = plan->ttrans_ld > 0 ? plan->s2t : plan->s2;
+    if (!s0.empty()) {
+        s = run_passes(plan, s0, in, ws, inv, 0, 1.0, stream, &mk);
         if (s != FFTU_SUCCESS) return s;
         src = ws;
     } else if (in == out) {
-        // N = 1: the exchange below must not read and write the same buffer.
+        // the exchange below must not read and write the same buffer
         hipError_t e = hipMemcpyAsync(ws, in, plan->grid.N * plan->esize, hipMemcpyDeviceToDevice, stream);
         if (e != hipSuccess) return from_hip(e);
         src = ws;
     }
-    const int conj_first = plan->s0.empty() ? inv : 0;
+    const int conj_first = s0.empty() ? inv : 0;
     if (plan->fused) {
         ExchangeDesc ex = plan->ex;
         ex.g.conj_in = conj_first;
@@ -1980,8 +2006,13 @@ fftu_status execute_with(fftu_plan_s *plan, const void *in, void *out, void *ws,
     g.conj_in = conj_first;
     hipError_t e;
     if (plan->ttrans) {
-        // src is the workspace, or the input when it differs from out
-        e = fftu::launch_ttranspose(plan->prec, src, out, g, plan->table, stream);
+        // src is the workspace, or the input when it differs from out; the last kernel
+        // when no Superstep-2 pass follows
+        if (s2.empty()) {
+            g.conj_out = inv;
+            g.scale = scale;
+        }
+        e = fftu::launch_ttranspose(plan->prec, src, out, g, plan->ttrans_ld, plan->table, stream);
     } else {
         e = fftu::launch_twiddle(plan->prec, src, ws, g, plan->table, stream);
         if (e == hipSuccess) {
@@ -1991,7 +2022,7 @@ fftu_status execute_with(fftu_plan_s *plan, const void *in, void *out, void *ws,
     }
     if (e != hipSuccess) return from_hip(e);
     mk.mark();
-    s = run_passes(plan, plan->s2, out, out, 0, inv, scale, stream, &mk);
+    s = run_passes(plan, s2, out, out, 0, inv, scale, stream, &mk);
     if (s != FFTU_SUCCESS || !mul) return s;
     return from_hip(fftu::launch_pointwise(plan->prec, out, mul, out, plan->grid.N, 1.0, stream));
 }

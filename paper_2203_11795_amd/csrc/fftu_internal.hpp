@@ -344,8 +344,10 @@ hipError_t launch_exchange(Precision prec, const void *in, void *out, const Exch
                            hipStream_t stream);
 hipError_t launch_pair(Precision prec, const void *in, void *out, const PassDesc &pd, hipStream_t stream);
 // Superstep 0's twiddle and Superstep 1 as one tiled transpose, for grids with every
-// q_l = 1 (m = p) and M >= 64; in and out must differ.
-hipError_t launch_ttranspose(Precision prec, const void *in, void *out, const GridDesc &g, const void *table,
+// q_l = 1 (m = p) and M >= 64; in and out must differ. ld > 0: also the innermost
+// dimension's length-2^ld FFTs of Superstep 0 (before the twiddle) and of Superstep 2
+// (after the transpose); g.conj_out and g.scale apply on the store.
+hipError_t launch_ttranspose(Precision prec, const void *in, void *out, const GridDesc &g, int ld, const void *table,
                              hipStream_t stream);
 hipError_t launch_long(Precision prec, const void *in, void *out, const PassDesc &pd, const void *table,
                        hipStream_t stream);

@@ -216,9 +216,43 @@ __global__ __launch_bounds__(kPointwiseThreads) void k_permute(const cx<T> *__re
 // stay in cache, where the exponents k_l s_l of a large n_l would scatter over the
 // whole table (2^24 entries for the 2^24 x 64 shape). The tile's loads are issued
 // before the factors are built.
+//
+// LD > 0: the innermost dimension has m_d = p_d = 2^LD <= 32 points, so the tile's
+// 64 consecutive local indices hold whole lines of it, and its 64 consecutive
+// processors whole groups of its p_d. The kernel then also runs Superstep 0's
+// length-m_d FFTs (on the rows, before the twiddle) and Superstep 2's length-p_d
+// FFTs (on the columns, after it) in registers with exact roots: the local FFT
+// factorises over dimensions (eq. (1.3)), as does Superstep 2's, so the other
+// dimensions' passes may come before and after. It may then be the last kernel:
+// the store conjugates and scales as the descriptor says.
 constexpr int kTransposeTile = 64;
 
-template <typename T>
+// length-2^LD DFTs along groups of 2^LD consecutive entries of the rows (ROWS) or
+// columns of the tile (rows of TT + 1)
+template <typename T, int LD, bool ROWS>
+__device__ __forceinline__ void tile_dfts(cx<T> *tile, int tid)
+{
+    constexpr int TT = kTransposeTile, R = 1 << LD;
+    constexpr int LINES = TT * TT / R;
+    for (int line = tid; line < LINES; line += kPointwiseThreads) {
+        int base, step;
+        if constexpr (ROWS) {
+            base = (line >> (6 - LD)) * (TT + 1) + ((line & ((TT >> LD) - 1)) << LD);
+            step = 1;
+        } else {
+            base = ((line >> 6) << LD) * (TT + 1) + (line & (TT - 1));
+            step = TT + 1;
+        }
+        cx<T> x[R];
+#pragma unroll
+        for (int i = 0; i < R; ++i) x[i] = tile[base + i * step];
+        Dft<T, R>::run(x);
+#pragma unroll
+        for (int i = 0; i < R; ++i) tile[base + i * step] = x[i];
+    }
+}
+
+template <typename T, int LD>
 __global__ __launch_bounds__(kPointwiseThreads) void k_ttranspose(const cx<T> *__restrict__ in,
                                                                   cx<T> *__restrict__ out, const GridDesc g,
                                                                   const cx<T> *__restrict__ table)
@@ -262,7 +296,18 @@ __global__ __launch_bounds__(kPointwiseThreads) void k_ttranspose(const cx<T> *_
         const int h = (g.lognmax + 1) >> 1;
         fac[i] = cmul(table[e & ~((uint32_t(1) << h) - 1)], table[e & ((uint32_t(1) << h) - 1)]);
     }
-    __syncthreads();
+    if constexpr (LD > 0) {
+        // Superstep 0 along the innermost dimension: rows, before the twiddle
+#pragma unroll
+        for (int i = 0; i < PER; ++i) tile[((tid >> 6) + i * (kPointwiseThreads / TT)) * (TT + 1) + dk] = r[i];
+        __syncthreads();
+        tile_dfts<T, LD, true>(tile, tid);
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < PER; ++i) r[i] = tile[((tid >> 6) + i * (kPointwiseThreads / TT)) * (TT + 1) + dk];
+    } else {
+        __syncthreads();
+    }
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
         const int ds = (tid >> 6) + i * (kPointwiseThreads / TT);
@@ -278,10 +323,19 @@ __global__ __launch_bounds__(kPointwiseThreads) void k_ttranspose(const cx<T> *_
         tile[ds * (TT + 1) + dk] = v;
     }
     __syncthreads();
+    if constexpr (LD > 0) {
+        // Superstep 2 along the innermost grid dimension: columns (consecutive s)
+        tile_dfts<T, LD, false>(tile, tid);
+        __syncthreads();
+    }
     const int ds = tid & (TT - 1);
+    const T scale = static_cast<T>(g.scale);
 #pragma unroll 4
-    for (int dk2 = tid >> 6; dk2 < TT; dk2 += kPointwiseThreads / TT)
-        put<false>(&out[((k0 + dk2) << logM) + s0 + ds], tile[ds * (TT + 1) + dk2]);
+    for (int dk2 = tid >> 6; dk2 < TT; dk2 += kPointwiseThreads / TT) {
+        cx<T> v = conj_if(tile[ds * (TT + 1) + dk2], g.conj_out);
+        if (g.scale != 1.0) v = {v.x * scale, v.y * scale};
+        put<false>(&out[((k0 + dk2) << logM) + s0 + ds], v);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -358,26 +412,46 @@ uint32_t ttranspose_lds_bytes(const GridDesc &g, int esize)
     return uint32_t((kTransposeTile * (kTransposeTile + 1) + total) * esize);
 }
 
-hipError_t launch_ttranspose(Precision prec, const void *in, void *out, const GridDesc &g, const void *table,
+namespace {
+template <typename T, int LD>
+void launch_ttranspose_t(const void *in, void *out, const GridDesc &g, const void *table, int64_t tiles, uint32_t lds,
+                         hipStream_t stream)
+{
+    hipLaunchKernelGGL((k_ttranspose<T, LD>), dim3(uint32_t(tiles)), dim3(kPointwiseThreads), lds, stream,
+                       static_cast<const cx<T> *>(in), static_cast<cx<T> *>(out), g, static_cast<const cx<T> *>(table));
+}
+
+template <typename T>
+hipError_t launch_ttranspose_ld(int ld, const void *in, void *out, const GridDesc &g, const void *table, int64_t tiles,
+                                uint32_t lds, hipStream_t stream)
+{
+    switch (ld) {
+    case 0: launch_ttranspose_t<T, 0>(in, out, g, table, tiles, lds, stream); break;
+    case 1: launch_ttranspose_t<T, 1>(in, out, g, table, tiles, lds, stream); break;
+    case 2: launch_ttranspose_t<T, 2>(in, out, g, table, tiles, lds, stream); break;
+    case 3: launch_ttranspose_t<T, 3>(in, out, g, table, tiles, lds, stream); break;
+    case 4: launch_ttranspose_t<T, 4>(in, out, g, table, tiles, lds, stream); break;
+    case 5: launch_ttranspose_t<T, 5>(in, out, g, table, tiles, lds, stream); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_ttranspose(Precision prec, const void *in, void *out, const GridDesc &g, int ld, const void *table,
                              hipStream_t stream)
 {
     const int logM = g.logmstride[0] + g.logm[0];
     for (int l = 0; l < g.d; ++l)
         if (g.logm[l] != g.logp[l] || g.logmstride[l] != g.logpstride[l]) return hipErrorInvalidValue;
     if (logM < 6 || g.N != (int64_t(1) << (2 * logM)) || in == out) return hipErrorInvalidValue;
+    if (ld != 0 && (ld > 5 || g.logm[g.d - 1] != ld)) return hipErrorInvalidValue;
     const int64_t tiles = int64_t(1) << (2 * logM - 12);
     if (tiles > (int64_t(1) << 31) / kPointwiseThreads) return hipErrorInvalidValue;
     const int esize = prec == Precision::F64 ? 16 : 8;
     const uint32_t lds = ttranspose_lds_bytes(g, esize);
-    if (prec == Precision::F64)
-        hipLaunchKernelGGL(k_ttranspose<double>, dim3(uint32_t(tiles)), dim3(kPointwiseThreads), lds, stream,
-                           static_cast<const cx<double> *>(in), static_cast<cx<double> *>(out), g,
-                           static_cast<const cx<double> *>(table));
-    else
-        hipLaunchKernelGGL(k_ttranspose<float>, dim3(uint32_t(tiles)), dim3(kPointwiseThreads), lds, stream,
-                           static_cast<const cx<float> *>(in), static_cast<cx<float> *>(out), g,
-                           static_cast<const cx<float> *>(table));
-    return hipGetLastError();
+    return prec == Precision::F64 ? launch_ttranspose_ld<double>(ld, in, out, g, table, tiles, lds, stream)
+                                  : launch_ttranspose_ld<float>(ld, in, out, g, table, tiles, lds, stream);
 }
 
 }  // namespace fftu

@@ -44,8 +44,9 @@ hipError_t launch_twiddle(Precision, const void *, void *, const GridDesc &, con
     return hipSuccess;
 }
 hipError_t launch_permute(Precision, const void *, void *, const GridDesc &, hipStream_t) { return hipSuccess; }
-hipError_t launch_ttranspose(Precision, const void *in, void *out, const GridDesc &g, const void *, hipStream_t)
+hipError_t launch_ttranspose(Precision, const void *in, void *out, const GridDesc &g, int ld, const void *, hipStream_t)
 {
+    if (ld < 0 || ld > 5 || (ld > 0 && g.logm[g.d - 1] != ld)) std::abort();
     // every q_l = 1, a whole number of 64 x 64 tiles, distinct buffers
     for (int l = 0; l < g.d; ++l)
         if (g.logm[l] != g.logp[l]) std::abort();

@@ -2,9 +2,12 @@
 grids with every q_l = n_l / p_l^2 equal to 1 (then m = p, M = P, and the
 all-to-all W^(r)[s] = Z^(s)[r] transposes the P x M matrix of blocks).
 
-Whole transforms through the C ABI against the FP64 oracle (eq. (1.2)), forward
-and inverse, in place and out of place, at sizes of one to 64 tiles of 64 x 64
-and with dimensions whose digits lie inside or outside a tile's low 6 index bits.
+Where the innermost side m_d = p_d is 2..32, the kernel also runs that
+dimension's FFTs of Superstep 0 (before the twiddle) and Superstep 2 (after the
+transpose). Whole transforms through the C ABI against the FP64 oracle (eq.
+(1.2)), forward and inverse, in place and out of place, at sizes of one to 64
+tiles of 64 x 64, with dimensions whose digits lie inside or outside a tile's
+low 6 index bits, with and without the fused FFTs.
 Tolerances (relative L2): 1e-12 complex128, 5e-6 complex64.
 """
 import sys
@@ -29,6 +32,7 @@ CASES = [
     ((64, 64, 64), (8, 8, 8)),           # 64 tiles, three dimensions
     ((4096, 64), (64, 8)),               # dimension 1 entirely above the low 6 bits
     ((4,) * 8, (2,) * 8),                # d = 8, one bit per dimension
+    ((64, 4096), (8, 64)),               # innermost side 64: the transpose without the fused FFTs
 ]
 IDS = [f"{'x'.join(map(str, n))}-p{'x'.join(map(str, p))}" for n, p in CASES]
 
@@ -65,7 +69,10 @@ def test_transpose_exchange_matches_oracle(torch_dev, n, p, dtype, direction):
     with fftu.Plan(n, p, dtype, direction) as plan:
         names = plan.launch_names()
         info = plan.info()
-        assert info["exchange_fused"] == 0 and f"fftu::k_ttranspose<{TNAME[dtype]}>" in names, names
+        ld = (n[-1] // p[-1]).bit_length() - 1          # m_d = p_d = 2^ld
+        fused = ld if ld <= 5 else 0                       # innermost FFTs inside the transpose
+        assert info["exchange_fused"] == 0 and f"fftu::k_ttranspose<{TNAME[dtype]}, {fused}>" in names, names
+        assert len(names) == info["launches"]
         assert "fftu::k_permute" not in " ".join(names)
         got = run(torch_dev, plan, D, dtype)
         again = run(torch_dev, plan, D, dtype, inplace=True)
