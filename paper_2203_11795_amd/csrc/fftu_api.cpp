@@ -945,7 +945,7 @@ std::string pass_kernel_name(const PassDesc &pd, fftu_dtype dt)
         return "fftu::k_pair<" + t + ", " + std::to_string(pd.loglen[0]) + ", " + std::to_string(pd.loglen[1]) + ", " +
                std::to_string(__builtin_ctz(unsigned(pd.threads))) + ">";
     if (pd.kind == fftu::kLong)
-        return "fftu::k_long<" + t + ", " + std::to_string(pd.loglen[0]) + ", " + std::to_string(pd.logW) + ">";
+        return "fftu::k_long<" + t + ", " + std::to_string(pd.loglen[0]) + ", " + std::to_string(pd.logB) + ">";
     if (pd.kind == fftu::kTilePass) return "fftu::k_pass<" + t + ">";
     return "fftu::k_line<" + t + ", " + std::to_string(pd.loglen[0]) + ", " + std::to_string(pd.kind) + ">";
 }

@@ -205,7 +205,13 @@ __global__ __launch_bounds__(kLongThreads) void k_long(const cx<T> *in, cx<T> *o
 #pragma unroll
     for (int c = 0; c < E; ++c) {
         r[c].y = ld[at(tid + c * NT)];
-        put<false>(&out[goff(tid + c * NT)], r[c]);
+        // two tiles share each line when B = 2W: plain stores let L2 merge their halves
+        // (non-temporal ones wrote 1.35 times the bytes to HBM)
+        if constexpr (LOGB > LOGW) {
+            out[goff(tid + c * NT)] = r[c];
+        } else {
+            put<false>(&out[goff(tid + c * NT)], r[c]);
+        }
     }
 }
 

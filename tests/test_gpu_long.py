@@ -22,16 +22,17 @@ TOL = {"complex128": 1e-12, "complex64": 5e-6}
 NP_DTYPE = {"complex128": np.complex128, "complex64": np.complex64}
 TNAME = {"complex128": "double", "complex64": "float"}
 
-# (n, p, dtype, the k_long launch expected: (log2 L, log2 W))
+# (n, p, dtype, the k_long launch expected: (log2 L, log2 B)); W = 4 lines per tile for
+# 4096-point complex64 and 2048-point complex128, 8 for 2048-point complex64
 CASES = [
-    ((8192, 16), (2, 2), "complex64", (12, 2)),      # lines of 4096, rows of 8 = 2 W: half a row per tile
-    ((8, 8192, 16), (2, 2, 2), "complex64", (12, 2)),  # the same over 64 tiles: paired tiles on one XCD
+    ((8192, 16), (2, 2), "complex64", (12, 3)),      # lines of 4096, rows of 8 = 2 W: half a row per tile
+    ((8, 8192, 16), (2, 2, 2), "complex64", (12, 3)),  # the same over 64 tiles: paired tiles on one XCD
     ((8192, 8), (2, 2), "complex64", (12, 2)),       # rows of 4 = W: one block per tile
-    ((8192, 4), (2, 2), "complex64", (12, 2)),       # rows of 2: two blocks per tile
-    ((4096, 16), (2, 2), "complex64", (11, 3)),      # lines of 2048 over 8 lines per tile
-    ((4096, 32), (2, 2), "complex64", (11, 3)),      # rows of 16 = 2 W
-    ((4096, 16), (2, 2), "complex128", (11, 2)),     # rows of 8 = 2 W
-    ((8, 4096, 16), (2, 2, 2), "complex128", (11, 2)),
+    ((8192, 4), (2, 2), "complex64", (12, 1)),       # rows of 2: two blocks per tile
+    ((4096, 16), (2, 2), "complex64", (11, 3)),      # lines of 2048, rows of 8 = W
+    ((4096, 32), (2, 2), "complex64", (11, 4)),      # rows of 16 = 2 W
+    ((4096, 16), (2, 2), "complex128", (11, 3)),     # rows of 8 = 2 W
+    ((8, 4096, 16), (2, 2, 2), "complex128", (11, 3)),
     ((2048, 8), (1, 2), "complex128", (11, 2)),      # p_1 = 1, rows of 4 = W
 ]
 IDS = [f"{'x'.join(map(str, n))}-p{'x'.join(map(str, p))}-{dt}" for n, p, dt, _ in CASES]
@@ -89,7 +90,7 @@ def test_unfused_superstep2_with_long_lines(torch_dev):
     D = synth.uniform_complex(N, 32, np.complex64).astype(np.complex128)
     with fftu.Plan(n, p, "complex64", FORWARD) as plan:
         names = plan.launch_names()
-        assert names.count("fftu::k_long<float, 11, 3>") == 2, names
+        assert names.count("fftu::k_long<float, 11, 2>") == 2, names
         assert plan.info()["exchange_fused"] == 0
         got = run(torch_dev, plan, D, "complex64")
     assert oracle.rel_l2(got, oracle.cyclic_dft(D, n, p)) <= TOL["complex64"]
