@@ -281,14 +281,14 @@ bool make_line_pass(int logA, int logL, int logB, fftu_dtype dt, int lognmax, Pa
 }
 
 // A pass over an array viewed as (A, group..., B).
-// k_long: lines of 2^11 / 2^12 points whose rows of B columns fit a tile of W whole
-// lines (B <= W), where k_line has no per-thread split.
+// k_long: lines of 2^11 / 2^12 points over rows of B <= 4W columns (W whole lines per
+// tile), where k_line has no per-thread split.
 bool make_long_pass(int logA, int logL, int logB, fftu_dtype dt, int lognmax, PassDesc &pd)
 {
     const int esize = dt == FFTU_C128 ? 16 : 8;
     if (logL < fftu::kLongMinLogL || logL > fftu::kLongMaxLogL || (esize == 16 && logL != 11)) return false;
     const int logW = fftu::long_logw(logL, esize);
-    if (logB > logW + 1 || logA + logB < logW) return false;
+    if (logB > logW + 2 || logA + logB < logW) return false;
     const int64_t tiles = int64_t(1) << (logA + logB - logW);
     if (tiles > fftu::kLongMaxTiles) return false;
     pd = PassDesc{};

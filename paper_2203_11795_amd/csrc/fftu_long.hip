@@ -3,19 +3,21 @@
 // Superstep 2) of Algorithm 2.3 (arXiv 2203.11795) where no per-thread split of
 // k_line fits: a line of 4096 complex64 spans 32 KiB.
 //
-// A workgroup of 1024 threads takes W whole lines (E = 16 complex64 or 8 complex128
-// elements per thread):
-// W / B whole outer blocks of L rows of B columns when B <= W (one contiguous run),
-// or W of the B = 2W columns of one outer block. It
+// A workgroup of 512 threads takes W whole lines (E = 16 complex64 or 8 complex128
+// elements per thread, within 128 VGPRs, so two workgroups share a CU and one loads
+// or stores while the other computes): W / B whole outer blocks of L rows of B
+// columns when B <= W (one contiguous run), or W of the G W columns (G = 2, 4) of one
+// outer block. It
 //   1. loads the tile linearly (consecutive lanes on consecutive addresses);
 //   2. regroups it through LDS so that thread j of line w holds positions
 //      j + TPL m, m in [E];
 //   3. runs radix-E stages (the last one may be smaller; Stockham autosort,
 //      in-register DFTs with exact roots), exchanging through LDS between stages;
 //   4. regroups through LDS once more and stores the tile linearly.
-// With B = 2W the two tiles of an outer block share every 128-byte line; they are
-// dispatched to the same XCD one after the other (workgroups go to the 8 XCDs
-// round-robin), so the second reads the lines from that XCD's L2.
+// With G tiles per outer block they share every 128-byte line: they run on the same
+// XCD at the same time (workgroups go to the 8 XCDs round-robin), so all but the
+// first read the lines from that XCD's L2, and they store with plain stores so that
+// L2 merges the pieces of each line.
 // LDS holds one word per element (real parts, then imaginary parts), rows of
 // L + L/16 + 64/W words per line: one pad word per 16 positions spreads the radix
 // scatters over the banks, and the row length spreads the linear accesses. The
@@ -114,7 +116,7 @@ __global__ __launch_bounds__(kLongThreads) void k_long(const cx<T> *in, cx<T> *o
     constexpr int NT = kLongThreads;
     constexpr int LOGW = long_logw(LOGL, int(sizeof(T) * 2));
     constexpr int LOGTPL = kLongLogThreads - LOGW;
-    static_assert(LOGB <= LOGW + 1, "rows of at most 2 W columns");
+    static_assert(LOGB <= LOGW + 2, "rows of at most 4 W columns");
     using PL = LongPlan<LOGL, LOGL - LOGTPL, LOGL - LOGTPL>;
     constexpr int E = PL::E, L = PL::L, TPL = PL::TPL;
     static_assert(E * NT == (L << LOGW), "the tile is W whole lines");
@@ -129,19 +131,24 @@ __global__ __launch_bounds__(kLongThreads) void k_long(const cx<T> *in, cx<T> *o
     }
     const int j = tid & (TPL - 1), w = tid >> LOGTPL;
     constexpr int lb = LOGB;   // compile-time, so that the staged LDS addresses fold into offsets
-    // tile index: with B = 2W the two tiles of a block go to one XCD in a row
+    // tile index: with B = G W (G = 2 or 4) the G tiles of a block are workgroups
+    // v, v + 8, ..., which run on one XCD at the same time (a bijection on each
+    // aligned run of 8 G)
+    constexpr int LOGG = LOGB > LOGW ? LOGB - LOGW : 0;
     int64_t t = blockIdx.x;
     if constexpr (LOGB > LOGW) {
         const int64_t nb = gridDim.x;
-        if ((nb & 15) == 0) t = ((((t >> 3) >> 1) << 3 | (t & 7)) << 1) | ((t >> 3) & 1);
+        if ((nb & ((8 << LOGG) - 1)) == 0)
+            t = ((((t >> 3) >> LOGG) << 3 | (t & 7)) << LOGG) | ((t >> 3) & ((1 << LOGG) - 1));
     }
     // element e of the tile -> (global offset, LDS word). B <= W: outer block e / (L B),
-    // row x, column c, line (block, c). B = 2W: row e / W, column (t mod 2) W + e mod W.
+    // row x, column c, line (block, c). B = G W: row e / W, column (t mod G) W + e mod W
+    // of block t / G.
     auto goff = [&](int e) -> int64_t {
         if constexpr (LOGB <= LOGW) {
             return (t << (LOGW + LOGL)) + e;
         } else {
-            return ((t >> 1) << (LOGL + LOGB)) + (int64_t(e >> LOGW) << LOGB) + ((t & 1) << LOGW) + (e & ((1 << LOGW) - 1));
+            return ((t >> LOGG) << (LOGL + LOGB)) + (int64_t(e >> LOGW) << LOGB) + ((t & ((1 << LOGG) - 1)) << LOGW) + (e & ((1 << LOGW) - 1));
         }
     };
     auto at = [&](int e) {
@@ -205,8 +212,8 @@ __global__ __launch_bounds__(kLongThreads) void k_long(const cx<T> *in, cx<T> *o
 #pragma unroll
     for (int c = 0; c < E; ++c) {
         r[c].y = ld[at(tid + c * NT)];
-        // two tiles share each line when B = 2W: plain stores let L2 merge their halves
-        // (non-temporal ones wrote 1.35 times the bytes to HBM)
+        // G tiles share each line when B = G W: plain stores let L2 merge the pieces
+        // (non-temporal ones wrote 1.35 times the bytes to HBM with G = 2)
         if constexpr (LOGB > LOGW) {
             out[goff(tid + c * NT)] = r[c];
         } else {
@@ -233,7 +240,7 @@ template <typename T, int LOGL, int LOGB = 0>
 hipError_t launch_long_b(const void *in, void *out, const PassDesc &pd, const void *table, hipStream_t stream)
 {
     if (pd.logB == LOGB) return launch_long_t<T, LOGL, LOGB>(in, out, pd, table, stream);
-    if constexpr (LOGB <= long_logw(LOGL, int(sizeof(T) * 2)))
+    if constexpr (LOGB <= long_logw(LOGL, int(sizeof(T) * 2)) + 1)
         return launch_long_b<T, LOGL, LOGB + 1>(in, out, pd, table, stream);
     return hipErrorInvalidValue;
 }

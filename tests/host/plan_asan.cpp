@@ -26,10 +26,10 @@ hipError_t launch_pass(Precision, const void *, void *, const PassDesc &pd, cons
         return hipSuccess;
     }
     if (pd.kind == kLong) {
-        // a compiled line length, rows of at most 2 W columns, LDS within the CU
+        // a compiled line length, rows of at most 4 W columns, LDS within the CU
         const int esize = pd.lds_bytes == long_lds_bytes(pd.loglen[0], 16) ? 16 : 8;
         if (pd.naxes != 1 || pd.loglen[0] < kLongMinLogL || pd.loglen[0] > kLongMaxLogL ||
-            pd.logW != long_logw(pd.loglen[0], esize) || pd.logB > pd.logW + 1 || pd.tiles > kLongMaxTiles ||
+            pd.logW != long_logw(pd.loglen[0], esize) || pd.logB > pd.logW + 2 || pd.tiles > kLongMaxTiles ||
             pd.lds_bytes != long_lds_bytes(pd.loglen[0], esize) || pd.lds_bytes > 160u * 1024u ||
             pd.threads != kLongThreads)
             std::abort();

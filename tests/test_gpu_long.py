@@ -3,9 +3,9 @@ per-thread split of k_line fits.
 
 Checked against the FP64 oracle through the C ABI: the local-FFT stage alone
 (against the oracle's per-block local FFT) and whole transforms, forward and
-inverse, for every compiled line length, rows of B = 2..16 (several outer blocks
-per tile, one, or half of one with the two halves paired on an XCD), and the
-unfused Superstep 2 of a grid with p_1 = 2048. Tolerances (relative L2): 1e-12 complex128, 5e-6 complex64.
+inverse, for every compiled line length, rows of B = 1..16 (several outer blocks
+per tile, one, or a half or quarter of one with the pieces grouped on an XCD),
+and the unfused Superstep 2 of a grid with p_1 = 2048. Tolerances (relative L2): 1e-12 complex128, 5e-6 complex64.
 """
 import sys
 
@@ -22,18 +22,20 @@ TOL = {"complex128": 1e-12, "complex64": 5e-6}
 NP_DTYPE = {"complex128": np.complex128, "complex64": np.complex64}
 TNAME = {"complex128": "double", "complex64": "float"}
 
-# (n, p, dtype, the k_long launch expected: (log2 L, log2 B)); W = 4 lines per tile for
-# 4096-point complex64 and 2048-point complex128, 8 for 2048-point complex64
+# (n, p, dtype, the k_long launch expected: (log2 L, log2 B)); W = 2 lines per tile for
+# 4096-point complex64 and 2048-point complex128, 4 for 2048-point complex64
 CASES = [
-    ((8192, 16), (2, 2), "complex64", (12, 3)),      # lines of 4096, rows of 8 = 2 W: half a row per tile
-    ((8, 8192, 16), (2, 2, 2), "complex64", (12, 3)),  # the same over 64 tiles: paired tiles on one XCD
-    ((8192, 8), (2, 2), "complex64", (12, 2)),       # rows of 4 = W: one block per tile
-    ((8192, 4), (2, 2), "complex64", (12, 1)),       # rows of 2: two blocks per tile
-    ((4096, 16), (2, 2), "complex64", (11, 3)),      # lines of 2048, rows of 8 = W
-    ((4096, 32), (2, 2), "complex64", (11, 4)),      # rows of 16 = 2 W
-    ((4096, 16), (2, 2), "complex128", (11, 3)),     # rows of 8 = 2 W
+    ((8192, 16), (2, 2), "complex64", (12, 3)),      # lines of 4096, rows of 8 = 4 W: a quarter row per tile
+    ((8, 8192, 16), (2, 2, 2), "complex64", (12, 3)),  # the same over 128 tiles, grouped by four on an XCD
+    ((8192, 8), (2, 2), "complex64", (12, 2)),       # rows of 4 = 2 W
+    ((8192, 4), (2, 2), "complex64", (12, 1)),       # rows of 2 = W: one block per tile
+    ((4096, 16), (2, 2), "complex64", (11, 3)),      # lines of 2048, rows of 8 = 2 W
+    ((4096, 32), (2, 2), "complex64", (11, 4)),      # rows of 16 = 4 W
+    ((4096, 4), (2, 2), "complex64", (11, 1)),       # rows of 2 < W: two blocks per tile
+    ((4096, 16), (2, 2), "complex128", (11, 3)),     # rows of 8 = 4 W
     ((8, 4096, 16), (2, 2, 2), "complex128", (11, 3)),
-    ((2048, 8), (1, 2), "complex128", (11, 2)),      # p_1 = 1, rows of 4 = W
+    ((2048, 8), (1, 2), "complex128", (11, 2)),      # p_1 = 1, rows of 4 = 2 W
+    ((2048, 4), (1, 2), "complex128", (11, 1)),      # rows of 2 = W: one block per tile
 ]
 IDS = [f"{'x'.join(map(str, n))}-p{'x'.join(map(str, p))}-{dt}" for n, p, dt, _ in CASES]
 
