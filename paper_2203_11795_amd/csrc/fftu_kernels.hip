@@ -220,37 +220,14 @@ __global__ __launch_bounds__(kPointwiseThreads) void k_permute(const cx<T> *__re
 // LD > 0: the innermost dimension has m_d = p_d = 2^LD <= 32 points, so the tile's
 // 64 consecutive local indices hold whole lines of it, and its 64 consecutive
 // processors whole groups of its p_d. The kernel then also runs Superstep 0's
-// length-m_d FFTs (on the rows, before the twiddle) and Superstep 2's length-p_d
-// FFTs (on the columns, after it) in registers with exact roots: the local FFT
+// length-m_d FFTs (on the rows, with the twiddle applied as each line is written
+// back) and Superstep 2's length-p_d FFTs (on the columns, each line stored straight
+// from registers: its outputs are consecutive s, and plain stores let L2 join the
+// lanes' pieces of each line) in registers with exact roots. The local FFT
 // factorises over dimensions (eq. (1.3)), as does Superstep 2's, so the other
 // dimensions' passes may come before and after. It may then be the last kernel:
 // the store conjugates and scales as the descriptor says.
 constexpr int kTransposeTile = 64;
-
-// length-2^LD DFTs along groups of 2^LD consecutive entries of the rows (ROWS) or
-// columns of the tile (rows of TT + 1)
-template <typename T, int LD, bool ROWS>
-__device__ __forceinline__ void tile_dfts(cx<T> *tile, int tid)
-{
-    constexpr int TT = kTransposeTile, R = 1 << LD;
-    constexpr int LINES = TT * TT / R;
-    for (int line = tid; line < LINES; line += kPointwiseThreads) {
-        int base, step;
-        if constexpr (ROWS) {
-            base = (line >> (6 - LD)) * (TT + 1) + ((line & ((TT >> LD) - 1)) << LD);
-            step = 1;
-        } else {
-            base = ((line >> 6) << LD) * (TT + 1) + (line & (TT - 1));
-            step = TT + 1;
-        }
-        cx<T> x[R];
-#pragma unroll
-        for (int i = 0; i < R; ++i) x[i] = tile[base + i * step];
-        Dft<T, R>::run(x);
-#pragma unroll
-        for (int i = 0; i < R; ++i) tile[base + i * step] = x[i];
-    }
-}
 
 template <typename T, int LD>
 __global__ __launch_bounds__(kPointwiseThreads) void k_ttranspose(const cx<T> *__restrict__ in,
@@ -296,38 +273,60 @@ __global__ __launch_bounds__(kPointwiseThreads) void k_ttranspose(const cx<T> *_
         const int h = (g.lognmax + 1) >> 1;
         fac[i] = cmul(table[e & ~((uint32_t(1) << h) - 1)], table[e & ((uint32_t(1) << h) - 1)]);
     }
+    auto twiddle = [&](int dkk, int dss) {
+        cx<T> w = {T(1), T(0)};
+        int off = 0;
+        for (int l = 0; l < g.d; ++l) {
+            const int bl = lowbits(l);
+            const int a = (dkk >> g.logmstride[l]) & ((1 << bl) - 1);
+            const int b = (dss >> g.logpstride[l]) & ((1 << bl) - 1);
+            w = cmul(w, fac[off + (a << bl) + b]);
+            off += 1 << (2 * bl);
+        }
+        return w;
+    };
     if constexpr (LD > 0) {
-        // Superstep 0 along the innermost dimension: rows, before the twiddle
+        constexpr int R = 1 << LD, LINES = TT * TT / R, GR = TT >> LD;
 #pragma unroll
         for (int i = 0; i < PER; ++i) tile[((tid >> 6) + i * (kPointwiseThreads / TT)) * (TT + 1) + dk] = r[i];
         __syncthreads();
-        tile_dfts<T, LD, true>(tile, tid);
-        __syncthreads();
+        // rows: Superstep 0 along the innermost dimension, then the twiddle, in place
+        for (int line = tid; line < LINES; line += kPointwiseThreads) {
+            const int dss = line / GR, base = dss * (TT + 1) + (line % GR) * R;
+            cx<T> x[R];
 #pragma unroll
-        for (int i = 0; i < PER; ++i) r[i] = tile[((tid >> 6) + i * (kPointwiseThreads / TT)) * (TT + 1) + dk];
+            for (int i = 0; i < R; ++i) x[i] = tile[base + i];
+            Dft<T, R>::run(x);
+#pragma unroll
+            for (int i = 0; i < R; ++i) tile[base + i] = cmul(x[i], twiddle((line % GR) * R + i, dss));
+        }
+        __syncthreads();
+        // columns: Superstep 2 along the innermost grid dimension, stored straight out (the
+        // R outputs of a lane are consecutive s; plain stores let L2 join the lanes' pieces)
+        const T scale = static_cast<T>(g.scale);
+        for (int line = tid; line < LINES; line += kPointwiseThreads) {
+            const int gg = line % GR, dkk = line / GR;
+            cx<T> x[R];
+#pragma unroll
+            for (int i = 0; i < R; ++i) x[i] = tile[(gg * R + i) * (TT + 1) + dkk];
+            Dft<T, R>::run(x);
+#pragma unroll
+            for (int i = 0; i < R; ++i) {
+                cx<T> v = conj_if(x[i], g.conj_out);
+                if (g.scale != 1.0) v = {v.x * scale, v.y * scale};
+                out[((k0 + dkk) << logM) + s0 + gg * R + i] = v;
+            }
+        }
+        return;
     } else {
         __syncthreads();
     }
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
         const int ds = (tid >> 6) + i * (kPointwiseThreads / TT);
-        cx<T> v = r[i];
-        int off = 0;
-        for (int l = 0; l < g.d; ++l) {
-            const int bl = lowbits(l);
-            const int a = (dk >> g.logmstride[l]) & ((1 << bl) - 1);
-            const int b = (ds >> g.logpstride[l]) & ((1 << bl) - 1);
-            v = cmul(v, fac[off + (a << bl) + b]);
-            off += 1 << (2 * bl);
-        }
-        tile[ds * (TT + 1) + dk] = v;
+        tile[ds * (TT + 1) + dk] = cmul(r[i], twiddle(dk, ds));
     }
     __syncthreads();
-    if constexpr (LD > 0) {
-        // Superstep 2 along the innermost grid dimension: columns (consecutive s)
-        tile_dfts<T, LD, false>(tile, tid);
-        __syncthreads();
-    }
     const int ds = tid & (TT - 1);
     const T scale = static_cast<T>(g.scale);
 #pragma unroll 4
