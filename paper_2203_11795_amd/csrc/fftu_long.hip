@@ -22,8 +22,9 @@
 // L + L/16 + 64/W words per line: one pad word per 16 positions spreads the radix
 // scatters over the banks, and the row length spreads the linear accesses. The
 // stage twiddles omega_L^e are products of two small LDS tables,
-// omega_L^(e mod 64) and omega_L^(64 (e div 64)): the full table of L entries would
-// not fit beside the tile.
+// omega_L^(e mod 64) and omega_L^(64 (e div 64)), 1 KiB per tile: a copy of the
+// full table of L entries (32 KiB for 4096 complex64) per tile cost more than the
+// extra multiply.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
