@@ -109,6 +109,14 @@ def test_p_max_examples():
     ((60, 60), (2, 2), "complex128", 2, 1, 3),            # mixed radix: 2 passes, then k_mexchange
     ((49, 27, 8), (7, 3, 2), "complex64", 3, 1, 4),
     ((1000, 60), (10, 2), "complex128", 2, 0, 5),         # p = 10: twiddle + permutation, then 2 passes
+    # the paper's sizes: 1024^3 takes the 1024-thread k_lastx; 2^24 x 64 (every q_l = 1) takes
+    # k_long, k_ttranspose with the 8-point FFTs of Supersteps 0 and 2, k_long
+    ((1024,) * 3, (4, 4, 4), "complex128", 2, 2, 3),
+    ((1 << 24, 64), (4096, 8), "complex64", 1, 0, 3),
+    ((64, 4096), (8, 64), "complex64", 1, 0, 4),            # every q_l = 1, innermost side 64: plain transpose
+    ((64, 64, 64), (8, 8, 8), "complex128", 2, 0, 5),       # P = 512: k_ttranspose with the 8-point FFTs
+    ((8192, 16), (2, 2), "complex64", 2, 1, 3),             # k_long for the lines of 4096
+    ((16, 16, 16, 32, 64), (2,) * 5, "complex64", 2, 2, 3),  # two k_pair passes, then k_lastx
 ])
 def test_describe(n, p, dtype, s0, fused, launches):
     info = fftu.describe(n, p, dtype)
