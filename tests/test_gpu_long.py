@@ -82,17 +82,19 @@ def test_long_lines_match_oracle(torch_dev, n, p, dtype, lw, direction):
     assert np.array_equal(got, again), "in place must equal out of place"
 
 
-def test_unfused_superstep2_with_long_lines(torch_dev):
+@pytest.mark.parametrize("direction", [FORWARD, INVERSE])
+def test_unfused_superstep2_with_long_lines(torch_dev, direction):
     """p_1 = 2048: P = 4096 takes the unfused exchange, and Superstep 2's transforms
-    along p_1 run on k_long as Superstep 0's along m_1 do."""
+    along p_1 run on k_long as Superstep 0's along m_1 do; k_long is then the last
+    kernel (conjugation and 1/N of the inverse on its store)."""
     import paper_2203_11795_amd as fftu
     n, p = (1 << 22, 8), (2048, 2)
     N = int(np.prod(n))
-    say(f"long S2 n={n} p={p}")
+    say(f"long S2 n={n} p={p} dir={direction}")
     D = synth.uniform_complex(N, 32, np.complex64).astype(np.complex128)
-    with fftu.Plan(n, p, "complex64", FORWARD) as plan:
+    with fftu.Plan(n, p, "complex64", direction) as plan:
         names = plan.launch_names()
-        assert names.count("fftu::k_long<float, 11, 2>") == 2, names
+        assert names.count("fftu::k_long<float, 11, 2>") == 2 and names[-1] == "fftu::k_long<float, 11, 2>", names
         assert plan.info()["exchange_fused"] == 0
         got = run(torch_dev, plan, D, "complex64")
-    assert oracle.rel_l2(got, oracle.cyclic_dft(D, n, p)) <= TOL["complex64"]
+    assert oracle.rel_l2(got, oracle.cyclic_dft(D, n, p, direction)) <= TOL["complex64"]
