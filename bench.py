@@ -368,7 +368,12 @@ def run_paper_workloads(args, torch, fftu):
                                  "achieved": round(alg / (ms * 1e-3) / 1e9, 1),
                                  "frac": round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
                     "rel_l2_roundtrip": rt,
-                    "kernels": [{"kernel": k, "avg_ms": round(t, 3)} for k, t in zip(names, per_launch)]})
+                    # traffic: HBM bytes per launch from the committed counter summary (None when
+                    # it was taken from other kernel sources)
+                    "kernels": [{"kernel": k, "avg_ms": round(t, 3),
+                                 "GBps_alg": round(2.0 * N * esize / (t * 1e-3) / 1e9, 1) if t > 0 else None,
+                                 "algorithmic_bytes": 2.0 * N * esize, "traffic": measured_traffic("paper", k)}
+                                for k, t in zip(names, per_launch)]})
         del x, y
         torch.cuda.empty_cache()
         log(f"[bench] paper workload {'x'.join(map(str, n))}: {ms:.2f} ms, {res[-1]['GFLOPs']} GFLOP/s")

@@ -15,9 +15,9 @@
 //      in-register DFTs with exact roots), exchanging through LDS between stages;
 //   4. regroups through LDS once more and stores the tile linearly.
 // With G tiles per outer block they share every 128-byte line: they run on the same
-// XCD at the same time (workgroups go to the 8 XCDs round-robin), so all but the
-// first read the lines from that XCD's L2, and they store with plain stores so that
-// L2 merges the pieces of each line.
+// XCD at the same time (workgroups go to the 8 XCDs round-robin) and load and store
+// with plain (not non-temporal) accesses, so that all but the first read the lines
+// from that XCD's L2 and L2 merges the pieces of each line they write.
 // LDS holds one word per element (real parts, then imaginary parts), rows of
 // L + L/16 + 64/W words per line: one pad word per 16 positions spreads the radix
 // scatters over the banks, and the row length spreads the linear accesses. The
@@ -164,7 +164,15 @@ __global__ __launch_bounds__(kLongThreads) void k_long(const cx<T> *in, cx<T> *o
 
     cx<T> r[E];
 #pragma unroll
-    for (int c = 0; c < E; ++c) r[c] = conj_if(get(&in[goff(tid + c * NT)]), pd.conj_in);
+    for (int c = 0; c < E; ++c) {
+        // G tiles share each line when B = G W: plain loads keep the lines in L2 for the
+        // others (non-temporal ones fetched 2.06 times the bytes from HBM with G = 4)
+        if constexpr (LOGB > LOGW) {
+            r[c] = conj_if(in[goff(tid + c * NT)], pd.conj_in);
+        } else {
+            r[c] = conj_if(get(&in[goff(tid + c * NT)]), pd.conj_in);
+        }
+    }
     cx<T> v[E];
 #pragma unroll
     for (int c = 0; c < E; ++c) ld[at(tid + c * NT)] = r[c].x;
