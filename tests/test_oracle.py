@@ -299,3 +299,64 @@ def test_pins_detect_planted_mistakes():
     }
     for name, fn in mutants.items():
         assert not _pins_pass(fn), name
+
+
+# ---------------------------------------------------------------- the error measure itself
+
+def _read_rel_l2_cases():
+    cases = []
+    for line in open(os.path.join(GOLDEN, "rel_l2.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        _, ys, refs, expect = [f.strip() for f in line.split("|")]
+        y = np.array([complex(*map(float, t.split(","))) for t in ys.split()])
+        ref = np.array([complex(*map(float, t.split(","))) for t in refs.split()])
+        cases.append((y, ref, float(expect)))
+    return cases
+
+
+def _rel_l2_pins_pass(fn):
+    """Every hand-worked case of tests/golden/rel_l2.txt, to 1e-15 relative."""
+    for y, ref, expect in _read_rel_l2_cases():
+        got = fn(y, ref)
+        if np.isinf(expect):
+            if not np.isinf(got):
+                return False
+        elif expect == 0.0:
+            if got != 0.0:
+                return False
+        elif not abs(got - expect) <= 1e-15 * expect:
+            return False
+    return True
+
+
+def test_rel_l2_hand_worked_cases():
+    cases = _read_rel_l2_cases()
+    assert len(cases) == 9
+    assert _rel_l2_pins_pass(oracle.rel_l2)
+    # shape and dtype of the operands do not matter: the measure is over all entries
+    y, ref, expect = cases[2]
+    assert oracle.rel_l2(y.reshape(2, 1), ref) == pytest.approx(expect, rel=1e-15)
+    assert oracle.rel_l2(y.astype(np.complex64), ref) == pytest.approx(expect, rel=1e-15)
+
+
+def test_rel_l2_pins_detect_planted_mistakes():
+    def ratio(num, den):
+        return 0.0 if den == 0 and num == 0 else (float("inf") if den == 0 else num / den)
+
+    def l2(v):
+        return np.sqrt(np.sum(np.abs(v) ** 2))
+
+    mutants = {
+        "no square root": lambda y, r: ratio(np.sum(np.abs(y - r) ** 2), np.sum(np.abs(r) ** 2)),
+        "max-abs ratio": lambda y, r: ratio(np.max(np.abs(y - r)), np.max(np.abs(r))),
+        "no denominator": lambda y, r: ratio(l2(y - r), 1.0 if l2(r) else 0.0),
+        "normalised by y": lambda y, r: ratio(l2(y - r), l2(y)) if l2(r) else ratio(l2(y), 0.0),
+        "L1 norms": lambda y, r: ratio(np.sum(np.abs(y - r)), np.sum(np.abs(r))),
+        "real parts only": lambda y, r: ratio(l2((y - r).real), l2(r.real)) if l2(r) else ratio(l2(y), 0.0),
+        "single precision": lambda y, r: ratio(float(l2((y - r).astype(np.complex64))),
+                                               float(l2(r.astype(np.complex64)))),
+        "zero reference passes anything": lambda y, r: 0.0 if l2(r) == 0 else ratio(l2(y - r), l2(r)),
+    }
+    for name, fn in mutants.items():
+        assert not _rel_l2_pins_pass(fn), name
