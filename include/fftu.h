@@ -176,7 +176,10 @@ size_t fftu_plan_device_bytes(fftu_plan_t plan);
  * cyclic buffer layout above. in and out are device pointers to N elements of
  * the plan's dtype, on the plan's device; in == out is allowed (in-place);
  * otherwise the buffers must not overlap and in is left unchanged. Enqueued on
- * `stream` (0 = the null stream); returns without waiting.
+ * `stream` (0 = the null stream); returns without waiting. A batch plan
+ * (fftu_plan_batch) is refused with FFTU_ERROR_INVALID_VALUE here and in
+ * fftu_execute_ws and the fftu_stage_* calls: it runs only through
+ * fftu_execute_batch.
  */
 fftu_status fftu_execute(fftu_plan_t plan, const void *in, void *out, hipStream_t stream);
 
@@ -244,11 +247,17 @@ fftu_status fftu_timing_end(fftu_plan_t plan, float *avg_ms, int capacity, int *
  * sum_i N_i elements and the work list in device memory.
  *
  * fftu_execute_batch runs every transform: out[i] = F(in[i]); in and out are
- * host arrays of `count` device pointers (in[i] == out[i] allowed). The
- * pointers are bound to the plan's device work list; when they differ from the
- * previous call the new ones are uploaded first, which waits for `stream` and
- * copies the list synchronously. With unchanged pointers the call only enqueues
- * two kernels (a counter reset and the persistent kernel) and returns.
+ * host arrays of `count` device pointers, each aligned to the element size.
+ * in[i] == out[i] is allowed; otherwise in[i] and out[i] must not overlap, and
+ * no out[i] may overlap another transform's input or output
+ * (FFTU_ERROR_INVALID_VALUE, checked on the host before anything is enqueued).
+ * The pointers are read by the persistent kernel from a small device array of
+ * the plan. When they differ from the previous call's, the call first enqueues
+ * one small kernel per 96 transforms on `stream` that writes the new pointers
+ * there (the pointers travel as kernel arguments), so the call never waits for
+ * the host or the device and never allocates. It then enqueues a counter reset
+ * and the persistent kernel, and returns. As for every plan, one stream at a
+ * time may execute it.
  *
  * fftu_batch_error reports (after waiting for the device) whether the last
  * batch on this plan hit its bounded dependency wait (1) or not (0).
@@ -263,8 +272,11 @@ fftu_status fftu_batch_error(fftu_plan_t plan, int *flag);
  * (count = 0, in/out point at one device pointer each) or one
  * fftu_execute_batch (count = the batch size, in/out arrays of count device
  * pointers) on a private stream and instantiates them. fftu_graph_launch
- * replays the graph on `stream`; the buffers are the ones given at capture.
- * The graph refers to the plan, which must outlive it. NULL on failure.
+ * replays the graph on `stream`; the buffers are the ones given at capture,
+ * whatever the plan ran on in between (a batch graph rewrites the plan's
+ * pointer array as its first step). A graph replay counts as an execution of
+ * its plan: one stream at a time. The graph refers to the plan, which must
+ * outlive it. Buffer checks as for the execution it records. NULL on failure.
  */
 typedef struct fftu_graph_s *fftu_graph_t;
 fftu_graph_t fftu_graph_capture(fftu_plan_t plan, int count, const void *const in[], void *const out[]);

@@ -96,8 +96,10 @@ def _time_ms(run, reps: int) -> float:
 
 def _search(make_runner, reps: int):
     """Coordinate descent over the knobs. make_runner() builds a plan under the
-    current knobs and returns (run, close), or raises FftuError if the setting
-    is not plannable."""
+    current knobs and returns (run, close) or (run, close, valid), or raises
+    FftuError if the setting is not plannable. valid(), called after the timed
+    runs, says whether the candidate's last output is right; a candidate that
+    fails it is recorded as rejected and never kept, however fast it ran."""
     saved = current()
     table = []
     best = {k: -1 for k in KNOB_NAMES}
@@ -113,14 +115,20 @@ def _search(make_runner, reps: int):
                     continue
                 try:
                     apply(cand)
-                    run, close = make_runner()
+                    runner = make_runner()
                 except _b.FftuError:
                     tried[key] = None
                     continue
+                run, close = runner[0], runner[1]
                 try:
                     ms = _time_ms(run, reps)
+                    ok = runner[2]() if len(runner) > 2 else True
                 finally:
                     close()
+                if not ok:
+                    tried[key] = None
+                    table.append({**cand, "ms": round(ms, 4), "rejected": True})
+                    continue
                 tried[key] = ms
                 table.append({**cand, "ms": round(ms, 4)})
                 if best_ms is None or ms < best_ms:
@@ -138,9 +146,27 @@ def tune_batch(shapes, grids, dtype, direction, xs, outs, reps: int = 5, use_cac
         if hit:
             return {**hit, "cached": True}
 
+    import torch
+    saved = current()
+    try:
+        apply({})                          # the reference output: library defaults
+        with _b.BatchPlan(shapes, grids, dtype, direction) as bp:
+            ref = [o.clone() for o in bp(xs, [torch.empty_like(x) for x in xs])]
+            torch.cuda.synchronize()
+            if bp.error_flag() != 0:
+                raise RuntimeError("the batch with default knobs hit its dependency wait limit")
+    finally:
+        apply(saved)
+
     def make_runner():
         bp = _b.BatchPlan(shapes, grids, dtype, direction)
-        return (lambda: bp(xs, outs)), bp.close
+
+        def valid():
+            # the bounded dependency wait gives up by skipping work (and so runs faster);
+            # tiling never changes arithmetic, so outputs must equal the defaults' bit for bit
+            torch.cuda.synchronize()
+            return bp.error_flag() == 0 and all(torch.equal(o, r) for o, r in zip(outs, ref))
+        return (lambda: bp(xs, outs)), bp.close, valid
 
     best, best_ms, table = _search(make_runner, reps)
     res = {"knobs": best, "ms": round(best_ms, 4) if best_ms is not None else None, "candidates": table}
@@ -156,9 +182,23 @@ def tune_plan(n, p, dtype, direction, x, out, reps: int = 5, use_cache: bool = T
         if hit:
             return {**hit, "cached": True}
 
+    import torch
+    saved = current()
+    try:
+        apply({})
+        with _b.Plan(n, p, dtype, direction) as pl:
+            ref = pl(x, torch.empty_like(out)).clone()
+            torch.cuda.synchronize()
+    finally:
+        apply(saved)
+
     def make_runner():
         pl = _b.Plan(n, p, dtype, direction)
-        return (lambda: pl(x, out)), pl.close
+
+        def valid():
+            torch.cuda.synchronize()
+            return torch.equal(out, ref)
+        return (lambda: pl(x, out)), pl.close, valid
 
     best, best_ms, table = _search(make_runner, reps)
     res = {"knobs": best, "ms": round(best_ms, 4) if best_ms is not None else None, "candidates": table}

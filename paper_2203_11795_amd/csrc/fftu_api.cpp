@@ -78,7 +78,8 @@ struct fftu_plan_s {
     void *ddone = nullptr;
     void *dnext = nullptr;
     void *derror = nullptr;
-    std::vector<const void *> bound_in;
+    void *dbind = nullptr;                     // [count] BatchBind: the buffers the device list holds
+    std::vector<const void *> bound_in;        // what dbind holds once the enqueued work has run
     std::vector<void *> bound_out;
     std::vector<hipEvent_t> events;  // timing_max x (launches + 1)
     int timing_max = 0;
@@ -1013,7 +1014,7 @@ bool aligned(const void *p, size_t esize) { return (reinterpret_cast<uintptr_t>(
 
 fftu_status check_exec_args(const fftu_plan_s *plan, const void *in, const void *out)
 {
-    if (!plan || !in || !out) return FFTU_ERROR_INVALID_VALUE;
+    if (!plan || !in || !out || plan->is_batch) return FFTU_ERROR_INVALID_VALUE;
     if (!aligned(in, plan->esize) || !aligned(out, plan->esize)) return FFTU_ERROR_INVALID_VALUE;
     if (in != out) {
         const char *a = static_cast<const char *>(in);
@@ -1037,30 +1038,63 @@ bool batch_exchange_ok(const ExchangeSplit &sp)
 
 void free_batch(fftu_plan_s *pl)
 {
-    for (void *ptr : {pl->dstages, pl->dstarts, pl->ddep, pl->ddone, pl->dnext, pl->derror})
+    for (void *ptr : {pl->dstages, pl->dstarts, pl->ddep, pl->ddone, pl->dnext, pl->derror, pl->dbind})
         if (ptr) (void)hipFree(ptr);
-    pl->dstages = pl->dstarts = pl->ddep = pl->ddone = pl->dnext = pl->derror = nullptr;
+    pl->dstages = pl->dstarts = pl->ddep = pl->ddone = pl->dnext = pl->derror = pl->dbind = nullptr;
 }
 
-// Upload the work list with the given buffers (waits for `stream` first).
-fftu_status bind_batch(fftu_plan_s *pl, const void *const in[], void *const out[], hipStream_t stream)
+// The buffers of a batch call: none NULL, each aligned to the element size,
+// in[f] and out[f] either equal or disjoint, and no output overlapping another
+// transform's input or output. O(count log count).
+fftu_status check_batch_args(const fftu_plan_s *pl, const void *const in[], void *const out[])
 {
-    hipError_t e = hipStreamSynchronize(stream);
-    if (e != hipSuccess) return from_hip(e);
-    const size_t es = pl->esize;
-    for (size_t k = 0; k < pl->hstages.size(); ++k) {
-        const int f = pl->stage_member[k];
-        char *ws = static_cast<char *>(pl->ws) + pl->member_ws[size_t(f)] * es;
-        fftu::BatchStage &st = pl->hstages[k];
-        st.src = pl->stage_first[k] ? in[f] : ws;
-        st.dst = pl->stage_last[k] ? out[f] : static_cast<void *>(ws);
+    if (!pl || !pl->is_batch || !in || !out) return FFTU_ERROR_INVALID_VALUE;
+    struct Span {
+        uintptr_t lo, hi;
+        int f;
+    };
+    std::vector<Span> outs(size_t(pl->count));
+    for (int f = 0; f < pl->count; ++f) {
+        if (!in[f] || !out[f] || !aligned(in[f], pl->esize) || !aligned(out[f], pl->esize))
+            return FFTU_ERROR_INVALID_VALUE;
+        const uintptr_t o = reinterpret_cast<uintptr_t>(out[f]);
+        outs[size_t(f)] = {o, o + uintptr_t(pl->member_N[size_t(f)]) * pl->esize, f};
     }
-    e = hipMemcpy(pl->dstages, pl->hstages.data(), pl->hstages.size() * sizeof(fftu::BatchStage),
-                  hipMemcpyHostToDevice);
-    if (e != hipSuccess) return from_hip(e);
-    pl->bound_in.assign(in, in + pl->count);
-    pl->bound_out.assign(out, out + pl->count);
+    std::sort(outs.begin(), outs.end(), [](const Span &a, const Span &b) { return a.lo < b.lo; });
+    for (size_t i = 1; i < outs.size(); ++i)
+        if (outs[i].lo < outs[i - 1].hi) return FFTU_ERROR_INVALID_VALUE;   // two outputs overlap
+    // the outputs are disjoint and sorted, so their ends are sorted too
+    for (int f = 0; f < pl->count; ++f) {
+        const uintptr_t lo = reinterpret_cast<uintptr_t>(in[f]);
+        const uintptr_t hi = lo + uintptr_t(pl->member_N[size_t(f)]) * pl->esize;
+        auto it = std::upper_bound(outs.begin(), outs.end(), lo, [](uintptr_t v, const Span &s) { return v < s.hi; });
+        for (; it != outs.end() && it->lo < hi; ++it)
+            if (it->f != f || it->lo != lo) return FFTU_ERROR_INVALID_VALUE;   // only in[f] == out[f] may meet
+    }
     return FFTU_SUCCESS;
+}
+
+// Write the buffers into the device list on `stream` (k_batch_bind launches that
+// carry the pointers as arguments): stream-ordered, no host wait.
+fftu_status enqueue_bind(const fftu_plan_s *pl, const void *const in[], void *const out[], hipStream_t stream)
+{
+    for (int first = 0; first < pl->count; first += fftu::kBindChunk) {
+        fftu::BindChunk c{};
+        c.first = first;
+        c.count = std::min(fftu::kBindChunk, pl->count - first);
+        for (int i = 0; i < c.count; ++i) c.b[i] = {in[first + i], out[first + i]};
+        hipError_t e = fftu::launch_batch_bind(static_cast<fftu::BatchBind *>(pl->dbind), c, stream);
+        if (e != hipSuccess) return from_hip(e);
+    }
+    return FFTU_SUCCESS;
+}
+
+bool same_binding(const fftu_plan_s *pl, const void *const in[], void *const out[])
+{
+    if (pl->bound_in.size() != size_t(pl->count)) return false;
+    for (int f = 0; f < pl->count; ++f)
+        if (pl->bound_in[size_t(f)] != in[f] || pl->bound_out[size_t(f)] != out[f]) return false;
+    return true;
 }
 
 // The reset kernel, then the persistent kernel; with a marker, timing events
@@ -1077,6 +1111,7 @@ fftu_status enqueue_batch(fftu_plan_s *pl, hipStream_t stream, Marker *mk = null
     bd.done = static_cast<int32_t *>(pl->ddone);
     bd.next = static_cast<unsigned long long *>(pl->dnext);
     bd.error = static_cast<int32_t *>(pl->derror);
+    bd.bind = static_cast<const fftu::BatchBind *>(pl->dbind);
     if (mk) mk->mark();
     hipError_t e = fftu::launch_batch_reset(bd, stream);
     if (e != hipSuccess) return from_hip(e);
@@ -1095,6 +1130,9 @@ fftu_status execute_with(fftu_plan_s *plan, const void *in, void *out, void *ws,
 struct fftu_graph_s {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    fftu_plan_s *batch = nullptr;            // batch graphs: the plan, whose device list each replay rebinds
+    std::vector<const void *> in;            // the buffers captured (batch graphs)
+    std::vector<void *> out;
 };
 
 namespace {
@@ -1556,6 +1594,8 @@ fftu_status build_batch_worklist(int count, const int d[], const int64_t *const 
             // every stage indexes the batch's one table of omega_{2^lognmax}
             st.pd.lognmax = lognmax;
             st.ex.g.lognmax = lognmax;
+            st.member = f;
+            st.io = (s == 0 ? 1 : 0) | (s == ns0 ? 2 : 0);
             wl.stages.push_back(st);
             wl.member.push_back(f);
             wl.first.push_back(s == 0 ? 1 : 0);
@@ -1621,6 +1661,19 @@ fftu_plan_t fftu_plan_batch(int count, const int d[], const int64_t *const n[], 
     if (e == hipSuccess) e = hipMalloc(&pl->ddone, K * sizeof(int32_t));
     if (e == hipSuccess) e = hipMalloc(&pl->dnext, sizeof(unsigned long long));
     if (e == hipSuccess) e = hipMalloc(&pl->derror, sizeof(int32_t));
+    if (e == hipSuccess) e = hipMalloc(&pl->dbind, size_t(count) * sizeof(fftu::BatchBind));
+    if (e == hipSuccess) {
+        // stages between a transform's first and last read and write its workspace;
+        // the caller's buffers come from the bind array
+        for (size_t k = 0; k < K; ++k) {
+            const int f = pl->stage_member[k];
+            char *ws = static_cast<char *>(pl->ws) + pl->member_ws[size_t(f)] * pl->esize;
+            fftu::BatchStage &st = pl->hstages[k];
+            st.src = pl->stage_first[k] ? nullptr : ws;
+            st.dst = pl->stage_last[k] ? nullptr : static_cast<void *>(ws);
+        }
+        e = hipMemcpy(pl->dstages, pl->hstages.data(), K * sizeof(fftu::BatchStage), hipMemcpyHostToDevice);
+    }
     if (e == hipSuccess) e = hipMemcpy(pl->dstarts, starts.data(), (K + 1) * sizeof(int64_t), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(pl->ddep, dep.data(), K * sizeof(int32_t), hipMemcpyHostToDevice);
     if (e == hipSuccess) {
@@ -1661,15 +1714,12 @@ fftu_plan_t fftu_plan_batch(int count, const int d[], const int64_t *const n[], 
 fftu_status fftu_execute_batch(fftu_plan_t plan, const void *const in[], void *const out[], hipStream_t stream)
 {
     if (!plan || !plan->is_batch || !in || !out) return record(FFTU_ERROR_INVALID_VALUE);
-    bool same = plan->bound_in.size() == size_t(plan->count);
-    for (int f = 0; f < plan->count; ++f) {
-        if (!in[f] || !out[f] || !aligned(in[f], plan->esize) || !aligned(out[f], plan->esize))
-            return record(FFTU_ERROR_INVALID_VALUE);
-        if (same && (plan->bound_in[size_t(f)] != in[f] || plan->bound_out[size_t(f)] != out[f])) same = false;
-    }
-    if (!same) {
-        fftu_status s = bind_batch(plan, in, out, stream);
+    if (!same_binding(plan, in, out)) {
+        fftu_status s = check_batch_args(plan, in, out);
+        if (s == FFTU_SUCCESS) s = enqueue_bind(plan, in, out, stream);
         if (s != FFTU_SUCCESS) return record(s);
+        plan->bound_in.assign(in, in + plan->count);
+        plan->bound_out.assign(out, out + plan->count);
     }
     Marker mk(plan, stream);
     return record(enqueue_batch(plan, stream, &mk));
@@ -1706,25 +1756,26 @@ fftu_graph_t fftu_graph_capture(fftu_plan_t plan, int count, const void *const i
         record(FFTU_ERROR_DEVICE);
         return nullptr;
     }
-    fftu_status st = FFTU_SUCCESS;
-    if (count > 0) {
-        // bind outside the capture (the upload synchronises)
-        bool same = plan->bound_in.size() == size_t(count);
-        for (int f = 0; f < count && same; ++f)
-            same = plan->bound_in[size_t(f)] == in[f] && plan->bound_out[size_t(f)] == out[f];
-        if (!same) st = bind_batch(plan, in, out, s);
-    }
+    fftu_status st = count > 0 ? check_batch_args(plan, in, out) : FFTU_SUCCESS;
     fftu_graph_s *gr = nullptr;
     if (st == FFTU_SUCCESS) {
         gr = new (std::nothrow) fftu_graph_s();
         if (!gr) st = FFTU_ERROR_OUT_OF_MEMORY;
+    }
+    if (st == FFTU_SUCCESS && count > 0) {
+        gr->batch = plan;
+        gr->in.assign(in, in + count);
+        gr->out.assign(out, out + count);
     }
     if (st == FFTU_SUCCESS) {
         hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) {
             const int saved_max = plan->timing_max;
             plan->timing_max = 0;   // no timing events inside a graph
-            st = count > 0 ? enqueue_batch(plan, s) : fftu_execute(plan, in[0], out[0], s);
+            // a batch graph binds its own buffers first, so each replay runs on them
+            // whatever the plan ran on in between
+            if (count > 0) st = enqueue_bind(plan, in, out, s);
+            if (st == FFTU_SUCCESS) st = count > 0 ? enqueue_batch(plan, s) : fftu_execute(plan, in[0], out[0], s);
             plan->timing_max = saved_max;
             hipError_t e2 = hipStreamEndCapture(s, &gr->graph);
             if (st == FFTU_SUCCESS && e2 != hipSuccess) st = from_hip(e2);
@@ -1750,7 +1801,13 @@ fftu_graph_t fftu_graph_capture(fftu_plan_t plan, int count, const void *const i
 fftu_status fftu_graph_launch(fftu_graph_t graph, hipStream_t stream)
 {
     if (!graph || !graph->exec) return record(FFTU_ERROR_INVALID_VALUE);
-    return record(from_hip(hipGraphLaunch(graph->exec, stream)));
+    fftu_status st = from_hip(hipGraphLaunch(graph->exec, stream));
+    if (st == FFTU_SUCCESS && graph->batch) {
+        // the replay leaves the plan's device list holding the graph's buffers
+        graph->batch->bound_in = graph->in;
+        graph->batch->bound_out = graph->out;
+    }
+    return record(st);
 }
 
 void fftu_graph_destroy(fftu_graph_t graph)

@@ -25,7 +25,9 @@
 // device-scope acquire fence (which drops stale lines from its L2) before
 // reading the data.
 // Counters are cleared by k_batch_reset (a kernel, so the pair can be captured
-// in a graph and replayed).
+// in a graph and replayed). The caller's buffers are read from a device array
+// that k_batch_bind writes on the same stream before the batch, so a change of
+// buffers never waits for the host and a graph replays with its own.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -45,7 +47,12 @@ __global__ void k_batch_reset(BatchDesc bd)
     }
 }
 
-// Tiles [first, last) of a k_line pass; the block's twiddles are loaded once.
+__global__ void k_batch_bind(BatchBind *bind, const BindChunk c)
+{
+    const int i = threadIdx.x;
+    if (i < c.count) bind[c.first + i] = c.b[i];
+}
+
 // Values every lane of a wave holds alike, moved to scalar registers. The
 // persistent loop below decides its branches and loop bounds only on such values:
 // the compiler then keeps its control flow wave-uniform, so every thread of the
@@ -64,11 +71,12 @@ __device__ __forceinline__ int64_t uniform64(int64_t v)
 // Tiles [first, last) of a k_line pass; the block's twiddles are loaded once.
 // key = log2(line length) * 8 + pass kind, uniform.
 template <typename T>
-__device__ __forceinline__ void run_line(const BatchStage &st, int key, const cx<T> *__restrict__ table, cx<T> *tw,
-                                         cx<T> *tile, int64_t first, int64_t last, int tid)
+__device__ __forceinline__ void run_line(const BatchStage &st, const void *src, void *dst, int key,
+                                         const cx<T> *__restrict__ table, cx<T> *tw, cx<T> *tile, int64_t first,
+                                         int64_t last, int tid)
 {
-    const cx<T> *in = static_cast<const cx<T> *>(st.src);
-    cx<T> *out = static_cast<cx<T> *>(st.dst);
+    const cx<T> *in = static_cast<const cx<T> *>(src);
+    cx<T> *out = static_cast<cx<T> *>(dst);
     const PassDesc &pd = st.pd;
 #define FFTU_LINE_CASE(LG, MD)                                                    \
     case (LG) * 8 + (MD):                                                         \
@@ -99,11 +107,12 @@ __device__ __forceinline__ void run_line(const BatchStage &st, int key, const cx
 // (not inlined) for each plane shape: inlined, the 25 shapes raised the register
 // use of the whole persistent kernel.
 template <typename T, int A, int B>
-__device__ __noinline__ void group2_item(const BatchStage &st, const cx<T> *__restrict__ table, cx<T> *tw,
-                                         cx<T> *tile, int64_t first, int64_t last, int tid)
+__device__ __noinline__ void group2_item(const BatchStage &st, const void *src, void *dst,
+                                         const cx<T> *__restrict__ table, cx<T> *tw, cx<T> *tile, int64_t first,
+                                         int64_t last, int tid)
 {
-    const cx<T> *in = static_cast<const cx<T> *>(st.src);
-    cx<T> *out = static_cast<cx<T> *>(st.dst);
+    const cx<T> *in = static_cast<const cx<T> *>(src);
+    cx<T> *out = static_cast<cx<T> *>(dst);
     const PassDesc &pd = st.pd;
     // arguments arrive in vector registers: the tile loop (which holds barriers)
     // runs on scalar copies
@@ -118,10 +127,12 @@ __device__ __noinline__ void group2_item(const BatchStage &st, const cx<T> *__re
 
 // key = log2(L1) * 8 + log2(L2), uniform.
 template <typename T>
-__device__ __forceinline__ void run_group2(const BatchStage &st, int key, const cx<T> *__restrict__ table, cx<T> *tw,
-                                           cx<T> *tile, int64_t first, int64_t last, int tid)
+__device__ __forceinline__ void run_group2(const BatchStage &st, const void *src, void *dst, int key,
+                                           const cx<T> *__restrict__ table, cx<T> *tw, cx<T> *tile, int64_t first,
+                                           int64_t last, int tid)
 {
-#define FFTU_G2_CASE(A, B) case (A) * 8 + (B): group2_item<T, A, B>(st, table, tw, tile, first, last, tid); break;
+#define FFTU_G2_CASE(A, B) \
+    case (A) * 8 + (B): group2_item<T, A, B>(st, src, dst, table, tw, tile, first, last, tid); break;
 #define FFTU_G2_ROW(A) FFTU_G2_CASE(A, 2) FFTU_G2_CASE(A, 3) FFTU_G2_CASE(A, 4) FFTU_G2_CASE(A, 5) FFTU_G2_CASE(A, 6)
     switch (key) {
         FFTU_G2_ROW(2)
@@ -139,11 +150,12 @@ __device__ __forceinline__ void run_group2(const BatchStage &st, int key, const 
 // indices (no wave dimensions in a batch, so no LDS is shared between tiles).
 // key = register dimensions * 8 + log2(their radix), uniform.
 template <typename T>
-__device__ __forceinline__ void run_exchange(const BatchStage &st, int key, const cx<T> *__restrict__ table,
-                                             unsigned char *smem, int64_t first, int64_t last, int tid)
+__device__ __forceinline__ void run_exchange(const BatchStage &st, const void *src, void *dst, int key,
+                                             const cx<T> *__restrict__ table, unsigned char *smem, int64_t first,
+                                             int64_t last, int tid)
 {
-    const cx<T> *Z = static_cast<const cx<T> *>(st.src);
-    cx<T> *V = static_cast<cx<T> *>(st.dst);
+    const cx<T> *Z = static_cast<const cx<T> *>(src);
+    cx<T> *V = static_cast<cx<T> *>(dst);
     const ExchangeDesc &ex = st.ex;
 #define FFTU_EX_CASE(NR, LPR)                                                     \
     case (NR) * 8 + (LPR):                                                        \
@@ -231,13 +243,20 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(const BatchDesc bd, con
         const int64_t tiles = uniform64(st.tiles);
         const int64_t first = (item - uniform64(bd.starts[k])) * per;
         const int64_t last = first + per < tiles ? first + per : tiles;
+        const int io = uniform32(st.io);
+        const int mem = uniform32(st.member);
+        const void *src = reinterpret_cast<const void *>(
+            uniform64(int64_t(reinterpret_cast<uintptr_t>((io & 1) ? bd.bind[mem].in : st.src))));
+        void *dst = reinterpret_cast<void *>(
+            uniform64(int64_t(reinterpret_cast<uintptr_t>((io & 2) ? bd.bind[mem].out : st.dst))));
         if (kind == kExchangeStage)
-            run_exchange<T>(st, uniform32(st.ex.nr * 8 + st.ex.lpr), table,
+            run_exchange<T>(st, src, dst, uniform32(st.ex.nr * 8 + st.ex.lpr), table,
                             smem_raw + kBatchMaxLine * sizeof(cx<T>), first, last, tid);
         else if (kind == kGroup2)
-            run_group2<T>(st, uniform32(st.pd.loglen[0] * 8 + st.pd.loglen[1]), table, tw, tile, first, last, tid);
+            run_group2<T>(st, src, dst, uniform32(st.pd.loglen[0] * 8 + st.pd.loglen[1]), table, tw, tile, first,
+                          last, tid);
         else
-            run_line<T>(st, uniform32(st.pd.loglen[0] * 8 + kind), table, tw, tile, first, last, tid);
+            run_line<T>(st, src, dst, uniform32(st.pd.loglen[0] * 8 + kind), table, tw, tile, first, last, tid);
     }
 }
 
@@ -253,6 +272,12 @@ int batch_blocks_per_cu(Precision prec, uint32_t lds_bytes)
 hipError_t launch_batch_reset(const BatchDesc &bd, hipStream_t stream)
 {
     hipLaunchKernelGGL(k_batch_reset, dim3(uint32_t((bd.nstages + 255) / 256 + 1)), dim3(256), 0, stream, bd);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_bind(BatchBind *bind, const BindChunk &c, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_batch_bind, dim3(1), dim3(kBindChunk), 0, stream, bind, c);
     return hipGetLastError();
 }
 

@@ -275,10 +275,26 @@ struct BatchStage {
     int32_t kind;          // kLineStrided / kLineContig / kLineStaged, or kExchangeStage
     int32_t per_item;      // tiles (line tiles, or exchange groups of 4 x 64 indices) per work item
     int64_t tiles;
-    const void *src;
-    void *dst;
+    int32_t member;        // transform this stage belongs to
+    int32_t io;            // bit 0: reads the transform's input, bit 1: writes its output (BatchDesc::bind)
+    const void *src;       // the transform's workspace, unless io bit 0
+    void *dst;             // the transform's workspace, unless io bit 1
     PassDesc pd;           // line passes
     ExchangeDesc ex;       // the exchange (no wave dimensions)
+};
+
+// The caller's buffers of one transform. They live in a device array of their
+// own, written by k_batch_bind on the execution stream, so that new buffers are
+// bound in stream order (no host wait) and a captured graph carries its own.
+struct BatchBind {
+    const void *in;
+    void *out;
+};
+constexpr int kBindChunk = 96;         // buffer pairs per k_batch_bind launch (passed by value)
+struct BindChunk {
+    int32_t first;                     // first transform of this chunk
+    int32_t count;                     // pairs used, <= kBindChunk
+    BatchBind b[kBindChunk];
 };
 
 struct BatchDesc {
@@ -292,6 +308,7 @@ struct BatchDesc {
     int32_t *done;               // [nstages] finished items
     unsigned long long *next;    // next item to hand out
     int32_t *error;              // set when a wait gave up
+    const BatchBind *bind;       // [transforms] the caller's buffers
 };
 
 // Host-side work list of a batch plan (built by build_batch_worklist in fftu_api.cpp).
@@ -322,6 +339,7 @@ hipError_t launch_line(Precision prec, const void *in, void *out, const PassDesc
 hipError_t launch_group2(Precision prec, const void *in, void *out, const PassDesc &pd, const void *table,
                          hipStream_t stream);
 hipError_t launch_batch_reset(const BatchDesc &bd, hipStream_t stream);   // counters to zero (a kernel)
+hipError_t launch_batch_bind(BatchBind *bind, const BindChunk &c, hipStream_t stream);   // bind[first + i] = b[i]
 hipError_t launch_mline(Precision prec, const void *in, void *out, const MixedPassDesc &pd, const void *table,
                         hipStream_t stream);
 hipError_t launch_mtwiddle(Precision prec, const void *in, void *out, const MixedGridDesc &g, const void *table,

@@ -436,15 +436,24 @@ class BatchPlan:
         if st != 0:
             raise FftuError(st, "fftu_execute_batch")
 
+    def check_buffers(self, xs, outs):
+        """Inputs and outputs: one contiguous device tensor of the planned size and
+        dtype per transform (the library checks alignment and overlaps)."""
+        for name, ts in (("inputs", xs), ("outputs", outs)):
+            if len(ts) != len(self.sizes):
+                raise ValueError(f"one {name[:-1]} tensor per transform")
+            for t, n in zip(ts, self.sizes):
+                if not t.is_cuda or t.dtype != self.torch_dtype or t.numel() != n or not t.is_contiguous():
+                    raise ValueError(f"{name} must be contiguous {self.torch_dtype} device tensors "
+                                     f"of the planned sizes")
+
     def __call__(self, xs, outs=None, stream=None):
         import torch
         if len(xs) != len(self.sizes):
             raise ValueError("one input tensor per transform")
-        for x, n in zip(xs, self.sizes):
-            if not x.is_cuda or x.dtype != self.torch_dtype or x.numel() != n or not x.is_contiguous():
-                raise ValueError(f"inputs must be contiguous {self.torch_dtype} device tensors of the planned sizes")
         if outs is None:
             outs = [torch.empty_like(x) for x in xs]
+        self.check_buffers(xs, outs)
         if stream is None:
             stream = torch.cuda.current_stream(xs[0].device)
         self.execute_ptrs([x.data_ptr() for x in xs], [o.data_ptr() for o in outs], int(stream.cuda_stream))
@@ -502,8 +511,11 @@ class Graph:
         self._lib = load_library()
         self.plan = plan                 # the plan must outlive the graph
         if isinstance(plan, BatchPlan):
+            plan.check_buffers(xs, outs)
             count = len(xs)
         else:
+            plan._check_tensor(xs, "input")
+            plan._check_tensor(outs, "output")
             count = 0
             xs, outs = [xs], [outs]
         self._bufs = (xs, outs)

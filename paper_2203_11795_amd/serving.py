@@ -91,6 +91,13 @@ def next_queue(stream: int, lanes: int, large, small):
     return small if small else None
 
 
+def fits_arena(req: Request, capacity: int) -> bool:
+    """Whether the request's two blocks (buffer and workspace, each rounded up to
+    ALIGN) fit an empty arena of `capacity` bytes."""
+    block = (req.N * req.esize + ALIGN - 1) // ALIGN * ALIGN
+    return 2 * block <= capacity
+
+
 class Arena:
     """First-fit allocator over [0, capacity) with coalescing (offsets in bytes)."""
 
@@ -173,6 +180,7 @@ class ServeResult:
     plan_hits: int = 0
     plan_misses: int = 0
     peak_arena_bytes: int = 0
+    refused: list = field(default_factory=list)      # rids larger than the whole arena (never admissible)
 
 
 class Server:
@@ -272,8 +280,11 @@ class Server:
                 break
             while i < n and reqs[i].arrival <= now:
                 r = reqs[i]
-                (large if request_class(r, lanes, self.large_bytes) == "large" else small).append(r)
                 i += 1
+                if not fits_arena(r, self.arena_bytes):
+                    res.refused.append(r.rid)     # would wait forever for memory that never frees
+                    continue
+                (large if request_class(r, lanes, self.large_bytes) == "large" else small).append(r)
             progressed = False
             for s in range(nstreams):
                 run = running[s]
@@ -311,7 +322,7 @@ class Server:
                 finish(running[s])
         torch.cuda.synchronize()
         res.wall = time.perf_counter() - t0
-        res.unfinished = len(reqs) - res.completed
+        res.unfinished = len(reqs) - res.completed - len(res.refused)
         res.plan_hits = self.plans.hits - hits0
         res.plan_misses = self.plans.misses - miss0
         return res
@@ -332,5 +343,5 @@ def summarize(res: ServeResult, requests) -> dict:
         "achieved_rps": round(res.completed / res.wall, 1) if res.wall > 0 else None,
         "GFLOPs": round(flops / res.wall / 1e9, 1) if res.wall > 0 else None,
         "wall_s": round(res.wall, 3), "plan_hits": res.plan_hits, "plan_misses": res.plan_misses,
-        "peak_arena_GiB": round(res.peak_arena_bytes / 2 ** 30, 3),
+        "peak_arena_GiB": round(res.peak_arena_bytes / 2 ** 30, 3), "refused": len(res.refused),
     }

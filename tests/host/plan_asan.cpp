@@ -73,6 +73,11 @@ hipError_t launch_lastx(Precision, const void *, void *, const LastxDesc &lx, co
     return hipSuccess;
 }
 hipError_t launch_batch_reset(const BatchDesc &, hipStream_t) { return hipSuccess; }
+hipError_t launch_batch_bind(BatchBind *, const BindChunk &c, hipStream_t)
+{
+    if (c.count < 1 || c.count > kBindChunk || c.first < 0) std::abort();
+    return hipSuccess;
+}
 hipError_t launch_fill_uniform(Precision, void *, int64_t, uint32_t, uint32_t, uint64_t, hipStream_t) { return hipSuccess; }
 hipError_t launch_pointwise(Precision, const void *, const void *, void *, int64_t, double, hipStream_t) { return hipSuccess; }
 hipError_t launch_mline(Precision, const void *, void *, const MixedPassDesc &, const void *, hipStream_t) { return hipSuccess; }

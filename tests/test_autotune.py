@@ -55,3 +55,21 @@ def test_candidates_are_in_the_knob_ranges():
     finally:
         for k in autotune.KNOB_NAMES:
             binding.set_tuning(k, -1)
+
+
+def test_search_never_keeps_a_candidate_with_a_wrong_output(monkeypatch):
+    """A setting that runs fastest because it skipped work (a batch whose bounded
+    wait gave up) must lose to every valid one."""
+    state = {k: -1 for k in autotune.KNOB_NAMES}
+    monkeypatch.setattr(autotune, "current", lambda: dict(state))
+    monkeypatch.setattr(autotune, "apply", lambda knobs: state.update({k: int(knobs.get(k, -1)) for k in state}))
+    monkeypatch.setattr(autotune, "_time_ms", lambda run, reps: run())
+
+    def make_runner():
+        broken = state["line_pad"] == 0
+        c = 0.1 if broken else 1.0 + abs(state["max_lds_kb"] - 96) / 100.0
+        return (lambda: c), (lambda: None), (lambda: not broken)
+
+    best, best_ms, table = autotune._search(make_runner, reps=1)
+    assert best["line_pad"] != 0 and best["max_lds_kb"] == 96 and best_ms == 1.0
+    assert any(r.get("rejected") for r in table)

@@ -171,3 +171,100 @@ def test_autotune_batch_keeps_results_and_caches(torch, tmp_path, monkeypatch):
         autotune.apply({})
     for a, b in zip(base, tuned):
         assert torch.equal(a, b)
+
+
+def test_batch_graph_keeps_its_buffers(torch):
+    """A graph captured on (xs, outs) replays on them even after the plan ran
+    eagerly on other buffers; those other outputs are left alone."""
+    import paper_2203_11795_amd as fftu
+    shapes, grids = members(7, 13)
+    xs_h = [synth.uniform_complex(int(np.prod(s)), 110 + i, np.complex64) for i, s in enumerate(shapes)]
+    xs = to_dev(torch, xs_h, "complex64")
+    xs2 = [x * 0.5 for x in xs]
+    outs = [torch.empty_like(x) for x in xs]
+    outs2 = [torch.empty_like(x) for x in xs]
+    with fftu.BatchPlan(shapes, grids, "complex64", FORWARD) as bp:
+        want = [o.clone() for o in bp(xs)]
+        g = fftu.Graph(bp, xs, outs)
+        for rep in range(3):
+            bp(xs2, outs2)                       # rebinds the plan to other buffers
+            torch.cuda.synchronize()
+            snap = [o.clone() for o in outs2]
+            for o in outs:
+                o.fill_(float("nan"))
+            torch.cuda.synchronize()
+            g.launch()
+            torch.cuda.synchronize()
+            for i, (o, w) in enumerate(zip(outs, want)):
+                assert torch.equal(o, w), f"replay {rep}, member {i}"
+            for i, (o, s) in enumerate(zip(outs2, snap)):
+                assert torch.equal(o, s), f"replay {rep} wrote the eager outputs (member {i})"
+            again = bp(xs2, outs2)               # and eager calls after a replay rebind again
+            torch.cuda.synchronize()
+            for o, s in zip(again, snap):
+                assert torch.equal(o, s)
+        g.close()
+
+
+def test_batch_rebind_does_not_wait(torch):
+    """New buffers are bound in stream order: the call returns while earlier work
+    on the stream is still running."""
+    import paper_2203_11795_amd as fftu
+    shapes, grids = members(5, 17)
+    xs = [torch.ones(int(np.prod(s)), dtype=torch.complex64, device="cuda") for s in shapes]
+    outs = [torch.empty_like(x) for x in xs]
+    big = torch.zeros(512 ** 3, dtype=torch.complex128, device="cuda")
+    with fftu.BatchPlan(shapes, grids, "complex64", FORWARD) as bp, \
+            fftu.Plan((512, 512, 512), (4, 4, 4), "complex128", FORWARD) as slow:
+        bp(xs, outs)
+        torch.cuda.synchronize()
+        stream = torch.cuda.current_stream()
+        for _ in range(10):                      # about 20 ms of queued work
+            slow(big, big)
+        xs2 = [x.clone() for x in xs]            # enqueued after the transforms too
+        outs2 = [torch.empty_like(x) for x in xs]
+        bp(xs2, outs2)
+        busy = not stream.query()
+        torch.cuda.synchronize()
+        assert busy, "fftu_execute_batch waited for the stream"
+        for a, b in zip(outs, outs2):
+            assert torch.equal(a, b)
+
+
+def test_batch_rejects_bad_buffers(torch):
+    """Overlaps that would race inside the persistent kernel, and misaligned or
+    NULL pointers, are refused before anything is enqueued."""
+    import paper_2203_11795_amd as fftu
+    shapes, grids = [(16, 16, 16), (16, 32, 16)], [(2, 2, 2)] * 2
+    sizes = [int(np.prod(s)) for s in shapes]
+    pool = torch.zeros(4 * sum(sizes) + 16, dtype=torch.complex64, device="cuda")
+    base = pool.data_ptr()
+    es = 8
+    a0, a1 = base, base + sizes[0] * es
+    b0, b1 = a1 + sizes[1] * es, a1 + sizes[1] * es + sizes[0] * es
+    with fftu.BatchPlan(shapes, grids, "complex64", FORWARD) as bp:
+        bp.execute_ptrs([a0, a1], [b0, b1])             # disjoint: fine
+        bp.execute_ptrs([a0, a1], [a0, a1])             # in place: fine
+        torch.cuda.synchronize()
+        bad = {
+            "outputs overlap": ([a0, a1], [b0, b0 + 8 * es]),
+            "output over another input": ([a0, a1], [a1, b1]),
+            "partial in/out overlap": ([a0, a1], [a0 + es, b1]),
+            "misaligned": ([a0 + 4, a1], [b0, b1]),
+            "null": ([0, a1], [b0, b1]),
+        }
+        for name, (ins, outs) in bad.items():
+            with pytest.raises(fftu.FftuError) as err:
+                bp.execute_ptrs(ins, outs)
+            assert err.value.status == 1, name
+        with pytest.raises(ValueError):
+            bp([pool[:sizes[0]], pool[sizes[0]:sizes[0] + sizes[1]]], [pool[:sizes[0]], pool[:7]])
+        # a batch plan runs only through fftu_execute_batch
+        lib = fftu.load_library()
+        import ctypes
+        h = bp._h
+        for entry in ["fftu_execute", "fftu_stage_local_fft", "fftu_stage_twiddle", "fftu_stage_exchange",
+                      "fftu_stage_remaining_fft"]:
+            assert getattr(lib, entry)(h, ctypes.c_void_p(a0), ctypes.c_void_p(b0), None) == 1, entry
+        assert lib.fftu_execute_ws(h, ctypes.c_void_p(a0), ctypes.c_void_p(b0), ctypes.c_void_p(b1), None) == 1
+        torch.cuda.synchronize()

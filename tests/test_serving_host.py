@@ -71,3 +71,11 @@ def test_size_classes_and_lane_queues():
     assert serving.next_queue(2, 2, large, collections.deque()) is None
     assert serving.next_queue(0, 2, collections.deque(), small) is small   # an idle large lane takes small
     assert serving.next_queue(0, 0, large, small) is small                 # FIFO: no lanes
+
+
+def test_requests_larger_than_the_arena_are_refused_not_queued():
+    r = serving.Request(0, 0.0, (64, 64), "complex128", -1)      # 64 KiB per block
+    assert serving.fits_arena(r, 2 * 65536)
+    assert not serving.fits_arena(r, 2 * 65536 - 1)
+    odd = serving.Request(1, 0.0, (3, 5), "complex64", -1)        # 120 B, rounded up to one 256-byte block
+    assert serving.fits_arena(odd, 512) and not serving.fits_arena(odd, 511)
