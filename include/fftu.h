@@ -204,6 +204,29 @@ fftu_plan_t fftu_plan_external(int d, const int64_t n[], const int64_t p[], fftu
 fftu_status fftu_execute_ws(fftu_plan_t plan, const void *in, void *out, void *workspace, hipStream_t stream);
 
 /*
+ * For callers that cannot allocate device memory (code under stream capture,
+ * serving loops and harnesses that forbid hipMalloc): fftu_execute_ws with the
+ * library's own fixed workspace, a device array of FFTU_NOALLOC_MAX_BYTES that
+ * every device the library runs on holds from the time the library's code is
+ * loaded there until the process ends. The call allocates nothing (the plan's
+ * own workspace, if it has one, is not used); the caller passes the input and
+ * output as for fftu_execute. Results are bitwise those of fftu_execute_ws.
+ *
+ * Requirements: the plan's device is the current device (else
+ * FFTU_ERROR_INVALID_VALUE); N b <= FFTU_NOALLOC_MAX_BYTES, i.e. at most 4 Mi
+ * complex128 or 8 Mi complex64 elements (else FFTU_ERROR_OUT_OF_MEMORY, before
+ * anything is enqueued); not a batch plan (FFTU_ERROR_INVALID_VALUE). Buffer
+ * rules and the other errors as for fftu_execute_ws.
+ *
+ * Concurrency: every call on one device uses that device's one array, which
+ * keeps the last call's contents (nothing in it needs to start at zero). Calls
+ * whose work overlaps on one device race and give wrong results: enqueue them
+ * on one stream, or order them with events.
+ */
+#define FFTU_NOALLOC_MAX_BYTES (64u << 20)
+fftu_status fftu_execute_noalloc(fftu_plan_t plan, const void *in, void *out, hipStream_t stream);
+
+/*
  * The supersteps one at a time, for checking each against its definition.
  * All use the plan's direction for every weight and none applies 1/N.
  * Same buffer rules as fftu_execute, except fftu_stage_exchange, which needs

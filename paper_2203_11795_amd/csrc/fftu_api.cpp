@@ -2086,6 +2086,13 @@ fftu_status execute_with(fftu_plan_s *plan, const void *in, void *out, void *ws,
 
 }  // namespace
 
+namespace fftu {
+bool plan_is_batch(const fftu_plan_s *plan) { return plan->is_batch; }
+int plan_device(const fftu_plan_s *plan) { return plan->device; }
+size_t plan_workspace_bytes(const fftu_plan_s *plan) { return size_t(plan->grid.N) * plan->esize; }
+fftu_status record_status(fftu_status s) { return record(s); }
+}  // namespace fftu
+
 extern "C" {
 
 fftu_status fftu_timing_begin(fftu_plan_t plan, int max_calls)

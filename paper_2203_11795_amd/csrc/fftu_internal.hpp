@@ -372,4 +372,10 @@ hipError_t launch_long(Precision prec, const void *in, void *out, const PassDesc
 hipError_t launch_lastx(Precision prec, const void *in, void *out, const LastxDesc &lx, const void *table,
                         hipStream_t stream);
 
+// Plan facts for entry points outside fftu_api.cpp.
+bool plan_is_batch(const fftu_plan_s *plan);
+int plan_device(const fftu_plan_s *plan);                 // device the plan was made on
+size_t plan_workspace_bytes(const fftu_plan_s *plan);     // N b: the workspace one execution needs
+fftu_status record_status(fftu_status s);                 // sets fftu_last_error() of this thread
+
 }  // namespace fftu

@@ -18,13 +18,14 @@ INVERSE = 1
 C64 = 1
 C128 = 2
 MAX_DIMS = 8
+NOALLOC_MAX_BYTES = 64 << 20     # FFTU_NOALLOC_MAX_BYTES: the fixed workspace of fftu_execute_noalloc
 
 STATUS = {0: "FFTU_SUCCESS", 1: "FFTU_ERROR_INVALID_VALUE", 2: "FFTU_ERROR_NOT_DIVISIBLE",
           3: "FFTU_ERROR_UNSUPPORTED", 4: "FFTU_ERROR_OUT_OF_MEMORY", 5: "FFTU_ERROR_DEVICE"}
 
 # Every entry point declared in include/fftu.h.
 EXPORTS = ["fftu_version", "fftu_status_string", "fftu_last_error", "fftu_check", "fftu_describe", "fftu_plan",
-           "fftu_get_plan_info", "fftu_plan_device_bytes", "fftu_execute", "fftu_plan_external", "fftu_execute_ws",
+           "fftu_get_plan_info", "fftu_plan_device_bytes", "fftu_execute", "fftu_plan_external", "fftu_execute_ws", "fftu_execute_noalloc",
            "fftu_stage_local_fft",
            "fftu_stage_twiddle", "fftu_stage_exchange", "fftu_stage_remaining_fft", "fftu_timing_begin",
            "fftu_timing_end", "fftu_set_tuning", "fftu_get_tuning", "fftu_launch_name", "fftu_plan_batch", "fftu_execute_batch", "fftu_batch_error",
@@ -88,6 +89,8 @@ def load_library(path: str = LIB_PATH):
     lib.fftu_plan_external.argtypes = [ctypes.c_int, i64p, i64p, ctypes.c_int, ctypes.c_int]
     lib.fftu_execute_ws.restype = ctypes.c_int
     lib.fftu_execute_ws.argtypes = [vp, vp, vp, vp, vp]
+    lib.fftu_execute_noalloc.restype = ctypes.c_int
+    lib.fftu_execute_noalloc.argtypes = [vp, vp, vp, vp]
     lib.fftu_timing_begin.restype = ctypes.c_int
     lib.fftu_timing_begin.argtypes = [vp, ctypes.c_int]
     lib.fftu_timing_end.restype = ctypes.c_int
@@ -298,6 +301,17 @@ class Plan:
         if stream is None:
             stream = torch.cuda.current_stream(x.device)
         self.execute_ws_ptr(x.data_ptr(), out.data_ptr(), workspace.data_ptr(), int(stream.cuda_stream))
+        return out
+
+    def execute_noalloc(self, x, out, stream=None):
+        """out = F(x) with the library's fixed device workspace (fftu_execute_noalloc):
+        nothing is allocated, by the library or here."""
+        self._check_tensor(x, "input")
+        self._check_tensor(out, "output")
+        if stream is None:
+            import torch
+            stream = torch.cuda.current_stream(x.device)
+        self.execute_ptr(x.data_ptr(), out.data_ptr(), int(stream.cuda_stream), "fftu_execute_noalloc")
         return out
 
     def stage(self, name: str, x, out=None, stream=None):
