@@ -20,7 +20,16 @@
  * arrays are row-major, Section 3). With p = (1, ..., 1) this is the ordinary
  * row-major array.
  *
- * Requirements on a plan (Algorithm 2.3, Input): p_l^2 divides n_l for every l.
+ * Requirements on a plan (Algorithm 2.3, Input): p_l^2 divides n_l for every l;
+ * the transform then has one communication superstep. Grids beyond that
+ * (Section 2.3, after eq. (2.13): p_l | n_l but not p_l^2 | n_l for some l) take
+ * several supersteps through the group-cyclic distribution: per dimension, with
+ * m_l = n_l / p_l, level i handles sub-transforms of n_i points on groups of p_i
+ * processors (n_0 = n_l, p_0 = p_l; n_{i+1} = p_i, p_{i+1} = p_i / m_l, which
+ * needs m_l | p_i) until a level h has p_h^2 | n_h; the transform takes
+ * max_l (h_l + 1) supersteps. A grid whose chain fails (e.g. n_l = p_l > 1)
+ * gives FFTU_ERROR_NOT_DIVISIBLE. Such grids run on the mixed-radix kernels and
+ * have its limits (below), with lines of m_l and p_h points.
  * This implementation also requires 1 <= d <= FFTU_MAX_DIMS and either
  *   - every n_l and p_l a power of two, N < 2^40, n_l/p_l and p_l <= 2048
  *     (complex128) or 4096 (complex64); or
@@ -121,6 +130,7 @@ typedef struct {
     int32_t launches;         /* kernel launches of one fftu_execute */
     uint64_t workspace_bytes; /* device workspace owned by the plan */
     uint64_t table_bytes;     /* device twiddle table owned by the plan */
+    int32_t supersteps;       /* communication supersteps: 1 when every p_l^2 | n_l, more on group-cyclic grids */
 } fftu_plan_info;
 
 /* Library version string ("fftu <major>.<minor>"). */
@@ -241,6 +251,23 @@ fftu_status fftu_stage_local_fft(fftu_plan_t plan, const void *in, void *out, hi
 fftu_status fftu_stage_twiddle(fftu_plan_t plan, const void *in, void *out, hipStream_t stream);
 fftu_status fftu_stage_exchange(fftu_plan_t plan, const void *in, void *out, hipStream_t stream);
 fftu_status fftu_stage_remaining_fft(fftu_plan_t plan, const void *in, void *out, hipStream_t stream);
+
+/*
+ * The same for any plan, one step of one superstep at a time (the four calls
+ * above refuse plans with several supersteps). With H = supersteps:
+ *   part 0, phase c in [0, H]:  computation phase c's local FFTs (phase 0: every
+ *            local F_{m_l}; later phases: the next level's F_{m_l} of dimensions
+ *            with levels left, and the length-p_h FFTs of dimensions whose last
+ *            Put was superstep c - 1, along the local index s' (n_h/p_h^2) + t)
+ *   part 1, phase c in [0, H):  superstep c's twiddle omega_{n_i}^{u k} of each
+ *            dimension's level c (u: member of the group, k: local index), in place
+ *            of each element
+ *   part 2, phase c in [0, H):  superstep c's Put (data movement only; in != out)
+ * For H = 1 these are local_fft, twiddle, exchange and remaining_fft. Weights
+ * follow the plan's direction; none applies 1/N. INVALID_VALUE for a phase or
+ * part out of range, otherwise errors as for fftu_execute.
+ */
+fftu_status fftu_stage_superstep(fftu_plan_t plan, int phase, int part, const void *in, void *out, hipStream_t stream);
 
 /*
  * Per-kernel timing on the execution stream. After fftu_timing_begin(plan, K),

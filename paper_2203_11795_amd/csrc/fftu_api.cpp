@@ -57,6 +57,11 @@ struct fftu_plan_s {
     bool lastx = false;              // k_lastx: the innermost dimension's lines fused with the exchange
     std::vector<PassDesc> s0x;       // the other Superstep 0 passes, run before k_lastx
     fftu::LastxDesc lx{};
+    // grids beyond p_max (some p_l^2 not dividing n_l): group-cyclic levels, several supersteps
+    bool gc = false;
+    int gc_H = 0;                                       // communication supersteps
+    std::vector<std::vector<fftu::MixedPassDesc>> gphase;   // computation phases 0..H: local FFT passes
+    std::vector<fftu::GroupPutDesc> gput;                   // communication supersteps 0..H-1 (twiddle + Put)
     // per-kernel timing (fftu_timing_begin / fftu_timing_end)
     std::vector<std::string> launch_names;   // kernel of each launch of fftu_execute
     // batch plans (fftu_plan_batch)
@@ -148,6 +153,45 @@ int log_tile(fftu_dtype dt) { return dt == FFTU_C128 ? fftu::kLogTileF64 : fftu:
 int64_t max_len(fftu_dtype dt) { return int64_t(1) << log_tile(dt); }
 int log_wmax(fftu_dtype dt) { return dt == FFTU_C128 ? 5 : 6; }       // 512-byte column runs
 
+// The group-cyclic levels of one dimension (Section 2.3, the paragraph after
+// eq. (2.13)): level i transforms sub-transforms of n_i points on groups of p_i
+// processors; n_0 = n, p_0 = p, and while p_i^2 does not divide n_i the level's
+// m = n / p sub-transforms of each group go to groups of p_{i+1} = p_i / m
+// (which needs m | p_i) as sub-transforms of n_{i+1} = p_i points. Level h, the
+// first with p_h^2 | n_h, ends with Algorithm 2.2's own Put.
+struct GcLevels {
+    int h = 0;
+    int64_t m = 1;
+    int64_t n[fftu::kGcMaxLevels] = {};
+    int64_t p[fftu::kGcMaxLevels] = {};
+};
+
+bool gc_levels(int64_t n, int64_t p, GcLevels &lv)
+{
+    lv = GcLevels{};
+    if (p < 1 || n % p) return false;
+    lv.m = n / p;
+    int64_t ni = n, pi = p;
+    for (int i = 0; i < fftu::kGcMaxLevels; ++i) {
+        lv.n[i] = ni;
+        lv.p[i] = pi;
+        lv.h = i;
+        if ((ni / pi) % pi == 0) return true;
+        if (lv.m == 1 || pi % lv.m) return false;
+        ni = pi;
+        pi /= lv.m;
+    }
+    return false;
+}
+
+// Some dimension has p_l | n_l but not p_l^2 | n_l.
+bool plan_is_group_cyclic(int d, const int64_t n[], const int64_t p[])
+{
+    for (int l = 0; l < d; ++l)
+        if (p[l] >= 1 && n[l] % p[l] == 0 && (n[l] / p[l]) % p[l] != 0) return true;
+    return false;
+}
+
 fftu_status validate(int d, const int64_t n[], const int64_t p[], fftu_dtype dtype, fftu_direction direction)
 {
     if (d < 1 || !n || !p) return FFTU_ERROR_INVALID_VALUE;
@@ -156,9 +200,25 @@ fftu_status validate(int d, const int64_t n[], const int64_t p[], fftu_dtype dty
     if (d > FFTU_MAX_DIMS) return FFTU_ERROR_UNSUPPORTED;
     for (int l = 0; l < d; ++l)
         if (n[l] < 1 || p[l] < 1) return FFTU_ERROR_INVALID_VALUE;
-    // Algorithm 2.3, Input: p_l^2 | n_l.
+    // Algorithm 2.3, Input: p_l^2 | n_l. Otherwise (p_l | n_l only) the grid needs the
+    // group-cyclic levels of Section 2.3 (gc_levels).
     for (int l = 0; l < d; ++l)
-        if (n[l] % p[l] != 0 || (n[l] / p[l]) % p[l] != 0) return FFTU_ERROR_NOT_DIVISIBLE;
+        if (n[l] % p[l] != 0) return FFTU_ERROR_NOT_DIVISIBLE;
+    if (plan_is_group_cyclic(d, n, p)) {
+        int64_t N = 1, T = 1;
+        for (int l = 0; l < d; ++l) {
+            GcLevels lv;
+            if (!gc_levels(n[l], p[l], lv)) return FFTU_ERROR_NOT_DIVISIBLE;
+            if (!is_smooth(n[l])) return FFTU_ERROR_UNSUPPORTED;
+            if (n[l] / p[l] > max_mixed_len(dtype) || lv.p[lv.h] > max_mixed_len(dtype)) return FFTU_ERROR_UNSUPPORTED;
+            if (N > (int64_t(1) << 31) / n[l]) return FFTU_ERROR_UNSUPPORTED;
+            N *= n[l];
+            T = lcm64(T, n[l]);
+            if (T > (int64_t(1) << 24)) return FFTU_ERROR_UNSUPPORTED;
+        }
+        if (N >= (int64_t(1) << 31)) return FFTU_ERROR_UNSUPPORTED;
+        return FFTU_SUCCESS;
+    }
     bool all_pow2 = true;
     for (int l = 0; l < d; ++l) all_pow2 = all_pow2 && is_pow2(n[l]) && is_pow2(p[l]);
     if (all_pow2) {
@@ -894,6 +954,106 @@ void fill_info_mixed(const MixedPlan &mp, fftu_dtype dt, fftu_plan_info *info)
     info->launches = info->s0_kernels + (mp.fused ? 1 : info->s2_kernels);
     info->workspace_bytes = uint64_t(mp.g.N) * esize;
     info->table_bytes = uint64_t(mp.T) * esize;
+    info->supersteps = 1;
+}
+
+// Grids beyond p_max: every dimension's levels run side by side (Algorithm 2.3's
+// combination of Algorithm 2.2 per dimension), H = max_l (h_l + 1) communication
+// supersteps. Computation phase c: the local F_{m_l} of every dimension with
+// levels left (c <= h_l), and the length-p_h FFTs of every dimension whose last
+// Put was superstep c - 1 (local index s' q + t, lines along s'). Superstep c:
+// one k_gput with each dimension's Put of level c (none for finished dimensions).
+struct GcPlan {
+    int H = 0;
+    int64_t T = 1, N = 1, P = 1, M = 1;
+    std::vector<std::vector<fftu::MixedPassDesc>> phase;
+    std::vector<fftu::GroupPutDesc> put;
+};
+
+bool plan_gc(int d, const int64_t n[], const int64_t p[], fftu_dtype dt, GcPlan &gp)
+{
+    gp = GcPlan{};
+    GcLevels lv[fftu::kMaxDims];
+    int64_t m[fftu::kMaxDims];
+    for (int l = 0; l < d; ++l) {
+        if (!gc_levels(n[l], p[l], lv[l])) return false;
+        m[l] = n[l] / p[l];
+        gp.H = std::max(gp.H, lv[l].h + 1);
+        gp.N *= n[l];
+        gp.P *= p[l];
+        gp.T = lcm64(gp.T, n[l]);
+    }
+    gp.M = gp.N / gp.P;
+    for (int c = 0; c <= gp.H; ++c) {
+        std::vector<fftu::MixedPassDesc> ph;
+        for (int l = d - 1; l >= 0; --l) {
+            int64_t A = gp.P, B = 1;
+            for (int j = 0; j < l; ++j) A *= m[j];
+            for (int j = l + 1; j < d; ++j) B *= m[j];
+            int64_t L = 1;
+            if (c <= lv[l].h) {
+                L = m[l];                              // level c's local F_m
+            } else if (c == lv[l].h + 1) {
+                L = lv[l].p[lv[l].h];                  // level h's length-p_h FFTs
+                B *= m[l] / L;
+            }
+            if (L == 1) continue;
+            fftu::MixedPassDesc pd;
+            if (!make_mixed_pass(A, L, B, dt, gp.T, pd)) return false;
+            ph.push_back(pd);
+        }
+        gp.phase.push_back(ph);
+    }
+    for (int c = 0; c < gp.H; ++c) {
+        fftu::GroupPutDesc g{};
+        g.d = d;
+        g.N = gp.N;
+        g.M = gp.M;
+        g.T = gp.T;
+        g.twiddle = 1;
+        g.permute = 1;
+        g.scale = 1.0;
+        for (int l = 0; l < d; ++l) {
+            fftu::GroupPutDim &D = g.dim[l];
+            D.m = int32_t(m[l]);
+            D.p = int32_t(p[l]);
+            if (c > lv[l].h) continue;                 // mode 0: this dimension is done
+            D.mode = c < lv[l].h ? 1 : 2;
+            D.pi = int32_t(lv[l].p[c]);
+            D.ni = int32_t(lv[l].n[c]);
+            D.tstep = gp.T / lv[l].n[c];
+            if (D.mode == 1) {
+                D.pn = int32_t(lv[l].p[c] / m[l]);
+            } else {
+                D.q = int32_t(m[l] / lv[l].p[c]);
+                int64_t mh = 1;
+                for (int i = 0; i < lv[l].h; ++i) mh *= m[l];
+                D.mh = int32_t(mh);
+                D.h = lv[l].h;
+            }
+        }
+        gp.put.push_back(g);
+    }
+    return true;
+}
+
+void fill_info_gc(const GcPlan &gp, int d, fftu_dtype dt, fftu_plan_info *info)
+{
+    const uint64_t esize = dt == FFTU_C128 ? 16 : 8;
+    *info = fftu_plan_info{};
+    info->d = d;
+    info->N = gp.N;
+    info->P = gp.P;
+    info->M = gp.M;
+    info->s0_kernels = int32_t(gp.phase[0].size());
+    info->exchange_fused = 0;
+    int rest = gp.H;
+    for (size_t c = 1; c < gp.phase.size(); ++c) rest += int(gp.phase[c].size());
+    info->s2_kernels = rest;
+    info->launches = info->s0_kernels + rest;
+    info->supersteps = gp.H;
+    info->workspace_bytes = uint64_t(gp.N) * esize;
+    info->table_bytes = uint64_t(gp.T) * esize;
 }
 
 // The unfused exchange of a grid with every q_l = 1 (m = p, so M = P) is a transpose
@@ -934,6 +1094,7 @@ void fill_info(const Geometry &G, const std::vector<PassDesc> &s0, bool fused, s
     if (lastx) info->exchange_fused = 2;   // s0 holds the passes before k_lastx
     info->workspace_bytes = uint64_t(info->N) * esize;
     info->table_bytes = (uint64_t(1) << G.lognmax) * esize;
+    info->supersteps = 1;
 }
 
 // Profiler name of the kernel that runs a pass (matches the template arguments).
@@ -1304,6 +1465,65 @@ fftu_plan_s *build_mixed_plan(int d, const int64_t n[], const int64_t p[], fftu_
     return pl;
 }
 
+fftu_plan_s *build_gc_plan(int d, const int64_t n[], const int64_t p[], fftu_dtype dtype, fftu_direction direction,
+                           bool external, int device)
+{
+    GcPlan gp;
+    if (!plan_gc(d, n, p, dtype, gp)) {
+        record(FFTU_ERROR_UNSUPPORTED);
+        return nullptr;
+    }
+    fftu_plan_s *pl = new (std::nothrow) fftu_plan_s();
+    if (!pl) {
+        record(FFTU_ERROR_OUT_OF_MEMORY);
+        return nullptr;
+    }
+    pl->d = d;
+    for (int l = 0; l < d; ++l) {
+        pl->n[l] = n[l];
+        pl->p[l] = p[l];
+    }
+    pl->dtype = dtype;
+    pl->dir = direction;
+    pl->prec = dtype == FFTU_C128 ? Precision::F64 : Precision::F32;
+    pl->esize = dtype == FFTU_C128 ? 16 : 8;
+    pl->device = device;
+    pl->external = external;
+    pl->gc = true;
+    pl->gc_H = gp.H;
+    pl->gphase = gp.phase;
+    pl->gput = gp.put;
+    pl->table_T = gp.T;
+    pl->grid.N = gp.N;
+    pl->grid.M = gp.M;
+    pl->grid.d = d;
+    const std::string t = dtype == FFTU_C128 ? "double" : "float";
+    for (int c = 0; c <= gp.H; ++c) {
+        for (size_t i = 0; i < gp.phase[size_t(c)].size(); ++i) pl->launch_names.push_back("fftu::k_mline<" + t + ">");
+        if (c < gp.H) pl->launch_names.push_back("fftu::k_gput<" + t + ">");
+    }
+    pl->launches = int(pl->launch_names.size());
+    hipError_t e = hipSuccess;
+    if (external) {
+        e = shared_table_exact(device, dtype, gp.T, &pl->table);
+    } else {
+        pl->table_bytes = uint64_t(gp.T) * pl->esize;
+        pl->ws_bytes = uint64_t(gp.N) * pl->esize;
+        e = upload_table_general(&pl->table, gp.T, dtype);
+        if (e == hipSuccess) e = hipMalloc(&pl->ws, pl->ws_bytes);
+    }
+    if (e != hipSuccess) {
+        const fftu_status st = from_hip(e);
+        if (!external && pl->table) (void)hipFree(pl->table);
+        if (pl->ws) (void)hipFree(pl->ws);
+        delete pl;
+        record(st);
+        return nullptr;
+    }
+    record(FFTU_SUCCESS);
+    return pl;
+}
+
 fftu_plan_s *build_plan(int d, const int64_t n[], const int64_t p[], fftu_dtype dtype, fftu_direction direction,
                         bool external)
 {
@@ -1317,6 +1537,7 @@ fftu_plan_s *build_plan(int d, const int64_t n[], const int64_t p[], fftu_dtype 
         record(FFTU_ERROR_DEVICE);
         return nullptr;
     }
+    if (plan_is_group_cyclic(d, n, p)) return build_gc_plan(d, n, p, dtype, direction, external, device);
     if (plan_is_mixed(d, n, p)) return build_mixed_plan(d, n, p, dtype, direction, external, device);
     Geometry G = geometry(d, n, p);
     void *shared = nullptr;
@@ -1457,6 +1678,12 @@ fftu_status fftu_describe(int d, const int64_t n[], const int64_t p[], fftu_dtyp
     fftu_status s = validate(d, n, p, dtype, direction);
     if (s != FFTU_SUCCESS) return record(s);
     if (!info) return record(FFTU_ERROR_INVALID_VALUE);
+    if (plan_is_group_cyclic(d, n, p)) {
+        GcPlan gp;
+        if (!plan_gc(d, n, p, dtype, gp)) return record(FFTU_ERROR_UNSUPPORTED);
+        fill_info_gc(gp, d, dtype, info);
+        return record(FFTU_SUCCESS);
+    }
     if (plan_is_mixed(d, n, p)) {
         MixedPlan mp;
         if (!plan_mixed(d, n, p, dtype, mp)) return record(FFTU_ERROR_UNSUPPORTED);
@@ -1502,7 +1729,8 @@ fftu_status build_batch_worklist(int count, const int d[], const int64_t *const 
     for (int f = 0; f < count; ++f) {
         fftu_status s = validate(d[f], n[f], p[f], dtype, direction);
         if (s != FFTU_SUCCESS) return s;
-        if (plan_is_mixed(d[f], n[f], p[f])) return FFTU_ERROR_UNSUPPORTED;   // batches: powers of two only
+        // batches: powers of two with one exchange only
+        if (plan_is_mixed(d[f], n[f], p[f]) || plan_is_group_cyclic(d[f], n[f], p[f])) return FFTU_ERROR_UNSUPPORTED;
     }
     const size_t esize = dtype == FFTU_C128 ? 16 : 8;
     const int inv = direction == FFTU_INVERSE ? 1 : 0;
@@ -1822,6 +2050,18 @@ void fftu_graph_destroy(fftu_graph_t graph)
 fftu_status fftu_get_plan_info(fftu_plan_t plan, fftu_plan_info *info)
 {
     if (!plan || !info) return record(FFTU_ERROR_INVALID_VALUE);
+    if (plan->gc) {
+        GcPlan gp;
+        gp.H = plan->gc_H;
+        gp.T = plan->table_T;
+        gp.N = plan->grid.N;
+        gp.M = plan->grid.M;
+        gp.P = plan->grid.N / plan->grid.M;
+        gp.phase = plan->gphase;
+        gp.put = plan->gput;
+        fill_info_gc(gp, plan->d, plan->dtype, info);
+        return record(FFTU_SUCCESS);
+    }
     if (plan->mixed) {
         MixedPlan mp;
         mp.s0 = plan->ms0;
@@ -1939,7 +2179,7 @@ fftu_status run_mixed_passes(const fftu_plan_s *pl, const std::vector<fftu::Mixe
 {
     if (passes.empty()) {
         if (in != out)
-            return from_hip(hipMemcpyAsync(out, in, size_t(pl->mg.N) * pl->esize, hipMemcpyDeviceToDevice, stream));
+            return from_hip(hipMemcpyAsync(out, in, size_t(pl->grid.N) * pl->esize, hipMemcpyDeviceToDevice, stream));
         return FFTU_SUCCESS;
     }
     const void *src = in;
@@ -1997,11 +2237,50 @@ fftu_status execute_mixed(fftu_plan_s *plan, const void *in, void *out, void *ws
     return from_hip(fftu::launch_pointwise(plan->prec, out, mul, out, plan->mg.N, 1.0, stream));
 }
 
+// Grids beyond p_max: computation phase 0 (reads `in`), then H times a k_gput
+// (twiddle and Put, out of place) and the next phase's passes (in place). The
+// buffers alternate between `out` and the workspace so that the last Put lands
+// in `out`: phase c runs in `out` when H - c is even.
+fftu_status execute_gc(fftu_plan_s *plan, const void *in, void *out, void *ws, hipStream_t stream, const void *mul,
+                       Marker &mk)
+{
+    const int inv = plan->dir == FFTU_INVERSE ? 1 : 0;
+    const double scale = inv ? 1.0 / double(plan->grid.N) : 1.0;
+    const int H = plan->gc_H;
+    auto buf = [&](int c) -> void * { return ((H - c) % 2 == 0) ? out : ws; };
+    const bool last_empty = plan->gphase[size_t(H)].empty();
+    fftu_status s = run_mixed_passes(plan, plan->gphase[0], in, buf(0), inv, 0, 1.0, stream, &mk);
+    if (s != FFTU_SUCCESS) return s;
+    for (int c = 0; c < H; ++c) {
+        fftu::GroupPutDesc g = plan->gput[size_t(c)];
+        g.conj_in = (c == 0 && plan->gphase[0].empty()) ? inv : 0;
+        g.conj_out = 0;
+        g.scale = 1.0;
+        if (c == H - 1 && last_empty) {
+            g.conj_out = inv;
+            g.scale = scale;
+        }
+        hipError_t e = fftu::launch_gput(plan->prec, buf(c), buf(c + 1), g, plan->table, stream);
+        if (e != hipSuccess) return from_hip(e);
+        mk.mark();
+        const bool last = c + 1 == H;
+        s = run_mixed_passes(plan, plan->gphase[size_t(c + 1)], buf(c + 1), buf(c + 1), 0, last ? inv : 0,
+                             last ? scale : 1.0, stream, &mk);
+        if (s != FFTU_SUCCESS) return s;
+    }
+    if (!mul) return FFTU_SUCCESS;
+    return from_hip(fftu::launch_pointwise(plan->prec, out, mul, out, plan->grid.N, 1.0, stream));
+}
+
 fftu_status execute_with(fftu_plan_s *plan, const void *in, void *out, void *ws, hipStream_t stream, const void *mul)
 {
     fftu_status s = check_exec_args(plan, in, out);
     if (s != FFTU_SUCCESS) return s;
     Marker mk(plan, stream);
+    if (plan->gc) {
+        mk.mark();
+        return execute_gc(plan, in, out, ws, stream, mul, mk);
+    }
     if (plan->mixed) {
         mk.mark();
         return execute_mixed(plan, in, out, ws, stream, mul, mk);
@@ -2153,6 +2432,7 @@ fftu_status fftu_stage_local_fft(fftu_plan_t plan, const void *in, void *out, hi
 {
     fftu_status s = check_exec_args(plan, in, out);
     if (s != FFTU_SUCCESS) return record(s);
+    if (plan->gc) return record(FFTU_ERROR_INVALID_VALUE);   // several supersteps: fftu_stage_superstep
     const int inv = plan->dir == FFTU_INVERSE ? 1 : 0;
     if (plan->mixed) return record(run_mixed_passes(plan, plan->ms0, in, out, inv, inv, 1.0, stream));
     return record(run_passes(plan, plan->s0, in, out, inv, inv, 1.0, stream));
@@ -2162,6 +2442,7 @@ fftu_status fftu_stage_twiddle(fftu_plan_t plan, const void *in, void *out, hipS
 {
     fftu_status s = check_exec_args(plan, in, out);
     if (s != FFTU_SUCCESS) return record(s);
+    if (plan->gc) return record(FFTU_ERROR_INVALID_VALUE);   // several supersteps: fftu_stage_superstep
     if (plan->mixed) {
         fftu::MixedGridDesc mg = plan->mg;
         mg.conj_in = mg.conj_out = plan->dir == FFTU_INVERSE ? 1 : 0;
@@ -2177,6 +2458,7 @@ fftu_status fftu_stage_exchange(fftu_plan_t plan, const void *in, void *out, hip
 {
     fftu_status s = check_exec_args(plan, in, out);
     if (s != FFTU_SUCCESS) return record(s);
+    if (plan->gc) return record(FFTU_ERROR_INVALID_VALUE);   // several supersteps: fftu_stage_superstep
     if (in == out) return record(FFTU_ERROR_INVALID_VALUE);
     if (plan->mixed) {
         fftu::MixedGridDesc mg = plan->mg;
@@ -2192,9 +2474,38 @@ fftu_status fftu_stage_remaining_fft(fftu_plan_t plan, const void *in, void *out
 {
     fftu_status s = check_exec_args(plan, in, out);
     if (s != FFTU_SUCCESS) return record(s);
+    if (plan->gc) return record(FFTU_ERROR_INVALID_VALUE);   // several supersteps: fftu_stage_superstep
     const int inv = plan->dir == FFTU_INVERSE ? 1 : 0;
     if (plan->mixed) return record(run_mixed_passes(plan, plan->ms2, in, out, inv, inv, 1.0, stream));
     return record(run_passes(plan, plan->s2, in, out, inv, inv, 1.0, stream));
+}
+
+fftu_status fftu_stage_superstep(fftu_plan_t plan, int phase, int part, const void *in, void *out, hipStream_t stream)
+{
+    fftu_status s = check_exec_args(plan, in, out);
+    if (s != FFTU_SUCCESS) return record(s);
+    const int H = plan->gc ? plan->gc_H : 1;
+    const bool ok = (part == 0 && phase >= 0 && phase <= H) || ((part == 1 || part == 2) && phase >= 0 && phase < H);
+    if (!ok) return record(FFTU_ERROR_INVALID_VALUE);
+    if (!plan->gc) {
+        // one superstep: Algorithm 2.3's stages
+        if (part == 0) return phase == 0 ? fftu_stage_local_fft(plan, in, out, stream)
+                                         : fftu_stage_remaining_fft(plan, in, out, stream);
+        return part == 1 ? fftu_stage_twiddle(plan, in, out, stream) : fftu_stage_exchange(plan, in, out, stream);
+    }
+    const int inv = plan->dir == FFTU_INVERSE ? 1 : 0;
+    if (part == 0) return record(run_mixed_passes(plan, plan->gphase[size_t(phase)], in, out, inv, inv, 1.0, stream));
+    fftu::GroupPutDesc g = plan->gput[size_t(phase)];
+    g.scale = 1.0;
+    if (part == 1) {
+        g.permute = 0;                  // the twiddle alone, element by element
+        g.conj_in = g.conj_out = inv;
+    } else {
+        if (in == out) return record(FFTU_ERROR_INVALID_VALUE);
+        g.twiddle = 0;                  // the Put alone: pure data movement
+        g.conj_in = g.conj_out = 0;
+    }
+    return record(from_hip(fftu::launch_gput(plan->prec, in, out, g, plan->table, stream)));
 }
 
 void fftu_destroy(fftu_plan_t plan)

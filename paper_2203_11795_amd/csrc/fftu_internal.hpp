@@ -249,6 +249,33 @@ struct MixedGridDesc {
     const void *mul;           // k_mexchange: null, or N elements in the output layout to multiply by
 };
 
+// Grids beyond p_max (some p_l^2 not dividing n_l): the group-cyclic levels of
+// each dimension and the Put of one communication superstep (fftu_gcyclic.hip).
+// Level i of dimension l works on sub-transforms of n_i points, each held by a
+// group of p_i processors (p_0 = p_l, n_0 = n_l, n_{i+1} = p_i, p_{i+1} = p_i / m_l);
+// the last level h has p_h^2 | n_h.
+constexpr int kGcMaxLevels = 32;
+struct GroupPutDim {
+    int32_t mode;          // 0: nothing moves along this dimension; 1: Put of a level below h; 2: Put of level h
+    int32_t m, p;          // local side m_l and grid side p_l
+    int32_t pi;            // group size p_i of the level
+    int32_t pn;            // mode 1: p_{i+1} = p_i / m
+    int32_t q;             // mode 2: m / p_h
+    int32_t mh;            // mode 2: m^h, groups of the last level
+    int32_t h;             // mode 2: base-m digits of a group number
+    int32_t ni;            // n_i: the twiddle is omega_{n_i}^{u k}
+    int32_t reserved;
+    int64_t tstep;         // T / n_i
+};
+struct GroupPutDesc {
+    int32_t d;
+    int32_t twiddle;       // multiply by the level's twiddle of the source element
+    int32_t permute;       // move the element (0: the twiddle alone, in place of the source)
+    int32_t conj_in, conj_out;
+    int64_t N, M, T;
+    double scale;
+    GroupPutDim dim[kMaxDims];
+};
 // k_mexchange: P sources of 64 local indices in LDS, grid sides of one radix stage.
 constexpr int64_t kMexMaxP = 64;
 constexpr int kMexThreads = 512;
@@ -371,6 +398,9 @@ hipError_t launch_long(Precision prec, const void *in, void *out, const PassDesc
                        hipStream_t stream);
 hipError_t launch_lastx(Precision prec, const void *in, void *out, const LastxDesc &lx, const void *table,
                         hipStream_t stream);
+// One communication superstep of a group-cyclic plan (fftu_gcyclic.hip); in != out when g.permute.
+hipError_t launch_gput(Precision prec, const void *in, void *out, const GroupPutDesc &g, const void *table,
+                       hipStream_t stream);
 
 // Plan facts for entry points outside fftu_api.cpp.
 bool plan_is_batch(const fftu_plan_s *plan);

@@ -27,7 +27,7 @@ STATUS = {0: "FFTU_SUCCESS", 1: "FFTU_ERROR_INVALID_VALUE", 2: "FFTU_ERROR_NOT_D
 EXPORTS = ["fftu_version", "fftu_status_string", "fftu_last_error", "fftu_check", "fftu_describe", "fftu_plan",
            "fftu_get_plan_info", "fftu_plan_device_bytes", "fftu_execute", "fftu_plan_external", "fftu_execute_ws", "fftu_execute_noalloc",
            "fftu_stage_local_fft",
-           "fftu_stage_twiddle", "fftu_stage_exchange", "fftu_stage_remaining_fft", "fftu_timing_begin",
+           "fftu_stage_twiddle", "fftu_stage_exchange", "fftu_stage_remaining_fft", "fftu_stage_superstep", "fftu_timing_begin",
            "fftu_timing_end", "fftu_set_tuning", "fftu_get_tuning", "fftu_launch_name", "fftu_plan_batch", "fftu_execute_batch", "fftu_batch_error",
            "fftu_graph_capture", "fftu_graph_launch", "fftu_graph_destroy", "fftu_fill_uniform", "fftu_plan_convolution",
            "fftu_execute_convolution", "fftu_pointwise_mul", "fftu_destroy"]
@@ -45,7 +45,8 @@ class PlanInfo(ctypes.Structure):
     _fields_ = [("d", ctypes.c_int32), ("N", ctypes.c_int64), ("P", ctypes.c_int64), ("M", ctypes.c_int64),
                 ("s0_kernels", ctypes.c_int32), ("exchange_fused", ctypes.c_int32),
                 ("s2_kernels", ctypes.c_int32), ("launches", ctypes.c_int32),
-                ("workspace_bytes", ctypes.c_uint64), ("table_bytes", ctypes.c_uint64)]
+                ("workspace_bytes", ctypes.c_uint64), ("table_bytes", ctypes.c_uint64),
+                ("supersteps", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -85,6 +86,8 @@ def load_library(path: str = LIB_PATH):
         fn = getattr(lib, name)
         fn.restype = ctypes.c_int
         fn.argtypes = [vp, vp, vp, vp]
+    lib.fftu_stage_superstep.restype = ctypes.c_int
+    lib.fftu_stage_superstep.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, vp, vp]
     lib.fftu_plan_external.restype = vp
     lib.fftu_plan_external.argtypes = [ctypes.c_int, i64p, i64p, ctypes.c_int, ctypes.c_int]
     lib.fftu_execute_ws.restype = ctypes.c_int
@@ -319,6 +322,22 @@ class Plan:
         if name not in ("local_fft", "twiddle", "exchange", "remaining_fft"):
             raise ValueError(f"unknown stage {name!r}")
         return self._run(f"fftu_stage_{name}", x, out, stream)
+
+    def superstep(self, phase: int, part: int, x, out=None, stream=None):
+        """One step of the transform (fftu_stage_superstep): part 0 = computation
+        phase `phase`'s local FFTs, 1 = superstep `phase`'s twiddle, 2 = its Put."""
+        import torch
+        self._check_tensor(x, "input")
+        if out is None:
+            out = torch.empty_like(x)
+        self._check_tensor(out, "output")
+        if stream is None:
+            stream = torch.cuda.current_stream(x.device)
+        st = self._lib.fftu_stage_superstep(self._h, int(phase), int(part), ctypes.c_void_p(x.data_ptr()),
+                                            ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(int(stream.cuda_stream)))
+        if st != 0:
+            raise FftuError(st, "fftu_stage_superstep")
+        return out
 
     # -- per-kernel timing with HIP events on the execution stream
     def timing_begin(self, max_calls: int) -> None:

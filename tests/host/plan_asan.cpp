@@ -73,6 +73,23 @@ hipError_t launch_lastx(Precision, const void *, void *, const LastxDesc &lx, co
     return hipSuccess;
 }
 hipError_t launch_batch_reset(const BatchDesc &, hipStream_t) { return hipSuccess; }
+hipError_t launch_gput(Precision, const void *in, void *out, const GroupPutDesc &g, const void *, hipStream_t)
+{
+    if (g.d < 1 || g.d > kMaxDims || g.N < 1 || g.M < 1 || g.T < 1 || (g.permute && in == out)) std::abort();
+    int64_t P = 1, M = 1;
+    for (int l = 0; l < g.d; ++l) {
+        const GroupPutDim &D = g.dim[l];
+        if (D.m < 1 || D.p < 1 || D.mode < 0 || D.mode > 2) std::abort();
+        if (D.mode != 0 && (D.pi < 1 || D.p % D.pi || D.ni != D.pi * D.m || g.T % D.ni || D.tstep != g.T / D.ni))
+            std::abort();
+        if (D.mode == 1 && D.pn * D.m != D.pi) std::abort();
+        if (D.mode == 2 && (D.q * D.pi != D.m || int64_t(D.mh) * D.pi != D.p)) std::abort();
+        P *= D.p;
+        M *= D.m;
+    }
+    if (M != g.M || P * M != g.N) std::abort();
+    return hipSuccess;
+}
 hipError_t launch_batch_bind(BatchBind *, const BindChunk &c, hipStream_t)
 {
     if (c.count < 1 || c.count > kBindChunk || c.first < 0) std::abort();
@@ -244,6 +261,9 @@ int main()
         {{1024, 64}, {32, 8}}, {{64, 64, 64}, {8, 8, 8}},
         // mixed radix (factors 2, 3, 5, 7), and one side with a factor 11 (unsupported)
         {{60, 60}, {2, 2}}, {{49, 27, 8}, {7, 3, 2}}, {{1000}, {10}}, {{126, 12, 1}, {3, 2, 1}}, {{44, 12}, {2, 2}},
+        // grids beyond p_max: group-cyclic levels, several supersteps
+        {{512, 512, 512}, {32, 32, 32}}, {{16, 16}, {8, 2}}, {{1024}, {64}}, {{64, 64, 64}, {16, 16, 8}},
+        {{8, 27}, {4, 9}}, {{16}, {8}},
     };
     int bad = 0;
     for (const Case &c : cases) {

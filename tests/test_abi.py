@@ -45,8 +45,11 @@ def test_version_and_status_strings():
     ((8,), (2,), 0),
     ((1,), (1,), 0),
     ((16,), (4,), 0),            # p^2 = n: q = 1
-    ((8,), (4,), 2),             # 16 does not divide 8
-    ((32, 32), (2, 8), 2),
+    ((8,), (4,), 0),             # 16 does not divide 8: group-cyclic levels (8 over 4, then 4 over 2)
+    ((32, 32), (2, 8), 0),       # 32 over 8, then 8 over 2
+    ((8,), (8,), 2),             # one element per processor: no group-cyclic chain
+    ((12,), (6,), 2),            # 12 over 6 (m = 2), then 6 over 3: 2 does not divide 3
+    ((16,), (3,), 2),            # 3 does not divide 16
     ((12,), (2,), 0),            # mixed radix: 12 = 4 * 3
     ((60, 36), (2, 3), 0),
     ((44,), (2,), 3),            # p^2 | n holds, but 11 is not a radix of the mixed path
@@ -77,7 +80,8 @@ def test_check_rejects_bad_enums_and_null():
 
 def test_p_max_examples():
     """eq. (2.13) and the examples after it: the largest grid with one all-to-all is
-    accepted, and doubling any side of it is rejected as not divisible."""
+    planned with one superstep, and doubling any side of it needs more than one
+    (the group-cyclic levels) or is refused."""
     for line in open(os.path.join(GOLDEN, "pmax_examples.txt")):
         if line.startswith("#") or not line.strip():
             continue
@@ -93,10 +97,15 @@ def test_p_max_examples():
         assert prod == int(pmax_s)
         st = fftu.check(n, grid)
         assert st in (0, 3)     # 3 only where a local length exceeds one tile (2^24 x 64)
+        if st == 0:
+            assert fftu.describe(n, grid)["supersteps"] == 1
         for l in range(len(n)):
             bigger = list(grid)
             bigger[l] *= 2
-            assert fftu.check(n, bigger) == 2
+            st = fftu.check(n, bigger)
+            assert st in (0, 3)     # 3: group-cyclic lines beyond the mixed-radix tile (2^24 x 64)
+            if st == 0:
+                assert fftu.describe(n, bigger)["supersteps"] == 2
 
 
 @pytest.mark.parametrize("n,p,dtype,s0,fused,launches", [
@@ -129,13 +138,26 @@ def test_describe(n, p, dtype, s0, fused, launches):
     assert info["N"] == N and info["P"] == P and info["M"] == N // P
     assert info["s0_kernels"] == s0 and info["exchange_fused"] == fused and info["launches"] == launches
     assert info["workspace_bytes"] == N * (16 if dtype == "complex128" else 8)
+    assert info["supersteps"] == 1
     with pytest.raises(fftu.FftuError):
-        fftu.describe((8,), (4,))
+        fftu.describe((8,), (8,))
+
+
+@pytest.mark.parametrize("n,p,supersteps,launches", [
+    ((8,), (4,), 2, 5),                       # F_2, Put, F_2, Put, F_2
+    ((512, 512, 512), (32, 32, 32), 2, 11),   # 3 local passes, Put, 3 passes, Put, 3 passes of length 2
+    ((16, 16), (8, 2), 3, 9),
+    ((1024,), (64,), 2, 5),
+])
+def test_describe_group_cyclic(n, p, supersteps, launches):
+    info = fftu.describe(n, p, "complex128")
+    assert info["supersteps"] == supersteps and info["exchange_fused"] == 0 and info["launches"] == launches
 
 
 def test_info_struct_layout_matches_header():
-    # int32 d, int64 N, P, M, 4 x int32, 2 x uint64
-    assert ctypes.sizeof(binding.PlanInfo) == 4 + 4 + 8 * 3 + 4 * 4 + 8 * 2
+    # int32 d, int64 N, P, M, 4 x int32, 2 x uint64, int32 supersteps (+ tail padding to 8)
+    assert ctypes.sizeof(binding.PlanInfo) == 4 + 4 + 8 * 3 + 4 * 4 + 8 * 2 + 8
+    assert binding.PlanInfo.supersteps.offset == 4 + 4 + 8 * 3 + 4 * 4 + 8 * 2
 
 
 def test_tuning_knobs_roundtrip_and_ranges():
