@@ -101,6 +101,41 @@ def ideal_passes(n, p, esize, lds=160 * 1024):
     return groups + 1
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_single_thread(np, oracle, synth, X, flops):
+    """The oracle on one host thread: the headline array once, and the 64^3 small
+    case (median of 3) on one thread and on all. (The oracle's thread count is
+    process-wide state: the last call restores the full count.)"""
+    nt_all = oracle.max_threads()
+    t0 = time.perf_counter()
+    oracle.fft_axes(X, range(X.ndim), oracle.FORWARD, nthreads=1)
+    t1 = time.perf_counter() - t0
+    Xs = oracle.from_cyclic(synth.uniform_complex(64 ** 3, 1), (64, 64, 64), (2, 2, 2))
+    fs = 5.0 * 64 ** 3 * math.log2(64 ** 3)
+    small = {}
+    for label, nt in (("1_thread", 1), ("all_threads", nt_all)):
+        ts = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            oracle.fft_axes(Xs, range(3), oracle.FORWARD, nthreads=nt)
+            ts.append(time.perf_counter() - t0)
+        small[label] = {"median_s": round(float(np.median(ts)), 5), "GFLOPs": round(fs / float(np.median(ts)) / 1e9, 3),
+                        "threads": nt}
+    return {"single_thread": {"value": round(flops / t1 / 1e9, 3), "unit": "GFLOP/s", "cores": 1,
+                              "sample": f"the same transform on one thread: {t1:.2f} s"},
+            "small_64cube": small}
+
+
 def run_batch(args, torch, np, fftu, synth, with_oracle):
     """The batch workload: 256 uneven 3-D complex64 transforms on 2x2x2 grids."""
     from paper_2203_11795_amd import autotune
@@ -322,12 +357,113 @@ def run_mixed(args, torch, np, fftu, synth, with_oracle):
     return res
 
 
+def run_group_cyclic(args, torch, np, fftu, synth, with_oracle):
+    """A grid beyond p_max = sqrt(N): 512^3 complex128 over 32^3 virtual processors
+    (P = 32768 > 11585), where p_l^2 does not divide n_l, so the transform takes two
+    communication supersteps through the group-cyclic distribution; per-kernel
+    times from HIP events, beside the one-superstep 4^3 plan of the same array."""
+    n, p = (512, 512, 512), (32, 32, 32)
+    N = math.prod(n)
+    esize = 16
+    dev = torch.device("cuda:0")
+    log("[bench] group-cyclic 512^3 over 32^3: generating input")
+    D = synth.uniform_complex(N, 8, np.complex128)
+    x = torch.from_numpy(D).to(dev)
+    out = torch.empty_like(x)
+    plan = fftu.Plan(n, p, "complex128", fftu.FORWARD)
+    info = plan.info()
+    stream = torch.cuda.current_stream(dev)
+    steps = max(3, args.steps // 2)
+    for _ in range(args.warmup):
+        plan(x, out, stream=stream)
+    torch.cuda.synchronize()
+    plan.timing_begin(steps)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        plan(x, out, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    per_launch, _ = plan.timing_end()
+    names = plan.launch_names()
+    alg = 2.0 * N * esize
+    flops = 5.0 * N * math.log2(N)
+    per_sym = {}
+    for k, t in zip(names, per_launch):
+        tot, cnt = per_sym.get(k, (0.0, 0))
+        per_sym[k] = (tot + t, cnt + 1)
+    dom = max(per_sym, key=lambda k: per_sym[k][0])
+    dom_ms = per_sym[dom][0] / per_sym[dom][1]
+    res = {"workload": "512x512x512 complex128 forward DFT, 32x32x32 virtual grid (P = 32768 > sqrt(N)): "
+                       "group-cyclic levels, two communication supersteps",
+           "ms_per_transform": round(ms, 4), "GFLOPs": round(flops / (ms * 1e-3) / 1e9, 1),
+           "supersteps": info["supersteps"], "launches": info["launches"],
+           "roofline": {"bound": "hbm", "kernel": dom, "avg_launch_ms": round(dom_ms, 4),
+                        "algorithmic_bytes_per_launch": alg,
+                        "achieved": round(alg / (dom_ms * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(alg / (dom_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                        "traffic": measured_traffic("512cube_gc", dom)},
+           "hbm_roofline_frac_transform": round(info["launches"] * alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+           "kernels": [{"kernel": k, "avg_ms": round(t, 4), "GBps_alg": round(alg / (t * 1e-3) / 1e9, 1)}
+                       for k, t in zip(names, per_launch)]}
+    if with_oracle:
+        import oracle
+        X = oracle.from_cyclic(D, n, p)
+        ks = [(0, 0, 0), (1, 2, 3), (511, 256, 17), (100, 333, 451)]
+        flat = [int(np.ravel_multi_index(k, n)) for k in ks]
+        want = oracle.dft_points(X, flat)
+        got = oracle.from_cyclic(out.cpu().numpy(), n, p).reshape(-1)[flat]
+        res["sampled_max_rel_error_vs_oracle"] = float(np.abs(got - want).max() / np.abs(want).max())
+    plan.close()
+    log(f"[bench] group-cyclic 512^3 over 32^3: {ms:.3f} ms, {res['GFLOPs']} GFLOP/s")
+    return res
+
+
+def cyclic_positions(np, idx, n, p):
+    """Buffer positions of natural multi-indices idx[:, l] in the cyclic layout
+    (processor rank row-major over s = j mod p, then the local index j div p)."""
+    idx = np.asarray(idx, dtype=np.int64)
+    rank = np.zeros(len(idx), dtype=np.int64)
+    lin = np.zeros(len(idx), dtype=np.int64)
+    for l, (nl, pl) in enumerate(zip(n, p)):
+        rank = rank * pl + idx[:, l] % pl
+        lin = lin * (nl // pl) + idx[:, l] // pl
+    return rank * (math.prod(n) // math.prod(p)) + lin
+
+
+def sparse_forward_check(np, torch, plan, n, p, tdt, seed, nonzeros=40, samples=500):
+    """Forward transform of a sparse input: each output is a sum of `nonzeros` terms
+    of eq. (1.2), evaluated in FP64 with exact integer phases per dimension, at
+    `samples` random outputs. Returns the max error relative to the largest output."""
+    rng = np.random.default_rng(seed)
+    N = math.prod(n)
+    js = np.unique(np.stack([rng.integers(0, nl, nonzeros) for nl in n], axis=1), axis=0)
+    vals = rng.uniform(-1, 1, len(js)) + 1j * rng.uniform(-1, 1, len(js))
+    x = torch.zeros(N, dtype=tdt, device="cuda:0")
+    x[torch.from_numpy(cyclic_positions(np, js, n, p)).cuda()] = torch.from_numpy(vals).to(tdt).cuda()
+    vals = x[torch.from_numpy(cyclic_positions(np, js, n, p)).cuda()].cpu().numpy().astype(np.complex128)
+    y = plan(x)
+    torch.cuda.synchronize()
+    ks = np.stack([rng.integers(0, nl, samples) for nl in n], axis=1)
+    got = y[torch.from_numpy(cyclic_positions(np, ks, n, p)).cuda()].cpu().numpy().astype(np.complex128)
+    turns = np.zeros((samples, len(js)))
+    for l, nl in enumerate(n):
+        turns += ((ks[:, l:l + 1] * js[None, :, l]) % nl) / float(nl)
+    want = (np.exp(-2j * np.pi * turns) * vals[None, :]).sum(axis=1)
+    del x, y
+    return float(np.abs(got - want).max() / np.abs(want).max())
+
+
 def run_paper_workloads(args, torch, fftu):
     """The paper's own test sizes on one GPU: 1024^3 complex128 (4^3 grid, the fused
     exchange) and the very rectangular 16,777,216 x 64 (complex64 on a 4096 x 8 grid:
     the only grids for it have a local line of 4096, and P = 32768 takes the unfused
     exchange). Input from the device generator; checked by the round trip (forward,
-    then inverse, against the input) on the device."""
+    then inverse, against the input) on the device, and the forward transform of a
+    sparse input at 500 sampled outputs against eq. (1.2)."""
+    import numpy as np
     res = []
     for n, p, dt in [((1024, 1024, 1024), (4, 4, 4), "complex128"), ((1 << 24, 64), (4096, 8), "complex64")]:
         N = math.prod(n)
@@ -353,6 +489,7 @@ def run_paper_workloads(args, torch, fftu):
         per_launch, _ = fwd.timing_end()
         names = fwd.launch_names()
         info = fwd.info()
+        fwd_err = sparse_forward_check(np, torch, fwd, n, p, tdt, seed=17)
         fwd.close()
         inv = fftu.Plan(n, p, dt, fftu.INVERSE)
         inv(y, y, stream=stream)                 # in place: y becomes the round trip
@@ -367,7 +504,7 @@ def run_paper_workloads(args, torch, fftu):
                     "roofline": {"bound": "hbm", "algorithmic_bytes": alg, "unit": "GB/s", "peak": HBM_PEAK_GBS,
                                  "achieved": round(alg / (ms * 1e-3) / 1e9, 1),
                                  "frac": round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
-                    "rel_l2_roundtrip": rt,
+                    "rel_l2_roundtrip": rt, "sparse_forward_max_rel_error": fwd_err,
                     # traffic: HBM bytes per launch from the committed counter summary (None when
                     # it was taken from other kernel sources)
                     "kernels": [{"kernel": k, "avg_ms": round(t, 3),
@@ -524,6 +661,8 @@ def main():
     ap.add_argument("--no-serving", action="store_true", help="skip the serving workload")
     ap.add_argument("--no-convolution", action="store_true", help="skip the convolution workload")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-radix workload")
+    ap.add_argument("--no-group-cyclic", action="store_true",
+                    help="skip the grid beyond p_max (512^3 over 32^3, two supersteps)")
     ap.add_argument("--no-paper", action="store_true",
                     help="skip the paper's own sizes (1024^3 complex128, 16777216 x 64 complex64)")
     ap.add_argument("--no-small", action="store_true", help="skip the 64^3 latency workload")
@@ -584,15 +723,15 @@ def main():
     torch.cuda.synchronize()
 
     plan.timing_begin(args.steps)
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     torch.cuda.synchronize()
-    ev0.record(stream)
-    for _ in range(args.steps):
+    evs[0].record(stream)
+    for i in range(args.steps):
         plan(x, out, stream=stream)
-    ev1.record(stream)
+        evs[i + 1].record(stream)
     torch.cuda.synchronize()
-    total_ms = ev0.elapsed_time(ev1)
+    total_ms = evs[0].elapsed_time(evs[-1])
+    step_ms = np.array([evs[i].elapsed_time(evs[i + 1]) for i in range(args.steps)])
     per_launch, ncalls = plan.timing_end()
     ms = total_ms / args.steps
     flops = 5.0 * N * math.log2(N)
@@ -620,16 +759,24 @@ def main():
                for i, (s, t) in enumerate(zip(syms, per_launch))]
     transform_bytes = info["launches"] * alg_bytes
     frac_transform = transform_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS
+    # the scope's algorithmic bytes: the fewest passes this shape needs (local dimensions
+    # grouped under the LDS budget, plus the exchange), each one read and one write
+    b_alg = ideal_passes(n, p, esize) * alg_bytes
 
     result = {
         "metric": METRIC, "value": round(gflops, 2), "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
+        "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "strong",
         "vs_baseline": None, "dtype": "f64" if esize == 16 else "f32", "data": "synthetic",
         "config": {"workload": wl["name"], "n": list(n), "p": list(p), "direction": "forward",
                    "input": f"iid {wl['dist']} real/imag, seed {wl['seed']}"},
         "roofline": roofline,
+        "timing": {"ms_mean": round(ms, 4), "ms_median": round(float(np.median(step_ms)), 4),
+                   "ms_p10": round(float(np.percentile(step_ms, 10)), 4),
+                   "ms_p90": round(float(np.percentile(step_ms, 90)), 4), "steps": args.steps},
         "hbm_roofline_frac_transform": round(frac_transform, 4),
         "transform_algorithmic_bytes": transform_bytes,
+        "hbm_roofline_frac_ideal_passes": round(b_alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "ideal_passes": ideal_passes(n, p, esize), "launches": info["launches"],
         "kernels": kernels,
     }
 
@@ -646,7 +793,9 @@ def main():
                 "value": round(flops / t_oracle / 1e9, 3), "unit": "GFLOP/s", "cores": oracle.max_threads(),
                 "kind": "oracle",
                 "sample": f"one full {'x'.join(map(str, n))} forward DFT (FP64 separable radix-2, natural order) "
-                          f"of the same seeded input: {t_oracle:.2f} s"}
+                          f"of the same seeded input: {t_oracle:.2f} s",
+                "cpu_model": cpu_model()}
+            result["cpu_baseline"].update(oracle_single_thread(np, oracle, synth, X, flops))
         if not args.no_check:
             got = out.cpu().numpy()
             result["rel_l2_vs_oracle"] = oracle.rel_l2(got, oracle.to_cyclic(Y, p))
@@ -667,6 +816,9 @@ def main():
         torch.cuda.empty_cache()
     if args.workload == "512cube" and not args.no_mixed:
         result["mixed_radix"] = run_mixed(args, torch, np, fftu, synth, not args.no_check)
+        torch.cuda.empty_cache()
+    if args.workload == "512cube" and not args.no_group_cyclic:
+        result["group_cyclic"] = run_group_cyclic(args, torch, np, fftu, synth, not args.no_check)
         torch.cuda.empty_cache()
     if args.workload == "512cube" and not args.no_batch:
         result["batch"] = run_batch(args, torch, np, fftu, synth, not args.no_check)
