@@ -14,8 +14,10 @@ With the default workload the line also carries a "batch" object: 256 uneven
 3-D complex64 transforms (sides 2^4..2^8 per dimension, 2x2x2 grids) in one
 persistent launch, its HIP-graph replay, and the same 256 transforms as plain
 per-transform executions, after a measured tuning of the tiling knobs; and a
-"serving" object: p50/p99 latency of a real-time request stream served with
-continuous batching and with a plain one-at-a-time FIFO.
+"serving" object: p50/p99 latency of the 30 s real-time request stream served
+with four streams, with small waiting requests coalesced into persistent batch
+launches, and with a plain one-at-a-time FIFO, and the FP32 error of every
+complex64 result.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload 512cube|64cube|64pow5]
                     [--no-batch] [--retune] [--no-serving] [--serving-seconds S]
@@ -623,8 +625,11 @@ def run_small(args, torch, np, fftu, synth, with_oracle):
 def run_serving(args, torch, synth):
     """The serving workload: a Poisson stream of 2-D/3-D/4-D requests (2000/s,
     sides 2^5..2^10, at most 2^26 points, complex64/complex128, forward/inverse,
-    trace seed 5), served in real time with the continuous policy and with the
-    plain one-at-a-time FIFO, on the same arena, plan cache and kernels."""
+    trace seed 5), served in real time with the continuous policy (4 streams),
+    the coalesced policy (continuous, and small requests that wait together run
+    as one persistent batch launch) and the plain one-at-a-time FIFO, on the same
+    arena, plan cache and kernels. Then every complex64 result's error against
+    the complex128 transform of its own input."""
     from paper_2203_11795_amd import serving
     secs = float(args.serving_seconds)
     reqs = serving.requests_from_trace(synth.serving_trace(seed=5, rate=2000.0, duration=30.0), limit_seconds=secs)
@@ -637,13 +642,30 @@ def run_serving(args, torch, synth):
                            "input generated on the device (Philox4x32-10, key (5, request id))",
                "streams": srv.nstreams, "large_lanes": srv.large_lanes, "large_MiB": srv.large_bytes >> 20,
                "arena_GiB": srv.arena_bytes / 2 ** 30}
-        for policy in ("continuous", "fifo"):
+        out["coalesce_MiB"] = srv.coalesce_bytes >> 20
+        out["coalesce_max"] = srv.coalesce_max
+        for policy in ("continuous", "coalesced", "fifo"):
             res = srv.serve(reqs, policy, time_limit=3 * secs + 5)
             out[policy] = serving.summarize(res, reqs)
             log(f"[bench] serving {policy}: {out[policy]}")
-        c, f = out["continuous"], out["fifo"]
-        out["p99_speedup_vs_fifo"] = round(f["p99_ms"] / c["p99_ms"], 3) if c["p99_ms"] > 0 else None
-        out["p50_speedup_vs_fifo"] = round(f["p50_ms"] / c["p50_ms"], 3) if c["p50_ms"] > 0 else None
+        f = out["fifo"]
+        for policy in ("continuous", "coalesced"):
+            c = out[policy]
+            c["p99_speedup_vs_fifo"] = round(f["p99_ms"] / c["p99_ms"], 3) if c["p99_ms"] > 0 else None
+            c["p50_speedup_vs_fifo"] = round(f["p50_ms"] / c["p50_ms"], 3) if c["p50_ms"] > 0 else None
+        if not args.no_check:
+            import numpy as np
+            log("[bench] serving: FP32 error of every complex64 result against complex128")
+            t0 = time.perf_counter()
+            errs = {}
+            for k in range(0, len(reqs), 5000):
+                errs.update(serving.precision_errors(srv, reqs[k:k + 5000]))
+                log(f"[bench] serving: FP32 errors of {len(errs)} results so far")
+            ev = np.array(list(errs.values())) if errs else np.array([float("nan")])
+            out["precision_complex64_vs_complex128"] = {
+                "results": len(errs), "max": float(ev.max()), "median": float(np.median(ev)),
+                "p99": float(np.percentile(ev, 99)), "tolerance": 5e-6,
+                "within_tolerance": int((ev <= 5e-6).sum()), "seconds": round(time.perf_counter() - t0, 1)}
     finally:
         srv.close()
     return out
@@ -667,7 +689,7 @@ def main():
                     help="skip the paper's own sizes (1024^3 complex128, 16777216 x 64 complex64)")
     ap.add_argument("--no-small", action="store_true", help="skip the 64^3 latency workload")
     ap.add_argument("--no-precision", action="store_true", help="skip the 64^5 complex64 precision workload")
-    ap.add_argument("--serving-seconds", type=float, default=10.0,
+    ap.add_argument("--serving-seconds", type=float, default=30.0,
                     help="seconds of the 30 s request trace to serve (each policy runs it in real time)")
     ap.add_argument("--retune", action="store_true", help="measure the tiling knobs again instead of the cached ones")
     ap.add_argument("--copy-calibration", action="store_true",

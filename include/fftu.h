@@ -318,6 +318,37 @@ fftu_status fftu_execute_batch(fftu_plan_t plan, const void *const in[], void *c
 fftu_status fftu_batch_error(fftu_plan_t plan, int *flag);
 
 /*
+ * Batches that own no device memory, for callers that manage HBM themselves (a
+ * serving loop that coalesces waiting requests into one launch, with its own
+ * arena). fftu_plan_batch_external takes the arguments of fftu_plan_batch and
+ * applies its checks, builds the work list on the host only and uses the twiddle
+ * table shared with fftu_plan_external plans (allocated on first use, as there).
+ * Its results are bitwise those of fftu_plan_batch for the same members.
+ *
+ * fftu_batch_workspace_bytes: device bytes one execution needs (the members'
+ * workspaces, the work list, its counters and buffer array).
+ * fftu_batch_staging_bytes: host bytes of the work-list image a call writes.
+ *
+ * fftu_execute_batch_ws runs every transform as fftu_execute_batch does, with
+ * `workspace` (device, 256-byte aligned, at least fftu_batch_workspace_bytes,
+ * overlapping no buffer) and `host_staging` (page-locked host memory from
+ * hipHostMalloc, at least fftu_batch_staging_bytes). The call writes the work
+ * list for these buffers into host_staging, enqueues its copy into the workspace,
+ * the counter reset and the persistent kernel on `stream`, and returns without
+ * waiting. The caller must leave host_staging unchanged until the enqueued copy
+ * has run (an event recorded after the call marks it), and the workspace until
+ * the batch has finished. fftu_execute_batch and fftu_graph_capture refuse such
+ * plans (INVALID_VALUE); fftu_batch_error reads the flag of the last call's
+ * workspace. Errors as for fftu_execute_batch.
+ */
+fftu_plan_t fftu_plan_batch_external(int count, const int d[], const int64_t *const n[], const int64_t *const p[],
+                                     fftu_dtype dtype, fftu_direction direction);
+size_t fftu_batch_workspace_bytes(fftu_plan_t plan);
+size_t fftu_batch_staging_bytes(fftu_plan_t plan);
+fftu_status fftu_execute_batch_ws(fftu_plan_t plan, const void *const in[], void *const out[], void *workspace,
+                                  void *host_staging, hipStream_t stream);
+
+/*
  * HIP graphs: fftu_graph_capture records the launches of one fftu_execute
  * (count = 0, in/out point at one device pointer each) or one
  * fftu_execute_batch (count = the batch size, in/out arrays of count device

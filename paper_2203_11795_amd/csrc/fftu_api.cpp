@@ -84,6 +84,9 @@ struct fftu_plan_s {
     void *dnext = nullptr;
     void *derror = nullptr;
     void *dbind = nullptr;                     // [count] BatchBind: the buffers the device list holds
+    std::vector<int64_t> hstarts;              // external batches: the work list's item ranges and
+    std::vector<int32_t> hdep;                 // dependencies, copied with the list on every call
+    void *last_ws = nullptr;                   // external batches: workspace of the last call (error flag)
     std::vector<const void *> bound_in;        // what dbind holds once the enqueued work has run
     std::vector<void *> bound_out;
     std::vector<hipEvent_t> events;  // timing_max x (launches + 1)
@@ -1235,6 +1238,33 @@ fftu_status check_batch_args(const fftu_plan_s *pl, const void *const in[], void
     return FFTU_SUCCESS;
 }
 
+// Workspace of an external batch (bytes, 256-aligned pieces): the members'
+// workspaces, then the image the host stages (stages, starts, dep, bind: the
+// staging buffer holds [stages, staged) of this layout), then the counters that
+// k_batch_reset clears.
+struct BatchWsLayout {
+    size_t stages = 0, starts = 0, dep = 0, bind = 0, staged = 0, done = 0, next = 0, error = 0, total = 0;
+};
+
+BatchWsLayout batch_ws_layout(const fftu_plan_s *pl)
+{
+    auto up = [](size_t v) { return (v + 255) / 256 * 256; };
+    const size_t K = pl->hstages.size();
+    int64_t Ntot = 0;
+    for (int64_t v : pl->member_N) Ntot += v;
+    BatchWsLayout L;
+    L.stages = up(size_t(Ntot) * pl->esize);
+    L.starts = up(L.stages + K * sizeof(fftu::BatchStage));
+    L.dep = up(L.starts + (K + 1) * sizeof(int64_t));
+    L.bind = up(L.dep + K * sizeof(int32_t));
+    L.staged = L.bind + size_t(pl->count) * sizeof(fftu::BatchBind);
+    L.done = up(L.staged);
+    L.next = up(L.done + K * sizeof(int32_t));
+    L.error = L.next + sizeof(unsigned long long);
+    L.total = up(L.error + sizeof(int32_t));
+    return L;
+}
+
 // Write the buffers into the device list on `stream` (k_batch_bind launches that
 // carry the pointers as arguments): stream-ordered, no host wait.
 fftu_status enqueue_bind(const fftu_plan_s *pl, const void *const in[], void *const out[], hipStream_t stream)
@@ -1939,8 +1969,152 @@ fftu_plan_t fftu_plan_batch(int count, const int d[], const int64_t *const n[], 
     return pl;
 }
 
+fftu_plan_t fftu_plan_batch_external(int count, const int d[], const int64_t *const n[], const int64_t *const p[],
+                                     fftu_dtype dtype, fftu_direction direction)
+{
+    fftu::BatchWorklist wl;
+    fftu_status bs = fftu::build_batch_worklist(count, d, n, p, dtype, direction, wl);
+    if (bs != FFTU_SUCCESS) {
+        record(bs);
+        return nullptr;
+    }
+    int device = 0, cus = 0, clock_khz = 0;
+    if (hipGetDevice(&device) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
+        hipDeviceGetAttribute(&clock_khz, hipDeviceAttributeWallClockRate, device) != hipSuccess) {
+        record(FFTU_ERROR_DEVICE);
+        return nullptr;
+    }
+    void *table = nullptr;
+    int logK = 0;
+    hipError_t e = shared_table(device, dtype, wl.lognmax, &table, &logK);
+    if (e != hipSuccess) {
+        record(from_hip(e));
+        return nullptr;
+    }
+    fftu_plan_s *pl = new (std::nothrow) fftu_plan_s();
+    if (!pl) {
+        record(FFTU_ERROR_OUT_OF_MEMORY);
+        return nullptr;
+    }
+    pl->is_batch = true;
+    pl->external = true;
+    pl->count = count;
+    pl->dtype = dtype;
+    pl->dir = direction;
+    pl->prec = dtype == FFTU_C128 ? Precision::F64 : Precision::F32;
+    pl->esize = dtype == FFTU_C128 ? 16 : 8;
+    pl->device = device;
+    pl->table = table;                      // shared, not owned
+    pl->hstages = wl.stages;
+    for (fftu::BatchStage &st : pl->hstages) {
+        // the shared table is omega_{2^logK}, logK >= lognmax: the same entries at a finer stride
+        st.pd.lognmax = logK;
+        st.ex.g.lognmax = logK;
+    }
+    pl->stage_member = wl.member;
+    pl->stage_first = wl.first;
+    pl->stage_last = wl.last;
+    pl->member_N = wl.N;
+    pl->member_ws = wl.ws;
+    pl->hstarts = wl.starts;
+    pl->hdep = wl.dep;
+    pl->batch_items = wl.items;
+    pl->batch_lds = wl.lds;
+    pl->batch_wait_ticks = int64_t(clock_khz > 0 ? clock_khz : 100000) * 2000;   // 2 s
+    const int64_t resident = int64_t(fftu::batch_blocks_per_cu(pl->prec, pl->batch_lds)) * int64_t(cus);
+    pl->batch_blocks = uint32_t(std::max<int64_t>(1, std::min<int64_t>(resident, pl->batch_items)));
+    pl->launches = 2;
+    pl->launch_names = {"fftu::k_batch_reset", std::string("fftu::k_batch<") +
+                                                   (dtype == FFTU_C128 ? "double" : "float") + ">"};
+    int64_t Ntot = 0;
+    for (int64_t v : pl->member_N) Ntot += v;
+    pl->grid.N = Ntot;
+    pl->ws_bytes = 0;
+    record(FFTU_SUCCESS);
+    return pl;
+}
+
+size_t fftu_batch_workspace_bytes(fftu_plan_t plan)
+{
+    if (!plan || !plan->is_batch || !plan->external) {
+        record(FFTU_ERROR_INVALID_VALUE);
+        return 0;
+    }
+    record(FFTU_SUCCESS);
+    return batch_ws_layout(plan).total;
+}
+
+size_t fftu_batch_staging_bytes(fftu_plan_t plan)
+{
+    if (!plan || !plan->is_batch || !plan->external) {
+        record(FFTU_ERROR_INVALID_VALUE);
+        return 0;
+    }
+    record(FFTU_SUCCESS);
+    const BatchWsLayout lay = batch_ws_layout(plan);
+    return lay.staged - lay.stages;
+}
+
+fftu_status fftu_execute_batch_ws(fftu_plan_t plan, const void *const in[], void *const out[], void *workspace,
+                                  void *host_staging, hipStream_t stream)
+{
+    if (!plan || !plan->is_batch || !plan->external || !workspace || !host_staging || !aligned(workspace, 256))
+        return record(FFTU_ERROR_INVALID_VALUE);
+    fftu_status s = check_batch_args(plan, in, out);
+    if (s != FFTU_SUCCESS) return record(s);
+    const BatchWsLayout lay = batch_ws_layout(plan);
+    const uintptr_t w0 = reinterpret_cast<uintptr_t>(workspace), w1 = w0 + lay.total;
+    for (int f = 0; f < plan->count; ++f) {
+        // the workspace must overlap no buffer
+        const uintptr_t bytes = uintptr_t(plan->member_N[size_t(f)]) * plan->esize;
+        for (const void *b : {in[f], static_cast<const void *>(out[f])}) {
+            const uintptr_t a = reinterpret_cast<uintptr_t>(b);
+            if (a < w1 && w0 < a + bytes) return record(FFTU_ERROR_INVALID_VALUE);
+        }
+    }
+    char *ws = static_cast<char *>(workspace);
+    // the image of [stages | starts | dep | bind] for these buffers and this workspace,
+    // laid out as in the workspace from offset lay.stages on
+    char *img = static_cast<char *>(host_staging) - lay.stages;
+    fftu::BatchStage *st = reinterpret_cast<fftu::BatchStage *>(img + lay.stages);
+    const size_t K = plan->hstages.size();
+    for (size_t k = 0; k < K; ++k) {
+        st[k] = plan->hstages[k];
+        const int f = plan->stage_member[k];
+        char *mws = ws + plan->member_ws[size_t(f)] * plan->esize;
+        st[k].src = plan->stage_first[k] ? nullptr : mws;
+        st[k].dst = plan->stage_last[k] ? nullptr : static_cast<void *>(mws);
+    }
+    std::memcpy(img + lay.starts, plan->hstarts.data(), (K + 1) * sizeof(int64_t));
+    std::memcpy(img + lay.dep, plan->hdep.data(), K * sizeof(int32_t));
+    fftu::BatchBind *bind = reinterpret_cast<fftu::BatchBind *>(img + lay.bind);
+    for (int f = 0; f < plan->count; ++f) bind[f] = {in[f], out[f]};
+    hipError_t e = hipMemcpyAsync(ws + lay.stages, img + lay.stages, lay.staged - lay.stages, hipMemcpyHostToDevice,
+                                  stream);
+    if (e != hipSuccess) return record(from_hip(e));
+    fftu::BatchDesc bd{};
+    bd.nstages = int32_t(K);
+    bd.wait_limit = plan->batch_wait_ticks;
+    bd.nitems = plan->batch_items;
+    bd.stages = reinterpret_cast<const fftu::BatchStage *>(ws + lay.stages);
+    bd.starts = reinterpret_cast<const int64_t *>(ws + lay.starts);
+    bd.dep = reinterpret_cast<const int32_t *>(ws + lay.dep);
+    bd.bind = reinterpret_cast<const fftu::BatchBind *>(ws + lay.bind);
+    bd.done = reinterpret_cast<int32_t *>(ws + lay.done);
+    bd.next = reinterpret_cast<unsigned long long *>(ws + lay.next);
+    bd.error = reinterpret_cast<int32_t *>(ws + lay.error);
+    e = fftu::launch_batch_reset(bd, stream);
+    if (e == hipSuccess)
+        e = fftu::launch_batch(plan->prec, bd, plan->table, plan->batch_blocks, plan->batch_lds, stream);
+    if (e != hipSuccess) return record(from_hip(e));
+    plan->last_ws = workspace;
+    return record(FFTU_SUCCESS);
+}
+
 fftu_status fftu_execute_batch(fftu_plan_t plan, const void *const in[], void *const out[], hipStream_t stream)
 {
+    if (plan && plan->external) return record(FFTU_ERROR_INVALID_VALUE);   // needs fftu_execute_batch_ws
     if (!plan || !plan->is_batch || !in || !out) return record(FFTU_ERROR_INVALID_VALUE);
     if (!same_binding(plan, in, out)) {
         fftu_status s = check_batch_args(plan, in, out);
@@ -1966,8 +2140,13 @@ fftu_status fftu_fill_uniform(void *out, int64_t count, fftu_dtype dtype, uint32
 fftu_status fftu_batch_error(fftu_plan_t plan, int *flag)
 {
     if (!plan || !plan->is_batch || !flag) return record(FFTU_ERROR_INVALID_VALUE);
+    const void *src = plan->derror;
+    if (plan->external) {
+        if (!plan->last_ws) return record(FFTU_ERROR_INVALID_VALUE);
+        src = static_cast<const char *>(plan->last_ws) + batch_ws_layout(plan).error;
+    }
     int32_t v = 0;
-    hipError_t e = hipMemcpy(&v, plan->derror, sizeof(v), hipMemcpyDeviceToHost);
+    hipError_t e = hipMemcpy(&v, src, sizeof(v), hipMemcpyDeviceToHost);
     if (e != hipSuccess) return record(from_hip(e));
     *flag = v;
     return record(FFTU_SUCCESS);
@@ -1975,7 +2154,8 @@ fftu_status fftu_batch_error(fftu_plan_t plan, int *flag)
 
 fftu_graph_t fftu_graph_capture(fftu_plan_t plan, int count, const void *const in[], void *const out[])
 {
-    if (!plan || !in || !out || count < 0 || (count > 0) != plan->is_batch || (count > 0 && count != plan->count)) {
+    if (!plan || !in || !out || count < 0 || (count > 0) != plan->is_batch || (count > 0 && count != plan->count) ||
+        (plan->is_batch && plan->external)) {
         record(FFTU_ERROR_INVALID_VALUE);
         return nullptr;
     }

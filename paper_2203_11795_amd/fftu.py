@@ -29,6 +29,7 @@ EXPORTS = ["fftu_version", "fftu_status_string", "fftu_last_error", "fftu_check"
            "fftu_stage_local_fft",
            "fftu_stage_twiddle", "fftu_stage_exchange", "fftu_stage_remaining_fft", "fftu_stage_superstep", "fftu_timing_begin",
            "fftu_timing_end", "fftu_set_tuning", "fftu_get_tuning", "fftu_launch_name", "fftu_plan_batch", "fftu_execute_batch", "fftu_batch_error",
+           "fftu_plan_batch_external", "fftu_batch_workspace_bytes", "fftu_batch_staging_bytes", "fftu_execute_batch_ws",
            "fftu_graph_capture", "fftu_graph_launch", "fftu_graph_destroy", "fftu_fill_uniform", "fftu_plan_convolution",
            "fftu_execute_convolution", "fftu_pointwise_mul", "fftu_destroy"]
 
@@ -111,6 +112,14 @@ def load_library(path: str = LIB_PATH):
                                     ctypes.POINTER(i64p), ctypes.c_int, ctypes.c_int]
     lib.fftu_execute_batch.restype = ctypes.c_int
     lib.fftu_execute_batch.argtypes = [vp, ptr_arr, ptr_arr, vp]
+    lib.fftu_plan_batch_external.restype = vp
+    lib.fftu_plan_batch_external.argtypes = lib.fftu_plan_batch.argtypes
+    lib.fftu_batch_workspace_bytes.restype = ctypes.c_size_t
+    lib.fftu_batch_workspace_bytes.argtypes = [vp]
+    lib.fftu_batch_staging_bytes.restype = ctypes.c_size_t
+    lib.fftu_batch_staging_bytes.argtypes = [vp]
+    lib.fftu_execute_batch_ws.restype = ctypes.c_int
+    lib.fftu_execute_batch_ws.argtypes = [vp, ptr_arr, ptr_arr, vp, vp, vp]
     lib.fftu_batch_error.restype = ctypes.c_int
     lib.fftu_batch_error.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
     lib.fftu_graph_capture.restype = vp
@@ -439,7 +448,10 @@ class BatchPlan:
     (fftu_plan_batch / fftu_execute_batch). shapes[i] and grids[i] give n and p
     of transform i; all share dtype and direction."""
 
-    def __init__(self, shapes, grids, dtype="complex64", direction=FORWARD):
+    def __init__(self, shapes, grids, dtype="complex64", direction=FORWARD, external=False):
+        """external=True: fftu_plan_batch_external (no device memory of its own; run
+        it with execute_ws and a workspace and page-locked staging buffer)."""
+        self.external = bool(external)
         self.shapes = [tuple(int(v) for v in s) for s in shapes]
         self.grids = [tuple(int(v) for v in g) for g in grids]
         if len(self.shapes) != len(self.grids) or not self.shapes:
@@ -453,9 +465,11 @@ class BatchPlan:
         i64p = ctypes.POINTER(ctypes.c_int64)
         ns = (i64p * count)(*[ctypes.cast(a, i64p) for a in self._keep[:count]])
         ps = (i64p * count)(*[ctypes.cast(a, i64p) for a in self._keep[count:]])
-        h = self._lib.fftu_plan_batch(count, ds, ns, ps, self.dtype_code, self.direction)
+        make = self._lib.fftu_plan_batch_external if self.external else self._lib.fftu_plan_batch
+        h = make(count, ds, ns, ps, self.dtype_code, self.direction)
         if not h:
-            raise FftuError(self._lib.fftu_last_error(), "fftu_plan_batch")
+            raise FftuError(self._lib.fftu_last_error(),
+                            "fftu_plan_batch_external" if self.external else "fftu_plan_batch")
         self._h = ctypes.c_void_p(h)
         self.sizes = [_prod(s) for s in self.shapes]
 
@@ -490,6 +504,38 @@ class BatchPlan:
         if stream is None:
             stream = torch.cuda.current_stream(xs[0].device)
         self.execute_ptrs([x.data_ptr() for x in xs], [o.data_ptr() for o in outs], int(stream.cuda_stream))
+        return outs
+
+    @property
+    def workspace_bytes(self) -> int:
+        """Device bytes execute_ws needs (external batches)."""
+        return int(self._lib.fftu_batch_workspace_bytes(self._h))
+
+    @property
+    def staging_bytes(self) -> int:
+        """Page-locked host bytes execute_ws writes (external batches)."""
+        return int(self._lib.fftu_batch_staging_bytes(self._h))
+
+    def execute_ws_ptrs(self, in_ptrs, out_ptrs, workspace_ptr: int, staging_ptr: int, stream: int = 0) -> None:
+        st = self._lib.fftu_execute_batch_ws(self._h, _ptrs(in_ptrs), _ptrs(out_ptrs), ctypes.c_void_p(workspace_ptr),
+                                             ctypes.c_void_p(staging_ptr), ctypes.c_void_p(stream))
+        if st != 0:
+            raise FftuError(st, "fftu_execute_batch_ws")
+
+    def execute_ws(self, xs, outs, workspace, staging, stream=None):
+        """outs[i] = F(xs[i]) with a device workspace tensor (>= workspace_bytes) and a
+        pinned host tensor (>= staging_bytes) that stays untouched until the
+        enqueued copy has run."""
+        import torch
+        self.check_buffers(xs, outs)
+        if not workspace.is_cuda or workspace.numel() * workspace.element_size() < self.workspace_bytes:
+            raise ValueError(f"workspace must be a device tensor of at least {self.workspace_bytes} bytes")
+        if staging.is_cuda or not staging.is_pinned() or staging.numel() * staging.element_size() < self.staging_bytes:
+            raise ValueError(f"staging must be a pinned host tensor of at least {self.staging_bytes} bytes")
+        if stream is None:
+            stream = torch.cuda.current_stream(xs[0].device)
+        self.execute_ws_ptrs([x.data_ptr() for x in xs], [o.data_ptr() for o in outs], workspace.data_ptr(),
+                             staging.data_ptr(), int(stream.cuda_stream))
         return outs
 
     def error_flag(self) -> int:

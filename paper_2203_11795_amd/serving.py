@@ -16,7 +16,7 @@ request is admitted, in arrival order, only when both fit, and otherwise waits
 for running requests to release theirs. Plans hold no device memory, so the plan
 cache is an LRU of host objects.
 
-Two policies over the same arena, plan cache and kernels:
+Three policies over the same arena, plan cache and kernels:
   "continuous"  up to `streams` requests run at once, one per HIP stream (all of
                 default priority); a stream that finishes takes the next
                 admitted request at once, and no stream waits for the host.
@@ -26,6 +26,15 @@ Two policies over the same arena, plan cache and kernels:
                 each take twice as long), while small requests never queue
                 behind a large one. A large lane with no large request waiting
                 takes a small one.
+  "coalesced"   "continuous", and the requests of at most `coalesce_bytes` that
+                the persistent batch kernel supports (every local side n_l/2 <=
+                256) always run through it: a free stream takes the first waiting
+                one together with up to `coalesce_max` - 1 more of the same dtype
+                and direction that wait with it, and runs them as one batch
+                (fftu_plan_batch_external: a host-only plan; its work list goes
+                over from a page-locked staging ring, its workspace comes from the
+                arena). A request alone runs as a batch of one, so its result is
+                bitwise the same alone and coalesced.
   "fifo"        one request at a time on one stream; the host waits for each to
                 finish before it starts the next (the plain baseline).
 """
@@ -163,10 +172,11 @@ class PlanCache:
 
 @dataclass
 class _Running:
-    req: Request
+    reqs: list               # the requests this launch serves (one, or a coalesced batch)
     blocks: list
     end: object              # torch.cuda.Event
-    out: object              # the request's buffer (a view into the arena)
+    outs: list               # their buffers (views into the arena)
+    slot: int = -1           # staging slot held until `end` (coalesced batches)
 
 
 @dataclass
@@ -181,13 +191,17 @@ class ServeResult:
     plan_misses: int = 0
     peak_arena_bytes: int = 0
     refused: list = field(default_factory=list)      # rids larger than the whole arena (never admissible)
+    batches: int = 0                                 # launches of the persistent batch kernel ("coalesced")
+    coalesced_requests: int = 0                      # requests served by them
+    max_batch: int = 0
 
 
 class Server:
     """Serves requests with one of the two policies over a shared arena and plan cache."""
 
     def __init__(self, arena_bytes: int = 16 << 30, streams: int = 4, seed: int = 5, plan_cache: int = 4096,
-                 large_bytes: int = 64 << 20, large_lanes: int = 2):
+                 large_bytes: int = 64 << 20, large_lanes: int = 2, coalesce_bytes: int = 4 << 20,
+                 coalesce_max: int = 64, staging_slots: int = 16, staging_bytes: int = 2 << 20):
         import torch
         self.torch = torch
         self.dev = torch.device("cuda:0")
@@ -199,10 +213,44 @@ class Server:
         self.plans = PlanCache(plan_cache)
         self.large_bytes = int(large_bytes)
         self.large_lanes = max(1, min(int(large_lanes), self.nstreams))
+        self.coalesce_bytes = int(coalesce_bytes)
+        self.coalesce_max = max(1, int(coalesce_max))
+        # page-locked staging ring for the batch work lists; a slot is free again once
+        # the event recorded after its batch has passed
+        self.staging = [torch.empty(int(staging_bytes), dtype=torch.uint8, pin_memory=True)
+                        for _ in range(int(staging_slots))]
+        self.slot_busy = [None] * len(self.staging)
+        self._batchable = {}
 
     def close(self):
         self.plans.close()
         self.mem = None
+        self.staging = []
+
+    def batchable(self, req: Request) -> bool:
+        """Whether the coalesced policy runs this request through the batch kernel:
+        at most coalesce_bytes, a shape the persistent kernel supports, and a work
+        list that fits one staging slot on its own."""
+        if req.N * req.esize > self.coalesce_bytes or not self.staging:
+            return False
+        key = (req.shape, req.dtype)
+        ok = self._batchable.get(key)
+        if ok is None:
+            try:
+                bp = _b.BatchPlan([req.shape], [req.grid], req.dtype, req.direction, external=True)
+                ok = bp.staging_bytes <= self.staging[0].numel()
+                bp.close()
+            except _b.FftuError:
+                ok = False
+            self._batchable[key] = ok
+        return ok
+
+    def _free_slot(self):
+        for i, ev in enumerate(self.slot_busy):
+            if ev is None or ev.query():
+                self.slot_busy[i] = None
+                return i
+        return -1
 
     def _view(self, off: int, req: Request):
         t = self.torch.complex128 if req.dtype == "complex128" else self.torch.complex64
@@ -224,17 +272,62 @@ class Server:
         plan(buf, buf, stream=stream, workspace=ws)
         end = self.torch.cuda.Event(enable_timing=True)
         end.record(stream)
-        return _Running(req, [a, b], end, buf)
+        return _Running([req], [a, b], end, [buf])
+
+    def _launch_batch(self, group, arena: Arena, stream):
+        """One persistent launch for the requests in `group` (same dtype and
+        direction): their buffers and the batch workspace from the arena, the work
+        list through a free staging slot. None when memory or a slot is lacking."""
+        slot = self._free_slot()
+        if slot < 0:
+            return None
+        first = group[0]
+        bp = _b.BatchPlan([r.shape for r in group], [r.grid for r in group], first.dtype, first.direction,
+                          external=True)
+        try:
+            if bp.staging_bytes > self.staging[slot].numel():
+                return None
+            blocks = []
+            for r in group:
+                a = arena.alloc(r.N * r.esize)
+                if a is None:
+                    break
+                blocks.append(a)
+            w = arena.alloc(bp.workspace_bytes) if len(blocks) == len(group) else None
+            if w is None:
+                for blk in blocks:
+                    arena.release(*blk)
+                return None
+            bufs = [self._view(a[0], r) for a, r in zip(blocks, group)]
+            for r, buf in zip(group, bufs):
+                _b.fill_uniform(buf, self.seed, r.rid, 0, stream=stream)
+            bp.execute_ws_ptrs([b.data_ptr() for b in bufs], [b.data_ptr() for b in bufs],
+                               self.mem.data_ptr() + w[0], self.staging[slot].data_ptr(), int(stream.cuda_stream))
+        finally:
+            bp.close()                    # host-only plan: the enqueued work does not refer to it
+        end = self.torch.cuda.Event(enable_timing=True)
+        end.record(stream)
+        self.slot_busy[slot] = end
+        return _Running(list(group), blocks + [w], end, bufs, slot)
 
     def warmup(self, requests, count: int = 8):
         """Run the largest few requests untimed (first-use costs: the shared twiddle
-        tables, the kernels' first launches)."""
+        tables, the kernels' first launches), and one small batch of each dtype."""
         arena = Arena(self.arena_bytes)
         for r in sorted(requests, key=lambda r: -r.N)[:count]:
             run = self._launch(r, arena, self.streams[0])
             run.end.synchronize()
             for blk in run.blocks:
                 arena.release(*blk)
+        for dt in ("complex64", "complex128"):
+            group = [r for r in requests if r.dtype == dt and self.batchable(r)][:4]
+            group = [q for q in group if q.direction == group[0].direction] if group else []
+            if group:
+                run = self._launch_batch(group, arena, self.streams[0])
+                if run is not None:
+                    run.end.synchronize()
+                    for blk in run.blocks:
+                        arena.release(*blk)
         self.torch.cuda.synchronize()
 
     def serve(self, requests, policy: str = "continuous", keep=(), time_limit: float = None) -> ServeResult:
@@ -242,11 +335,12 @@ class Server:
         are copied to the host. time_limit: stop admitting after this many seconds
         (requests not done by then count as unfinished)."""
         torch = self.torch
-        if policy not in ("continuous", "fifo"):
+        if policy not in ("continuous", "coalesced", "fifo"):
             raise ValueError(policy)
         reqs = sorted(requests, key=lambda r: r.arrival)
         keep = set(keep)
-        nstreams = self.nstreams if policy == "continuous" else 1
+        nstreams = 1 if policy == "fifo" else self.nstreams
+        coalesce = policy == "coalesced"
         arena = Arena(self.arena_bytes)
         res = ServeResult(policy)
         hits0, miss0 = self.plans.hits, self.plans.misses
@@ -259,17 +353,48 @@ class Server:
 
         def finish(run: _Running):
             done = ref.elapsed_time(run.end) * 1e-3
-            res.latencies[run.req.rid] = done - run.req.arrival
-            res.completed += 1
-            if run.req.rid in keep:
-                res.outputs[run.req.rid] = run.out.cpu().numpy()
+            for r, buf in zip(run.reqs, run.outs):
+                res.latencies[r.rid] = done - r.arrival
+                res.completed += 1
+                if r.rid in keep:
+                    res.outputs[r.rid] = buf.cpu().numpy()
             for blk in run.blocks:
                 arena.release(*blk)
 
-        # continuous: streams [0, large_lanes) serve the large class first; fifo: one queue
+        def take(q, s):
+            """Launch the head of q on stream s (with its coalescing partners); None if
+            memory or a staging slot is lacking."""
+            head = q[0]
+            if not (coalesce and self.batchable(head)):
+                run = self._launch(head, arena, self.streams[s])
+                if run is not None:
+                    q.popleft()
+                return run
+            group, idx = [head], [0]
+            for j in range(1, min(len(q), 4 * self.coalesce_max)):
+                if len(group) >= self.coalesce_max:
+                    break
+                r = q[j]
+                if r.dtype == head.dtype and r.direction == head.direction and self.batchable(r):
+                    group.append(r)
+                    idx.append(j)
+            run = self._launch_batch(group, arena, self.streams[s])
+            if run is None and len(group) > 1:   # too big for memory or staging now: the head alone
+                group, idx = [head], [0]
+                run = self._launch_batch(group, arena, self.streams[s])
+            if run is None:
+                return None
+            for j in reversed(idx):
+                del q[j]
+            res.batches += 1
+            res.coalesced_requests += len(group)
+            res.max_batch = max(res.max_batch, len(group))
+            return run
+
+        # continuous / coalesced: streams [0, large_lanes) serve the large class first; fifo: one queue
         small = collections.deque()
         large = collections.deque()
-        lanes = self.large_lanes if policy == "continuous" else 0
+        lanes = 0 if policy == "fifo" else self.large_lanes
         running = [None] * nstreams
         i = 0
         n = len(reqs)
@@ -299,11 +424,15 @@ class Server:
                 q = next_queue(s, lanes, large, small)
                 if q is None:
                     continue
-                run = self._launch(q[0], arena, self.streams[s])
+                run = take(q, s)
                 if run is None:
+                    if all(r is None for r in running):
+                        # nothing runs, so nothing will free memory or a staging slot: this
+                        # request can never start
+                        res.refused.append(q.popleft().rid)
+                        continue
                     blocked = True                # HBM admission: wait for running requests
                     continue
-                q.popleft()
                 res.peak_arena_bytes = max(res.peak_arena_bytes, arena.used)
                 running[s] = run
                 progressed = True
@@ -328,6 +457,34 @@ class Server:
         return res
 
 
+def precision_errors(server: "Server", requests) -> dict:
+    """The error of every complex64 request's result, stated per result: the
+    request's own input (Philox, key (seed, rid)) transformed by its complex64
+    plan, against the complex128 transform of the same values promoted exactly;
+    rel-L2 = ||y32 - y64|| / ||y64||, computed on the device. Returns rid -> error."""
+    torch = server.torch
+    out = {}
+    stream = server.streams[0]
+    with torch.cuda.stream(stream):
+        for r in requests:
+            if r.dtype != "complex64":
+                continue
+            p32 = server.plans.get(r)
+            r64 = Request(r.rid, r.arrival, r.shape, "complex128", r.direction)
+            p64 = server.plans.get(r64)
+            x32 = torch.empty(r.N, dtype=torch.complex64, device=server.dev)
+            _b.fill_uniform(x32, server.seed, r.rid, 0, stream=stream)
+            x64 = x32.to(torch.complex128)
+            ws32 = torch.empty_like(x32)
+            ws64 = torch.empty_like(x64)
+            p32(x32, x32, stream=stream, workspace=ws32)
+            p64(x64, x64, stream=stream, workspace=ws64)
+            num = torch.linalg.vector_norm(x32.to(torch.complex128) - x64)
+            den = torch.linalg.vector_norm(x64)
+            out[r.rid] = (num / den).item()
+    return out
+
+
 def summarize(res: ServeResult, requests) -> dict:
     """p50/p99 latency, offered and achieved rates and GFLOP/s (5 N log2 N) of a run."""
     import numpy as np
@@ -344,4 +501,5 @@ def summarize(res: ServeResult, requests) -> dict:
         "GFLOPs": round(flops / res.wall / 1e9, 1) if res.wall > 0 else None,
         "wall_s": round(res.wall, 3), "plan_hits": res.plan_hits, "plan_misses": res.plan_misses,
         "peak_arena_GiB": round(res.peak_arena_bytes / 2 ** 30, 3), "refused": len(res.refused),
+        "batches": res.batches, "coalesced_requests": res.coalesced_requests, "max_batch": res.max_batch,
     }

@@ -119,3 +119,119 @@ def test_serving_admission_with_a_small_arena(torch):
             assert res.completed == len(reqs) and res.peak_arena_bytes <= cap
     finally:
         srv.close()
+
+
+def test_serving_large_lanes_alone_equals_mix(torch):
+    """The first 0.1 s of the serving trace itself (2000 requests/s, sides up to
+    1024, up to 2^26 points): 104 of its 235 requests are 64 MiB or more and run
+    on the large lanes. Large requests of both dtypes, and two small ones, give
+    bitwise the same result alone as in the mix."""
+    from paper_2203_11795_amd import serving
+    reqs = serving.requests_from_trace(synth.serving_trace(seed=5, rate=2000.0, duration=30.0), limit_seconds=0.1)
+    big = [r for r in reqs if r.N * r.esize >= 64 << 20]
+    pick = ([r for r in big if r.dtype == "complex64"][:2] + [r for r in big if r.dtype == "complex128"][:2]
+            + [r for r in reqs if r.N * r.esize < 1 << 20][:2])
+    assert len(pick) == 6
+    say(f"serving {len(reqs)} requests ({len(big)} large); checking {[(r.rid, r.shape, r.dtype) for r in pick]}")
+    srv = serving.Server(arena_bytes=16 << 30, streams=4)
+    try:
+        mix = srv.serve(reqs, "continuous", keep=[r.rid for r in pick], time_limit=60)
+        assert mix.completed == len(reqs) and mix.unfinished == 0
+        for r in pick:
+            alone = srv.serve([serving.Request(r.rid, 0.0, r.shape, r.dtype, r.direction)], "fifo", keep=[r.rid],
+                              time_limit=20)
+            assert np.array_equal(alone.outputs[r.rid], mix.outputs[r.rid]), r
+    finally:
+        srv.close()
+
+
+def test_coalesced_batches_alone_equal_mix_and_oracle(torch):
+    """Small requests that wait together run as one persistent batch launch. Each
+    result is bitwise the same alone (a batch of one) as coalesced, within
+    tolerance of the plain per-request path, and the smallest match the oracle
+    fed by the host Philox twin."""
+    from paper_2203_11795_amd import serving
+    base = serving_requests(0.2, exps=(5, 6, 7), rate=1000.0)
+    # a burst of the requests of at most 4 MiB: everything arrives at once, so requests wait together
+    reqs = [serving.Request(r.rid, 0.0, r.shape, r.dtype, r.direction) for r in base if r.N * r.esize <= 4 << 20]
+    assert len(reqs) >= 40
+    srv = serving.Server(arena_bytes=2 << 30, streams=4, coalesce_max=32)
+    try:
+        assert all(srv.batchable(r) for r in reqs)
+        mix = srv.serve(reqs, "coalesced", keep=[r.rid for r in reqs], time_limit=60)
+        say(f"coalesced: {len(reqs)} requests in {mix.batches} batches (largest {mix.max_batch})")
+        assert mix.completed == len(reqs) and mix.coalesced_requests == len(reqs)
+        assert mix.max_batch > 1 and mix.batches < len(reqs)
+        plain = srv.serve(reqs, "continuous", keep=[r.rid for r in reqs], time_limit=60)
+        rng = np.random.default_rng(4)
+        for i in sorted(rng.choice(len(reqs), size=6, replace=False)):
+            r = reqs[i]
+            alone = srv.serve([r], "coalesced", keep=[r.rid], time_limit=20)
+            assert alone.batches == 1 and alone.max_batch == 1
+            assert np.array_equal(alone.outputs[r.rid], mix.outputs[r.rid]), r
+        for r in reqs:
+            assert oracle.rel_l2(mix.outputs[r.rid], plain.outputs[r.rid]) <= 2 * TOL[r.dtype], r
+        for r in sorted(reqs, key=lambda q: q.N)[:4]:
+            x = philox.uniform_complex(r.N, 5, r.rid, NP[r.dtype]).astype(np.complex128)
+            want = oracle.cyclic_dft(x, r.shape, r.grid, r.direction)
+            assert oracle.rel_l2(mix.outputs[r.rid], want) <= TOL[r.dtype], r
+    finally:
+        srv.close()
+
+
+def test_precision_error_is_stated_per_result(torch):
+    """Every complex64 request's error against the complex128 transform of its own
+    input, within the FP32 tolerance; the complex128 transform of the smallest
+    against the oracle."""
+    from paper_2203_11795_amd import serving
+    reqs = serving_requests(0.05, exps=(5, 6, 7))
+    srv = serving.Server(arena_bytes=1 << 30, streams=2)
+    try:
+        errs = serving.precision_errors(srv, reqs)
+        c64 = [r for r in reqs if r.dtype == "complex64"]
+        assert set(errs) == {r.rid for r in c64} and c64
+        say(f"FP32 errors over {len(errs)} results: max {max(errs.values()):.2e}")
+        assert all(0 < e <= 5e-6 for e in errs.values())
+        r = min(c64, key=lambda q: q.N)
+        x = philox.uniform_complex(r.N, 5, r.rid, np.complex64).astype(np.complex128)
+        want = oracle.cyclic_dft(x, r.shape, r.grid, r.direction)
+        y = torch.from_numpy(x).cuda()
+        with __import__("paper_2203_11795_amd").Plan(r.shape, r.grid, "complex128", r.direction) as pl:
+            got = pl(y).cpu().numpy()
+        assert oracle.rel_l2(got, want) <= 1e-12
+    finally:
+        srv.close()
+
+
+def test_external_batch_equals_batch_bitwise(torch):
+    """fftu_plan_batch_external with a caller workspace and pinned staging gives
+    bitwise the results of fftu_plan_batch; a second call on other buffers reuses
+    nothing stale."""
+    import paper_2203_11795_amd as fftu
+    shapes = synth.batch_shapes(9, 21, exponents=(4, 5, 6))
+    grids = [(2, 2, 2)] * 9
+    xs = [torch.from_numpy(synth.uniform_complex(int(np.prod(s)), 500 + i, np.complex64)).cuda()
+          for i, s in enumerate(shapes)]
+    with fftu.BatchPlan(shapes, grids, "complex64", FORWARD) as a, \
+            fftu.BatchPlan(shapes, grids, "complex64", FORWARD, external=True) as b:
+        want = a(xs)
+        ws = torch.empty(b.workspace_bytes, dtype=torch.uint8, device="cuda")
+        stage = torch.empty(b.staging_bytes, dtype=torch.uint8, pin_memory=True)
+        outs = [torch.empty_like(x) for x in xs]
+        b.execute_ws(xs, outs, ws, stage)
+        torch.cuda.synchronize()
+        assert b.error_flag() == 0
+        for o, w in zip(outs, want):
+            assert torch.equal(o, w)
+        xs2 = [x.clone() for x in xs]
+        b.execute_ws(xs2, xs2, ws, stage)              # in place, new buffers
+        torch.cuda.synchronize()
+        for o, w in zip(xs2, want):
+            assert torch.equal(o, w)
+        with pytest.raises(fftu.FftuError):
+            b(xs)                                      # needs execute_ws
+        with pytest.raises(ValueError):
+            b.execute_ws(xs, outs, ws, torch.empty(b.staging_bytes, dtype=torch.uint8))   # not pinned
+        with pytest.raises(fftu.FftuError):
+            b.execute_ws_ptrs([x.data_ptr() for x in xs], [ws.data_ptr()] + [o.data_ptr() for o in outs[1:]],
+                              ws.data_ptr(), stage.data_ptr())    # an output inside the workspace
