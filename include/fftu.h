@@ -194,6 +194,32 @@ size_t fftu_plan_device_bytes(fftu_plan_t plan);
 fftu_status fftu_execute(fftu_plan_t plan, const void *in, void *out, hipStream_t stream);
 
 /*
+ * The transform of a real array (Section 6 names the real-to-complex FFT as the
+ * method's next transform). X is real, n_1 x ... x n_d with n_d even; its
+ * spectrum Y (eq. (1.2)) satisfies Y[-k] = conj Y[k], so the half k_d <= n_d/2
+ * holds all of it. Layouts (h = n_d / 2, n' = (n_1, ..., n_{d-1}, h)):
+ *   real side: the N reals of X as its packed complex view
+ *     z[j', j] = X[j', 2j] + i X[j', 2j + 1] (shape n'), in the cyclic buffer
+ *     layout above over the grid p, each element read as (re, im): N reals of the
+ *     plan's precision (double for FFTU_C128, float for FFTU_C64). With
+ *     p = (1, ..., 1) this is the row-major real array.
+ *   complex side: the half spectrum Y[k', k], k < h (shape n', cyclic over p: the
+ *     real side's layout), then the Nyquist plane Y[k', h] (shape n_1 x ... x
+ *     n_{d-1}, cyclic over p_1 x ... x p_{d-1}; one element for d = 1):
+ *     N/2 + N/n_d complex elements.
+ * fftu_plan_real(d, n, p, dtype, FFTU_FORWARD) maps the real side to the complex
+ * side (unnormalised); FFTU_INVERSE maps a complex side whose half spectrum
+ * belongs to a real array back to the real side, times 1/N. Requirements: n_d
+ * even, p_d | n_d/2 (else NOT_DIVISIBLE), and every requirement of fftu_plan for
+ * the complex array n' over p (the transform runs the complex path on z, then one
+ * pass that separates the even and odd halves of the last dimension; the inverse
+ * runs that pass first). Execute with fftu_execute; in == out is allowed (the
+ * buffer must hold the larger side), otherwise the buffers must not overlap.
+ * fftu_execute_ws, fftu_execute_noalloc and the stage calls refuse real plans.
+ */
+fftu_plan_t fftu_plan_real(int d, const int64_t n[], const int64_t p[], fftu_dtype dtype, fftu_direction direction);
+
+/*
  * Plans that own no device memory, for callers that manage HBM themselves (a
  * serving loop with its own arena). fftu_plan_external takes the same arguments
  * and applies the same checks as fftu_plan, but allocates nothing for the plan:

@@ -57,6 +57,13 @@ struct fftu_plan_s {
     bool lastx = false;              // k_lastx: the innermost dimension's lines fused with the exchange
     std::vector<PassDesc> s0x;       // the other Superstep 0 passes, run before k_lastx
     fftu::LastxDesc lx{};
+    // real-input transforms (fftu_plan_real): the complex plan of the packed array, the
+    // split / merge step and its omega_{n_d} table
+    bool real = false;
+    fftu_plan_s *rc = nullptr;
+    fftu::RealDesc rd{};
+    void *rtable = nullptr;
+    int64_t real_in_elems = 0, real_out_elems = 0;   // complex elements of each side's buffer
     // grids beyond p_max (some p_l^2 not dividing n_l): group-cyclic levels, several supersteps
     bool gc = false;
     int gc_H = 0;                                       // communication supersteps
@@ -1178,7 +1185,7 @@ bool aligned(const void *p, size_t esize) { return (reinterpret_cast<uintptr_t>(
 
 fftu_status check_exec_args(const fftu_plan_s *plan, const void *in, const void *out)
 {
-    if (!plan || !in || !out || plan->is_batch) return FFTU_ERROR_INVALID_VALUE;
+    if (!plan || !in || !out || plan->is_batch || plan->real) return FFTU_ERROR_INVALID_VALUE;
     if (!aligned(in, plan->esize) || !aligned(out, plan->esize)) return FFTU_ERROR_INVALID_VALUE;
     if (in != out) {
         const char *a = static_cast<const char *>(in);
@@ -1314,7 +1321,7 @@ fftu_status enqueue_batch(fftu_plan_s *pl, hipStream_t stream, Marker *mk = null
 }
 
 fftu_status execute_with(fftu_plan_s *plan, const void *in, void *out, void *ws, hipStream_t stream,
-                         const void *mul = nullptr);
+                         const void *mul = nullptr, Marker *outer = nullptr);
 
 }  // namespace
 
@@ -1738,6 +1745,77 @@ fftu_status fftu_describe(int d, const int64_t n[], const int64_t p[], fftu_dtyp
 fftu_plan_t fftu_plan(int d, const int64_t n[], const int64_t p[], fftu_dtype dtype, fftu_direction direction)
 {
     return build_plan(d, n, p, dtype, direction, false);
+}
+
+fftu_plan_t fftu_plan_real(int d, const int64_t n[], const int64_t p[], fftu_dtype dtype, fftu_direction direction)
+{
+    if (d < 1 || d > FFTU_MAX_DIMS || !n || !p) {
+        record(d > FFTU_MAX_DIMS ? FFTU_ERROR_UNSUPPORTED : FFTU_ERROR_INVALID_VALUE);
+        return nullptr;
+    }
+    if (n[d - 1] < 2 || n[d - 1] % 2 || p[d - 1] < 1 || (n[d - 1] / 2) % p[d - 1]) {
+        record(n[d - 1] >= 2 && n[d - 1] % 2 == 0 && p[d - 1] >= 1 ? FFTU_ERROR_NOT_DIVISIBLE
+                                                                      : FFTU_ERROR_INVALID_VALUE);
+        return nullptr;
+    }
+    int64_t np[fftu::kMaxDims];
+    for (int l = 0; l < d; ++l) np[l] = n[l];
+    np[d - 1] = n[d - 1] / 2;
+    fftu_plan_s *rc = build_plan(d, np, p, dtype, direction, false);
+    if (!rc) return nullptr;
+    fftu_plan_s *pl = new (std::nothrow) fftu_plan_s();
+    if (!pl) {
+        fftu_destroy(rc);
+        record(FFTU_ERROR_OUT_OF_MEMORY);
+        return nullptr;
+    }
+    pl->real = true;
+    pl->rc = rc;
+    pl->d = d;
+    for (int l = 0; l < d; ++l) {
+        pl->n[l] = n[l];
+        pl->p[l] = p[l];
+    }
+    pl->dtype = dtype;
+    pl->dir = direction;
+    pl->prec = rc->prec;
+    pl->esize = rc->esize;
+    pl->device = rc->device;
+    fftu::RealDesc &rd = pl->rd;
+    rd.d = d;
+    rd.h = int32_t(n[d - 1] / 2);
+    int64_t P = 1, Pp = 1, Nh = 1, Np = 1;
+    for (int l = 0; l < d; ++l) {
+        rd.n[l] = int32_t(np[l]);
+        rd.p[l] = int32_t(p[l]);
+        rd.m[l] = int32_t(np[l] / p[l]);
+        P *= p[l];
+        Nh *= np[l];
+        if (l < d - 1) {
+            Pp *= p[l];
+            Np *= n[l];
+        }
+    }
+    rd.Nh = Nh;
+    rd.Mh = Nh / P;
+    rd.Mp = Np / Pp;
+    pl->real_in_elems = direction == FFTU_FORWARD ? Nh : Nh + Np;
+    pl->real_out_elems = direction == FFTU_FORWARD ? Nh + Np : Nh;
+    pl->grid.N = Nh;
+    const std::string t = dtype == FFTU_C128 ? "double" : "float";
+    if (direction == FFTU_INVERSE) pl->launch_names.push_back("fftu::k_rmerge<" + t + ">");
+    for (const std::string &k : rc->launch_names) pl->launch_names.push_back(k);
+    if (direction == FFTU_FORWARD) pl->launch_names.push_back("fftu::k_rsplit<" + t + ">");
+    pl->launches = int(pl->launch_names.size());
+    pl->table_bytes = uint64_t(n[d - 1]) * pl->esize;
+    hipError_t e = upload_table_general(&pl->rtable, n[d - 1], dtype);
+    if (e != hipSuccess) {
+        fftu_destroy(pl);
+        record(from_hip(e));
+        return nullptr;
+    }
+    record(FFTU_SUCCESS);
+    return pl;
 }
 
 fftu_plan_t fftu_plan_external(int d, const int64_t n[], const int64_t p[], fftu_dtype dtype,
@@ -2230,6 +2308,16 @@ void fftu_graph_destroy(fftu_graph_t graph)
 fftu_status fftu_get_plan_info(fftu_plan_t plan, fftu_plan_info *info)
 {
     if (!plan || !info) return record(FFTU_ERROR_INVALID_VALUE);
+    if (plan->real) {
+        // the complex plan of the packed array, plus the split or merge pass
+        fftu_status st = fftu_get_plan_info(plan->rc, info);
+        if (st != FFTU_SUCCESS) return st;
+        info->N = 2 * plan->rd.Nh;
+        info->M = info->N / info->P;
+        info->launches += 1;
+        info->table_bytes += plan->table_bytes;
+        return record(FFTU_SUCCESS);
+    }
     if (plan->gc) {
         GcPlan gp;
         gp.H = plan->gc_H;
@@ -2452,20 +2540,30 @@ fftu_status execute_gc(fftu_plan_s *plan, const void *in, void *out, void *ws, h
     return from_hip(fftu::launch_pointwise(plan->prec, out, mul, out, plan->grid.N, 1.0, stream));
 }
 
-fftu_status execute_with(fftu_plan_s *plan, const void *in, void *out, void *ws, hipStream_t stream, const void *mul)
+fftu_status execute_real(fftu_plan_s *plan, const void *in, void *out, hipStream_t stream, Marker &mk);
+
+fftu_status execute_with(fftu_plan_s *plan, const void *in, void *out, void *ws, hipStream_t stream, const void *mul,
+                         Marker *outer)
 {
+    if (plan && plan->real) {
+        if (!in || !out || !aligned(in, plan->esize) || !aligned(out, plan->esize)) return FFTU_ERROR_INVALID_VALUE;
+        if (in != out) {
+            const char *a = static_cast<const char *>(in);
+            const char *b = static_cast<const char *>(out);
+            if (a < b + plan->real_out_elems * plan->esize && b < a + plan->real_in_elems * plan->esize)
+                return FFTU_ERROR_INVALID_VALUE;   // partial overlap
+        }
+        Marker mk(plan, stream);
+        mk.mark();
+        return execute_real(plan, in, out, stream, mk);
+    }
     fftu_status s = check_exec_args(plan, in, out);
     if (s != FFTU_SUCCESS) return s;
-    Marker mk(plan, stream);
-    if (plan->gc) {
-        mk.mark();
-        return execute_gc(plan, in, out, ws, stream, mul, mk);
-    }
-    if (plan->mixed) {
-        mk.mark();
-        return execute_mixed(plan, in, out, ws, stream, mul, mk);
-    }
-    mk.mark();
+    Marker own(plan, stream);
+    Marker &mk = outer ? *outer : own;
+    if (!outer) mk.mark();   // the start event (an outer marker has recorded its own)
+    if (plan->gc) return execute_gc(plan, in, out, ws, stream, mul, mk);
+    if (plan->mixed) return execute_mixed(plan, in, out, ws, stream, mul, mk);
     const int inv = plan->dir == FFTU_INVERSE ? 1 : 0;
     const double scale = inv ? 1.0 / double(plan->grid.N) : 1.0;
     const void *src = in;
@@ -2543,6 +2641,27 @@ fftu_status execute_with(fftu_plan_s *plan, const void *in, void *out, void *ws,
     return from_hip(fftu::launch_pointwise(plan->prec, out, mul, out, plan->grid.N, 1.0, stream));
 }
 
+}  // namespace
+
+namespace {
+// Real-input transforms: forward = the complex transform of the packed array into
+// the output, then the split in place; inverse = the merge into the output, then
+// the inverse complex transform in place.
+fftu_status execute_real(fftu_plan_s *plan, const void *in, void *out, hipStream_t stream, Marker &mk)
+{
+    fftu_plan_s *rc = plan->rc;
+    if (plan->dir == FFTU_FORWARD) {
+        fftu_status s = execute_with(rc, in, out, rc->ws, stream, nullptr, &mk);
+        if (s != FFTU_SUCCESS) return s;
+        hipError_t e = fftu::launch_rsplit(plan->prec, out, plan->rd, plan->rtable, stream);
+        if (e == hipSuccess) mk.mark();
+        return from_hip(e);
+    }
+    hipError_t e = fftu::launch_rmerge(plan->prec, in, out, plan->rd, plan->rtable, stream);
+    if (e != hipSuccess) return from_hip(e);
+    mk.mark();
+    return execute_with(rc, out, out, rc->ws, stream, nullptr, &mk);
+}
 }  // namespace
 
 namespace fftu {
@@ -2695,6 +2814,10 @@ void fftu_destroy(fftu_plan_t plan)
         fftu_destroy(plan->conv_inv);
         plan->conv_inv = nullptr;
     }
+    if (plan->rc) {
+        fftu_destroy(plan->rc);
+        plan->rc = nullptr;
+    }
     int cur = 0;
     const bool have_cur = hipGetDevice(&cur) == hipSuccess;
     if (have_cur && cur != plan->device) (void)hipSetDevice(plan->device);
@@ -2702,6 +2825,7 @@ void fftu_destroy(fftu_plan_t plan)
     free_batch(plan);
     if (plan->table && !plan->external) (void)hipFree(plan->table);
     if (plan->ws) (void)hipFree(plan->ws);
+    if (plan->rtable) (void)hipFree(plan->rtable);
     if (have_cur && cur != plan->device) (void)hipSetDevice(cur);
     delete plan;
     record(FFTU_SUCCESS);

@@ -276,6 +276,20 @@ struct GroupPutDesc {
     double scale;
     GroupPutDim dim[kMaxDims];
 };
+// The real-input transform (fftu_real.hip): the packed complex array of shape
+// n' = (n_1, ..., n_{d-1}, n_d/2), cyclic over p, and the Nyquist plane of shape
+// (n_1, ..., n_{d-1}), cyclic over (p_1, ..., p_{d-1}), stored after it.
+struct RealDesc {
+    int32_t d;
+    int32_t h;              // n_d / 2
+    int64_t Nh;             // elements of the packed array (N / 2)
+    int64_t Mh;             // of them per processor (Nh / P)
+    int64_t Mp;             // elements of the Nyquist plane per processor of dimensions 1..d-1
+    int32_t n[kMaxDims];    // n'
+    int32_t p[kMaxDims];
+    int32_t m[kMaxDims];    // n'_l / p_l
+};
+
 // k_mexchange: P sources of 64 local indices in LDS, grid sides of one radix stage.
 constexpr int64_t kMexMaxP = 64;
 constexpr int kMexThreads = 512;
@@ -398,6 +412,13 @@ hipError_t launch_long(Precision prec, const void *in, void *out, const PassDesc
                        hipStream_t stream);
 hipError_t launch_lastx(Precision prec, const void *in, void *out, const LastxDesc &lx, const void *table,
                         hipStream_t stream);
+// The real-input transform's steps around the complex transform of the packed
+// array (fftu_real.hip); `table` holds omega_{n_d}^j, j in [n_d]. rsplit: in place
+// on buf (forward; writes the Nyquist plane after the Nh packed elements). rmerge:
+// from in (half spectrum and plane) to out (Nh elements; in == out allowed).
+hipError_t launch_rsplit(Precision prec, void *buf, const RealDesc &rd, const void *table, hipStream_t stream);
+hipError_t launch_rmerge(Precision prec, const void *in, void *out, const RealDesc &rd, const void *table,
+                         hipStream_t stream);
 // One communication superstep of a group-cyclic plan (fftu_gcyclic.hip); in != out when g.permute.
 hipError_t launch_gput(Precision prec, const void *in, void *out, const GroupPutDesc &g, const void *table,
                        hipStream_t stream);

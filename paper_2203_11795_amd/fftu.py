@@ -25,7 +25,7 @@ STATUS = {0: "FFTU_SUCCESS", 1: "FFTU_ERROR_INVALID_VALUE", 2: "FFTU_ERROR_NOT_D
 
 # Every entry point declared in include/fftu.h.
 EXPORTS = ["fftu_version", "fftu_status_string", "fftu_last_error", "fftu_check", "fftu_describe", "fftu_plan",
-           "fftu_get_plan_info", "fftu_plan_device_bytes", "fftu_execute", "fftu_plan_external", "fftu_execute_ws", "fftu_execute_noalloc",
+           "fftu_get_plan_info", "fftu_plan_device_bytes", "fftu_execute", "fftu_plan_external", "fftu_execute_ws", "fftu_execute_noalloc", "fftu_plan_real",
            "fftu_stage_local_fft",
            "fftu_stage_twiddle", "fftu_stage_exchange", "fftu_stage_remaining_fft", "fftu_stage_superstep", "fftu_timing_begin",
            "fftu_timing_end", "fftu_set_tuning", "fftu_get_tuning", "fftu_launch_name", "fftu_plan_batch", "fftu_execute_batch", "fftu_batch_error",
@@ -91,6 +91,8 @@ def load_library(path: str = LIB_PATH):
     lib.fftu_stage_superstep.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, vp, vp]
     lib.fftu_plan_external.restype = vp
     lib.fftu_plan_external.argtypes = [ctypes.c_int, i64p, i64p, ctypes.c_int, ctypes.c_int]
+    lib.fftu_plan_real.restype = vp
+    lib.fftu_plan_real.argtypes = [ctypes.c_int, i64p, i64p, ctypes.c_int, ctypes.c_int]
     lib.fftu_execute_ws.restype = ctypes.c_int
     lib.fftu_execute_ws.argtypes = [vp, vp, vp, vp, vp]
     lib.fftu_execute_noalloc.restype = ctypes.c_int
@@ -380,6 +382,52 @@ class Plan:
 
     def __exit__(self, *exc):
         self.close()
+
+
+class RealPlan(Plan):
+    """The transform of a real array (fftu_plan_real). Forward: a real tensor of N
+    values (float64 for dtype complex128, float32 for complex64; the packed cyclic
+    layout) to a complex tensor of N/2 + N/n_d elements (the half spectrum cyclic
+    over p, then the Nyquist plane). Inverse: the other way, times 1/N."""
+
+    def __init__(self, n, p, dtype="complex128", direction=FORWARD):
+        self.n = tuple(int(v) for v in n)
+        self.p = tuple(int(v) for v in p)
+        if len(self.n) != len(self.p):
+            raise ValueError("n and p must have the same length")
+        self.dtype_code = _dtype_code(dtype)
+        self.direction = int(direction)
+        self.external = False
+        self._lib = load_library()
+        h = self._lib.fftu_plan_real(len(self.n), _arr(self.n), _arr(self.p), self.dtype_code, self.direction)
+        if not h:
+            raise FftuError(self._lib.fftu_last_error(), "fftu_plan_real")
+        self._h = ctypes.c_void_p(h)
+        self.N = _prod(self.n)
+        self.complex_elems = self.N // 2 + self.N // self.n[-1]
+
+    @property
+    def real_dtype(self):
+        import torch
+        return torch.float64 if self.dtype_code == C128 else torch.float32
+
+    def __call__(self, x, out=None, stream=None):
+        import torch
+        fwd = self.direction == FORWARD
+        in_dt, in_n = (self.real_dtype, self.N) if fwd else (self.torch_dtype, self.complex_elems)
+        out_dt, out_n = (self.torch_dtype, self.complex_elems) if fwd else (self.real_dtype, self.N)
+        for t, dt, n, name in ((x, in_dt, in_n, "input"), (out, out_dt, out_n, "output")):
+            if t is None:
+                continue
+            if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != dt or t.numel() != n \
+                    or not t.is_contiguous():
+                raise ValueError(f"{name} must be a contiguous {dt} device tensor of {n} elements")
+        if out is None:
+            out = torch.empty(out_n, dtype=out_dt, device=x.device)
+        if stream is None:
+            stream = torch.cuda.current_stream(x.device)
+        self.execute_ptr(x.data_ptr(), out.data_ptr(), int(stream.cuda_stream), "fftu_execute")
+        return out
 
 
 class ConvolutionPlan(Plan):

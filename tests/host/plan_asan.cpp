@@ -73,6 +73,16 @@ hipError_t launch_lastx(Precision, const void *, void *, const LastxDesc &lx, co
     return hipSuccess;
 }
 hipError_t launch_batch_reset(const BatchDesc &, hipStream_t) { return hipSuccess; }
+hipError_t launch_rsplit(Precision, void *, const RealDesc &rd, const void *, hipStream_t)
+{
+    if (rd.d < 1 || rd.Nh < 1 || rd.h < 1) std::abort();
+    return hipSuccess;
+}
+hipError_t launch_rmerge(Precision, const void *, void *, const RealDesc &rd, const void *, hipStream_t)
+{
+    if (rd.d < 1 || rd.Nh < 1 || rd.h < 1) std::abort();
+    return hipSuccess;
+}
 hipError_t launch_gput(Precision, const void *in, void *out, const GroupPutDesc &g, const void *, hipStream_t)
 {
     if (g.d < 1 || g.d > kMaxDims || g.N < 1 || g.M < 1 || g.T < 1 || (g.permute && in == out)) std::abort();
