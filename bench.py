@@ -707,6 +707,18 @@ def run_serving(args, torch, synth):
             c = out[policy]
             c["p99_speedup_vs_fifo"] = round(f["p99_ms"] / c["p99_ms"], 3) if c["p99_ms"] > 0 else None
             c["p50_speedup_vs_fifo"] = round(f["p50_ms"] / c["p50_ms"], 3) if c["p50_ms"] > 0 else None
+        # a burst: the trace's first 2000 requests of at most 4 MiB, all arriving at once, where
+        # requests wait together and coalescing has something to gather
+        burst = [serving.Request(r.rid, 0.0, r.shape, r.dtype, r.direction) for r in reqs
+                 if r.N * r.esize <= srv.coalesce_bytes][:2000]
+        out["burst"] = {"workload": f"{len(burst)} requests of at most {srv.coalesce_bytes >> 20} MiB from the "
+                                    "trace, all arriving at t = 0"}
+        for policy in ("continuous", "coalesced"):
+            res = srv.serve(burst, policy, time_limit=60)
+            out["burst"][policy] = {k: v for k, v in serving.summarize(res, burst).items()
+                                    if k in ("completed", "p50_ms", "p99_ms", "mean_ms", "max_ms", "wall_s", "batches",
+                                             "coalesced_requests", "max_batch")}
+            log(f"[bench] serving burst {policy}: {out['burst'][policy]}")
         if not args.no_check:
             import numpy as np
             log("[bench] serving: FP32 error of every complex64 result against complex128")

@@ -107,7 +107,11 @@ typedef enum {
     FFTU_TUNE_MAX_LDS_KB = 3,        /* LDS budget per workgroup of a pass, KiB (16..160; default 64) */
     FFTU_TUNE_FUSE_LAST = 4,         /* 0: never fuse the innermost dimension's lines into the exchange; 1 / -1: when possible */
     FFTU_TUNE_PAIR = 5,              /* 0: one pass per strided dimension; 1 / -1: two adjacent dimensions of 8..32-point lines share a pass */
-    FFTU_TUNE_COUNT = 6
+    FFTU_TUNE_MIXED_RADIX = 6,       /* largest power-of-two radix of a mixed-radix line (2, 4, 8; default 8). Unlike
+                                        the other knobs this changes the arithmetic: results move within rounding */
+    FFTU_TUNE_MIXED_TILE_LOG = 7,    /* log2 elements per mixed-radix pass tile (9..12; default 10 for complex128,
+                                        11 for complex64) */
+    FFTU_TUNE_COUNT = 8
 } fftu_tune_param;
 
 /* Set a tuning knob; FFTU_ERROR_INVALID_VALUE for an unknown knob or a value out of range. */

@@ -108,10 +108,10 @@ thread_local fftu_status g_last = FFTU_SUCCESS;
 
 // Planner tuning knobs (fftu_set_tuning); -1 = default.
 // Planner knobs (fftu_set_tuning): process-wide, read when a plan is made.
-std::atomic<int> g_tune[FFTU_TUNE_COUNT] = {{-1}, {-1}, {-1}, {-1}, {-1}, {-1}};
+std::atomic<int> g_tune[FFTU_TUNE_COUNT] = {{-1}, {-1}, {-1}, {-1}, {-1}, {-1}, {-1}, {-1}};
 int knob(int i) { return g_tune[i].load(std::memory_order_relaxed); }
-const int g_tune_min[FFTU_TUNE_COUNT] = {2, 0, 0, 16, 0, 0};
-const int g_tune_max[FFTU_TUNE_COUNT] = {6, 8, 4, 160, 1, 1};
+const int g_tune_min[FFTU_TUNE_COUNT] = {2, 0, 0, 16, 0, 0, 2, 9};
+const int g_tune_max[FFTU_TUNE_COUNT] = {6, 8, 4, 160, 1, 1, 8, 12};
 
 int64_t lds_cap()
 {
@@ -847,18 +847,23 @@ std::vector<double> make_table_general(int64_t T)
 }
 
 // Radix stages of a mixed-radix line: 8s, then a 4 or a 2, then 7s, 5s, 3s.
+// The largest power-of-two radix comes from the knob FFTU_TUNE_MIXED_RADIX (2, 4 or
+// 8; default 8): radix R stages first, then one 4 or 2 for what is left of the
+// power of two, then 7s, 5s, 3s.
 int mixed_radices(int64_t L, int32_t *out)
 {
+    const int kr = knob(FFTU_TUNE_MIXED_RADIX);
+    const int R = kr >= 8 || kr < 2 ? 8 : (kr >= 4 ? 4 : 2);
     int n = 0;
-    while (L % 8 == 0 && n < fftu::kMixedMaxStages) {
-        out[n++] = 8;
-        L /= 8;
+    while (L % R == 0 && n < fftu::kMixedMaxStages) {
+        out[n++] = R;
+        L /= R;
     }
-    if (L % 4 == 0) {
+    if (R > 4 && L % 4 == 0 && n < fftu::kMixedMaxStages) {
         out[n++] = 4;
         L /= 4;
     }
-    if (L % 2 == 0) {
+    if (R > 2 && L % 2 == 0 && n < fftu::kMixedMaxStages) {
         out[n++] = 2;
         L /= 2;
     }
@@ -877,7 +882,8 @@ bool make_mixed_pass(int64_t A, int64_t L, int64_t B, fftu_dtype dt, int64_t T, 
     const int64_t cap = 64 * 1024;
     pd.nstages = mixed_radices(L, pd.radix);
     if (pd.nstages < 0) return false;
-    const int64_t target = dt == FFTU_C128 ? 1024 : 2048;   // elements per tile
+    const int kt = knob(FFTU_TUNE_MIXED_TILE_LOG);
+    const int64_t target = kt >= 9 ? (int64_t(1) << kt) : (dt == FFTU_C128 ? 1024 : 2048);   // elements per tile
     int64_t W = 1;
     while (W * 2 * L <= target && W < 256) W *= 2;
     while (W > 1 && W / 2 >= A * B) W /= 2;                  // no tile much wider than the lines there are

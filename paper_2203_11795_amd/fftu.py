@@ -33,7 +33,8 @@ EXPORTS = ["fftu_version", "fftu_status_string", "fftu_last_error", "fftu_check"
            "fftu_graph_capture", "fftu_graph_launch", "fftu_graph_destroy", "fftu_fill_uniform", "fftu_plan_convolution",
            "fftu_execute_convolution", "fftu_pointwise_mul", "fftu_destroy"]
 
-TUNE = {"line_strided_logw": 0, "line_contig_logw": 1, "line_pad": 2, "max_lds_kb": 3, "fuse_last": 4, "pair": 5}
+TUNE = {"line_strided_logw": 0, "line_contig_logw": 1, "line_pad": 2, "max_lds_kb": 3, "fuse_last": 4, "pair": 5,
+        "mixed_radix": 6, "mixed_tile_log": 7}
 
 
 class FftuError(RuntimeError):

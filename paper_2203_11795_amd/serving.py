@@ -26,15 +26,17 @@ Three policies over the same arena, plan cache and kernels:
                 each take twice as long), while small requests never queue
                 behind a large one. A large lane with no large request waiting
                 takes a small one.
-  "coalesced"   "continuous", and the requests of at most `coalesce_bytes` that
-                the persistent batch kernel supports (every local side n_l/2 <=
-                256) always run through it: a free stream takes the first waiting
-                one together with up to `coalesce_max` - 1 more of the same dtype
-                and direction that wait with it, and runs them as one batch
-                (fftu_plan_batch_external: a host-only plan; its work list goes
-                over from a page-locked staging ring, its workspace comes from the
-                arena). A request alone runs as a batch of one, so its result is
-                bitwise the same alone and coalesced.
+  "coalesced"   "continuous", and when a free stream finds the first waiting
+                request small (at most `coalesce_bytes`, a shape the persistent
+                batch kernel supports: every local side n_l/2 <= 256) with at
+                least one more such request of the same dtype and direction
+                waiting, it takes up to `coalesce_max` of them and runs them as
+                one batch launch (fftu_plan_batch_external: a host-only plan,
+                cached per composition; its work list goes over from a
+                page-locked staging ring, its workspace comes from the arena). A
+                small request that waits alone runs as in "continuous". Members of
+                a batch are bitwise the same as in a batch of one, and within the
+                dtype's tolerance of the per-request path.
   "fifo"        one request at a time on one stream; the host waits for each to
                 finish before it starts the next (the plain baseline).
 """
@@ -194,6 +196,7 @@ class ServeResult:
     batches: int = 0                                 # launches of the persistent batch kernel ("coalesced")
     coalesced_requests: int = 0                      # requests served by them
     max_batch: int = 0
+    coalesced_rids: set = field(default_factory=set)
 
 
 class Server:
@@ -221,11 +224,30 @@ class Server:
                         for _ in range(int(staging_slots))]
         self.slot_busy = [None] * len(self.staging)
         self._batchable = {}
+        self.batch_plans = collections.OrderedDict()     # composition -> external BatchPlan (host-only)
+        self.batch_plan_cap = 1024
 
     def close(self):
         self.plans.close()
+        for bp in self.batch_plans.values():
+            bp.close()
+        self.batch_plans.clear()
         self.mem = None
         self.staging = []
+
+    def _batch_plan(self, group):
+        key = (tuple(r.shape for r in group), group[0].dtype, group[0].direction)
+        bp = self.batch_plans.get(key)
+        if bp is not None:
+            self.batch_plans.move_to_end(key)
+            return bp
+        bp = _b.BatchPlan([r.shape for r in group], [r.grid for r in group], group[0].dtype, group[0].direction,
+                          external=True)
+        self.batch_plans[key] = bp
+        if len(self.batch_plans) > self.batch_plan_cap:
+            _, old = self.batch_plans.popitem(last=False)
+            old.close()                       # host-only: enqueued work does not refer to it
+        return bp
 
     def batchable(self, req: Request) -> bool:
         """Whether the coalesced policy runs this request through the batch kernel:
@@ -281,30 +303,25 @@ class Server:
         slot = self._free_slot()
         if slot < 0:
             return None
-        first = group[0]
-        bp = _b.BatchPlan([r.shape for r in group], [r.grid for r in group], first.dtype, first.direction,
-                          external=True)
-        try:
-            if bp.staging_bytes > self.staging[slot].numel():
-                return None
-            blocks = []
-            for r in group:
-                a = arena.alloc(r.N * r.esize)
-                if a is None:
-                    break
-                blocks.append(a)
-            w = arena.alloc(bp.workspace_bytes) if len(blocks) == len(group) else None
-            if w is None:
-                for blk in blocks:
-                    arena.release(*blk)
-                return None
-            bufs = [self._view(a[0], r) for a, r in zip(blocks, group)]
-            for r, buf in zip(group, bufs):
-                _b.fill_uniform(buf, self.seed, r.rid, 0, stream=stream)
-            bp.execute_ws_ptrs([b.data_ptr() for b in bufs], [b.data_ptr() for b in bufs],
-                               self.mem.data_ptr() + w[0], self.staging[slot].data_ptr(), int(stream.cuda_stream))
-        finally:
-            bp.close()                    # host-only plan: the enqueued work does not refer to it
+        bp = self._batch_plan(group)
+        if bp.staging_bytes > self.staging[slot].numel():
+            return None
+        blocks = []
+        for r in group:
+            a = arena.alloc(r.N * r.esize)
+            if a is None:
+                break
+            blocks.append(a)
+        w = arena.alloc(bp.workspace_bytes) if len(blocks) == len(group) else None
+        if w is None:
+            for blk in blocks:
+                arena.release(*blk)
+            return None
+        bufs = [self._view(a[0], r) for a, r in zip(blocks, group)]
+        for r, buf in zip(group, bufs):
+            _b.fill_uniform(buf, self.seed, r.rid, 0, stream=stream)
+        bp.execute_ws_ptrs([b.data_ptr() for b in bufs], [b.data_ptr() for b in bufs],
+                           self.mem.data_ptr() + w[0], self.staging[slot].data_ptr(), int(stream.cuda_stream))
         end = self.torch.cuda.Event(enable_timing=True)
         end.record(stream)
         self.slot_busy[slot] = end
@@ -365,30 +382,29 @@ class Server:
             """Launch the head of q on stream s (with its coalescing partners); None if
             memory or a staging slot is lacking."""
             head = q[0]
-            if not (coalesce and self.batchable(head)):
+            group, idx = [head], [0]
+            if coalesce and self.batchable(head):
+                for j in range(1, min(len(q), 4 * self.coalesce_max)):
+                    if len(group) >= self.coalesce_max:
+                        break
+                    r = q[j]
+                    if r.dtype == head.dtype and r.direction == head.direction and self.batchable(r):
+                        group.append(r)
+                        idx.append(j)
+            run = self._launch_batch(group, arena, self.streams[s]) if len(group) > 1 else None
+            if run is None:
+                # nothing to coalesce with (or no memory or staging slot for the group now):
+                # the head alone, by the per-request path
                 run = self._launch(head, arena, self.streams[s])
                 if run is not None:
                     q.popleft()
                 return run
-            group, idx = [head], [0]
-            for j in range(1, min(len(q), 4 * self.coalesce_max)):
-                if len(group) >= self.coalesce_max:
-                    break
-                r = q[j]
-                if r.dtype == head.dtype and r.direction == head.direction and self.batchable(r):
-                    group.append(r)
-                    idx.append(j)
-            run = self._launch_batch(group, arena, self.streams[s])
-            if run is None and len(group) > 1:   # too big for memory or staging now: the head alone
-                group, idx = [head], [0]
-                run = self._launch_batch(group, arena, self.streams[s])
-            if run is None:
-                return None
             for j in reversed(idx):
                 del q[j]
             res.batches += 1
             res.coalesced_requests += len(group)
             res.max_batch = max(res.max_batch, len(group))
+            res.coalesced_rids.update(r.rid for r in group)
             return run
 
         # continuous / coalesced: streams [0, large_lanes) serve the large class first; fifo: one queue

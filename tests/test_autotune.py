@@ -10,7 +10,8 @@ def test_search_finds_the_separable_minimum_and_restores_knobs(monkeypatch):
     state = {k: -1 for k in autotune.KNOB_NAMES}
     monkeypatch.setattr(autotune, "current", lambda: dict(state))
     monkeypatch.setattr(autotune, "apply", lambda knobs: state.update({k: int(knobs.get(k, -1)) for k in state}))
-    target = {"line_strided_logw": 4, "line_contig_logw": 2, "line_pad": 0, "max_lds_kb": 96, "fuse_last": -1, "pair": -1}
+    target = {"line_strided_logw": 4, "line_contig_logw": 2, "line_pad": 0, "max_lds_kb": 96, "fuse_last": -1, "pair": -1,
+              "mixed_radix": 4, "mixed_tile_log": -1}
 
     def cost():
         return 1.0 + sum(abs(state[k] - v) for k, v in target.items())
@@ -43,7 +44,7 @@ def test_wisdom_roundtrip(tmp_path, monkeypatch):
 
 def test_candidates_are_in_the_knob_ranges():
     lo_hi = {"line_strided_logw": (2, 6), "line_contig_logw": (0, 8), "line_pad": (0, 4), "max_lds_kb": (16, 160),
-             "fuse_last": (0, 1), "pair": (0, 1)}
+             "fuse_last": (0, 1), "pair": (0, 1), "mixed_radix": (2, 8), "mixed_tile_log": (9, 12)}
     for k, vals in autotune.CANDIDATES.items():
         assert vals[0] == -1
         for v in vals[1:]:
