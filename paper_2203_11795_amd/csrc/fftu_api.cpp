@@ -884,21 +884,24 @@ bool make_mixed_pass(int64_t A, int64_t L, int64_t B, fftu_dtype dt, int64_t T, 
     if (pd.nstages < 0) return false;
     const int kt = knob(FFTU_TUNE_MIXED_TILE_LOG);
     const int64_t target = kt >= 9 ? (int64_t(1) << kt) : (dt == FFTU_C128 ? 1024 : 2048);   // elements per tile
+    // strided lines: odd pitch in LDS, so that lanes over consecutive lines hit different banks;
+    // contiguous lines are loaded along the line, pitch L
+    const int64_t pitch = (B == 1 || L % 2) ? L : L + 1;
     int64_t W = 1;
-    while (W * 2 * L <= target && W < 256) W *= 2;
+    while (W * 2 * L <= target && W < fftu::kMixedMaxW) W *= 2;
     while (W > 1 && W / 2 >= A * B) W /= 2;                  // no tile much wider than the lines there are
-    while (W > 1 && (2 * W * L + L) * esize > cap) W /= 2;
-    if ((2 * W * L + L) * esize > cap) return false;
+    while (W > 1 && (2 * W * pitch + L) * esize > cap) W /= 2;
+    if ((2 * W * pitch + L) * esize > cap) return false;
     pd.A = A;
     pd.B = B;
     pd.L = int32_t(L);
     pd.W = int32_t(W);
     pd.logW = ilog2(W);
-    pd.nbt = 0;
+    pd.pitch = pitch;
     pd.tiles = (A * B + W - 1) / W;
     pd.tstep = T / L;
     pd.scale = 1.0;
-    pd.lds_bytes = uint32_t((2 * W * L + L) * esize);
+    pd.lds_bytes = uint32_t((2 * W * pitch + L) * esize);
     return true;
 }
 

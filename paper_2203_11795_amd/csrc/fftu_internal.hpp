@@ -217,6 +217,7 @@ struct LastxDesc {
 // Mixed-radix path (fftu_mixed.hip): sides with factors 2, 3, 5 and 7.
 constexpr int kMixedThreads = 256;
 constexpr int kMixedBatch = 4;         // global loads per thread in flight in k_mline
+constexpr int kMixedMaxW = 256;        // lines per k_mline tile at most
 constexpr int kMixedMaxStages = 24;
 
 // A pass of 1-D FFTs of length L over an array viewed as (A, L, B), B the
@@ -225,7 +226,8 @@ constexpr int kMixedMaxStages = 24;
 struct MixedPassDesc {
     int64_t A, B;
     int64_t tiles;         // ceil(A B / W)
-    int64_t nbt;           // unused
+    int64_t pitch;         // LDS elements per tile line: L, or L + 1 when L is even (odd: no bank conflicts
+                           // between consecutive lines)
     int32_t L;
     int32_t W, logW;
     int32_t nstages;

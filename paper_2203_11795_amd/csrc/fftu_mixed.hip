@@ -94,10 +94,11 @@ __device__ __forceinline__ int div_small(int n, int d, float inv)
     return q;
 }
 
-// One Stockham stage of radix R over `lines` lines of length L (src -> dst in LDS).
+// One Stockham stage of radix R over `lines` lines of length L (src -> dst in LDS;
+// line w starts at w * pitch).
 template <typename T, int R>
-__device__ __forceinline__ void mixed_stage(const cx<T> *src, cx<T> *dst, const cx<T> *tw, int L, int Ns, int lines,
-                                            int tid, int nt)
+__device__ __forceinline__ void mixed_stage(const cx<T> *src, cx<T> *dst, const cx<T> *tw, int L, int pitch, int Ns,
+                                            int lines, int tid, int nt)
 {
     const int LR = L / R;
     const int span = L / (Ns * R);          // omega_{Ns R} = omega_L^span
@@ -110,7 +111,7 @@ __device__ __forceinline__ void mixed_stage(const cx<T> *src, cx<T> *dst, const 
         const int j = bi - wl * LR;
         const int jd = div_small(j, Ns, inv_ns);
         const int k = j - jd * Ns;
-        const cx<T> *s = src + wl * L + j;
+        const cx<T> *s = src + wl * pitch + j;
         cx<T> x[8];
 #pragma unroll
         for (int r = 0; r < R; ++r) x[r] = s[r * LR];
@@ -119,7 +120,7 @@ __device__ __forceinline__ void mixed_stage(const cx<T> *src, cx<T> *dst, const 
             for (int r = 1; r < R; ++r) x[r] = cmul(x[r], tw[r * k * span]);
         }
         dft_small<T, R>(x, w, 1);
-        cx<T> *o = dst + wl * L + jd * Ns * R + k;
+        cx<T> *o = dst + wl * pitch + jd * Ns * R + k;
 #pragma unroll
         for (int r = 0; r < R; ++r) o[r * Ns] = x[r];
     }
@@ -132,10 +133,12 @@ __global__ __launch_bounds__(kMixedThreads) void k_mline(const cx<T> *in, cx<T> 
                                                          const cx<T> *__restrict__ table)
 {
     extern __shared__ unsigned char smem_raw[];
+    __shared__ int64_t lbase[kMixedMaxW];   // strided tiles: global offset of each line's first element
     const int L = pd.L, W = pd.W;
+    const int pitch = int(pd.pitch);   // strided tiles: odd, so consecutive lines fall on different LDS banks
     cx<T> *tw = reinterpret_cast<cx<T> *>(smem_raw);
     cx<T> *buf0 = tw + L;
-    cx<T> *buf1 = buf0 + W * L;
+    cx<T> *buf1 = buf0 + W * pitch;
     const int tid = threadIdx.x;
     // launch sizes in scalar registers: the tile loop holds barriers
     const int nt = __builtin_amdgcn_readfirstlane(int(blockDim.x));
@@ -150,22 +153,31 @@ __global__ __launch_bounds__(kMixedThreads) void k_mline(const cx<T> *in, cx<T> 
         const uint32_t total = uint32_t(pd.A) * B;
         const int lines = int(total - u0 < uint32_t(W) ? total - u0 : uint32_t(W));
         __syncthreads();   // twiddle copy done / previous tile's LDS reads done
+        if (B != 1) {
+            // line u = a B + b starts at (a L) B + b: one division per line, not per element
+            for (int w = tid; w < lines; w += nt) {
+                const uint32_t u = u0 + uint32_t(w);
+                const uint32_t a = u / B;
+                lbase[w] = int64_t(a) * L * B + (u - a * B);
+            }
+            __syncthreads();
+        }
         const int n = lines * L;
+        const float inv_lines = 1.0f / float(lines);
         // element e of the tile: LDS offset (line w, position x) and global offset. With
-        // B = 1 the tile's lines are contiguous in memory and e runs along them; otherwise
-        // lanes run over consecutive lines (consecutive b: runs of up to min(W, B) elements).
+        // B = 1 the tile's lines are contiguous in memory and e runs along them (the LDS
+        // pitch is L there); otherwise lanes run over consecutive lines (consecutive b:
+        // runs of up to min(W, B) elements). e < 2^22, so the quotient comes from one
+        // float estimate and a correction.
         auto where = [&](int e, int &off) -> int64_t {
             if (B == 1) {
                 off = e;
                 return int64_t(u0) * L + e;
             }
-            const int x = e / lines;
+            const int x = div_small(e, lines, inv_lines);
             const int w = e - x * lines;
-            off = w * L + x;
-            const uint32_t u = u0 + uint32_t(w);
-            const uint32_t a = u / B;
-            const uint32_t b = u - a * B;
-            return (int64_t(a) * L + x) * B + b;
+            off = w * pitch + x;
+            return lbase[w] + int64_t(x) * B;
         };
         // kMixedBatch loads per thread in flight, then their LDS stores
         for (int e0 = tid; e0 < n; e0 += kMixedBatch * nt) {
@@ -185,12 +197,12 @@ __global__ __launch_bounds__(kMixedThreads) void k_mline(const cx<T> *in, cx<T> 
         int Ns = 1;
         for (int s = 0; s < pd.nstages; ++s) {
             switch (pd.radix[s]) {
-            case 2: mixed_stage<T, 2>(src, dst, tw, L, Ns, lines, tid, nt); break;
-            case 3: mixed_stage<T, 3>(src, dst, tw, L, Ns, lines, tid, nt); break;
-            case 4: mixed_stage<T, 4>(src, dst, tw, L, Ns, lines, tid, nt); break;
-            case 5: mixed_stage<T, 5>(src, dst, tw, L, Ns, lines, tid, nt); break;
-            case 7: mixed_stage<T, 7>(src, dst, tw, L, Ns, lines, tid, nt); break;
-            case 8: mixed_stage<T, 8>(src, dst, tw, L, Ns, lines, tid, nt); break;
+            case 2: mixed_stage<T, 2>(src, dst, tw, L, pitch, Ns, lines, tid, nt); break;
+            case 3: mixed_stage<T, 3>(src, dst, tw, L, pitch, Ns, lines, tid, nt); break;
+            case 4: mixed_stage<T, 4>(src, dst, tw, L, pitch, Ns, lines, tid, nt); break;
+            case 5: mixed_stage<T, 5>(src, dst, tw, L, pitch, Ns, lines, tid, nt); break;
+            case 7: mixed_stage<T, 7>(src, dst, tw, L, pitch, Ns, lines, tid, nt); break;
+            case 8: mixed_stage<T, 8>(src, dst, tw, L, pitch, Ns, lines, tid, nt); break;
             default: break;
             }
             __syncthreads();
