@@ -514,14 +514,15 @@ def run_real(args, torch, np, fftu, synth, with_oracle):
 
 def run_paper_workloads(args, torch, fftu):
     """The paper's own test sizes on one GPU: 1024^3 complex128 (4^3 grid, the fused
-    exchange) and the very rectangular 16,777,216 x 64 (complex64 on a 4096 x 8 grid:
-    the only grids for it have a local line of 4096, and P = 32768 takes the unfused
-    exchange). Input from the device generator; checked by the round trip (forward,
+    exchange) and the very rectangular 16,777,216 x 64 (complex64 and complex128 on a
+    4096 x 8 grid: the only grids for it have a local line of 4096, and P = 32768 takes
+    the unfused exchange). Input from the device generator; checked by the round trip (forward,
     then inverse, against the input) on the device, and the forward transform of a
     sparse input at 500 sampled outputs against eq. (1.2)."""
     import numpy as np
     res = []
-    for n, p, dt in [((1024, 1024, 1024), (4, 4, 4), "complex128"), ((1 << 24, 64), (4096, 8), "complex64")]:
+    for n, p, dt in [((1024, 1024, 1024), (4, 4, 4), "complex128"), ((1 << 24, 64), (4096, 8), "complex64"),
+                     ((1 << 24, 64), (4096, 8), "complex128")]:
         N = math.prod(n)
         tdt = torch.complex128 if dt == "complex128" else torch.complex64
         log(f"[bench] paper workload {'x'.join(map(str, n))} {dt}")
@@ -753,7 +754,7 @@ def main():
     ap.add_argument("--no-group-cyclic", action="store_true",
                     help="skip the grid beyond p_max (512^3 over 32^3, two supersteps)")
     ap.add_argument("--no-paper", action="store_true",
-                    help="skip the paper's own sizes (1024^3 complex128, 16777216 x 64 complex64)")
+                    help="skip the paper's own sizes (1024^3 complex128, 16777216 x 64 complex64 and complex128)")
     ap.add_argument("--no-small", action="store_true", help="skip the 64^3 latency workload")
     ap.add_argument("--no-precision", action="store_true", help="skip the 64^5 complex64 precision workload")
     ap.add_argument("--serving-seconds", type=float, default=30.0,

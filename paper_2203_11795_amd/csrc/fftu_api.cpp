@@ -235,7 +235,16 @@ fftu_status validate(int d, const int64_t n[], const int64_t p[], fftu_dtype dty
         int logN = 0;
         for (int l = 0; l < d; ++l) {
             logN += ilog2(n[l]);
-            if (n[l] / p[l] > max_len(dtype) || p[l] > max_len(dtype)) return FFTU_ERROR_UNSUPPORTED;
+            if (n[l] / p[l] > max_len(dtype) || p[l] > max_len(dtype)) {
+                // complex128 lines of 4096 points exist only in k_long, for rows of at most 8
+                // columns after the dimension (Superstep 0: the local sides after l;
+                // Superstep 2: q_l times them)
+                if (dtype != FFTU_C128 || n[l] / p[l] > 4096 || p[l] > 4096) return FFTU_ERROR_UNSUPPORTED;
+                int64_t after = 1;
+                for (int j = l + 1; j < d; ++j) after *= n[j] / p[j];
+                if (n[l] / p[l] == 4096 && after > 8) return FFTU_ERROR_UNSUPPORTED;
+                if (p[l] == 4096 && (n[l] / p[l] / p[l]) * after > 8) return FFTU_ERROR_UNSUPPORTED;
+            }
         }
         if (logN >= 40) return FFTU_ERROR_UNSUPPORTED;
         return FFTU_SUCCESS;
@@ -357,9 +366,9 @@ bool make_line_pass(int logA, int logL, int logB, fftu_dtype dt, int lognmax, Pa
 bool make_long_pass(int logA, int logL, int logB, fftu_dtype dt, int lognmax, PassDesc &pd)
 {
     const int esize = dt == FFTU_C128 ? 16 : 8;
-    if (logL < fftu::kLongMinLogL || logL > fftu::kLongMaxLogL || (esize == 16 && logL != 11)) return false;
+    if (logL < fftu::kLongMinLogL || logL > fftu::kLongMaxLogL) return false;
     const int logW = fftu::long_logw(logL, esize);
-    if (logB > logW + 2 || logA + logB < logW) return false;
+    if (logB > logW + (logW == 0 ? 3 : 2) || logA + logB < logW) return false;
     const int64_t tiles = int64_t(1) << (logA + logB - logW);
     if (tiles > fftu::kLongMaxTiles) return false;
     pd = PassDesc{};

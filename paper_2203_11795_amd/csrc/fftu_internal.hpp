@@ -122,7 +122,8 @@ constexpr int64_t pair_max_tiles(int lognt) { return int64_t(1) << (31 - lognt);
 
 // k_long (fftu_long.hip): 512 threads hold W whole lines of L = 2^11 or 2^12 points,
 // E elements per thread: 16 complex64 (W = 2 for L = 4096, 4 for L = 2048) or 8
-// complex128 (W = 2, L = 2048), within 128 VGPRs so that two workgroups share a CU.
+// complex128 (W = 2 for L = 2048, 1 for L = 4096), within 128 VGPRs so that two
+// workgroups share a CU.
 // A tile is W / B whole outer blocks when rows have B <= W columns, or W of the
 // B = 2W or 4W columns of one outer block. LDS: two twiddle tables of 64 and L / 64
 // entries, then W rows of long_pitch words of one real part.

@@ -1,7 +1,8 @@
 // k_long: batched 1-D FFTs of long lines (2^11 or 2^12 points) along a dimension
 // whose rows are short (B elements after it), for Superstep 0 (and the unfused
 // Superstep 2) of Algorithm 2.3 (arXiv 2203.11795) where no per-thread split of
-// k_line fits: a line of 4096 complex64 spans 32 KiB.
+// k_line fits: a line of 4096 complex64 spans 32 KiB, of 4096 complex128 64 KiB
+// (W = 1 line per workgroup, up to B = 8 columns: eight tiles share each line).
 //
 // A workgroup of 512 threads takes W whole lines (E = 16 complex64 or 8 complex128
 // elements per thread, within 128 VGPRs, so two workgroups share a CU and one loads
@@ -117,7 +118,7 @@ __global__ __launch_bounds__(kLongThreads) void k_long(const cx<T> *in, cx<T> *o
     constexpr int NT = kLongThreads;
     constexpr int LOGW = long_logw(LOGL, int(sizeof(T) * 2));
     constexpr int LOGTPL = kLongLogThreads - LOGW;
-    static_assert(LOGB <= LOGW + 2, "rows of at most 4 W columns");
+    static_assert(LOGB <= LOGW + (LOGW == 0 ? 3 : 2), "rows of at most 4 W columns (8 when W = 1)");
     using PL = LongPlan<LOGL, LOGL - LOGTPL, LOGL - LOGTPL>;
     constexpr int E = PL::E, L = PL::L, TPL = PL::TPL;
     static_assert(E * NT == (L << LOGW), "the tile is W whole lines");
@@ -132,7 +133,7 @@ __global__ __launch_bounds__(kLongThreads) void k_long(const cx<T> *in, cx<T> *o
     }
     const int j = tid & (TPL - 1), w = tid >> LOGTPL;
     constexpr int lb = LOGB;   // compile-time, so that the staged LDS addresses fold into offsets
-    // tile index: with B = G W (G = 2 or 4) the G tiles of a block are workgroups
+    // tile index: with B = G W (G = 2, 4, or 8 when W = 1) the G tiles of a block are workgroups
     // v, v + 8, ..., which run on one XCD at the same time (a bijection on each
     // aligned run of 8 G)
     constexpr int LOGG = LOGB > LOGW ? LOGB - LOGW : 0;
@@ -249,7 +250,8 @@ template <typename T, int LOGL, int LOGB = 0>
 hipError_t launch_long_b(const void *in, void *out, const PassDesc &pd, const void *table, hipStream_t stream)
 {
     if (pd.logB == LOGB) return launch_long_t<T, LOGL, LOGB>(in, out, pd, table, stream);
-    if constexpr (LOGB <= long_logw(LOGL, int(sizeof(T) * 2)) + 1)
+    constexpr int logw = long_logw(LOGL, int(sizeof(T) * 2));
+    if constexpr (LOGB < logw + (logw == 0 ? 3 : 2))
         return launch_long_b<T, LOGL, LOGB + 1>(in, out, pd, table, stream);
     return hipErrorInvalidValue;
 }
@@ -262,6 +264,7 @@ hipError_t launch_long(Precision prec, const void *in, void *out, const PassDesc
     if (pd.kind != kLong || pd.naxes != 1) return hipErrorInvalidValue;
     const int logL = pd.loglen[0];
     if (prec == Precision::F64) {
+        if (logL == 12) return launch_long_b<double, 12>(in, out, pd, table, stream);
         if (logL == 11) return launch_long_b<double, 11>(in, out, pd, table, stream);
     } else {
         if (logL == 12) return launch_long_b<float, 12>(in, out, pd, table, stream);

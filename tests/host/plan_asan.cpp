@@ -274,6 +274,8 @@ int main()
         // grids beyond p_max: group-cyclic levels, several supersteps
         {{512, 512, 512}, {32, 32, 32}}, {{16, 16}, {8, 2}}, {{1024}, {64}}, {{64, 64, 64}, {16, 16, 8}},
         {{8, 27}, {4, 9}}, {{16}, {8}},
+        // complex128 lines of 4096 (k_long with one line per tile) in both supersteps
+        {{1 << 24, 2}, {4096, 1}},
     };
     int bad = 0;
     for (const Case &c : cases) {

@@ -4,8 +4,8 @@ per-thread split of k_line fits.
 Checked against the FP64 oracle through the C ABI: the local-FFT stage alone
 (against the oracle's per-block local FFT) and whole transforms, forward and
 inverse, for every compiled line length, rows of B = 1..16 (several outer blocks
-per tile, one, or a half or quarter of one with the pieces grouped on an XCD),
-and the unfused Superstep 2 of a grid with p_1 = 2048. Tolerances (relative L2): 1e-12 complex128, 5e-6 complex64.
+per tile, one, or a half, quarter or eighth of one with the pieces grouped on an
+XCD), and the unfused Superstep 2 of grids with p_1 = 2048 and 4096. Tolerances (relative L2): 1e-12 complex128, 5e-6 complex64.
 """
 import sys
 
@@ -36,6 +36,12 @@ CASES = [
     ((8, 4096, 16), (2, 2, 2), "complex128", (11, 3)),
     ((2048, 8), (1, 2), "complex128", (11, 2)),      # p_1 = 1, rows of 4 = 2 W
     ((2048, 4), (1, 2), "complex128", (11, 1)),      # rows of 2 = W: one block per tile
+    # 4096-point complex128: W = 1 line per tile, rows of up to 8 = 8 W columns
+    ((8192, 16), (2, 2), "complex128", (12, 3)),     # rows of 8: an eighth of a row per tile
+    ((8, 8192, 16), (2, 2, 2), "complex128", (12, 3)),  # 512 tiles, grouped by eight on an XCD
+    ((8192, 8), (2, 2), "complex128", (12, 2)),      # rows of 4
+    ((8192, 2), (2, 1), "complex128", (12, 1)),      # rows of 2
+    ((8192,), (2,), "complex128", (12, 0)),          # one line per tile
 ]
 IDS = [f"{'x'.join(map(str, n))}-p{'x'.join(map(str, p))}-{dt}" for n, p, dt, _ in CASES]
 
@@ -98,3 +104,19 @@ def test_unfused_superstep2_with_long_lines(torch_dev, direction):
         assert plan.info()["exchange_fused"] == 0
         got = run(torch_dev, plan, D, "complex64")
     assert oracle.rel_l2(got, oracle.cyclic_dft(D, n, p, direction)) <= TOL["complex64"]
+
+
+@pytest.mark.parametrize("direction", [FORWARD, INVERSE])
+def test_unfused_superstep2_with_long_complex128_lines(torch_dev, direction):
+    """p_1 = 4096 in complex128 (one line per tile): Superstep 2's transforms along p_1
+    on k_long<double, 12>, rows of q_1 = 1 times the local side 2 after it."""
+    import paper_2203_11795_amd as fftu
+    n, p = (1 << 24, 2), (4096, 1)
+    N = int(np.prod(n))
+    say(f"long S2 c128 n={n} p={p} dir={direction}")
+    D = synth.uniform_complex(N, 33, np.complex128)
+    with fftu.Plan(n, p, "complex128", direction) as plan:
+        names = plan.launch_names()
+        assert names.count("fftu::k_long<double, 12, 1>") == 2 and names[-1] == "fftu::k_long<double, 12, 1>", names
+        got = run(torch_dev, plan, D, "complex128")
+    assert oracle.rel_l2(got, oracle.cyclic_dft(D, n, p, direction)) <= TOL["complex128"]

@@ -25,4 +25,4 @@ def test_planner_under_asan(tmp_path):
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0")
     r = subprocess.run([str(exe)], capture_output=True, text=True, env=env, timeout=120)
     assert r.returncode == 0, r.stdout + r.stderr
-    assert r.stdout.count("describe=") == 64 and r.stdout.count("batch plan=") == 2
+    assert r.stdout.count("describe=") == 66 and r.stdout.count("batch plan=") == 2
