@@ -67,7 +67,9 @@ struct fftu_plan_s {
     // grids beyond p_max (some p_l^2 not dividing n_l): group-cyclic levels, several supersteps
     bool gc = false;
     int gc_H = 0;                                       // communication supersteps
+    bool gc_pow2 = false;                                   // phases on the power-of-two pass kernels
     std::vector<std::vector<fftu::MixedPassDesc>> gphase;   // computation phases 0..H: local FFT passes
+    std::vector<std::vector<PassDesc>> gphase2;             // the same with every side a power of two
     std::vector<fftu::GroupPutDesc> gput;                   // communication supersteps 0..H-1 (twiddle + Put)
     // per-kernel timing (fftu_timing_begin / fftu_timing_end)
     std::vector<std::string> launch_names;   // kernel of each launch of fftu_execute
@@ -519,33 +521,41 @@ bool make_pair_pass(int logA, int logLA, int logLB, int logB, fftu_dtype dt, int
     return true;
 }
 
-// Superstep 0: the local d-D FFT as a sequence of passes, innermost dimension
-// first (the order is free: the DFT factorises over dimensions, eq. (1.3)).
-// The two innermost dimensions share one k_group2 pass when their planes are
-// small; further dimensions share k_pair passes two by two where their lines
-// are short, and the rest get one pass each.
-// skip_last: leave the innermost dimension out (k_ttranspose runs it).
-std::vector<PassDesc> plan_s0(const Geometry &G, fftu_dtype dt, bool skip_last = false)
+// Passes over the block array (P, m_1, ..., m_d) (2^logP blocks, sides 2^logm[l]) that
+// transform lines of 2^len[l] points along each dimension with len[l] > 0, the
+// points 2^sub[l] elements apart inside that dimension's own extent (len + sub =
+// logm: sub = 0 is the whole side). Innermost dimension first (the order is free:
+// the DFT factorises over dimensions, eq. (1.3)). The two innermost dimensions
+// share one k_group2 pass when they are whole, contiguous (B = 1) and their planes
+// small (allow_group2); further whole dimensions with nothing between them share
+// k_pair passes two by two where their lines are short; the rest get one pass each.
+std::vector<PassDesc> plan_local(int d, int logP, const int logm[], const int len[], const int sub[], fftu_dtype dt,
+                                 int lognmax, bool allow_group2)
 {
     std::vector<PassDesc> passes;
-    std::vector<int> dims;   // dimensions with m_l > 1, innermost first
-    for (int l = G.d - 1 - (skip_last ? 1 : 0); l >= 0; --l)
-        if (G.logm[l] > 0) dims.push_back(l);
+    std::vector<int> dims;   // dimensions with lines to transform, innermost first
+    for (int l = d - 1; l >= 0; --l)
+        if (len[l] > 0) dims.push_back(l);
     auto outer_of = [&](int l) {
-        int logA = G.logP;
-        for (int j = 0; j < l; ++j) logA += G.logm[j];
+        int logA = logP;
+        for (int j = 0; j < l; ++j) logA += logm[j];
         return logA;
     };
     auto inner_of = [&](int l) {
         int logB = 0;
-        for (int j = l + 1; j < G.d; ++j) logB += G.logm[j];
+        for (int j = l + 1; j < d; ++j) logB += logm[j];
         return logB;
     };
+    // whole sides li (inner) and lo (outer) with no elements between them
+    auto adjacent = [&](int lo, int li) {
+        return sub[lo] == 0 && sub[li] == 0 && inner_of(lo) == logm[li] + inner_of(li);
+    };
     size_t first = 0;
-    if (dims.size() >= 2 && !skip_last) {
+    if (dims.size() >= 2 && allow_group2) {
         PassDesc pd;
         const int li = dims[0], lo = dims[1];
-        if (make_group2_pass(outer_of(lo), G.logm[lo], G.logm[li], dt, G.lognmax, pd)) {
+        if (inner_of(li) == 0 && adjacent(lo, li) &&
+            make_group2_pass(outer_of(lo), len[lo], len[li], dt, lognmax, pd)) {
             passes.push_back(pd);
             first = 2;
         }
@@ -553,15 +563,28 @@ std::vector<PassDesc> plan_s0(const Geometry &G, fftu_dtype dt, bool skip_last =
     for (size_t i = first; i < dims.size(); ++i) {
         const int l = dims[i];
         PassDesc pd;
-        if (i + 1 < dims.size() &&
-            make_pair_pass(outer_of(dims[i + 1]), G.logm[dims[i + 1]], G.logm[l], inner_of(l), dt, G.lognmax, pd)) {
+        if (i + 1 < dims.size() && adjacent(dims[i + 1], l) &&
+            make_pair_pass(outer_of(dims[i + 1]), len[dims[i + 1]], len[l], inner_of(l), dt, lognmax, pd)) {
             passes.push_back(pd);
             ++i;
             continue;
         }
-        passes.push_back(make_pass(outer_of(l), {G.logm[l]}, inner_of(l), dt, G.lognmax));
+        passes.push_back(make_pass(outer_of(l), {len[l]}, inner_of(l) + sub[l], dt, lognmax));
     }
     return passes;
+}
+
+// Superstep 0: the local d-D FFT (every side whole).
+// skip_last: leave the innermost dimension out (k_ttranspose runs it).
+std::vector<PassDesc> plan_s0(const Geometry &G, fftu_dtype dt, bool skip_last = false)
+{
+    int len[fftu::kMaxDims], sub[fftu::kMaxDims];
+    for (int l = 0; l < G.d; ++l) {
+        len[l] = G.logm[l];
+        sub[l] = 0;
+    }
+    if (skip_last) len[G.d - 1] = 0;
+    return plan_local(G.d, G.logP, G.logm, len, sub, dt, G.lognmax, !skip_last);
 }
 
 // Superstep 2 in unfused form: one pass per grid dimension with p_l > 1; inside a
@@ -991,12 +1014,22 @@ void fill_info_mixed(const MixedPlan &mp, fftu_dtype dt, fftu_plan_info *info)
 // levels left (c <= h_l), and the length-p_h FFTs of every dimension whose last
 // Put was superstep c - 1 (local index s' q + t, lines along s'). Superstep c:
 // one k_gput with each dimension's Put of level c (none for finished dimensions).
+//
+// When every side is a power of two the phases run on the power-of-two pass kernels
+// (k_line, k_long, k_group2, k_pair: the same passes as Superstep 0 of the cyclic
+// path), else on k_mline.
 struct GcPlan {
     int H = 0;
     int64_t T = 1, N = 1, P = 1, M = 1;
-    std::vector<std::vector<fftu::MixedPassDesc>> phase;
+    bool pow2 = false;
+    std::vector<std::vector<fftu::MixedPassDesc>> phase;   // mixed radix
+    std::vector<std::vector<PassDesc>> phase2;             // powers of two
     std::vector<fftu::GroupPutDesc> put;
+    size_t phase_size(size_t c) const { return pow2 ? phase2[c].size() : phase[c].size(); }
 };
+
+// A pass that its kernel can run (the tile pass has no check of its own).
+bool pass_fits(const PassDesc &pd) { return pd.kind != fftu::kTilePass || int64_t(pd.lds_bytes) <= lds_cap(); }
 
 bool plan_gc(int d, const int64_t n[], const int64_t p[], fftu_dtype dt, GcPlan &gp)
 {
@@ -1012,7 +1045,38 @@ bool plan_gc(int d, const int64_t n[], const int64_t p[], fftu_dtype dt, GcPlan 
         gp.T = lcm64(gp.T, n[l]);
     }
     gp.M = gp.N / gp.P;
-    for (int c = 0; c <= gp.H; ++c) {
+    bool all_pow2 = true;
+    for (int l = 0; l < d; ++l) all_pow2 = all_pow2 && is_pow2(n[l]);
+    if (all_pow2) {
+        int logm[fftu::kMaxDims], logP = 0, lognmax = 0;
+        for (int l = 0; l < d; ++l) {
+            logm[l] = ilog2(m[l]);
+            logP += ilog2(p[l]);
+            lognmax = std::max(lognmax, ilog2(n[l]));
+        }
+        bool ok = true;
+        for (int c = 0; c <= gp.H && ok; ++c) {
+            int len[fftu::kMaxDims], sub[fftu::kMaxDims];
+            for (int l = 0; l < d; ++l) {
+                len[l] = sub[l] = 0;
+                if (c <= lv[l].h) {
+                    len[l] = logm[l];                                  // level c's local F_m
+                } else if (c == lv[l].h + 1) {
+                    len[l] = ilog2(lv[l].p[lv[l].h]);                  // level h's length-p_h FFTs
+                    sub[l] = logm[l] - len[l];
+                }
+            }
+            std::vector<PassDesc> ph = plan_local(d, logP, logm, len, sub, dt, lognmax, true);
+            for (const PassDesc &pd : ph) ok = ok && pass_fits(pd);
+            gp.phase2.push_back(ph);
+        }
+        if (ok) {
+            gp.pow2 = true;
+        } else {
+            gp.phase2.clear();
+        }
+    }
+    for (int c = 0; c <= gp.H && !gp.pow2; ++c) {
         std::vector<fftu::MixedPassDesc> ph;
         for (int l = d - 1; l >= 0; --l) {
             int64_t A = gp.P, B = 1;
@@ -1073,10 +1137,10 @@ void fill_info_gc(const GcPlan &gp, int d, fftu_dtype dt, fftu_plan_info *info)
     info->N = gp.N;
     info->P = gp.P;
     info->M = gp.M;
-    info->s0_kernels = int32_t(gp.phase[0].size());
+    info->s0_kernels = int32_t(gp.phase_size(0));
     info->exchange_fused = 0;
     int rest = gp.H;
-    for (size_t c = 1; c < gp.phase.size(); ++c) rest += int(gp.phase[c].size());
+    for (size_t c = 1; c <= size_t(gp.H); ++c) rest += int(gp.phase_size(c));
     info->s2_kernels = rest;
     info->launches = info->s0_kernels + rest;
     info->supersteps = gp.H;
@@ -1547,6 +1611,8 @@ fftu_plan_s *build_gc_plan(int d, const int64_t n[], const int64_t p[], fftu_dty
     pl->gc = true;
     pl->gc_H = gp.H;
     pl->gphase = gp.phase;
+    pl->gphase2 = gp.phase2;
+    pl->gc_pow2 = gp.pow2;
     pl->gput = gp.put;
     pl->table_T = gp.T;
     pl->grid.N = gp.N;
@@ -1554,7 +1620,11 @@ fftu_plan_s *build_gc_plan(int d, const int64_t n[], const int64_t p[], fftu_dty
     pl->grid.d = d;
     const std::string t = dtype == FFTU_C128 ? "double" : "float";
     for (int c = 0; c <= gp.H; ++c) {
-        for (size_t i = 0; i < gp.phase[size_t(c)].size(); ++i) pl->launch_names.push_back("fftu::k_mline<" + t + ">");
+        if (gp.pow2) {
+            for (const PassDesc &pd : gp.phase2[size_t(c)]) pl->launch_names.push_back(pass_kernel_name(pd, dtype));
+        } else {
+            for (size_t i = 0; i < gp.phase[size_t(c)].size(); ++i) pl->launch_names.push_back("fftu::k_mline<" + t + ">");
+        }
         if (c < gp.H) pl->launch_names.push_back("fftu::k_gput<" + t + ">");
     }
     pl->launches = int(pl->launch_names.size());
@@ -2344,6 +2414,8 @@ fftu_status fftu_get_plan_info(fftu_plan_t plan, fftu_plan_info *info)
         gp.M = plan->grid.M;
         gp.P = plan->grid.N / plan->grid.M;
         gp.phase = plan->gphase;
+        gp.phase2 = plan->gphase2;
+        gp.pow2 = plan->gc_pow2;
         gp.put = plan->gput;
         fill_info_gc(gp, plan->d, plan->dtype, info);
         return record(FFTU_SUCCESS);
@@ -2523,6 +2595,19 @@ fftu_status execute_mixed(fftu_plan_s *plan, const void *in, void *out, void *ws
     return from_hip(fftu::launch_pointwise(plan->prec, out, mul, out, plan->mg.N, 1.0, stream));
 }
 
+// Computation phase c of a group-cyclic plan.
+bool gc_phase_empty(const fftu_plan_s *pl, int c)
+{
+    return pl->gc_pow2 ? pl->gphase2[size_t(c)].empty() : pl->gphase[size_t(c)].empty();
+}
+
+fftu_status run_gc_phase(const fftu_plan_s *pl, int c, const void *in, void *out, int conj_first, int conj_last,
+                         double scale_last, hipStream_t stream, Marker *mk = nullptr)
+{
+    if (pl->gc_pow2) return run_passes(pl, pl->gphase2[size_t(c)], in, out, conj_first, conj_last, scale_last, stream, mk);
+    return run_mixed_passes(pl, pl->gphase[size_t(c)], in, out, conj_first, conj_last, scale_last, stream, mk);
+}
+
 // Grids beyond p_max: computation phase 0 (reads `in`), then H times a k_gput
 // (twiddle and Put, out of place) and the next phase's passes (in place). The
 // buffers alternate between `out` and the workspace so that the last Put lands
@@ -2534,12 +2619,12 @@ fftu_status execute_gc(fftu_plan_s *plan, const void *in, void *out, void *ws, h
     const double scale = inv ? 1.0 / double(plan->grid.N) : 1.0;
     const int H = plan->gc_H;
     auto buf = [&](int c) -> void * { return ((H - c) % 2 == 0) ? out : ws; };
-    const bool last_empty = plan->gphase[size_t(H)].empty();
-    fftu_status s = run_mixed_passes(plan, plan->gphase[0], in, buf(0), inv, 0, 1.0, stream, &mk);
+    const bool last_empty = gc_phase_empty(plan, H);
+    fftu_status s = run_gc_phase(plan, 0, in, buf(0), inv, 0, 1.0, stream, &mk);
     if (s != FFTU_SUCCESS) return s;
     for (int c = 0; c < H; ++c) {
         fftu::GroupPutDesc g = plan->gput[size_t(c)];
-        g.conj_in = (c == 0 && plan->gphase[0].empty()) ? inv : 0;
+        g.conj_in = (c == 0 && gc_phase_empty(plan, 0)) ? inv : 0;
         g.conj_out = 0;
         g.scale = 1.0;
         if (c == H - 1 && last_empty) {
@@ -2550,8 +2635,7 @@ fftu_status execute_gc(fftu_plan_s *plan, const void *in, void *out, void *ws, h
         if (e != hipSuccess) return from_hip(e);
         mk.mark();
         const bool last = c + 1 == H;
-        s = run_mixed_passes(plan, plan->gphase[size_t(c + 1)], buf(c + 1), buf(c + 1), 0, last ? inv : 0,
-                             last ? scale : 1.0, stream, &mk);
+        s = run_gc_phase(plan, c + 1, buf(c + 1), buf(c + 1), 0, last ? inv : 0, last ? scale : 1.0, stream, &mk);
         if (s != FFTU_SUCCESS) return s;
     }
     if (!mul) return FFTU_SUCCESS;
@@ -2811,7 +2895,7 @@ fftu_status fftu_stage_superstep(fftu_plan_t plan, int phase, int part, const vo
         return part == 1 ? fftu_stage_twiddle(plan, in, out, stream) : fftu_stage_exchange(plan, in, out, stream);
     }
     const int inv = plan->dir == FFTU_INVERSE ? 1 : 0;
-    if (part == 0) return record(run_mixed_passes(plan, plan->gphase[size_t(phase)], in, out, inv, inv, 1.0, stream));
+    if (part == 0) return record(run_gc_phase(plan, phase, in, out, inv, inv, 1.0, stream));
     fftu::GroupPutDesc g = plan->gput[size_t(phase)];
     g.scale = 1.0;
     if (part == 1) {

@@ -145,7 +145,9 @@ def test_describe(n, p, dtype, s0, fused, launches):
 
 @pytest.mark.parametrize("n,p,supersteps,launches", [
     ((8,), (4,), 2, 5),                       # F_2, Put, F_2, Put, F_2
-    ((512, 512, 512), (32, 32, 32), 2, 11),   # 3 local passes, Put, 3 passes, Put, 3 passes of length 2
+    # 16^3 local blocks: a k_group2 pass of the two inner sides and a k_line pass, Put, the
+    # same two passes, Put, 3 passes of length 2
+    ((512, 512, 512), (32, 32, 32), 2, 9),
     ((16, 16), (8, 2), 3, 9),
     ((1024,), (64,), 2, 5),
 ])

@@ -47,6 +47,7 @@ GRIDS = [
     ((27, 8), (9, 4)),              # mixed radix: 27 over 9 (m = 3), then 9 over 3
     ((125,), (25,)),
     ((2, 8, 8, 4), (1, 4, 4, 2)),
+    ((1 << 20, 8), (2048, 2)),      # lines of 512 and length-4 FFTs 128 apart, over 4096 blocks
 ]
 
 
@@ -129,6 +130,24 @@ def test_puts_move_exactly_the_emulators_elements(torch, n, p):
             y = plan.superstep(c, 2, x)
             torch.cuda.synchronize()
             assert np.array_equal(y.cpu().numpy(), gc.put_superstep(idx, n, p, c)), f"Put {c}"
+
+
+def test_kernels_of_each_phase(torch):
+    """Power-of-two sides run the phases on the power-of-two pass kernels (the
+    passes of the cyclic path's Superstep 0), other sides on k_mline."""
+    import paper_2203_11795_amd as fftu
+    with fftu.Plan((512, 512, 512), (32, 32, 32), "complex128") as plan:
+        names = plan.launch_names()
+    # 16^3 blocks: the two inner sides in one k_group2 pass, the outer side in a k_line
+    # pass; the last phase's length-2 FFTs one k_line pass per dimension
+    assert len(names) == 9 and names[2] == names[5] == "fftu::k_gput<double>", names
+    assert names[0] == names[3] == "fftu::k_group2<double, 4, 4>", names
+    assert all(k.startswith("fftu::k_line<double, 4,") for k in (names[1], names[4])), names
+    assert all(k.startswith("fftu::k_line<double, 1,") for k in names[6:]), names
+    with fftu.Plan((27, 8), (9, 4), "complex64") as plan:
+        names = plan.launch_names()
+    assert names.count("fftu::k_gput<float>") == 2 and all(k in ("fftu::k_gput<float>", "fftu::k_mline<float>")
+                                                            for k in names), names
 
 
 def _cyclic_position(j, n, p):
