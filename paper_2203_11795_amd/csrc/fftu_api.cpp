@@ -68,6 +68,7 @@ struct fftu_plan_s {
     bool gc = false;
     int gc_H = 0;                                       // communication supersteps
     bool gc_pow2 = false;                                   // phases on the power-of-two pass kernels
+    int gc_last_logg = 0;                                   // > 0: k_gplast fuses the last Put and phase H
     std::vector<std::vector<fftu::MixedPassDesc>> gphase;   // computation phases 0..H: local FFT passes
     std::vector<std::vector<PassDesc>> gphase2;             // the same with every side a power of two
     std::vector<fftu::GroupPutDesc> gput;                   // communication supersteps 0..H-1 (twiddle + Put)
@@ -1022,10 +1023,18 @@ struct GcPlan {
     int H = 0;
     int64_t T = 1, N = 1, P = 1, M = 1;
     bool pow2 = false;
+    int last_logg = 0;   // > 0: k_gplast runs the last Put and phase H (2^last_logg elements per thread)
     std::vector<std::vector<fftu::MixedPassDesc>> phase;   // mixed radix
     std::vector<std::vector<PassDesc>> phase2;             // powers of two
     std::vector<fftu::GroupPutDesc> put;
     size_t phase_size(size_t c) const { return pow2 ? phase2[c].size() : phase[c].size(); }
+    // launches of the whole transform
+    int launches() const
+    {
+        int k = H;
+        for (int c = 0; c <= H; ++c) k += int(phase_size(size_t(c)));
+        return last_logg > 0 ? k - int(phase_size(size_t(H))) : k;
+    }
 };
 
 // A pass that its kernel can run (the tile pass has no check of its own).
@@ -1126,6 +1135,15 @@ bool plan_gc(int d, const int64_t n[], const int64_t p[], fftu_dtype dt, GcPlan 
         }
         gp.put.push_back(g);
     }
+    // The last Put (every dimension in mode 2 or 0) and phase H (the length-p_h FFTs of
+    // the mode-2 dimensions) in one k_gplast pass when the FFTs of one thread fit in
+    // its registers.
+    if (gp.pow2) {
+        int logg = 0;
+        for (int l = 0; l < d; ++l)
+            if (gp.put[size_t(gp.H - 1)].dim[l].mode == 2) logg += ilog2(gp.put[size_t(gp.H - 1)].dim[l].pi);
+        if (logg >= 1 && logg <= fftu::kGplastMaxLogG && gp.N < (int64_t(1) << 31)) gp.last_logg = logg;
+    }
     return true;
 }
 
@@ -1139,10 +1157,8 @@ void fill_info_gc(const GcPlan &gp, int d, fftu_dtype dt, fftu_plan_info *info)
     info->M = gp.M;
     info->s0_kernels = int32_t(gp.phase_size(0));
     info->exchange_fused = 0;
-    int rest = gp.H;
-    for (size_t c = 1; c <= size_t(gp.H); ++c) rest += int(gp.phase_size(c));
-    info->s2_kernels = rest;
-    info->launches = info->s0_kernels + rest;
+    info->launches = gp.launches();
+    info->s2_kernels = info->launches - info->s0_kernels;
     info->supersteps = gp.H;
     info->workspace_bytes = uint64_t(gp.N) * esize;
     info->table_bytes = uint64_t(gp.T) * esize;
@@ -1613,6 +1629,7 @@ fftu_plan_s *build_gc_plan(int d, const int64_t n[], const int64_t p[], fftu_dty
     pl->gphase = gp.phase;
     pl->gphase2 = gp.phase2;
     pl->gc_pow2 = gp.pow2;
+    pl->gc_last_logg = gp.last_logg;
     pl->gput = gp.put;
     pl->table_T = gp.T;
     pl->grid.N = gp.N;
@@ -1620,12 +1637,16 @@ fftu_plan_s *build_gc_plan(int d, const int64_t n[], const int64_t p[], fftu_dty
     pl->grid.d = d;
     const std::string t = dtype == FFTU_C128 ? "double" : "float";
     for (int c = 0; c <= gp.H; ++c) {
+        if (c == gp.H && gp.last_logg > 0) break;
         if (gp.pow2) {
             for (const PassDesc &pd : gp.phase2[size_t(c)]) pl->launch_names.push_back(pass_kernel_name(pd, dtype));
         } else {
             for (size_t i = 0; i < gp.phase[size_t(c)].size(); ++i) pl->launch_names.push_back("fftu::k_mline<" + t + ">");
         }
-        if (c < gp.H) pl->launch_names.push_back("fftu::k_gput<" + t + ">");
+        if (c + 1 == gp.H && gp.last_logg > 0)
+            pl->launch_names.push_back("fftu::k_gplast<" + t + ", " + std::to_string(gp.last_logg) + ">");
+        else if (c < gp.H)
+            pl->launch_names.push_back("fftu::k_gput<" + t + ">");
     }
     pl->launches = int(pl->launch_names.size());
     hipError_t e = hipSuccess;
@@ -2416,6 +2437,7 @@ fftu_status fftu_get_plan_info(fftu_plan_t plan, fftu_plan_info *info)
         gp.phase = plan->gphase;
         gp.phase2 = plan->gphase2;
         gp.pow2 = plan->gc_pow2;
+        gp.last_logg = plan->gc_last_logg;
         gp.put = plan->gput;
         fill_info_gc(gp, plan->d, plan->dtype, info);
         return record(FFTU_SUCCESS);
@@ -2609,9 +2631,10 @@ fftu_status run_gc_phase(const fftu_plan_s *pl, int c, const void *in, void *out
 }
 
 // Grids beyond p_max: computation phase 0 (reads `in`), then H times a k_gput
-// (twiddle and Put, out of place) and the next phase's passes (in place). The
-// buffers alternate between `out` and the workspace so that the last Put lands
-// in `out`: phase c runs in `out` when H - c is even.
+// (twiddle and Put, out of place) and the next phase's passes (in place); with
+// power-of-two sides the last Put and phase H run as one k_gplast. The buffers
+// alternate between `out` and the workspace so that the last Put lands in `out`:
+// phase c runs in `out` when H - c is even.
 fftu_status execute_gc(fftu_plan_s *plan, const void *in, void *out, void *ws, hipStream_t stream, const void *mul,
                        Marker &mk)
 {
@@ -2627,6 +2650,15 @@ fftu_status execute_gc(fftu_plan_s *plan, const void *in, void *out, void *ws, h
         g.conj_in = (c == 0 && gc_phase_empty(plan, 0)) ? inv : 0;
         g.conj_out = 0;
         g.scale = 1.0;
+        if (c == H - 1 && plan->gc_last_logg > 0) {
+            // the last Put and phase H's length-p_h FFTs in one pass, the chain's last store
+            g.conj_out = inv;
+            g.scale = scale;
+            hipError_t e = fftu::launch_gplast(plan->prec, buf(c), buf(c + 1), g, plan->table, stream);
+            if (e != hipSuccess) return from_hip(e);
+            mk.mark();
+            break;
+        }
         if (c == H - 1 && last_empty) {
             g.conj_out = inv;
             g.scale = scale;

@@ -101,6 +101,242 @@ __global__ __launch_bounds__(256) void k_gput(const cx<T> *__restrict__ in, cx<T
     }
 }
 
+namespace {
+
+// In-register DFT along bits [POS, POS + R) of the group index (natural order).
+template <typename T, int LOGG, int POS, int R>
+__device__ __forceinline__ void dft_axis(cx<T> (&v)[1 << LOGG])
+{
+    if constexpr (POS + R <= LOGG) {
+        constexpr int G = 1 << LOGG, L = 1 << R;
+#pragma unroll
+        for (int base = 0; base < G; ++base) {
+            if ((base >> POS) & (L - 1)) continue;
+            cx<T> x[L];
+#pragma unroll
+            for (int i = 0; i < L; ++i) x[i] = v[base + (i << POS)];
+            Dft<T, L>::run(x);
+#pragma unroll
+            for (int i = 0; i < L; ++i) v[base + (i << POS)] = x[i];
+        }
+    }
+}
+
+template <typename T, int LOGG, int POS>
+__device__ __forceinline__ void dft_axis_r(cx<T> (&v)[1 << LOGG], int r)
+{
+    switch (r) {
+    case 1: dft_axis<T, LOGG, POS, 1>(v); break;
+    case 2: dft_axis<T, LOGG, POS, 2>(v); break;
+    case 3: dft_axis<T, LOGG, POS, 3>(v); break;
+    case 4: dft_axis<T, LOGG, POS, 4>(v); break;
+    default: break;
+    }
+}
+
+template <typename T, int LOGG>
+__device__ __forceinline__ void dft_axis_at(cx<T> (&v)[1 << LOGG], int pos, int r)
+{
+    switch (pos) {
+    case 0: dft_axis_r<T, LOGG, 0>(v, r); break;
+    case 1: dft_axis_r<T, LOGG, 1>(v, r); break;
+    case 2: dft_axis_r<T, LOGG, 2>(v, r); break;
+    case 3: dft_axis_r<T, LOGG, 3>(v, r); break;
+    default: break;
+    }
+}
+
+}  // namespace
+
+// The last communication superstep of a plan whose sides are powers of two, with
+// the length-p_h FFTs that follow it (Algorithm 2.2's Superstep 2 of every
+// dimension whose level h this is) in the same pass. Every dimension is then in
+// mode 2 (its last Put) or mode 0 (done). A thread takes the G = prod p_h
+// elements that one set of those FFTs combines: source local index k (per
+// dimension s_k = rho + t p_h) and the source group b (mode 2) or processor
+// (mode 0), all members s of the groups. It gathers them (consecutive threads
+// read consecutive k of one source processor), applies the level's twiddle
+// omega^(s s_k), runs the length-p_h DFTs along each dimension's s in
+// registers, and stores output s' of dimension l at local s' q + t of processor
+// rho m^h + rev(b). The FFT output index replaces s in place, so the
+// destination is the Put's destination of the same s.
+template <typename T, int LOGG>
+__global__ __launch_bounds__(256) void k_gplast(const cx<T> *__restrict__ in, cx<T> *__restrict__ out,
+                                                const GroupPutDesc g, const cx<T> *__restrict__ table)
+{
+    constexpr int G = 1 << LOGG;
+    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    const T scale = static_cast<T>(g.scale);
+    const uint32_t M = uint32_t(g.M), T_ = uint32_t(g.T);
+    const int logM = __builtin_ctz(M);
+    const int d = g.d;
+    // bit j of the group index: the source offset, the destination offset (both uniform)
+    // and the dimension that owns it
+    uint32_t srcw[LOGG > 0 ? LOGG : 1], dstw[LOGG > 0 ? LOGG : 1];
+    int owner[LOGG > 0 ? LOGG : 1], shift[LOGG > 0 ? LOGG : 1];
+    {
+        uint32_t pstride = 1, mstride = 1;
+        int pos = 0;
+        for (int l = d - 1; l >= 0; --l) {
+            const GroupPutDim &D = g.dim[l];
+            if (D.mode == 2) {
+                const int r = __builtin_ctz(uint32_t(D.pi));
+#pragma unroll
+                for (int j = 0; j < LOGG; ++j)
+                    if (j >= pos && j < pos + r) {
+                        srcw[j] = (pstride << (j - pos)) * M;
+                        dstw[j] = (uint32_t(D.q) * mstride) << (j - pos);
+                        owner[j] = l;
+                        shift[j] = j - pos;
+                    }
+                pos += r;
+            }
+            pstride *= uint32_t(D.p);
+            mstride *= uint32_t(D.m);
+        }
+    }
+    const int64_t nthreads = g.N >> LOGG;
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < nthreads; i += stride) {
+        const uint32_t ksrc = uint32_t(i) & (M - 1);
+        uint32_t rp = uint32_t(i >> logM);
+        uint32_t rem = ksrc;
+        uint32_t srank = 0, drank = 0, dloc = 0, pstride = 1, mstride = 1;
+        uint32_t a[kMaxDims];                       // s_k T / n_h mod T: the twiddle of member s is a s
+#pragma unroll
+        for (int l = kMaxDims - 1; l >= 0; --l) {   // unrolled: a[] stays in registers
+            a[l] = 0;
+            if (l >= d) continue;
+            const GroupPutDim &D = g.dim[l];
+            const int logm = __builtin_ctz(uint32_t(D.m));
+            const uint32_t sk = rem & uint32_t(D.m - 1);
+            rem >>= logm;
+            if (D.mode == 2) {
+                const int logpi = __builtin_ctz(uint32_t(D.pi));
+                const int logb = __builtin_ctz(uint32_t(D.p)) - logpi;
+                const uint32_t b = rp & ((1u << logb) - 1);
+                rp >>= logb;
+                uint32_t bs = b, rv = 0;
+                for (int h = 0; h < D.h; ++h) {
+                    rv = (rv << logm) | (bs & uint32_t(D.m - 1));
+                    bs >>= logm;
+                }
+                const uint32_t rho = sk & uint32_t(D.pi - 1), t = sk >> logpi;
+                srank += (b << logpi) * pstride;
+                drank += ((rho << (D.h * logm)) | rv) * pstride;
+                dloc += t * mstride;
+                a[l] = uint32_t((uint64_t(sk) * uint64_t(D.tstep)) % T_);
+            } else {
+                const int logp = __builtin_ctz(uint32_t(D.p));
+                const uint32_t r = rp & uint32_t(D.p - 1);
+                rp >>= logp;
+                srank += r * pstride;
+                drank += r * pstride;
+                dloc += sk * mstride;
+            }
+            pstride *= uint32_t(D.p);
+            mstride *= uint32_t(D.m);
+        }
+        uint32_t ew[LOGG > 0 ? LOGG : 1];
+#pragma unroll
+        for (int j = 0; j < LOGG; ++j) {
+            // a s < T for every member s < p_h, so each weight a 2^shift is below T
+            uint32_t av = 0;
+#pragma unroll
+            for (int l = 0; l < kMaxDims; ++l)
+                if (l == owner[j]) av = a[l];
+            ew[j] = av << shift[j];
+        }
+        const int64_t sbase = int64_t(srank) * M + ksrc;
+        const int64_t dbase = int64_t(drank) * M + dloc;
+        cx<T> v[G];
+#pragma unroll
+        for (int gi = 0; gi < G; ++gi) {
+            uint32_t off = 0;
+#pragma unroll
+            for (int j = 0; j < LOGG; ++j)
+                if ((gi >> j) & 1) off += srcw[j];
+            // a gather: plain load (the neighbouring elements serve other threads)
+            v[gi] = conj_if(get<true>(&in[sbase + off]), g.conj_in);
+        }
+        if (g.twiddle) {
+#pragma unroll
+            for (int gi = 1; gi < G; ++gi) {
+                uint32_t e = 0;
+#pragma unroll
+                for (int j = 0; j < LOGG; ++j)
+                    if ((gi >> j) & 1) {
+                        e += ew[j];
+                        e = e >= T_ ? e - T_ : e;
+                    }
+                v[gi] = cmul(v[gi], table[e]);
+            }
+        }
+        // the length-p_h DFTs, one dimension at a time
+        {
+            int pos = 0;
+            for (int l = d - 1; l >= 0; --l) {
+                const GroupPutDim &D = g.dim[l];
+                if (D.mode != 2) continue;
+                const int r = __builtin_ctz(uint32_t(D.pi));
+                dft_axis_at<T, LOGG>(v, pos, r);
+                pos += r;
+            }
+        }
+#pragma unroll
+        for (int gi = 0; gi < G; ++gi) {
+            uint32_t off = 0;
+#pragma unroll
+            for (int j = 0; j < LOGG; ++j)
+                if ((gi >> j) & 1) off += dstw[j];
+            cx<T> w = conj_if(v[gi], g.conj_out);
+            if (g.scale != 1.0) w = {w.x * scale, w.y * scale};
+            put<false>(&out[dbase + off], w);
+        }
+    }
+}
+
+template <typename T>
+hipError_t launch_gplast_t(const void *in, void *out, const GroupPutDesc &g, const void *table, int logg,
+                           hipStream_t stream)
+{
+    const int64_t want = ((g.N >> logg) + 255) / 256;
+    const uint32_t blocks = uint32_t(want < 65536 ? (want > 0 ? want : 1) : 65536);
+    const cx<T> *a = static_cast<const cx<T> *>(in), *tab = static_cast<const cx<T> *>(table);
+    cx<T> *b = static_cast<cx<T> *>(out);
+    switch (logg) {
+    case 1: hipLaunchKernelGGL((k_gplast<T, 1>), dim3(blocks), dim3(256), 0, stream, a, b, g, tab); break;
+    case 2: hipLaunchKernelGGL((k_gplast<T, 2>), dim3(blocks), dim3(256), 0, stream, a, b, g, tab); break;
+    case 3: hipLaunchKernelGGL((k_gplast<T, 3>), dim3(blocks), dim3(256), 0, stream, a, b, g, tab); break;
+    case 4: hipLaunchKernelGGL((k_gplast<T, 4>), dim3(blocks), dim3(256), 0, stream, a, b, g, tab); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_gplast(Precision prec, const void *in, void *out, const GroupPutDesc &g, const void *table,
+                         hipStream_t stream)
+{
+    // every side a power of two, each dimension in mode 0 or 2, G = prod p_h in 2..16
+    auto pow2 = [](int64_t v) { return v > 0 && (v & (v - 1)) == 0; };
+    if (g.d < 1 || g.d > kMaxDims || g.N >= (int64_t(1) << 31) || !pow2(g.M) || g.T >= (int64_t(1) << 26) ||
+        !g.permute)
+        return hipErrorInvalidValue;
+    int logg = 0;
+    for (int l = 0; l < g.d; ++l) {
+        const GroupPutDim &D = g.dim[l];
+        if (!pow2(D.m) || !pow2(D.p)) return hipErrorInvalidValue;
+        if (D.mode == 2) {
+            if (!pow2(D.pi) || !pow2(D.q) || D.pi > D.p || int64_t(D.pi) * D.q != D.m) return hipErrorInvalidValue;
+            logg += __builtin_ctz(uint32_t(D.pi));
+        } else if (D.mode != 0) {
+            return hipErrorInvalidValue;
+        }
+    }
+    if (logg < 1 || logg > kGplastMaxLogG) return hipErrorInvalidValue;
+    return prec == Precision::F64 ? launch_gplast_t<double>(in, out, g, table, logg, stream)
+                                  : launch_gplast_t<float>(in, out, g, table, logg, stream);
+}
+
 hipError_t launch_gput(Precision prec, const void *in, void *out, const GroupPutDesc &g, const void *table,
                        hipStream_t stream)
 {

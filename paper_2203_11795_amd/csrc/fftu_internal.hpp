@@ -270,6 +270,9 @@ struct GroupPutDim {
     int32_t reserved;
     int64_t tstep;         // T / n_i
 };
+// k_gplast (fftu_gcyclic.hip): the last Put of a power-of-two plan with its length-p_h
+// FFTs, G = prod p_h <= 2^kGplastMaxLogG elements per thread.
+constexpr int kGplastMaxLogG = 4;
 struct GroupPutDesc {
     int32_t d;
     int32_t twiddle;       // multiply by the level's twiddle of the source element
@@ -423,6 +426,8 @@ hipError_t launch_rsplit(Precision prec, void *buf, const RealDesc &rd, const vo
 hipError_t launch_rmerge(Precision prec, const void *in, void *out, const RealDesc &rd, const void *table,
                          hipStream_t stream);
 // One communication superstep of a group-cyclic plan (fftu_gcyclic.hip); in != out when g.permute.
+hipError_t launch_gplast(Precision prec, const void *in, void *out, const GroupPutDesc &g, const void *table,
+                         hipStream_t stream);
 hipError_t launch_gput(Precision prec, const void *in, void *out, const GroupPutDesc &g, const void *table,
                        hipStream_t stream);
 

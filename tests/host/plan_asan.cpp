@@ -100,6 +100,19 @@ hipError_t launch_gput(Precision, const void *in, void *out, const GroupPutDesc 
     if (M != g.M || P * M != g.N) std::abort();
     return hipSuccess;
 }
+hipError_t launch_gplast(Precision prec, const void *in, void *out, const GroupPutDesc &g, const void *t,
+                         hipStream_t st)
+{
+    int logg = 0;
+    for (int l = 0; l < g.d; ++l) {
+        const GroupPutDim &D = g.dim[l];
+        if (D.mode == 1) std::abort();             // the last Put: every dimension in mode 0 or 2
+        if (D.mode == 2) logg += __builtin_ctz(unsigned(D.pi));
+        if ((D.m & (D.m - 1)) || (D.p & (D.p - 1))) std::abort();
+    }
+    if (logg < 1 || logg > kGplastMaxLogG) std::abort();
+    return launch_gput(prec, in, out, g, t, st);
+}
 hipError_t launch_batch_bind(BatchBind *, const BindChunk &c, hipStream_t)
 {
     if (c.count < 1 || c.count > kBindChunk || c.first < 0) std::abort();

@@ -144,12 +144,13 @@ def test_describe(n, p, dtype, s0, fused, launches):
 
 
 @pytest.mark.parametrize("n,p,supersteps,launches", [
-    ((8,), (4,), 2, 5),                       # F_2, Put, F_2, Put, F_2
+    ((8,), (4,), 2, 4),                       # F_2, Put, F_2, the last Put with its F_2 (k_gplast)
     # 16^3 local blocks: a k_group2 pass of the two inner sides and a k_line pass, Put, the
-    # same two passes, Put, 3 passes of length 2
-    ((512, 512, 512), (32, 32, 32), 2, 9),
-    ((16, 16), (8, 2), 3, 9),
-    ((1024,), (64,), 2, 5),
+    # same two passes, then the last Put with the 2 x 2 x 2 FFTs of length p_h = 2
+    ((512, 512, 512), (32, 32, 32), 2, 6),
+    ((16, 16), (8, 2), 3, 8),
+    ((1024,), (64,), 2, 4),
+    ((27, 8), (9, 4), 2, 8),                  # mixed radix: the phases on k_mline, no fused last Put
 ])
 def test_describe_group_cyclic(n, p, supersteps, launches):
     info = fftu.describe(n, p, "complex128")

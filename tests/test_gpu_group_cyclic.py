@@ -139,11 +139,11 @@ def test_kernels_of_each_phase(torch):
     with fftu.Plan((512, 512, 512), (32, 32, 32), "complex128") as plan:
         names = plan.launch_names()
     # 16^3 blocks: the two inner sides in one k_group2 pass, the outer side in a k_line
-    # pass; the last phase's length-2 FFTs one k_line pass per dimension
-    assert len(names) == 9 and names[2] == names[5] == "fftu::k_gput<double>", names
+    # pass; the last Put with the 2 x 2 x 2 FFTs of length p_h = 2 in one k_gplast
+    assert len(names) == 6 and names[2] == "fftu::k_gput<double>", names
     assert names[0] == names[3] == "fftu::k_group2<double, 4, 4>", names
     assert all(k.startswith("fftu::k_line<double, 4,") for k in (names[1], names[4])), names
-    assert all(k.startswith("fftu::k_line<double, 1,") for k in names[6:]), names
+    assert names[5] == "fftu::k_gplast<double, 3>", names
     with fftu.Plan((27, 8), (9, 4), "complex64") as plan:
         names = plan.launch_names()
     assert names.count("fftu::k_gput<float>") == 2 and all(k in ("fftu::k_gput<float>", "fftu::k_mline<float>")
