@@ -1643,8 +1643,11 @@ fftu_plan_s *build_gc_plan(int d, const int64_t n[], const int64_t p[], fftu_dty
         } else {
             for (size_t i = 0; i < gp.phase[size_t(c)].size(); ++i) pl->launch_names.push_back("fftu::k_mline<" + t + ">");
         }
+        fftu::GputTileDesc tl{};
         if (c + 1 == gp.H && gp.last_logg > 0)
             pl->launch_names.push_back("fftu::k_gplast<" + t + ", " + std::to_string(gp.last_logg) + ">");
+        else if (c < gp.H && fftu::gput_tiling(gp.put[size_t(c)], int(pl->esize), tl) && tl.K >= 8)
+            pl->launch_names.push_back("fftu::k_gputt<" + t + ", " + std::to_string(1 << (tl.K - 8)) + ">");
         else if (c < gp.H)
             pl->launch_names.push_back("fftu::k_gput<" + t + ">");
     }

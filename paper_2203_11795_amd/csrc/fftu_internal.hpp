@@ -428,6 +428,18 @@ hipError_t launch_rmerge(Precision prec, const void *in, void *out, const RealDe
 // One communication superstep of a group-cyclic plan (fftu_gcyclic.hip); in != out when g.permute.
 hipError_t launch_gplast(Precision prec, const void *in, void *out, const GroupPutDesc &g, const void *table,
                          hipStream_t stream);
+// k_gputt (fftu_gcyclic.hip): a power-of-two Put as a bit permutation in tiles of
+// 2^K <= 2^kGputTileLog elements (see gput_tiling).
+constexpr int kGputTileLog = 10;
+struct GputTileDesc {
+    int32_t K;              // log2 elements per tile
+    int32_t ntb;            // bits that enumerate the tiles
+    int32_t pad_shift;      // LDS slot s at s + (s >> pad_shift)
+    int32_t lsrc[kGputTileLog], dslot[kGputTileLog], xdst[kGputTileLog];
+    int32_t ysrc[31], ydst[31];
+    int64_t ntiles;
+};
+bool gput_tiling(const GroupPutDesc &g, int esize, GputTileDesc &tl);
 hipError_t launch_gput(Precision prec, const void *in, void *out, const GroupPutDesc &g, const void *table,
                        hipStream_t stream);
 

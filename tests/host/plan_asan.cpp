@@ -113,6 +113,7 @@ hipError_t launch_gplast(Precision prec, const void *in, void *out, const GroupP
     if (logg < 1 || logg > kGplastMaxLogG) std::abort();
     return launch_gput(prec, in, out, g, t, st);
 }
+bool gput_tiling(const GroupPutDesc &, int, GputTileDesc &) { return false; }
 hipError_t launch_batch_bind(BatchBind *, const BindChunk &c, hipStream_t)
 {
     if (c.count < 1 || c.count > kBindChunk || c.first < 0) std::abort();

@@ -140,10 +140,17 @@ def test_kernels_of_each_phase(torch):
         names = plan.launch_names()
     # 16^3 blocks: the two inner sides in one k_group2 pass, the outer side in a k_line
     # pass; the last Put with the 2 x 2 x 2 FFTs of length p_h = 2 in one k_gplast
-    assert len(names) == 6 and names[2] == "fftu::k_gput<double>", names
+    assert len(names) == 6 and names[2] == "fftu::k_gputt<double, 4>", names
     assert names[0] == names[3] == "fftu::k_group2<double, 4, 4>", names
     assert all(k.startswith("fftu::k_line<double, 4,") for k in (names[1], names[4])), names
     assert names[5] == "fftu::k_gplast<double, 3>", names
+    with fftu.Plan((16, 16), (8, 2), "complex128") as plan:
+        names = plan.launch_names()
+    # N = 256: the first two Puts move one tile of 256 elements; the last is k_gplast
+    assert names.count("fftu::k_gputt<double, 1>") == 2 and names[-1] == "fftu::k_gplast<double, 1>", names
+    with fftu.Plan((16,), (8,), "complex128") as plan:
+        names = plan.launch_names()
+    assert names.count("fftu::k_gput<double>") == 2, names   # N = 16: below one tile, the gather
     with fftu.Plan((27, 8), (9, 4), "complex64") as plan:
         names = plan.launch_names()
     assert names.count("fftu::k_gput<float>") == 2 and all(k in ("fftu::k_gput<float>", "fftu::k_mline<float>")
