@@ -23,6 +23,9 @@ What it computes (Koopman & Bisseling, arXiv 2203.11795):
 * :func:`emulate` -- Algorithm 2.3 carried out literally, virtual processor by
   virtual processor, exposing the buffer after each superstep, so that each
   GPU stage can be checked on its own.
+* :mod:`oracle.real`, :mod:`oracle.r2r`, :mod:`oracle.group_cyclic` -- the real-input
+  transform, the DCT / DST in the zig-zag cyclic distribution and grids beyond
+  p_max (Sections 6 and 2.3), each with its reading of the paper in its docstring.
 * :func:`circular_convolution` -- the cyclic convolution of two arrays of one
   shape, summed from its definition (the application that motivates keeping
   input and output in the same distribution: forward transform, pointwise
