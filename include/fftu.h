@@ -224,6 +224,38 @@ fftu_status fftu_execute(fftu_plan_t plan, const void *in, void *out, hipStream_
 fftu_plan_t fftu_plan_real(int d, const int64_t n[], const int64_t p[], fftu_dtype dtype, fftu_direction direction);
 
 /*
+ * The discrete cosine and sine transforms (Section 6 names the DCT and the DST as
+ * the method's next transforms, built from 1-D algorithms dimension by dimension,
+ * with the zig-zag cyclic distribution to exploit their symmetry). Per dimension of
+ * length n (applied along every dimension):
+ *   FFTU_DCT, FFTU_FORWARD (DCT-II):  y[k] = 2 sum_j x[j] cos(pi k (2j + 1) / (2n))
+ *   FFTU_DST, FFTU_FORWARD (DST-II):  y[k] = 2 sum_j x[j] sin(pi (k + 1) (2j + 1) / (2n))
+ *   FFTU_INVERSE: the exact inverse of the forward transform (DCT-III / DST-III
+ *   times 1/n per dimension), so that inverse(forward(x)) = x.
+ * Layouts (N reals of the plan's precision on each side, double for FFTU_C128 and
+ * float for FFTU_C64):
+ *   signal side (x): the zig-zag order v[m(j)] = x[j] along every dimension,
+ *     m(j) = j/2 for even j and n - 1 - (j-1)/2 for odd j (even samples ascending,
+ *     then odd samples descending), in the real side layout of fftu_plan_real over
+ *     p. The DCT-II of x follows from the DFT of v alone, so this dealing of x
+ *     (its zig-zag cyclic distribution) makes the reordering free.
+ *   coefficient side (y): the cyclic buffer layout above over p.
+ * FFTU_FORWARD maps the signal side to the coefficient side, FFTU_INVERSE back.
+ * The transform runs fftu_plan_real's forward transform of v and one pass that
+ * combines each index with its mirror images n_l - k_l; the inverse runs the
+ * combining pass first. The DST is the DCT of the signal with the samples of odd
+ * j negated (one more pass), stored at n_l - 1 - k_l.
+ * Requirements: 1 <= d <= 4 (else UNSUPPORTED), every n_l even (else
+ * INVALID_VALUE), and every requirement of fftu_plan_real for v. Execute with
+ * fftu_execute (in == out allowed; otherwise the buffers must not overlap);
+ * fftu_execute_ws, fftu_execute_noalloc and the stage calls refuse these plans.
+ * The plan owns a spectrum workspace of N/2 + N/n_d complex elements.
+ */
+typedef enum { FFTU_DCT = 0, FFTU_DST = 1 } fftu_r2r_kind;
+fftu_plan_t fftu_plan_r2r(int d, const int64_t n[], const int64_t p[], fftu_dtype dtype, fftu_r2r_kind kind,
+                          fftu_direction direction);
+
+/*
  * Plans that own no device memory, for callers that manage HBM themselves (a
  * serving loop with its own arena). fftu_plan_external takes the same arguments
  * and applies the same checks as fftu_plan, but allocates nothing for the plan:

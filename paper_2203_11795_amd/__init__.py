@@ -5,8 +5,8 @@ The transform runs in the HIP kernels of ``libfftu.so`` (C ABI in
 ``include/fftu.h``); :mod:`.fftu` is its Python binding.
 """
 from .fftu import (C64, C128, FORWARD, INVERSE, NOALLOC_MAX_BYTES, BatchPlan, ConvolutionPlan, FftuError, Graph, Plan,
-                   RealPlan, check, describe, fill_uniform, get_tuning, load_library, pointwise_mul, set_tuning)
+                   R2RPlan, RealPlan, check, describe, fill_uniform, get_tuning, load_library, pointwise_mul, set_tuning)
 
-__all__ = ["Plan", "RealPlan", "BatchPlan", "ConvolutionPlan", "Graph", "FftuError", "check", "describe", "fill_uniform",
+__all__ = ["Plan", "RealPlan", "R2RPlan", "BatchPlan", "ConvolutionPlan", "Graph", "FftuError", "check", "describe", "fill_uniform",
            "pointwise_mul", "load_library",
            "set_tuning", "get_tuning", "FORWARD", "INVERSE", "C64", "C128", "NOALLOC_MAX_BYTES"]

@@ -17,7 +17,8 @@ LIB = os.path.join(HERE, "libfftu.so")
 ARCH = "gfx950"
 
 SOURCES = ["fftu_api.cpp", "fftu_kernels.hip", "fftu_line.hip", "fftu_exchange.hip", "fftu_group.hip", "fftu_pair.hip", "fftu_long.hip",
-           "fftu_lastx_f32.hip", "fftu_lastx_f64.hip", "fftu_batch.hip", "fftu_fill.hip", "fftu_pointwise.hip", "fftu_mixed.hip", "fftu_scratch.hip", "fftu_gcyclic.hip", "fftu_real.hip"]
+           "fftu_lastx_f32.hip", "fftu_lastx_f64.hip", "fftu_batch.hip", "fftu_fill.hip", "fftu_pointwise.hip", "fftu_mixed.hip", "fftu_scratch.hip", "fftu_gcyclic.hip", "fftu_real.hip",
+           "fftu_r2r.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 COMMON = [

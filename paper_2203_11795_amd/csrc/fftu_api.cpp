@@ -64,6 +64,11 @@ struct fftu_plan_s {
     fftu::RealDesc rd{};
     void *rtable = nullptr;
     int64_t real_in_elems = 0, real_out_elems = 0;   // complex elements of each side's buffer
+    // DCT / DST (fftu_plan_r2r): the real plan of the zig-zag signal (rc), the
+    // coefficient step and its omega_{T4} table (rtable), the spectrum in ws
+    bool r2r = false;
+    fftu_r2r_kind r2r_kind = FFTU_DCT;
+    fftu::R2RDesc r2d{};
     // grids beyond p_max (some p_l^2 not dividing n_l): group-cyclic levels, several supersteps
     bool gc = false;
     int gc_H = 0;                                       // communication supersteps
@@ -1283,7 +1288,7 @@ bool aligned(const void *p, size_t esize) { return (reinterpret_cast<uintptr_t>(
 
 fftu_status check_exec_args(const fftu_plan_s *plan, const void *in, const void *out)
 {
-    if (!plan || !in || !out || plan->is_batch || plan->real) return FFTU_ERROR_INVALID_VALUE;
+    if (!plan || !in || !out || plan->is_batch || plan->real || plan->r2r) return FFTU_ERROR_INVALID_VALUE;
     if (!aligned(in, plan->esize) || !aligned(out, plan->esize)) return FFTU_ERROR_INVALID_VALUE;
     if (in != out) {
         const char *a = static_cast<const char *>(in);
@@ -1930,6 +1935,92 @@ fftu_plan_t fftu_plan_real(int d, const int64_t n[], const int64_t p[], fftu_dty
     return pl;
 }
 
+fftu_plan_t fftu_plan_r2r(int d, const int64_t n[], const int64_t p[], fftu_dtype dtype, fftu_r2r_kind kind,
+                          fftu_direction direction)
+{
+    if (d < 1 || !n || !p || (kind != FFTU_DCT && kind != FFTU_DST)) {
+        record(FFTU_ERROR_INVALID_VALUE);
+        return nullptr;
+    }
+    if (d > fftu::kR2RMaxDims) {
+        record(FFTU_ERROR_UNSUPPORTED);
+        return nullptr;
+    }
+    for (int l = 0; l < d; ++l)
+        if (n[l] < 2 || n[l] % 2 || p[l] < 1 || n[l] >= (int64_t(1) << 30)) {
+            record(FFTU_ERROR_INVALID_VALUE);
+            return nullptr;
+        }
+    // the signal's real transform (its own checks: p | n, p_d | n_d / 2, the grid)
+    fftu_plan_s *rc = fftu_plan_real(d, n, p, dtype, direction);
+    if (!rc) return nullptr;
+    fftu_plan_s *pl = new (std::nothrow) fftu_plan_s();
+    if (!pl) {
+        fftu_destroy(rc);
+        record(FFTU_ERROR_OUT_OF_MEMORY);
+        return nullptr;
+    }
+    pl->r2r = true;
+    pl->r2r_kind = kind;
+    pl->rc = rc;
+    pl->d = d;
+    int64_t T4 = 1, groups = 1, P = 1, N = 1;
+    for (int l = 0; l < d; ++l) {
+        pl->n[l] = n[l];
+        pl->p[l] = p[l];
+        T4 = lcm64(T4, 4 * n[l]);
+        groups *= n[l] / 2 + 1;
+        P *= p[l];
+        N *= n[l];
+    }
+    pl->dtype = dtype;
+    pl->dir = direction;
+    pl->prec = rc->prec;
+    pl->esize = rc->esize;
+    pl->device = rc->device;
+    pl->grid.N = N / 2;
+    fftu::R2RDesc &g = pl->r2d;
+    g.d = d;
+    g.dst = kind == FFTU_DST ? 1 : 0;
+    for (int l = 0; l < d; ++l) {
+        g.n[l] = int32_t(n[l]);
+        g.p[l] = int32_t(p[l]);
+        g.m[l] = int32_t(n[l] / p[l]);
+        g.tstep[l] = int32_t(T4 / (4 * n[l]));
+    }
+    g.M = N / P;
+    g.groups = groups;
+    g.rd = rc->rd;
+    const std::string t = dtype == FFTU_C128 ? "double" : "float";
+    const std::string dd = std::to_string(d);
+    const bool dst = kind == FFTU_DST;
+    if (direction == FFTU_FORWARD) {
+        if (dst) pl->launch_names.push_back("fftu::k_r2rsign<" + t + ">");
+        for (const std::string &k : rc->launch_names) pl->launch_names.push_back(k);
+        pl->launch_names.push_back("fftu::k_r2rpost<" + t + ", " + dd + ">");
+    } else {
+        pl->launch_names.push_back("fftu::k_r2rpre<" + t + ", " + dd + ">");
+        for (const std::string &k : rc->launch_names) pl->launch_names.push_back(k);
+        if (dst) pl->launch_names.push_back("fftu::k_r2rsign<" + t + ">");
+    }
+    pl->launches = int(pl->launch_names.size());
+    pl->table_T = T4;
+    pl->table_bytes = uint64_t(T4) * pl->esize;
+    // the spectrum: the half spectrum and the Nyquist plane
+    pl->ws_bytes = uint64_t(rc->real_in_elems > rc->real_out_elems ? rc->real_in_elems : rc->real_out_elems) *
+                   pl->esize;
+    hipError_t e = T4 < (int64_t(1) << 26) ? upload_table_general(&pl->rtable, T4, dtype) : hipErrorInvalidValue;
+    if (e == hipSuccess) e = hipMalloc(&pl->ws, pl->ws_bytes);
+    if (e != hipSuccess) {
+        const fftu_status st = T4 < (int64_t(1) << 26) ? from_hip(e) : FFTU_ERROR_UNSUPPORTED;
+        fftu_destroy(pl);
+        record(st);
+        return nullptr;
+    }
+    record(FFTU_SUCCESS);
+    return pl;
+}
+
 fftu_plan_t fftu_plan_external(int d, const int64_t n[], const int64_t p[], fftu_dtype dtype,
                                fftu_direction direction)
 {
@@ -2420,6 +2511,15 @@ void fftu_graph_destroy(fftu_graph_t graph)
 fftu_status fftu_get_plan_info(fftu_plan_t plan, fftu_plan_info *info)
 {
     if (!plan || !info) return record(FFTU_ERROR_INVALID_VALUE);
+    if (plan->r2r) {
+        // the real plan of the signal, plus the coefficient step (and the sign pass of a DST)
+        fftu_status st = fftu_get_plan_info(plan->rc, info);
+        if (st != FFTU_SUCCESS) return st;
+        info->launches = plan->launches;
+        info->table_bytes += plan->table_bytes;
+        info->workspace_bytes += plan->ws_bytes;
+        return record(FFTU_SUCCESS);
+    }
     if (plan->real) {
         // the complex plan of the packed array, plus the split or merge pass
         fftu_status st = fftu_get_plan_info(plan->rc, info);
@@ -2479,8 +2579,11 @@ size_t fftu_plan_device_bytes(fftu_plan_t plan)
         record(FFTU_ERROR_INVALID_VALUE);
         return 0;
     }
+    // a real or DCT / DST plan also owns the plan it runs on
+    size_t bytes = 0;
+    for (const fftu_plan_s *q = plan; q; q = q->rc) bytes += size_t(q->table_bytes + q->ws_bytes);
     record(FFTU_SUCCESS);
-    return size_t(plan->table_bytes + plan->ws_bytes);
+    return bytes;
 }
 
 fftu_status fftu_execute(fftu_plan_t plan, const void *in, void *out, hipStream_t stream)
@@ -2678,10 +2781,22 @@ fftu_status execute_gc(fftu_plan_s *plan, const void *in, void *out, void *ws, h
 }
 
 fftu_status execute_real(fftu_plan_s *plan, const void *in, void *out, hipStream_t stream, Marker &mk);
+fftu_status execute_r2r(fftu_plan_s *plan, const void *in, void *out, hipStream_t stream, Marker &mk);
 
 fftu_status execute_with(fftu_plan_s *plan, const void *in, void *out, void *ws, hipStream_t stream, const void *mul,
                          Marker *outer)
 {
+    if (plan && plan->r2r) {
+        // N reals on each side
+        const size_t rsize = plan->esize / 2, bytes = size_t(2 * plan->grid.N) * rsize;
+        if (!in || !out || !aligned(in, rsize) || !aligned(out, rsize)) return FFTU_ERROR_INVALID_VALUE;
+        const char *a = static_cast<const char *>(in);
+        const char *b = static_cast<const char *>(out);
+        if (in != out && a < b + bytes && b < a + bytes) return FFTU_ERROR_INVALID_VALUE;   // partial overlap
+        Marker mk(plan, stream);
+        mk.mark();
+        return execute_r2r(plan, in, out, stream, mk);
+    }
     if (plan && plan->real) {
         if (!in || !out || !aligned(in, plan->esize) || !aligned(out, plan->esize)) return FFTU_ERROR_INVALID_VALUE;
         if (in != out) {
@@ -2784,6 +2899,38 @@ namespace {
 // Real-input transforms: forward = the complex transform of the packed array into
 // the output, then the split in place; inverse = the merge into the output, then
 // the inverse complex transform in place.
+// DCT / DST: forward = [signs] -> real transform into the spectrum workspace ->
+// coefficients; inverse = spectrum from the coefficients -> inverse real
+// transform -> [signs] (in place on the output).
+fftu_status execute_r2r(fftu_plan_s *plan, const void *in, void *out, hipStream_t stream, Marker &mk)
+{
+    fftu_plan_s *rp = plan->rc;
+    const bool dst = plan->r2r_kind == FFTU_DST;
+    hipError_t e = hipSuccess;
+    if (plan->dir == FFTU_FORWARD) {
+        const void *sig = in;
+        if (dst) {
+            e = fftu::launch_r2r_sign(plan->prec, in, out, plan->r2d, stream);
+            if (e != hipSuccess) return from_hip(e);
+            mk.mark();
+            sig = out;
+        }
+        fftu_status s = execute_real(rp, sig, plan->ws, stream, mk);
+        if (s != FFTU_SUCCESS) return s;
+        e = fftu::launch_r2r_post(plan->prec, plan->ws, out, plan->r2d, plan->rtable, stream);
+        if (e == hipSuccess) mk.mark();
+        return from_hip(e);
+    }
+    e = fftu::launch_r2r_pre(plan->prec, in, plan->ws, plan->r2d, plan->rtable, stream);
+    if (e != hipSuccess) return from_hip(e);
+    mk.mark();
+    fftu_status s = execute_real(rp, plan->ws, out, stream, mk);
+    if (s != FFTU_SUCCESS || !dst) return s;
+    e = fftu::launch_r2r_sign(plan->prec, out, out, plan->r2d, stream);
+    if (e == hipSuccess) mk.mark();
+    return from_hip(e);
+}
+
 fftu_status execute_real(fftu_plan_s *plan, const void *in, void *out, hipStream_t stream, Marker &mk)
 {
     fftu_plan_s *rc = plan->rc;

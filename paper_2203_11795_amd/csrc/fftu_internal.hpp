@@ -296,6 +296,23 @@ struct RealDesc {
     int32_t m[kMaxDims];    // n'_l / p_l
 };
 
+// The DCT-II / DST-II and their inverses (fftu_r2r.hip) on top of the real transform:
+// the signal v (the zig-zag order of x) in the real-side layout of RealDesc, the
+// coefficients y (N reals) cyclic over p. A thread takes one group of indices that
+// are mirror images k_l <-> n_l - k_l in any subset of the dimensions.
+constexpr int kR2RMaxDims = 4;
+struct R2RDesc {
+    int32_t d;
+    int32_t dst;            // 1: DST (coefficients stored at n_l - 1 - k_l, the DCT of the signed signal)
+    int32_t n[kMaxDims];    // full sides n_l
+    int32_t p[kMaxDims];
+    int32_t m[kMaxDims];    // n_l / p_l
+    int32_t tstep[kMaxDims];  // T4 / (4 n_l): omega_{4 n_l}^k is table entry k tstep_l
+    int64_t M;              // coefficients per processor (N / P)
+    int64_t groups;         // prod_l (n_l / 2 + 1)
+    RealDesc rd;            // the half spectrum of the signal (packed shape, Nyquist plane)
+};
+
 // k_mexchange: P sources of 64 local indices in LDS, grid sides of one radix stage.
 constexpr int64_t kMexMaxP = 64;
 constexpr int kMexThreads = 512;
@@ -423,6 +440,13 @@ hipError_t launch_lastx(Precision prec, const void *in, void *out, const LastxDe
 // on buf (forward; writes the Nyquist plane after the Nh packed elements). rmerge:
 // from in (half spectrum and plane) to out (Nh elements; in == out allowed).
 hipError_t launch_rsplit(Precision prec, void *buf, const RealDesc &rd, const void *table, hipStream_t stream);
+// Coefficients from the half spectrum (forward), the half spectrum from the
+// coefficients (inverse), and the sign pattern of the DST's signal (in place allowed).
+hipError_t launch_r2r_post(Precision prec, const void *spec, void *y, const R2RDesc &g, const void *table4,
+                           hipStream_t stream);
+hipError_t launch_r2r_pre(Precision prec, const void *y, void *spec, const R2RDesc &g, const void *table4,
+                          hipStream_t stream);
+hipError_t launch_r2r_sign(Precision prec, const void *in, void *out, const R2RDesc &g, hipStream_t stream);
 hipError_t launch_rmerge(Precision prec, const void *in, void *out, const RealDesc &rd, const void *table,
                          hipStream_t stream);
 // One communication superstep of a group-cyclic plan (fftu_gcyclic.hip); in != out when g.permute.

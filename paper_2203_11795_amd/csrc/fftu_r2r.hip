@@ -1,0 +1,316 @@
+// The DCT-II and DST-II (and their exact inverses) in the zig-zag cyclic
+// distribution, on top of the real transform. arXiv 2203.11795, Section 6, names
+// them as the method's next transforms, built from 1-D algorithms dimension by
+// dimension, with the zig-zag cyclic distribution to exploit their symmetry.
+//
+// Signal side: v, the zig-zag order of x along every dimension (v[m(j)] = x[j]:
+// even samples ascending, then odd samples descending), in the real transform's
+// packed layout. Its DFT V (the real transform's half spectrum and Nyquist plane)
+// gives the DCT-II coefficients through one operator per dimension,
+//     (C f)[k] = w^k f[k] + w^-k f[n - k],   w = exp(-2 pi i / (4 n)),
+// (index n - 0 read as 0): y = (C_1 x ... x C_d) V, which is real. C_l couples
+// k_l and n_l - k_l only, so a thread takes the 2^d indices that are mirror images
+// of one representative (k_l in [0, n_l/2]) in any subset of the dimensions,
+// reads V there (the conjugate of the half spectrum at -k where k_d > n_d/2),
+// applies the C_l in registers and stores y. On a pair (a, b) = (f[k], f[n - k]):
+//     C a = w^k a + w^-k b,   C b = i (w^k a - w^-k b).
+// The inverse applies C_l^-1, a = w^-k (g_a - i g_b) / 2, b = w^k (g_a + i g_b) / 2
+// (k = 0: a = g_a / 2), writes V on the half spectrum and the plane, and the
+// inverse real transform gives v. At k = 0 and k = n/2 a and b are one element:
+// only the first copy is stored.
+// DST-II: y_s[k] = DCT-II(x')[n - 1 - k] with x'[j] = (-1)^j x[j], that is
+// v'[m] = v[m] for m < n/2 and -v[m] otherwise along every dimension: a sign
+// pass on the signal, the DCT, and the store at n_l - 1 - k_l.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "fftu_device.hpp"
+#include "fftu_internal.hpp"
+
+namespace fftu {
+
+namespace {
+
+// Buffer position of natural index k of the packed array n' (dims = d), or of the
+// Nyquist plane's index (dims = d - 1, after the Nh packed elements).
+__device__ __forceinline__ int64_t spec_position(const RealDesc &rd, const int32_t *k, int dims)
+{
+    uint32_t r = 0, i = 0;
+    for (int l = 0; l < dims; ++l) {
+        r = r * uint32_t(rd.p[l]) + uint32_t(k[l]) % uint32_t(rd.p[l]);
+        i = i * uint32_t(rd.m[l]) + uint32_t(k[l]) / uint32_t(rd.p[l]);
+    }
+    return dims == rd.d ? int64_t(r) * rd.Mh + i : rd.Nh + int64_t(r) * rd.Mp + i;
+}
+
+// V at full index k (k_d in [0, n_d)): the half spectrum, the plane, or the
+// conjugate of the half spectrum at -k.
+template <typename T, int D>
+__device__ __forceinline__ cx<T> spectrum_at(const cx<T> *spec, const R2RDesc &g, const int32_t (&k)[D])
+{
+    const int32_t h = g.rd.h, kd = k[D - 1];
+    if (kd < h) return spec[spec_position(g.rd, k, D)];
+    if (kd == h) return spec[spec_position(g.rd, k, D - 1)];
+    int32_t nk[D];
+#pragma unroll
+    for (int l = 0; l < D - 1; ++l) nk[l] = k[l] == 0 ? 0 : g.n[l] - k[l];
+    nk[D - 1] = g.n[D - 1] - kd;
+    const cx<T> a = spec[spec_position(g.rd, nk, D)];
+    return {a.x, -a.y};
+}
+
+// Position of coefficient index k (cyclic over p).
+template <int D>
+__device__ __forceinline__ int64_t coeff_position(const R2RDesc &g, const int32_t (&k)[D])
+{
+    uint32_t r = 0, i = 0;
+#pragma unroll
+    for (int l = 0; l < D; ++l) {
+        r = r * uint32_t(g.p[l]) + uint32_t(k[l]) % uint32_t(g.p[l]);
+        i = i * uint32_t(g.m[l]) + uint32_t(k[l]) / uint32_t(g.p[l]);
+    }
+    return int64_t(r) * g.M + i;
+}
+
+// The representative of group t (k_l in [0, n_l/2], last dimension fastest).
+template <int D>
+__device__ __forceinline__ void representative(const R2RDesc &g, int64_t t, int32_t (&k)[D])
+{
+#pragma unroll
+    for (int l = D - 1; l >= 0; --l) {
+        const int64_t span = g.n[l] / 2 + 1;
+        const int64_t q = t / span;
+        k[l] = int32_t(t - q * span);
+        t = q;
+    }
+}
+
+// Member `mask` of the group: k_l mirrored where bit l is set.
+template <int D>
+__device__ __forceinline__ void member(const R2RDesc &g, const int32_t (&k)[D], int mask, int32_t (&kk)[D])
+{
+#pragma unroll
+    for (int l = 0; l < D; ++l) kk[l] = ((mask >> l) & 1) ? (k[l] == 0 ? 0 : g.n[l] - k[l]) : k[l];
+}
+
+// A member that repeats another (a mirrored self-image: k_l = 0 or n_l / 2).
+template <int D>
+__device__ __forceinline__ bool repeated(const R2RDesc &g, const int32_t (&k)[D], int mask)
+{
+    bool rep = false;
+#pragma unroll
+    for (int l = 0; l < D; ++l) rep = rep || (((mask >> l) & 1) && (k[l] == 0 || 2 * k[l] == g.n[l]));
+    return rep;
+}
+
+template <typename T>
+__device__ __forceinline__ cx<T> times_i(cx<T> a) { return {-a.y, a.x}; }
+
+}  // namespace
+
+template <typename T, int D>
+__global__ __launch_bounds__(256) void k_r2rpost(const cx<T> *__restrict__ spec, T *__restrict__ y, const R2RDesc g,
+                                                 const cx<T> *__restrict__ table)
+{
+    constexpr int G = 1 << D;
+    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < g.groups; t += stride) {
+        int32_t k[D];
+        representative<D>(g, t, k);
+        cx<T> v[G];
+#pragma unroll
+        for (int mask = 0; mask < G; ++mask) {
+            int32_t kk[D];
+            member<D>(g, k, mask, kk);
+            v[mask] = spectrum_at<T, D>(spec, g, kk);
+        }
+#pragma unroll
+        for (int l = 0; l < D; ++l) {
+            const cx<T> w = table[int64_t(k[l]) * g.tstep[l]];
+            const cx<T> wc = {w.x, -w.y};
+#pragma unroll
+            for (int mask = 0; mask < G; ++mask) {
+                if ((mask >> l) & 1) continue;
+                const int mb = mask | (1 << l);
+                const cx<T> a = cmul(w, v[mask]), b = cmul(wc, v[mb]);
+                v[mask] = a + b;
+                v[mb] = times_i(a - b);
+            }
+        }
+#pragma unroll
+        for (int mask = 0; mask < G; ++mask) {
+            if (repeated<D>(g, k, mask)) continue;
+            int32_t kk[D];
+            member<D>(g, k, mask, kk);
+            if (g.dst) {
+#pragma unroll
+                for (int l = 0; l < D; ++l) kk[l] = g.n[l] - 1 - kk[l];
+            }
+            y[coeff_position<D>(g, kk)] = v[mask].x;
+        }
+    }
+}
+
+template <typename T, int D>
+__global__ __launch_bounds__(256) void k_r2rpre(const T *__restrict__ y, cx<T> *__restrict__ spec, const R2RDesc g,
+                                                const cx<T> *__restrict__ table)
+{
+    constexpr int G = 1 << D;
+    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < g.groups; t += stride) {
+        int32_t k[D];
+        representative<D>(g, t, k);
+        cx<T> v[G];
+#pragma unroll
+        for (int mask = 0; mask < G; ++mask) {
+            int32_t kk[D];
+            member<D>(g, k, mask, kk);
+            if (g.dst) {
+#pragma unroll
+                for (int l = 0; l < D; ++l) kk[l] = g.n[l] - 1 - kk[l];
+            }
+            v[mask] = {y[coeff_position<D>(g, kk)], T(0)};
+        }
+#pragma unroll
+        for (int l = 0; l < D; ++l) {
+            const cx<T> w = table[int64_t(k[l]) * g.tstep[l]];
+            const cx<T> wc = {w.x, -w.y};
+#pragma unroll
+            for (int mask = 0; mask < G; ++mask) {
+                if ((mask >> l) & 1) continue;
+                const int mb = mask | (1 << l);
+                const cx<T> a = v[mask], b = v[mb];
+                if (k[l] == 0) {
+                    v[mask] = {a.x * T(0.5), a.y * T(0.5)};
+                    v[mb] = v[mask];
+                } else {
+                    const cx<T> ib = times_i(b);
+                    const cx<T> lo = cmul(wc, a - ib), hi = cmul(w, a + ib);
+                    v[mask] = {lo.x * T(0.5), lo.y * T(0.5)};
+                    v[mb] = {hi.x * T(0.5), hi.y * T(0.5)};
+                }
+            }
+        }
+        // the half spectrum and the plane: the members with k_d <= n_d / 2
+#pragma unroll
+        for (int mask = 0; mask < G / 2; ++mask) {
+            if (repeated<D>(g, k, mask)) continue;
+            int32_t kk[D];
+            member<D>(g, k, mask, kk);
+            const int64_t pos = kk[D - 1] < g.rd.h ? spec_position(g.rd, kk, D) : spec_position(g.rd, kk, D - 1);
+            spec[pos] = v[mask];
+        }
+    }
+}
+
+// The signs of the DST's signal: v[m] negated once for each dimension with
+// m_l >= n_l / 2 (the odd samples of x), on the packed layout.
+template <typename T>
+__global__ __launch_bounds__(256) void k_r2rsign(const cx<T> *in, cx<T> *out, const R2RDesc g)
+{
+    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    const RealDesc &rd = g.rd;
+    for (int64_t pos = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; pos < rd.Nh; pos += stride) {
+        uint32_t r = uint32_t(pos / rd.Mh);
+        uint32_t i = uint32_t(pos - int64_t(r) * rd.Mh);
+        T s = T(1), s0 = T(1), s1 = T(1);
+        for (int l = rd.d - 1; l >= 0; --l) {
+            const uint32_t sl = r % uint32_t(rd.p[l]);
+            r /= uint32_t(rd.p[l]);
+            const uint32_t il = i % uint32_t(rd.m[l]);
+            i /= uint32_t(rd.m[l]);
+            const int32_t j = int32_t(sl + il * uint32_t(rd.p[l]));   // packed natural index
+            if (l == rd.d - 1) {
+                s0 = 2 * j < rd.h ? T(1) : T(-1);                     // signal index 2j against n_d / 2
+                s1 = 2 * j + 1 < rd.h ? T(1) : T(-1);
+            } else if (2 * j >= g.n[l]) {
+                s = -s;
+            }
+        }
+        const cx<T> a = in[pos];
+        out[pos] = {a.x * s * s0, a.y * s * s1};
+    }
+}
+
+namespace {
+
+uint32_t grid_of(int64_t count)
+{
+    const int64_t want = (count + 255) / 256;
+    return uint32_t(want < 65536 ? (want > 0 ? want : 1) : 65536);
+}
+
+bool r2r_ok(const R2RDesc &g)
+{
+    if (g.d < 1 || g.d > kR2RMaxDims || g.d != g.rd.d || g.groups < 1) return false;
+    for (int l = 0; l < g.d; ++l)
+        if (g.n[l] < 2 || g.n[l] % 2 || g.p[l] < 1 || g.m[l] * g.p[l] != g.n[l] || g.tstep[l] < 1) return false;
+    return true;
+}
+
+template <typename T>
+hipError_t post_t(const void *spec, void *y, const R2RDesc &g, const void *table, hipStream_t stream)
+{
+    const cx<T> *a = static_cast<const cx<T> *>(spec), *tab = static_cast<const cx<T> *>(table);
+    T *b = static_cast<T *>(y);
+    const uint32_t blocks = grid_of(g.groups);
+    switch (g.d) {
+    case 1: hipLaunchKernelGGL((k_r2rpost<T, 1>), dim3(blocks), dim3(256), 0, stream, a, b, g, tab); break;
+    case 2: hipLaunchKernelGGL((k_r2rpost<T, 2>), dim3(blocks), dim3(256), 0, stream, a, b, g, tab); break;
+    case 3: hipLaunchKernelGGL((k_r2rpost<T, 3>), dim3(blocks), dim3(256), 0, stream, a, b, g, tab); break;
+    case 4: hipLaunchKernelGGL((k_r2rpost<T, 4>), dim3(blocks), dim3(256), 0, stream, a, b, g, tab); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t pre_t(const void *y, void *spec, const R2RDesc &g, const void *table, hipStream_t stream)
+{
+    const T *a = static_cast<const T *>(y);
+    cx<T> *b = static_cast<cx<T> *>(spec);
+    const cx<T> *tab = static_cast<const cx<T> *>(table);
+    const uint32_t blocks = grid_of(g.groups);
+    switch (g.d) {
+    case 1: hipLaunchKernelGGL((k_r2rpre<T, 1>), dim3(blocks), dim3(256), 0, stream, a, b, g, tab); break;
+    case 2: hipLaunchKernelGGL((k_r2rpre<T, 2>), dim3(blocks), dim3(256), 0, stream, a, b, g, tab); break;
+    case 3: hipLaunchKernelGGL((k_r2rpre<T, 3>), dim3(blocks), dim3(256), 0, stream, a, b, g, tab); break;
+    case 4: hipLaunchKernelGGL((k_r2rpre<T, 4>), dim3(blocks), dim3(256), 0, stream, a, b, g, tab); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_r2r_post(Precision prec, const void *spec, void *y, const R2RDesc &g, const void *table4,
+                           hipStream_t stream)
+{
+    if (!r2r_ok(g)) return hipErrorInvalidValue;
+    return prec == Precision::F64 ? post_t<double>(spec, y, g, table4, stream)
+                                  : post_t<float>(spec, y, g, table4, stream);
+}
+
+hipError_t launch_r2r_pre(Precision prec, const void *y, void *spec, const R2RDesc &g, const void *table4,
+                          hipStream_t stream)
+{
+    if (!r2r_ok(g)) return hipErrorInvalidValue;
+    return prec == Precision::F64 ? pre_t<double>(y, spec, g, table4, stream)
+                                  : pre_t<float>(y, spec, g, table4, stream);
+}
+
+hipError_t launch_r2r_sign(Precision prec, const void *in, void *out, const R2RDesc &g, hipStream_t stream)
+{
+    if (!r2r_ok(g)) return hipErrorInvalidValue;
+    const uint32_t blocks = grid_of(g.rd.Nh);
+    if (prec == Precision::F64)
+        hipLaunchKernelGGL(k_r2rsign<double>, dim3(blocks), dim3(256), 0, stream,
+                           static_cast<const cx<double> *>(in), static_cast<cx<double> *>(out), g);
+    else
+        hipLaunchKernelGGL(k_r2rsign<float>, dim3(blocks), dim3(256), 0, stream, static_cast<const cx<float> *>(in),
+                           static_cast<cx<float> *>(out), g);
+    return hipGetLastError();
+}
+
+}  // namespace fftu

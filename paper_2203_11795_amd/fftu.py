@@ -26,6 +26,7 @@ STATUS = {0: "FFTU_SUCCESS", 1: "FFTU_ERROR_INVALID_VALUE", 2: "FFTU_ERROR_NOT_D
 # Every entry point declared in include/fftu.h.
 EXPORTS = ["fftu_version", "fftu_status_string", "fftu_last_error", "fftu_check", "fftu_describe", "fftu_plan",
            "fftu_get_plan_info", "fftu_plan_device_bytes", "fftu_execute", "fftu_plan_external", "fftu_execute_ws", "fftu_execute_noalloc", "fftu_plan_real",
+           "fftu_plan_r2r",
            "fftu_stage_local_fft",
            "fftu_stage_twiddle", "fftu_stage_exchange", "fftu_stage_remaining_fft", "fftu_stage_superstep", "fftu_timing_begin",
            "fftu_timing_end", "fftu_set_tuning", "fftu_get_tuning", "fftu_launch_name", "fftu_plan_batch", "fftu_execute_batch", "fftu_batch_error",
@@ -94,6 +95,8 @@ def load_library(path: str = LIB_PATH):
     lib.fftu_plan_external.argtypes = [ctypes.c_int, i64p, i64p, ctypes.c_int, ctypes.c_int]
     lib.fftu_plan_real.restype = vp
     lib.fftu_plan_real.argtypes = [ctypes.c_int, i64p, i64p, ctypes.c_int, ctypes.c_int]
+    lib.fftu_plan_r2r.restype = vp
+    lib.fftu_plan_r2r.argtypes = [ctypes.c_int, i64p, i64p, ctypes.c_int, ctypes.c_int, ctypes.c_int]
     lib.fftu_execute_ws.restype = ctypes.c_int
     lib.fftu_execute_ws.argtypes = [vp, vp, vp, vp, vp]
     lib.fftu_execute_noalloc.restype = ctypes.c_int
@@ -425,6 +428,55 @@ class RealPlan(Plan):
                 raise ValueError(f"{name} must be a contiguous {dt} device tensor of {n} elements")
         if out is None:
             out = torch.empty(out_n, dtype=out_dt, device=x.device)
+        if stream is None:
+            stream = torch.cuda.current_stream(x.device)
+        self.execute_ptr(x.data_ptr(), out.data_ptr(), int(stream.cuda_stream), "fftu_execute")
+        return out
+
+
+R2R_KIND = {"dct": 0, "dst": 1}      # fftu_r2r_kind
+
+
+class R2RPlan(Plan):
+    """The DCT-II / DST-II (forward) or its exact inverse (fftu_plan_r2r): N reals
+    (float64 for dtype complex128, float32 for complex64) on both sides. Forward:
+    the signal in the zig-zag cyclic layout to the coefficients cyclic over p;
+    inverse: the other way."""
+
+    def __init__(self, n, p, kind="dct", dtype="complex128", direction=FORWARD):
+        self.n = tuple(int(v) for v in n)
+        self.p = tuple(int(v) for v in p)
+        if len(self.n) != len(self.p):
+            raise ValueError("n and p must have the same length")
+        if kind not in R2R_KIND:
+            raise ValueError(f"kind must be one of {sorted(R2R_KIND)}")
+        self.kind = kind
+        self.dtype_code = _dtype_code(dtype)
+        self.direction = int(direction)
+        self.external = False
+        self._lib = load_library()
+        h = self._lib.fftu_plan_r2r(len(self.n), _arr(self.n), _arr(self.p), self.dtype_code, R2R_KIND[kind],
+                                    self.direction)
+        if not h:
+            raise FftuError(self._lib.fftu_last_error(), "fftu_plan_r2r")
+        self._h = ctypes.c_void_p(h)
+        self.N = _prod(self.n)
+
+    @property
+    def real_dtype(self):
+        import torch
+        return torch.float64 if self.dtype_code == C128 else torch.float32
+
+    def __call__(self, x, out=None, stream=None):
+        import torch
+        for t, name in ((x, "input"), (out, "output")):
+            if t is None:
+                continue
+            if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != self.real_dtype or \
+                    t.numel() != self.N or not t.is_contiguous():
+                raise ValueError(f"{name} must be a contiguous {self.real_dtype} device tensor of {self.N} elements")
+        if out is None:
+            out = torch.empty(self.N, dtype=self.real_dtype, device=x.device)
         if stream is None:
             stream = torch.cuda.current_stream(x.device)
         self.execute_ptr(x.data_ptr(), out.data_ptr(), int(stream.cuda_stream), "fftu_execute")

@@ -114,6 +114,21 @@ hipError_t launch_gplast(Precision prec, const void *in, void *out, const GroupP
     return launch_gput(prec, in, out, g, t, st);
 }
 bool gput_tiling(const GroupPutDesc &, int, GputTileDesc &) { return false; }
+hipError_t launch_r2r_post(Precision, const void *, void *, const R2RDesc &g, const void *, hipStream_t)
+{
+    if (g.d < 1 || g.d > kR2RMaxDims || g.groups < 1) std::abort();
+    return hipSuccess;
+}
+hipError_t launch_r2r_pre(Precision, const void *, void *, const R2RDesc &g, const void *, hipStream_t)
+{
+    if (g.d < 1 || g.d > kR2RMaxDims || g.groups < 1) std::abort();
+    return hipSuccess;
+}
+hipError_t launch_r2r_sign(Precision, const void *, void *, const R2RDesc &g, hipStream_t)
+{
+    if (g.d < 1 || g.d > kR2RMaxDims) std::abort();
+    return hipSuccess;
+}
 hipError_t launch_batch_bind(BatchBind *, const BindChunk &c, hipStream_t)
 {
     if (c.count < 1 || c.count > kBindChunk || c.first < 0) std::abort();
