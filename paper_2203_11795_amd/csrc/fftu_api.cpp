@@ -1995,8 +1995,9 @@ fftu_plan_t fftu_plan_r2r(int d, const int64_t n[], const int64_t p[], fftu_dtyp
     const std::string dd = std::to_string(d);
     const bool dst = kind == FFTU_DST;
     if (direction == FFTU_FORWARD) {
+        // the complex transform of the packed signal, then the split and the coefficients in one pass
         if (dst) pl->launch_names.push_back("fftu::k_r2rsign<" + t + ">");
-        for (const std::string &k : rc->launch_names) pl->launch_names.push_back(k);
+        for (const std::string &k : rc->rc->launch_names) pl->launch_names.push_back(k);
         pl->launch_names.push_back("fftu::k_r2rpost<" + t + ", " + dd + ">");
     } else {
         pl->launch_names.push_back("fftu::k_r2rpre<" + t + ", " + dd + ">");
@@ -2899,9 +2900,9 @@ namespace {
 // Real-input transforms: forward = the complex transform of the packed array into
 // the output, then the split in place; inverse = the merge into the output, then
 // the inverse complex transform in place.
-// DCT / DST: forward = [signs] -> real transform into the spectrum workspace ->
-// coefficients; inverse = spectrum from the coefficients -> inverse real
-// transform -> [signs] (in place on the output).
+// DCT / DST: forward = [signs] -> complex transform of the packed signal into the
+// workspace -> split and coefficients in one pass; inverse = spectrum from the
+// coefficients -> inverse real transform -> [signs] (in place on the output).
 fftu_status execute_r2r(fftu_plan_s *plan, const void *in, void *out, hipStream_t stream, Marker &mk)
 {
     fftu_plan_s *rp = plan->rc;
@@ -2915,7 +2916,7 @@ fftu_status execute_r2r(fftu_plan_s *plan, const void *in, void *out, hipStream_
             mk.mark();
             sig = out;
         }
-        fftu_status s = execute_real(rp, sig, plan->ws, stream, mk);
+        fftu_status s = execute_with(rp->rc, sig, plan->ws, rp->rc->ws, stream, nullptr, &mk);
         if (s != FFTU_SUCCESS) return s;
         e = fftu::launch_r2r_post(plan->prec, plan->ws, out, plan->r2d, plan->rtable, stream);
         if (e == hipSuccess) mk.mark();

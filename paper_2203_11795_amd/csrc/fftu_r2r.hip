@@ -5,19 +5,20 @@
 //
 // Signal side: v, the zig-zag order of x along every dimension (v[m(j)] = x[j]:
 // even samples ascending, then odd samples descending), in the real transform's
-// packed layout. Its DFT V (the real transform's half spectrum and Nyquist plane)
-// gives the DCT-II coefficients through one operator per dimension,
+// packed layout. Its DFT V gives the DCT-II coefficients through one operator per
+// dimension,
 //     (C f)[k] = w^k f[k] + w^-k f[n - k],   w = exp(-2 pi i / (4 n)),
 // (index n - 0 read as 0): y = (C_1 x ... x C_d) V, which is real. C_l couples
 // k_l and n_l - k_l only, so a thread takes the 2^d indices that are mirror images
 // of one representative (k_l in [0, n_l/2]) in any subset of the dimensions,
-// reads V there (the conjugate of the half spectrum at -k where k_d > n_d/2),
-// applies the C_l in registers and stores y. On a pair (a, b) = (f[k], f[n - k]):
+// forms V there from the complex transform of the packed signal (the real
+// transform's split, in the same pass), applies the C_l in registers and stores
+// y. On a pair (a, b) = (f[k], f[n - k]):
 //     C a = w^k a + w^-k b,   C b = i (w^k a - w^-k b).
 // The inverse applies C_l^-1, a = w^-k (g_a - i g_b) / 2, b = w^k (g_a + i g_b) / 2
-// (k = 0: a = g_a / 2), writes V on the half spectrum and the plane, and the
-// inverse real transform gives v. At k = 0 and k = n/2 a and b are one element:
-// only the first copy is stored.
+// (k = 0: a = g_a / 2), writes V on the half spectrum and the plane (the real
+// transform's complex side), and the inverse real transform gives v. At k = 0 and
+// k = n/2 a and b are one element: only the first copy is stored.
 // DST-II: y_s[k] = DCT-II(x')[n - 1 - k] with x'[j] = (-1)^j x[j], that is
 // v'[m] = v[m] for m < n/2 and -v[m] otherwise along every dimension: a sign
 // pass on the signal, the DCT, and the store at n_l - 1 - k_l.
@@ -42,22 +43,6 @@ __device__ __forceinline__ int64_t spec_position(const RealDesc &rd, const int32
         i = i * uint32_t(rd.m[l]) + uint32_t(k[l]) / uint32_t(rd.p[l]);
     }
     return dims == rd.d ? int64_t(r) * rd.Mh + i : rd.Nh + int64_t(r) * rd.Mp + i;
-}
-
-// V at full index k (k_d in [0, n_d)): the half spectrum, the plane, or the
-// conjugate of the half spectrum at -k.
-template <typename T, int D>
-__device__ __forceinline__ cx<T> spectrum_at(const cx<T> *spec, const R2RDesc &g, const int32_t (&k)[D])
-{
-    const int32_t h = g.rd.h, kd = k[D - 1];
-    if (kd < h) return spec[spec_position(g.rd, k, D)];
-    if (kd == h) return spec[spec_position(g.rd, k, D - 1)];
-    int32_t nk[D];
-#pragma unroll
-    for (int l = 0; l < D - 1; ++l) nk[l] = k[l] == 0 ? 0 : g.n[l] - k[l];
-    nk[D - 1] = g.n[D - 1] - kd;
-    const cx<T> a = spec[spec_position(g.rd, nk, D)];
-    return {a.x, -a.y};
 }
 
 // Position of coefficient index k (cyclic over p).
@@ -109,21 +94,42 @@ __device__ __forceinline__ cx<T> times_i(cx<T> a) { return {-a.y, a.x}; }
 
 }  // namespace
 
+// Forward: the real transform's split and the coefficients in one pass. It reads
+// Z = F(z), the complex transform of the packed signal z[j', j] = v[j', 2j] +
+// i v[j', 2j + 1] (shape n', h = n_d / 2), before the split into the half
+// spectrum: V[k] = E + w_{n_d}^{k_d} O at every full index k, with E = (Z[k~] +
+// conj Z[-k~]) / 2 and O = (Z[k~] - conj Z[-k~]) / (2i), k~ = k with k_d mod h. The
+// packed indices a group needs are the mirror images of its representative in
+// packed space (k_d and n_d - k_d reduce to k_d and h - k_d mod h), and -k~ is the
+// image with every coordinate mirrored: the complementary member.
 template <typename T, int D>
-__global__ __launch_bounds__(256) void k_r2rpost(const cx<T> *__restrict__ spec, T *__restrict__ y, const R2RDesc g,
+__global__ __launch_bounds__(256) void k_r2rpost(const cx<T> *__restrict__ zf, T *__restrict__ y, const R2RDesc g,
                                                  const cx<T> *__restrict__ table)
 {
     constexpr int G = 1 << D;
     const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    const int32_t h = g.rd.h;
+    const int64_t wstep = 4 * int64_t(g.tstep[D - 1]);   // omega_{n_d}^e = table entry e wstep
     for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < g.groups; t += stride) {
         int32_t k[D];
         representative<D>(g, t, k);
+        cx<T> zv[G];
+#pragma unroll
+        for (int mask = 0; mask < G; ++mask) {
+            int32_t pk[D];
+            member<D>(g, k, mask, pk);
+            const int32_t base = k[D - 1] == h ? 0 : k[D - 1];
+            pk[D - 1] = ((mask >> (D - 1)) & 1) ? (base == 0 ? 0 : h - base) : base;
+            zv[mask] = zf[spec_position(g.rd, pk, D)];
+        }
         cx<T> v[G];
 #pragma unroll
         for (int mask = 0; mask < G; ++mask) {
-            int32_t kk[D];
-            member<D>(g, k, mask, kk);
-            v[mask] = spectrum_at<T, D>(spec, g, kk);
+            const cx<T> a = zv[mask], b = zv[(G - 1) ^ mask];
+            const cx<T> E = {(a.x + b.x) * T(0.5), (a.y - b.y) * T(0.5)};
+            const cx<T> O = {(a.y + b.y) * T(0.5), (b.x - a.x) * T(0.5)};
+            const int32_t kd = ((mask >> (D - 1)) & 1) ? (k[D - 1] == 0 ? 0 : g.n[D - 1] - k[D - 1]) : k[D - 1];
+            v[mask] = E + cmul(table[int64_t(kd) * wstep], O);
         }
 #pragma unroll
         for (int l = 0; l < D; ++l) {
