@@ -930,6 +930,23 @@ def main():
     kernels = [{"launch": i, "kernel": s, "avg_ms": round(t, 4),
                 "GBps_alg": round(alg_bytes / (t * 1e-3) / 1e9, 1) if t > 0 else None}
                for i, (s, t) in enumerate(zip(syms, per_launch))]
+    # a practical reference beside the peak: a device-to-device copy of the same array
+    # (torch's copy_, the runtime's copy), timed with HIP events on the same stream
+    scratch = torch.empty_like(x)          # `out` keeps the transform for the check below
+    for _ in range(3):
+        scratch.copy_(x)
+    c0 = torch.cuda.Event(enable_timing=True)
+    c1 = torch.cuda.Event(enable_timing=True)
+    c0.record(stream)
+    for _ in range(10):
+        scratch.copy_(x)
+    c1.record(stream)
+    torch.cuda.synchronize()
+    copy_gbps = alg_bytes / (c0.elapsed_time(c1) / 10 * 1e-3) / 1e9
+    del scratch
+    roofline["copy_reference"] = {"what": "device-to-device copy of the same array (torch copy_)",
+                                  "GBps": round(copy_gbps, 1), "frac": round(copy_gbps / HBM_PEAK_GBS, 4),
+                                  "dominant_kernel_vs_copy": round(achieved / copy_gbps, 3)}
     transform_bytes = info["launches"] * alg_bytes
     frac_transform = transform_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS
     # the scope's algorithmic bytes: the fewest passes this shape needs (local dimensions
