@@ -245,8 +245,9 @@ fftu_plan_t fftu_plan_real(int d, const int64_t n[], const int64_t p[], fftu_dty
  * combines each index with its mirror images n_l - k_l; the inverse runs the
  * combining pass first. The DST is the DCT of the signal with the samples of odd
  * j negated (one more pass), stored at n_l - 1 - k_l.
- * Requirements: 1 <= d <= 4 (else UNSUPPORTED), every n_l even (else
- * INVALID_VALUE), and every requirement of fftu_plan_real for v. Execute with
+ * Requirements: 1 <= d <= 4 and lcm(4 n_l) < 2^26 (the table of the combining pass;
+ * else UNSUPPORTED), every n_l even (else INVALID_VALUE), and every requirement of
+ * fftu_plan_real for v. Execute with
  * fftu_execute (in == out allowed; otherwise the buffers must not overlap);
  * fftu_execute_ws, fftu_execute_noalloc and the stage calls refuse these plans.
  * The plan owns a spectrum workspace of N/2 + N/n_d complex elements.

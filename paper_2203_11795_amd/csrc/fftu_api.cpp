@@ -1147,7 +1147,8 @@ bool plan_gc(int d, const int64_t n[], const int64_t p[], fftu_dtype dt, GcPlan 
         int logg = 0;
         for (int l = 0; l < d; ++l)
             if (gp.put[size_t(gp.H - 1)].dim[l].mode == 2) logg += ilog2(gp.put[size_t(gp.H - 1)].dim[l].pi);
-        if (logg >= 1 && logg <= fftu::kGplastMaxLogG && gp.N < (int64_t(1) << 31)) gp.last_logg = logg;
+        if (logg >= 1 && logg <= fftu::kGplastMaxLogG && gp.N < (int64_t(1) << 31) && gp.T < (int64_t(1) << 26))
+            gp.last_logg = logg;
     }
     return true;
 }
