@@ -415,17 +415,26 @@ class RealPlan(Plan):
         import torch
         return torch.float64 if self.dtype_code == C128 else torch.float32
 
-    def __call__(self, x, out=None, stream=None):
-        import torch
+    def _sides(self):
         fwd = self.direction == FORWARD
-        in_dt, in_n = (self.real_dtype, self.N) if fwd else (self.torch_dtype, self.complex_elems)
-        out_dt, out_n = (self.torch_dtype, self.complex_elems) if fwd else (self.real_dtype, self.N)
+        in_side = (self.real_dtype, self.N) if fwd else (self.torch_dtype, self.complex_elems)
+        out_side = (self.torch_dtype, self.complex_elems) if fwd else (self.real_dtype, self.N)
+        return in_side, out_side
+
+    def _check_io(self, x, out):
+        import torch
+        (in_dt, in_n), (out_dt, out_n) = self._sides()
         for t, dt, n, name in ((x, in_dt, in_n, "input"), (out, out_dt, out_n, "output")):
             if t is None:
                 continue
             if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != dt or t.numel() != n \
                     or not t.is_contiguous():
                 raise ValueError(f"{name} must be a contiguous {dt} device tensor of {n} elements")
+
+    def __call__(self, x, out=None, stream=None):
+        import torch
+        self._check_io(x, out)
+        (_, _), (out_dt, out_n) = self._sides()
         if out is None:
             out = torch.empty(out_n, dtype=out_dt, device=x.device)
         if stream is None:
@@ -467,7 +476,7 @@ class R2RPlan(Plan):
         import torch
         return torch.float64 if self.dtype_code == C128 else torch.float32
 
-    def __call__(self, x, out=None, stream=None):
+    def _check_io(self, x, out):
         import torch
         for t, name in ((x, "input"), (out, "output")):
             if t is None:
@@ -475,6 +484,10 @@ class R2RPlan(Plan):
             if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != self.real_dtype or \
                     t.numel() != self.N or not t.is_contiguous():
                 raise ValueError(f"{name} must be a contiguous {self.real_dtype} device tensor of {self.N} elements")
+
+    def __call__(self, x, out=None, stream=None):
+        import torch
+        self._check_io(x, out)
         if out is None:
             out = torch.empty(self.N, dtype=self.real_dtype, device=x.device)
         if stream is None:
@@ -694,8 +707,11 @@ class Graph:
             plan.check_buffers(xs, outs)
             count = len(xs)
         else:
-            plan._check_tensor(xs, "input")
-            plan._check_tensor(outs, "output")
+            if hasattr(plan, "_check_io"):        # real and DCT / DST plans: their own sides
+                plan._check_io(xs, outs)
+            else:
+                plan._check_tensor(xs, "input")
+                plan._check_tensor(outs, "output")
             count = 0
             xs, outs = [xs], [outs]
         self._bufs = (xs, outs)
