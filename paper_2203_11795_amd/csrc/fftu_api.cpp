@@ -40,7 +40,9 @@ struct fftu_plan_s {
     fftu_plan_s *conv_inv = nullptr; // fftu_plan_convolution: the inverse plan (external, uses this plan's workspace)
     // mixed-radix plans (some side not a power of two)
     bool mixed = false;
-    bool mfused = false;             // mixed radix with k_mexchange
+    bool mfused = false;             // mixed radix with k_mexchange (or k_mxexchange)
+    bool mx = false;                 // the fused exchange on k_mxexchange
+    fftu::MxSplit mxs{};
     std::vector<fftu::MixedPassDesc> ms0, ms2;
     fftu::MixedGridDesc mg{};
     int64_t table_T = 0;             // entries of the twiddle table omega_T
@@ -948,6 +950,8 @@ struct MixedPlan {
     fftu::MixedGridDesc g{};
     int64_t T = 1;
     bool fused = false;   // k_mexchange: twiddle, Put and Superstep 2 in one kernel
+    bool mx = false;      // the fused form on k_mxexchange (every grid side a power of two)
+    fftu::MxSplit mxs{};
 };
 
 bool plan_mixed(int d, const int64_t n[], const int64_t p[], fftu_dtype dt, MixedPlan &mp)
@@ -993,6 +997,28 @@ bool plan_mixed(int d, const int64_t n[], const int64_t p[], fftu_dtype dt, Mixe
     }
     mp.fused = g.P <= fftu::kMexMaxP;
     for (int l = 0; l < d; ++l) mp.fused = mp.fused && fftu::mexchange_radix_ok(g.p[l]);
+    // every grid side a power of two: the register split of the power-of-two exchange
+    bool pow2_grid = g.P > 1;
+    for (int l = 0; l < d; ++l) pow2_grid = pow2_grid && is_pow2(p[l]);
+    if (pow2_grid && g.N < (int64_t(1) << 31)) {
+        Geometry G{};
+        G.d = d;
+        for (int l = 0; l < d; ++l) G.logp[l] = ilog2(p[l]);
+        ExchangeSplit sp;
+        if (exchange_split(G, dt, &sp)) {
+            mp.mx = true;
+            mp.fused = true;
+            mp.mxs = fftu::MxSplit{};
+            mp.mxs.nr = sp.nr;
+            mp.mxs.lpr = sp.lpr;
+            mp.mxs.nh = sp.nh;
+            mp.mxs.lph = sp.lph;
+            for (size_t i = 0; i < sp.rdims.size(); ++i) mp.mxs.rdim[i] = sp.rdims[i];
+            for (size_t i = 0; i < sp.hdims.size(); ++i) mp.mxs.hdim[i] = sp.hdims[i];
+            const int logR = sp.nr * sp.lpr;
+            mp.mxs.lds_bytes = sp.nh > 0 ? uint32_t(fftu::kExchangeThreads / 64) * 64u * (1u << logR) * 8u : 0u;
+        }
+    }
     return true;
 }
 
@@ -1575,10 +1601,17 @@ fftu_plan_s *build_mixed_plan(int d, const int64_t n[], const int64_t p[], fftu_
     pl->grid.M = mp.g.M;
     pl->grid.d = d;
     pl->mfused = mp.fused;
+    pl->mx = mp.mx;
+    pl->mxs = mp.mxs;
     pl->launches = int(mp.s0.size() + 1 + (mp.fused ? 0 : mp.s2.size()));
     const std::string t = dtype == FFTU_C128 ? "double" : "float";
     for (size_t i = 0; i < mp.s0.size(); ++i) pl->launch_names.push_back("fftu::k_mline<" + t + ">");
-    if (mp.fused) {
+    if (mp.mx) {
+        auto sv = [](int v) { return std::to_string(v); };
+        const fftu::MxSplit &x = mp.mxs;
+        pl->launch_names.push_back("fftu::k_mxexchange<" + t + ", " + sv(x.nr) + ", " + sv(x.nr ? x.lpr : 0) + ", " +
+                                   sv(x.nh) + ", " + sv(x.nh ? x.lph : 0) + ">");
+    } else if (mp.fused) {
         const bool tl = fftu::mexchange_table_in_lds(mp.g.P, mp.T, int(pl->esize));
         pl->launch_names.push_back("fftu::k_mexchange<" + t + (tl ? ", true>" : ", false>"));
     } else {
@@ -2706,7 +2739,8 @@ fftu_status execute_mixed(fftu_plan_s *plan, const void *in, void *out, void *ws
         g.mul = mul;
         const void *src = ws;
         if (plan->ms0.empty() && in != out) src = in;
-        hipError_t e = fftu::launch_mexchange(plan->prec, src, out, g, plan->table, stream);
+        hipError_t e = plan->mx ? fftu::launch_mxexchange(plan->prec, src, out, g, plan->mxs, plan->table, stream)
+                                : fftu::launch_mexchange(plan->prec, src, out, g, plan->table, stream);
         if (e == hipSuccess) mk.mark();
         return from_hip(e);
     }

@@ -313,6 +313,21 @@ struct R2RDesc {
     RealDesc rd;            // the half spectrum of the signal (packed shape, Nyquist plane)
 };
 
+// k_mxexchange (fftu_mixed.hip): the mixed-radix exchange for grids whose sides are
+// powers of two (any local sides): the register and wave split of k_exchange (NR
+// register dimensions of 2^LPR, NH wave dimensions of 2^LPH) with general index
+// arithmetic for the local sides.
+struct MxSplit {
+    int32_t nr, lpr, nh, lph;
+    int32_t rdim[kMaxDims];
+    int32_t hdim[kMaxDims];
+    uint32_t lds_bytes;
+};
+// k_mxexchange work items: W = rows x nchunk, bit consecutive items per workgroup.
+struct MxRows {
+    uint32_t nchunk, W, bit;
+};
+
 // k_mexchange: P sources of 64 local indices in LDS, grid sides of one radix stage.
 constexpr int64_t kMexMaxP = 64;
 constexpr int kMexThreads = 512;
@@ -439,6 +454,8 @@ hipError_t launch_lastx(Precision prec, const void *in, void *out, const LastxDe
 // array (fftu_real.hip); `table` holds omega_{n_d}^j, j in [n_d]. rsplit: in place
 // on buf (forward; writes the Nyquist plane after the Nh packed elements). rmerge:
 // from in (half spectrum and plane) to out (Nh elements; in == out allowed).
+hipError_t launch_mxexchange(Precision prec, const void *in, void *out, const MixedGridDesc &g, const MxSplit &sp,
+                             const void *table, hipStream_t stream);
 hipError_t launch_rsplit(Precision prec, void *buf, const RealDesc &rd, const void *table, hipStream_t stream);
 // Coefficients from the half spectrum (forward), the half spectrum from the
 // coefficients (inverse), and the sign pattern of the DST's signal (in place allowed).

@@ -24,6 +24,7 @@
 #include <cstdint>
 
 #include "fftu_device.hpp"
+#include "fftu_exchange.hpp"
 #include "fftu_internal.hpp"
 
 namespace fftu {
@@ -428,6 +429,303 @@ __global__ __launch_bounds__(kMexThreads) void k_mexchange(const cx<T> *__restri
             }
         }
     }
+}
+
+// The mixed-radix exchange where every grid side is a power of two (the local sides
+// may be any product of 2, 3, 5, 7): the structure of k_exchange (fftu_exchange.hip)
+// with general index arithmetic. A group is 64 consecutive local indices k (one
+// per lane) of every source block; for k = r + t p (per dimension) the P sources
+// s' are the inputs of one F_{p_1} x ... x F_{p_d} whose output k' lands in
+// V^(r)[t + k' q] (Theorem 2.1). The grid dimensions with p_l > 1 split into NH
+// leading wave dimensions of 2^LPH and NR trailing register dimensions of 2^LPR: a
+// thread holds the 2^(NR LPR) sources of one wave index in registers (each load
+// instruction reads 64 consecutive elements of one block), twiddles them by
+// omega_T^e, e = sum_l s'_l k_l T / n_l (every term below T, the sum reduced with one
+// quotient estimate), runs the register dimensions' DFTs with compile-time roots,
+// swaps through LDS so that each thread holds every wave index of some register
+// outputs, runs the wave dimensions' DFTs and scatters (runs of 64 / p_d elements).
+template <typename T, int NR, int LPR, int NH, int LPH>
+__global__ __launch_bounds__(kExchangeThreads) void k_mxexchange(const cx<T> *__restrict__ Z, cx<T> *__restrict__ V,
+                                                                const MixedGridDesc g, const MxSplit sp,
+                                                                const MxRows rw, const cx<T> *__restrict__ table)
+{
+    constexpr int LOGR = NR * LPR, LOGH = NH * LPH;
+    constexpr int R = 1 << LOGR;
+    constexpr int H = 1 << LOGH;
+    constexpr int U = LOGH > 0 ? R / H : R;   // register slots per thread after the LDS swap
+    constexpr int KG = (kExchangeThreads / 64) / H;
+    extern __shared__ unsigned char smem_raw[];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wv = tid >> 6;
+    const int hw = wv & (H - 1);
+    const int grp = wv >> LOGH;
+    const uint32_t M = uint32_t(g.M);          // N < 2^31: 32-bit indices
+    const uint32_t tn = uint32_t(g.T);
+    const float inv_tn = 1.0f / float(tn);
+    const T scale = static_cast<T>(g.scale);
+    const cx<T> *mul = static_cast<const cx<T> *>(g.mul);
+    // output offset of digit 1 of each register and wave dimension: k'_l moves by
+    // q_l prod_{j>l} m_j (uniform)
+    uint32_t ors[NR > 0 ? NR : 1], ohs[NH > 0 ? NH : 1];
+    {
+        uint32_t ms = 1;
+#pragma unroll
+        for (int l = kMaxDims - 1; l >= 0; --l) {
+            if (l >= g.d) continue;
+#pragma unroll
+            for (int dd = 0; dd < NR; ++dd)
+                if (sp.rdim[dd] == l) ors[dd] = uint32_t(g.q[l]) * ms;
+#pragma unroll
+            for (int dd = 0; dd < NH; ++dd)
+                if (sp.hdim[dd] == l) ohs[dd] = uint32_t(g.q[l]) * ms;
+            ms *= uint32_t(g.m[l]);
+        }
+    }
+    auto reduce = [&](uint32_t e) {
+        int32_t r = int32_t(e - uint32_t(float(e) * inv_tn) * tn);
+        r += r < 0 ? int32_t(tn) : 0;
+        r -= r >= int32_t(tn) ? int32_t(tn) : 0;
+        return uint32_t(r);
+    };
+    // Work item it = (row rho, chunk c): the KG*64 slots of a workgroup take columns
+    // k_{d-1} in [c KG 64, (c + 1) KG 64) of source row rho, so the row's outputs (one
+    // full row of m_{d-1} elements per destination block and output digit) are written
+    // by one workgroup. Rows run over k_0..k_{d-2} with k_{d-2} = r + p t taken t-fastest:
+    // consecutive rows fill adjacent output rows, and a block of rw.bit items per
+    // workgroup keeps a cache line shared by two rows inside one workgroup.
+    const uint32_t mlast = uint32_t(g.m[g.d - 1]);
+    const uint32_t nblk = __builtin_amdgcn_readfirstlane(int(gridDim.x));
+    for (uint32_t it0 = blockIdx.x * rw.bit; it0 < rw.W; it0 += nblk * rw.bit)
+    for (uint32_t it = it0; it < it0 + rw.bit && it < rw.W; ++it) {
+        const uint32_t rho = it / rw.nchunk;
+        const uint32_t kd = (it - rho * rw.nchunk) * uint32_t(KG * 64) + uint32_t(grp * 64 + lane);
+        const bool valid = kd < mlast;
+        uint32_t kx[kMaxDims];
+        {
+            uint32_t rem = rho;
+#pragma unroll
+            for (int l = kMaxDims - 1; l >= 0; --l) {
+                kx[l] = 0;
+                if (l >= g.d) continue;
+                if (l == g.d - 1) {
+                    kx[l] = valid ? kd : 0u;
+                    continue;
+                }
+                const uint32_t ml = uint32_t(g.m[l]);
+                const uint32_t raw = rem % ml;
+                rem /= ml;
+                if (l == g.d - 2) {
+                    const uint32_t ql = uint32_t(g.q[l]);
+                    kx[l] = raw / ql + uint32_t(g.p[l]) * (raw % ql);
+                } else {
+                    kx[l] = raw;
+                }
+            }
+        }
+        // k (row-major over m), the twiddle steps c_l = k_l T / n_l of the register and
+        // wave dimensions, the destination block r and offset t
+        uint32_t cr[NR > 0 ? NR : 1], ch[NH > 0 ? NH : 1];
+        uint32_t k = 0, rank_r = 0, dst_t = 0;
+        {
+            uint32_t ms = 1, ps = 1;
+#pragma unroll
+            for (int l = kMaxDims - 1; l >= 0; --l) {
+                if (l >= g.d) continue;
+                const uint32_t ml = uint32_t(g.m[l]), pl = uint32_t(g.p[l]);
+                const uint32_t kl = kx[l];
+                const uint32_t cl = kl * uint32_t(g.tstep[l]);
+#pragma unroll
+                for (int dd = 0; dd < NR; ++dd)
+                    if (sp.rdim[dd] == l) cr[dd] = cl;
+#pragma unroll
+                for (int dd = 0; dd < NH; ++dd)
+                    if (sp.hdim[dd] == l) ch[dd] = cl;
+                k += kl * ms;
+                rank_r += (kl & (pl - 1)) * ps;          // p_l a power of two
+                dst_t += (kl / pl) * ms;
+                ms *= ml;
+                ps *= pl;
+            }
+        }
+        uint32_t e_hi = 0;
+#pragma unroll
+        for (int dd = 0; dd < NH; ++dd) e_hi += uint32_t((hw >> (LPH * (NH - 1 - dd))) & ((1 << LPH) - 1)) * ch[dd];
+
+        cx<T> v[R];
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            const uint32_t s = (uint32_t(hw) << LOGR) + uint32_t(j);
+            v[j] = valid ? get(&Z[s * M + k]) : cx<T>{T(0), T(0)};
+        }
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            uint32_t e = e_hi;
+#pragma unroll
+            for (int dd = 0; dd < NR; ++dd) e += uint32_t((j >> (LPR * (NR - 1 - dd))) & ((1 << LPR) - 1)) * cr[dd];
+            v[j] = conj_if(v[j], g.conj_in);
+            if (g.twiddle) v[j] = cmul(v[j], table[reduce(e)]);
+        }
+        dft_digits<T, NR, LPR, 1, 1>(v);
+
+        const uint32_t obase = rank_r * M + dst_t;
+        auto roff = [&](int j) {
+            uint32_t off = 0;
+#pragma unroll
+            for (int dd = 0; dd < NR; ++dd) off += uint32_t((j >> (LPR * (NR - 1 - dd))) & ((1 << LPR) - 1)) * ors[dd];
+            return off;
+        };
+        auto hoff = [&](int i) {
+            uint32_t off = 0;
+#pragma unroll
+            for (int dd = 0; dd < NH; ++dd) off += uint32_t((i >> (LPH * (NH - 1 - dd))) & ((1 << LPH) - 1)) * ohs[dd];
+            return off;
+        };
+        auto store = [&](uint32_t idx, cx<T> w) {
+            w = conj_if(w, g.conj_out);
+            if (g.scale != 1.0) w = {w.x * scale, w.y * scale};
+            if (mul) w = cmul(w, mul[idx]);
+            V[idx] = w;   // cached: L2 merges the partial lines of neighbouring output runs
+        };
+        if constexpr (LOGH == 0) {
+            if (valid) {
+#pragma unroll
+                for (int j = 0; j < R; ++j) store(obase + roff(j), v[j]);
+            }
+        } else {
+            // swap through LDS: register j of wave hw goes to the wave that owns slot j
+            // (complex128 in two rounds of doubles)
+            cx<T> w[H * U];
+            if constexpr (sizeof(T) == 8) {
+                T *ld = reinterpret_cast<T *>(smem_raw);
+                __syncthreads();
+#pragma unroll
+                for (int j = 0; j < R; ++j) ld[((hw * R + j) * KG + grp) * 64 + lane] = v[j].x;
+                __syncthreads();
+#pragma unroll
+                for (int x = 0; x < H; ++x)
+#pragma unroll
+                    for (int u = 0; u < U; ++u) w[x * U + u].x = ld[((x * R + hw * U + u) * KG + grp) * 64 + lane];
+                __syncthreads();
+#pragma unroll
+                for (int j = 0; j < R; ++j) ld[((hw * R + j) * KG + grp) * 64 + lane] = v[j].y;
+                __syncthreads();
+#pragma unroll
+                for (int x = 0; x < H; ++x)
+#pragma unroll
+                    for (int u = 0; u < U; ++u) w[x * U + u].y = ld[((x * R + hw * U + u) * KG + grp) * 64 + lane];
+            } else {
+                cx<T> *lds = reinterpret_cast<cx<T> *>(smem_raw);
+                __syncthreads();
+#pragma unroll
+                for (int j = 0; j < R; ++j) lds[((hw * R + j) * KG + grp) * 64 + lane] = v[j];
+                __syncthreads();
+#pragma unroll
+                for (int x = 0; x < H; ++x)
+#pragma unroll
+                    for (int u = 0; u < U; ++u) w[x * U + u] = lds[((x * R + hw * U + u) * KG + grp) * 64 + lane];
+            }
+            dft_digits<T, NH, LPH, U, U>(w);
+            if (valid) {
+#pragma unroll
+                for (int i = 0; i < H * U; ++i) store(obase + hoff(i / U) + roff(hw * U + i % U), w[i]);
+            }
+        }
+    }
+}
+
+namespace {
+
+// Work items of k_mxexchange: rows of the last dimension cut into chunks of `slots`
+// columns. Rows go to workgroups in blocks of B (and all their chunks) when a row of
+// the output is not a whole number of 128-byte lines, B the fewest rows that are and
+// that divide q_{d-2}; otherwise one chunk per item.
+MxRows mx_rows(const MixedGridDesc &g, int slots, size_t elem)
+{
+    MxRows rw{};
+    const int64_t mlast = g.m[g.d - 1];
+    rw.nchunk = uint32_t((mlast + slots - 1) / slots);
+    const uint32_t rows = uint32_t(g.M / mlast);
+    rw.W = rows * rw.nchunk;
+    rw.bit = 1;
+    const int64_t rowbytes = mlast * int64_t(elem);
+    if (g.d >= 2 && rowbytes % 128 != 0)
+        for (int b = 2; b <= 8; ++b)
+            if ((b * rowbytes) % 128 == 0 && g.q[g.d - 2] % b == 0) {
+                rw.bit = uint32_t(b) * rw.nchunk;
+                break;
+            }
+    return rw;
+}
+
+template <typename T, int NR, int LPR, int NH, int LPH>
+hipError_t mx_launch_t(const void *in, void *out, const MixedGridDesc &g, const MxSplit &sp, const void *table,
+                       hipStream_t stream)
+{
+    constexpr int KG = (kExchangeThreads / 64) >> (NH * LPH);
+    const MxRows rw = mx_rows(g, KG * 64, sizeof(cx<T>));
+    const int64_t want = (int64_t(rw.W) + rw.bit - 1) / rw.bit;
+    const uint32_t blocks = uint32_t(want < (int64_t(1) << 20) ? want : (int64_t(1) << 20));
+    hipLaunchKernelGGL((k_mxexchange<T, NR, LPR, NH, LPH>), dim3(blocks), dim3(kExchangeThreads), sp.lds_bytes, stream,
+                       static_cast<const cx<T> *>(in), static_cast<cx<T> *>(out), g, sp, rw,
+                       static_cast<const cx<T> *>(table));
+    return hipGetLastError();
+}
+
+template <typename T, int NR, int LPR>
+hipError_t mx_launch_h(const void *in, void *out, const MixedGridDesc &g, const MxSplit &sp, const void *table,
+                       hipStream_t stream)
+{
+    constexpr int LOGR = NR * LPR;
+    if (sp.nh == 0) return mx_launch_t<T, NR, LPR, 0, 0>(in, out, g, sp, table, stream);
+    if constexpr (LOGR >= 1)
+        if (sp.nh == 1 && sp.lph == 1) return mx_launch_t<T, NR, LPR, 1, 1>(in, out, g, sp, table, stream);
+    if constexpr (LOGR >= 2) {
+        if (sp.nh == 1 && sp.lph == 2) return mx_launch_t<T, NR, LPR, 1, 2>(in, out, g, sp, table, stream);
+        if (sp.nh == 2 && sp.lph == 1) return mx_launch_t<T, NR, LPR, 2, 1>(in, out, g, sp, table, stream);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <typename T, int MAXR>
+hipError_t mx_launch_r(const void *in, void *out, const MixedGridDesc &g, const MxSplit &sp, const void *table,
+                       hipStream_t stream)
+{
+    switch (sp.nr * 8 + sp.lpr) {
+    case 0 * 8 + 0: return mx_launch_h<T, 0, 0>(in, out, g, sp, table, stream);
+    case 1 * 8 + 1: return mx_launch_h<T, 1, 1>(in, out, g, sp, table, stream);
+    case 2 * 8 + 1: return mx_launch_h<T, 2, 1>(in, out, g, sp, table, stream);
+    case 3 * 8 + 1: return mx_launch_h<T, 3, 1>(in, out, g, sp, table, stream);
+    case 4 * 8 + 1: return mx_launch_h<T, 4, 1>(in, out, g, sp, table, stream);
+    case 1 * 8 + 2: return mx_launch_h<T, 1, 2>(in, out, g, sp, table, stream);
+    case 2 * 8 + 2: return mx_launch_h<T, 2, 2>(in, out, g, sp, table, stream);
+    case 1 * 8 + 3: return mx_launch_h<T, 1, 3>(in, out, g, sp, table, stream);
+    case 1 * 8 + 4: return mx_launch_h<T, 1, 4>(in, out, g, sp, table, stream);
+    case 5 * 8 + 1:
+        if constexpr (MAXR >= 5) return mx_launch_h<T, 5, 1>(in, out, g, sp, table, stream);
+        return hipErrorInvalidValue;
+    case 1 * 8 + 5:
+        if constexpr (MAXR >= 5) return mx_launch_h<T, 1, 5>(in, out, g, sp, table, stream);
+        return hipErrorInvalidValue;
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_mxexchange(Precision prec, const void *in, void *out, const MixedGridDesc &g, const MxSplit &sp,
+                             const void *table, hipStream_t stream)
+{
+    if (g.P < 1 || g.T >= (int64_t(1) << 24) || g.N >= (int64_t(1) << 31) || g.d < 1 || g.d > kMaxDims)
+        return hipErrorInvalidValue;
+    int64_t P = 1;
+    for (int l = 0; l < g.d; ++l) {
+        if (g.p[l] < 1 || (g.p[l] & (g.p[l] - 1)) || g.m[l] % g.p[l] || g.q[l] * g.p[l] != g.m[l]) return hipErrorInvalidValue;
+        P *= g.p[l];
+    }
+    if (P != g.P || (int64_t(1) << (sp.nr * sp.lpr + sp.nh * sp.lph)) != P) return hipErrorInvalidValue;
+    return prec == Precision::F64 ? mx_launch_r<double, kExchangeRegBitsF64>(in, out, g, sp, table, stream)
+                                  : mx_launch_r<float, kExchangeRegBitsF32>(in, out, g, sp, table, stream);
 }
 
 namespace {

@@ -114,6 +114,12 @@ hipError_t launch_gplast(Precision prec, const void *in, void *out, const GroupP
     return launch_gput(prec, in, out, g, t, st);
 }
 bool gput_tiling(const GroupPutDesc &, int, GputTileDesc &) { return false; }
+hipError_t launch_mxexchange(Precision, const void *in, void *out, const MixedGridDesc &g, const MxSplit &sp,
+                             const void *, hipStream_t)
+{
+    if (in == out || g.d < 1 || g.P < 2 || (int64_t(1) << (sp.nr * sp.lpr + sp.nh * sp.lph)) != g.P) std::abort();
+    return hipSuccess;
+}
 hipError_t launch_r2r_post(Precision, const void *, void *, const R2RDesc &g, const void *, hipStream_t)
 {
     if (g.d < 1 || g.d > kR2RMaxDims || g.groups < 1) std::abort();

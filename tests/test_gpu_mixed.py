@@ -20,7 +20,9 @@ CASES = [((12,), (2,)), ((36,), (3,)), ((100,), (5,)), ((1000,), (10,)), ((7,), 
          ((126, 12), (3, 2)), ((49, 27), (7, 3)), ((18, 20, 12), (3, 2, 2)), ((96, 96), (4, 2)), ((45, 8), (3, 2)),
          ((384,), (8,)), ((30, 30, 30), (1, 1, 1)), ((3072,), (4,)),
          ((48, 48, 48), (4, 4, 4)),          # P = 64 in k_mexchange, the 480^3 benchmark's grid
-         ((192, 64), (8, 8)), ((75, 98), (5, 7)), ((36, 36, 36), (6, 3, 2))]   # p = 6: unfused
+         ((192, 64), (8, 8)), ((75, 98), (5, 7)), ((36, 36, 36), (6, 3, 2)),   # p = 6: unfused
+         # rows of the last dimension that are not whole 128-byte lines: blocks of 2 or 4 rows per workgroup
+         ((80, 200), (2, 2)), ((96, 48, 240), (4, 2, 4))]
 
 
 @pytest.fixture(scope="module")
@@ -48,7 +50,13 @@ def test_mixed_transform_matches_oracle(torch, n, p, dtype, direction):
         assert info["exchange_fused"] == (1 if fused else 0)
         t = "double" if dtype == "complex128" else "float"
         if fused:
-            assert names[-1].startswith(f"fftu::k_mexchange<{t}, ") and len(names) == info["s0_kernels"] + 1
+            # power-of-two grids with a register split take k_mxexchange, the others k_mexchange
+            assert (names[-1].startswith(f"fftu::k_mexchange<{t}, ") or names[-1].startswith(f"fftu::k_mxexchange<{t}, ")) \
+                and len(names) == info["s0_kernels"] + 1, names
+            if p == (4, 4, 4):
+                assert names[-1] == f"fftu::k_mxexchange<{t}, 2, 2, 1, 2>", names
+            if p == (3, 2):
+                assert names[-1].startswith(f"fftu::k_mexchange<{t}, "), names
         else:
             assert f"fftu::k_mpermute<{t}>" in names
         assert "k_mline" in names[0] or info["s0_kernels"] == 0
