@@ -923,15 +923,19 @@ bool make_mixed_pass(int64_t A, int64_t L, int64_t B, fftu_dtype dt, int64_t T, 
     pd.nstages = mixed_radices(L, pd.radix);
     if (pd.nstages < 0) return false;
     const int kt = knob(FFTU_TUNE_MIXED_TILE_LOG);
-    const int64_t target = kt >= 9 ? (int64_t(1) << kt) : (dt == FFTU_C128 ? 1024 : 2048);   // elements per tile
+    // elements per tile: at most what the threads hold while they prefetch the next tile
+    const int64_t held = int64_t(dt == FFTU_C128 ? fftu::kMixedPreF64 : fftu::kMixedPreF32) * fftu::kMixedThreads;
+    const int64_t target = std::min(kt >= 9 ? (int64_t(1) << kt) : held, held);
+    if (L > held) return false;
     // strided lines: odd pitch in LDS, so that lanes over consecutive lines hit different banks;
     // contiguous lines are loaded along the line, pitch L
     const int64_t pitch = (B == 1 || L % 2) ? L : L + 1;
     int64_t W = 1;
     while (W * 2 * L <= target && W < fftu::kMixedMaxW) W *= 2;
     while (W > 1 && W / 2 >= A * B) W /= 2;                  // no tile much wider than the lines there are
-    while (W > 1 && (2 * W * pitch + L) * esize > cap) W /= 2;
-    if ((2 * W * pitch + L) * esize > cap) return false;
+    auto lds = [&](int64_t w) { return (2 * w * pitch + L) * esize; };
+    while (W > 1 && lds(W) > cap) W /= 2;
+    if (lds(W) > cap) return false;
     pd.A = A;
     pd.B = B;
     pd.L = int32_t(L);
@@ -941,7 +945,7 @@ bool make_mixed_pass(int64_t A, int64_t L, int64_t B, fftu_dtype dt, int64_t T, 
     pd.tiles = (A * B + W - 1) / W;
     pd.tstep = T / L;
     pd.scale = 1.0;
-    pd.lds_bytes = uint32_t((2 * W * pitch + L) * esize);
+    pd.lds_bytes = uint32_t(lds(W));
     return true;
 }
 

@@ -161,6 +161,16 @@ __device__ __forceinline__ cx<T> get(const cx<T> *p)
     }
 }
 
+// Workgroup barrier that orders LDS only: this wave's LDS accesses complete before
+// the barrier and later ones start after it, while global loads stay in flight
+// (__syncthreads() also waits for every outstanding global access).
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Store of one element: non-temporal, as get(). With CO (device-coherent), the
 // store is a device-scope relaxed atomic instead: it is written through to the
 // level that every workgroup of the device reads from, so that once the storing

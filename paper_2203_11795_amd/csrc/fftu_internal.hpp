@@ -217,7 +217,8 @@ struct LastxDesc {
 
 // Mixed-radix path (fftu_mixed.hip): sides with factors 2, 3, 5 and 7.
 constexpr int kMixedThreads = 256;
-constexpr int kMixedBatch = 4;         // global loads per thread in flight in k_mline
+constexpr int kMixedPreF64 = 4;        // k_mline: tile elements per thread (the next tile, prefetched)
+constexpr int kMixedPreF32 = 8;
 constexpr int kMixedMaxW = 256;        // lines per k_mline tile at most
 constexpr int kMixedMaxStages = 24;
 

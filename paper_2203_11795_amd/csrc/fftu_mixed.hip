@@ -21,6 +21,7 @@
 // takes N < 2^31. Loops that hold barriers run on wave-uniform values.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdint>
 
 #include "fftu_device.hpp"
@@ -129,12 +130,21 @@ __device__ __forceinline__ void mixed_stage(const cx<T> *src, cx<T> *dst, const 
 
 }  // namespace
 
+// Elements of a tile per thread (the tile holds at most kMixedThreads times as many).
 template <typename T>
-__global__ __launch_bounds__(kMixedThreads) void k_mline(const cx<T> *in, cx<T> *out, const MixedPassDesc pd,
-                                                         const cx<T> *__restrict__ table)
+constexpr int mline_pre() { return sizeof(T) == 8 ? kMixedPreF64 : kMixedPreF32; }
+
+// The grid is persistent (about as many workgroups as fit on the device at once):
+// a workgroup loads its next tile into registers while it transforms the current
+// one, so each CU keeps loads in flight through the LDS stages as well. Its
+// barriers order LDS only, so that they do not wait for those loads.
+template <typename T>
+__global__ __launch_bounds__(kMixedThreads) void k_mline(const cx<T> *__restrict__ in, cx<T> *__restrict__ out,
+                                                         const MixedPassDesc pd, const cx<T> *__restrict__ table)
 {
+    constexpr int PRE = mline_pre<T>();
     extern __shared__ unsigned char smem_raw[];
-    __shared__ int64_t lbase[kMixedMaxW];   // strided tiles: global offset of each line's first element
+    __shared__ uint32_t lbase[2][kMixedMaxW];   // strided tiles: offset of each line's first element (two tiles)
     const int L = pd.L, W = pd.W;
     const int pitch = int(pd.pitch);   // strided tiles: odd, so consecutive lines fall on different LDS banks
     cx<T> *tw = reinterpret_cast<cx<T> *>(smem_raw);
@@ -143,57 +153,82 @@ __global__ __launch_bounds__(kMixedThreads) void k_mline(const cx<T> *in, cx<T> 
     const int tid = threadIdx.x;
     // launch sizes in scalar registers: the tile loop holds barriers
     const int nt = __builtin_amdgcn_readfirstlane(int(blockDim.x));
-    const int64_t nblocks = __builtin_amdgcn_readfirstlane(int(gridDim.x));
-    for (int j = tid; j < L; j += nt) tw[j] = table[int64_t(j) * pd.tstep];
-    const T scale = static_cast<T>(pd.scale);
+    const uint32_t nblocks = __builtin_amdgcn_readfirstlane(int(gridDim.x));
     const uint32_t B = uint32_t(pd.B);
-    for (int64_t t = blockIdx.x; t < pd.tiles; t += nblocks) {
-        // the tile holds lines u0 .. u0 + lines - 1 of the A B lines (line u = a B + b);
-        // `lines` is wave-uniform
-        const uint32_t u0 = uint32_t(t) << pd.logW;
-        const uint32_t total = uint32_t(pd.A) * B;
-        const int lines = int(total - u0 < uint32_t(W) ? total - u0 : uint32_t(W));
-        __syncthreads();   // twiddle copy done / previous tile's LDS reads done
-        if (B != 1) {
-            // line u = a B + b starts at (a L) B + b: one division per line, not per element
-            for (int w = tid; w < lines; w += nt) {
-                const uint32_t u = u0 + uint32_t(w);
-                const uint32_t a = u / B;
-                lbase[w] = int64_t(a) * L * B + (u - a * B);
-            }
-            __syncthreads();
+    const uint32_t total = uint32_t(pd.A) * B;    // lines
+    const uint32_t tiles = uint32_t(pd.tiles);
+    const T scale = static_cast<T>(pd.scale);
+    auto tile_lines = [&](uint32_t t) {
+        const uint32_t u0 = t << pd.logW;
+        return int(total - u0 < uint32_t(W) ? total - u0 : uint32_t(W));
+    };
+    // line u = a B + b starts at (a L) B + b: one division per line, not per element
+    auto set_lbase = [&](uint32_t t, int slot) {
+        const uint32_t u0 = t << pd.logW;
+        const int lines = tile_lines(t);
+        for (int w = tid; w < lines; w += nt) {
+            const uint32_t u = u0 + uint32_t(w);
+            const uint32_t a = u / B;
+            lbase[slot][w] = a * uint32_t(L) * B + (u - a * B);
         }
+    };
+    // element e of tile t: LDS offset (line w, position x) and global offset. With B = 1
+    // the tile's lines are contiguous in memory and e runs along them (the LDS pitch is
+    // L there); otherwise lanes run over consecutive lines (consecutive b: runs of up
+    // to min(W, B) elements). e < 2^22, so the quotient comes from one float estimate
+    // and a correction.
+    auto where = [&](uint32_t t, int lines, int slot, int e, int &off) -> uint32_t {
+        if (B == 1) {
+            off = e;
+            return (t << pd.logW) * uint32_t(L) + uint32_t(e);
+        }
+        const int x = div_small(e, lines, 1.0f / float(lines));
+        const int w = e - x * lines;
+        off = w * pitch + x;
+        return lbase[slot][w] + uint32_t(x) * B;
+    };
+    // branch-free (elements past the tile reload element 0), so that the loads issue
+    // back to back and are waited for only where the values are used
+    auto prefetch = [&](cx<T> (&r)[PRE], uint32_t t, int slot) {
+        const int lines = tile_lines(t);
         const int n = lines * L;
-        const float inv_lines = 1.0f / float(lines);
-        // element e of the tile: LDS offset (line w, position x) and global offset. With
-        // B = 1 the tile's lines are contiguous in memory and e runs along them (the LDS
-        // pitch is L there); otherwise lanes run over consecutive lines (consecutive b:
-        // runs of up to min(W, B) elements). e < 2^22, so the quotient comes from one
-        // float estimate and a correction.
-        auto where = [&](int e, int &off) -> int64_t {
-            if (B == 1) {
-                off = e;
-                return int64_t(u0) * L + e;
-            }
-            const int x = div_small(e, lines, inv_lines);
-            const int w = e - x * lines;
-            off = w * pitch + x;
-            return lbase[w] + int64_t(x) * B;
-        };
-        // kMixedBatch loads per thread in flight, then their LDS stores
-        for (int e0 = tid; e0 < n; e0 += kMixedBatch * nt) {
-            cx<T> r[kMixedBatch];
-            int off[kMixedBatch];
 #pragma unroll
-            for (int i = 0; i < kMixedBatch; ++i) {
-                const int e = e0 + i * nt;
-                if (e < n) r[i] = get(&in[where(e, off[i])]);
-            }
-#pragma unroll
-            for (int i = 0; i < kMixedBatch; ++i)
-                if (e0 + i * nt < n) buf0[off[i]] = conj_if(r[i], pd.conj_in);
+        for (int i = 0; i < PRE; ++i) {
+            const int e = tid + i * nt;
+            int off;
+            r[i] = get(&in[where(t, lines, slot, e < n ? e : 0, off)]);
         }
-        __syncthreads();
+    };
+
+    for (int j = tid; j < L; j += nt) tw[j] = table[int64_t(j) * pd.tstep];
+    cx<T> pre[PRE];
+    int slot = 0;
+    if (blockIdx.x < tiles) {
+        if (B != 1) {
+            set_lbase(blockIdx.x, 0);
+            lds_barrier();
+        }
+        prefetch(pre, blockIdx.x, 0);
+    }
+    for (uint32_t t = blockIdx.x; t < tiles; t += nblocks) {
+        const int lines = tile_lines(t);
+        const int n = lines * L;
+        // the next tile (the last one reloads itself: the prefetch takes no branch, so
+        // its loads are waited for only where the values are used)
+        const uint32_t tn = t + nblocks < tiles ? t + nblocks : t;
+        lds_barrier();   // twiddle copy done / previous tile's LDS reads done
+#pragma unroll
+        for (int i = 0; i < PRE; ++i) {
+            const int e = tid + i * nt;
+            if (e < n) {
+                int off;
+                where(t, lines, slot, e, off);
+                buf0[off] = conj_if(pre[i], pd.conj_in);
+            }
+        }
+        if (B != 1) set_lbase(tn, slot ^ 1);
+        lds_barrier();
+        prefetch(pre, tn, slot ^ 1);   // in flight through the stages below
         cx<T> *src = buf0, *dst = buf1;
         int Ns = 1;
         for (int s = 0; s < pd.nstages; ++s) {
@@ -206,25 +241,24 @@ __global__ __launch_bounds__(kMixedThreads) void k_mline(const cx<T> *in, cx<T> 
             case 8: mixed_stage<T, 8>(src, dst, tw, L, pitch, Ns, lines, tid, nt); break;
             default: break;
             }
-            __syncthreads();
+            lds_barrier();
             cx<T> *tmp = src;
             src = dst;
             dst = tmp;
             Ns *= pd.radix[s];
         }
-        for (int e0 = tid; e0 < n; e0 += kMixedBatch * nt) {
 #pragma unroll
-            for (int i = 0; i < kMixedBatch; ++i) {
-                const int e = e0 + i * nt;
-                if (e < n) {
-                    int off;
-                    const int64_t addr = where(e, off);
-                    cx<T> v = conj_if(src[off], pd.conj_out);
-                    if (pd.scale != 1.0) v = {v.x * scale, v.y * scale};
-                    put<false>(&out[addr], v);
-                }
+        for (int i = 0; i < PRE; ++i) {
+            const int e = tid + i * nt;
+            if (e < n) {
+                int off;
+                const uint32_t addr = where(t, lines, slot, e, off);
+                cx<T> v = conj_if(src[off], pd.conj_out);
+                if (pd.scale != 1.0) v = {v.x * scale, v.y * scale};
+                put<false>(&out[addr], v);
             }
         }
+        slot ^= 1;
     }
 }
 
@@ -738,10 +772,50 @@ uint32_t grid_for(int64_t count)
 
 }  // namespace
 
+namespace {
+
+// Persistent grid of k_mline: the workgroups that fit on the device at once (per
+// device and LDS size, cached), at most one per tile.
+uint32_t mline_blocks(Precision prec, const MixedPassDesc &pd)
+{
+    constexpr int kDevices = 64, kLdsSlots = 65;
+    static std::atomic<int> cus[kDevices];
+    static std::atomic<int> per_cu[2][kLdsSlots];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kDevices) return 0;
+    int c = cus[dev].load(std::memory_order_relaxed);
+    if (c == 0) {
+        if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || c < 1) return 0;
+        cus[dev].store(c, std::memory_order_relaxed);
+    }
+    const int slot = int((pd.lds_bytes + 1023) / 1024);
+    if (slot >= kLdsSlots) return 0;
+    std::atomic<int> &cached = per_cu[prec == Precision::F64 ? 1 : 0][slot];
+    int nb = cached.load(std::memory_order_relaxed);
+    if (nb == 0) {
+        const hipError_t e =
+            prec == Precision::F64
+                ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_mline<double>, kMixedThreads, uint32_t(slot) * 1024u)
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_mline<float>, kMixedThreads, uint32_t(slot) * 1024u);
+        if (e != hipSuccess || nb < 1) nb = 1;
+        cached.store(nb, std::memory_order_relaxed);
+    }
+    const int64_t want = int64_t(c) * nb;
+    return uint32_t(pd.tiles < want ? pd.tiles : want);
+}
+
+}  // namespace
+
 hipError_t launch_mline(Precision prec, const void *in, void *out, const MixedPassDesc &pd, const void *table,
                         hipStream_t stream)
 {
-    const uint32_t blocks = uint32_t(pd.tiles < (int64_t(1) << 20) ? pd.tiles : (int64_t(1) << 20));
+    // a tile must fit the registers of the prefetch, and the indices 32 bits
+    const int pre = prec == Precision::F64 ? kMixedPreF64 : kMixedPreF32;
+    if (pd.W < 1 || pd.W > kMixedMaxW || (1 << pd.logW) != pd.W || int64_t(pd.W) * pd.L > int64_t(pre) * kMixedThreads ||
+        pd.A * pd.B * pd.L >= (int64_t(1) << 31) || pd.tiles != (pd.A * pd.B + pd.W - 1) / pd.W)
+        return hipErrorInvalidValue;
+    const uint32_t blocks = mline_blocks(prec, pd);
+    if (blocks == 0) return hipErrorInvalidValue;
     if (prec == Precision::F64)
         hipLaunchKernelGGL(k_mline<double>, dim3(blocks), dim3(kMixedThreads), pd.lds_bytes, stream,
                            static_cast<const cx<double> *>(in), static_cast<cx<double> *>(out), pd,

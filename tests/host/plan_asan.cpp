@@ -142,7 +142,18 @@ hipError_t launch_batch_bind(BatchBind *, const BindChunk &c, hipStream_t)
 }
 hipError_t launch_fill_uniform(Precision, void *, int64_t, uint32_t, uint32_t, uint64_t, hipStream_t) { return hipSuccess; }
 hipError_t launch_pointwise(Precision, const void *, const void *, void *, int64_t, double, hipStream_t) { return hipSuccess; }
-hipError_t launch_mline(Precision, const void *, void *, const MixedPassDesc &, const void *, hipStream_t) { return hipSuccess; }
+hipError_t launch_mline(Precision prec, const void *, void *, const MixedPassDesc &pd, const void *, hipStream_t)
+{
+    // the tile fits the prefetch registers and its LDS; the tiles cover the lines
+    const int64_t pre = prec == Precision::F64 ? kMixedPreF64 : kMixedPreF32;
+    const int64_t esize = prec == Precision::F64 ? 16 : 8;
+    int64_t prod = 1;
+    for (int s = 0; s < pd.nstages; ++s) prod *= pd.radix[s];
+    if (pd.nstages < 1 || prod != pd.L || int64_t(pd.W) * pd.L > pre * kMixedThreads ||
+        (2 * pd.W * pd.pitch + pd.L) * esize != int64_t(pd.lds_bytes) || pd.tiles != (pd.A * pd.B + pd.W - 1) / pd.W)
+        std::abort();
+    return hipSuccess;
+}
 hipError_t launch_mtwiddle(Precision, const void *, void *, const MixedGridDesc &, const void *, hipStream_t) { return hipSuccess; }
 hipError_t launch_mpermute(Precision, const void *, void *, const MixedGridDesc &, const void *, hipStream_t) { return hipSuccess; }
 hipError_t launch_mexchange(Precision, const void *, void *, const MixedGridDesc &g, const void *, hipStream_t)
