@@ -598,7 +598,9 @@ __global__ __launch_bounds__(kExchangeThreads) void k_mxexchange(const cx<T> *__
 #pragma unroll
             for (int dd = 0; dd < NR; ++dd) e += uint32_t((j >> (LPR * (NR - 1 - dd))) & ((1 << LPR) - 1)) * cr[dd];
             v[j] = conj_if(v[j], g.conj_in);
-            if (g.twiddle) v[j] = cmul(v[j], table[reduce(e)]);
+            // no branch around the table load (table[0] = 1 exactly when there is no
+            // twiddle), so that the R loads issue back to back
+            v[j] = cmul(v[j], table[g.twiddle ? reduce(e) : 0u]);
         }
         dft_digits<T, NR, LPR, 1, 1>(v);
 
