@@ -165,20 +165,20 @@ __global__ __launch_bounds__(256) void k_gputt(const cx<T> *__restrict__ in, cx<
         for (int e = 0; e < EPT; ++e) {
             const int64_t si = sbase | soff[e];
             cx<T> v = conj_if(get(&in[si]), g.conj_in);
-            if (g.twiddle) {
-                uint32_t rank = uint32_t(si >> logM), loc = uint32_t(si) & (M - 1);
-                uint32_t ex = 0;
+            // no branch around the table load (entry 0 = 1 exactly without a twiddle), so
+            // that the loads of the EPT elements issue back to back
+            uint32_t rank = uint32_t(si >> logM), loc = uint32_t(si) & (M - 1);
+            uint32_t ex = 0;
 #pragma unroll
-                for (int l = kMaxDims - 1; l >= 0; --l) {
-                    if (l >= g.d) continue;
-                    const GroupPutDim &D = g.dim[l];
-                    const uint32_t sr = rank & uint32_t(D.p - 1), sk = loc & uint32_t(D.m - 1);
-                    rank >>= __builtin_ctz(uint32_t(D.p));
-                    loc >>= __builtin_ctz(uint32_t(D.m));
-                    if (D.mode != 0) ex += (sr & uint32_t(D.pi - 1)) * sk * uint32_t(D.tstep);
-                }
-                v = cmul(v, table[ex & tmask]);
+            for (int l = kMaxDims - 1; l >= 0; --l) {
+                if (l >= g.d) continue;
+                const GroupPutDim &D = g.dim[l];
+                const uint32_t sr = rank & uint32_t(D.p - 1), sk = loc & uint32_t(D.m - 1);
+                rank >>= __builtin_ctz(uint32_t(D.p));
+                loc >>= __builtin_ctz(uint32_t(D.m));
+                if (D.mode != 0) ex += (sr & uint32_t(D.pi - 1)) * sk * uint32_t(D.tstep);
             }
+            v = cmul(v, table[g.twiddle ? ex & tmask : 0u]);
             lds[slot[e]] = v;
         }
         __syncthreads();
