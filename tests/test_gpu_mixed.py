@@ -22,7 +22,9 @@ CASES = [((12,), (2,)), ((36,), (3,)), ((100,), (5,)), ((1000,), (10,)), ((7,), 
          ((48, 48, 48), (4, 4, 4)),          # P = 64 in k_mexchange, the 480^3 benchmark's grid
          ((192, 64), (8, 8)), ((75, 98), (5, 7)), ((36, 36, 36), (6, 3, 2)),   # p = 6: unfused
          # rows of the last dimension that are not whole 128-byte lines: blocks of 2 or 4 rows per workgroup
-         ((80, 200), (2, 2)), ((96, 48, 240), (4, 2, 4))]
+         ((80, 200), (2, 2)), ((96, 48, 240), (4, 2, 4)),
+         # d = 4 on a power-of-two grid; rows of 300 in several chunks (blocks of 2 rows in complex128)
+         ((12, 20, 6, 24), (2, 2, 1, 2)), ((10, 600), (1, 2))]
 
 
 @pytest.fixture(scope="module")
