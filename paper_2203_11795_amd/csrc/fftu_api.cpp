@@ -1958,9 +1958,10 @@ fftu_plan_t fftu_plan_real(int d, const int64_t n[], const int64_t p[], fftu_dty
     pl->real_out_elems = direction == FFTU_FORWARD ? Nh + Np : Nh;
     pl->grid.N = Nh;
     const std::string t = dtype == FFTU_C128 ? "double" : "float";
-    if (direction == FFTU_INVERSE) pl->launch_names.push_back("fftu::k_rmerge<" + t + ">");
+    const std::string dd = ", " + std::to_string(d) + ">";
+    if (direction == FFTU_INVERSE) pl->launch_names.push_back("fftu::k_rmerge<" + t + dd);
     for (const std::string &k : rc->launch_names) pl->launch_names.push_back(k);
-    if (direction == FFTU_FORWARD) pl->launch_names.push_back("fftu::k_rsplit<" + t + ">");
+    if (direction == FFTU_FORWARD) pl->launch_names.push_back("fftu::k_rsplit<" + t + dd);
     pl->launches = int(pl->launch_names.size());
     pl->table_bytes = uint64_t(n[d - 1]) * pl->esize;
     hipError_t e = upload_table_general(&pl->rtable, n[d - 1], dtype);

@@ -34,6 +34,8 @@ SHAPES = [
     ((60, 36), (2, 3)),                    # mixed radix: 60 x 18 over 2 x 3
     ((16, 32), (8, 4)),                    # packed 16 x 16 over 8 x 4: group-cyclic
     ((1, 4096), (1, 8)),
+    ((4, 6, 4, 2, 8), (1, 1, 2, 1, 2)),    # d = 5 (mixed radix)
+    ((2, 2, 2, 2, 2, 2, 4, 8), (1, 1, 1, 1, 1, 1, 2, 2)),   # d = 8, the most the library takes
 ]
 
 
