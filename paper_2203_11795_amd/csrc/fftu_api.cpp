@@ -2035,13 +2035,13 @@ fftu_plan_t fftu_plan_r2r(int d, const int64_t n[], const int64_t p[], fftu_dtyp
     const bool dst = kind == FFTU_DST;
     if (direction == FFTU_FORWARD) {
         // the complex transform of the packed signal, then the split and the coefficients in one pass
-        if (dst) pl->launch_names.push_back("fftu::k_r2rsign<" + t + ">");
+        if (dst) pl->launch_names.push_back("fftu::k_r2rsign<" + t + ", " + std::to_string(d) + ">");
         for (const std::string &k : rc->rc->launch_names) pl->launch_names.push_back(k);
         pl->launch_names.push_back("fftu::k_r2rpost<" + t + ", " + dd + ">");
     } else {
         pl->launch_names.push_back("fftu::k_r2rpre<" + t + ", " + dd + ">");
         for (const std::string &k : rc->launch_names) pl->launch_names.push_back(k);
-        if (dst) pl->launch_names.push_back("fftu::k_r2rsign<" + t + ">");
+        if (dst) pl->launch_names.push_back("fftu::k_r2rsign<" + t + ", " + std::to_string(d) + ">");
     }
     pl->launches = int(pl->launch_names.size());
     pl->table_T = T4;

@@ -25,6 +25,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "fftu_device.hpp"
 #include "fftu_internal.hpp"
@@ -33,16 +34,19 @@ namespace fftu {
 
 namespace {
 
-// Buffer position of natural index k of the packed array n' (dims = d), or of the
-// Nyquist plane's index (dims = d - 1, after the Nh packed elements).
-__device__ __forceinline__ int64_t spec_position(const RealDesc &rd, const int32_t *k, int dims)
+// Buffer position of natural index k of the packed array n' (DIMS = D = d), or of
+// the Nyquist plane's index (DIMS = D - 1, after the Nh packed elements). Compile-time
+// dimension counts: the loop unrolls and k stays in registers.
+template <int D, int DIMS>
+__device__ __forceinline__ int64_t spec_position(const RealDesc &rd, const int32_t (&k)[D])
 {
     uint32_t r = 0, i = 0;
-    for (int l = 0; l < dims; ++l) {
+#pragma unroll
+    for (int l = 0; l < DIMS; ++l) {
         r = r * uint32_t(rd.p[l]) + uint32_t(k[l]) % uint32_t(rd.p[l]);
         i = i * uint32_t(rd.m[l]) + uint32_t(k[l]) / uint32_t(rd.p[l]);
     }
-    return dims == rd.d ? int64_t(r) * rd.Mh + i : rd.Nh + int64_t(r) * rd.Mp + i;
+    return DIMS == D ? int64_t(r) * rd.Mh + i : rd.Nh + int64_t(r) * rd.Mp + i;
 }
 
 // Position of coefficient index k (cyclic over p).
@@ -120,7 +124,7 @@ __global__ __launch_bounds__(256) void k_r2rpost(const cx<T> *__restrict__ zf, T
             member<D>(g, k, mask, pk);
             const int32_t base = k[D - 1] == h ? 0 : k[D - 1];
             pk[D - 1] = ((mask >> (D - 1)) & 1) ? (base == 0 ? 0 : h - base) : base;
-            zv[mask] = zf[spec_position(g.rd, pk, D)];
+            zv[mask] = zf[spec_position<D, D>(g.rd, pk)];
         }
         cx<T> v[G];
 #pragma unroll
@@ -204,7 +208,7 @@ __global__ __launch_bounds__(256) void k_r2rpre(const T *__restrict__ y, cx<T> *
             if (repeated<D>(g, k, mask)) continue;
             int32_t kk[D];
             member<D>(g, k, mask, kk);
-            const int64_t pos = kk[D - 1] < g.rd.h ? spec_position(g.rd, kk, D) : spec_position(g.rd, kk, D - 1);
+            const int64_t pos = kk[D - 1] < g.rd.h ? spec_position<D, D>(g.rd, kk) : spec_position<D, D - 1>(g.rd, kk);
             spec[pos] = v[mask];
         }
     }
@@ -212,7 +216,7 @@ __global__ __launch_bounds__(256) void k_r2rpre(const T *__restrict__ y, cx<T> *
 
 // The signs of the DST's signal: v[m] negated once for each dimension with
 // m_l >= n_l / 2 (the odd samples of x), on the packed layout.
-template <typename T>
+template <typename T, int D>
 __global__ __launch_bounds__(256) void k_r2rsign(const cx<T> *in, cx<T> *out, const R2RDesc g)
 {
     const int64_t stride = int64_t(gridDim.x) * blockDim.x;
@@ -221,13 +225,14 @@ __global__ __launch_bounds__(256) void k_r2rsign(const cx<T> *in, cx<T> *out, co
         uint32_t r = uint32_t(pos / rd.Mh);
         uint32_t i = uint32_t(pos - int64_t(r) * rd.Mh);
         T s = T(1), s0 = T(1), s1 = T(1);
-        for (int l = rd.d - 1; l >= 0; --l) {
+#pragma unroll
+        for (int l = D - 1; l >= 0; --l) {
             const uint32_t sl = r % uint32_t(rd.p[l]);
             r /= uint32_t(rd.p[l]);
             const uint32_t il = i % uint32_t(rd.m[l]);
             i /= uint32_t(rd.m[l]);
             const int32_t j = int32_t(sl + il * uint32_t(rd.p[l]));   // packed natural index
-            if (l == rd.d - 1) {
+            if (l == D - 1) {
                 s0 = 2 * j < rd.h ? T(1) : T(-1);                     // signal index 2j against n_d / 2
                 s1 = 2 * j + 1 < rd.h ? T(1) : T(-1);
             } else if (2 * j >= g.n[l]) {
@@ -310,12 +315,22 @@ hipError_t launch_r2r_sign(Precision prec, const void *in, void *out, const R2RD
 {
     if (!r2r_ok(g)) return hipErrorInvalidValue;
     const uint32_t blocks = grid_of(g.rd.Nh);
-    if (prec == Precision::F64)
-        hipLaunchKernelGGL(k_r2rsign<double>, dim3(blocks), dim3(256), 0, stream,
-                           static_cast<const cx<double> *>(in), static_cast<cx<double> *>(out), g);
-    else
-        hipLaunchKernelGGL(k_r2rsign<float>, dim3(blocks), dim3(256), 0, stream, static_cast<const cx<float> *>(in),
-                           static_cast<cx<float> *>(out), g);
+    auto go = [&](auto dc) {
+        constexpr int D = decltype(dc)::value;
+        if (prec == Precision::F64)
+            hipLaunchKernelGGL((k_r2rsign<double, D>), dim3(blocks), dim3(256), 0, stream,
+                               static_cast<const cx<double> *>(in), static_cast<cx<double> *>(out), g);
+        else
+            hipLaunchKernelGGL((k_r2rsign<float, D>), dim3(blocks), dim3(256), 0, stream,
+                               static_cast<const cx<float> *>(in), static_cast<cx<float> *>(out), g);
+    };
+    switch (g.d) {   // r2r_ok: d <= kR2RMaxDims = 4
+    case 1: go(std::integral_constant<int, 1>{}); break;
+    case 2: go(std::integral_constant<int, 2>{}); break;
+    case 3: go(std::integral_constant<int, 3>{}); break;
+    case 4: go(std::integral_constant<int, 4>{}); break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
