@@ -273,10 +273,15 @@ __global__ __launch_bounds__(kPointwiseThreads) void k_ttranspose(const cx<T> *_
         const int h = (g.lognmax + 1) >> 1;
         fac[i] = cmul(table[e & ~((uint32_t(1) << h) - 1)], table[e & ((uint32_t(1) << h) - 1)]);
     }
+    // per-element product of the factors: the loop runs over every possible dimension
+    // (compile-time indices, so the per-dimension constants stay in scalar registers)
+    // and stops at g.d
     auto twiddle = [&](int dkk, int dss) {
         cx<T> w = {T(1), T(0)};
         int off = 0;
-        for (int l = 0; l < g.d; ++l) {
+#pragma unroll
+        for (int l = 0; l < kMaxDims; ++l) {
+            if (l >= g.d) break;
             const int bl = lowbits(l);
             const int a = (dkk >> g.logmstride[l]) & ((1 << bl) - 1);
             const int b = (dss >> g.logpstride[l]) & ((1 << bl) - 1);
