@@ -266,20 +266,22 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_mtwiddle(const cx<T> *in, cx<T> *out, const MixedGridDesc g,
                                                   const cx<T> *__restrict__ table)
 {
-    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
-    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < g.N; i += stride) {
-        uint32_t rank = uint32_t(i / g.M);
-        uint32_t k = uint32_t(i - int64_t(rank) * g.M);
-        int64_t e = 0;
+    // N < 2^31 and T < 2^24 on this path: 32-bit index arithmetic throughout
+    const uint32_t stride = gridDim.x * blockDim.x;
+    const uint32_t M = uint32_t(g.M), tn = uint32_t(g.T);
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < uint32_t(g.N); i += stride) {
+        uint32_t rank = i / M;
+        uint32_t k = i - rank * M;
+        uint32_t e = 0;
         for (int l = g.d - 1; l >= 0; --l) {
             const uint32_t sl = rank % uint32_t(g.p[l]);
             rank /= uint32_t(g.p[l]);
             const uint32_t kl = k % uint32_t(g.m[l]);
             k /= uint32_t(g.m[l]);
-            e += int64_t(kl) * sl * g.tstep[l];      // k_l s_l < n_l, times T / n_l: below T
+            e += (kl * sl) * uint32_t(g.tstep[l]);  // k_l s_l < n_l, times T / n_l: below T; d T < 2^27
         }
         cx<T> v = conj_if(get(&in[i]), g.conj_in);
-        v = cmul(v, table[e % g.T]);
+        v = cmul(v, table[e % tn]);
         put<false>(&out[i], conj_if(v, g.conj_out));
     }
 }
@@ -290,12 +292,14 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_mpermute(const cx<T> *in, cx<T> *out, const MixedGridDesc g,
                                                   const cx<T> *__restrict__ table)
 {
-    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    // N < 2^31 and T < 2^24 on this path: 32-bit index arithmetic throughout
+    const uint32_t stride = gridDim.x * blockDim.x;
+    const uint32_t M = uint32_t(g.M), tn = uint32_t(g.T);
     const T scale = static_cast<T>(g.scale);
-    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < g.N; i += stride) {
-        uint32_t r = uint32_t(i / g.M);
-        uint32_t j = uint32_t(i - int64_t(r) * g.M);
-        int64_t src_rank = 0, src_k = 0, rmul = 1, kmul = 1, e = 0;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < uint32_t(g.N); i += stride) {
+        uint32_t r = i / M;
+        uint32_t j = i - r * M;
+        uint32_t src_rank = 0, src_k = 0, rmul = 1, kmul = 1, e = 0;
         for (int l = g.d - 1; l >= 0; --l) {
             const uint32_t jl = j % uint32_t(g.m[l]);
             j /= uint32_t(g.m[l]);
@@ -303,15 +307,15 @@ __global__ __launch_bounds__(256) void k_mpermute(const cx<T> *in, cx<T> *out, c
             r /= uint32_t(g.p[l]);
             const uint32_t sl = jl / uint32_t(g.q[l]);          // j_l = s_l q_l + t_l
             const uint32_t tl = jl - sl * uint32_t(g.q[l]);
-            const int64_t kl = int64_t(rl) + int64_t(tl) * g.p[l];  // k_l = r_l + t_l p_l
-            src_rank += int64_t(sl) * rmul;
+            const uint32_t kl = rl + tl * uint32_t(g.p[l]);     // k_l = r_l + t_l p_l
+            src_rank += sl * rmul;
             src_k += kl * kmul;
-            e += kl * sl * g.tstep[l];
-            rmul *= g.p[l];
-            kmul *= g.m[l];
+            e += (kl * sl) * uint32_t(g.tstep[l]);              // below T each; d T < 2^27
+            rmul *= uint32_t(g.p[l]);
+            kmul *= uint32_t(g.m[l]);
         }
-        cx<T> v = conj_if(get(&in[src_rank * g.M + src_k]), g.conj_in);
-        if (g.twiddle) v = cmul(v, table[e % g.T]);
+        cx<T> v = conj_if(get(&in[src_rank * M + src_k]), g.conj_in);
+        if (g.twiddle) v = cmul(v, table[e % tn]);
         v = conj_if(v, g.conj_out);
         if (g.scale != 1.0) v = {v.x * scale, v.y * scale};
         put<false>(&out[i], v);
@@ -832,6 +836,8 @@ hipError_t launch_mline(Precision prec, const void *in, void *out, const MixedPa
 hipError_t launch_mtwiddle(Precision prec, const void *in, void *out, const MixedGridDesc &g, const void *table,
                            hipStream_t stream)
 {
+    if (g.N < 1 || g.N >= (int64_t(1) << 31) || g.T < 1 || g.T >= (int64_t(1) << 24) || g.d < 1 || g.d > kMaxDims)
+        return hipErrorInvalidValue;   // the kernel's 32-bit index arithmetic
     if (prec == Precision::F64)
         hipLaunchKernelGGL(k_mtwiddle<double>, dim3(grid_for(g.N)), dim3(256), 0, stream,
                            static_cast<const cx<double> *>(in), static_cast<cx<double> *>(out), g,
@@ -846,6 +852,8 @@ hipError_t launch_mtwiddle(Precision prec, const void *in, void *out, const Mixe
 hipError_t launch_mpermute(Precision prec, const void *in, void *out, const MixedGridDesc &g, const void *table,
                            hipStream_t stream)
 {
+    if (g.N < 1 || g.N >= (int64_t(1) << 31) || g.T < 1 || g.T >= (int64_t(1) << 24) || g.d < 1 || g.d > kMaxDims)
+        return hipErrorInvalidValue;   // the kernel's 32-bit index arithmetic
     if (prec == Precision::F64)
         hipLaunchKernelGGL(k_mpermute<double>, dim3(grid_for(g.N)), dim3(256), 0, stream,
                            static_cast<const cx<double> *>(in), static_cast<cx<double> *>(out), g,
