@@ -1614,7 +1614,8 @@ fftu_plan_s *build_mixed_plan(int d, const int64_t n[], const int64_t p[], fftu_
         auto sv = [](int v) { return std::to_string(v); };
         const fftu::MxSplit &x = mp.mxs;
         pl->launch_names.push_back("fftu::k_mxexchange<" + t + ", " + sv(x.nr) + ", " + sv(x.nr ? x.lpr : 0) + ", " +
-                                   sv(x.nh) + ", " + sv(x.nh ? x.lph : 0) + ">");
+                                   sv(x.nh) + ", " + sv(x.nh ? x.lph : 0) + ", " +
+                                   (fftu::mx_rows_staged(mp.g, x, pl->esize) ? "true>" : "false>"));
     } else if (mp.fused) {
         const bool tl = fftu::mexchange_table_in_lds(mp.g.P, mp.T, int(pl->esize));
         pl->launch_names.push_back("fftu::k_mexchange<" + t + (tl ? ", true>" : ", false>"));

@@ -329,6 +329,22 @@ struct MxRows {
     uint32_t nchunk, W, bit;
 };
 
+// k_mxexchange with whole rows staged in LDS (kMxRowsThreads threads take one row of the
+// last dimension and write each output row contiguously): where the output segments of
+// q_{d-1} elements are not whole 128-byte lines, the last dimension is a register
+// dimension of the split, there are wave dimensions (their LDS is reused) and a row
+// fits the workgroup (m_{d-1} <= kMxRowsThreads / 2^(NH LPH)).
+constexpr int kMxRowsThreads = 512;
+inline bool mx_rows_staged(const MixedGridDesc &g, const MxSplit &sp, size_t esize)
+{
+    if (sp.nh < 1 || sp.nr < 1 || sp.nr * sp.lpr > 4 || g.d < 1) return false;
+    const int last = g.d - 1;
+    if (sp.rdim[sp.nr - 1] != last || (1 << sp.lpr) != g.p[last]) return false;
+    const int H = 1 << (sp.nh * sp.lph);
+    if (int64_t(g.m[last]) > int64_t(kMxRowsThreads / H)) return false;
+    return (int64_t(g.q[last]) * int64_t(esize)) % 128 != 0;
+}
+
 // k_mexchange: P sources of 64 local indices in LDS, grid sides of one radix stage.
 constexpr int64_t kMexMaxP = 64;
 constexpr int kMexThreads = 512;

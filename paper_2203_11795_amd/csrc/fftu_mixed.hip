@@ -482,16 +482,18 @@ __global__ __launch_bounds__(kMexThreads) void k_mexchange(const cx<T> *__restri
 // quotient estimate), runs the register dimensions' DFTs with compile-time roots,
 // swaps through LDS so that each thread holds every wave index of some register
 // outputs, runs the wave dimensions' DFTs and scatters (runs of 64 / p_d elements).
-template <typename T, int NR, int LPR, int NH, int LPH>
-__global__ __launch_bounds__(kExchangeThreads) void k_mxexchange(const cx<T> *__restrict__ Z, cx<T> *__restrict__ V,
-                                                                const MixedGridDesc g, const MxSplit sp,
-                                                                const MxRows rw, const cx<T> *__restrict__ table)
+template <typename T, int NR, int LPR, int NH, int LPH, bool ROWS>
+__global__ __launch_bounds__(ROWS ? kMxRowsThreads : kExchangeThreads) void k_mxexchange(
+    const cx<T> *__restrict__ Z, cx<T> *__restrict__ V, const MixedGridDesc g, const MxSplit sp, const MxRows rw,
+    const cx<T> *__restrict__ table)
 {
     constexpr int LOGR = NR * LPR, LOGH = NH * LPH;
     constexpr int R = 1 << LOGR;
     constexpr int H = 1 << LOGH;
     constexpr int U = LOGH > 0 ? R / H : R;   // register slots per thread after the LDS swap
-    constexpr int KG = (kExchangeThreads / 64) / H;
+    constexpr int NT = ROWS ? kMxRowsThreads : kExchangeThreads;
+    constexpr int KG = (NT / 64) / H;
+    static_assert(!ROWS || (LOGH > 0 && NR > 0), "k_mxexchange: staged rows reuse the wave swap's LDS");
     extern __shared__ unsigned char smem_raw[];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -666,7 +668,40 @@ __global__ __launch_bounds__(kExchangeThreads) void k_mxexchange(const cx<T> *__
                     for (int u = 0; u < U; ++u) w[x * U + u] = lds[((x * R + hw * U + u) * KG + grp) * 64 + lane];
             }
             dft_digits<T, NH, LPH, U, U>(w);
-            if (valid) {
+            if constexpr (ROWS) {
+                // One round per wave digit x: every thread puts its U outputs of that x into
+                // LDS as whole rows (row = the destination block's r_d and the register digits
+                // other than the last dimension's, position u_{d-1} q_{d-1} + t), and the
+                // workgroup stores the rows linearly: each row, m_{d-1} elements of one
+                // destination block, is written contiguously.
+                constexpr int RPR = R >> LPR;                 // rows per value of r_d
+                const uint32_t plast = 1u << LPR, qlast = uint32_t(g.q[g.d - 1]);
+                const uint32_t rd = kx[g.d - 1] & (plast - 1), tt = kx[g.d - 1] >> LPR;
+                const uint32_t rank_hi = rank_r - rd, dst_hi = dst_t - tt;   // the row's block and offset
+                const uint32_t relems = uint32_t(R) * mlast;
+                const float inv_m = 1.0f / float(mlast);
+                cx<T> *stage = reinterpret_cast<cx<T> *>(smem_raw);
+#pragma unroll
+                for (int x = 0; x < H; ++x) {
+                    __syncthreads();   // the swap's (or the previous round's) LDS reads are done
+                    if (valid) {
+#pragma unroll
+                        for (int u = 0; u < U; ++u) {
+                            const int j = hw * U + u;
+                            const uint32_t row = rd * RPR + uint32_t(j >> LPR);
+                            stage[row * mlast + uint32_t(j & ((1 << LPR) - 1)) * qlast + tt] = w[x * U + u];
+                        }
+                    }
+                    __syncthreads();
+                    const uint32_t xoff = hoff(x);
+                    for (uint32_t e = uint32_t(tid); e < relems; e += NT) {
+                        const uint32_t row = uint32_t(div_small(int(e), int(mlast), inv_m));
+                        const uint32_t pos = e - row * mlast;
+                        const uint32_t r = row / RPR, jh = row % RPR;
+                        store((rank_hi + r) * M + dst_hi + xoff + roff(int(jh << LPR)) + pos, stage[e]);
+                    }
+                }
+            } else if (valid) {
 #pragma unroll
                 for (int i = 0; i < H * U; ++i) store(obase + hoff(i / U) + roff(hw * U + i % U), w[i]);
             }
@@ -702,12 +737,29 @@ template <typename T, int NR, int LPR, int NH, int LPH>
 hipError_t mx_launch_t(const void *in, void *out, const MixedGridDesc &g, const MxSplit &sp, const void *table,
                        hipStream_t stream)
 {
+    if constexpr (NH * LPH > 0 && NR > 0 && NR * LPR <= 4) {
+        if (mx_rows_staged(g, sp, sizeof(cx<T>))) {
+            // one row per work item; LDS: the wave swap of kMxRowsThreads threads (8-byte words),
+            // which also holds the R m_{d-1} staged outputs (m_{d-1} <= 512 / H)
+            MxRows rw{};
+            rw.nchunk = 1;
+            rw.bit = 1;
+            rw.W = uint32_t(g.M / g.m[g.d - 1]);
+            const uint32_t lds = uint32_t(kMxRowsThreads) * (1u << (NR * LPR)) * 8u;
+            if (uint64_t(1u << (NR * LPR)) * uint64_t(g.m[g.d - 1]) * sizeof(cx<T>) > lds) return hipErrorInvalidValue;
+            const uint32_t blocks = rw.W < (1u << 20) ? rw.W : (1u << 20);
+            hipLaunchKernelGGL((k_mxexchange<T, NR, LPR, NH, LPH, true>), dim3(blocks), dim3(kMxRowsThreads), lds, stream,
+                               static_cast<const cx<T> *>(in), static_cast<cx<T> *>(out), g, sp, rw,
+                               static_cast<const cx<T> *>(table));
+            return hipGetLastError();
+        }
+    }
     constexpr int KG = (kExchangeThreads / 64) >> (NH * LPH);
     const MxRows rw = mx_rows(g, KG * 64, sizeof(cx<T>));
     const int64_t want = (int64_t(rw.W) + rw.bit - 1) / rw.bit;
     const uint32_t blocks = uint32_t(want < (int64_t(1) << 20) ? want : (int64_t(1) << 20));
-    hipLaunchKernelGGL((k_mxexchange<T, NR, LPR, NH, LPH>), dim3(blocks), dim3(kExchangeThreads), sp.lds_bytes, stream,
-                       static_cast<const cx<T> *>(in), static_cast<cx<T> *>(out), g, sp, rw,
+    hipLaunchKernelGGL((k_mxexchange<T, NR, LPR, NH, LPH, false>), dim3(blocks), dim3(kExchangeThreads), sp.lds_bytes,
+                       stream, static_cast<const cx<T> *>(in), static_cast<cx<T> *>(out), g, sp, rw,
                        static_cast<const cx<T> *>(table));
     return hipGetLastError();
 }
