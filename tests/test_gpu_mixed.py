@@ -24,7 +24,14 @@ CASES = [((12,), (2,)), ((36,), (3,)), ((100,), (5,)), ((1000,), (10,)), ((7,), 
          # rows of the last dimension that are not whole 128-byte lines: blocks of 2 or 4 rows per workgroup
          ((80, 200), (2, 2)), ((96, 48, 240), (4, 2, 4)),
          # d = 4 on a power-of-two grid; rows of 300 in several chunks (blocks of 2 rows in complex128)
-         ((12, 20, 6, 24), (2, 2, 1, 2)), ((10, 600), (1, 2))]
+         ((12, 20, 6, 24), (2, 2, 1, 2)), ((10, 600), (1, 2)),
+         # whole output rows staged in LDS (segments of q_{d-1} elements not whole 128-byte lines):
+         # one wave dimension of 2 (complex128), two wave dimensions (complex128), rows of 108 of 128 slots
+         ((4, 4, 4, 4, 40), (2, 2, 2, 2, 2)), ((4, 4, 4, 4, 4, 24), (2, 2, 2, 2, 2, 2)), ((16, 16, 432), (4, 4, 4))]
+
+# (grid, dtype) pairs whose exchange takes the row-staged k_mxexchange
+STAGED = {((48, 48, 48), "complex64"), ((48, 48, 48), "complex128"), ((4, 4, 4, 4, 40), "complex128"),
+          ((4, 4, 4, 4, 4, 24), "complex128"), ((16, 16, 432), "complex64"), ((16, 16, 432), "complex128")}
 
 
 @pytest.fixture(scope="module")
@@ -60,6 +67,8 @@ def test_mixed_transform_matches_oracle(torch, n, p, dtype, direction):
                 assert names[-1] == f"fftu::k_mxexchange<{t}, 2, 2, 1, 2, true>", names
             if p == (3, 2):
                 assert names[-1].startswith(f"fftu::k_mexchange<{t}, "), names
+            if names[-1].startswith("fftu::k_mxexchange"):
+                assert names[-1].endswith(", true>" if (n, dtype) in STAGED else ", false>"), names
         else:
             assert f"fftu::k_mpermute<{t}>" in names
         assert "k_mline" in names[0] or info["s0_kernels"] == 0
@@ -115,6 +124,28 @@ def test_mixed_external_plan_and_convolution(torch, dtype):
         y = conv.convolve(dx, hhat)
         got = oracle.from_cyclic(y.cpu().numpy().astype(np.complex128), n, p)
         assert oracle.rel_l2(got, want) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", ["complex64", "complex128"])
+def test_mixed_staged_rows_convolution(torch, dtype):
+    """Convolution on a grid whose exchange stages whole output rows (16 x 16 x 48
+    over 4^3, q_{d-1} = 3): the product by the filter spectrum happens in the staged
+    store."""
+    import paper_2203_11795_amd as fftu
+    n, p = (16, 16, 48), (4, 4, 4)
+    N = 16 * 16 * 48
+    x = synth.uniform_complex(N, 12, NP[dtype])
+    h = synth.uniform_complex(N, 13, NP[dtype])
+    X = oracle.from_cyclic(x.astype(np.complex128), n, p)
+    H = oracle.from_cyclic(h.astype(np.complex128), n, p)
+    want = oracle.circular_convolution(X, H)
+    with fftu.ConvolutionPlan(n, p, dtype) as conv:
+        names = conv.launch_names()
+        assert names[-1].startswith("fftu::k_mxexchange") and names[-1].endswith(", true>"), names
+        hhat = conv(torch.from_numpy(h).cuda())
+        y = conv.convolve(torch.from_numpy(x).cuda(), hhat)
+        got = oracle.from_cyclic(y.cpu().numpy().astype(np.complex128), n, p)
+    assert oracle.rel_l2(got, want) <= TOL[dtype]
 
 
 @pytest.mark.parametrize("n,p,dtype", [((2880,), (3,), "complex128"),      # m = 960: longest mixed line, FP64
