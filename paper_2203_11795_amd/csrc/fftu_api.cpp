@@ -2038,7 +2038,8 @@ fftu_plan_t fftu_plan_r2r(int d, const int64_t n[], const int64_t p[], fftu_dtyp
         // the complex transform of the packed signal, then the split and the coefficients in one pass
         if (dst) pl->launch_names.push_back("fftu::k_r2rsign<" + t + ", " + std::to_string(d) + ">");
         for (const std::string &k : rc->rc->launch_names) pl->launch_names.push_back(k);
-        pl->launch_names.push_back("fftu::k_r2rpost<" + t + ", " + dd + ">");
+        const bool rows = fftu::r2rpost_rows_lds(g, dtype == FFTU_C128 ? sizeof(double) : sizeof(float)) > 0;
+        pl->launch_names.push_back((rows ? "fftu::k_r2rpost_rows<" : "fftu::k_r2rpost<") + t + ", " + dd + ">");
     } else {
         pl->launch_names.push_back("fftu::k_r2rpre<" + t + ", " + dd + ">");
         for (const std::string &k : rc->launch_names) pl->launch_names.push_back(k);

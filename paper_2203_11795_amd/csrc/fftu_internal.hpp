@@ -314,6 +314,20 @@ struct R2RDesc {
     RealDesc rd;            // the half spectrum of the signal (packed shape, Nyquist plane)
 };
 
+// k_r2rpost_rows (whole coefficient rows staged in LDS) where every wave's lanes start
+// on a multiple of 64 along the last dimension (n_d / 2 a multiple of 64), the
+// 2^(d-1) rows of a workgroup fit 32 KiB and there are enough rows to fill the device;
+// returns its LDS bytes, or 0 for the one-group-per-thread k_r2rpost.
+inline uint32_t r2rpost_rows_lds(const R2RDesc &g, size_t esize)
+{
+    if (g.d < 2 || g.d > kR2RMaxDims) return 0;
+    const int64_t nd = g.n[g.d - 1], h = nd / 2;
+    if (h % 64 != 0 || nd >= (int64_t(1) << 22)) return 0;
+    const int64_t bytes = (int64_t(1) << (g.d - 1)) * int64_t(g.p[g.d - 1]) * (int64_t(g.m[g.d - 1]) + 1) * int64_t(esize);
+    if (bytes > 32768 || g.groups / (h + 1) < 1024) return 0;
+    return uint32_t(bytes);
+}
+
 // k_mxexchange (fftu_mixed.hip): the mixed-radix exchange for grids whose sides are
 // powers of two (any local sides): the register and wave split of k_exchange (NR
 // register dimensions of 2^LPR, NH wave dimensions of 2^LPH) with general index

@@ -162,6 +162,128 @@ __global__ __launch_bounds__(256) void k_r2rpost(const cx<T> *__restrict__ zf, T
     }
 }
 
+// The forward pass with whole coefficient rows staged in LDS. A workgroup takes one
+// row of representatives (k_0..k_{D-2} fixed, k_{D-1} in [0, n_D / 2]): lane j takes
+// k_{D-1} = j < h, and the lane with j = 0 also finishes the group k_{D-1} = h, whose
+// packed inputs are the same (k_D mod h = 0 for both). The row's outputs are the
+// 2^(D-1) coefficient rows of its leading mirror images, every one complete over
+// k_{D-1} in [0, n_D); they go into LDS as [mirror][r_D][i_D] (one element of padding
+// per segment) and out as p_D contiguous runs of m_D coefficients each. The
+// arithmetic per group is that of k_r2rpost.
+template <typename T, int D>
+__global__ __launch_bounds__(256) void k_r2rpost_rows(const cx<T> *__restrict__ zf, T *__restrict__ y, const R2RDesc g,
+                                                      const cx<T> *__restrict__ table, const int64_t rows)
+{
+    static_assert(D >= 2, "k_r2rpost_rows: rows of the last dimension");
+    constexpr int G = 1 << D, GL = 1 << (D - 1);
+    extern __shared__ unsigned char smem_raw[];
+    T *stage = reinterpret_cast<T *>(smem_raw);
+    __shared__ int64_t rowbase[GL];
+    const int tid = threadIdx.x;
+    const int32_t h = g.rd.h, nd = g.n[D - 1], pd = g.p[D - 1], md = g.m[D - 1];
+    const int32_t seg = md + 1, rstride = pd * seg;
+    const int64_t wstep = 4 * int64_t(g.tstep[D - 1]);
+    const float inv_nd = 1.0f / float(nd), inv_md = 1.0f / float(md);
+    auto udiv = [](int32_t a, int32_t b, float inv) {   // a / b for a < 2^22, one float estimate, corrected
+        int32_t q = int32_t(float(a) * inv);
+        const int32_t r = a - q * b;
+        q += r >= b ? 1 : 0;
+        q -= r < 0 ? 1 : 0;
+        return q;
+    };
+    for (int64_t row = blockIdx.x; row < rows; row += gridDim.x) {
+        int32_t k[D];
+        {
+            int64_t t = row;
+#pragma unroll
+            for (int l = D - 2; l >= 0; --l) {
+                const int64_t span = g.n[l] / 2 + 1;
+                const int64_t q = t / span;
+                k[l] = int32_t(t - q * span);
+                t = q;
+            }
+            k[D - 1] = 0;
+        }
+        if (tid < GL) {
+            // output position of coefficient row `tid` at k_{D-1} = 0 (-1: a repeated image)
+            int32_t kk[D];
+            member<D>(g, k, tid, kk);
+            bool rep = false;
+#pragma unroll
+            for (int l = 0; l < D - 1; ++l) rep = rep || (((tid >> l) & 1) && (k[l] == 0 || 2 * k[l] == g.n[l]));
+            uint32_t r = 0, i = 0;
+#pragma unroll
+            for (int l = 0; l < D - 1; ++l) {
+                const int32_t kl = g.dst ? g.n[l] - 1 - kk[l] : kk[l];
+                r = r * uint32_t(g.p[l]) + uint32_t(kl) % uint32_t(g.p[l]);
+                i = i * uint32_t(g.m[l]) + uint32_t(kl) / uint32_t(g.p[l]);
+            }
+            rowbase[tid] = rep ? int64_t(-1) : int64_t(r) * pd * g.M + int64_t(i) * md;
+        }
+        for (int32_t j = tid; j < h; j += 256) {
+            k[D - 1] = j;
+            cx<T> zv[G];
+#pragma unroll
+            for (int mask = 0; mask < G; ++mask) {
+                int32_t pk[D];
+                member<D>(g, k, mask, pk);
+                pk[D - 1] = ((mask >> (D - 1)) & 1) ? (j == 0 ? 0 : h - j) : j;
+                zv[mask] = zf[spec_position<D, D>(g.rd, pk)];
+            }
+            // one pass for k_{D-1} = j; the lane with j = 0 makes a second for k_{D-1} = h
+            const int npass = j == 0 ? 2 : 1;
+#pragma unroll 1
+            for (int pass = 0; pass < npass; ++pass) {
+                const int32_t klast = pass ? h : j;
+                int32_t kr[D];
+#pragma unroll
+                for (int l = 0; l < D; ++l) kr[l] = k[l];
+                kr[D - 1] = klast;
+                cx<T> v[G];
+#pragma unroll
+                for (int mask = 0; mask < G; ++mask) {
+                    const cx<T> a = zv[mask], b = zv[(G - 1) ^ mask];
+                    const cx<T> E = {(a.x + b.x) * T(0.5), (a.y - b.y) * T(0.5)};
+                    const cx<T> O = {(a.y + b.y) * T(0.5), (b.x - a.x) * T(0.5)};
+                    const int32_t kd = ((mask >> (D - 1)) & 1) ? (klast == 0 ? 0 : nd - klast) : klast;
+                    v[mask] = E + cmul(table[int64_t(kd) * wstep], O);
+                }
+#pragma unroll
+                for (int l = 0; l < D; ++l) {
+                    const cx<T> w = table[int64_t(kr[l]) * g.tstep[l]];
+                    const cx<T> wc = {w.x, -w.y};
+#pragma unroll
+                    for (int mask = 0; mask < G; ++mask) {
+                        if ((mask >> l) & 1) continue;
+                        const int mb = mask | (1 << l);
+                        const cx<T> a = cmul(w, v[mask]), b = cmul(wc, v[mb]);
+                        v[mask] = a + b;
+                        v[mb] = times_i(a - b);
+                    }
+                }
+#pragma unroll
+                for (int mask = 0; mask < G; ++mask) {
+                    if (repeated<D>(g, kr, mask)) continue;
+                    int32_t kl = ((mask >> (D - 1)) & 1) ? (klast == 0 ? 0 : nd - klast) : klast;
+                    if (g.dst) kl = nd - 1 - kl;
+                    const int32_t rl = kl % pd, il = kl / pd;
+                    stage[(mask & (GL - 1)) * rstride + rl * seg + il] = v[mask].x;
+                }
+            }
+        }
+        __syncthreads();
+        for (int32_t e = tid; e < GL * nd; e += 256) {
+            const int32_t ml = udiv(e, nd, inv_nd);
+            const int32_t pos = e - ml * nd;
+            const int32_t rl = udiv(pos, md, inv_md);
+            const int32_t il = pos - rl * md;
+            const int64_t base = rowbase[ml];
+            if (base >= 0) y[base + int64_t(rl) * g.M + il] = stage[ml * rstride + rl * seg + il];
+        }
+        __syncthreads();
+    }
+}
+
 template <typename T, int D>
 __global__ __launch_bounds__(256) void k_r2rpre(const T *__restrict__ y, cx<T> *__restrict__ spec, const R2RDesc g,
                                                 const cx<T> *__restrict__ table)
@@ -267,6 +389,18 @@ hipError_t post_t(const void *spec, void *y, const R2RDesc &g, const void *table
 {
     const cx<T> *a = static_cast<const cx<T> *>(spec), *tab = static_cast<const cx<T> *>(table);
     T *b = static_cast<T *>(y);
+    const uint32_t lds = r2rpost_rows_lds(g, sizeof(T));
+    if (lds > 0) {
+        const int64_t rows = g.groups / (g.n[g.d - 1] / 2 + 1);
+        const uint32_t blocks = uint32_t(rows < (int64_t(1) << 20) ? rows : (int64_t(1) << 20));
+        switch (g.d) {
+        case 2: hipLaunchKernelGGL((k_r2rpost_rows<T, 2>), dim3(blocks), dim3(256), lds, stream, a, b, g, tab, rows); break;
+        case 3: hipLaunchKernelGGL((k_r2rpost_rows<T, 3>), dim3(blocks), dim3(256), lds, stream, a, b, g, tab, rows); break;
+        case 4: hipLaunchKernelGGL((k_r2rpost_rows<T, 4>), dim3(blocks), dim3(256), lds, stream, a, b, g, tab, rows); break;
+        default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     const uint32_t blocks = grid_of(g.groups);
     switch (g.d) {
     case 1: hipLaunchKernelGGL((k_r2rpost<T, 1>), dim3(blocks), dim3(256), 0, stream, a, b, g, tab); break;

@@ -33,7 +33,21 @@ SHAPES = [
     ((32, 64), (8, 4)),                    # packed 32 x 32 over 8 x 4: group-cyclic levels
     ((64, 64, 64), (2, 2, 2)),
     ((8, 16, 8, 32), (2, 2, 2, 2)),        # d = 4: groups of 16 mirror images
+    # whole coefficient rows staged in LDS (n_d / 2 a multiple of 64, at least 1024 rows)
+    ((2048, 128), (4, 2)), ((64, 64, 128), (2, 2, 2)), ((32, 16, 16, 128), (2, 2, 2, 2)),
+    ((96, 40, 128), (2, 2, 2)),            # mixed radix below, rows staged in the last pass
 ]
+
+
+def post_rows(n, p, dtype):
+    """Whether the forward pass takes k_r2rpost_rows: n_d / 2 a multiple of 64, the
+    2^(d-1) staged rows within 32 KiB, at least 1024 rows of representatives."""
+    d = len(n)
+    if d < 2 or (n[-1] // 2) % 64:
+        return False
+    es = 8 if dtype == "complex128" else 4
+    rows = int(np.prod([v // 2 + 1 for v in n[:-1]]))
+    return 2 ** (d - 1) * p[-1] * (n[-1] // p[-1] + 1) * es <= 32768 and rows >= 1024
 
 
 @pytest.mark.parametrize("n,p", SHAPES)
@@ -48,7 +62,8 @@ def test_forward_and_inverse_match_the_oracle(torch, n, p, kind, dtype):
     x = torch.from_numpy(sig).cuda()
     with fftu.R2RPlan(n, p, kind, dtype, FORWARD) as fwd, fftu.R2RPlan(n, p, kind, dtype, INVERSE) as inv:
         names = fwd.launch_names()
-        assert names[-1] == f"fftu::k_r2rpost<{'double' if dtype == 'complex128' else 'float'}, {len(n)}>", names
+        post = "k_r2rpost_rows" if post_rows(n, p, dtype) else "k_r2rpost"
+        assert names[-1] == f"fftu::{post}<{'double' if dtype == 'complex128' else 'float'}, {len(n)}>", names
         assert (names[0].startswith("fftu::k_r2rsign")) == (kind == "dst"), names
         y = fwd(x)
         z = x.clone()
