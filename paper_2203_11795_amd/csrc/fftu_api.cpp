@@ -2041,7 +2041,7 @@ fftu_plan_t fftu_plan_r2r(int d, const int64_t n[], const int64_t p[], fftu_dtyp
         const bool rows = fftu::r2rpost_rows_lds(g, dtype == FFTU_C128 ? sizeof(double) : sizeof(float)) > 0;
         pl->launch_names.push_back((rows ? "fftu::k_r2rpost_rows<" : "fftu::k_r2rpost<") + t + ", " + dd + ">");
     } else {
-        pl->launch_names.push_back("fftu::k_r2rpre<" + t + ", " + dd + ">");
+        pl->launch_names.push_back("fftu::k_r2rpre<" + t + ", " + dd + (fftu::r2rpre_rows(g) ? ", true>" : ", false>"));
         for (const std::string &k : rc->launch_names) pl->launch_names.push_back(k);
         if (dst) pl->launch_names.push_back("fftu::k_r2rsign<" + t + ", " + std::to_string(d) + ">");
     }

@@ -328,6 +328,15 @@ inline uint32_t r2rpost_rows_lds(const R2RDesc &g, size_t esize)
     return uint32_t(bytes);
 }
 
+// k_r2rpre with one workgroup per row of representatives (n_d / 2 a multiple of 64,
+// at least 1024 rows), or one group per thread.
+inline bool r2rpre_rows(const R2RDesc &g)
+{
+    if (g.d < 2 || g.d > kR2RMaxDims) return false;
+    const int64_t h = g.n[g.d - 1] / 2;
+    return h % 64 == 0 && g.groups / (h + 1) >= 1024;
+}
+
 // k_mxexchange (fftu_mixed.hip): the mixed-radix exchange for grids whose sides are
 // powers of two (any local sides): the register and wave split of k_exchange (NR
 // register dimensions of 2^LPR, NH wave dimensions of 2^LPH) with general index

@@ -284,15 +284,16 @@ __global__ __launch_bounds__(256) void k_r2rpost_rows(const cx<T> *__restrict__ 
     }
 }
 
-template <typename T, int D>
+// ROWS: one workgroup per row of representatives (k_0..k_{D-2} fixed), lane j taking
+// k_{D-1} = j and the lane with j = 0 also k_{D-1} = n_D / 2, so that every wave's
+// half-spectrum stores (the members with k_D < n_D / 2) start on a multiple of 64
+// along the last dimension; otherwise one group per thread over all groups.
+template <typename T, int D, bool ROWS>
 __global__ __launch_bounds__(256) void k_r2rpre(const T *__restrict__ y, cx<T> *__restrict__ spec, const R2RDesc g,
-                                                const cx<T> *__restrict__ table)
+                                                const cx<T> *__restrict__ table, const int64_t rows)
 {
     constexpr int G = 1 << D;
-    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
-    for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < g.groups; t += stride) {
-        int32_t k[D];
-        representative<D>(g, t, k);
+    auto group = [&](const int32_t (&k)[D]) {
         cx<T> v[G];
 #pragma unroll
         for (int mask = 0; mask < G; ++mask) {
@@ -332,6 +333,31 @@ __global__ __launch_bounds__(256) void k_r2rpre(const T *__restrict__ y, cx<T> *
             member<D>(g, k, mask, kk);
             const int64_t pos = kk[D - 1] < g.rd.h ? spec_position<D, D>(g.rd, kk) : spec_position<D, D - 1>(g.rd, kk);
             spec[pos] = v[mask];
+        }
+    };
+    if constexpr (ROWS) {
+        const int32_t h = g.rd.h;
+        for (int64_t row = blockIdx.x; row < rows; row += gridDim.x) {
+            int32_t k[D];
+            int64_t t = row;
+#pragma unroll
+            for (int l = D - 2; l >= 0; --l) {
+                const int64_t span = g.n[l] / 2 + 1;
+                const int64_t q = t / span;
+                k[l] = int32_t(t - q * span);
+                t = q;
+            }
+            for (int32_t j = threadIdx.x; j <= h; j += blockDim.x) {
+                k[D - 1] = j;
+                group(k);
+            }
+        }
+    } else {
+        const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+        for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < g.groups; t += stride) {
+            int32_t k[D];
+            representative<D>(g, t, k);
+            group(k);
         }
     }
 }
@@ -418,12 +444,23 @@ hipError_t pre_t(const void *y, void *spec, const R2RDesc &g, const void *table,
     const T *a = static_cast<const T *>(y);
     cx<T> *b = static_cast<cx<T> *>(spec);
     const cx<T> *tab = static_cast<const cx<T> *>(table);
+    if (r2rpre_rows(g)) {
+        const int64_t rows = g.groups / (g.n[g.d - 1] / 2 + 1);
+        const uint32_t blocks = uint32_t(rows < (int64_t(1) << 20) ? rows : (int64_t(1) << 20));
+        switch (g.d) {
+        case 2: hipLaunchKernelGGL((k_r2rpre<T, 2, true>), dim3(blocks), dim3(256), 0, stream, a, b, g, tab, rows); break;
+        case 3: hipLaunchKernelGGL((k_r2rpre<T, 3, true>), dim3(blocks), dim3(256), 0, stream, a, b, g, tab, rows); break;
+        case 4: hipLaunchKernelGGL((k_r2rpre<T, 4, true>), dim3(blocks), dim3(256), 0, stream, a, b, g, tab, rows); break;
+        default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     const uint32_t blocks = grid_of(g.groups);
     switch (g.d) {
-    case 1: hipLaunchKernelGGL((k_r2rpre<T, 1>), dim3(blocks), dim3(256), 0, stream, a, b, g, tab); break;
-    case 2: hipLaunchKernelGGL((k_r2rpre<T, 2>), dim3(blocks), dim3(256), 0, stream, a, b, g, tab); break;
-    case 3: hipLaunchKernelGGL((k_r2rpre<T, 3>), dim3(blocks), dim3(256), 0, stream, a, b, g, tab); break;
-    case 4: hipLaunchKernelGGL((k_r2rpre<T, 4>), dim3(blocks), dim3(256), 0, stream, a, b, g, tab); break;
+    case 1: hipLaunchKernelGGL((k_r2rpre<T, 1, false>), dim3(blocks), dim3(256), 0, stream, a, b, g, tab, int64_t(0)); break;
+    case 2: hipLaunchKernelGGL((k_r2rpre<T, 2, false>), dim3(blocks), dim3(256), 0, stream, a, b, g, tab, int64_t(0)); break;
+    case 3: hipLaunchKernelGGL((k_r2rpre<T, 3, false>), dim3(blocks), dim3(256), 0, stream, a, b, g, tab, int64_t(0)); break;
+    case 4: hipLaunchKernelGGL((k_r2rpre<T, 4, false>), dim3(blocks), dim3(256), 0, stream, a, b, g, tab, int64_t(0)); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -39,6 +39,12 @@ SHAPES = [
 ]
 
 
+def pre_rows(n):
+    """Whether the inverse's first pass takes k_r2rpre's row form: n_d / 2 a multiple
+    of 64, at least 1024 rows of representatives."""
+    return len(n) >= 2 and (n[-1] // 2) % 64 == 0 and int(np.prod([v // 2 + 1 for v in n[:-1]])) >= 1024
+
+
 def post_rows(n, p, dtype):
     """Whether the forward pass takes k_r2rpost_rows: n_d / 2 a multiple of 64, the
     2^(d-1) staged rows within 32 KiB, at least 1024 rows of representatives."""
@@ -65,6 +71,8 @@ def test_forward_and_inverse_match_the_oracle(torch, n, p, kind, dtype):
         post = "k_r2rpost_rows" if post_rows(n, p, dtype) else "k_r2rpost"
         assert names[-1] == f"fftu::{post}<{'double' if dtype == 'complex128' else 'float'}, {len(n)}>", names
         assert (names[0].startswith("fftu::k_r2rsign")) == (kind == "dst"), names
+        t = "double" if dtype == "complex128" else "float"
+        assert inv.launch_names()[0] == f"fftu::k_r2rpre<{t}, {len(n)}, {'true' if pre_rows(n) else 'false'}>"
         y = fwd(x)
         z = x.clone()
         fwd(z, z)                                        # in place
