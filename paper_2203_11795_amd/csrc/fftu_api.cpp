@@ -70,6 +70,7 @@ struct fftu_plan_s {
     // coefficient step and its omega_{T4} table (rtable), the spectrum in ws
     bool r2r = false;
     fftu_r2r_kind r2r_kind = FFTU_DCT;
+    bool r2r_sign_fused = false;   // DST forward: the signs in the complex transform's first pass
     fftu::R2RDesc r2d{};
     // grids beyond p_max (some p_l^2 not dividing n_l): group-cyclic levels, several supersteps
     bool gc = false;
@@ -1975,6 +1976,48 @@ fftu_plan_t fftu_plan_real(int d, const int64_t n[], const int64_t p[], fftu_dty
     return pl;
 }
 
+namespace {
+// The DST's signal signs (negated once per dimension with natural index m_l >= n_l / 2;
+// on the packed array, packed index >= n_d / 4 along the last dimension) depend only on
+// the local index when every local side m_l of the packed array is even: m_l >= n_l / 2
+// exactly when i_l >= m_l / 2, the top bit of i_l's field in the local index where the
+// sides are powers of two. They go into the complex transform's first pass (as the
+// parity of the local index bits under one mask) when that pass is a line pass;
+// returns whether they did.
+bool fuse_dst_signs(fftu_plan_s *rp, int d, const int64_t n[], const int64_t p[])
+{
+    fftu_plan_s *cp = rp ? rp->rc : nullptr;
+    if (!cp || cp->gc || cp->mixed || cp->is_batch || cp->launch_names.empty()) return false;
+    std::vector<PassDesc> *first = nullptr;
+    if (cp->lastx)
+        first = cp->s0x.empty() ? nullptr : &cp->s0x;
+    else
+        first = cp->ttrans_ld > 0 ? &cp->s0t : &cp->s0;
+    if (!first || first->empty()) return false;
+    PassDesc &pd = (*first)[0];
+    if (pd.kind != fftu::kLineStrided && pd.kind != fftu::kLineContig && pd.kind != fftu::kLineStaged) return false;
+    const std::string lname = "fftu::k_line<";
+    if (cp->launch_names[0].compare(0, lname.size(), lname) != 0) return false;
+    uint64_t mask = 0;
+    int off = 0;
+    int64_t M = 1;
+    for (int l = d - 1; l >= 0; --l) {
+        const int64_t nl = l == d - 1 ? n[l] / 2 : n[l];
+        if (nl % p[l]) return false;
+        const int64_t ml = nl / p[l];
+        if (ml < 2 || !is_pow2(ml)) return false;
+        const int lg = ilog2(ml);
+        mask |= uint64_t(1) << (off + lg - 1);
+        off += lg;
+        M *= ml;
+    }
+    if (M != cp->grid.M || off > 62) return false;
+    pd.sign_mask = mask;
+    cp->launch_names[0] = "fftu::k_line_sign<" + cp->launch_names[0].substr(lname.size());
+    return true;
+}
+}  // namespace
+
 fftu_plan_t fftu_plan_r2r(int d, const int64_t n[], const int64_t p[], fftu_dtype dtype, fftu_r2r_kind kind,
                           fftu_direction direction)
 {
@@ -2003,6 +2046,7 @@ fftu_plan_t fftu_plan_r2r(int d, const int64_t n[], const int64_t p[], fftu_dtyp
     pl->r2r = true;
     pl->r2r_kind = kind;
     pl->rc = rc;
+    if (kind == FFTU_DST && direction == FFTU_FORWARD) pl->r2r_sign_fused = fuse_dst_signs(rc, d, n, p);
     pl->d = d;
     int64_t T4 = 1, groups = 1, P = 1, N = 1;
     for (int l = 0; l < d; ++l) {
@@ -2036,7 +2080,7 @@ fftu_plan_t fftu_plan_r2r(int d, const int64_t n[], const int64_t p[], fftu_dtyp
     const bool dst = kind == FFTU_DST;
     if (direction == FFTU_FORWARD) {
         // the complex transform of the packed signal, then the split and the coefficients in one pass
-        if (dst) pl->launch_names.push_back("fftu::k_r2rsign<" + t + ", " + std::to_string(d) + ">");
+        if (dst && !pl->r2r_sign_fused) pl->launch_names.push_back("fftu::k_r2rsign<" + t + ", " + std::to_string(d) + ">");
         for (const std::string &k : rc->rc->launch_names) pl->launch_names.push_back(k);
         const bool rows = fftu::r2rpost_rows_lds(g, dtype == FFTU_C128 ? sizeof(double) : sizeof(float)) > 0;
         pl->launch_names.push_back((rows ? "fftu::k_r2rpost_rows<" : "fftu::k_r2rpost<") + t + ", " + dd + ">");
@@ -2942,8 +2986,9 @@ namespace {
 // Real-input transforms: forward = the complex transform of the packed array into
 // the output, then the split in place; inverse = the merge into the output, then
 // the inverse complex transform in place.
-// DCT / DST: forward = [signs] -> complex transform of the packed signal into the
-// workspace -> split and coefficients in one pass; inverse = spectrum from the
+// DCT / DST: forward = [signs, unless the complex transform's first pass applies
+// them] -> complex transform of the packed signal into the workspace -> split and
+// coefficients in one pass; inverse = spectrum from the
 // coefficients -> inverse real transform -> [signs] (in place on the output).
 fftu_status execute_r2r(fftu_plan_s *plan, const void *in, void *out, hipStream_t stream, Marker &mk)
 {
@@ -2952,7 +2997,7 @@ fftu_status execute_r2r(fftu_plan_s *plan, const void *in, void *out, hipStream_
     hipError_t e = hipSuccess;
     if (plan->dir == FFTU_FORWARD) {
         const void *sig = in;
-        if (dst) {
+        if (dst && !plan->r2r_sign_fused) {
             e = fftu::launch_r2r_sign(plan->prec, in, out, plan->r2d, stream);
             if (e != hipSuccess) return from_hip(e);
             mk.mark();

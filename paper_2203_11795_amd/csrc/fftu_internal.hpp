@@ -66,6 +66,9 @@ struct PassDesc {
     int32_t conj_out;      // conjugate on store
     double scale;          // multiply on store (1.0: none)
     uint32_t lds_bytes;    // dynamic LDS per workgroup
+    // k_line_sign: the element at buffer index i is negated on load when i & sign_mask
+    // has an odd number of bits (0: no signs; only that kernel reads it)
+    uint64_t sign_mask = 0;
 };
 
 // Geometry of the cyclic buffer: d dimensions, n = m * p, m = q * p.

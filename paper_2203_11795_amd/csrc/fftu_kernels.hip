@@ -369,6 +369,9 @@ uint32_t pointwise_blocks(int64_t n)
 hipError_t launch_pass(Precision prec, const void *in, void *out, const PassDesc &pd, const void *table,
                        hipStream_t stream)
 {
+    // the signed load exists in the line kernels only
+    if (pd.sign_mask != 0 && pd.kind != kLineStrided && pd.kind != kLineContig && pd.kind != kLineStaged)
+        return hipErrorInvalidValue;
     if (pd.kind == kGroup2) return launch_group2(prec, in, out, pd, table, stream);
     if (pd.kind == kPair) return launch_pair(prec, in, out, pd, stream);
     if (pd.kind == kLong) return launch_long(prec, in, out, pd, table, stream);

@@ -47,6 +47,25 @@ __global__ __launch_bounds__(kLineMaxThreads) void k_line(const cx<T> *in, cx<T>
     }
 }
 
+// k_line with the loaded elements negated by the parity of their index bits under
+// pd.sign_mask: the first pass of a transform whose input is a signed copy of the
+// buffer (the DST-II's signal), without a pass of its own for the signs.
+template <typename T, int LOGL, int MODE>
+__global__ __launch_bounds__(kLineMaxThreads) void k_line_sign(const cx<T> *in, cx<T> *out, const PassDesc pd,
+                                                               const cx<T> *__restrict__ table)
+{
+    using PL = LinePlan<LOGL>;
+    extern __shared__ unsigned char smem_raw[];
+    cx<T> *tw = reinterpret_cast<cx<T> *>(smem_raw);
+    cx<T> *lds = tw + PL::L;
+    const int64_t nblocks = __builtin_amdgcn_readfirstlane(int(gridDim.x));
+    line_twiddles<T, LOGL>(tw, table, pd.lognmax, threadIdx.x);
+    for (int64_t t = blockIdx.x; t < pd.tiles; t += nblocks) {
+        __syncthreads();
+        line_tile<T, LOGL, MODE, false, true>(in, out, pd, tw, lds, t, threadIdx.x);
+    }
+}
+
 namespace {
 constexpr int64_t kMaxLineBlocks = int64_t(1) << 21;
 
@@ -54,9 +73,14 @@ template <typename T, int LOGL, int MODE>
 hipError_t launch_line_t(const void *in, void *out, const PassDesc &pd, const void *table, hipStream_t stream)
 {
     const uint32_t blocks = uint32_t(pd.tiles < kMaxLineBlocks ? pd.tiles : kMaxLineBlocks);
-    hipLaunchKernelGGL((k_line<T, LOGL, MODE>), dim3(blocks), dim3(uint32_t(pd.threads)), pd.lds_bytes, stream,
-                       static_cast<const cx<T> *>(in), static_cast<cx<T> *>(out), pd,
-                       static_cast<const cx<T> *>(table));
+    if (pd.sign_mask != 0)
+        hipLaunchKernelGGL((k_line_sign<T, LOGL, MODE>), dim3(blocks), dim3(uint32_t(pd.threads)), pd.lds_bytes, stream,
+                           static_cast<const cx<T> *>(in), static_cast<cx<T> *>(out), pd,
+                           static_cast<const cx<T> *>(table));
+    else
+        hipLaunchKernelGGL((k_line<T, LOGL, MODE>), dim3(blocks), dim3(uint32_t(pd.threads)), pd.lds_bytes, stream,
+                           static_cast<const cx<T> *>(in), static_cast<cx<T> *>(out), pd,
+                           static_cast<const cx<T> *>(table));
     return hipGetLastError();
 }
 

@@ -91,8 +91,9 @@ __device__ __forceinline__ void line_stages(cx<T> (&v)[LinePlan<LOGL>::E], int j
 // One tile of a k_line pass: W lines (see the layouts above) with pd.threads
 // working threads; threads with tid >= pd.threads (a larger workgroup) only join
 // the barriers. tw holds omega_L^e, e in [L]; lds is the tile's LDS. CO: the
-// results are stored device-coherently (see put()).
-template <typename T, int LOGL, int MODE, bool CO = false>
+// results are stored device-coherently (see put()). SIGN: every loaded element is
+// negated where its buffer index has an odd number of bits under pd.sign_mask.
+template <typename T, int LOGL, int MODE, bool CO = false, bool SIGN = false>
 __device__ __forceinline__ void line_tile(const cx<T> *in, cx<T> *out, const PassDesc &pd, const cx<T> *tw,
                                           cx<T> *lds, int64_t t, int tid)
 {
@@ -109,6 +110,12 @@ __device__ __forceinline__ void line_tile(const cx<T> *in, cx<T> *out, const Pas
         w = tid >> PL::LOGTPL;
     }
     const T scale = static_cast<T>(pd.scale);
+    auto sign_of = [&](int64_t idx, cx<T> a) {
+        if constexpr (SIGN) {
+            if (__popcll(uint64_t(idx) & pd.sign_mask) & 1) a = {-a.x, -a.y};
+        }
+        return a;
+    };
     cx<T> v[PL::E];
     int64_t base;      // global offset of element 0 of this thread's line
     int64_t xstride;   // global distance between consecutive line elements
@@ -132,6 +139,10 @@ __device__ __forceinline__ void line_tile(const cx<T> *in, cx<T> *out, const Pas
             cx<T> r[PL::E];
 #pragma unroll
             for (int c = 0; c < PL::E; ++c) r[c] = get<CO>(&in[tbase + tid + c * pd.threads]);
+            if constexpr (SIGN) {
+#pragma unroll
+                for (int c = 0; c < PL::E; ++c) r[c] = sign_of(tbase + tid + c * pd.threads, r[c]);
+            }
 #pragma unroll
             for (int c = 0; c < PL::E; ++c) {
                 const int e = tid + c * pd.threads;
@@ -145,6 +156,10 @@ __device__ __forceinline__ void line_tile(const cx<T> *in, cx<T> *out, const Pas
     } else if (active) {
 #pragma unroll
         for (int m = 0; m < PL::E; ++m) v[m] = conj_if(get<CO>(&in[base + int64_t(j + m * PL::TPL) * xstride]), pd.conj_in);
+        if constexpr (SIGN) {
+#pragma unroll
+            for (int m = 0; m < PL::E; ++m) v[m] = sign_of(base + int64_t(j + m * PL::TPL) * xstride, v[m]);
+        }
     }
 
     line_stages<T, LOGL, MODE>(v, j, w, pitch, static_cast<void *>(lds), tw, active);
