@@ -1984,6 +1984,42 @@ namespace {
 // sides are powers of two. They go into the complex transform's first pass (as the
 // parity of the local index bits under one mask) when that pass is a line pass;
 // returns whether they did.
+uint64_t dst_sign_mask(const fftu_plan_s *cp, int d, const int64_t n[], const int64_t p[])
+{
+    uint64_t mask = 0;
+    int off = 0;
+    int64_t M = 1;
+    for (int l = d - 1; l >= 0; --l) {
+        const int64_t nl = l == d - 1 ? n[l] / 2 : n[l];
+        if (nl % p[l]) return 0;
+        const int64_t ml = nl / p[l];
+        if (ml < 2 || !is_pow2(ml)) return 0;
+        const int lg = ilog2(ml);
+        mask |= uint64_t(1) << (off + lg - 1);
+        off += lg;
+        M *= ml;
+    }
+    return (M == cp->grid.M && off <= 62) ? mask : 0;
+}
+
+// Inverse: the signs go into the complex transform's last kernel when that is the
+// fused exchange (k_exchange_sign negates its outputs by the same parity).
+bool fuse_dst_signs_inverse(fftu_plan_s *rp, int d, const int64_t n[], const int64_t p[])
+{
+    fftu_plan_s *cp = rp ? rp->rc : nullptr;
+    if (!cp || cp->gc || cp->mixed || cp->is_batch || cp->lastx || cp->ttrans || !cp->fused) return false;
+    const std::string xname = "fftu::k_exchange<";
+    if (cp->launch_names.empty() || cp->launch_names.back().compare(0, xname.size(), xname) != 0) return false;
+    if (rp->launch_names.empty() || rp->launch_names.back() != cp->launch_names.back()) return false;
+    const uint64_t mask = dst_sign_mask(cp, d, n, p);
+    if (!mask) return false;
+    cp->ex.sign_mask = mask;
+    const std::string renamed = "fftu::k_exchange_sign<" + cp->launch_names.back().substr(xname.size());
+    cp->launch_names.back() = renamed;
+    rp->launch_names.back() = renamed;
+    return true;
+}
+
 bool fuse_dst_signs(fftu_plan_s *rp, int d, const int64_t n[], const int64_t p[])
 {
     fftu_plan_s *cp = rp ? rp->rc : nullptr;
@@ -1998,20 +2034,8 @@ bool fuse_dst_signs(fftu_plan_s *rp, int d, const int64_t n[], const int64_t p[]
     if (pd.kind != fftu::kLineStrided && pd.kind != fftu::kLineContig && pd.kind != fftu::kLineStaged) return false;
     const std::string lname = "fftu::k_line<";
     if (cp->launch_names[0].compare(0, lname.size(), lname) != 0) return false;
-    uint64_t mask = 0;
-    int off = 0;
-    int64_t M = 1;
-    for (int l = d - 1; l >= 0; --l) {
-        const int64_t nl = l == d - 1 ? n[l] / 2 : n[l];
-        if (nl % p[l]) return false;
-        const int64_t ml = nl / p[l];
-        if (ml < 2 || !is_pow2(ml)) return false;
-        const int lg = ilog2(ml);
-        mask |= uint64_t(1) << (off + lg - 1);
-        off += lg;
-        M *= ml;
-    }
-    if (M != cp->grid.M || off > 62) return false;
+    const uint64_t mask = dst_sign_mask(cp, d, n, p);
+    if (!mask) return false;
     pd.sign_mask = mask;
     cp->launch_names[0] = "fftu::k_line_sign<" + cp->launch_names[0].substr(lname.size());
     return true;
@@ -2046,7 +2070,8 @@ fftu_plan_t fftu_plan_r2r(int d, const int64_t n[], const int64_t p[], fftu_dtyp
     pl->r2r = true;
     pl->r2r_kind = kind;
     pl->rc = rc;
-    if (kind == FFTU_DST && direction == FFTU_FORWARD) pl->r2r_sign_fused = fuse_dst_signs(rc, d, n, p);
+    if (kind == FFTU_DST)
+        pl->r2r_sign_fused = direction == FFTU_FORWARD ? fuse_dst_signs(rc, d, n, p) : fuse_dst_signs_inverse(rc, d, n, p);
     pl->d = d;
     int64_t T4 = 1, groups = 1, P = 1, N = 1;
     for (int l = 0; l < d; ++l) {
@@ -2087,7 +2112,7 @@ fftu_plan_t fftu_plan_r2r(int d, const int64_t n[], const int64_t p[], fftu_dtyp
     } else {
         pl->launch_names.push_back("fftu::k_r2rpre<" + t + ", " + dd + (fftu::r2rpre_rows(g) ? ", true>" : ", false>"));
         for (const std::string &k : rc->launch_names) pl->launch_names.push_back(k);
-        if (dst) pl->launch_names.push_back("fftu::k_r2rsign<" + t + ", " + std::to_string(d) + ">");
+        if (dst && !pl->r2r_sign_fused) pl->launch_names.push_back("fftu::k_r2rsign<" + t + ", " + std::to_string(d) + ">");
     }
     pl->launches = int(pl->launch_names.size());
     pl->table_T = T4;
@@ -2988,8 +3013,9 @@ namespace {
 // the inverse complex transform in place.
 // DCT / DST: forward = [signs, unless the complex transform's first pass applies
 // them] -> complex transform of the packed signal into the workspace -> split and
-// coefficients in one pass; inverse = spectrum from the
-// coefficients -> inverse real transform -> [signs] (in place on the output).
+// coefficients in one pass; inverse = spectrum from the coefficients -> inverse
+// real transform -> [signs, unless its last kernel applies them] (in place on the
+// output).
 fftu_status execute_r2r(fftu_plan_s *plan, const void *in, void *out, hipStream_t stream, Marker &mk)
 {
     fftu_plan_s *rp = plan->rc;
@@ -3013,7 +3039,7 @@ fftu_status execute_r2r(fftu_plan_s *plan, const void *in, void *out, hipStream_
     if (e != hipSuccess) return from_hip(e);
     mk.mark();
     fftu_status s = execute_real(rp, plan->ws, out, stream, mk);
-    if (s != FFTU_SUCCESS || !dst) return s;
+    if (s != FFTU_SUCCESS || !dst || plan->r2r_sign_fused) return s;
     e = fftu::launch_r2r_sign(plan->prec, out, out, plan->r2d, stream);
     if (e == hipSuccess) mk.mark();
     return from_hip(e);

@@ -38,6 +38,22 @@ __global__ __launch_bounds__(kExchangeThreads) void k_exchange(const cx<T> *__re
         exchange_group<T, NR, LPR, NH, LPH>(Z, V, ex, table, smem_raw, gb, threadIdx.x);
 }
 
+// k_exchange with every output negated by the parity of its buffer index under
+// ex.sign_mask (no pointwise product): the last kernel of a transform whose result
+// is wanted with signs (the inverse DST-II's signal).
+template <typename T, int NR, int LPR, int NH, int LPH>
+__global__ __launch_bounds__(kExchangeThreads) void k_exchange_sign(const cx<T> *__restrict__ Z,
+                                                                    cx<T> *__restrict__ V, const ExchangeDesc ex,
+                                                                    const cx<T> *__restrict__ table)
+{
+    constexpr int KG = (kExchangeThreads / 64) >> (NH * LPH);
+    extern __shared__ unsigned char smem_raw[];
+    const int64_t ngroups = (ex.g.M + 63) >> 6;
+    const int64_t nblocks = __builtin_amdgcn_readfirstlane(int(gridDim.x));   // uniform loop (barriers inside)
+    for (int64_t gb = int64_t(blockIdx.x) * KG; gb < ngroups; gb += nblocks * KG)
+        exchange_group<T, NR, LPR, NH, LPH, false, 3>(Z, V, ex, table, smem_raw, gb, threadIdx.x);
+}
+
 namespace {
 constexpr int64_t kMaxExchangeBlocks = int64_t(1) << 20;
 
@@ -48,6 +64,13 @@ hipError_t launch_t(const void *in, void *out, const ExchangeDesc &ex, const voi
     const int64_t ngroups = (ex.g.M + 63) >> 6;
     const int64_t want = (ngroups + KG - 1) / KG;
     const uint32_t blocks = uint32_t(want < kMaxExchangeBlocks ? want : kMaxExchangeBlocks);
+    if (ex.sign_mask != 0) {
+        if (ex.mul) return hipErrorInvalidValue;   // signs and a product are not combined
+        hipLaunchKernelGGL((k_exchange_sign<T, NR, LPR, NH, LPH>), dim3(blocks), dim3(kExchangeThreads), ex.lds_bytes,
+                           stream, static_cast<const cx<T> *>(in), static_cast<cx<T> *>(out), ex,
+                           static_cast<const cx<T> *>(table));
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL((k_exchange<T, NR, LPR, NH, LPH>), dim3(blocks), dim3(kExchangeThreads), ex.lds_bytes,
                        stream, static_cast<const cx<T> *>(in), static_cast<cx<T> *>(out), ex,
                        static_cast<const cx<T> *>(table));

@@ -66,7 +66,8 @@ __device__ __forceinline__ int64_t digit_offset(const int32_t *dims, const Excha
 // stored at V[idx(i)]. MULM 0: the product when ex.mul is set, element by
 // element; 1: never; 2: always, with every multiplier loaded before the first
 // store (loads and stores share one wait counter, so a load issued after a
-// store waits for it).
+// store waits for it); 3: no product, the output negated where idx(i) has an odd
+// number of bits under ex.sign_mask.
 template <typename T, bool CO, int MULM, int NOUT, typename IDX>
 __device__ __forceinline__ void exchange_store(cx<T> *__restrict__ V, const ExchangeDesc &ex, cx<T> (&o)[NOUT],
                                                IDX idx, bool valid)
@@ -86,6 +87,9 @@ __device__ __forceinline__ void exchange_store(cx<T> *__restrict__ V, const Exch
         if (valid) {
             if constexpr (MULM == 2) w = cmul(w, mv[i]);
             if (MULM == 0 && mul) w = cmul(w, mul[idx(i)]);
+            if constexpr (MULM == 3) {
+                if (__popcll(uint64_t(idx(i)) & ex.sign_mask) & 1) w = {-w.x, -w.y};
+            }
             put<CO>(&V[idx(i)], w);
         }
     }
@@ -208,7 +212,7 @@ __device__ __forceinline__ void exchange_core(cx<T> *__restrict__ V, const Excha
 }
 
 // exchange_core over kExchangeThreads threads, gathering from the S0 output Z.
-template <typename T, int NR, int LPR, int NH, int LPH, bool CO = false>
+template <typename T, int NR, int LPR, int NH, int LPH, bool CO = false, int MULM = 0>
 __device__ __forceinline__ void exchange_group(const cx<T> *__restrict__ Z, cx<T> *__restrict__ V,
                                                const ExchangeDesc &ex, const cx<T> *__restrict__ table,
                                                unsigned char *smem_raw, int64_t gb, int tid)
@@ -216,7 +220,7 @@ __device__ __forceinline__ void exchange_group(const cx<T> *__restrict__ Z, cx<T
     const int logM = ex.g.logmstride[0] + ex.g.logm[0];
     constexpr int H = 1 << (NH * LPH);
     const int64_t k = ((gb + ((tid >> 6) / H)) << 6) + (tid & 63);   // group grp = wave / H, one index per lane
-    exchange_core<T, NR, LPR, NH, LPH, kExchangeThreads, CO, 0>(
+    exchange_core<T, NR, LPR, NH, LPH, kExchangeThreads, CO, MULM>(
         V, ex, table, smem_raw, k, tid, [&](int j, int hw, int64_t k, bool valid) {
             const int64_t s = (int64_t(hw) << (NR * LPR)) + j;
             return valid ? get<CO>(&Z[(s << logM) + k]) : cx<T>{T(0), T(0)};

@@ -100,6 +100,9 @@ struct ExchangeDesc {
     int32_t oshift[kMaxDims];
     uint32_t lds_bytes;
     const void *mul;       // null, or N elements in the output layout that every output is multiplied by
+    // k_exchange_sign: the output at buffer index i is negated when i & sign_mask has an
+    // odd number of bits (0: no signs; only that kernel reads it)
+    uint64_t sign_mask = 0;
 };
 
 // k_pair (fftu_pair.hip): lines of 2^3..2^5 points along two adjacent dimensions,

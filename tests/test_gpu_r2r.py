@@ -75,7 +75,13 @@ def test_forward_and_inverse_match_the_oracle(torch, n, p, kind, dtype):
         assert (names[0].startswith("fftu::k_r2rsign") or fused) == (kind == "dst"), names
         assert not (fused and names[0].startswith("fftu::k_r2rsign")), names
         t = "double" if dtype == "complex128" else "float"
-        assert inv.launch_names()[0] == f"fftu::k_r2rpre<{t}, {len(n)}, {'true' if pre_rows(n) else 'false'}>"
+        inames = inv.launch_names()
+        assert inames[0] == f"fftu::k_r2rpre<{t}, {len(n)}, {'true' if pre_rows(n) else 'false'}>"
+        # the inverse DST's signs: a pass of their own, or in the last exchange's stores
+        ifused = any(k.startswith("fftu::k_exchange_sign<") for k in inames)
+        assert (inames[-1].startswith("fftu::k_r2rsign") or ifused) == (kind == "dst"), inames
+        assert not (ifused and inames[-1].startswith("fftu::k_r2rsign")), inames
+        assert inv.info()["launches"] == len(inames)
         y = fwd(x)
         z = x.clone()
         fwd(z, z)                                        # in place
@@ -163,8 +169,9 @@ def test_dct_512cube_full_size(torch):
 
 def test_dst_512cube_signs_in_first_pass(torch):
     """512^3 FP64 DST-II over 4^3 at full size, whose signal signs are applied by the
-    complex transform's first line pass: 2000 sampled coefficients of a sparse signal
-    against the definition summed over its nonzeros, and the round trip."""
+    complex transform's first line pass (forward) and last exchange (inverse): 2000
+    sampled coefficients of a sparse signal against the definition summed over its
+    nonzeros, and the round trip."""
     import paper_2203_11795_amd as fftu
     n, p = (512, 512, 512), (4, 4, 4)
     N = 512 ** 3
@@ -180,6 +187,8 @@ def test_dst_512cube_signs_in_first_pass(torch):
             fftu.R2RPlan(n, p, "dst", "complex128", INVERSE) as inv:
         names = fwd.launch_names()
         assert names[0].startswith("fftu::k_line_sign<double, ") and not any("r2rsign" in k for k in names), names
+        inames = inv.launch_names()
+        assert inames[-1].startswith("fftu::k_exchange_sign<double, ") and not any("r2rsign" in k for k in inames), inames
         y = fwd(x)
         torch.cuda.synchronize()
         ks = rng.integers(0, 512, size=(2000, 3))
