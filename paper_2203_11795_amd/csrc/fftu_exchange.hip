@@ -26,6 +26,8 @@
 
 namespace fftu {
 
+// Without a pointwise product (ex.mul null): the product's code would hold 32 more
+// VGPRs (158 against 126 for complex128 <2, 2, 1, 2>), one wave per SIMD less.
 template <typename T, int NR, int LPR, int NH, int LPH>
 __global__ __launch_bounds__(kExchangeThreads) void k_exchange(const cx<T> *__restrict__ Z, cx<T> *__restrict__ V,
                                                                const ExchangeDesc ex, const cx<T> *__restrict__ table)
@@ -35,7 +37,21 @@ __global__ __launch_bounds__(kExchangeThreads) void k_exchange(const cx<T> *__re
     const int64_t ngroups = (ex.g.M + 63) >> 6;
     const int64_t nblocks = __builtin_amdgcn_readfirstlane(int(gridDim.x));   // uniform loop (barriers inside)
     for (int64_t gb = int64_t(blockIdx.x) * KG; gb < ngroups; gb += nblocks * KG)
-        exchange_group<T, NR, LPR, NH, LPH>(Z, V, ex, table, smem_raw, gb, threadIdx.x);
+        exchange_group<T, NR, LPR, NH, LPH, false, 1>(Z, V, ex, table, smem_raw, gb, threadIdx.x);
+}
+
+// With the pointwise product by ex.mul (a convolution's filter spectrum).
+template <typename T, int NR, int LPR, int NH, int LPH>
+__global__ __launch_bounds__(kExchangeThreads) void k_exchange_mul(const cx<T> *__restrict__ Z,
+                                                                   cx<T> *__restrict__ V, const ExchangeDesc ex,
+                                                                   const cx<T> *__restrict__ table)
+{
+    constexpr int KG = (kExchangeThreads / 64) >> (NH * LPH);
+    extern __shared__ unsigned char smem_raw[];
+    const int64_t ngroups = (ex.g.M + 63) >> 6;
+    const int64_t nblocks = __builtin_amdgcn_readfirstlane(int(gridDim.x));   // uniform loop (barriers inside)
+    for (int64_t gb = int64_t(blockIdx.x) * KG; gb < ngroups; gb += nblocks * KG)
+        exchange_group<T, NR, LPR, NH, LPH, false, 0>(Z, V, ex, table, smem_raw, gb, threadIdx.x);
 }
 
 // k_exchange with every output negated by the parity of its buffer index under
@@ -71,9 +87,14 @@ hipError_t launch_t(const void *in, void *out, const ExchangeDesc &ex, const voi
                            static_cast<const cx<T> *>(table));
         return hipGetLastError();
     }
-    hipLaunchKernelGGL((k_exchange<T, NR, LPR, NH, LPH>), dim3(blocks), dim3(kExchangeThreads), ex.lds_bytes,
-                       stream, static_cast<const cx<T> *>(in), static_cast<cx<T> *>(out), ex,
-                       static_cast<const cx<T> *>(table));
+    if (ex.mul)
+        hipLaunchKernelGGL((k_exchange_mul<T, NR, LPR, NH, LPH>), dim3(blocks), dim3(kExchangeThreads), ex.lds_bytes,
+                           stream, static_cast<const cx<T> *>(in), static_cast<cx<T> *>(out), ex,
+                           static_cast<const cx<T> *>(table));
+    else
+        hipLaunchKernelGGL((k_exchange<T, NR, LPR, NH, LPH>), dim3(blocks), dim3(kExchangeThreads), ex.lds_bytes,
+                           stream, static_cast<const cx<T> *>(in), static_cast<cx<T> *>(out), ex,
+                           static_cast<const cx<T> *>(table));
     return hipGetLastError();
 }
 
