@@ -723,20 +723,31 @@ bool plan_lastx(const Geometry &G, const GridDesc &g, fftu_dtype dt, std::vector
     const int li = G.d - 1;
     const int logl = G.logm[li];
     if (logl < fftu::kLastxMinLogL || logl > fftu::kLastxMaxLogL) return false;
-    const int loge = fftu::line_loge(logl);
-    // 512 threads per workgroup, or 1024 where 512 cannot hold a row of every block
+    // 512 threads per workgroup, or 1024 where 512 cannot hold a row of every block; the
+    // line held as k_line holds it, or (lines of 64) as 16 elements per thread for a
+    // split of 16 register sources
     ExchangeSplit sp;
-    int lognt = fftu::kLastxLogThreads;
-    if (!exchange_split(G, dt, &sp, loge, logl, lognt)) {
+    int lognt = fftu::kLastxLogThreads, loge = -1;
+    std::vector<int> cands = {fftu::line_loge(logl)};
+    if (fftu::lastx_loge(logl, 4) != cands[0]) cands.push_back(fftu::lastx_loge(logl, 4));
+    for (const int cand : cands) {
+        lognt = fftu::kLastxLogThreads;
+        if (exchange_split(G, dt, &sp, cand, logl, lognt)) {
+            loge = cand;
+            break;
+        }
         lognt = fftu::kLastxMaxLogThreads;
-        if (!exchange_split(G, dt, &sp, loge, logl, lognt) ||
-            !fftu::lastx_split_needs_1024(logl, sp.nr, sp.lpr, sp.nh, sp.lph))
-            return false;
+        if (exchange_split(G, dt, &sp, cand, logl, lognt) &&
+            fftu::lastx_split_needs_1024(logl, sp.nr, sp.lpr, sp.nh, sp.lph)) {
+            loge = cand;
+            break;
+        }
     }
+    if (loge < 0) return false;
     const int logrw = lognt - (logl - loge) - G.logP;
     if (G.logM - logl < logrw) return false;
     const int esize = dt == FFTU_C128 ? 16 : 8;
-    const uint32_t lds = fftu::lastx_lds_bytes(logl, esize, lognt);
+    const uint32_t lds = fftu::lastx_lds_bytes(logl, loge, esize, lognt);
     if (lds > 160u * 1024u) return false;
     if ((int64_t(1) << (G.logM - logrw - logl)) > fftu::lastx_max_tiles(lognt)) return false;
     // the other dimensions outermost first (measured about 1% faster at 512^3 than
@@ -774,7 +785,7 @@ bool plan_lastx(const Geometry &G, const GridDesc &g, fftu_dtype dt, std::vector
     lx.logl = logl;
     lx.lognt = lognt;
     lx.tiles = int64_t(1) << (G.logM - logrw - logl);
-    lx.table_lds = fftu::lastx_table_in_lds(logl, G.lognmax, esize, lognt) ? 1 : 0;
+    lx.table_lds = fftu::lastx_table_in_lds(logl, loge, G.lognmax, esize, lognt) ? 1 : 0;
     lx.lds_bytes = lds + (lx.table_lds ? uint32_t(esize) << G.lognmax : 0u);
     return true;
 }
@@ -2003,18 +2014,24 @@ uint64_t dst_sign_mask(const fftu_plan_s *cp, int d, const int64_t n[], const in
 }
 
 // Inverse: the signs go into the complex transform's last kernel when that is the
-// fused exchange (k_exchange_sign negates its outputs by the same parity).
+// fused exchange or k_lastx (k_exchange_sign / k_lastx_sign negate their outputs by
+// the same parity).
 bool fuse_dst_signs_inverse(fftu_plan_s *rp, int d, const int64_t n[], const int64_t p[])
 {
     fftu_plan_s *cp = rp ? rp->rc : nullptr;
-    if (!cp || cp->gc || cp->mixed || cp->is_batch || cp->lastx || cp->ttrans || !cp->fused) return false;
-    const std::string xname = "fftu::k_exchange<";
+    if (!cp || cp->gc || cp->mixed || cp->is_batch || cp->ttrans || !(cp->fused || cp->lastx)) return false;
+    // the fused exchange, or k_lastx (the innermost lines with the exchange)
+    const std::string xname = cp->lastx ? "fftu::k_lastx<" : "fftu::k_exchange<";
     if (cp->launch_names.empty() || cp->launch_names.back().compare(0, xname.size(), xname) != 0) return false;
     if (rp->launch_names.empty() || rp->launch_names.back() != cp->launch_names.back()) return false;
     const uint64_t mask = dst_sign_mask(cp, d, n, p);
     if (!mask) return false;
-    cp->ex.sign_mask = mask;
-    const std::string renamed = "fftu::k_exchange_sign<" + cp->launch_names.back().substr(xname.size());
+    if (cp->lastx)
+        cp->lx.ex.sign_mask = mask;
+    else
+        cp->ex.sign_mask = mask;
+    const std::string renamed = (cp->lastx ? "fftu::k_lastx_sign<" : "fftu::k_exchange_sign<") +
+                                cp->launch_names.back().substr(xname.size());
     cp->launch_names.back() = renamed;
     rp->launch_names.back() = renamed;
     return true;
@@ -2950,7 +2967,8 @@ fftu_status execute_with(fftu_plan_s *plan, const void *in, void *out, void *ws,
         lx.ex.mul = mul;
         if (mul) {   // the multiplying instantiation keeps the table in HBM
             lx.table_lds = 0;
-            lx.lds_bytes = fftu::lastx_lds_bytes(lx.logl, int(plan->esize), lx.lognt);
+            lx.lds_bytes = fftu::lastx_lds_bytes(lx.logl, fftu::lastx_loge(lx.logl, lx.ex.nr * lx.ex.lpr),
+                                                 int(plan->esize), lx.lognt);
         }
         hipError_t e = fftu::launch_lastx(plan->prec, src, out, lx, plan->table, stream);
         if (e == hipSuccess) mk.mark();

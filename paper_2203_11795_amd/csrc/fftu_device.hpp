@@ -108,13 +108,14 @@ struct Dft<T, 1> {
 };
 
 // Compile-time radix plan of a line of 2^LOGL split over TPL = L / E threads with
-// E elements each (see line_stages_of / line_loge in fftu_internal.hpp). Register
-// m of thread j holds line position j + TPL m before the first and after the last
-// stage. Stage s has radix 2^lr(s) and follows Ns = 2^lns(s) points.
-template <int LOGL>
+// E = 2^LOGE_ elements each (by default k_line's, see line_stages_of / line_loge in
+// fftu_internal.hpp; k_lastx may hold more). Register m of thread j holds line
+// position j + TPL m before the first and after the last stage. Stage s has radix
+// 2^lr(s) (the last one may be smaller) and follows Ns = 2^lns(s) points.
+template <int LOGL, int LOGE_ = line_loge(LOGL)>
 struct LinePlan {
-    static constexpr int NS = line_stages_of(LOGL);
-    static constexpr int LOGE = line_loge(LOGL);
+    static constexpr int NS = LOGE_ == line_loge(LOGL) ? line_stages_of(LOGL) : (LOGL + LOGE_ - 1) / LOGE_;
+    static constexpr int LOGE = LOGE_;
     static constexpr int E = 1 << LOGE;
     static constexpr int LOGTPL = LOGL - LOGE;
     static constexpr int TPL = 1 << LOGTPL;
@@ -124,10 +125,10 @@ struct LinePlan {
 };
 
 // Radix stage S on the thread's registers (register m <-> position j + TPL m).
-template <typename T, int LOGL, int S>
-__device__ __forceinline__ void line_compute(cx<T> (&v)[LinePlan<LOGL>::E], int j, const cx<T> *tw)
+template <typename T, int LOGL, int S, int LOGE = line_loge(LOGL)>
+__device__ __forceinline__ void line_compute(cx<T> (&v)[1 << LOGE], int j, const cx<T> *tw)
 {
-    using PL = LinePlan<LOGL>;
+    using PL = LinePlan<LOGL, LOGE>;
     constexpr int LR = PL::lr(S), R = 1 << LR, LNS = PL::lns(S), NB = PL::E / R;
 #pragma unroll
     for (int c = 0; c < NB; ++c) {

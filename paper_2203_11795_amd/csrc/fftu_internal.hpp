@@ -155,7 +155,7 @@ constexpr uint32_t long_lds_bytes(int logl, int esize)
 // k_lastx (fftu_lastx.hpp): the innermost dimension's Superstep-0 lines fused with
 // the exchange. A workgroup of 2^lognt threads holds RW rows of all P blocks; its
 // threads hold E = 2^logr elements in both the line plan (a line of 2^logl,
-// line_loge(logl) == logr) and the exchange (logr register bits, logh wave bits).
+// lastx_loge(logl, logr) == logr) and the exchange (logr register bits, logh wave bits).
 // lognt is 9, or 10 where 512 threads cannot hold one row of every block (a line
 // of 256 over 64 blocks).
 constexpr int kLastxLogThreads = 9;
@@ -167,9 +167,14 @@ constexpr int64_t lastx_max_tiles(int lognt) { return int64_t(1) << (31 - lognt)
 
 // Compiled register/wave splits: 2^3 = (2,2,2) or 2^4 = (2,2,2,2) / (4,4) in registers,
 // and none, one 2, two 2s or one 4 across waves.
+// k_lastx's line elements per thread (2^loge, which must be the split's 2^logr
+// register sources): k_line's, except that lines of 64 meet a split of 16 register
+// sources as 16 elements per thread (stages of 16 and 4) instead of 8.
+constexpr int lastx_loge(int logl, int logr) { return logl == 6 && logr == 4 ? 4 : line_loge(logl); }
+
 constexpr bool lastx_split_ok(int logl, int nr, int lpr, int nh, int lph, int lognt = kLastxLogThreads)
 {
-    const int loge = line_loge(logl);
+    const int loge = lastx_loge(logl, nr * lpr);
     const bool reg = (loge == 3 && nr == 3 && lpr == 1) || (loge == 4 && ((nr == 4 && lpr == 1) || (nr == 2 && lpr == 2)));
     const bool wave = (nh == 0) || (nh == 1 && (lph == 1 || lph == 2)) || (nh == 2 && lph == 1);
     const int logh = nh * lph, logp = nr * lpr + logh;
@@ -188,27 +193,27 @@ constexpr bool lastx_split_needs_1024(int logl, int nr, int lpr, int nh, int lph
 
 // k_lastx reads its tile linearly and regroups it through LDS when one thread's run
 // of a line (TPL = L / E elements) is shorter than 128 bytes.
-constexpr bool lastx_staged_load(int logl, int esize)
+constexpr bool lastx_staged_load(int logl, int loge, int esize)
 {
-    return (int64_t(1) << (logl - line_loge(logl))) * esize < 128;
+    return (int64_t(1) << (logl - loge)) * esize < 128;
 }
 
 // LDS bytes of k_lastx: omega_L table, then max(transpose, line stages) rows of 8-byte words.
-constexpr uint32_t lastx_lds_bytes(int logl, int esize, int lognt = kLastxLogThreads)
+constexpr uint32_t lastx_lds_bytes(int logl, int loge, int esize, int lognt = kLastxLogThreads)
 {
     const int L = 1 << logl;
-    const int tpl = 1 << (logl - line_loge(logl));
+    const int tpl = 1 << (logl - loge);
     const int lp = L + tpl, pitch = L + L / 16 + 1;
-    const int lines = 1 << (lognt - (logl - line_loge(logl)));
+    const int lines = 1 << (lognt - (logl - loge));
     return uint32_t(L * esize + lines * (lp > pitch ? lp : pitch) * 8);
 }
 
 // k_lastx copies the omega table into LDS when two 512-thread workgroups per CU still fit.
 constexpr uint32_t kLastxTableLdsMax = 80 * 1024;
-constexpr bool lastx_table_in_lds(int logl, int lognmax, int esize, int lognt = kLastxLogThreads)
+constexpr bool lastx_table_in_lds(int logl, int loge, int lognmax, int esize, int lognt = kLastxLogThreads)
 {
     return lognt == kLastxLogThreads &&
-           uint64_t(lastx_lds_bytes(logl, esize, lognt)) + (uint64_t(esize) << lognmax) <= kLastxTableLdsMax;
+           uint64_t(lastx_lds_bytes(logl, loge, esize, lognt)) + (uint64_t(esize) << lognmax) <= kLastxTableLdsMax;
 }
 
 struct LastxDesc {

@@ -31,7 +31,7 @@ namespace fftu {
 
 template <int LOGL, int LOGR, int LOGH, int LOGNT>
 struct LastxShape {
-    using PL = LinePlan<LOGL>;
+    using PL = LinePlan<LOGL, lastx_loge(LOGL, LOGR)>;
     static constexpr int LOGP = LOGR + LOGH;
     static constexpr int LOGW = LOGNT - PL::LOGTPL;   // lines per tile: P x RW
     static constexpr int LOGRW = LOGW - LOGP;         // rows per tile
@@ -49,10 +49,11 @@ struct LastxShape {
 // to 256 VGPRs. TL: the exchange's twiddles come from an LDS copy of the omega
 // table, placed after the work area (the planner takes it when two 512-thread
 // workgroups per CU still fit).
-template <typename T, int LOGL, int NR, int LPR, int NH, int LPH, bool MUL, bool TL, int LOGNT>
-__global__ __launch_bounds__(1 << LOGNT, (MUL && LOGNT == 9) ? 2 : 4) void k_lastx(const cx<T> *__restrict__ in,
-                                                                      cx<T> *__restrict__ out, const LastxDesc lx,
-                                                                      const cx<T> *__restrict__ table)
+// One tile of k_lastx; MULM is the exchange's store mode (exchange_store: 1 plain,
+// 2 the pointwise product, 3 the signs under lx.ex.sign_mask).
+template <typename T, int LOGL, int NR, int LPR, int NH, int LPH, int MULM, bool TL, int LOGNT>
+__device__ __forceinline__ void lastx_tile(const cx<T> *__restrict__ in, cx<T> *__restrict__ out, const LastxDesc &lx,
+                                           const cx<T> *__restrict__ table)
 {
     constexpr int LOGR = NR * LPR, LOGH = NH * LPH;
     constexpr int NT = 1 << LOGNT;
@@ -60,7 +61,7 @@ __global__ __launch_bounds__(1 << LOGNT, (MUL && LOGNT == 9) ? 2 : 4) void k_las
     using PL = typename S::PL;
     static_assert(lastx_split_ok(LOGL, NR, LPR, NH, LPH, LOGNT), "k_lastx: no such split");
     static_assert(PL::LOGE == LOGR && S::LOGRW >= 0, "k_lastx: the line plan and the exchange split disagree");
-    static_assert(lastx_lds_bytes(LOGL, sizeof(cx<T>), LOGNT) == S::L * sizeof(cx<T>) + S::WORDS * 8,
+    static_assert(lastx_lds_bytes(LOGL, PL::LOGE, sizeof(cx<T>), LOGNT) == S::L * sizeof(cx<T>) + S::WORDS * 8,
                   "k_lastx: LDS size");
     constexpr int R = 1 << LOGR;
     constexpr int H = 1 << LOGH;
@@ -100,7 +101,7 @@ __global__ __launch_bounds__(1 << LOGNT, (MUL && LOGNT == 9) ? 2 : 4) void k_las
     {
         const int64_t tile = blockIdx.x;   // one tile per workgroup (the launcher checks the grid)
         cx<T> v[PL::E];
-        if constexpr (lastx_staged_load(LOGL, sizeof(cx<T>))) {
+        if constexpr (lastx_staged_load(LOGL, PL::LOGE, sizeof(cx<T>))) {
             // a thread's run of a line (TPL elements) is under 128 bytes: read the tile's
             // RW L contiguous elements of each block linearly instead (64 consecutive
             // elements per wave instruction) and hand each thread its line positions
@@ -144,7 +145,7 @@ __global__ __launch_bounds__(1 << LOGNT, (MUL && LOGNT == 9) ? 2 : 4) void k_las
             __syncthreads();   // the omega_L table is in LDS
         }
 
-        line_stages<T, LOGL, kLineContig>(v, j, w, S::PITCH, static_cast<void *>(work), tw, true);
+        line_stages<T, LOGL, kLineContig, PL::LOGE>(v, j, w, S::PITCH, static_cast<void *>(work), tw, true);
 
         // transpose: element (s, row, x) to LDS word (s RW + row) LP + x + x / 32, read back
         // as (hw R + jj, kk); the register index is the row of R LP RW words
@@ -176,10 +177,29 @@ __global__ __launch_bounds__(1 << LOGNT, (MUL && LOGNT == 9) ? 2 : 4) void k_las
             for (int jj = 0; jj < R; ++jj) u[jj] = ld[rd + (jj << S::LOGRW) * S::LP];
         }
 
-        exchange_core<T, NR, LPR, NH, LPH, NT, false, MUL ? 2 : 1>(
+        exchange_core<T, NR, LPR, NH, LPH, NT, false, MULM>(
             out, lx.ex, TL ? ttab : table, work, (tile << S::LOGK) + kk, tid,
             [&](int jj, int, int64_t, bool) { return u[jj]; });
     }
+}
+
+template <typename T, int LOGL, int NR, int LPR, int NH, int LPH, bool MUL, bool TL, int LOGNT>
+__global__ __launch_bounds__(1 << LOGNT, (MUL && LOGNT == 9) ? 2 : 4) void k_lastx(const cx<T> *__restrict__ in,
+                                                                      cx<T> *__restrict__ out, const LastxDesc lx,
+                                                                      const cx<T> *__restrict__ table)
+{
+    lastx_tile<T, LOGL, NR, LPR, NH, LPH, MUL ? 2 : 1, TL, LOGNT>(in, out, lx, table);
+}
+
+// k_lastx with every output negated by the parity of its buffer index under
+// lx.ex.sign_mask (no product; MUL is false, kept so that the name lists the same
+// arguments): the last kernel of a transform whose result is wanted with signs.
+template <typename T, int LOGL, int NR, int LPR, int NH, int LPH, bool MUL, bool TL, int LOGNT>
+__global__ __launch_bounds__(1 << LOGNT, 4) void k_lastx_sign(const cx<T> *__restrict__ in, cx<T> *__restrict__ out,
+                                                              const LastxDesc lx, const cx<T> *__restrict__ table)
+{
+    static_assert(!MUL, "k_lastx_sign: no product");
+    lastx_tile<T, LOGL, NR, LPR, NH, LPH, 3, TL, LOGNT>(in, out, lx, table);
 }
 
 namespace lastx_detail {
@@ -192,8 +212,23 @@ hipError_t go_nt(const void *in, void *out, const LastxDesc &lx, const void *tab
     const dim3 threads(1u << LOGNT);
     const cx<T> *a = static_cast<const cx<T> *>(in), *tab = static_cast<const cx<T> *>(table);
     cx<T> *b = static_cast<cx<T> *>(out);
-    const uint32_t base = lastx_lds_bytes(LOGL, sizeof(cx<T>), LOGNT);
-    if (lx.ex.mul) {
+    const uint32_t base = lastx_lds_bytes(LOGL, lastx_loge(LOGL, NR * LPR), sizeof(cx<T>), LOGNT);
+    if (lx.ex.sign_mask != 0) {
+        if (lx.ex.mul) return hipErrorInvalidValue;   // signs and a product are not combined
+        if (lx.table_lds) {
+            if constexpr (LOGNT == kLastxLogThreads) {
+                if (lx.lds_bytes != base + (uint32_t(sizeof(cx<T>)) << lx.ex.g.lognmax)) return hipErrorInvalidValue;
+                hipLaunchKernelGGL((k_lastx_sign<T, LOGL, NR, LPR, NH, LPH, false, true, LOGNT>), dim3(blocks), threads,
+                                   lx.lds_bytes, stream, a, b, lx, tab);
+            } else {
+                return hipErrorInvalidValue;
+            }
+        } else {
+            if (lx.lds_bytes != base) return hipErrorInvalidValue;
+            hipLaunchKernelGGL((k_lastx_sign<T, LOGL, NR, LPR, NH, LPH, false, false, LOGNT>), dim3(blocks), threads,
+                               lx.lds_bytes, stream, a, b, lx, tab);
+        }
+    } else if (lx.ex.mul) {
         if (lx.lds_bytes != base) return hipErrorInvalidValue;
         hipLaunchKernelGGL((k_lastx<T, LOGL, NR, LPR, NH, LPH, true, false, LOGNT>), dim3(blocks), threads,
                            lx.lds_bytes, stream, a, b, lx, tab);
@@ -242,6 +277,10 @@ hipError_t regs(const void *in, void *out, const LastxDesc &lx, const void *tabl
     const ExchangeDesc &ex = lx.ex;
     if constexpr (line_loge(LOGL) == 3) {
         if (ex.nr == 3 && ex.lpr == 1) return waves<T, LOGL, 3, 1>(in, out, lx, table, stream);
+        if constexpr (lastx_loge(LOGL, 4) == 4) {   // lines of 64 as 16 elements per thread
+            if (ex.nr == 4 && ex.lpr == 1) return waves<T, LOGL, 4, 1>(in, out, lx, table, stream);
+            if (ex.nr == 2 && ex.lpr == 2) return waves<T, LOGL, 2, 2>(in, out, lx, table, stream);
+        }
     } else if constexpr (line_loge(LOGL) == 4) {
         if (ex.nr == 4 && ex.lpr == 1) return waves<T, LOGL, 4, 1>(in, out, lx, table, stream);
         if (ex.nr == 2 && ex.lpr == 2) return waves<T, LOGL, 2, 2>(in, out, lx, table, stream);

@@ -26,11 +26,11 @@ __device__ __forceinline__ int lidx(int x, int w, int pitch)
 // (register m <-> position j + TPL m) are read back. complex128 lines go through
 // LDS as two rounds of doubles (real parts, then imaginary parts) so that a tile
 // needs 8 bytes of LDS per element; complex64 lines go in one round.
-template <typename T, int LOGL, int S, int MODE, typename V, typename GET>
-__device__ __forceinline__ void line_scatter(const cx<T> (&v)[LinePlan<LOGL>::E], int j, int w, int pitch, V *lds,
-                                             GET get)
+template <typename T, int LOGL, int S, int MODE, int LOGE = line_loge(LOGL), typename V, typename GET>
+__device__ __forceinline__ void line_scatter(const cx<T> (&v)[1 << LOGE], int j, int w, int pitch,
+                                             V *lds, GET get)
 {
-    using PL = LinePlan<LOGL>;
+    using PL = LinePlan<LOGL, LOGE>;
     constexpr int LR = PL::lr(S), R = 1 << LR, LNS = PL::lns(S), NB = PL::E / R;
 #pragma unroll
     for (int c = 0; c < NB; ++c) {
@@ -41,50 +41,50 @@ __device__ __forceinline__ void line_scatter(const cx<T> (&v)[LinePlan<LOGL>::E]
     }
 }
 
-template <typename T, int LOGL, int MODE, typename V, typename PUT>
-__device__ __forceinline__ void line_gather(cx<T> (&v)[LinePlan<LOGL>::E], int j, int w, int pitch, const V *lds,
-                                            PUT put)
+template <typename T, int LOGL, int MODE, int LOGE = line_loge(LOGL), typename V, typename PUT>
+__device__ __forceinline__ void line_gather(cx<T> (&v)[1 << LOGE], int j, int w, int pitch,
+                                            const V *lds, PUT put)
 {
-    using PL = LinePlan<LOGL>;
+    using PL = LinePlan<LOGL, LOGE>;
 #pragma unroll
     for (int m = 0; m < PL::E; ++m) put(v[m], lds[lidx<MODE>(j + m * PL::TPL, w, pitch)]);
 }
 
-template <typename T, int LOGL, int S, int MODE>
-__device__ __forceinline__ void line_exchange(cx<T> (&v)[LinePlan<LOGL>::E], int j, int w, int pitch, void *smem,
-                                              bool active)
+template <typename T, int LOGL, int S, int MODE, int LOGE = line_loge(LOGL)>
+__device__ __forceinline__ void line_exchange(cx<T> (&v)[1 << LOGE], int j, int w, int pitch,
+                                              void *smem, bool active)
 {
     if constexpr (sizeof(T) == 8) {
         T *lds = static_cast<T *>(smem);
-        if (active) line_scatter<T, LOGL, S, MODE>(v, j, w, pitch, lds, [](const cx<T> &a) { return a.x; });
+        if (active) line_scatter<T, LOGL, S, MODE, LOGE>(v, j, w, pitch, lds, [](const cx<T> &a) { return a.x; });
         __syncthreads();
-        if (active) line_gather<T, LOGL, MODE>(v, j, w, pitch, lds, [](cx<T> &a, T b) { a.x = b; });
+        if (active) line_gather<T, LOGL, MODE, LOGE>(v, j, w, pitch, lds, [](cx<T> &a, T b) { a.x = b; });
         __syncthreads();
-        if (active) line_scatter<T, LOGL, S, MODE>(v, j, w, pitch, lds, [](const cx<T> &a) { return a.y; });
+        if (active) line_scatter<T, LOGL, S, MODE, LOGE>(v, j, w, pitch, lds, [](const cx<T> &a) { return a.y; });
         __syncthreads();
-        if (active) line_gather<T, LOGL, MODE>(v, j, w, pitch, lds, [](cx<T> &a, T b) { a.y = b; });
+        if (active) line_gather<T, LOGL, MODE, LOGE>(v, j, w, pitch, lds, [](cx<T> &a, T b) { a.y = b; });
     } else {
         cx<T> *lds = static_cast<cx<T> *>(smem);
-        if (active) line_scatter<T, LOGL, S, MODE>(v, j, w, pitch, lds, [](const cx<T> &a) { return a; });
+        if (active) line_scatter<T, LOGL, S, MODE, LOGE>(v, j, w, pitch, lds, [](const cx<T> &a) { return a; });
         __syncthreads();
-        if (active) line_gather<T, LOGL, MODE>(v, j, w, pitch, lds, [](cx<T> &a, cx<T> b) { a = b; });
+        if (active) line_gather<T, LOGL, MODE, LOGE>(v, j, w, pitch, lds, [](cx<T> &a, cx<T> b) { a = b; });
     }
 }
 
-template <typename T, int LOGL, int MODE>
-__device__ __forceinline__ void line_stages(cx<T> (&v)[LinePlan<LOGL>::E], int j, int w, int pitch, void *smem,
-                                            const cx<T> *tw, bool active)
+template <typename T, int LOGL, int MODE, int LOGE = line_loge(LOGL)>
+__device__ __forceinline__ void line_stages(cx<T> (&v)[1 << LOGE], int j, int w, int pitch,
+                                            void *smem, const cx<T> *tw, bool active)
 {
-    using PL = LinePlan<LOGL>;
-    if (active) line_compute<T, LOGL, 0>(v, j, tw);
+    using PL = LinePlan<LOGL, LOGE>;
+    if (active) line_compute<T, LOGL, 0, LOGE>(v, j, tw);
     if constexpr (PL::NS > 1) {
-        line_exchange<T, LOGL, 0, MODE>(v, j, w, pitch, smem, active);
-        if (active) line_compute<T, LOGL, 1>(v, j, tw);
+        line_exchange<T, LOGL, 0, MODE, LOGE>(v, j, w, pitch, smem, active);
+        if (active) line_compute<T, LOGL, 1, LOGE>(v, j, tw);
     }
     if constexpr (PL::NS > 2) {
         __syncthreads();
-        line_exchange<T, LOGL, 1, MODE>(v, j, w, pitch, smem, active);
-        if (active) line_compute<T, LOGL, 2>(v, j, tw);
+        line_exchange<T, LOGL, 1, MODE, LOGE>(v, j, w, pitch, smem, active);
+        if (active) line_compute<T, LOGL, 2, LOGE>(v, j, tw);
     }
 }
 

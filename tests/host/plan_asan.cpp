@@ -66,7 +66,7 @@ hipError_t launch_lastx(Precision, const void *, void *, const LastxDesc &lx, co
     if (!lastx_split_ok(lx.logl, ex.nr, ex.lpr, ex.nh, ex.lph, lx.lognt) || ex.g.conj_in != 0) std::abort();
     if (lx.lognt != kLastxLogThreads && !lastx_split_needs_1024(lx.logl, ex.nr, ex.lpr, ex.nh, ex.lph)) std::abort();
     const int logp = ex.nr * ex.lpr + ex.nh * ex.lph;
-    const int logrw = lx.lognt - (lx.logl - line_loge(lx.logl)) - logp;
+    const int logrw = lx.lognt - (lx.logl - lastx_loge(lx.logl, ex.nr * ex.lpr)) - logp;
     if ((lx.tiles << (logrw + lx.logl)) != ex.g.M || lx.lds_bytes > 160 * 1024) std::abort();
     if (lx.table_lds && (ex.mul || lx.lds_bytes > kLastxTableLdsMax)) std::abort();
     if (ex.g.logm[ex.g.d - 1] != lx.logl) std::abort();

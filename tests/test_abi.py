@@ -126,6 +126,9 @@ def test_p_max_examples():
     ((64, 64, 64), (8, 8, 8), "complex128", 2, 0, 5),       # P = 512: k_ttranspose with the 8-point FFTs
     ((8192, 16), (2, 2), "complex64", 2, 1, 3),             # k_long for the lines of 4096
     ((16, 16, 16, 32, 64), (2,) * 5, "complex64", 2, 2, 3),  # two k_pair passes, then k_lastx
+    # lines of 64 over a 4 x 4 x 4 split: k_lastx with 16 elements per thread (the packed
+    # array of the 512^3 real transforms)
+    ((512, 512, 256), (4, 4, 4), "complex128", 2, 2, 3),
 ])
 def test_describe(n, p, dtype, s0, fused, launches):
     info = fftu.describe(n, p, dtype)

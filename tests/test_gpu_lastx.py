@@ -44,6 +44,11 @@ CASES = [
     ((4, 4, 16, 1024), (2, 2, 4, 4), (8, 2, 2, 2, 1)),
     ((16, 4, 4, 4, 512), (4, 2, 2, 2, 2), (8, 4, 1, 1, 2)),
     ((4, 4, 4, 4, 4, 512), (2, 2, 2, 2, 2, 2), (8, 4, 1, 2, 1)),
+    # lines of 64 held as 16 elements per thread (stages of 16 and 4) for splits of 16
+    # register sources: the packed 512 x 512 x 256 array of the real transforms over 4^3
+    ((32, 64, 256), (4, 4, 4), (6, 2, 2, 1, 2)),
+    ((32, 32, 256), (2, 4, 4), (6, 2, 2, 1, 1)),
+    ((256, 256), (4, 4), (6, 2, 2, 0, 0)),
 ]
 IDS = [f"{'x'.join(map(str, n))}-p{'x'.join(map(str, p))}" for n, p, _ in CASES]
 

@@ -78,7 +78,7 @@ def test_forward_and_inverse_match_the_oracle(torch, n, p, kind, dtype):
         inames = inv.launch_names()
         assert inames[0] == f"fftu::k_r2rpre<{t}, {len(n)}, {'true' if pre_rows(n) else 'false'}>"
         # the inverse DST's signs: a pass of their own, or in the last exchange's stores
-        ifused = any(k.startswith("fftu::k_exchange_sign<") for k in inames)
+        ifused = any(k.startswith(("fftu::k_exchange_sign<", "fftu::k_lastx_sign<")) for k in inames)
         assert (inames[-1].startswith("fftu::k_r2rsign") or ifused) == (kind == "dst"), inames
         assert not (ifused and inames[-1].startswith("fftu::k_r2rsign")), inames
         assert inv.info()["launches"] == len(inames)
@@ -169,7 +169,7 @@ def test_dct_512cube_full_size(torch):
 
 def test_dst_512cube_signs_in_first_pass(torch):
     """512^3 FP64 DST-II over 4^3 at full size, whose signal signs are applied by the
-    complex transform's first line pass (forward) and last exchange (inverse): 2000
+    complex transform's first line pass (forward) and its last kernel, k_lastx (inverse): 2000
     sampled coefficients of a sparse signal against the definition summed over its
     nonzeros, and the round trip."""
     import paper_2203_11795_amd as fftu
@@ -188,7 +188,7 @@ def test_dst_512cube_signs_in_first_pass(torch):
         names = fwd.launch_names()
         assert names[0].startswith("fftu::k_line_sign<double, ") and not any("r2rsign" in k for k in names), names
         inames = inv.launch_names()
-        assert inames[-1].startswith("fftu::k_exchange_sign<double, ") and not any("r2rsign" in k for k in inames), inames
+        assert inames[-1].startswith("fftu::k_lastx_sign<double, 6, ") and not any("r2rsign" in k for k in inames), inames
         y = fwd(x)
         torch.cuda.synchronize()
         ks = rng.integers(0, 512, size=(2000, 3))
