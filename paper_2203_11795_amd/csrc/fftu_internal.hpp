@@ -168,9 +168,13 @@ constexpr int64_t lastx_max_tiles(int lognt) { return int64_t(1) << (31 - lognt)
 // Compiled register/wave splits: 2^3 = (2,2,2) or 2^4 = (2,2,2,2) / (4,4) in registers,
 // and none, one 2, two 2s or one 4 across waves.
 // k_lastx's line elements per thread (2^loge, which must be the split's 2^logr
-// register sources): k_line's, except that lines of 64 meet a split of 16 register
-// sources as 16 elements per thread (stages of 16 and 4) instead of 8.
-constexpr int lastx_loge(int logl, int logr) { return logl == 6 && logr == 4 ? 4 : line_loge(logl); }
+// register sources): k_line's, except that lines of 32 and 64 meet a split of 16
+// register sources as 16 elements per thread (stages of 16 and 2, or 16 and 4)
+// instead of 8.
+constexpr int lastx_loge(int logl, int logr)
+{
+    return (logl == 5 || logl == 6) && logr == 4 ? 4 : line_loge(logl);
+}
 
 constexpr bool lastx_split_ok(int logl, int nr, int lpr, int nh, int lph, int lognt = kLastxLogThreads)
 {

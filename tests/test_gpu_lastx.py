@@ -49,6 +49,9 @@ CASES = [
     ((32, 64, 256), (4, 4, 4), (6, 2, 2, 1, 2)),
     ((32, 32, 256), (2, 4, 4), (6, 2, 2, 1, 1)),
     ((256, 256), (4, 4), (6, 2, 2, 0, 0)),
+    # lines of 32 the same way (stages of 16 and 2)
+    ((32, 64, 128), (4, 4, 4), (5, 2, 2, 1, 2)),
+    ((64, 128, 128), (4, 4, 4), (5, 2, 2, 1, 2)),
 ]
 IDS = [f"{'x'.join(map(str, n))}-p{'x'.join(map(str, p))}" for n, p, _ in CASES]
 
