@@ -71,6 +71,7 @@ struct fftu_plan_s {
     bool r2r = false;
     fftu_r2r_kind r2r_kind = FFTU_DCT;
     bool r2r_sign_fused = false;   // DST forward: the signs in the complex transform's first pass
+    bool r2r_pre_merge = false;    // inverse: k_r2rpre_merge in place of k_r2rpre and k_rmerge
     fftu::R2RDesc r2d{};
     // grids beyond p_max (some p_l^2 not dividing n_l): group-cyclic levels, several supersteps
     bool gc = false;
@@ -2126,6 +2127,12 @@ fftu_plan_t fftu_plan_r2r(int d, const int64_t n[], const int64_t p[], fftu_dtyp
         for (const std::string &k : rc->rc->launch_names) pl->launch_names.push_back(k);
         const bool rows = fftu::r2rpost_rows_lds(g, dtype == FFTU_C128 ? sizeof(double) : sizeof(float)) > 0;
         pl->launch_names.push_back((rows ? "fftu::k_r2rpost_rows<" : "fftu::k_r2rpost<") + t + ", " + dd + ">");
+    } else if (fftu::r2rpre_merge_lds(g, pl->esize) > 0) {
+        // the spectrum and the merge in one pass, then the inverse complex transform
+        pl->r2r_pre_merge = true;
+        pl->launch_names.push_back("fftu::k_r2rpre_merge<" + t + ", " + dd + ">");
+        for (const std::string &k : rc->rc->launch_names) pl->launch_names.push_back(k);
+        if (dst && !pl->r2r_sign_fused) pl->launch_names.push_back("fftu::k_r2rsign<" + t + ", " + std::to_string(d) + ">");
     } else {
         pl->launch_names.push_back("fftu::k_r2rpre<" + t + ", " + dd + (fftu::r2rpre_rows(g) ? ", true>" : ", false>"));
         for (const std::string &k : rc->launch_names) pl->launch_names.push_back(k);
@@ -3053,10 +3060,22 @@ fftu_status execute_r2r(fftu_plan_s *plan, const void *in, void *out, hipStream_
         if (e == hipSuccess) mk.mark();
         return from_hip(e);
     }
-    e = fftu::launch_r2r_pre(plan->prec, in, plan->ws, plan->r2d, plan->rtable, stream);
-    if (e != hipSuccess) return from_hip(e);
-    mk.mark();
-    fftu_status s = execute_real(rp, plan->ws, out, stream, mk);
+    fftu_status s;
+    if (plan->r2r_pre_merge) {
+        // the packed spectrum into the output (into the spectrum workspace when the call
+        // is in place: other workgroups still read the coefficients), then the inverse
+        // complex transform from there into the output
+        void *z = in == out ? plan->ws : out;
+        e = fftu::launch_r2r_pre_merge(plan->prec, in, z, plan->r2d, plan->rtable, stream);
+        if (e != hipSuccess) return from_hip(e);
+        mk.mark();
+        s = execute_with(rp->rc, z, out, rp->rc->ws, stream, nullptr, &mk);
+    } else {
+        e = fftu::launch_r2r_pre(plan->prec, in, plan->ws, plan->r2d, plan->rtable, stream);
+        if (e != hipSuccess) return from_hip(e);
+        mk.mark();
+        s = execute_real(rp, plan->ws, out, stream, mk);
+    }
     if (s != FFTU_SUCCESS || !dst || plan->r2r_sign_fused) return s;
     e = fftu::launch_r2r_sign(plan->prec, out, out, plan->r2d, stream);
     if (e == hipSuccess) mk.mark();

@@ -352,6 +352,16 @@ inline bool r2rpre_rows(const R2RDesc &g)
     return h % 64 == 0 && g.groups / (h + 1) >= 1024;
 }
 
+// k_r2rpre_merge (the inverse's spectrum and the real transform's merge in one pass)
+// where k_r2rpre takes rows and the row's 2^(d-1) (n_d / 2 + 1) spectrum values fit
+// 32 KiB of LDS; returns its LDS bytes, or 0.
+inline uint32_t r2rpre_merge_lds(const R2RDesc &g, size_t esize)
+{
+    if (!r2rpre_rows(g)) return 0;
+    const int64_t bytes = (int64_t(1) << (g.d - 1)) * (g.n[g.d - 1] / 2 + 1) * int64_t(esize);
+    return bytes <= 32768 ? uint32_t(bytes) : 0;
+}
+
 // k_mxexchange (fftu_mixed.hip): the mixed-radix exchange for grids whose sides are
 // powers of two (any local sides): the register and wave split of k_exchange (NR
 // register dimensions of 2^LPR, NH wave dimensions of 2^LPH) with general index
@@ -518,6 +528,10 @@ hipError_t launch_r2r_post(Precision prec, const void *spec, void *y, const R2RD
                            hipStream_t stream);
 hipError_t launch_r2r_pre(Precision prec, const void *y, void *spec, const R2RDesc &g, const void *table4,
                           hipStream_t stream);
+// The inverse's spectrum merged into the packed spectrum z (N / 2 complex) in one pass
+// (r2rpre_merge_lds(g, ...) > 0); z is the real transform's complex input.
+hipError_t launch_r2r_pre_merge(Precision prec, const void *y, void *z, const R2RDesc &g, const void *table4,
+                                hipStream_t stream);
 hipError_t launch_r2r_sign(Precision prec, const void *in, void *out, const R2RDesc &g, hipStream_t stream);
 hipError_t launch_rmerge(Precision prec, const void *in, void *out, const RealDesc &rd, const void *table,
                          hipStream_t stream);

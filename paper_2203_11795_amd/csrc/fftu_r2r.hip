@@ -362,6 +362,111 @@ __global__ __launch_bounds__(256) void k_r2rpre(const T *__restrict__ y, cx<T> *
     }
 }
 
+// The inverse's spectrum and the real transform's merge in one pass, one workgroup per
+// row of representatives as k_r2rpre's ROWS form: the half spectrum and the plane,
+// Y = (C_1^-1 x ... x C_d^-1) y, of every leading mirror image of the row stay in LDS
+// as [mirror][k_d] (k_d in [0, n_d / 2]), and the packed spectrum Z = E + i O is formed
+// from Y at (k', k_d) and (-k', n_d / 2 - k_d), or from Y at (k', 0) and the plane at k'
+// for k_d = 0, which are all in the row (E = (a + conj b) / 2, O = (a - conj b)
+// omega_{n_d}^{-k_d} / 2, as the merge computes them). Z goes out in runs of m'_d
+// elements per block. A mirror image that repeats another (k_l = 0 or n_l / 2) takes
+// that one's values and writes nothing.
+template <typename T, int D>
+__global__ __launch_bounds__(256) void k_r2rpre_merge(const T *__restrict__ y, cx<T> *__restrict__ zout,
+                                                      const R2RDesc g, const cx<T> *__restrict__ table,
+                                                      const int64_t rows)
+{
+    static_assert(D >= 2, "k_r2rpre_merge: rows of the last dimension");
+    constexpr int G = 1 << D, GL = 1 << (D - 1);
+    extern __shared__ unsigned char smem_raw[];
+    cx<T> *ys = reinterpret_cast<cx<T> *>(smem_raw);   // [GL][h + 1]
+    const int tid = threadIdx.x;
+    const int32_t h = g.rd.h, hp = h + 1;
+    const int32_t pd = g.rd.p[D - 1], md = g.rd.m[D - 1];   // the packed last side h = p_d m'_d
+    const int64_t wstep = 4 * int64_t(g.tstep[D - 1]);       // omega_{n_d}^e = table entry e wstep
+    for (int64_t row = blockIdx.x; row < rows; row += gridDim.x) {
+        int32_t k[D];
+        {
+            int64_t t = row;
+#pragma unroll
+            for (int l = D - 2; l >= 0; --l) {
+                const int64_t span = g.n[l] / 2 + 1;
+                const int64_t q = t / span;
+                k[l] = int32_t(t - q * span);
+                t = q;
+            }
+        }
+        uint32_t repbits = 0;   // leading dimensions whose mirror image is the same index
+#pragma unroll
+        for (int l = 0; l < D - 1; ++l)
+            if (k[l] == 0 || 2 * k[l] == g.n[l]) repbits |= 1u << l;
+        for (int32_t j = tid; j <= h; j += blockDim.x) {
+            k[D - 1] = j;
+            cx<T> v[G];
+#pragma unroll
+            for (int mask = 0; mask < G; ++mask) {
+                int32_t kk[D];
+                member<D>(g, k, mask, kk);
+                if (g.dst) {
+#pragma unroll
+                    for (int l = 0; l < D; ++l) kk[l] = g.n[l] - 1 - kk[l];
+                }
+                v[mask] = {y[coeff_position<D>(g, kk)], T(0)};
+            }
+#pragma unroll
+            for (int l = 0; l < D; ++l) {
+                const cx<T> w = table[int64_t(k[l]) * g.tstep[l]];
+                const cx<T> wc = {w.x, -w.y};
+#pragma unroll
+                for (int mask = 0; mask < G; ++mask) {
+                    if ((mask >> l) & 1) continue;
+                    const int mb = mask | (1 << l);
+                    const cx<T> a = v[mask], b = v[mb];
+                    if (k[l] == 0) {
+                        v[mask] = {a.x * T(0.5), a.y * T(0.5)};
+                        v[mb] = v[mask];
+                    } else {
+                        const cx<T> ib = times_i(b);
+                        const cx<T> lo = cmul(wc, a - ib), hi = cmul(w, a + ib);
+                        v[mask] = {lo.x * T(0.5), lo.y * T(0.5)};
+                        v[mb] = {hi.x * T(0.5), hi.y * T(0.5)};
+                    }
+                }
+            }
+            // the members with k_d <= n_d / 2 (last dimension not mirrored)
+#pragma unroll
+            for (int mask = 0; mask < GL; ++mask) ys[mask * hp + j] = v[mask];
+        }
+        __syncthreads();
+        for (int32_t e = tid; e < GL * h; e += blockDim.x) {
+            const int32_t ml = e / h, rem = e - ml * h;
+            if (uint32_t(ml) & repbits) continue;
+            const int32_t rdd = rem / md, id = rem - rdd * md;
+            const int32_t kd = rdd + pd * id;
+            const cx<T> a = ys[ml * hp + kd];
+            cx<T> zv;
+            if (kd == 0) {
+                const cx<T> c = ys[ml * hp + h];
+                const cx<T> E = {(a.x + c.x) * T(0.5), (a.y + c.y) * T(0.5)};
+                const cx<T> O = {(a.x - c.x) * T(0.5), (a.y - c.y) * T(0.5)};
+                zv = {E.x - O.y, E.y + O.x};
+            } else {
+                const int32_t mc = int32_t(uint32_t(ml ^ (GL - 1)) & ~repbits);   // -k'
+                const cx<T> b = ys[mc * hp + (h - kd)];
+                const cx<T> E = {(a.x + b.x) * T(0.5), (a.y - b.y) * T(0.5)};
+                const cx<T> w = table[int64_t(kd) * wstep];
+                const cx<T> O = cmul(cx<T>{(a.x - b.x) * T(0.5), (a.y + b.y) * T(0.5)}, cx<T>{w.x, -w.y});
+                zv = {E.x - O.y, E.y + O.x};
+            }
+            int32_t kk[D];
+            member<D>(g, k, ml, kk);
+            kk[D - 1] = kd;
+            zout[spec_position<D, D>(g.rd, kk)] = zv;
+        }
+        __syncthreads();
+    }
+}
+
 // The signs of the DST's signal: v[m] negated once for each dimension with
 // m_l >= n_l / 2 (the odd samples of x), on the packed layout.
 template <typename T, int D>
@@ -467,6 +572,34 @@ hipError_t pre_t(const void *y, void *spec, const R2RDesc &g, const void *table,
 }
 
 }  // namespace
+
+namespace {
+template <typename T>
+hipError_t pre_merge_t(const void *y, void *z, const R2RDesc &g, const void *table, hipStream_t stream)
+{
+    const uint32_t lds = r2rpre_merge_lds(g, sizeof(cx<T>));
+    if (lds == 0) return hipErrorInvalidValue;
+    const int64_t rows = g.groups / (g.n[g.d - 1] / 2 + 1);
+    const uint32_t blocks = uint32_t(rows < (int64_t(1) << 20) ? rows : (int64_t(1) << 20));
+    const T *a = static_cast<const T *>(y);
+    cx<T> *b = static_cast<cx<T> *>(z);
+    const cx<T> *tab = static_cast<const cx<T> *>(table);
+    switch (g.d) {
+    case 2: hipLaunchKernelGGL((k_r2rpre_merge<T, 2>), dim3(blocks), dim3(256), lds, stream, a, b, g, tab, rows); break;
+    case 3: hipLaunchKernelGGL((k_r2rpre_merge<T, 3>), dim3(blocks), dim3(256), lds, stream, a, b, g, tab, rows); break;
+    case 4: hipLaunchKernelGGL((k_r2rpre_merge<T, 4>), dim3(blocks), dim3(256), lds, stream, a, b, g, tab, rows); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_r2r_pre_merge(Precision prec, const void *y, void *z, const R2RDesc &g, const void *table4,
+                                hipStream_t stream)
+{
+    if (!r2r_ok(g)) return hipErrorInvalidValue;
+    return prec == Precision::F64 ? pre_merge_t<double>(y, z, g, table4, stream) : pre_merge_t<float>(y, z, g, table4, stream);
+}
 
 hipError_t launch_r2r_post(Precision prec, const void *spec, void *y, const R2RDesc &g, const void *table4,
                            hipStream_t stream)

@@ -130,6 +130,11 @@ hipError_t launch_r2r_pre(Precision, const void *, void *, const R2RDesc &g, con
     if (g.d < 1 || g.d > kR2RMaxDims || g.groups < 1) std::abort();
     return hipSuccess;
 }
+hipError_t launch_r2r_pre_merge(Precision, const void *, void *, const R2RDesc &g, const void *, hipStream_t)
+{
+    if (g.d < 2 || g.d > kR2RMaxDims || g.groups < 1 || r2rpre_merge_lds(g, 16) == 0) std::abort();
+    return hipSuccess;
+}
 hipError_t launch_r2r_sign(Precision, const void *, void *, const R2RDesc &g, hipStream_t)
 {
     if (g.d < 1 || g.d > kR2RMaxDims) std::abort();

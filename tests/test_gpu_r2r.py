@@ -45,6 +45,14 @@ def pre_rows(n):
     return len(n) >= 2 and (n[-1] // 2) % 64 == 0 and int(np.prod([v // 2 + 1 for v in n[:-1]])) >= 1024
 
 
+def pre_merge(n, dtype):
+    """Whether the inverse's first pass is k_r2rpre_merge (the spectrum and the real
+    transform's merge in one pass): the row form, with 2^(d-1) (n_d / 2 + 1) spectrum
+    values of a row within 32 KiB."""
+    es = 16 if dtype == "complex128" else 8
+    return pre_rows(n) and 2 ** (len(n) - 1) * (n[-1] // 2 + 1) * es <= 32768
+
+
 def post_rows(n, p, dtype):
     """Whether the forward pass takes k_r2rpost_rows: n_d / 2 a multiple of 64, the
     2^(d-1) staged rows within 32 KiB, at least 1024 rows of representatives."""
@@ -76,7 +84,10 @@ def test_forward_and_inverse_match_the_oracle(torch, n, p, kind, dtype):
         assert not (fused and names[0].startswith("fftu::k_r2rsign")), names
         t = "double" if dtype == "complex128" else "float"
         inames = inv.launch_names()
-        assert inames[0] == f"fftu::k_r2rpre<{t}, {len(n)}, {'true' if pre_rows(n) else 'false'}>"
+        if pre_merge(n, dtype):
+            assert inames[0] == f"fftu::k_r2rpre_merge<{t}, {len(n)}>" and not any("rmerge" in k for k in inames)
+        else:
+            assert inames[0] == f"fftu::k_r2rpre<{t}, {len(n)}, {'true' if pre_rows(n) else 'false'}>"
         # the inverse DST's signs: a pass of their own, or in the last exchange's stores
         ifused = any(k.startswith(("fftu::k_exchange_sign<", "fftu::k_lastx_sign<")) for k in inames)
         assert (inames[-1].startswith("fftu::k_r2rsign") or ifused) == (kind == "dst"), inames
@@ -97,6 +108,10 @@ def test_forward_and_inverse_match_the_oracle(torch, n, p, kind, dtype):
         torch.cuda.synchronize()
         assert oracle.rel_l2(xb.cpu().numpy(), r2r.r2r_cyclic(want, n, p, kind, INVERSE)) <= TOL[dtype]
         assert oracle.rel_l2(rt.cpu().numpy(), sig.astype(np.float64)) <= TOL[dtype]
+        yi = yc.clone()
+        inv(yi, yi)                                      # the inverse in place
+        torch.cuda.synchronize()
+        assert np.array_equal(yi.cpu().numpy(), xb.cpu().numpy())
         assert fwd.info()["launches"] == len(names)
 
 
