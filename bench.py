@@ -514,8 +514,8 @@ def run_real(args, torch, np, fftu, synth, with_oracle):
 
 def run_r2r(args, torch, np, fftu, with_oracle):
     """The DCT-II and DST-II at the headline shape: a real 512^3 FP64 signal in the
-    zig-zag cyclic layout over 4x4x4, forward to the coefficients (cyclic); per-kernel
-    times from HIP events. Checked on 1000 sampled coefficients of a sparse signal
+    zig-zag cyclic layout over 4x4x4, forward to the coefficients (cyclic) and back;
+    per-kernel times from HIP events. Checked on 1000 sampled coefficients of a sparse signal
     against the definitions summed over its nonzeros, and by the dense round trip."""
     n, p = (512, 512, 512), (4, 4, 4)
     N = math.prod(n)
@@ -558,6 +558,21 @@ def run_r2r(args, torch, np, fftu, with_oracle):
         rt = inv(y)
         torch.cuda.synchronize()
         res["rel_l2_roundtrip"] = (torch.linalg.vector_norm(rt - x) / torch.linalg.vector_norm(x)).item()
+        # the inverse (coefficients to signal), timed the same way
+        for _ in range(args.warmup):
+            inv(y, rt, stream=stream)
+        torch.cuda.synchronize()
+        inv.timing_begin(steps)
+        e0.record(stream)
+        for _ in range(steps):
+            inv(y, rt, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ims = e0.elapsed_time(e1) / steps
+        iper, _ = inv.timing_end()
+        inames = inv.launch_names()
+        res["inverse"] = {"ms_per_transform": round(ims, 4), "launches": len(inames),
+                          "kernels": [{"kernel": k, "avg_ms": round(t, 4)} for k, t in zip(inames, iper)]}
         del rt
         if with_oracle:
             from oracle import r2r
@@ -589,7 +604,7 @@ def run_r2r(args, torch, np, fftu, with_oracle):
         inv.close()
         del x, y
         torch.cuda.empty_cache()
-        log(f"[bench] {kind} 512^3: {ms:.3f} ms")
+        log(f"[bench] {kind} 512^3: {ms:.3f} ms, inverse {ims:.3f} ms")
         out[kind] = res
     return out
 
